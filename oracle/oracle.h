@@ -1,0 +1,120 @@
+/*
+ * oracle.h - TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, sequential, fp64 CPU oracle of GSP-Louvain (Sahu, "GSP-Louvain:
+ * Fast Louvain Algorithm ... for splitting disconnected communities", arXiv
+ * 2402.11454).  Only the tests, the smoke check and the bench's CPU-baseline
+ * leg may load it; the GPU library never includes, links or calls it, and it
+ * shares no code with the GPU library.
+ *
+ * Graph convention (Section 3, notation): an undirected graph is given as a
+ * CSR holding both directions of every edge; row i lists (j, w_ij).  A
+ * self-loop is stored once, in its own row.  K_i is the full row sum, and
+ * 2m (called M2 below) is the sum of all stored entries.
+ *
+ * Memberships and labels are int32 values in [0, n).  Weights are fp64.
+ * Every function returns a negative value on invalid arguments.
+ */
+#ifndef GSP_ORACLE_H
+#define GSP_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* K_i = sum of row i (self-loop included), returns M2 = sum_i K_i. */
+double orc_vertex_weights(int64_t n, const int64_t *off, const int32_t *col, const double *w, double *K);
+
+/* Modularity of a membership, Eq. 1 (community form). 0 when M2 = 0. */
+double orc_modularity(int64_t n, const int64_t *off, const int32_t *col, const double *w, const int32_t *memb);
+
+/* Delta-modularity of moving i from its community to c, Eq. 2.  K_{i->x}
+ * excludes i's self-loop; Sigma_d includes K_i. */
+double orc_delta_modularity(int64_t n, const int64_t *off, const int32_t *col, const double *w,
+                            const int32_t *memb, int64_t i, int32_t c);
+
+/* Asynchronous sequential local-moving phase (Algorithm "louvainMove", one
+ * thread).  memb/sigma are updated in place; returns l_i (iterations run)
+ * and writes the per-iteration delta-modularity sums to dq_iter (length
+ * max_iter, may be NULL). */
+int32_t orc_move_async(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
+                       const double *K, int32_t *memb, double *sigma, double tau, int32_t max_iter,
+                       double *dq_iter);
+
+/* One synchronous move step from a snapshot (memb, sigma, csize); vertices
+ * with active[i] = 0 keep their community (active NULL = all).  Writes the
+ * chosen community (or the current one) to dec and the integer-style gain
+ * numerator G(c*) - G(stay) to gain (0 for non-movers).  Returns the number
+ * of movers. */
+int64_t orc_move_sync_step(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
+                           const double *K, const int32_t *memb, const double *sigma, const int32_t *csize,
+                           const uint8_t *active, int32_t *dec, double *gain);
+
+/* Synchronous local-moving phase in `rounds` ordered sub-rounds (a power of
+ * two, 1..64): vertex i belongs to sub-round (i * 0x9E3779B97F4A7C15) >> (64 -
+ * log2 rounds).  Each sub-round is one snapshot step over the unprocessed
+ * vertices of its group; movers mark their neighbours unprocessed.  memb is
+ * updated in place; returns l_i; dq_iter and moved_iter (length max_iter,
+ * may be NULL) receive the per-iteration delta-modularity sums and mover
+ * counts. */
+int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
+                      const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
+                      double *dq_iter, int64_t *moved_iter);
+
+/* Split of internally-disconnected communities by BFS (Algorithm
+ * "splitDisconnectedBfs", one thread, lowest unvisited source):
+ * labels[i] = smallest vertex id of i's component in the same-community
+ * subgraph. */
+int32_t orc_split_bfs(int64_t n, const int64_t *off, const int32_t *col, const int32_t *memb, int32_t *labels);
+
+/* Same split by minimum-label propagation (Algorithm "splitDisconnectedLp"),
+ * pruned = 1 for LPP.  Returns the number of sweeps. */
+int32_t orc_split_lp(int64_t n, const int64_t *off, const int32_t *col, const int32_t *memb, int32_t pruned,
+                     int32_t *labels);
+
+/* Renumbers labels (values in [0, n)) to [0, G) in ascending label order;
+ * returns G. */
+int64_t orc_renumber(int64_t n, const int32_t *labels, int32_t *out);
+
+/* Aggregation (Algorithm "louvainAggregate"): memb holds values in
+ * [0, ncomm).  Writes the super-vertex CSR: off2[ncomm+1], col2/w2 with
+ * room for cap entries, rows sorted by column.  Returns its entry count, or
+ * -1 if cap is too small. */
+int64_t orc_aggregate(int64_t n, const int64_t *off, const int32_t *col, const double *w, const int32_t *memb,
+                      int64_t ncomm, int64_t *off2, int32_t *col2, double *w2, int64_t cap);
+
+/* Disconnected communities (Algorithm "disconnectedCommunities", one
+ * thread): flags[c] = 1 if community c is internally disconnected (flags
+ * has length n, may be NULL).  Returns the number of such communities. */
+int64_t orc_disconnected(int64_t n, const int64_t *off, const int32_t *col, const int32_t *memb, uint8_t *flags);
+
+typedef struct orc_options {
+    double tolerance;              /* tau for the first pass */
+    int32_t max_passes;
+    int32_t max_iterations;
+    double tolerance_drop;
+    double aggregation_tolerance;  /* tau_agg */
+    int32_t sync_moves;            /* 0: asynchronous sequential, 1: synchronous sub-rounds */
+    int32_t sync_rounds;           /* sub-rounds per iteration when sync_moves = 1 */
+    int32_t split_mode;            /* 0: every pass (SP), 1: after the last pass (SL), 2: none */
+} orc_options;
+
+typedef struct orc_stats {
+    int32_t passes;
+    int32_t iterations[64];        /* l_i per pass */
+    int64_t communities[64];       /* |Gamma| after each pass's split */
+    int64_t vertices[64];          /* N' of each pass */
+    double modularity;
+} orc_stats;
+
+/* The whole method (Algorithm "louvain").  memb_out[n] gets the top-level
+ * membership, numbered by ascending smallest vertex id.  Returns the number
+ * of passes run. */
+int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const double *w, const orc_options *opt,
+                    int32_t *memb_out, orc_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,51 @@
+"""The seeded generators produce valid symmetric CSR graphs, deterministically."""
+import numpy as np
+import pytest
+
+import gsp_inputs as gi
+
+
+def _check_csr(g):
+    assert g.offsets[0] == 0 and g.offsets[-1] == g.nnz
+    assert np.all(np.diff(g.offsets) >= 0)
+    assert np.all((g.cols >= 0) & (g.cols < g.n))
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    assert not np.any(rows == g.cols)                      # no self-loops
+    key = rows.astype(np.int64) * g.n + g.cols
+    assert np.all(np.diff(key) > 0)                         # sorted, no duplicates
+    rev = np.sort(g.cols.astype(np.int64) * g.n + rows)
+    assert np.array_equal(rev, key)                         # symmetric
+    if g.weights is not None:
+        order = np.argsort(g.cols.astype(np.int64) * g.n + rows)
+        assert np.array_equal(g.weights[order], g.weights)  # w_ij = w_ji
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gi.planted_sbm_10k(),
+    lambda: gi.rmat_small(12, 1),
+    lambda: gi.rmat_small(12, 2, weights=(1.0, 10.0)),
+    lambda: gi.sbm(3000, 7, 0.05, 0.001, 5, weights=(1.0, 4.0)),
+])
+def test_valid_and_deterministic(make):
+    a, b = make(), make()
+    _check_csr(a)
+    assert np.array_equal(a.offsets, b.offsets) and np.array_equal(a.cols, b.cols)
+    if a.weights is not None:
+        assert np.array_equal(a.weights, b.weights)
+        assert a.weights.min() >= 1.0
+
+
+def test_planted_sbm_shape():
+    g = gi.planted_sbm_10k()
+    assert g.n == 10_000
+    assert 19.0 < g.nnz / g.n < 21.0                        # expected degree 20
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    intra = (g.block[rows] == g.block[g.cols]).mean()
+    assert 0.78 < intra < 0.82                              # 80% intra-block
+    assert np.all(np.bincount(g.block) == 100)
+
+
+def test_batch_params():
+    ps = gi.batch_sbm_params(512)
+    ns = np.array([p["n"] for p in ps])
+    assert ns.min() >= 1000 and ns.max() <= 200_000
