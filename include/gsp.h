@@ -1,0 +1,204 @@
+/*
+ * gsp.h - C ABI of the GSP-Louvain library for AMD Instinct MI355X (gfx950).
+ *
+ * GSP-Louvain (Sahu, arXiv 2402.11454) finds disjoint communities of an
+ * undirected weighted graph by modularity maximisation (Eq. 1).  Each pass of
+ * Algorithm "louvain" runs the local-moving phase (Algorithm "louvainMove",
+ * gains by Eq. 2), splits every internally-disconnected community into its
+ * connected parts (Section 4.1, split in every pass), renumbers the
+ * communities, updates the top-level membership (dendrogram lookup) and
+ * aggregates the communities into super-vertices (Algorithm
+ * "louvainAggregate").  This library runs every step on one GPU.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * - Graphs are CSR with both directions of every undirected edge stored
+ *   (Section 3: w_ij = w_ji).  A self-loop is stored once, in its own row.
+ *   Offsets are int64 (n+1 entries, offsets[0] = 0, non-decreasing,
+ *   offsets[n] = nnz); columns are int32 in [0, n); weights are finite and
+ *   >= 0, fp32 or fp64, or NULL for unit weights.  Rows may be unsorted.
+ *   K_i is the row sum; 2m (M2) is the sum of all entries.
+ * - `where` says where a pointer lives: GSP_HOST (pageable or pinned host
+ *   memory) or GSP_DEVICE (device memory on the context's GPU).
+ * - Memberships and labels are int32 values in [0, n).
+ * - Inputs are copied or only read during the call; the caller keeps
+ *   ownership of every buffer it passes.  Outputs go to caller buffers.
+ * - Every function returns a gsp_status.  On failure the context keeps a
+ *   message readable with gsp_last_error(); no exception or abort crosses
+ *   the ABI.  GSP_EHIP carries the HIP runtime's error string.
+ * - All GPU work is ordered on the context's stream; every entry point
+ *   returns after its work has completed (host outputs are valid, device
+ *   outputs are written).
+ * - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef GSP_H
+#define GSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsp_ctx gsp_ctx;
+
+typedef enum gsp_status {
+    GSP_OK = 0,
+    GSP_EINVAL = -1,  /* bad argument (NULL pointer, negative size, label out of range) */
+    GSP_ENOMEM = -2,  /* device allocation failed or exceeds mem_limit_bytes */
+    GSP_EHIP = -3,    /* HIP runtime error */
+    GSP_ESTATE = -4,  /* call out of order (no graph loaded, no result yet) */
+    GSP_EGRAPH = -5   /* malformed CSR (offsets, columns, weights) */
+} gsp_status;
+
+enum { GSP_HOST = 0, GSP_DEVICE = 1 };
+
+/* When the split of internally-disconnected communities runs (Section 4.1). */
+enum { GSP_SPLIT_PASS = 0, GSP_SPLIT_LAST = 1, GSP_SPLIT_NONE = 2 };
+
+#define GSP_MAX_PASSES_STATS 64
+
+typedef struct gsp_options {
+    int32_t max_iterations;        /* MAX_ITERATIONS of the local-moving phase (default 20) */
+    int32_t sub_rounds;            /* ordered sub-rounds per iteration, power of two 1..64 (default 8) */
+    double tolerance_drop;         /* TOLERANCE_DROP of threshold scaling (default 10) */
+    double aggregation_tolerance;  /* tau_agg: stop when |Gamma|/N' exceeds it (default 0.8) */
+    int32_t split_mode;            /* GSP_SPLIT_PASS (default), GSP_SPLIT_LAST or GSP_SPLIT_NONE */
+    int32_t timing;                /* 0: none; 1: per-phase HIP-event times; 2: also per-kernel times */
+    uint64_t mem_limit_bytes;      /* refuse device allocations beyond this total (0 = no limit) */
+} gsp_options;
+
+/* Per-kernel-class counters (timing = 2). */
+enum {
+    GSP_K_MOVE_SMALL = 0,  /* local-move scan+decide, degree <= 64 (sub-wave groups) */
+    GSP_K_MOVE_LARGE,      /* local-move scan+decide, 64 < degree <= 2048 (wave / workgroup) */
+    GSP_K_MOVE_HUB,        /* local-move scan+decide, degree > 2048 (global tables) */
+    GSP_K_MOVE_APPLY,      /* apply moves, community totals */
+    GSP_K_FRONTIER,        /* sub-round queue compaction */
+    GSP_K_SPLIT,           /* split: union-find hooking and compression */
+    GSP_K_AGGREGATE,       /* aggregation kernels */
+    GSP_K_OTHER,           /* weights, renumber, lookup, scans */
+    GSP_K_COUNT
+};
+
+typedef struct gsp_kernel_stat {
+    int64_t launches;
+    double ms;             /* summed HIP-event time of the launches */
+    double bytes;          /* algorithmic bytes of those launches (see the library's notes) */
+    int64_t items;         /* work items: scanned entries for the move kernels */
+} gsp_kernel_stat;
+
+typedef struct gsp_stats {
+    int32_t passes;
+    int32_t iterations[GSP_MAX_PASSES_STATS];  /* l_i of each pass */
+    int64_t vertices[GSP_MAX_PASSES_STATS];    /* N' of each pass */
+    int64_t communities[GSP_MAX_PASSES_STATS]; /* |Gamma| after each pass's split */
+    int64_t moves;                             /* vertices moved, all passes */
+    int64_t scanned_entries;                   /* CSR entries scanned by the local-moving phase */
+    double ms_move, ms_split, ms_aggregate, ms_other, ms_total;  /* timing >= 1 */
+    gsp_kernel_stat kernels[GSP_K_COUNT];       /* timing = 2 */
+} gsp_stats;
+
+/* Fills *out with the defaults above. */
+gsp_status gsp_default_options(gsp_options *out);
+
+/* Creates a context on HIP device `device`.  hip_stream is a hipStream_t to
+ * run on (the caller keeps it alive for the context's life), or NULL for a
+ * stream the context creates (default priority) and destroys. */
+gsp_status gsp_create(int device, void *hip_stream, gsp_ctx **out);
+
+/* Frees every device buffer of the context and the context itself. */
+gsp_status gsp_destroy(gsp_ctx *ctx);
+
+/* Last error message of the context ("" if none).  Valid until the next call
+ * on the context.  Accepts NULL (returns a static message). */
+const char *gsp_last_error(const gsp_ctx *ctx);
+
+/* Loads the graph G (Section 3) and validates it on the device: offsets
+ * start at 0, never decrease and end at nnz; columns lie in [0, n); weights
+ * are finite and >= 0.  A malformed graph gives GSP_EGRAPH and leaves no
+ * graph loaded.  Symmetry is the caller's promise and is not checked.
+ * Replaces any graph loaded before and frees the previous result.
+ * weights = NULL means unit weights. */
+gsp_status gsp_load_csr(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                        const float *weights, int where);
+
+/* Same with int32 offsets (graphs below 2^31 entries). */
+gsp_status gsp_load_csr32(gsp_ctx *ctx, int32_t n, int32_t nnz, const int32_t *offsets, const int32_t *cols,
+                          const float *weights, int where);
+
+/* Same with fp64 weights (e.g. super-vertex graphs with self-loops). */
+gsp_status gsp_load_csr_f64(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                            const double *weights, int where);
+
+/* Runs GSP-Louvain (Algorithm "louvain") on the loaded graph with iteration
+ * tolerance `tolerance` (tau of the first pass) and at most max_passes
+ * passes (max_passes = 0 leaves every vertex alone).  opt = NULL uses
+ * gsp_default_options.  The local-moving phase is synchronous in ordered
+ * sub-rounds: vertex i belongs to sub-round (i * 0x9E3779B97F4A7C15) >> (64 -
+ * log2 sub_rounds); within a sub-round every decision comes from one
+ * snapshot of memberships and community totals; ties go to the lowest
+ * community id; a vertex moves only for a positive gain, and a vertex alone
+ * in its community does not join another one-vertex community with a larger
+ * id.  Communities of the result are numbered by ascending smallest vertex
+ * id.  The result stays in the context until the next load or run. */
+gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *opt);
+
+/* Copies the last run's membership (n values) to out. */
+gsp_status gsp_get_membership(gsp_ctx *ctx, int32_t *out, int where);
+
+/* Modularity (Eq. 1) of the last run's membership. */
+gsp_status gsp_get_modularity(gsp_ctx *ctx, double *out);
+
+/* Statistics of the last run. */
+gsp_status gsp_get_stats(gsp_ctx *ctx, gsp_stats *out);
+
+/* Modularity (Eq. 1, community form) of `membership` on the loaded graph,
+ * in fp64.  Labels outside [0, n) give GSP_EINVAL. */
+gsp_status gsp_modularity(gsp_ctx *ctx, const int32_t *membership, int where, double *out);
+
+/* Number of communities of `membership` that are internally disconnected
+ * (Algorithm "disconnectedCommunities"). */
+gsp_status gsp_count_disconnected(gsp_ctx *ctx, const int32_t *membership, int where, int64_t *out);
+
+/* ---- stepwise hooks on the loaded graph (used to check each step) ---- */
+
+/* One synchronous local-moving step (Algorithm "louvainMove", gains by
+ * Eq. 2) from the snapshot given by `membership`: community totals and
+ * sizes are computed from it.  Vertices with active[i] = 0 stay (active =
+ * NULL: all).  dec_out[i] receives the chosen community (or the current
+ * one), gain_out[i] the gain numerator G(c*) - G(stay) with
+ * G(c) = M2 K_{i->c} - K_i Sigma_c and G(stay) = M2 K_{i->d} - K_i (Sigma_d - K_i)
+ * (0 for vertices that stay; gain_out may be NULL), *moved the number of
+ * movers.  All pointers share `where`. */
+gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t *active, int where,
+                         int32_t *dec_out, double *gain_out, int64_t *moved);
+
+/* The whole local-moving phase (iterations of ordered sub-rounds, as in
+ * gsp_run) on the loaded graph, starting from `membership_inout` (updated
+ * in place).  Returns l_i in *iterations; dq_iter / moved_iter (length
+ * max_iterations, may be NULL) receive each iteration's gain total
+ * (delta-modularity) and mover count.  Host pointers for the per-iteration
+ * arrays; `where` applies to membership_inout. */
+gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance,
+                          int32_t max_iterations, int32_t sub_rounds, int32_t *iterations, double *dq_iter,
+                          int64_t *moved_iter);
+
+/* Split of internally-disconnected communities (Section 4.1): labels_out[i]
+ * = smallest vertex id of i's connected component in the subgraph of edges
+ * whose ends share a community. */
+gsp_status gsp_step_split(gsp_ctx *ctx, const int32_t *membership, int where, int32_t *labels_out);
+
+/* Aggregation (Algorithm "louvainAggregate") of the loaded graph by
+ * `membership` after renumbering its labels in ascending order: super-vertex
+ * c of G'' is the c-th smallest label.  Row c holds (d, w) with w the sum of
+ * w_ij over entries with i in c and j in d (self-loops kept), fp64, in no
+ * particular order.  With offsets = NULL only *n_out and *nnz_out are set;
+ * otherwise offsets (n_out + 1), cols and weights (nnz_out) are filled. */
+gsp_status gsp_step_aggregate(gsp_ctx *ctx, const int32_t *membership, int where, int64_t *n_out,
+                              int64_t *nnz_out, int64_t *offsets, int32_t *cols, double *weights);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSP_H */

@@ -1,0 +1,943 @@
+// capi.hip - the C ABI (include/gsp.h) and the pass driver of Algorithm
+// "louvain": per pass, reset -> local moving (synchronous sub-rounds) ->
+// split -> renumber + dendrogram lookup -> convergence tests -> aggregation
+// -> threshold scaling.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/gsp.h"
+#include "gsp_internal.h"
+
+using namespace gsp;
+
+namespace {
+
+struct EventPair {
+    int cls;
+    hipEvent_t a, b;
+};
+
+// Records HIP events around phases / kernel classes and sums them later.
+struct Timer {
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<EventPair> open;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void reset() {
+        used = 0;
+        open.clear();
+    }
+    int begin(int cls) {
+        hipEvent_t a = get(), b = get();
+        if (!a || !b) return -1;
+        (void)hipEventRecord(a, s);
+        open.push_back({cls, a, b});
+        return (int)open.size() - 1;
+    }
+    void end(int k) {
+        if (k >= 0) (void)hipEventRecord(open[k].b, s);
+    }
+    // Adds elapsed ms per class into out[cls].
+    void collect(double *out, int ncls) {
+        for (auto &p : open) {
+            float ms = 0.f;
+            if (p.cls >= 0 && p.cls < ncls && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) out[p.cls] += ms;
+        }
+        reset();
+    }
+    ~Timer() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+enum { PH_MOVE = 0, PH_SPLIT, PH_AGG, PH_OTHER, PH_COUNT };
+
+}  // namespace
+
+struct gsp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<void *> allocs;
+    uint64_t mem_used = 0;
+    uint64_t mem_limit = 0;
+
+    // input graph (level 0)
+    bool loaded = false;
+    int64_t n = 0, nnz = 0;
+    int wt0 = W_UNIT;
+    int64_t *off0 = nullptr;
+    int32_t *col0 = nullptr;
+    void *w0 = nullptr;
+    int32_t *deg0 = nullptr;
+    double *K0 = nullptr;
+    double M2 = 0.0;
+
+    // super-vertex levels (ping-pong) and the gapped aggregation rows
+    int64_t *offL[2] = {nullptr, nullptr};
+    int32_t *colL[2] = {nullptr, nullptr};
+    double *wL[2] = {nullptr, nullptr};
+    int32_t *degL[2] = {nullptr, nullptr};
+    double *KL[2] = {nullptr, nullptr};
+    int32_t *gap_col = nullptr;
+    double *gap_w = nullptr;
+
+    // per-vertex work arrays
+    double *sig = nullptr;
+    int32_t *cm = nullptr, *csize = nullptr, *dec = nullptr, *movers = nullptr, *queue = nullptr;
+    int32_t *lab = nullptr, *top = nullptr, *bl = nullptr, *tmp32 = nullptr;
+    uint8_t *flag = nullptr, *hub_act = nullptr;
+    int64_t *hub_off = nullptr;
+    double *gain_tmp = nullptr;
+    Scratch sc;
+    IterCounters *ctr = nullptr;      // device, 2 slots
+    IterCounters *ctr_h = nullptr;    // pinned host mirror
+    int64_t *i64_h = nullptr;         // pinned host scalars
+    double *f64_h = nullptr;
+
+    // last result
+    bool have_result = false;
+    bool have_q = false;
+    double q = 0.0;
+    gsp_stats stats;
+    Timer timer;
+    int64_t kernel_launches[GSP_K_COUNT] = {0};
+
+    gsp_status fail(gsp_status st, const std::string &msg) {
+        err = msg;
+        return st;
+    }
+    gsp_status fail_hip(hipError_t e, const char *what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? GSP_ENOMEM : GSP_EHIP;
+    }
+    template <class T>
+    T *dalloc(size_t count, hipError_t *e) {
+        void *p = nullptr;
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        *e = hipMalloc(&p, bytes);
+        if (*e != hipSuccess) return nullptr;
+        allocs.push_back(p);
+        mem_used += bytes;
+        return (T *)p;
+    }
+    void free_graph() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void *p : allocs) (void)hipFree(p);
+        allocs.clear();
+        mem_used = 0;
+        if (sc.hkeys) (void)hipFree(sc.hkeys);
+        if (sc.hvals) (void)hipFree(sc.hvals);
+        sc = Scratch();
+        for (int k = 0; k < 2; k++) {
+            offL[k] = nullptr;
+            colL[k] = nullptr;
+            wL[k] = nullptr;
+            degL[k] = nullptr;
+            KL[k] = nullptr;
+        }
+        gap_col = nullptr;
+        gap_w = nullptr;
+        ctr = nullptr;
+        loaded = false;
+        have_result = false;
+        have_q = false;
+        n = nnz = 0;
+    }
+};
+
+namespace gsp {
+
+hipError_t ensure_hub_tables(Scratch &sc, uint64_t slots, hipStream_t s) {
+    if (slots <= sc.hcap) return hipSuccess;
+    uint64_t cap = std::max<uint64_t>(slots, sc.hcap + sc.hcap / 2);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (sc.hkeys) (void)hipFree(sc.hkeys);
+    if (sc.hvals) (void)hipFree(sc.hvals);
+    sc.hkeys = nullptr;
+    sc.hvals = nullptr;
+    sc.hcap = 0;
+    e = hipMalloc(&sc.hkeys, cap * sizeof(int));
+    if (e != hipSuccess) return e;
+    e = hipMalloc(&sc.hvals, cap * sizeof(double));
+    if (e != hipSuccess) return e;
+    sc.hcap = cap;
+    launch_fill_i32(sc.hkeys, kEmpty, (int64_t)cap, s);
+    launch_fill_f64(sc.hvals, 0.0, (int64_t)cap, s);
+    return hipGetLastError();
+}
+
+}  // namespace gsp
+
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return ctx->fail_hip(_e, #expr); \
+    } while (0)
+
+namespace {
+
+Level level0(const gsp_ctx *ctx) {
+    Level g;
+    g.n = ctx->n;
+    g.nnz = ctx->nnz;
+    g.off = ctx->off0;
+    g.col = ctx->col0;
+    g.w = ctx->w0;
+    g.wt = ctx->wt0;
+    g.deg = ctx->deg0;
+    return g;
+}
+
+WorkLists make_lists(gsp_ctx *ctx) {
+    WorkLists wl;
+    wl.bl = ctx->bl;
+    wl.hub_off = ctx->hub_off;
+    return wl;
+}
+
+bool valid_rounds(int r) { return r >= 1 && r <= kMaxRounds && (r & (r - 1)) == 0; }
+
+gsp_status copy_in_i32(gsp_ctx *ctx, int32_t *dst, const int32_t *src, int64_t count, int where) {
+    if (count == 0) return GSP_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(int32_t),
+                           where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    return GSP_OK;
+}
+
+template <class T>
+gsp_status copy_out(gsp_ctx *ctx, T *dst, const T *src, int64_t count, int where) {
+    if (count == 0) return GSP_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(T),
+                           where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    return GSP_OK;
+}
+
+// Copies a caller membership into ctx->cm and checks every label is in [0, n).
+gsp_status take_membership(gsp_ctx *ctx, const int32_t *memb, int where) {
+    if (!ctx->loaded) return ctx->fail(GSP_ESTATE, "no graph loaded");
+    if (!memb && ctx->n > 0) return ctx->fail(GSP_EINVAL, "membership is NULL");
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    gsp_status st = copy_in_i32(ctx, ctx->cm, memb, ctx->n, where);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipMemsetAsync(ctx->sc.err, 0, sizeof(int), ctx->stream));
+    launch_check_labels(ctx->cm, ctx->n, ctx->sc.err, ctx->stream);
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, ctx->sc.err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (bad) return ctx->fail(GSP_EINVAL, "membership label outside [0, n)");
+    return GSP_OK;
+}
+
+// Renumbers labels (values in [0, n)) by ascending label into out; the
+// number of labels in use goes to *count (host).
+gsp_status renumber(gsp_ctx *ctx, const int32_t *labels, int64_t n, int32_t *out, int64_t *count) {
+    launch_renumber(labels, n, out, ctx->sc.i32a, ctx->sc.i32b, ctx->sc.i64e, ctx->sc.scan_tmp, ctx->stream);
+    HIP_TRY(hipMemcpyAsync(ctx->i64_h, ctx->sc.i64e, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *count = ctx->i64_h[0];
+    return GSP_OK;
+}
+
+// Algorithmic bytes of a scan+decide class (per processed vertex: offset,
+// degree, membership, K, Sigma of the own community, size; per entry:
+// column, weight, neighbour membership; per distinct key: Sigma; per mover:
+// decision, mover slot and one flag byte per entry).
+double move_bytes(int64_t verts, int64_t entries, int64_t keys, int wt) {
+    int ws = wt == W_UNIT ? 0 : (wt == W_F32 ? 4 : 8);
+    return 36.0 * (double)verts + (8.0 + ws) * (double)entries + 8.0 * (double)keys;
+}
+
+// The local-moving phase on level g (Algorithm "louvainMove" in ordered
+// sub-rounds).  cm/sig/csize hold the starting state; returns l_i.
+gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkLists &wl, double tau,
+                      int max_iter, bool timing_k, double *dq_out, int64_t *moved_out, int32_t *li_out,
+                      double *kernel_bytes) {
+    hipStream_t s = ctx->stream;
+    int P = wl.rounds;
+    launch_fill_u8(ctx->flag, 1, g.n, s);
+    int li = 0;
+    for (int it = 0; it < max_iter; it++) {
+        IterCounters *ctr = ctx->ctr + (it & 1);
+        HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(IterCounters), s));
+        for (int p = 0; p < P; p++) {
+            MoveArgs a;
+            a.g = g;
+            a.K = K;
+            a.sig = ctx->sig;
+            a.csize = ctx->csize;
+            a.cm = ctx->cm;
+            a.M2 = ctx->M2;
+            a.flag = ctx->flag;
+            a.dec = ctx->dec;
+            a.gain_out = nullptr;
+            a.movers = ctx->movers;
+            a.queue = ctx->queue;
+            int64_t cap = 0;
+            for (int b = 0; b < kNumBins; b++) {
+                a.qbase[b] = wl.bucket_begin(b, p);
+                a.qcap[b] = wl.bucket_size(b, p);
+                cap += a.qcap[b];
+            }
+            a.ctr = ctr;
+            a.round = p;
+            a.ch_vert = wl.ch_vert;
+            a.ch_beg = wl.ch_beg;
+            a.ch_first = wl.ch_poff[p];
+            a.ch_count = wl.ch_poff[p + 1] - wl.ch_poff[p];
+            a.hub_off = wl.hub_off;
+            a.hub_act = ctx->hub_act;
+            a.hkeys = ctx->sc.hkeys;
+            a.hvals = ctx->sc.hvals;
+            if (cap == 0) continue;
+            int t;
+            t = timing_k ? ctx->timer.begin(100 + GSP_K_FRONTIER) : -1;
+            launch_move_compact(a, wl, s);
+            ctx->timer.end(t);
+            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL) : -1;
+            launch_move_small(a, wl, s);
+            ctx->timer.end(t);
+            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_LARGE) : -1;
+            launch_move_large(a, wl, s);
+            ctx->timer.end(t);
+            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
+            launch_move_hub(a, wl, s);
+            ctx->timer.end(t);
+            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
+            launch_move_apply(a, cap, s);
+            ctx->timer.end(t);
+            if (timing_k) {
+                ctx->kernel_launches[GSP_K_FRONTIER]++;
+                ctx->kernel_launches[GSP_K_MOVE_SMALL]++;
+                ctx->kernel_launches[GSP_K_MOVE_LARGE]++;
+                ctx->kernel_launches[GSP_K_MOVE_HUB] += 2;
+                ctx->kernel_launches[GSP_K_MOVE_APPLY]++;
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const IterCounters &h = *ctx->ctr_h;
+        double dq = ctx->M2 > 0.0 ? (2.0 * h.gain) / (ctx->M2 * ctx->M2) : 0.0;
+        if (dq_out) dq_out[it] = dq;
+        if (moved_out) moved_out[it] = (int64_t)h.moved;
+        ctx->stats.moves += (int64_t)h.moved;
+        for (int c = 0; c < 3; c++) {
+            ctx->stats.scanned_entries += (int64_t)h.scanned[c];
+            ctx->stats.kernels[GSP_K_MOVE_SMALL + c].items += (int64_t)h.scanned[c];
+            if (kernel_bytes)
+                kernel_bytes[GSP_K_MOVE_SMALL + c] +=
+                    move_bytes((int64_t)h.verts[c], (int64_t)h.scanned[c], (int64_t)h.keys[c], g.wt);
+        }
+        li = it + 1;
+        if (dq <= tau) break;
+    }
+    *li_out = li;
+    return GSP_OK;
+}
+
+gsp_status ensure_levels(gsp_ctx *ctx) {
+    if (ctx->offL[0]) return GSP_OK;
+    if (ctx->mem_limit) {
+        uint64_t need = 2 * ((ctx->n + 1) * 8 + ctx->nnz * 12 + ctx->n * 12) + ctx->nnz * 12;
+        if (ctx->mem_used + need > ctx->mem_limit)
+            return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
+    }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2; k++) {
+        ctx->offL[k] = ctx->dalloc<int64_t>(ctx->n + 1, &e);
+        if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(level offsets)");
+        ctx->colL[k] = ctx->dalloc<int32_t>(ctx->nnz, &e);
+        if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(level columns)");
+        ctx->wL[k] = ctx->dalloc<double>(ctx->nnz, &e);
+        if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(level weights)");
+        ctx->degL[k] = ctx->dalloc<int32_t>(ctx->n, &e);
+        if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(level degrees)");
+        ctx->KL[k] = ctx->dalloc<double>(ctx->n, &e);
+        if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(level weights K)");
+    }
+    ctx->gap_col = ctx->dalloc<int32_t>(ctx->nnz, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gap columns)");
+    ctx->gap_w = ctx->dalloc<double>(ctx->nnz, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gap weights)");
+    return GSP_OK;
+}
+
+// Loads a CSR given as int64 offsets (off64) or int32 offsets (off32).
+gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64, const int32_t *off32,
+                     const int32_t *cols, const void *weights, int wt, int where) {
+    if (n < 0 || nnz < 0) return ctx->fail(GSP_EINVAL, "negative size");
+    if (n > 0x7fffffffLL - 1) return ctx->fail(GSP_EINVAL, "n must be below 2^31 - 1 (int32 vertex ids)");
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    if (!off64 && !off32) return ctx->fail(GSP_EINVAL, "offsets is NULL");
+    if (nnz > 0 && !cols) return ctx->fail(GSP_EINVAL, "cols is NULL");
+    ctx->free_graph();
+    hipError_t e = hipSuccess;
+    hipStream_t s = ctx->stream;
+    auto A = [&](auto *&ptr, size_t count, const char *what) -> gsp_status {
+        using T = std::remove_reference_t<decltype(*ptr)>;
+        ptr = ctx->dalloc<T>(count, &e);
+        if (e != hipSuccess) {
+            gsp_status st = ctx->fail_hip(e, what);
+            ctx->free_graph();
+            return st;
+        }
+        return GSP_OK;
+    };
+    gsp_status st;
+    int64_t n1 = n + 1;
+    if ((st = A(ctx->off0, n1, "hipMalloc(offsets)")) != GSP_OK) return st;
+    if ((st = A(ctx->col0, nnz, "hipMalloc(cols)")) != GSP_OK) return st;
+    if (wt == W_F32) {
+        float *w = nullptr;
+        if ((st = A(w, nnz, "hipMalloc(weights)")) != GSP_OK) return st;
+        ctx->w0 = w;
+    } else if (wt == W_F64) {
+        double *w = nullptr;
+        if ((st = A(w, nnz, "hipMalloc(weights)")) != GSP_OK) return st;
+        ctx->w0 = w;
+    }
+    if ((st = A(ctx->deg0, n, "hipMalloc(deg)")) != GSP_OK) return st;
+    if ((st = A(ctx->K0, n, "hipMalloc(K)")) != GSP_OK) return st;
+    if ((st = A(ctx->sig, n, "hipMalloc(sigma)")) != GSP_OK) return st;
+    if ((st = A(ctx->cm, n, "hipMalloc(membership)")) != GSP_OK) return st;
+    if ((st = A(ctx->csize, n, "hipMalloc(sizes)")) != GSP_OK) return st;
+    if ((st = A(ctx->dec, n, "hipMalloc(decisions)")) != GSP_OK) return st;
+    if ((st = A(ctx->movers, n, "hipMalloc(movers)")) != GSP_OK) return st;
+    if ((st = A(ctx->queue, n, "hipMalloc(queue)")) != GSP_OK) return st;
+    if ((st = A(ctx->lab, n, "hipMalloc(labels)")) != GSP_OK) return st;
+    if ((st = A(ctx->top, n, "hipMalloc(top membership)")) != GSP_OK) return st;
+    if ((st = A(ctx->bl, n, "hipMalloc(work lists)")) != GSP_OK) return st;
+    if ((st = A(ctx->tmp32, n + 1, "hipMalloc(tmp)")) != GSP_OK) return st;
+    if ((st = A(ctx->flag, n, "hipMalloc(flags)")) != GSP_OK) return st;
+    if ((st = A(ctx->hub_act, n, "hipMalloc(hub flags)")) != GSP_OK) return st;
+    if ((st = A(ctx->hub_off, n, "hipMalloc(hub offsets)")) != GSP_OK) return st;
+    if ((st = A(ctx->gain_tmp, n, "hipMalloc(gains)")) != GSP_OK) return st;
+    Scratch &sc = ctx->sc;
+    sc.n_cap = n;
+    sc.nnz_cap = nnz;
+    sc.scan_tmp_bytes = scan_tmp_bytes(n1 > nnz ? n1 : nnz);
+    char *stmp = nullptr;
+    if ((st = A(stmp, sc.scan_tmp_bytes, "hipMalloc(scan)")) != GSP_OK) return st;
+    sc.scan_tmp = stmp;
+    for (int64_t **p : {&sc.i64a, &sc.i64b, &sc.i64c, &sc.i64d, &sc.i64e})
+        if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
+    for (int32_t **p : {&sc.i32a, &sc.i32b, &sc.i32c, &sc.i32d, &sc.bl2})
+        if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
+    if ((st = A(sc.err, 4, "hipMalloc(err)")) != GSP_OK) return st;
+    if ((st = A(sc.u64, 2 * kNumBuckets + 16, "hipMalloc(counters)")) != GSP_OK) return st;
+    if ((st = A(sc.f64, 16, "hipMalloc(scalars)")) != GSP_OK) return st;
+    sc.ch_cap = nnz / 1024 + 16;
+    if ((st = A(sc.ch_vert, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(sc.ch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(ctx->ctr, 2, "hipMalloc(iteration counters)")) != GSP_OK) return st;
+
+    // copy in
+    hipMemcpyKind kind = where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (off64) {
+        HIP_TRY(hipMemcpyAsync(ctx->off0, off64, n1 * sizeof(int64_t), kind, s));
+    } else {
+        HIP_TRY(hipMemcpyAsync(ctx->tmp32, off32, n1 * sizeof(int32_t), kind, s));
+        launch_offsets_from_i32(ctx->tmp32, ctx->off0, n1, s);
+    }
+    if (nnz) HIP_TRY(hipMemcpyAsync(ctx->col0, cols, nnz * sizeof(int32_t), kind, s));
+    if (wt == W_F32 && nnz) HIP_TRY(hipMemcpyAsync(ctx->w0, weights, nnz * sizeof(float), kind, s));
+    if (wt == W_F64 && nnz) HIP_TRY(hipMemcpyAsync(ctx->w0, weights, nnz * sizeof(double), kind, s));
+    HIP_TRY(hipMemsetAsync(sc.err, 0, sizeof(int), s));
+    launch_validate(ctx->off0, ctx->col0, ctx->w0, wt, n, nnz, sc.err, s);
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, sc.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) {
+        ctx->free_graph();
+        std::string m = "malformed CSR:";
+        if (bad & 1) m += " offsets (must start at 0, not decrease, end at nnz, rows below 2^31 entries)";
+        if (bad & 2) m += " column outside [0, n)";
+        if (bad & 4) m += " weight negative, NaN or infinite";
+        return ctx->fail(GSP_EGRAPH, m);
+    }
+    ctx->n = n;
+    ctx->nnz = nnz;
+    ctx->wt0 = wt;
+    launch_degrees(ctx->off0, ctx->deg0, n, s);
+    HIP_TRY(hipMemsetAsync(sc.f64, 0, sizeof(double), s));
+    Level g = level0(ctx);
+    launch_vertex_weights(g, ctx->K0, sc.f64, s);
+    HIP_TRY(hipMemcpyAsync(ctx->f64_h, sc.f64, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    ctx->M2 = ctx->f64_h[0];
+    ctx->loaded = true;
+    return GSP_OK;
+}
+
+gsp_status check_where(gsp_ctx *ctx, int where) {
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    return GSP_OK;
+}
+
+// Q = sigma_in / M2 - sum_c (Sigma_c / M2)^2 of membership m (device, valid).
+gsp_status modularity_of(gsp_ctx *ctx, const int32_t *m, double *out) {
+    hipStream_t s = ctx->stream;
+    if (ctx->M2 <= 0.0) {
+        *out = 0.0;
+        return GSP_OK;
+    }
+    launch_fill_f64(ctx->sig, 0.0, ctx->n, s);
+    HIP_TRY(hipMemsetAsync(ctx->sc.f64, 0, 2 * sizeof(double), s));
+    launch_modularity_parts(level0(ctx), m, ctx->K0, ctx->sig, ctx->sc.f64, s);
+    launch_sum_squares(ctx->sig, ctx->n, ctx->M2, ctx->sc.f64 + 1, s);
+    HIP_TRY(hipMemcpyAsync(ctx->f64_h, ctx->sc.f64, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    *out = ctx->f64_h[0] / ctx->M2 - ctx->f64_h[1];
+    return GSP_OK;
+}
+
+}  // namespace
+
+// =====================================================================
+// C ABI
+// =====================================================================
+
+extern "C" {
+
+gsp_status gsp_default_options(gsp_options *out) {
+    if (!out) return GSP_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->max_iterations = 20;
+    out->sub_rounds = 8;
+    out->tolerance_drop = 10.0;
+    out->aggregation_tolerance = 0.8;
+    out->split_mode = GSP_SPLIT_PASS;
+    out->timing = 0;
+    out->mem_limit_bytes = 0;
+    return GSP_OK;
+}
+
+gsp_status gsp_create(int device, void *hip_stream, gsp_ctx **out) {
+    if (!out) return GSP_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSP_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return GSP_EHIP;
+    gsp_ctx *ctx = new (std::nothrow) gsp_ctx();
+    if (!ctx) return GSP_ENOMEM;
+    ctx->device = device;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return GSP_EHIP;
+        }
+        ctx->own_stream = true;
+    }
+    if (hipHostMalloc((void **)&ctx->ctr_h, sizeof(IterCounters), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->i64_h, 8 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->f64_h, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        gsp_destroy(ctx);
+        return GSP_ENOMEM;
+    }
+    ctx->timer.s = ctx->stream;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    *out = ctx;
+    return GSP_OK;
+}
+
+gsp_status gsp_destroy(gsp_ctx *ctx) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    ctx->free_graph();
+    if (ctx->ctr_h) (void)hipHostFree(ctx->ctr_h);
+    if (ctx->i64_h) (void)hipHostFree(ctx->i64_h);
+    if (ctx->f64_h) (void)hipHostFree(ctx->f64_h);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GSP_OK;
+}
+
+const char *gsp_last_error(const gsp_ctx *ctx) {
+    if (!ctx) return "no context";
+    return ctx->err.c_str();
+}
+
+gsp_status gsp_load_csr(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                        const float *weights, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return load_impl(ctx, n, nnz, offsets, nullptr, cols, weights, weights ? W_F32 : W_UNIT, where);
+}
+
+gsp_status gsp_load_csr32(gsp_ctx *ctx, int32_t n, int32_t nnz, const int32_t *offsets, const int32_t *cols,
+                          const float *weights, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!offsets) return ctx->fail(GSP_EINVAL, "offsets is NULL");
+    return load_impl(ctx, n, nnz, nullptr, offsets, cols, weights, weights ? W_F32 : W_UNIT, where);
+}
+
+gsp_status gsp_load_csr_f64(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                            const double *weights, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return load_impl(ctx, n, nnz, offsets, nullptr, cols, weights, weights ? W_F64 : W_UNIT, where);
+}
+
+gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *optp) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->loaded) return ctx->fail(GSP_ESTATE, "no graph loaded");
+    gsp_options opt;
+    if (optp)
+        opt = *optp;
+    else
+        gsp_default_options(&opt);
+    if (!(tolerance >= 0.0) || max_passes < 0) return ctx->fail(GSP_EINVAL, "tolerance < 0 or max_passes < 0");
+    if (opt.max_iterations < 0 || !valid_rounds(opt.sub_rounds) || !(opt.tolerance_drop > 0.0) ||
+        opt.split_mode < 0 || opt.split_mode > 2)
+        return ctx->fail(GSP_EINVAL, "bad options (sub_rounds must be a power of two in [1, 64])");
+    ctx->mem_limit = opt.mem_limit_bytes;
+    if (ctx->mem_limit && ctx->mem_used > ctx->mem_limit)
+        return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
+    gsp_status st = ensure_levels(ctx);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    ctx->have_result = false;
+    ctx->have_q = false;
+    memset(&ctx->stats, 0, sizeof(ctx->stats));
+    ctx->timer.reset();
+    bool tphase = opt.timing >= 1, tk = opt.timing >= 2;
+    double kbytes[GSP_K_COUNT] = {0};
+    for (int k = 0; k < GSP_K_COUNT; k++) ctx->kernel_launches[k] = 0;
+    int t_all = tphase ? ctx->timer.begin(PH_COUNT) : -1;
+
+    launch_iota_i32(ctx->top, ctx->n, s);
+    Level g = level0(ctx);
+    const double *K = ctx->K0;
+    double tau = tolerance;
+    int next = 0;
+    int passes = 0;
+    for (int lp = 0; lp < max_passes; lp++) {
+        passes = lp + 1;
+        int t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
+        WorkLists wl = make_lists(ctx);
+        HIP_TRY(build_work_lists(g, opt.sub_rounds, wl, ctx->sc, s));
+        // Sigma' <- K'; C' <- [0 .. |V'|); sizes 1
+        launch_iota_i32(ctx->cm, g.n, s);
+        HIP_TRY(hipMemcpyAsync(ctx->sig, K, g.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_fill_i32(ctx->csize, 1, g.n, s);
+        ctx->timer.end(t);
+        t = tphase ? ctx->timer.begin(PH_MOVE) : -1;
+        int32_t li = 0;
+        st = move_phase(ctx, g, K, wl, tau, opt.max_iterations, tk, nullptr, nullptr, &li, kbytes);
+        if (st != GSP_OK) return st;
+        ctx->timer.end(t);
+        const int32_t *labels = ctx->cm;
+        if (opt.split_mode == GSP_SPLIT_PASS) {
+            t = tphase ? ctx->timer.begin(PH_SPLIT) : -1;
+            int tk1 = tk ? ctx->timer.begin(100 + GSP_K_SPLIT) : -1;
+            launch_split(g, wl, ctx->cm, ctx->lab, s);
+            ctx->timer.end(tk1);
+            if (tk) ctx->kernel_launches[GSP_K_SPLIT] += 3;
+            ctx->timer.end(t);
+            labels = ctx->lab;
+        }
+        t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
+        int64_t ncomm = 0;
+        st = renumber(ctx, labels, g.n, ctx->cm, &ncomm);
+        if (st != GSP_OK) return st;
+        launch_lookup(ctx->top, ctx->n, ctx->cm, s);
+        ctx->timer.end(t);
+        if (lp < GSP_MAX_PASSES_STATS) {
+            ctx->stats.iterations[lp] = li;
+            ctx->stats.vertices[lp] = g.n;
+            ctx->stats.communities[lp] = ncomm;
+        }
+        if (li <= 1) break;                                               // globally converged
+        if ((double)ncomm / (double)g.n > opt.aggregation_tolerance) break; // low shrink
+        if (lp == max_passes - 1) break;                                   // G'' would be unused
+        t = tphase ? ctx->timer.begin(PH_AGG) : -1;
+        int tk2 = tk ? ctx->timer.begin(100 + GSP_K_AGGREGATE) : -1;
+        AggOut out{ctx->offL[next], ctx->colL[next], ctx->wL[next], ctx->KL[next], ctx->degL[next]};
+        int64_t nnz2 = 0;
+        HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s));
+        ctx->timer.end(tk2);
+        ctx->timer.end(t);
+        Level g2;
+        g2.n = ncomm;
+        g2.nnz = nnz2;
+        g2.off = out.off;
+        g2.col = out.col;
+        g2.w = out.w;
+        g2.wt = W_F64;
+        g2.deg = out.deg;
+        g = g2;
+        K = out.K;
+        next ^= 1;
+        tau = tau / opt.tolerance_drop;                                    // threshold scaling
+    }
+    if (opt.split_mode == GSP_SPLIT_LAST && ctx->n > 0) {
+        Level g0 = level0(ctx);
+        WorkLists wl = make_lists(ctx);
+        HIP_TRY(build_work_lists(g0, 1, wl, ctx->sc, s));
+        launch_split(g0, wl, ctx->top, ctx->lab, s);
+        HIP_TRY(hipMemcpyAsync(ctx->top, ctx->lab, ctx->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    if (opt.split_mode != GSP_SPLIT_PASS && ctx->n > 0) {
+        // number communities by ascending smallest vertex id
+        launch_canonical_labels(ctx->top, ctx->n, ctx->sc.i32c, ctx->lab, s);
+        int64_t G = 0;
+        st = renumber(ctx, ctx->lab, ctx->n, ctx->top, &G);
+        if (st != GSP_OK) return st;
+    }
+    ctx->timer.end(t_all);
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    ctx->stats.passes = passes;
+    if (tphase) {
+        double acc[100 + GSP_K_COUNT] = {0};
+        ctx->timer.collect(acc, 100 + GSP_K_COUNT);
+        ctx->stats.ms_move = acc[PH_MOVE];
+        ctx->stats.ms_split = acc[PH_SPLIT];
+        ctx->stats.ms_aggregate = acc[PH_AGG];
+        ctx->stats.ms_other = acc[PH_OTHER];
+        ctx->stats.ms_total = acc[PH_COUNT];
+        for (int k = 0; k < GSP_K_COUNT; k++) {
+            ctx->stats.kernels[k].ms = acc[100 + k];
+            ctx->stats.kernels[k].launches = ctx->kernel_launches[k];
+            ctx->stats.kernels[k].bytes = kbytes[k];
+        }
+    }
+    ctx->have_result = true;
+    return GSP_OK;
+}
+
+gsp_status gsp_get_membership(gsp_ctx *ctx, int32_t *out, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->have_result) return ctx->fail(GSP_ESTATE, "no result (call gsp_run)");
+    if (check_where(ctx, where) != GSP_OK) return GSP_EINVAL;
+    if (!out && ctx->n) return ctx->fail(GSP_EINVAL, "out is NULL");
+    gsp_status st = copy_out(ctx, out, ctx->top, ctx->n, where);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return GSP_OK;
+}
+
+gsp_status gsp_get_modularity(gsp_ctx *ctx, double *out) {
+    if (!ctx || !out) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->have_result) return ctx->fail(GSP_ESTATE, "no result (call gsp_run)");
+    if (!ctx->have_q) {
+        gsp_status st = modularity_of(ctx, ctx->top, &ctx->q);
+        if (st != GSP_OK) return st;
+        ctx->have_q = true;
+    }
+    *out = ctx->q;
+    return GSP_OK;
+}
+
+gsp_status gsp_get_stats(gsp_ctx *ctx, gsp_stats *out) {
+    if (!ctx || !out) return GSP_EINVAL;
+    if (!ctx->have_result) return ctx->fail(GSP_ESTATE, "no result (call gsp_run)");
+    *out = ctx->stats;
+    return GSP_OK;
+}
+
+gsp_status gsp_modularity(gsp_ctx *ctx, const int32_t *membership, int where, double *out) {
+    if (!ctx || !out) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    gsp_status st = take_membership(ctx, membership, where);
+    if (st != GSP_OK) return st;
+    return modularity_of(ctx, ctx->cm, out);
+}
+
+gsp_status gsp_count_disconnected(gsp_ctx *ctx, const int32_t *membership, int where, int64_t *out) {
+    if (!ctx || !out) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    gsp_status st = take_membership(ctx, membership, where);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    Level g = level0(ctx);
+    WorkLists wl = make_lists(ctx);
+    HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
+    launch_split(g, wl, ctx->cm, ctx->lab, s);
+    HIP_TRY(hipMemsetAsync(ctx->sc.u64, 0, sizeof(unsigned long long), s));
+    launch_count_disconnected(ctx->lab, ctx->cm, ctx->n, ctx->sc.i32a, ctx->sc.u64, s);
+    HIP_TRY(hipMemcpyAsync(ctx->i64_h, ctx->sc.u64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    *out = ctx->i64_h[0];
+    return GSP_OK;
+}
+
+gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t *active, int where,
+                         int32_t *dec_out, double *gain_out, int64_t *moved) {
+    if (!ctx || !moved) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!dec_out && ctx->n) return ctx->fail(GSP_EINVAL, "dec_out is NULL");
+    gsp_status st = take_membership(ctx, membership, where);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    Level g = level0(ctx);
+    launch_fill_f64(ctx->sig, 0.0, g.n, s);
+    launch_fill_i32(ctx->csize, 0, g.n, s);
+    launch_community_totals(ctx->K0, ctx->cm, g.n, ctx->sig, ctx->csize, s);
+    if (active) {
+        if (g.n)
+            HIP_TRY(hipMemcpyAsync(ctx->flag, active, g.n, where == GSP_DEVICE ? hipMemcpyDeviceToDevice
+                                                                                : hipMemcpyHostToDevice, s));
+    } else {
+        launch_fill_u8(ctx->flag, 1, g.n, s);
+    }
+    WorkLists wl = make_lists(ctx);
+    HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
+    launch_copy_i32(ctx->dec, ctx->cm, g.n, s);
+    launch_fill_f64(ctx->gain_tmp, 0.0, g.n, s);
+    IterCounters *ctr = ctx->ctr;
+    HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(IterCounters), s));
+    MoveArgs a;
+    a.g = g;
+    a.K = ctx->K0;
+    a.sig = ctx->sig;
+    a.csize = ctx->csize;
+    a.cm = ctx->cm;
+    a.M2 = ctx->M2;
+    a.flag = ctx->flag;
+    a.dec = ctx->dec;
+    a.gain_out = ctx->gain_tmp;
+    a.movers = ctx->movers;
+    a.queue = ctx->queue;
+    for (int b = 0; b < kNumBins; b++) {
+        a.qbase[b] = wl.bucket_begin(b, 0);
+        a.qcap[b] = wl.bucket_size(b, 0);
+    }
+    a.ctr = ctr;
+    a.round = 0;
+    a.ch_vert = wl.ch_vert;
+    a.ch_beg = wl.ch_beg;
+    a.ch_first = wl.ch_poff[0];
+    a.ch_count = wl.ch_poff[1] - wl.ch_poff[0];
+    a.hub_off = wl.hub_off;
+    a.hub_act = ctx->hub_act;
+    a.hkeys = ctx->sc.hkeys;
+    a.hvals = ctx->sc.hvals;
+    launch_move_compact(a, wl, s);
+    launch_move_small(a, wl, s);
+    launch_move_large(a, wl, s);
+    launch_move_hub(a, wl, s);
+    HIP_TRY(hipGetLastError());
+    st = copy_out(ctx, dec_out, ctx->dec, g.n, where);
+    if (st != GSP_OK) return st;
+    if (gain_out) {
+        st = copy_out(ctx, gain_out, ctx->gain_tmp, g.n, where);
+        if (st != GSP_OK) return st;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *moved = (int64_t)ctx->ctr_h->moved;
+    return GSP_OK;
+}
+
+gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance,
+                          int32_t max_iterations, int32_t sub_rounds, int32_t *iterations, double *dq_iter,
+                          int64_t *moved_iter) {
+    if (!ctx || !iterations) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (max_iterations < 0 || !valid_rounds(sub_rounds) || !(tolerance >= 0.0))
+        return ctx->fail(GSP_EINVAL, "bad max_iterations, sub_rounds or tolerance");
+    gsp_status st = take_membership(ctx, membership_inout, where);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    Level g = level0(ctx);
+    launch_fill_f64(ctx->sig, 0.0, g.n, s);
+    launch_fill_i32(ctx->csize, 0, g.n, s);
+    launch_community_totals(ctx->K0, ctx->cm, g.n, ctx->sig, ctx->csize, s);
+    WorkLists wl = make_lists(ctx);
+    HIP_TRY(build_work_lists(g, sub_rounds, wl, ctx->sc, s));
+    std::vector<double> dq(max_iterations > 0 ? max_iterations : 1);
+    std::vector<int64_t> mv(max_iterations > 0 ? max_iterations : 1);
+    int32_t li = 0;
+    st = move_phase(ctx, g, ctx->K0, wl, tolerance, max_iterations, false, dq.data(), mv.data(), &li, nullptr);
+    if (st != GSP_OK) return st;
+    st = copy_out(ctx, membership_inout, ctx->cm, g.n, where);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    *iterations = li;
+    for (int k = 0; k < li; k++) {
+        if (dq_iter) dq_iter[k] = dq[k];
+        if (moved_iter) moved_iter[k] = mv[k];
+    }
+    return GSP_OK;
+}
+
+gsp_status gsp_step_split(gsp_ctx *ctx, const int32_t *membership, int where, int32_t *labels_out) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!labels_out && ctx->n) return ctx->fail(GSP_EINVAL, "labels_out is NULL");
+    gsp_status st = take_membership(ctx, membership, where);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    Level g = level0(ctx);
+    WorkLists wl = make_lists(ctx);
+    HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
+    launch_split(g, wl, ctx->cm, ctx->lab, s);
+    HIP_TRY(hipGetLastError());
+    st = copy_out(ctx, labels_out, ctx->lab, g.n, where);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    return GSP_OK;
+}
+
+gsp_status gsp_step_aggregate(gsp_ctx *ctx, const int32_t *membership, int where, int64_t *n_out,
+                              int64_t *nnz_out, int64_t *offsets, int32_t *cols, double *weights) {
+    if (!ctx || !n_out || !nnz_out) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    gsp_status st = take_membership(ctx, membership, where);
+    if (st != GSP_OK) return st;
+    st = ensure_levels(ctx);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    Level g = level0(ctx);
+    int64_t ncomm = 0;
+    HIP_TRY(hipMemcpyAsync(ctx->lab, ctx->cm, g.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    st = renumber(ctx, ctx->lab, g.n, ctx->cm, &ncomm);
+    if (st != GSP_OK) return st;
+    WorkLists wl = make_lists(ctx);
+    HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
+    AggOut out{ctx->offL[0], ctx->colL[0], ctx->wL[0], ctx->KL[0], ctx->degL[0]};
+    int64_t nnz2 = 0;
+    HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s));
+    *n_out = ncomm;
+    *nnz_out = nnz2;
+    if (offsets) {
+        if ((nnz2 && (!cols || !weights))) return ctx->fail(GSP_EINVAL, "cols/weights NULL");
+        st = copy_out(ctx, offsets, out.off, ncomm + 1, where);
+        if (st != GSP_OK) return st;
+        st = copy_out(ctx, cols, out.col, nnz2, where);
+        if (st != GSP_OK) return st;
+        st = copy_out(ctx, weights, out.w, nnz2, where);
+        if (st != GSP_OK) return st;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return GSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+// device_common.h - device-side building blocks shared by the GSP-Louvain
+// kernels: degree bins, the sub-round hash, edge-weight loads, open-addressing
+// tables keyed by community id (in LDS and in global memory), and
+// wavefront-group reductions.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsp {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;            // threads per block for every kernel here
+constexpr int kEmpty = -1;             // empty table key (community ids are >= 0)
+
+// Degree bins.  A vertex (or a community, for aggregation) with d entries is
+// processed by:
+//   d <= 4, 8, 16, 32, 64 : a group of 4/8/16/32/64 lanes, one entry per lane,
+//                           table of 2*group slots in LDS;
+//   d <= 512              : one wavefront, table of 1024 slots in LDS;
+//   d <= 2048             : one 256-thread workgroup, table of 4096 slots in LDS;
+//   d > 2048              : several workgroups, table of nextpow2(2d) slots in
+//                           global memory ("hub").
+// Every table is at most half full, so linear probing always terminates.
+constexpr int kNumBins = 8;
+enum { BIN_G4 = 0, BIN_G8, BIN_G16, BIN_G32, BIN_G64, BIN_WAVE, BIN_BLOCK, BIN_HUB };
+constexpr int kNumSmallBins = 5;
+constexpr int kWaveMaxDeg = 512;
+constexpr int kWaveTable = 1024;
+constexpr int kBlockMaxDeg = 2048;
+constexpr int kBlockTable = 4096;
+constexpr int kHubChunk = 2048;        // entries per workgroup in the hub kernels
+
+__host__ __device__ inline int bin_of_degree(int64_t d) {
+    if (d <= 0) return -1;
+    if (d <= 4) return BIN_G4;
+    if (d <= 8) return BIN_G8;
+    if (d <= 16) return BIN_G16;
+    if (d <= 32) return BIN_G32;
+    if (d <= 64) return BIN_G64;
+    if (d <= kWaveMaxDeg) return BIN_WAVE;
+    if (d <= kBlockMaxDeg) return BIN_BLOCK;
+    return BIN_HUB;
+}
+
+__host__ __device__ inline uint64_t hub_table_size(int64_t d) {
+    uint64_t t = 1;
+    while (t < (uint64_t)(2 * d)) t <<= 1;
+    return t;
+}
+
+// Sub-round of vertex i when an iteration has 2^shift ordered sub-rounds:
+// the top `shift` bits of i * 0x9E3779B97F4A7C15 (Fibonacci hashing).
+__host__ __device__ inline int sub_round_of(int64_t i, int shift) {
+    if (shift == 0) return 0;
+    uint64_t x = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    return (int)(x >> (64 - shift));
+}
+
+enum WType { W_UNIT = 0, W_F32 = 1, W_F64 = 2 };
+
+template <int WT>
+__device__ __forceinline__ double edge_weight(const void *w, int64_t e) {
+    if constexpr (WT == W_UNIT) {
+        return 1.0;
+    } else if constexpr (WT == W_F32) {
+        return (double)((const float *)w)[e];
+    } else {
+        return ((const double *)w)[e];
+    }
+}
+
+__device__ __forceinline__ int32_t load_col(const int32_t *col, int64_t e) {
+    return col[e];
+}
+
+__device__ __forceinline__ uint32_t key_hash(int32_t k) {
+    uint32_t h = (uint32_t)k * 0x9E3779B1u;
+    return h ^ (h >> 15);
+}
+
+// Adds w to the value of `key` in an LDS table of mask+1 slots.
+__device__ __forceinline__ void lds_table_add(int *keys, double *vals, uint32_t mask, int key, double w) {
+    uint32_t s = key_hash(key) & mask;
+    while (true) {
+        int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            atomicAdd(&vals[s], w);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// Same on a table in global memory (device-scope atomics).
+__device__ __forceinline__ void gbl_table_add(int *keys, double *vals, uint64_t mask, int key, double w) {
+    uint64_t s = key_hash(key) & mask;
+    while (true) {
+        int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            unsafeAtomicAdd(&vals[s], w);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// (g, c) beats (g2, c2): larger score, ties to the lower community id.
+__device__ __forceinline__ bool better(double g, int c, double g2, int c2) {
+    return g > g2 || (g == g2 && c < c2);
+}
+
+// Argmax over the W lanes of an aligned lane group (W power of two <= 64).
+template <int W>
+__device__ __forceinline__ void group_argmax(double &g, int &c) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) {
+        double og = __shfl_xor(g, off, W);
+        int oc = __shfl_xor(c, off, W);
+        if (better(og, oc, g, c)) {
+            g = og;
+            c = oc;
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, W);
+    return x;
+}
+
+template <int W>
+__device__ __forceinline__ long long group_sum_ll(long long x) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, W);
+    return x;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Wave-aggregated append: every lane with `pred` gets a distinct slot of
+// counter *ctr; returns the slot (or -1).
+__device__ __forceinline__ int wave_append(bool pred, int *ctr) {
+    unsigned long long m = __ballot(pred);
+    if (m == 0) return -1;
+    int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(ctr, __popcll(m));
+    base = __shfl(base, leader);
+    unsigned long long below = m & ((1ull << lane_id()) - 1ull);
+    return pred ? base + __popcll(below) : -1;
+}
+
+}  // namespace gsp

@@ -1,0 +1,190 @@
+// gsp_internal.h - host-side declarations shared by the library's sources:
+// launch wrappers of every kernel and the per-level work lists.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace gsp {
+
+constexpr int kMaxRounds = 64;
+constexpr int kNumBuckets = kNumBins * kMaxRounds;  // bucket (bin b, sub-round p) = b * P + p
+
+// A graph level G' in device memory: CSR with int64 offsets, int32 columns
+// and weights of type wt (none, fp32 or fp64); deg[i] = off[i+1] - off[i].
+struct Level {
+    int64_t n = 0, nnz = 0;
+    const int64_t *off = nullptr;
+    const int32_t *col = nullptr;
+    const void *w = nullptr;
+    int wt = W_UNIT;
+    const int32_t *deg = nullptr;
+};
+
+// Vertex work lists of a level: every vertex with deg > 0 sits in bucket
+// (bin of its degree, its sub-round); bl holds the buckets back to back, in
+// bucket order, boff[k]..boff[k+1] is bucket k (host copy).
+// Hub vertices (bin BIN_HUB) are cut into chunks of kHubChunk entries:
+// chunk k covers entries [ch_beg[k], min(ch_beg[k] + kHubChunk, row end)) of
+// vertex ch_vert[k]; chunks of sub-round p are ch_poff[p]..ch_poff[p+1].
+// hub_off[i] is the offset of hub i's global table (hub_table_size(deg)).
+struct WorkLists {
+    int rounds = 1, shift = 0;
+    int32_t *bl = nullptr;
+    int64_t boff[kNumBuckets + 1] = {0};
+    int64_t bucket_entries[kNumBuckets] = {0};
+    int32_t *ch_vert = nullptr;
+    int64_t *ch_beg = nullptr;
+    int64_t nchunks = 0;
+    int64_t ch_poff[kMaxRounds + 1] = {0};
+    int64_t *hub_off = nullptr;
+    uint64_t hub_table_total = 0;
+
+    int64_t bucket_begin(int b, int p) const { return boff[b * rounds + p]; }
+    int64_t bucket_size(int b, int p) const { return boff[b * rounds + p + 1] - boff[b * rounds + p]; }
+    int64_t bin_begin(int b) const { return boff[b * rounds]; }
+    int64_t bin_size(int b) const { return boff[(b + 1) * rounds] - boff[b * rounds]; }
+};
+
+// Counters written by the kernels of one local-moving iteration.
+// Kernel classes of the scan+decide step: 0 small, 1 large, 2 hub.
+struct IterCounters {
+    int qcnt[kMaxRounds][kNumBins];   // queued vertices per sub-round and bin
+    int nmov[kMaxRounds];             // movers per sub-round
+    double gain;                      // sum of gain numerators G(c*) - G(stay)
+    unsigned long long moved;         // movers in the iteration
+    unsigned long long verts[3];      // vertices scanned, per class
+    unsigned long long scanned[3];    // CSR entries scanned, per class
+    unsigned long long keys[3];       // distinct neighbour communities met, per class
+};
+
+// Arguments of the local-moving kernels for one sub-round.
+struct MoveArgs {
+    Level g;
+    const double *K;
+    const double *sig;
+    const int32_t *csize;
+    const int32_t *cm;
+    double M2;
+    uint8_t *flag;           // unprocessed flags (read by compaction, set for neighbours of movers)
+    int32_t *dec;            // decision per mover
+    double *gain_out;        // per-vertex gain numerator (hooks), or nullptr
+    int32_t *movers;         // movers of this sub-round
+    int32_t *queue;          // queued vertices, bin b of this sub-round at qbase[b]
+    int64_t qbase[kNumBins];
+    int64_t qcap[kNumBins];  // bucket sizes (capacity of each queue)
+    IterCounters *ctr;       // this iteration's counters
+    int round;               // sub-round index p
+    // hubs
+    const int32_t *ch_vert;
+    const int64_t *ch_beg;
+    int64_t ch_first, ch_count;   // static chunk range of this sub-round's hubs
+    const int64_t *hub_off;
+    uint8_t *hub_act;
+    int *hkeys;
+    double *hvals;
+};
+
+// ---- k_util.hip ----
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+void launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
+void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
+// Exclusive scan of n values into out[0..n]; out[n] is the total.
+// tmp must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, void *tmp, hipStream_t s);
+void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, hipStream_t s);
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s);
+// Input checks; err bits: 1 offsets, 2 columns, 4 weights.
+void launch_validate(const int64_t *off, const int32_t *col, const void *w, int wt, int64_t n, int64_t nnz,
+                     int *err, hipStream_t s);
+void launch_offsets_from_i32(const int32_t *in, int64_t *out, int64_t n1, hipStream_t s);
+void launch_degrees(const int64_t *off, int32_t *deg, int64_t n, hipStream_t s);
+void launch_weights_to_f64(const float *in, double *out, int64_t nnz, hipStream_t s);
+// K_i = row sums (one wavefront per row) and *M2 += sum K_i.
+void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s);
+// Modularity parts: *sigma_in += sum of entries inside communities,
+// sig[c] += K_i; then q = sigma_in/M2 - sum_c (sig[c]/M2)^2.
+void launch_modularity_parts(const Level &g, const int32_t *memb, const double *K, double *sig, double *sigma_in,
+                             hipStream_t s);
+void launch_sum_squares(const double *sig, int64_t n, double M2, double *out, hipStream_t s);
+void launch_check_labels(const int32_t *memb, int64_t n, int *err, hipStream_t s);
+
+// ---- k_bins.hip ----
+// Builds the work lists of a level (all buckets of all sub-rounds).
+// Needs a host sync inside (bucket and chunk offsets are copied back).
+struct Scratch;
+hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s);
+// Only the buckets (no hub chunks or tables): items with deg[i] > 0 into
+// wl.bl by (bin of deg[i], sub-round of i).
+hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s);
+
+// ---- k_move.hip ----
+void launch_community_totals(const double *K, const int32_t *cm, int64_t n, double *sig, int32_t *csize,
+                             hipStream_t s);
+void launch_move_compact(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
+void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
+void launch_move_large(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
+void launch_move_hub(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
+void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
+
+// ---- k_split.hip ----
+// labels[i] = smallest vertex of i's component among same-community edges.
+void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, hipStream_t s);
+// Renumber labels (values in [0, n)) by ascending label: flag[l] = label l
+// in use, rank = exclusive scan of flag, out[i] = rank[labels[i]], *count =
+// number of labels in use.  flag/rank are n+1-sized temps.
+void launch_renumber(const int32_t *labels, int64_t n, int32_t *out, int32_t *flag, int32_t *rank, int64_t *count,
+                     void *tmp, hipStream_t s);
+void launch_lookup(int32_t *top, int64_t n, const int32_t *cm, hipStream_t s);
+// Counts communities (of memb) with more than one component (labels).
+void launch_count_disconnected(const int32_t *labels, const int32_t *memb, int64_t n, int32_t *roots_per_comm,
+                               unsigned long long *out, hipStream_t s);
+// lab[v] = smallest vertex of v's community (then renumber gives the
+// numbering by ascending smallest vertex).  first is an n-sized temp.
+void launch_canonical_labels(const int32_t *memb, int64_t n, int32_t *first, int32_t *lab, hipStream_t s);
+
+// ---- k_aggregate.hip ----
+struct AggOut {
+    int64_t *off;     // n2 + 1
+    int32_t *col;
+    double *w;
+    double *K;        // K'' (row sums of G'')
+    int32_t *deg;     // deg''
+};
+// Aggregates g by cm (values in [0, n2)) into the compact CSR `out`.
+// gap_* are scratch of capacity nnz (gapped rows before compaction).
+hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int64_t n2, AggOut out,
+                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s);
+
+// Device scratch owned by the context (sized at load).
+struct Scratch {
+    int64_t n_cap = 0, nnz_cap = 0;
+    void *scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
+    int64_t *i64a = nullptr, *i64b = nullptr, *i64c = nullptr, *i64d = nullptr, *i64e = nullptr;  // n_cap + 1
+    int32_t *i32a = nullptr, *i32b = nullptr, *i32c = nullptr, *i32d = nullptr;  // n_cap + 1
+    int32_t *bl2 = nullptr;  // n_cap: community work lists
+    int *err = nullptr;
+    unsigned long long *u64 = nullptr;  // 16 counters
+    double *f64 = nullptr;              // 16 scalars
+    // hub tables (grown on demand)
+    int *hkeys = nullptr;
+    double *hvals = nullptr;
+    uint64_t hcap = 0;
+    // hub chunk lists (sized for the input graph)
+    int32_t *ch_vert = nullptr;
+    int64_t *ch_beg = nullptr;
+    int64_t ch_cap = 0;
+    uint64_t *mem_used = nullptr;  // not owned
+};
+
+// Grows the hub-table pool of sc to at least `slots` (keys empty, values 0).
+hipError_t ensure_hub_tables(Scratch &sc, uint64_t slots, hipStream_t s);
+
+}  // namespace gsp

@@ -1,0 +1,213 @@
+// k_split.hip - splitting internally-disconnected communities (Section 4.1)
+// and the renumber / dendrogram-lookup steps of Algorithm "louvain".
+//
+// The paper splits with a BFS per community (Algorithm "splitDisconnectedBfs")
+// or minimum-label propagation (Algorithm "splitDisconnectedLp"); both give
+// the connected components of the subgraph whose edges join vertices of the
+// same community.  Here the components come from concurrent union-find over
+// those edges: roots are hooked larger-under-smaller with a compare-and-swap,
+// so every root is the smallest vertex of its set and the final label of a
+// vertex is the smallest vertex id of its component -- the label the
+// one-thread BFS from the lowest unvisited vertex gives.  Parent pointers
+// only decrease, so path halving with plain (agent-scope) stores is safe.
+#include "gsp_internal.h"
+
+namespace gsp {
+
+namespace {
+
+__device__ __forceinline__ int ld(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ int find_root(int32_t *parent, int x) {
+    while (true) {
+        int p = ld(parent + x);
+        if (p == x) return x;
+        int gp = ld(parent + p);
+        if (gp != p) st(parent + x, gp);
+        x = gp;
+    }
+}
+
+__device__ void unite(int32_t *parent, int a, int b) {
+    while (true) {
+        a = find_root(parent, a);
+        b = find_root(parent, b);
+        if (a == b) return;
+        if (a < b) {
+            int t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(parent + a, a, b) == a) return;
+    }
+}
+
+__device__ __forceinline__ void hook_entry(int32_t *parent, const int32_t *cm, int i, int ci, int j) {
+    if (j < i && cm[j] == ci) unite(parent, i, j);
+}
+
+// All vertices of the level through its work lists: groups of G lanes for
+// bins up to 64 entries, a wavefront per vertex up to 2048, a workgroup per
+// hub chunk beyond.  Unit ranges: [0, us) small, [us, us+uw) wave, then hubs.
+struct BinRanges {
+    int64_t beg[kNumBins], n[kNumBins];
+};
+
+__global__ void __launch_bounds__(kBlock) k_split_hook(Level g, const int32_t *bl, BinRanges br,
+                                                      const int32_t *ch_vert,
+                                                      const int64_t *ch_beg, int64_t nchunks, const int32_t *cm,
+                                                      int32_t *parent) {
+    const int64_t *binb = br.beg, *binn = br.n;
+    int64_t pre[kNumSmallBins + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int b = 0; b < kNumSmallBins; b++) {
+        int vpb = kBlock / (4 << b);
+        pre[b + 1] = pre[b] + (binn[b] + vpb - 1) / vpb;
+    }
+    int64_t nwave = binn[BIN_WAVE] + binn[BIN_BLOCK];
+    int64_t uw = (nwave + (kBlock / kWave) - 1) / (kBlock / kWave);
+    int64_t total = pre[kNumSmallBins] + uw + nchunks;
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        if (u < pre[kNumSmallBins]) {
+            int b = 0;
+            while (u >= pre[b + 1]) b++;
+            int G = 4 << b;
+            int64_t qi = (u - pre[b]) * (kBlock / G) + threadIdx.x / G;
+            int gl = threadIdx.x % G;
+            if (qi < binn[b]) {
+                int i = bl[binb[b] + qi];
+                if (gl < g.deg[i]) hook_entry(parent, cm, i, cm[i], g.col[g.off[i] + gl]);
+            }
+        } else if (u < pre[kNumSmallBins] + uw) {
+            int64_t qi = (u - pre[kNumSmallBins]) * (kBlock / kWave) + threadIdx.x / kWave;
+            if (qi < nwave) {
+                // wave and block bins are adjacent in the lists
+                int i = bl[binb[BIN_WAVE] + qi];
+                int ci = cm[i];
+                int64_t beg = g.off[i];
+                for (int e = lane_id(); e < g.deg[i]; e += kWave) hook_entry(parent, cm, i, ci, g.col[beg + e]);
+            }
+        } else {
+            int64_t k = u - pre[kNumSmallBins] - uw;
+            int i = ch_vert[k];
+            int ci = cm[i];
+            int64_t beg = ch_beg[k];
+            int64_t end = g.off[i] + g.deg[i];
+            if (end > beg + kHubChunk) end = beg + kHubChunk;
+            for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) hook_entry(parent, cm, i, ci, g.col[e]);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_split_compress(int32_t *parent, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int r = find_root(parent, (int)i);
+        st(parent + i, r);
+    }
+}
+
+// flag[l] = 1 for every label in use (all writers store 1).
+__global__ void __launch_bounds__(kBlock) k_mark_present(const int32_t *labels, int64_t n, int32_t *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        flag[labels[i]] = 1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_renumber_apply(const int32_t *labels, int64_t n, const int32_t *rank,
+                                                          int32_t *out, int64_t *count) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = rank[labels[i]];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = rank[n];
+}
+
+__global__ void __launch_bounds__(kBlock) k_lookup(int32_t *top, int64_t n, const int32_t *cm) {
+    for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+        top[v] = cm[top[v]];
+}
+
+__global__ void __launch_bounds__(kBlock) k_roots_per_comm(const int32_t *labels, const int32_t *memb, int64_t n,
+                                                          int32_t *cnt) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        if (labels[i] == (int32_t)i) atomicAdd(&cnt[memb[i]], 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_count_gt1(const int32_t *cnt, int64_t n, unsigned long long *out) {
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        c += cnt[i] > 1 ? 1 : 0;
+    c = (unsigned long long)group_sum_ll<kWave>((long long)c);
+    if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_min_vertex(const int32_t *memb, int64_t n, int32_t *first) {
+    for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+        atomicMin(&first[memb[v]], (int32_t)v);
+}
+
+__global__ void __launch_bounds__(kBlock) k_gather(const int32_t *tab, const int32_t *idx, int64_t n, int32_t *out) {
+    for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+        out[v] = tab[idx[v]];
+}
+
+inline unsigned grid1(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, hipStream_t s) {
+    if (g.n == 0) return;
+    launch_iota_i32(labels, g.n, s);
+    // per-bin begin/size over all sub-rounds (buckets of a bin are adjacent)
+    BinRanges br;
+    for (int b = 0; b < kNumBins; b++) {
+        br.beg[b] = wl.bin_begin(b);
+        br.n[b] = wl.bin_size(b);
+    }
+    int64_t units = 0;
+    for (int b = 0; b < kNumSmallBins; b++) {
+        int vpb = kBlock / (4 << b);
+        units += (wl.bin_size(b) + vpb - 1) / vpb;
+    }
+    units += (wl.bin_size(BIN_WAVE) + wl.bin_size(BIN_BLOCK) + 3) / 4 + wl.nchunks;
+    if (units > 0) {
+        unsigned gr = (unsigned)(units < 65536 ? units : 65536);
+        k_split_hook<<<gr, kBlock, 0, s>>>(g, wl.bl, br, wl.ch_vert, wl.ch_beg, wl.nchunks, cm, labels);
+    }
+    k_split_compress<<<grid1(g.n), kBlock, 0, s>>>(labels, g.n);
+}
+
+void launch_renumber(const int32_t *labels, int64_t n, int32_t *out, int32_t *flag, int32_t *rank, int64_t *count,
+                     void *tmp, hipStream_t s) {
+    launch_fill_i32(flag, 0, n, s);
+    k_mark_present<<<grid1(n), kBlock, 0, s>>>(labels, n, flag);
+    scan_exclusive_i32(flag, rank, n, tmp, s);
+    k_renumber_apply<<<grid1(n), kBlock, 0, s>>>(labels, n, rank, out, count);
+}
+
+void launch_lookup(int32_t *top, int64_t n, const int32_t *cm, hipStream_t s) {
+    if (n > 0) k_lookup<<<grid1(n), kBlock, 0, s>>>(top, n, cm);
+}
+
+void launch_count_disconnected(const int32_t *labels, const int32_t *memb, int64_t n, int32_t *roots_per_comm,
+                               unsigned long long *out, hipStream_t s) {
+    launch_fill_i32(roots_per_comm, 0, n, s);
+    k_roots_per_comm<<<grid1(n), kBlock, 0, s>>>(labels, memb, n, roots_per_comm);
+    k_count_gt1<<<grid1(n), kBlock, 0, s>>>(roots_per_comm, n, out);
+}
+
+void launch_canonical_labels(const int32_t *memb, int64_t n, int32_t *first, int32_t *lab, hipStream_t s) {
+    launch_fill_i32(first, 0x7fffffff, n, s);
+    k_min_vertex<<<grid1(n), kBlock, 0, s>>>(memb, n, first);
+    k_gather<<<grid1(n), kBlock, 0, s>>>(first, memb, n, lab);
+}
+
+}  // namespace gsp

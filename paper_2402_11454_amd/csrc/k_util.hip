@@ -1,0 +1,325 @@
+// k_util.hip - fills, device-wide exclusive scans, input validation, vertex
+// weights (Section 3: K_i = sum_j w_ij) and the parts of modularity (Eq. 1).
+#include <math.h>
+
+#include "gsp_internal.h"
+
+namespace gsp {
+
+namespace {
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+inline unsigned grid_for(int64_t n, int64_t per_block, unsigned cap = 1u << 20) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill(T *p, T v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_iota(int32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy_i32(int32_t *d, const int32_t *s, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) d[i] = s[i];
+}
+
+// Exclusive scan of the 256 values of a block (one per thread); returns the
+// exclusive prefix of this thread and sets *total.
+template <class T>
+__device__ T block_exclusive_scan(T x, T *total) {
+    __shared__ T wsum[kBlock / kWave];
+    int lane = lane_id(), w = threadIdx.x / kWave;
+    T inc = x;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        T y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; k++) {
+        if (k < w) before += wsum[k];
+        all += wsum[k];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - x;
+}
+
+template <class TIn, class TAcc>
+__global__ void __launch_bounds__(kBlock) k_scan_tile_sums(const TIn *in, int64_t n, TAcc *bsum) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    TAcc s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+        if (i < n) s += (TAcc)in[i];
+    }
+    TAcc tot;
+    block_exclusive_scan<TAcc>(s, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <class TAcc>
+__global__ void __launch_bounds__(kBlock) k_scan_block_sums(TAcc *bsum, int64_t nb) {
+    TAcc carry = 0;
+    for (int64_t base = 0; base < nb; base += kBlock) {
+        int64_t i = base + threadIdx.x;
+        TAcc x = i < nb ? bsum[i] : 0;
+        TAcc tot;
+        TAcc ex = block_exclusive_scan<TAcc>(x, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+template <class TIn, class TOut>
+__global__ void __launch_bounds__(kBlock) k_scan_down(const TIn *in, TOut *out, int64_t n, const TOut *bsum,
+                                                    int64_t nb) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    TOut v[kScanItems];
+    TOut s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        int64_t i = base + k;
+        v[k] = i < n ? (TOut)in[i] : 0;
+        s += v[k];
+    }
+    TOut tot;
+    TOut ex = block_exclusive_scan<TOut>(s, &tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        int64_t i = base + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
+}
+
+template <class TIn, class TOut>
+void scan_exclusive(const TIn *in, TOut *out, int64_t n, void *tmp, hipStream_t s) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb < 1) nb = 1;
+    TOut *bsum = (TOut *)tmp;
+    k_scan_tile_sums<TIn, TOut><<<(unsigned)nb, kBlock, 0, s>>>(in, n, bsum);
+    k_scan_block_sums<TOut><<<1, kBlock, 0, s>>>(bsum, nb);
+    k_scan_down<TIn, TOut><<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, bsum, nb);
+}
+
+__global__ void __launch_bounds__(kBlock) k_validate_offsets(const int64_t *off, int64_t n, int64_t nnz, int *err) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int64_t a = off[i], b = off[i + 1];
+        if (a > b || a < 0 || b > nnz || b - a > 0x7fffffffLL) atomicOr(err, 1);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        if (off[0] != 0 || off[n] != nnz) atomicOr(err, 1);
+}
+
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_validate_entries(const int32_t *col, const void *w, int64_t n,
+                                                            int64_t nnz, int *err) {
+    int bad = 0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
+        int32_t c = col[e];
+        if (c < 0 || (int64_t)c >= n) bad |= 2;
+        if constexpr (WT != W_UNIT) {
+            double x = edge_weight<WT>(w, e);
+            if (!(x >= 0.0) || isinf(x)) bad |= 4;
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void __launch_bounds__(kBlock) k_offsets_from_i32(const int32_t *in, int64_t *out, int64_t n1) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n1; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (int64_t)in[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_degrees(const int64_t *off, int32_t *deg, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        deg[i] = (int32_t)(off[i + 1] - off[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_weights_to_f64(const float *in, double *out, int64_t nnz) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (double)in[i];
+}
+
+// One wavefront per row: K_i = sum of the row, *M2 += sum_i K_i.
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, double *M2) {
+    __shared__ double part[kBlock / kWave];
+    int lane = lane_id(), w = threadIdx.x / kWave;
+    double blk = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + w; i < g.n; i += (int64_t)gridDim.x * (kBlock / kWave)) {
+        int64_t b = g.off[i], e = g.off[i + 1];
+        double s = 0.0;
+        for (int64_t k = b + lane; k < e; k += kWave) s += edge_weight<WT>(g.w, k);
+        s = group_sum<kWave>(s);
+        if (lane == 0) K[i] = s;
+        blk += s;
+    }
+    if (lane == 0) part[w] = blk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / kWave; k++) t += part[k];
+        unsafeAtomicAdd(M2, t);
+    }
+}
+
+// One wavefront per row: *sigma_in += entries of row i whose column shares
+// i's community; sig[c] += K_i.
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_modularity_parts(Level g, const int32_t *memb, const double *K,
+                                                            double *sig, double *sigma_in) {
+    __shared__ double part[kBlock / kWave];
+    int lane = lane_id(), w = threadIdx.x / kWave;
+    double blk = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + w; i < g.n; i += (int64_t)gridDim.x * (kBlock / kWave)) {
+        int64_t b = g.off[i], e = g.off[i + 1];
+        int32_t c = memb[i];
+        double s = 0.0;
+        for (int64_t k = b + lane; k < e; k += kWave)
+            if (memb[g.col[k]] == c) s += edge_weight<WT>(g.w, k);
+        s = group_sum<kWave>(s);
+        if (lane == 0) {
+            if (K[i] != 0.0) unsafeAtomicAdd(&sig[c], K[i]);
+            blk += s;
+        }
+    }
+    if (lane == 0) part[w] = blk;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / kWave; k++) t += part[k];
+        unsafeAtomicAdd(sigma_in, t);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_squares(const double *sig, int64_t n, double M2, double *out) {
+    __shared__ double part[kBlock / kWave];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double x = sig[i] / M2;
+        s += x * x;
+    }
+    s = group_sum<kWave>(s);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / kWave; k++) t += part[k];
+        unsafeAtomicAdd(out, t);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_check_labels(const int32_t *memb, int64_t n, int *err) {
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        if (memb[i] < 0 || (int64_t)memb[i] >= n) bad = 1;
+    if (bad) atomicOr(err, 1);
+}
+
+}  // namespace
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n > 0) k_fill<int32_t><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
+}
+void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+    if (n > 0) k_fill<uint8_t><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
+}
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+    if (n > 0) k_fill<double><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
+}
+void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
+    if (n > 0) k_fill<int64_t><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
+}
+void launch_iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+    if (n > 0) k_iota<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, n);
+}
+void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s) {
+    if (n > 0) k_copy_i32<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(dst, src, n);
+}
+
+size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile + 2) * sizeof(int64_t); }
+
+void scan_exclusive_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, void *tmp, hipStream_t s) {
+    scan_exclusive<int32_t, int64_t>(in, out, n, tmp, s);
+}
+void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, void *tmp, hipStream_t s) {
+    scan_exclusive<int64_t, int64_t>(in, out, n, tmp, s);
+}
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s) {
+    scan_exclusive<int32_t, int32_t>(in, out, n, tmp, s);
+}
+
+void launch_validate(const int64_t *off, const int32_t *col, const void *w, int wt, int64_t n, int64_t nnz,
+                     int *err, hipStream_t s) {
+    k_validate_offsets<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(off, n, nnz, err);
+    if (nnz == 0) return;
+    unsigned gr = grid_for(nnz, kBlock * 8, 16384);
+    if (wt == W_UNIT)
+        k_validate_entries<W_UNIT><<<gr, kBlock, 0, s>>>(col, w, n, nnz, err);
+    else if (wt == W_F32)
+        k_validate_entries<W_F32><<<gr, kBlock, 0, s>>>(col, w, n, nnz, err);
+    else
+        k_validate_entries<W_F64><<<gr, kBlock, 0, s>>>(col, w, n, nnz, err);
+}
+
+void launch_offsets_from_i32(const int32_t *in, int64_t *out, int64_t n1, hipStream_t s) {
+    k_offsets_from_i32<<<grid_for(n1, kBlock * 4, 8192), kBlock, 0, s>>>(in, out, n1);
+}
+
+void launch_degrees(const int64_t *off, int32_t *deg, int64_t n, hipStream_t s) {
+    if (n > 0) k_degrees<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(off, deg, n);
+}
+
+void launch_weights_to_f64(const float *in, double *out, int64_t nnz, hipStream_t s) {
+    if (nnz > 0) k_weights_to_f64<<<grid_for(nnz, kBlock * 4, 16384), kBlock, 0, s>>>(in, out, nnz);
+}
+
+void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s) {
+    if (g.n == 0) return;
+    unsigned gr = grid_for(g.n, kBlock / kWave, 65536);
+    if (g.wt == W_UNIT)
+        k_vertex_weights<W_UNIT><<<gr, kBlock, 0, s>>>(g, K, M2);
+    else if (g.wt == W_F32)
+        k_vertex_weights<W_F32><<<gr, kBlock, 0, s>>>(g, K, M2);
+    else
+        k_vertex_weights<W_F64><<<gr, kBlock, 0, s>>>(g, K, M2);
+}
+
+void launch_modularity_parts(const Level &g, const int32_t *memb, const double *K, double *sig, double *sigma_in,
+                             hipStream_t s) {
+    if (g.n == 0) return;
+    unsigned gr = grid_for(g.n, kBlock / kWave, 65536);
+    if (g.wt == W_UNIT)
+        k_modularity_parts<W_UNIT><<<gr, kBlock, 0, s>>>(g, memb, K, sig, sigma_in);
+    else if (g.wt == W_F32)
+        k_modularity_parts<W_F32><<<gr, kBlock, 0, s>>>(g, memb, K, sig, sigma_in);
+    else
+        k_modularity_parts<W_F64><<<gr, kBlock, 0, s>>>(g, memb, K, sig, sigma_in);
+}
+
+void launch_sum_squares(const double *sig, int64_t n, double M2, double *out, hipStream_t s) {
+    if (n > 0) k_sum_squares<<<grid_for(n, kBlock * 4, 4096), kBlock, 0, s>>>(sig, n, M2, out);
+}
+
+void launch_check_labels(const int32_t *memb, int64_t n, int *err, hipStream_t s) {
+    if (n > 0) k_check_labels<<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(memb, n, err);
+}
+
+}  // namespace gsp

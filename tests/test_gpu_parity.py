@@ -1,0 +1,276 @@
+"""GPU-vs-oracle parity through the C ABI (needs an MI355X).
+
+Bars (stated per test): modularity within 1e-9 in fp64; split labels,
+aggregated graphs (rows canonicalised by column), synchronous move decisions,
+gain numerators, whole local-moving phases and whole runs bit-exact.  All
+graphs here have integer weights or fp32 weights whose fp64 sums are exact,
+so the GPU's atomics cannot change a membership, a table value or a score;
+only the per-iteration total of fp32-weight gains (a sum of inexact
+products, taken in atomic order) is compared with a relative 1e-12.
+"""
+import numpy as np
+import pytest
+
+import gsp_inputs as gi
+import oracle
+import paper_2402_11454_amd as gsp
+
+pytestmark = pytest.mark.gpu
+
+
+def _hip_device_count():
+    try:
+        import torch
+        return torch.cuda.device_count()
+    except Exception:
+        return 0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if _hip_device_count() == 0:
+        pytest.skip("no GPU")
+    c = gsp.Context(0)
+    yield c
+    c.close()
+
+
+def _aggregated(g, k, seed):
+    """A super-vertex graph (fp64 weights, self-loops) from the oracle."""
+    m, G = oracle.renumber(gi.random_membership(g.n, k, seed))
+    h = oracle.aggregate(g, m, G)
+    return h
+
+
+GRAPHS = {
+    "sbm10k": lambda: gi.planted_sbm_10k(),
+    "rmat12": lambda: gi.rmat_small(12, 12),
+    "rmat13w": lambda: gi.rmat_small(13, 5, weights=(1.0, 4.0)),
+    "rmat15": lambda: gi.rmat_small(15, 3),
+    "sbm_w10": lambda: gi.sbm(4000, 25, 0.08, 0.002, 9, weights=(1.0, 10.0)),
+}
+
+_cache = {}
+
+
+def _graph(name):
+    if name not in _cache:
+        if name == "agg_rmat14":
+            _cache[name] = _aggregated(gi.rmat_small(14, 2), 3000, 1)
+        else:
+            _cache[name] = GRAPHS[name]()
+    return _cache[name]
+
+
+ALL = list(GRAPHS) + ["agg_rmat14"]
+
+
+def _integer_weights(g):
+    w = g.w if isinstance(g, oracle.CSR) else g.weights
+    return w is None or bool(np.all(np.asarray(w, dtype=np.float64) == np.round(w)))
+
+
+def _load(ctx, g):
+    if isinstance(g, oracle.CSR):
+        ctx.load(g.off, g.col, g.w, n=g.n)
+    else:
+        ctx.load_graph(g)
+
+
+def _memberships(n, seed):
+    yield np.arange(n, dtype=np.int32)
+    yield np.zeros(n, dtype=np.int32)
+    for k in (2, 37, max(2, n // 50), max(2, n // 3)):
+        yield gi.random_membership(n, k, seed + k)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_modularity(ctx, name):
+    g = _graph(name)
+    _load(ctx, g)
+    for m in _memberships(g.n, 11):
+        q_gpu = ctx.modularity(m)
+        q_ref = oracle.modularity(g, m)
+        assert abs(q_gpu - q_ref) <= 1e-9, (q_gpu, q_ref)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_split_bit_exact(ctx, name):
+    g = _graph(name)
+    _load(ctx, g)
+    for m in _memberships(g.n, 21):
+        lab = ctx.step_split(m)
+        np.testing.assert_array_equal(lab, oracle.split_bfs(g, m))
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_disconnected_count(ctx, name):
+    g = _graph(name)
+    _load(ctx, g)
+    for m in _memberships(g.n, 31):
+        assert ctx.count_disconnected(m) == oracle.disconnected(g, m)[0]
+
+
+def _canonical_rows(n, off, col, w):
+    rows = []
+    for c in range(n):
+        s, e = int(off[c]), int(off[c + 1])
+        o = np.argsort(col[s:e], kind="stable")
+        rows.append((col[s:e][o], w[s:e][o]))
+    return rows
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_aggregate_bit_exact(ctx, name):
+    g = _graph(name)
+    _load(ctx, g)
+    for m in list(_memberships(g.n, 41))[1:]:
+        mr, G = oracle.renumber(m)
+        ref = oracle.aggregate(g, mr, G)
+        n2, off, col, w = ctx.step_aggregate(m)
+        assert n2 == G
+        np.testing.assert_array_equal(off, ref.off)
+        for (c1, w1), (c2, w2) in zip(_canonical_rows(n2, off, col, w), _canonical_rows(G, ref.off, ref.col, ref.w)):
+            np.testing.assert_array_equal(c1, c2)
+            np.testing.assert_array_equal(w1, w2)
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_step_move_bit_exact(ctx, name):
+    g = _graph(name)
+    _load(ctx, g)
+    for t, m in enumerate(_memberships(g.n, 51)):
+        active = None if t % 2 == 0 else (gi.uniform(t, g.n) < 0.6).astype(np.uint8)
+        dec, gain, moved = ctx.step_move(m, active)
+        rdec, rgain, rmoved = oracle.move_sync_step(g, m, active)
+        np.testing.assert_array_equal(dec, rdec)
+        np.testing.assert_array_equal(gain, rgain)
+        assert moved == rmoved
+
+
+@pytest.mark.parametrize("name", ALL)
+@pytest.mark.parametrize("rounds", [1, 8])
+def test_move_phase_bit_exact(ctx, name, rounds):
+    g = _graph(name)
+    _load(ctx, g)
+    for tol in (0.0, 1e-2):
+        m, li, dq, mv = ctx.move_phase(None, tolerance=tol, max_iterations=20, sub_rounds=rounds)
+        rm, rli, rdq, rmv = oracle.move_sync(g, None, tau=tol, max_iter=20, rounds=rounds)
+        np.testing.assert_array_equal(m, rm)
+        assert li == rli
+        np.testing.assert_array_equal(mv, rmv)
+        if _integer_weights(g):
+            np.testing.assert_array_equal(dq, rdq)
+        else:
+            # gain numerators of fp32 weights are not exact; their sum depends
+            # on the order of the GPU's atomics
+            np.testing.assert_allclose(dq, rdq, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_run_bit_exact_and_quality(ctx, name):
+    g = _graph(name)
+    _load(ctx, g)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+    np.testing.assert_array_equal(res.membership, ref.membership)
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+    assert res.stats["iterations"] == ref.iterations
+    assert res.stats["communities"] == ref.communities
+    assert ctx.count_disconnected(res.membership) == 0
+    qa = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=False).modularity
+    assert res.modularity >= qa - 0.005
+
+
+def test_run_rmat20_full_size(ctx):
+    """R-MAT scale 20 (the bench workload): whole run bit-exact vs the
+    oracle's synchronous run, 0 disconnected, within 0.005 of async."""
+    g = gi.rmat20()
+    _load(ctx, g)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+    np.testing.assert_array_equal(res.membership, ref.membership)
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+
+
+@pytest.mark.parametrize("mode", [gsp.SPLIT_LAST, gsp.SPLIT_NONE])
+def test_split_modes(ctx, mode):
+    g = _graph("rmat15")
+    _load(ctx, g)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, split_mode=mode)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, split_mode=mode)
+    np.testing.assert_array_equal(res.membership, ref.membership)
+
+
+def test_edge_cases(ctx):
+    # no edges: singletons, Q = 0
+    ctx.load(np.zeros(6, np.int64), np.zeros(0, np.int32))
+    res = ctx.louvain()
+    assert res.membership.tolist() == list(range(5)) and res.modularity == 0.0
+    # isolated vertices and a self-loop-only vertex
+    g = gi.with_self_loops(gi.from_edges(7, [(0, 1), (1, 2), (0, 2), (3, 4)]), {6: 2.0})
+    _load(ctx, g)
+    res = ctx.louvain(tolerance=0.0)
+    ref = oracle.louvain(g, tolerance=0.0, sync=True, rounds=8)
+    np.testing.assert_array_equal(res.membership, ref.membership)
+    # zero passes
+    g = _graph("sbm10k")
+    _load(ctx, g)
+    ctx.run(max_passes=0)
+    assert ctx.membership().tolist() == list(range(g.n))
+    # int32 offsets give the same graph
+    ctx.load(g.offsets.astype(np.int32), g.cols)
+    assert ctx.n == g.n and ctx.modularity(np.zeros(g.n, np.int32)) == 0.0
+
+
+def test_error_paths(ctx):
+    with pytest.raises(gsp.GspError) as e:
+        ctx.load(np.array([0, 2, 1], np.int64), np.array([1, 0], np.int32))
+    assert e.value.status == gsp.GSP_EGRAPH
+    with pytest.raises(gsp.GspError) as e:
+        ctx.load(np.array([0, 1, 2], np.int64), np.array([1, 5], np.int32))
+    assert e.value.status == gsp.GSP_EGRAPH
+    with pytest.raises(gsp.GspError) as e:
+        ctx.load(np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([1.0, -1.0], np.float32))
+    assert e.value.status == gsp.GSP_EGRAPH
+    with pytest.raises(gsp.GspError) as e:
+        ctx.run()
+    assert e.value.status == gsp.GSP_ESTATE      # the failed load left no graph
+    g = _graph("rmat12")
+    _load(ctx, g)
+    with pytest.raises(gsp.GspError) as e:
+        ctx.modularity(np.full(g.n, g.n, np.int32))
+    assert e.value.status == gsp.GSP_EINVAL
+    with pytest.raises(gsp.GspError) as e:
+        ctx.run(sub_rounds=3)
+    assert e.value.status == gsp.GSP_EINVAL
+    with pytest.raises(gsp.GspError) as e:
+        ctx.run(mem_limit_bytes=1024)
+    assert e.value.status == gsp.GSP_ENOMEM
+
+
+def test_deterministic(ctx):
+    g = _graph("rmat15")
+    _load(ctx, g)
+    a = ctx.louvain().membership
+    b = ctx.louvain().membership
+    np.testing.assert_array_equal(a, b)
+
+
+def test_device_pointers(ctx):
+    import torch
+    g = _graph("rmat12")
+    dev = torch.device("cuda:0")
+    off = torch.from_numpy(g.offsets).to(dev)
+    col = torch.from_numpy(g.cols).to(dev)
+    ctx.load(off, col)
+    m = torch.from_numpy(gi.random_membership(g.n, 40, 3)).to(dev)
+    torch.cuda.synchronize()
+    assert abs(ctx.modularity(m) - oracle.modularity(g, m.cpu().numpy())) <= 1e-9
+    lab = ctx.step_split(m)
+    np.testing.assert_array_equal(lab.cpu().numpy(), oracle.split_bfs(g, m.cpu().numpy()))
+    ctx.run()
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ctx.membership(out)
+    np.testing.assert_array_equal(out.cpu().numpy(), ctx.membership())
