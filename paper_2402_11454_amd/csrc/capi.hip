@@ -102,6 +102,7 @@ struct gsp_ctx {
     int32_t *cm = nullptr, *csize = nullptr, *dec = nullptr, *movers = nullptr, *queue = nullptr;
     int32_t *lab = nullptr, *top = nullptr, *bl = nullptr, *tmp32 = nullptr;
     uint8_t *flag = nullptr, *hub_act = nullptr;
+    int32_t *hcnt = nullptr, *hub_ch0 = nullptr;
     int64_t *hub_off = nullptr;
     double *gain_tmp = nullptr;
     Scratch sc;
@@ -143,6 +144,7 @@ struct gsp_ctx {
         mem_used = 0;
         if (sc.hkeys) (void)hipFree(sc.hkeys);
         if (sc.hvals) (void)hipFree(sc.hvals);
+        if (sc.hlist) (void)hipFree(sc.hlist);
         sc = Scratch();
         for (int k = 0; k < 2; k++) {
             offL[k] = nullptr;
@@ -170,12 +172,16 @@ hipError_t ensure_hub_tables(Scratch &sc, uint64_t slots, hipStream_t s) {
     if (e != hipSuccess) return e;
     if (sc.hkeys) (void)hipFree(sc.hkeys);
     if (sc.hvals) (void)hipFree(sc.hvals);
+    if (sc.hlist) (void)hipFree(sc.hlist);
     sc.hkeys = nullptr;
     sc.hvals = nullptr;
+    sc.hlist = nullptr;
     sc.hcap = 0;
     e = hipMalloc(&sc.hkeys, cap * sizeof(int));
     if (e != hipSuccess) return e;
     e = hipMalloc(&sc.hvals, cap * sizeof(double));
+    if (e != hipSuccess) return e;
+    e = hipMalloc(&sc.hlist, cap * sizeof(int));
     if (e != hipSuccess) return e;
     sc.hcap = cap;
     launch_fill_i32(sc.hkeys, kEmpty, (int64_t)cap, s);
@@ -209,6 +215,7 @@ WorkLists make_lists(gsp_ctx *ctx) {
     WorkLists wl;
     wl.bl = ctx->bl;
     wl.hub_off = ctx->hub_off;
+    wl.hub_ch0 = ctx->hub_ch0;
     return wl;
 }
 
@@ -272,6 +279,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     hipStream_t s = ctx->stream;
     int P = wl.rounds;
     launch_fill_u8(ctx->flag, 1, g.n, s);
+    launch_fill_i32(ctx->hcnt, 0, g.n, s);
     int li = 0;
     for (int it = 0; it < max_iter; it++) {
         IterCounters *ctr = ctx->ctr + (it & 1);
@@ -303,8 +311,14 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.ch_count = wl.ch_poff[p + 1] - wl.ch_poff[p];
             a.hub_off = wl.hub_off;
             a.hub_act = ctx->hub_act;
+            a.hcnt = ctx->hcnt;
             a.hkeys = ctx->sc.hkeys;
             a.hvals = ctx->sc.hvals;
+            a.hlist = ctx->sc.hlist;
+            a.hub_ch0 = ctx->hub_ch0;
+            a.part_g = ctx->sc.part_g;
+            a.part_kid = ctx->sc.part_kid;
+            a.part_c = ctx->sc.part_c;
             if (cap == 0) continue;
             int t;
             t = timing_k ? ctx->timer.begin(100 + GSP_K_FRONTIER) : -1;
@@ -428,6 +442,8 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(ctx->flag, n, "hipMalloc(flags)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_act, n, "hipMalloc(hub flags)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_off, n, "hipMalloc(hub offsets)")) != GSP_OK) return st;
+    if ((st = A(ctx->hcnt, n, "hipMalloc(hub counters)")) != GSP_OK) return st;
+    if ((st = A(ctx->hub_ch0, n, "hipMalloc(hub chunk ids)")) != GSP_OK) return st;
     if ((st = A(ctx->gain_tmp, n, "hipMalloc(gains)")) != GSP_OK) return st;
     Scratch &sc = ctx->sc;
     sc.n_cap = n;
@@ -436,16 +452,23 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     char *stmp = nullptr;
     if ((st = A(stmp, sc.scan_tmp_bytes, "hipMalloc(scan)")) != GSP_OK) return st;
     sc.scan_tmp = stmp;
-    for (int64_t **p : {&sc.i64a, &sc.i64b, &sc.i64c, &sc.i64d, &sc.i64e})
+    for (int64_t **p : {&sc.i64a, &sc.i64b, &sc.i64c, &sc.i64d, &sc.i64e, &sc.i64f})
         if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
-    for (int32_t **p : {&sc.i32a, &sc.i32b, &sc.i32c, &sc.i32d, &sc.bl2})
+    for (int32_t **p : {&sc.i32a, &sc.i32b, &sc.i32c, &sc.i32d, &sc.i32e, &sc.bl2})
         if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
     if ((st = A(sc.err, 4, "hipMalloc(err)")) != GSP_OK) return st;
     if ((st = A(sc.u64, 2 * kNumBuckets + 16, "hipMalloc(counters)")) != GSP_OK) return st;
     if ((st = A(sc.f64, 16, "hipMalloc(scalars)")) != GSP_OK) return st;
-    sc.ch_cap = nnz / 1024 + 16;
+    // chunks: vertex hubs need <= nnz/2048 + #hubs, hub communities <=
+    // nnz/1024 + #hubs, with #hubs <= nnz/2049
+    sc.ch_cap = nnz / 512 + 16;
     if ((st = A(sc.ch_vert, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
     if ((st = A(sc.ch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(sc.cch_comm, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(sc.cch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(sc.part_g, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
+    if ((st = A(sc.part_kid, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
+    if ((st = A(sc.part_c, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
     if ((st = A(ctx->ctr, 2, "hipMalloc(iteration counters)")) != GSP_OK) return st;
 
     // copy in
@@ -501,6 +524,7 @@ gsp_status modularity_of(gsp_ctx *ctx, const int32_t *m, double *out) {
     }
     launch_fill_f64(ctx->sig, 0.0, ctx->n, s);
     HIP_TRY(hipMemsetAsync(ctx->sc.f64, 0, 2 * sizeof(double), s));
+    launch_community_totals(ctx->K0, m, ctx->n, ctx->sig, nullptr, s);
     launch_modularity_parts(level0(ctx), m, ctx->K0, ctx->sig, ctx->sc.f64, s);
     launch_sum_squares(ctx->sig, ctx->n, ctx->M2, ctx->sc.f64 + 1, s);
     HIP_TRY(hipMemcpyAsync(ctx->f64_h, ctx->sc.f64, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -656,6 +680,9 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
             launch_split(g, wl, ctx->cm, ctx->lab, s);
             ctx->timer.end(tk1);
             if (tk) ctx->kernel_launches[GSP_K_SPLIT] += 3;
+            // one pass over the level: column + membership of both ends per
+            // entry; offset, degree, membership, label write per vertex
+            kbytes[GSP_K_SPLIT] += 8.0 * (double)g.nnz + 24.0 * (double)g.n;
             ctx->timer.end(t);
             labels = ctx->lab;
         }
@@ -679,6 +706,15 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
         int64_t nnz2 = 0;
         HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s));
         ctx->timer.end(tk2);
+        {
+            // read every entry (column, weight, neighbour membership), write
+            // the gapped rows and copy them compact; per vertex membership,
+            // degree, offset and the member list
+            int ws = g.wt == W_UNIT ? 0 : (g.wt == W_F32 ? 4 : 8);
+            kbytes[GSP_K_AGGREGATE] += (8.0 + ws) * (double)g.nnz + 36.0 * (double)nnz2 + 28.0 * (double)g.n +
+                                       40.0 * (double)ncomm;
+            if (tk) ctx->kernel_launches[GSP_K_AGGREGATE] += 1;
+        }
         ctx->timer.end(t);
         Level g2;
         g2.n = ncomm;
@@ -811,6 +847,7 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
     launch_copy_i32(ctx->dec, ctx->cm, g.n, s);
     launch_fill_f64(ctx->gain_tmp, 0.0, g.n, s);
+    launch_fill_i32(ctx->hcnt, 0, g.n, s);
     IterCounters *ctr = ctx->ctr;
     HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(IterCounters), s));
     MoveArgs a;
@@ -837,8 +874,14 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     a.ch_count = wl.ch_poff[1] - wl.ch_poff[0];
     a.hub_off = wl.hub_off;
     a.hub_act = ctx->hub_act;
+    a.hcnt = ctx->hcnt;
     a.hkeys = ctx->sc.hkeys;
     a.hvals = ctx->sc.hvals;
+    a.hlist = ctx->sc.hlist;
+    a.hub_ch0 = ctx->hub_ch0;
+    a.part_g = ctx->sc.part_g;
+    a.part_kid = ctx->sc.part_kid;
+    a.part_c = ctx->sc.part_c;
     launch_move_compact(a, wl, s);
     launch_move_small(a, wl, s);
     launch_move_large(a, wl, s);

@@ -59,6 +59,8 @@ __host__ __device__ inline int sub_round_of(int64_t i, int shift) {
 
 enum WType { W_UNIT = 0, W_F32 = 1, W_F64 = 2 };
 
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
 template <int WT>
 __device__ __forceinline__ double edge_weight(const void *w, int64_t e) {
     if constexpr (WT == W_UNIT) {
@@ -105,6 +107,27 @@ __device__ __forceinline__ void gbl_table_add(int *keys, double *vals, uint64_t 
     }
 }
 
+// Global table that also lists its occupied slots: the first insertion of a
+// key appends its slot to list[] (counter *cnt), so readers visit only the
+// occupied slots.
+__device__ __forceinline__ void gbl_table_add_listed(int *keys, double *vals, int *list, int *cnt, uint64_t mask,
+                                                     int key, double w) {
+    uint64_t s = key_hash(key) & mask;
+    while (true) {
+        int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty) {
+            list[atomicAdd(cnt, 1)] = (int)s;
+            unsafeAtomicAdd(&vals[s], w);
+            return;
+        }
+        if (prev == key) {
+            unsafeAtomicAdd(&vals[s], w);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
 // (g, c) beats (g2, c2): larger score, ties to the lower community id.
 __device__ __forceinline__ bool better(double g, int c, double g2, int c2) {
     return g > g2 || (g == g2 && c < c2);
@@ -138,7 +161,73 @@ __device__ __forceinline__ long long group_sum_ll(long long x) {
     return x;
 }
 
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+// Wave-aggregated atomics keyed by an index: lanes of one wavefront that hit
+// the same element are combined into one atomic (a popular community would
+// otherwise serialise thousands of same-address atomics).  Lanes are taken
+// one distinct key at a time; at most 64 rounds.
+__device__ __forceinline__ void wave_add_i32_by_key(int *base, int key, int val, bool pred) {
+    unsigned long long pending = __ballot(pred);
+    while (pending) {
+        int leader = __ffsll((long long)pending) - 1;
+        int lk = __shfl(key, leader);
+        bool mine = pred && key == lk && ((pending >> lane_id()) & 1ull);
+        unsigned long long m = __ballot(mine);
+        int sum = mine ? val : 0;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (lane_id() == leader) atomicAdd(&base[lk], sum);
+        pending &= ~m;
+    }
+}
+
+__device__ __forceinline__ void wave_add_u64_by_key(unsigned long long *base, int key, unsigned long long val,
+                                                    bool pred) {
+    unsigned long long pending = __ballot(pred);
+    while (pending) {
+        int leader = __ffsll((long long)pending) - 1;
+        int lk = __shfl(key, leader);
+        bool mine = pred && key == lk && ((pending >> lane_id()) & 1ull);
+        unsigned long long m = __ballot(mine);
+        long long sum = mine ? (long long)val : 0;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (lane_id() == leader) atomicAdd(&base[lk], (unsigned long long)sum);
+        pending &= ~m;
+    }
+}
+
+__device__ __forceinline__ void wave_add_f64_by_key(double *base, int key, double val, bool pred) {
+    unsigned long long pending = __ballot(pred);
+    while (pending) {
+        int leader = __ffsll((long long)pending) - 1;
+        int lk = __shfl(key, leader);
+        bool mine = pred && key == lk && ((pending >> lane_id()) & 1ull);
+        unsigned long long m = __ballot(mine);
+        double sum = mine ? val : 0.0;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (lane_id() == leader && sum != 0.0) unsafeAtomicAdd(&base[lk], sum);
+        pending &= ~m;
+    }
+}
+
+// Each lane with `pred` gets a distinct slot of cursor[key].
+__device__ __forceinline__ int wave_reserve_by_key(int *cursor, int key, bool pred) {
+    unsigned long long pending = __ballot(pred);
+    int pos = -1;
+    while (pending) {
+        int leader = __ffsll((long long)pending) - 1;
+        int lk = __shfl(key, leader);
+        bool mine = pred && key == lk && ((pending >> lane_id()) & 1ull);
+        unsigned long long m = __ballot(mine);
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&cursor[lk], __popcll(m));
+        base = __shfl(base, leader);
+        if (mine) pos = base + __popcll(m & ((1ull << lane_id()) - 1ull));
+        pending &= ~m;
+    }
+    return pos;
+}
 
 // Wave-aggregated append: every lane with `pred` gets a distinct slot of
 // counter *ctr; returns the slot (or -1).

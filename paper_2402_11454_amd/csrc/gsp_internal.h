@@ -40,6 +40,7 @@ struct WorkLists {
     int64_t nchunks = 0;
     int64_t ch_poff[kMaxRounds + 1] = {0};
     int64_t *hub_off = nullptr;
+    int32_t *hub_ch0 = nullptr;
     uint64_t hub_table_total = 0;
 
     int64_t bucket_begin(int b, int p) const { return boff[b * rounds + p]; }
@@ -83,8 +84,13 @@ struct MoveArgs {
     int64_t ch_first, ch_count;   // static chunk range of this sub-round's hubs
     const int64_t *hub_off;
     uint8_t *hub_act;
+    int *hcnt;               // per vertex: occupied slots of its hub table
     int *hkeys;
     double *hvals;
+    int *hlist;              // occupied-slot lists, parallel to the tables
+    const int32_t *hub_ch0;  // per hub vertex: its first chunk id
+    double *part_g, *part_kid;  // per chunk: best score and K_{i->d} share
+    int *part_c;             // per chunk: best community
 };
 
 // ---- k_util.hip ----
@@ -167,19 +173,25 @@ struct Scratch {
     int64_t n_cap = 0, nnz_cap = 0;
     void *scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
-    int64_t *i64a = nullptr, *i64b = nullptr, *i64c = nullptr, *i64d = nullptr, *i64e = nullptr;  // n_cap + 1
-    int32_t *i32a = nullptr, *i32b = nullptr, *i32c = nullptr, *i32d = nullptr;  // n_cap + 1
+    int64_t *i64a = nullptr, *i64b = nullptr, *i64c = nullptr, *i64d = nullptr, *i64e = nullptr, *i64f = nullptr;
+    int32_t *i32a = nullptr, *i32b = nullptr, *i32c = nullptr, *i32d = nullptr, *i32e = nullptr;  // n_cap + 1
     int32_t *bl2 = nullptr;  // n_cap: community work lists
     int *err = nullptr;
     unsigned long long *u64 = nullptr;  // 16 counters
     double *f64 = nullptr;              // 16 scalars
-    // hub tables (grown on demand)
+    // hub tables (grown on demand): keys, values and occupied-slot lists
     int *hkeys = nullptr;
     double *hvals = nullptr;
+    int *hlist = nullptr;
     uint64_t hcap = 0;
-    // hub chunk lists (sized for the input graph)
+    // hub chunk lists (sized for the input graph): vertex hubs of a level,
+    // and hub communities of an aggregation
     int32_t *ch_vert = nullptr;
     int64_t *ch_beg = nullptr;
+    int32_t *cch_comm = nullptr;
+    int64_t *cch_beg = nullptr;
+    double *part_g = nullptr, *part_kid = nullptr;   // per chunk
+    int *part_c = nullptr;
     int64_t ch_cap = 0;
     uint64_t *mem_used = nullptr;  // not owned
 };

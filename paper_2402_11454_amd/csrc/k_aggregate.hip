@@ -29,22 +29,40 @@ inline unsigned grid1(int64_t n, int64_t cap = 8192) {
     return (unsigned)g;
 }
 
+// Community sizes and total degrees, with wave-aggregated atomics (a giant
+// community would otherwise serialise its members' atomics).
 __global__ void __launch_bounds__(kBlock) k_agg_count(Level g, const int32_t *cm, int32_t *csz, int64_t *ctot) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * kBlock) {
-        int c = cm[i];
-        atomicAdd(&csz[c], 1);
-        int d = g.deg[i];
-        if (d) atomicAdd((unsigned long long *)&ctot[c], (unsigned long long)d);
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < g.n; i0 += (int64_t)gridDim.x * kBlock) {
+        int64_t i = i0 + threadIdx.x;
+        bool ok = i < g.n;
+        int c = ok ? cm[i] : 0;
+        int d = ok ? g.deg[i] : 0;
+        wave_add_i32_by_key(csz, c, 1, ok);
+        wave_add_u64_by_key((unsigned long long *)ctot, c, (unsigned long long)d, ok && d > 0);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_agg_fill(int64_t n, const int32_t *cm, const int64_t *coff,
-                                                    int32_t *ccur, int32_t *members) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        int c = cm[i];
-        int k = atomicAdd(&ccur[c], 1);
-        members[coff[c] + k] = (int32_t)i;
+// Community vertices CSR: members with entries fill each community's range
+// from the front, members without entries from the back, so the first
+// members of a community all have at least one entry.
+__global__ void __launch_bounds__(kBlock) k_agg_fill(Level g, const int32_t *cm, const int64_t *coff,
+                                                    int32_t *front, int32_t *back, int32_t *members) {
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < g.n; i0 += (int64_t)gridDim.x * kBlock) {
+        int64_t i = i0 + threadIdx.x;
+        bool ok = i < g.n;
+        int c = ok ? cm[i] : 0;
+        bool has = ok && g.deg[i] > 0;
+        int pf = wave_reserve_by_key(front, c, has);
+        int pb = wave_reserve_by_key(back, c, ok && !has);
+        if (has) members[coff[c] + pf] = (int32_t)i;
+        if (ok && !has) members[coff[c + 1] - 1 - pb] = (int32_t)i;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_member_degrees(const int32_t *members, int64_t n, const int32_t *deg,
+                                                          int32_t *mdeg) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+        mdeg[k] = deg[members[k]];
 }
 
 __global__ void __launch_bounds__(kBlock) k_agg_cdeg(const int64_t *eoff, int64_t n2, int32_t *cdeg) {
@@ -72,6 +90,30 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_off(const int32_t *bl, int64
         ctab[bl[hb + k]] = toff[k];
 }
 
+constexpr int kAggChunk = 1024;          // entries per workgroup for hub communities
+constexpr int kAggChunkTable = 2 * kAggChunk;
+
+__global__ void __launch_bounds__(kBlock) k_agg_hub_nchunks(const int32_t *bl, int64_t hb, int64_t H,
+                                                           const int64_t *eoff, int64_t *nch) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
+        int c = bl[hb + k];
+        nch[k] = (eoff[c + 1] - eoff[c] + kAggChunk - 1) / kAggChunk;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_agg_hub_chunk_fill(const int32_t *bl, int64_t hb, int64_t H,
+                                                              const int64_t *eoff, const int64_t *choff,
+                                                              int32_t *cch_comm, int64_t *cch_beg) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
+        int c = bl[hb + k];
+        int64_t nc = choff[k + 1] - choff[k];
+        for (int64_t j = 0; j < nc; j++) {
+            cch_comm[choff[k] + j] = c;
+            cch_beg[choff[k] + j] = eoff[c] + j * kAggChunk;
+        }
+    }
+}
+
 struct AggArgs {
     Level g;
     const int32_t *cm;
@@ -86,8 +128,11 @@ struct AggArgs {
     int64_t cbeg[kNumBins], cn[kNumBins];
     int64_t n2;
     const int64_t *ctab;     // hub community table offsets (-1: not a hub)
+    const int64_t *mpre;     // exclusive scan of member degrees (flattened entry index)
+    int *hcnt;               // per community: occupied slots of its hub table
     int *hkeys;
     double *hvals;
+    int *hlist;
 };
 
 template <int W>
@@ -323,74 +368,99 @@ __global__ void __launch_bounds__(kBlock) k_agg_large(AggArgs a) {
 
 // ---------------------------------------------------------------- hubs
 
-struct BinRanges {
-    int64_t beg[kNumBins], n[kNumBins];
-};
-
-// Vertex by vertex: the row of every vertex of a hub community goes into
-// that community's global table (lane mapping of the level's work lists).
+// Hub communities, one workgroup per chunk of kAggChunk entries of the
+// community's flattened member rows (entry X of the level's member order is
+// entry X - mpre[k] of member k).  The chunk is reduced in LDS, then each
+// distinct (neighbour community, partial sum) goes to the community's global
+// table, whose occupied slots are listed.
 template <int WT>
-__global__ void __launch_bounds__(kBlock) k_agg_hub_insert(AggArgs a, const int32_t *bl, BinRanges br,
-                                                          const int32_t *ch_vert, const int64_t *ch_beg,
-                                                          int64_t nchunks) {
-    int64_t pre[kNumSmallBins + 1];
-    pre[0] = 0;
-#pragma unroll
-    for (int b = 0; b < kNumSmallBins; b++) {
-        int vpb = kBlock / (4 << b);
-        pre[b + 1] = pre[b] + (br.n[b] + vpb - 1) / vpb;
+__global__ void __launch_bounds__(kBlock) k_agg_hub_chunks(AggArgs a, const int32_t *cch_comm,
+                                                          const int64_t *cch_beg, int64_t nchunks) {
+    __shared__ int tkeys[kAggChunkTable];
+    __shared__ double tvals[kAggChunkTable];
+    __shared__ int64_t win[kAggChunk + 1];
+    __shared__ int64_t s_k0;
+    for (int k = threadIdx.x; k < kAggChunkTable; k += kBlock) {
+        tkeys[k] = kEmpty;
+        tvals[k] = 0.0;
     }
-    int64_t nwave = br.n[BIN_WAVE] + br.n[BIN_BLOCK];
-    int64_t uw = (nwave + 3) / 4;
-    int64_t total = pre[kNumSmallBins] + uw + nchunks;
-    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
-        int i = -1;
-        int64_t e0 = 0, e1 = 0, step = 1;
-        if (u < pre[kNumSmallBins]) {
-            int b = 0;
-            while (u >= pre[b + 1]) b++;
-            int G = 4 << b;
-            int64_t qi = (u - pre[b]) * (kBlock / G) + threadIdx.x / G;
-            if (qi < br.n[b]) {
-                i = bl[br.beg[b] + qi];
-                e0 = a.g.off[i] + threadIdx.x % G;
-                e1 = a.g.off[i] + a.g.deg[i];
-                step = G;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        int c = cch_comm[ch];
+        int64_t X0 = cch_beg[ch];
+        int64_t X1 = X0 + kAggChunk < a.eoff[c + 1] ? X0 + kAggChunk : a.eoff[c + 1];
+        int64_t m_end = a.coff[c + 1];
+        if (threadIdx.x == 0) {
+            // last member position k with mpre[k] <= X0 among c's members
+            int64_t lo = a.coff[c], hi = m_end - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi + 1) / 2;
+                if (a.mpre[mid] <= X0) lo = mid; else hi = mid - 1;
             }
-        } else if (u < pre[kNumSmallBins] + uw) {
-            int64_t qi = (u - pre[kNumSmallBins]) * 4 + threadIdx.x / kWave;
-            if (qi < nwave) {
-                i = bl[br.beg[BIN_WAVE] + qi];
-                e0 = a.g.off[i] + lane_id();
-                e1 = a.g.off[i] + a.g.deg[i];
-                step = kWave;
-            }
-        } else {
-            int64_t k = u - pre[kNumSmallBins] - uw;
-            i = ch_vert[k];
-            e0 = ch_beg[k] + threadIdx.x;
-            e1 = a.g.off[i] + a.g.deg[i];
-            if (e1 > ch_beg[k] + kHubChunk) e1 = ch_beg[k] + kHubChunk;
-            step = kBlock;
+            s_k0 = lo;
         }
-        if (i < 0) continue;
-        int c = a.cm[i];
-        int64_t tb = a.ctab[c];
-        if (tb < 0) continue;
-        uint64_t mask = comm_table_size(a.eoff[c + 1] - a.eoff[c], a.n2) - 1;
-        for (int64_t e = e0; e < e1; e += step) {
+        __syncthreads();
+        int64_t k0 = s_k0;
+        // members with entries come first, so the chunk's members lie in
+        // [k0, k0 + kAggChunk); the window holds their prefix values
+        for (int t = threadIdx.x; t <= kAggChunk; t += kBlock)
+            win[t] = (k0 + t < m_end) ? a.mpre[k0 + t] : a.eoff[c + 1];
+        __syncthreads();
+        for (int64_t X = X0 + threadIdx.x; X < X1; X += kBlock) {
+            int lo = 0, hi = kAggChunk - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) / 2;
+                if (win[mid] <= X) lo = mid; else hi = mid - 1;
+            }
+            int v = a.members[k0 + lo];
+            int64_t e = a.g.off[v] + (X - win[lo]);
             int32_t j = load_col(a.g.col, e);
-            gbl_table_add(a.hkeys + tb, a.hvals + tb, mask, a.cm[j], edge_weight<WT>(a.g.w, e));
+            lds_table_add(tkeys, tvals, kAggChunkTable - 1, a.cm[j], edge_weight<WT>(a.g.w, e));
         }
+        __syncthreads();
+        int64_t tb = a.ctab[c];
+        uint64_t mask = comm_table_size(a.eoff[c + 1] - a.eoff[c], a.n2) - 1;
+        for (int s = threadIdx.x; s < kAggChunkTable; s += kBlock) {
+            int key = tkeys[s];
+            if (key == kEmpty) continue;
+            double v = tvals[s];
+            tkeys[s] = kEmpty;
+            tvals[s] = 0.0;
+            gbl_table_add_listed(a.hkeys + tb, a.hvals + tb, a.hlist + tb, a.hcnt + c, mask, key, v);
+        }
+        __syncthreads();
     }
 }
 
+// One workgroup per hub community: its listed slots become row c of G''.
 __global__ void __launch_bounds__(kBlock) k_agg_hub_emit(AggArgs a) {
-    for (int64_t k = blockIdx.x; k < a.cn[BIN_HUB]; k += gridDim.x) {
-        int c = a.cbl[a.cbeg[BIN_HUB] + k];
+    __shared__ double s_sum[kBlock / kWave];
+    for (int64_t q = blockIdx.x; q < a.cn[BIN_HUB]; q += gridDim.x) {
+        int c = a.cbl[a.cbeg[BIN_HUB] + q];
         int64_t tb = a.ctab[c];
-        int64_t T = (int64_t)comm_table_size(a.eoff[c + 1] - a.eoff[c], a.n2);
-        emit_table<kBlock>(a, c, a.hkeys + tb, a.hvals + tb, T);
+        int used = a.hcnt[c];
+        int64_t base = a.eoff[c];
+        double sum = 0.0;
+        for (int k = threadIdx.x; k < used; k += kBlock) {
+            int s = a.hlist[tb + k];
+            int key = a.hkeys[tb + s];
+            double v = a.hvals[tb + s];
+            a.hkeys[tb + s] = kEmpty;
+            a.hvals[tb + s] = 0.0;
+            a.gap_col[base + k] = key;
+            a.gap_w[base + k] = v;
+            sum += v;
+        }
+        sum = group_sum<kWave>(sum);
+        if (lane_id() == 0) s_sum[threadIdx.x / kWave] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kBlock / kWave; w++) t += s_sum[w];
+            a.deg2[c] = used;
+            a.K2[c] = t;
+            a.hcnt[c] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -413,15 +483,17 @@ __global__ void __launch_bounds__(kBlock) k_agg_copy(const int64_t *eoff, const 
 
 hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int64_t n2, AggOut out,
                      int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s) {
-    int32_t *csz = sc.i32a, *ccur = sc.i32b, *members = sc.i32c, *cdeg = sc.i32d;
-    int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = sc.i64c, *ctab = sc.i64d;
+    (void)wl;
+    int32_t *csz = sc.i32a, *ccur = sc.i32b, *members = sc.i32c, *cdeg = sc.i32d, *mdeg = sc.i32e;
+    int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = sc.i64c, *mpre = sc.i64d, *ctab = sc.i64e, *tmp = sc.i64f;
     launch_fill_i32(csz, 0, n2, s);
     launch_fill_i64(ctot, 0, n2, s);
     k_agg_count<<<grid1(g.n), kBlock, 0, s>>>(g, cm, csz, ctot);
     scan_exclusive_i32_to_i64(csz, coff, n2, sc.scan_tmp, s);
     scan_exclusive_i64(ctot, eoff, n2, sc.scan_tmp, s);
     launch_fill_i32(ccur, 0, n2, s);
-    k_agg_fill<<<grid1(g.n), kBlock, 0, s>>>(g.n, cm, coff, ccur, members);
+    launch_fill_i32(csz, 0, n2, s);                  // csz becomes the back cursor
+    k_agg_fill<<<grid1(g.n), kBlock, 0, s>>>(g, cm, coff, ccur, csz, members);
     k_agg_cdeg<<<grid1(n2), kBlock, 0, s>>>(eoff, n2, cdeg);
     WorkLists cwl;
     cwl.bl = sc.bl2;
@@ -447,25 +519,39 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     }
     a.n2 = n2;
     a.ctab = ctab;
+    a.mpre = mpre;
+    a.hcnt = ccur;
 
-    // hub communities: table offsets in the global pool
-    int64_t H = a.cn[BIN_HUB];
+    // hub communities: table offsets in the global pool and entry chunks
+    int64_t H = a.cn[BIN_HUB], nchunks = 0;
     if (H > 0) {
-        launch_fill_i64(ctab, -1, n2, s);
         unsigned gr = grid1(H, 4096);
-        k_agg_hub_sizes<<<gr, kBlock, 0, s>>>(cwl.bl, a.cbeg[BIN_HUB], H, eoff, n2, sc.i64e);
-        scan_exclusive_i64(sc.i64e, ctot, H, sc.scan_tmp, s);   // ctot is free now
-        k_agg_hub_off<<<gr, kBlock, 0, s>>>(cwl.bl, a.cbeg[BIN_HUB], H, ctot, ctab);
-        int64_t ttot = 0;
-        e = hipMemcpyAsync(&ttot, ctot + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        int64_t hb = a.cbeg[BIN_HUB];
+        k_agg_hub_sizes<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, n2, ctot);    // ctot is free now
+        scan_exclusive_i64(ctot, tmp, H, sc.scan_tmp, s);
+        k_agg_hub_off<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, tmp, ctab);
+        int64_t host[2] = {0, 0};
+        e = hipMemcpyAsync(&host[0], tmp + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        k_agg_hub_nchunks<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, ctot);
+        scan_exclusive_i64(ctot, mpre, H, sc.scan_tmp, s);                        // mpre as temp
+        e = hipMemcpyAsync(&host[1], mpre + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        e = ensure_hub_tables(sc, (uint64_t)ttot, s);
+        nchunks = host[1];
+        if (nchunks > sc.ch_cap) return hipErrorInvalidValue;
+        k_agg_hub_chunk_fill<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, mpre, sc.cch_comm, sc.cch_beg);
+        e = ensure_hub_tables(sc, (uint64_t)host[0], s);
         if (e != hipSuccess) return e;
+        // flattened entry index of every member
+        k_member_degrees<<<grid1(g.n), kBlock, 0, s>>>(members, g.n, g.deg, mdeg);
+        scan_exclusive_i32_to_i64(mdeg, mpre, g.n, sc.scan_tmp, s);
+        launch_fill_i32(ccur, 0, n2, s);
     }
     a.hkeys = sc.hkeys;
     a.hvals = sc.hvals;
+    a.hlist = sc.hlist;
 
     int64_t us = 0;
     for (int b = 0; b < kNumSmallBins; b++) {
@@ -473,37 +559,22 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
         us += (a.cn[b] + vpb - 1) / vpb;
     }
     int64_t ul = (a.cn[BIN_WAVE] + 3) / 4 + a.cn[BIN_BLOCK];
+    unsigned gs = (unsigned)(us < 8192 ? us : 8192), gl = (unsigned)(ul < 2048 ? ul : 2048);
+    unsigned gh = (unsigned)(nchunks < 4096 ? nchunks : 4096);
     if (g.wt == W_UNIT) {
-        if (us) k_agg_small<W_UNIT><<<(unsigned)(us < 8192 ? us : 8192), kBlock, 0, s>>>(a);
-        if (ul) k_agg_large<W_UNIT><<<(unsigned)(ul < 2048 ? ul : 2048), kBlock, 0, s>>>(a);
+        if (us) k_agg_small<W_UNIT><<<gs, kBlock, 0, s>>>(a);
+        if (ul) k_agg_large<W_UNIT><<<gl, kBlock, 0, s>>>(a);
+        if (nchunks) k_agg_hub_chunks<W_UNIT><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     } else if (g.wt == W_F32) {
-        if (us) k_agg_small<W_F32><<<(unsigned)(us < 8192 ? us : 8192), kBlock, 0, s>>>(a);
-        if (ul) k_agg_large<W_F32><<<(unsigned)(ul < 2048 ? ul : 2048), kBlock, 0, s>>>(a);
+        if (us) k_agg_small<W_F32><<<gs, kBlock, 0, s>>>(a);
+        if (ul) k_agg_large<W_F32><<<gl, kBlock, 0, s>>>(a);
+        if (nchunks) k_agg_hub_chunks<W_F32><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     } else {
-        if (us) k_agg_small<W_F64><<<(unsigned)(us < 8192 ? us : 8192), kBlock, 0, s>>>(a);
-        if (ul) k_agg_large<W_F64><<<(unsigned)(ul < 2048 ? ul : 2048), kBlock, 0, s>>>(a);
+        if (us) k_agg_small<W_F64><<<gs, kBlock, 0, s>>>(a);
+        if (ul) k_agg_large<W_F64><<<gl, kBlock, 0, s>>>(a);
+        if (nchunks) k_agg_hub_chunks<W_F64><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     }
-    if (H > 0) {
-        BinRanges br;
-        for (int b = 0; b < kNumBins; b++) {
-            br.beg[b] = wl.bin_begin(b);
-            br.n[b] = wl.bin_size(b);
-        }
-        int64_t units = 0;
-        for (int b = 0; b < kNumSmallBins; b++) {
-            int vpb = kBlock / (4 << b);
-            units += (br.n[b] + vpb - 1) / vpb;
-        }
-        units += (br.n[BIN_WAVE] + br.n[BIN_BLOCK] + 3) / 4 + wl.nchunks;
-        unsigned gr = (unsigned)(units < 65536 ? (units > 0 ? units : 1) : 65536);
-        if (g.wt == W_UNIT)
-            k_agg_hub_insert<W_UNIT><<<gr, kBlock, 0, s>>>(a, wl.bl, br, wl.ch_vert, wl.ch_beg, wl.nchunks);
-        else if (g.wt == W_F32)
-            k_agg_hub_insert<W_F32><<<gr, kBlock, 0, s>>>(a, wl.bl, br, wl.ch_vert, wl.ch_beg, wl.nchunks);
-        else
-            k_agg_hub_insert<W_F64><<<gr, kBlock, 0, s>>>(a, wl.bl, br, wl.ch_vert, wl.ch_beg, wl.nchunks);
-        k_agg_hub_emit<<<(unsigned)(H < 4096 ? H : 4096), kBlock, 0, s>>>(a);
-    }
+    if (H > 0) k_agg_hub_emit<<<(unsigned)(H < 4096 ? H : 4096), kBlock, 0, s>>>(a);
     // compact
     scan_exclusive_i32_to_i64(out.deg, out.off, n2, sc.scan_tmp, s);
     e = hipMemcpyAsync(nnz_out, out.off + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s);

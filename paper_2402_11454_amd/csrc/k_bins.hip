@@ -87,10 +87,12 @@ __global__ void __launch_bounds__(kBlock) k_hub_sizes(const int32_t *bl, int64_t
 
 __global__ void __launch_bounds__(kBlock) k_hub_fill(const int32_t *bl, int64_t hb, int64_t H, const int32_t *deg,
                                                     const int64_t *off, const int64_t *toff, const int64_t *coff,
-                                                    int64_t *hub_off, int32_t *ch_vert, int64_t *ch_beg) {
+                                                    int64_t *hub_off, int32_t *hub_ch0, int32_t *ch_vert,
+                                                    int64_t *ch_beg) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
         int32_t i = bl[hb + k];
         hub_off[i] = toff[k];
+        hub_ch0[i] = (int32_t)coff[k];
         int64_t nc = coff[k + 1] - coff[k];
         for (int64_t c = 0; c < nc; c++) {
             ch_vert[coff[k] + c] = i;
@@ -173,8 +175,8 @@ hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &
         }
         e = ensure_hub_tables(sc, wl.hub_table_total, s);
         if (e != hipSuccess) return e;
-        k_hub_fill<<<gr, kBlock, 0, s>>>(wl.bl, hb, H, g.deg, g.off, sc.i64b, sc.i64a, wl.hub_off, sc.ch_vert,
-                                         sc.ch_beg);
+        k_hub_fill<<<gr, kBlock, 0, s>>>(wl.bl, hb, H, g.deg, g.off, sc.i64b, sc.i64a, wl.hub_off, wl.hub_ch0,
+                                         sc.ch_vert, sc.ch_beg);
     }
     wl.ch_vert = sc.ch_vert;
     wl.ch_beg = sc.ch_beg;

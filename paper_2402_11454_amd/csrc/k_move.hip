@@ -124,14 +124,44 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
 
 // ---------------------------------------------------------------- small
 
-template <int G, int WT>
-__device__ void small_unit(const MoveArgs &a, int bin, int64_t unit, int cnt, int *tkeys, double *tvals, Acc &acc) {
-    constexpr int kSlots = 2 * G;
-    const int grp = threadIdx.x / G, gl = threadIdx.x % G;
-    const int64_t qi = unit * (kBlock / G) + grp;
+// Orders the LDS operations of one wavefront (its lanes are the only users
+// of their table region): no workgroup barrier, so the waves of a block run
+// their units independently.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Argmax / sum over aligned groups of G lanes, G a runtime power of two.
+__device__ __forceinline__ void group_argmax_rt(double &g, int &c, int G) {
+    for (int off = G >> 1; off > 0; off >>= 1) {
+        double og = __shfl_xor(g, off);
+        int oc = __shfl_xor(c, off);
+        if (better(og, oc, g, c)) {
+            g = og;
+            c = oc;
+        }
+    }
+}
+
+__device__ __forceinline__ double group_sum_rt(double x, int G) {
+    for (int off = G >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// One wavefront handles 64/G vertices of one small bin: a group of G lanes
+// per vertex, one entry per lane, a table of 2G slots in the wave's LDS.
+// G is a runtime value, so the five bins share one code path.
+template <int WT>
+__device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int cnt, int *wkeys, double *wvals,
+                           Acc &acc) {
+    const int kSlots = 2 * G;
+    const int lane = lane_id();
+    const int grp = lane / G, gl = lane & (G - 1);
+    const int64_t qi = unit * (kWave / G) + grp;
     const bool valid = qi < cnt;
-    int *keys = tkeys + grp * kSlots;
-    double *vals = tvals + grp * kSlots;
+    int *keys = wkeys + grp * kSlots;
+    double *vals = wvals + grp * kSlots;
     int i = -1, di = 0, d = -1, j = -1;
     double ki = 0.0;
     if (valid) {
@@ -146,15 +176,15 @@ __device__ void small_unit(const MoveArgs &a, int bin, int64_t unit, int cnt, in
             if (j != i) lds_table_add(keys, vals, kSlots - 1, a.cm[j], w);
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     double bg = -INFINITY, kid = 0.0;
     int bc = kIntMax;
     if (valid) {
         take_slot(a, keys, vals, gl, d, ki, bg, bc, kid, acc.keys);
         take_slot(a, keys, vals, gl + G, d, ki, bg, bc, kid, acc.keys);
     }
-    group_argmax<G>(bg, bc);
-    kid = group_sum<G>(kid);
+    group_argmax_rt(bg, bc, G);
+    kid = group_sum_rt(kid, G);
     double gain = 0.0;
     bool mv = valid && decide(a, i, d, ki, kid, bg, bc, &gain);
     if (mv && j >= 0 && j != i) a.flag[j] = 1;
@@ -171,39 +201,36 @@ __device__ void small_unit(const MoveArgs &a, int bin, int64_t unit, int cnt, in
     }
     int slot = wave_append(lead && mv, &a.ctr->nmov[a.round]);
     if (slot >= 0) a.movers[slot] = i;
-    __syncthreads();
+    wave_lds_sync();
 }
 
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_move_small(MoveArgs a) {
     __shared__ int tkeys[2 * kBlock];
     __shared__ double tvals[2 * kBlock];
-    for (int k = threadIdx.x; k < 2 * kBlock; k += kBlock) {
-        tkeys[k] = kEmpty;
-        tvals[k] = 0.0;
+    const int w = threadIdx.x / kWave;
+    int *wkeys = tkeys + w * 2 * kWave;
+    double *wvals = tvals + w * 2 * kWave;
+    for (int k = lane_id(); k < 2 * kWave; k += kWave) {
+        wkeys[k] = kEmpty;
+        wvals[k] = 0.0;
     }
-    __syncthreads();
+    wave_lds_sync();
     int cnt[kNumSmallBins];
     int64_t pre[kNumSmallBins + 1];
     pre[0] = 0;
 #pragma unroll
     for (int b = 0; b < kNumSmallBins; b++) {
         cnt[b] = a.ctr->qcnt[a.round][b];
-        int vpb = kBlock / (4 << b);
-        pre[b + 1] = pre[b] + (cnt[b] + vpb - 1) / vpb;
+        int vpw = kWave / (4 << b);
+        pre[b + 1] = pre[b] + (cnt[b] + vpw - 1) / vpw;
     }
     Acc acc;
-    for (int64_t u = blockIdx.x; u < pre[kNumSmallBins]; u += gridDim.x) {
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t u = (int64_t)blockIdx.x * (kBlock / kWave) + w; u < pre[kNumSmallBins]; u += nw) {
         int b = 0;
         while (u >= pre[b + 1]) b++;
-        int64_t uu = u - pre[b];
-        switch (b) {
-            case 0: small_unit<4, WT>(a, 0, uu, cnt[0], tkeys, tvals, acc); break;
-            case 1: small_unit<8, WT>(a, 1, uu, cnt[1], tkeys, tvals, acc); break;
-            case 2: small_unit<16, WT>(a, 2, uu, cnt[2], tkeys, tvals, acc); break;
-            case 3: small_unit<32, WT>(a, 3, uu, cnt[3], tkeys, tvals, acc); break;
-            default: small_unit<64, WT>(a, 4, uu, cnt[4], tkeys, tvals, acc); break;
-        }
+        small_unit<WT>(a, b, 4 << b, u - pre[b], cnt[b], wkeys, wvals, acc);
     }
     flush_acc(acc, a.ctr, 0);
 }
@@ -230,100 +257,122 @@ __device__ void block_argmax_sum(double &bg, int &bc, double &x) {
     __syncthreads();
 }
 
+// One wavefront per vertex of 65..512 entries, 1024-slot table in its LDS.
 template <int WT>
-__device__ void wave_unit(const MoveArgs &a, int64_t unit, int cnt, int *tkeys, double *tvals, Acc &acc) {
+__global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
+    __shared__ int tkeys[kBlock / kWave * kWaveTable];
+    __shared__ double tvals[kBlock / kWave * kWaveTable];
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t qi = unit * (kBlock / kWave) + w;
-    const bool valid = qi < cnt;
     int *keys = tkeys + w * kWaveTable;
     double *vals = tvals + w * kWaveTable;
-    int i = -1, di = 0, d = -1;
-    int64_t beg = 0;
-    double ki = 0.0;
-    if (valid) {
-        i = a.queue[a.qbase[BIN_WAVE] + qi];
-        di = a.g.deg[i];
-        beg = a.g.off[i];
-        d = a.cm[i];
-        ki = a.K[i];
+    for (int k = lane; k < kWaveTable; k += kWave) {
+        keys[k] = kEmpty;
+        vals[k] = 0.0;
+    }
+    wave_lds_sync();
+    const int cnt = a.ctr->qcnt[a.round][BIN_WAVE];
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    Acc acc;
+    for (int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + w; qi < cnt; qi += nw) {
+        int i = a.queue[a.qbase[BIN_WAVE] + qi];
+        int di = a.g.deg[i];
+        int64_t beg = a.g.off[i];
+        int d = a.cm[i];
+        double ki = a.K[i];
         for (int e = lane; e < di; e += kWave) {
             int j = load_col(a.g.col, beg + e);
             double wt = edge_weight<WT>(a.g.w, beg + e);
             if (j != i) lds_table_add(keys, vals, kWaveTable - 1, a.cm[j], wt);
         }
-    }
-    __syncthreads();
-    double bg = -INFINITY, kid = 0.0;
-    int bc = kIntMax;
-    if (valid)
+        wave_lds_sync();
+        double bg = -INFINITY, kid = 0.0;
+        int bc = kIntMax;
         for (int s = lane; s < kWaveTable; s += kWave) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
-    group_argmax<kWave>(bg, bc);
-    kid = group_sum<kWave>(kid);
-    double gain = 0.0;
-    bool mv = valid && decide(a, i, d, ki, kid, bg, bc, &gain);
-    if (mv)
-        for (int e = lane; e < di; e += kWave) {
-            int j = load_col(a.g.col, beg + e);
-            if (j != i) a.flag[j] = 1;
+        group_argmax<kWave>(bg, bc);
+        kid = group_sum<kWave>(kid);
+        double gain = 0.0;
+        bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
+        if (mv)
+            for (int e = lane; e < di; e += kWave) {
+                int j = load_col(a.g.col, beg + e);
+                if (j != i) a.flag[j] = 1;
+            }
+        if (lane == 0) {
+            acc.verts++;
+            acc.scanned += (unsigned long long)di;
+            if (mv) {
+                a.dec[i] = bc;
+                acc.gain += gain;
+                acc.moved++;
+                a.movers[atomicAdd(&a.ctr->nmov[a.round], 1)] = i;
+            }
+            if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
-    bool lead = valid && lane == 0;
-    if (lead) {
-        acc.verts++;
-        acc.scanned += (unsigned long long)di;
-        if (mv) {
-            a.dec[i] = bc;
-            acc.gain += gain;
-            acc.moved++;
-        }
-        if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
+        wave_lds_sync();
     }
-    int slot = wave_append(lead && mv, &a.ctr->nmov[a.round]);
-    if (slot >= 0) a.movers[slot] = i;
-    __syncthreads();
+    flush_acc(acc, a.ctr, 1);
 }
 
+// One workgroup per vertex of 513..2048 entries, 4096-slot table in LDS.
 template <int WT>
-__device__ void block_unit(const MoveArgs &a, int64_t qi, int *keys, double *vals, Acc &acc) {
+__global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
+    __shared__ int keys[kBlockTable];
+    __shared__ double vals[kBlockTable];
     const int tid = threadIdx.x;
-    int i = a.queue[a.qbase[BIN_BLOCK] + qi];
-    int di = a.g.deg[i];
-    int64_t beg = a.g.off[i];
-    int d = a.cm[i];
-    double ki = a.K[i];
-    for (int e = tid; e < di; e += kBlock) {
-        int j = load_col(a.g.col, beg + e);
-        double wt = edge_weight<WT>(a.g.w, beg + e);
-        if (j != i) lds_table_add(keys, vals, kBlockTable - 1, a.cm[j], wt);
+    for (int k = tid; k < kBlockTable; k += kBlock) {
+        keys[k] = kEmpty;
+        vals[k] = 0.0;
     }
     __syncthreads();
-    double bg = -INFINITY, kid = 0.0;
-    int bc = kIntMax;
-    for (int s = tid; s < kBlockTable; s += kBlock) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
-    block_argmax_sum(bg, bc, kid);
-    double gain = 0.0;
-    bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
-    if (mv)
+    const int cnt = a.ctr->qcnt[a.round][BIN_BLOCK];
+    Acc acc;
+    for (int64_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+        int i = a.queue[a.qbase[BIN_BLOCK] + qi];
+        int di = a.g.deg[i];
+        int64_t beg = a.g.off[i];
+        int d = a.cm[i];
+        double ki = a.K[i];
         for (int e = tid; e < di; e += kBlock) {
             int j = load_col(a.g.col, beg + e);
-            if (j != i) a.flag[j] = 1;
+            double wt = edge_weight<WT>(a.g.w, beg + e);
+            if (j != i) lds_table_add(keys, vals, kBlockTable - 1, a.cm[j], wt);
         }
-    if (tid == 0) {
-        acc.verts++;
-        acc.scanned += (unsigned long long)di;
-        if (mv) {
-            a.dec[i] = bc;
-            acc.gain += gain;
-            acc.moved++;
-            int slot = atomicAdd(&a.ctr->nmov[a.round], 1);
-            a.movers[slot] = i;
+        __syncthreads();
+        double bg = -INFINITY, kid = 0.0;
+        int bc = kIntMax;
+        for (int s = tid; s < kBlockTable; s += kBlock) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        block_argmax_sum(bg, bc, kid);
+        double gain = 0.0;
+        bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
+        if (mv)
+            for (int e = tid; e < di; e += kBlock) {
+                int j = load_col(a.g.col, beg + e);
+                if (j != i) a.flag[j] = 1;
+            }
+        if (tid == 0) {
+            acc.verts++;
+            acc.scanned += (unsigned long long)di;
+            if (mv) {
+                a.dec[i] = bc;
+                acc.gain += gain;
+                acc.moved++;
+                a.movers[atomicAdd(&a.ctr->nmov[a.round], 1)] = i;
+            }
+            if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
-        if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
+        __syncthreads();
     }
-    __syncthreads();
+    flush_acc(acc, a.ctr, 1);
 }
 
+// ---------------------------------------------------------------- hubs
+
+// One workgroup per chunk of kHubChunk entries of an active hub: the chunk
+// is first reduced in an LDS table (so a community met many times in the
+// chunk costs one global atomic), then each distinct (community, partial
+// sum) goes into the hub's global table, whose occupied slots are listed.
 template <int WT>
-__global__ void __launch_bounds__(kBlock) k_move_large(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     __shared__ int tkeys[kBlockTable];
     __shared__ double tvals[kBlockTable];
     for (int k = threadIdx.x; k < kBlockTable; k += kBlock) {
@@ -331,24 +380,6 @@ __global__ void __launch_bounds__(kBlock) k_move_large(MoveArgs a) {
         tvals[k] = 0.0;
     }
     __syncthreads();
-    int cw = a.ctr->qcnt[a.round][BIN_WAVE];
-    int cb = a.ctr->qcnt[a.round][BIN_BLOCK];
-    int64_t uw = (cw + (kBlock / kWave) - 1) / (kBlock / kWave);
-    int64_t total = uw + cb;
-    Acc acc;
-    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
-        if (u < uw)
-            wave_unit<WT>(a, u, cw, tkeys, tvals, acc);
-        else
-            block_unit<WT>(a, u - uw, tkeys, tvals, acc);
-    }
-    flush_acc(acc, a.ctr, 1);
-}
-
-// ---------------------------------------------------------------- hubs
-
-template <int WT>
-__global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     Acc acc;
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
@@ -356,60 +387,108 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
         int64_t beg = a.ch_beg[k];
         int64_t end = a.g.off[i] + a.g.deg[i];
         if (end > beg + kHubChunk) end = beg + kHubChunk;
-        int64_t tb = a.hub_off[i];
-        uint64_t mask = hub_table_size(a.g.deg[i]) - 1;
         for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) {
             int j = load_col(a.g.col, e);
             double wt = edge_weight<WT>(a.g.w, e);
-            if (j != i) gbl_table_add(a.hkeys + tb, a.hvals + tb, mask, a.cm[j], wt);
+            if (j != i) lds_table_add(tkeys, tvals, kBlockTable - 1, a.cm[j], wt);
+        }
+        __syncthreads();
+        int64_t tb = a.hub_off[i];
+        uint64_t mask = hub_table_size(a.g.deg[i]) - 1;
+        for (int s = threadIdx.x; s < kBlockTable; s += kBlock) {
+            int key = tkeys[s];
+            if (key == kEmpty) continue;
+            double v = tvals[s];
+            tkeys[s] = kEmpty;
+            tvals[s] = 0.0;
+            gbl_table_add_listed(a.hkeys + tb, a.hvals + tb, a.hlist + tb, a.hcnt + i, mask, key, v);
         }
         if (threadIdx.x == 0) acc.scanned += (unsigned long long)(end - beg);
+        __syncthreads();
     }
     flush_acc(acc, a.ctr, 2);
 }
 
-__global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
-    int cnt = a.ctr->qcnt[a.round][BIN_HUB];
+// One workgroup per chunk again: the chunk's segment [s*kHubChunk,
+// (s+1)*kHubChunk) of the hub's occupied-slot list is scored (the table is
+// complete now) and reset; the segment's best candidate and its share of
+// K_{i->d} go to part_*[chunk].
+__global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
     Acc acc;
-    for (int64_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+    for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
+        int i = a.ch_vert[k];
+        if (!a.hub_act[i]) continue;
+        int64_t seg0 = a.ch_beg[k] - a.g.off[i];
+        int used = a.hcnt[i];
+        int64_t seg1 = seg0 + kHubChunk < used ? seg0 + kHubChunk : used;
+        int d = a.cm[i];
+        double ki = a.K[i];
+        int64_t tb = a.hub_off[i];
+        double bg = -INFINITY, kid = 0.0;
+        int bc = kIntMax;
+        for (int64_t q = seg0 + threadIdx.x; q < seg1; q += kBlock)
+            take_slot(a, a.hkeys + tb, a.hvals + tb, a.hlist[tb + q], d, ki, bg, bc, kid, acc.keys);
+        block_argmax_sum(bg, bc, kid);
+        if (threadIdx.x == 0) {
+            a.part_g[k] = bg;
+            a.part_c[k] = bc;
+            a.part_kid[k] = kid;
+        }
+    }
+    flush_acc(acc, a.ctr, 2);
+}
+
+// One wavefront per active hub: combines its chunks' partial results,
+// decides and marks the neighbours of a mover.
+__global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int cnt = a.ctr->qcnt[a.round][BIN_HUB];
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    Acc acc;
+    for (int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + w; qi < cnt; qi += nw) {
         int i = a.queue[a.qbase[BIN_HUB] + qi];
         int di = a.g.deg[i];
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
         double ki = a.K[i];
-        int64_t tb = a.hub_off[i];
-        int64_t T = (int64_t)hub_table_size(di);
+        int64_t c0 = a.hub_ch0[i];
+        int nch = (di + kHubChunk - 1) / kHubChunk;
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int64_t s = threadIdx.x; s < T; s += kBlock)
-            take_slot(a, a.hkeys + tb, a.hvals + tb, s, d, ki, bg, bc, kid, acc.keys);
-        block_argmax_sum(bg, bc, kid);
+        for (int q = lane; q < nch; q += kWave) {
+            double g = a.part_g[c0 + q];
+            int c = a.part_c[c0 + q];
+            if (better(g, c, bg, bc)) { bg = g; bc = c; }
+            kid += a.part_kid[c0 + q];
+        }
+        group_argmax<kWave>(bg, bc);
+        kid = group_sum<kWave>(kid);
         double gain = 0.0;
         bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
         if (mv)
-            for (int64_t e = threadIdx.x; e < di; e += kBlock) {
+            for (int64_t e = lane; e < di; e += kWave) {
                 int j = load_col(a.g.col, beg + e);
                 if (j != i) a.flag[j] = 1;
             }
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             acc.verts++;
             a.hub_act[i] = 0;
+            a.hcnt[i] = 0;
             if (mv) {
                 a.dec[i] = bc;
                 acc.gain += gain;
                 acc.moved++;
-                int slot = atomicAdd(&a.ctr->nmov[a.round], 1);
-                a.movers[slot] = i;
+                a.movers[atomicAdd(&a.ctr->nmov[a.round], 1)] = i;
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
-        __syncthreads();
     }
     flush_acc(acc, a.ctr, 2);
 }
 
 // ---------------------------------------------------------------- apply
 
+// Moves of the sub-round: C'[i] <- c*, Sigma and sizes updated.
 __global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a) {
     int n = a.ctr->nmov[a.round];
     int32_t *cm = const_cast<int32_t *>(a.cm);
@@ -421,8 +500,10 @@ __global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a) {
         int d = cm[i];
         double ki = a.K[i];
         cm[i] = c;
-        unsafeAtomicAdd(&sig[d], -ki);
-        unsafeAtomicAdd(&sig[c], ki);
+        if (ki != 0.0) {
+            unsafeAtomicAdd(&sig[d], -ki);
+            unsafeAtomicAdd(&sig[c], ki);
+        }
         atomicSub(&csize[d], 1);
         atomicAdd(&csize[c], 1);
     }
@@ -430,10 +511,13 @@ __global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a) {
 
 __global__ void __launch_bounds__(kBlock) k_community_totals(const double *K, const int32_t *cm, int64_t n,
                                                             double *sig, int32_t *csize) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        int c = cm[i];
-        if (K[i] != 0.0) unsafeAtomicAdd(&sig[c], K[i]);
-        atomicAdd(&csize[c], 1);
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < n; i0 += (int64_t)gridDim.x * kBlock) {
+        int64_t i = i0 + threadIdx.x;
+        bool ok = i < n;
+        int c = ok ? cm[i] : 0;
+        double k = ok ? K[i] : 0.0;
+        wave_add_f64_by_key(sig, c, k, ok && k != 0.0);
+        if (csize) wave_add_i32_by_key(csize, c, 1, ok);
     }
 }
 
@@ -458,13 +542,13 @@ void launch_move_compact(const MoveArgs &a, const WorkLists &wl, hipStream_t s) 
 
 void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
     (void)wl;
-    int64_t units = 0;
+    int64_t units = 0;   // wave units
     for (int b = 0; b < kNumSmallBins; b++) {
-        int vpb = kBlock / (4 << b);
-        units += (a.qcap[b] + vpb - 1) / vpb;
+        int vpw = kWave / (4 << b);
+        units += (a.qcap[b] + vpw - 1) / vpw;
     }
     if (units == 0) return;
-    unsigned gr = cap_grid(units, 4096);
+    unsigned gr = cap_grid((units + 3) / 4, 8192);
     if (a.g.wt == W_UNIT)
         k_move_small<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -475,28 +559,38 @@ void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
 
 void launch_move_large(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
     (void)wl;
-    int64_t units = (a.qcap[BIN_WAVE] + 3) / 4 + a.qcap[BIN_BLOCK];
-    if (units == 0) return;
-    unsigned gr = cap_grid(units, 2048);
-    if (a.g.wt == W_UNIT)
-        k_move_large<W_UNIT><<<gr, kBlock, 0, s>>>(a);
-    else if (a.g.wt == W_F32)
-        k_move_large<W_F32><<<gr, kBlock, 0, s>>>(a);
-    else
-        k_move_large<W_F64><<<gr, kBlock, 0, s>>>(a);
+    if (a.qcap[BIN_WAVE]) {
+        unsigned gr = cap_grid((a.qcap[BIN_WAVE] + 3) / 4, 4096);
+        if (a.g.wt == W_UNIT)
+            k_move_wave<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+        else if (a.g.wt == W_F32)
+            k_move_wave<W_F32><<<gr, kBlock, 0, s>>>(a);
+        else
+            k_move_wave<W_F64><<<gr, kBlock, 0, s>>>(a);
+    }
+    if (a.qcap[BIN_BLOCK]) {
+        unsigned gr = cap_grid(a.qcap[BIN_BLOCK], 2048);
+        if (a.g.wt == W_UNIT)
+            k_move_block<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+        else if (a.g.wt == W_F32)
+            k_move_block<W_F32><<<gr, kBlock, 0, s>>>(a);
+        else
+            k_move_block<W_F64><<<gr, kBlock, 0, s>>>(a);
+    }
 }
 
 void launch_move_hub(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
     (void)wl;
     if (a.qcap[BIN_HUB] == 0) return;
-    unsigned gr = cap_grid(a.ch_count, 2048);
+    unsigned gr = cap_grid(a.ch_count, 4096);
     if (a.g.wt == W_UNIT)
         k_move_hub_insert<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
         k_move_hub_insert<W_F32><<<gr, kBlock, 0, s>>>(a);
     else
         k_move_hub_insert<W_F64><<<gr, kBlock, 0, s>>>(a);
-    k_move_hub_final<<<cap_grid(a.qcap[BIN_HUB], 1024), kBlock, 0, s>>>(a);
+    k_move_hub_part<<<gr, kBlock, 0, s>>>(a);
+    k_move_hub_final<<<cap_grid((a.qcap[BIN_HUB] + 3) / 4, 1024), kBlock, 0, s>>>(a);
 }
 
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s) {

@@ -9,7 +9,8 @@
 // so every root is the smallest vertex of its set and the final label of a
 // vertex is the smallest vertex id of its component -- the label the
 // one-thread BFS from the lowest unvisited vertex gives.  Parent pointers
-// only decrease, so path halving with plain (agent-scope) stores is safe.
+// only decrease, so path halving with plain (agent-scope) stores is safe
+// while hooking; the final compression walks without halving (see there).
 #include "gsp_internal.h"
 
 namespace gsp {
@@ -105,9 +106,22 @@ __global__ void __launch_bounds__(kBlock) k_split_hook(Level g, const int32_t *b
     }
 }
 
+// Read-only walk to the root (no path halving): used once the forest no
+// longer changes.
+__device__ int find_root_ro(const int32_t *parent, int x) {
+    while (true) {
+        int p = ld(parent + x);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+// Final labels.  Each thread writes only parent[i] (its root); a halving
+// store from another thread's walk could otherwise overwrite that root with
+// an older, non-root ancestor read before it.
 __global__ void __launch_bounds__(kBlock) k_split_compress(int32_t *parent, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        int r = find_root(parent, (int)i);
+        int r = find_root_ro(parent, (int)i);
         st(parent + i, r);
     }
 }

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, d
 }
 
 // One wavefront per row: *sigma_in += entries of row i whose column shares
-// i's community; sig[c] += K_i.
+// i's community (the community totals come from launch_community_totals).
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_modularity_parts(Level g, const int32_t *memb, const double *K,
                                                             double *sig, double *sigma_in) {
@@ -195,10 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_modularity_parts(Level g, const int3
         for (int64_t k = b + lane; k < e; k += kWave)
             if (memb[g.col[k]] == c) s += edge_weight<WT>(g.w, k);
         s = group_sum<kWave>(s);
-        if (lane == 0) {
-            if (K[i] != 0.0) unsafeAtomicAdd(&sig[c], K[i]);
-            blk += s;
-        }
+        if (lane == 0) blk += s;
     }
     if (lane == 0) part[w] = blk;
     __syncthreads();

@@ -187,10 +187,11 @@ def test_run_rmat20_full_size(ctx):
     oracle's synchronous run, 0 disconnected, within 0.005 of async."""
     g = gi.rmat20()
     _load(ctx, g)
-    res = ctx.louvain(tolerance=1e-2, max_passes=10)
     ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
-    np.testing.assert_array_equal(res.membership, ref.membership)
-    assert abs(res.modularity - ref.modularity) <= 1e-9
+    for rep in range(3):   # repeated runs on one context: no state carried over
+        res = ctx.louvain(tolerance=1e-2, max_passes=10)
+        np.testing.assert_array_equal(res.membership, ref.membership)
+        assert abs(res.modularity - ref.modularity) <= 1e-9
     assert ctx.count_disconnected(res.membership) == 0
 
 
