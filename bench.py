@@ -23,14 +23,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edges/s per full GSP-Louvain run; learned-pruned vs plain at equal modularity"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {  # kernel class -> the kernel that dominates it (for rocprof)
+KERNEL_NAMES = {  # kernel class -> its kernel (as rocprof names it)
     "move_small": "k_move_small",
-    "move_large": "k_move_large",
+    "move_wave": "k_move_wave",
+    "move_block": "k_move_block",
     "move_hub": "k_move_hub_insert",
+    "move_hub_finish": "k_move_hub_part + k_move_hub_final",
     "move_apply": "k_move_apply",
     "frontier": "k_move_compact",
-    "split": "k_split_hook",
-    "aggregate": "k_agg_large",
+    "split": "k_split_hook + k_split_compress",
+    "aggregate": "aggregation kernels",
 }
 
 

@@ -68,16 +68,17 @@ typedef struct gsp_options {
     uint64_t mem_limit_bytes;      /* refuse device allocations beyond this total (0 = no limit) */
 } gsp_options;
 
-/* Per-kernel-class counters (timing = 2). */
+/* Per-kernel counters (timing = 2), one class per kernel of the hot path. */
 enum {
-    GSP_K_MOVE_SMALL = 0,  /* local-move scan+decide, degree <= 64 (sub-wave groups) */
-    GSP_K_MOVE_LARGE,      /* local-move scan+decide, 64 < degree <= 2048 (wave / workgroup) */
-    GSP_K_MOVE_HUB,        /* local-move scan+decide, degree > 2048 (global tables) */
+    GSP_K_MOVE_SMALL = 0,  /* local-move scan+decide, degree <= 64 (lane groups) */
+    GSP_K_MOVE_WAVE,       /* local-move scan+decide, 64 < degree <= 512 (a wavefront per vertex) */
+    GSP_K_MOVE_BLOCK,      /* local-move scan+decide, 512 < degree <= 2048 (a workgroup per vertex) */
+    GSP_K_MOVE_HUB,        /* local-move scan of hubs (degree > 2048): chunks into global tables */
+    GSP_K_MOVE_HUB_FINISH, /* hub decisions: table slices scored, then combined */
     GSP_K_MOVE_APPLY,      /* apply moves, community totals */
     GSP_K_FRONTIER,        /* sub-round queue compaction */
     GSP_K_SPLIT,           /* split: union-find hooking and compression */
     GSP_K_AGGREGATE,       /* aggregation kernels */
-    GSP_K_OTHER,           /* weights, renumber, lookup, scans */
     GSP_K_COUNT
 };
 

@@ -24,7 +24,8 @@ GSP_OK, GSP_EINVAL, GSP_ENOMEM, GSP_EHIP, GSP_ESTATE, GSP_EGRAPH = 0, -1, -2, -3
 HOST, DEVICE = 0, 1
 SPLIT_PASS, SPLIT_LAST, SPLIT_NONE = 0, 1, 2
 MAX_PASSES_STATS = 64
-KERNEL_CLASSES = ("move_small", "move_large", "move_hub", "move_apply", "frontier", "split", "aggregate", "other")
+KERNEL_CLASSES = ("move_small", "move_wave", "move_block", "move_hub", "move_hub_finish", "move_apply", "frontier",
+                  "split", "aggregate")
 
 _STATUS = {GSP_EINVAL: "GSP_EINVAL", GSP_ENOMEM: "GSP_ENOMEM", GSP_EHIP: "GSP_EHIP",
            GSP_ESTATE: "GSP_ESTATE", GSP_EGRAPH: "GSP_EGRAPH"}

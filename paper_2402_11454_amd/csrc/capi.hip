@@ -99,10 +99,10 @@ struct gsp_ctx {
 
     // per-vertex work arrays
     double *sig = nullptr;
-    int32_t *cm = nullptr, *csize = nullptr, *dec = nullptr, *movers = nullptr, *queue = nullptr;
+    int32_t *cm = nullptr, *csize = nullptr, *dec = nullptr, *queue = nullptr;
     int32_t *lab = nullptr, *top = nullptr, *bl = nullptr, *tmp32 = nullptr;
     uint8_t *flag = nullptr, *hub_act = nullptr;
-    int32_t *hcnt = nullptr, *hub_ch0 = nullptr;
+    int32_t *hub_ch0 = nullptr;
     int64_t *hub_off = nullptr;
     double *gain_tmp = nullptr;
     Scratch sc;
@@ -144,7 +144,6 @@ struct gsp_ctx {
         mem_used = 0;
         if (sc.hkeys) (void)hipFree(sc.hkeys);
         if (sc.hvals) (void)hipFree(sc.hvals);
-        if (sc.hlist) (void)hipFree(sc.hlist);
         sc = Scratch();
         for (int k = 0; k < 2; k++) {
             offL[k] = nullptr;
@@ -172,16 +171,12 @@ hipError_t ensure_hub_tables(Scratch &sc, uint64_t slots, hipStream_t s) {
     if (e != hipSuccess) return e;
     if (sc.hkeys) (void)hipFree(sc.hkeys);
     if (sc.hvals) (void)hipFree(sc.hvals);
-    if (sc.hlist) (void)hipFree(sc.hlist);
     sc.hkeys = nullptr;
     sc.hvals = nullptr;
-    sc.hlist = nullptr;
     sc.hcap = 0;
     e = hipMalloc(&sc.hkeys, cap * sizeof(int));
     if (e != hipSuccess) return e;
     e = hipMalloc(&sc.hvals, cap * sizeof(double));
-    if (e != hipSuccess) return e;
-    e = hipMalloc(&sc.hlist, cap * sizeof(int));
     if (e != hipSuccess) return e;
     sc.hcap = cap;
     launch_fill_i32(sc.hkeys, kEmpty, (int64_t)cap, s);
@@ -262,13 +257,22 @@ gsp_status renumber(gsp_ctx *ctx, const int32_t *labels, int64_t n, int32_t *out
     return GSP_OK;
 }
 
-// Algorithmic bytes of a scan+decide class (per processed vertex: offset,
-// degree, membership, K, Sigma of the own community, size; per entry:
-// column, weight, neighbour membership; per distinct key: Sigma; per mover:
-// decision, mover slot and one flag byte per entry).
-double move_bytes(int64_t verts, int64_t entries, int64_t keys, int wt) {
+// Algorithmic bytes of the local-moving kernels, per kernel class.
+//  scan+decide (small, wave, block): per vertex decided 36 B (offset, degree,
+//    membership, K, Sigma and size of its community, decision); per entry
+//    4 B column + 4 B neighbour membership + the weight (0 / 4 / 8 B); per
+//    distinct neighbour community 8 B (its Sigma);
+//  hub scan: per entry as above; per (chunk, community) insert into a global
+//    table 12 B (key compare-and-swap, value add);
+//  hub finish: per distinct community 20 B (key, value, Sigma); per hub 36 B.
+double move_bytes(int cls, const CounterStripe &h, int wt) {
     int ws = wt == W_UNIT ? 0 : (wt == W_F32 ? 4 : 8);
-    return 36.0 * (double)verts + (8.0 + ws) * (double)entries + 8.0 * (double)keys;
+    double v = (double)h.verts[cls], e = (double)h.scanned[cls], k = (double)h.keys[cls];
+    switch (cls) {
+        case 3: return (8.0 + ws) * e + 12.0 * (double)h.ginserts;
+        case 4: return 20.0 * k + 36.0 * v;
+        default: return 36.0 * v + (8.0 + ws) * e + 8.0 * k;
+    }
 }
 
 // The local-moving phase on level g (Algorithm "louvainMove" in ordered
@@ -279,7 +283,6 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     hipStream_t s = ctx->stream;
     int P = wl.rounds;
     launch_fill_u8(ctx->flag, 1, g.n, s);
-    launch_fill_i32(ctx->hcnt, 0, g.n, s);
     int li = 0;
     for (int it = 0; it < max_iter; it++) {
         IterCounters *ctr = ctx->ctr + (it & 1);
@@ -295,7 +298,6 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.flag = ctx->flag;
             a.dec = ctx->dec;
             a.gain_out = nullptr;
-            a.movers = ctx->movers;
             a.queue = ctx->queue;
             int64_t cap = 0;
             for (int b = 0; b < kNumBins; b++) {
@@ -311,10 +313,8 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.ch_count = wl.ch_poff[p + 1] - wl.ch_poff[p];
             a.hub_off = wl.hub_off;
             a.hub_act = ctx->hub_act;
-            a.hcnt = ctx->hcnt;
             a.hkeys = ctx->sc.hkeys;
             a.hvals = ctx->sc.hvals;
-            a.hlist = ctx->sc.hlist;
             a.hub_ch0 = ctx->hub_ch0;
             a.part_g = ctx->sc.part_g;
             a.part_kid = ctx->sc.part_kid;
@@ -327,37 +327,56 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL) : -1;
             launch_move_small(a, wl, s);
             ctx->timer.end(t);
-            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_LARGE) : -1;
-            launch_move_large(a, wl, s);
+            t = timing_k && a.qcap[BIN_WAVE] ? ctx->timer.begin(100 + GSP_K_MOVE_WAVE) : -1;
+            launch_move_wave(a, s);
             ctx->timer.end(t);
-            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
-            launch_move_hub(a, wl, s);
+            t = timing_k && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK) : -1;
+            launch_move_block(a, s);
+            ctx->timer.end(t);
+            t = timing_k && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
+            launch_move_hub_scan(a, s);
+            ctx->timer.end(t);
+            t = timing_k && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
+            launch_move_hub_finish(a, s);
             ctx->timer.end(t);
             t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
             launch_move_apply(a, cap, s);
             ctx->timer.end(t);
             if (timing_k) {
                 ctx->kernel_launches[GSP_K_FRONTIER]++;
-                ctx->kernel_launches[GSP_K_MOVE_SMALL]++;
-                ctx->kernel_launches[GSP_K_MOVE_LARGE]++;
-                ctx->kernel_launches[GSP_K_MOVE_HUB] += 2;
+                ctx->kernel_launches[GSP_K_MOVE_SMALL] += cap - a.qcap[BIN_WAVE] - a.qcap[BIN_BLOCK] -
+                                                          a.qcap[BIN_HUB] > 0;
+                ctx->kernel_launches[GSP_K_MOVE_WAVE] += a.qcap[BIN_WAVE] > 0;
+                ctx->kernel_launches[GSP_K_MOVE_BLOCK] += a.qcap[BIN_BLOCK] > 0;
+                ctx->kernel_launches[GSP_K_MOVE_HUB] += a.qcap[BIN_HUB] > 0;
+                ctx->kernel_launches[GSP_K_MOVE_HUB_FINISH] += 2 * (a.qcap[BIN_HUB] > 0);
                 ctx->kernel_launches[GSP_K_MOVE_APPLY]++;
             }
         }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const IterCounters &h = *ctx->ctr_h;
+        CounterStripe h;
+        memset(&h, 0, sizeof(h));
+        for (int q = 0; q < kStripes; q++) {
+            const CounterStripe &x = ctx->ctr_h->st[q];
+            h.gain += x.gain;   // exact on integer weights, in any order
+            h.moved += x.moved;
+            h.ginserts += x.ginserts;
+            for (int c = 0; c < kMoveClasses; c++) {
+                h.verts[c] += x.verts[c];
+                h.scanned[c] += x.scanned[c];
+                h.keys[c] += x.keys[c];
+            }
+        }
         double dq = ctx->M2 > 0.0 ? (2.0 * h.gain) / (ctx->M2 * ctx->M2) : 0.0;
         if (dq_out) dq_out[it] = dq;
         if (moved_out) moved_out[it] = (int64_t)h.moved;
         ctx->stats.moves += (int64_t)h.moved;
-        for (int c = 0; c < 3; c++) {
+        for (int c = 0; c < kMoveClasses; c++) {
             ctx->stats.scanned_entries += (int64_t)h.scanned[c];
             ctx->stats.kernels[GSP_K_MOVE_SMALL + c].items += (int64_t)h.scanned[c];
-            if (kernel_bytes)
-                kernel_bytes[GSP_K_MOVE_SMALL + c] +=
-                    move_bytes((int64_t)h.verts[c], (int64_t)h.scanned[c], (int64_t)h.keys[c], g.wt);
+            if (kernel_bytes) kernel_bytes[GSP_K_MOVE_SMALL + c] += move_bytes(c, h, g.wt);
         }
         li = it + 1;
         if (dq <= tau) break;
@@ -433,7 +452,6 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(ctx->cm, n, "hipMalloc(membership)")) != GSP_OK) return st;
     if ((st = A(ctx->csize, n, "hipMalloc(sizes)")) != GSP_OK) return st;
     if ((st = A(ctx->dec, n, "hipMalloc(decisions)")) != GSP_OK) return st;
-    if ((st = A(ctx->movers, n, "hipMalloc(movers)")) != GSP_OK) return st;
     if ((st = A(ctx->queue, n, "hipMalloc(queue)")) != GSP_OK) return st;
     if ((st = A(ctx->lab, n, "hipMalloc(labels)")) != GSP_OK) return st;
     if ((st = A(ctx->top, n, "hipMalloc(top membership)")) != GSP_OK) return st;
@@ -442,7 +460,6 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(ctx->flag, n, "hipMalloc(flags)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_act, n, "hipMalloc(hub flags)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_off, n, "hipMalloc(hub offsets)")) != GSP_OK) return st;
-    if ((st = A(ctx->hcnt, n, "hipMalloc(hub counters)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_ch0, n, "hipMalloc(hub chunk ids)")) != GSP_OK) return st;
     if ((st = A(ctx->gain_tmp, n, "hipMalloc(gains)")) != GSP_OK) return st;
     Scratch &sc = ctx->sc;
@@ -466,6 +483,8 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(sc.ch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
     if ((st = A(sc.cch_comm, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
     if ((st = A(sc.cch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(sc.cseg_comm, sc.ch_cap, "hipMalloc(segments)")) != GSP_OK) return st;
+    if ((st = A(sc.cseg_beg, sc.ch_cap, "hipMalloc(segments)")) != GSP_OK) return st;
     if ((st = A(sc.part_g, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
     if ((st = A(sc.part_kid, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
     if ((st = A(sc.part_c, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
@@ -847,7 +866,6 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
     launch_copy_i32(ctx->dec, ctx->cm, g.n, s);
     launch_fill_f64(ctx->gain_tmp, 0.0, g.n, s);
-    launch_fill_i32(ctx->hcnt, 0, g.n, s);
     IterCounters *ctr = ctx->ctr;
     HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(IterCounters), s));
     MoveArgs a;
@@ -860,7 +878,6 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     a.flag = ctx->flag;
     a.dec = ctx->dec;
     a.gain_out = ctx->gain_tmp;
-    a.movers = ctx->movers;
     a.queue = ctx->queue;
     for (int b = 0; b < kNumBins; b++) {
         a.qbase[b] = wl.bucket_begin(b, 0);
@@ -874,18 +891,18 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     a.ch_count = wl.ch_poff[1] - wl.ch_poff[0];
     a.hub_off = wl.hub_off;
     a.hub_act = ctx->hub_act;
-    a.hcnt = ctx->hcnt;
     a.hkeys = ctx->sc.hkeys;
     a.hvals = ctx->sc.hvals;
-    a.hlist = ctx->sc.hlist;
     a.hub_ch0 = ctx->hub_ch0;
     a.part_g = ctx->sc.part_g;
     a.part_kid = ctx->sc.part_kid;
     a.part_c = ctx->sc.part_c;
     launch_move_compact(a, wl, s);
     launch_move_small(a, wl, s);
-    launch_move_large(a, wl, s);
-    launch_move_hub(a, wl, s);
+    launch_move_wave(a, s);
+    launch_move_block(a, s);
+    launch_move_hub_scan(a, s);
+    launch_move_hub_finish(a, s);
     HIP_TRY(hipGetLastError());
     st = copy_out(ctx, dec_out, ctx->dec, g.n, where);
     if (st != GSP_OK) return st;
@@ -895,7 +912,9 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     }
     HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    *moved = (int64_t)ctx->ctr_h->moved;
+    int64_t mv = 0;
+    for (int q = 0; q < kStripes; q++) mv += (int64_t)ctx->ctr_h->st[q].moved;
+    *moved = mv;
     return GSP_OK;
 }
 

@@ -94,33 +94,22 @@ __device__ __forceinline__ void lds_table_add(int *keys, double *vals, uint32_t 
     }
 }
 
+// Slot of `key` in an LDS table of mask+1 slots (claimed if absent).
+__device__ __forceinline__ int lds_table_slot(int *keys, uint32_t mask, int key) {
+    uint32_t s = key_hash(key) & mask;
+    while (true) {
+        int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) return (int)s;
+        s = (s + 1) & mask;
+    }
+}
+
 // Same on a table in global memory (device-scope atomics).
 __device__ __forceinline__ void gbl_table_add(int *keys, double *vals, uint64_t mask, int key, double w) {
     uint64_t s = key_hash(key) & mask;
     while (true) {
         int prev = atomicCAS(&keys[s], kEmpty, key);
         if (prev == kEmpty || prev == key) {
-            unsafeAtomicAdd(&vals[s], w);
-            return;
-        }
-        s = (s + 1) & mask;
-    }
-}
-
-// Global table that also lists its occupied slots: the first insertion of a
-// key appends its slot to list[] (counter *cnt), so readers visit only the
-// occupied slots.
-__device__ __forceinline__ void gbl_table_add_listed(int *keys, double *vals, int *list, int *cnt, uint64_t mask,
-                                                     int key, double w) {
-    uint64_t s = key_hash(key) & mask;
-    while (true) {
-        int prev = atomicCAS(&keys[s], kEmpty, key);
-        if (prev == kEmpty) {
-            list[atomicAdd(cnt, 1)] = (int)s;
-            unsafeAtomicAdd(&vals[s], w);
-            return;
-        }
-        if (prev == key) {
             unsafeAtomicAdd(&vals[s], w);
             return;
         }

@@ -49,16 +49,25 @@ struct WorkLists {
     int64_t bin_size(int b) const { return boff[(b + 1) * rounds] - boff[b * rounds]; }
 };
 
+// Totals of the scan+decide kernels, per kernel class (0 small, 1 wave,
+// 2 block, 3 hub scan, 4 hub finish), striped over kStripes cache lines (a
+// block adds to stripe blockIdx % kStripes) so thousands of blocks do not
+// serialise on one address; the host sums the stripes.
+constexpr int kStripes = 16;
+constexpr int kMoveClasses = 5;
+struct alignas(128) CounterStripe {
+    double gain;                               // sum of gain numerators G(c*) - G(stay)
+    unsigned long long moved;                  // movers
+    unsigned long long verts[kMoveClasses];    // vertices decided
+    unsigned long long scanned[kMoveClasses];  // CSR entries scanned
+    unsigned long long keys[kMoveClasses];     // distinct neighbour communities scored
+    unsigned long long ginserts;               // hub scan: (chunk, community) inserts into global tables
+};
+
 // Counters written by the kernels of one local-moving iteration.
-// Kernel classes of the scan+decide step: 0 small, 1 large, 2 hub.
 struct IterCounters {
     int qcnt[kMaxRounds][kNumBins];   // queued vertices per sub-round and bin
-    int nmov[kMaxRounds];             // movers per sub-round
-    double gain;                      // sum of gain numerators G(c*) - G(stay)
-    unsigned long long moved;         // movers in the iteration
-    unsigned long long verts[3];      // vertices scanned, per class
-    unsigned long long scanned[3];    // CSR entries scanned, per class
-    unsigned long long keys[3];       // distinct neighbour communities met, per class
+    CounterStripe st[kStripes];
 };
 
 // Arguments of the local-moving kernels for one sub-round.
@@ -70,9 +79,8 @@ struct MoveArgs {
     const int32_t *cm;
     double M2;
     uint8_t *flag;           // unprocessed flags (read by compaction, set for neighbours of movers)
-    int32_t *dec;            // decision per mover
+    int32_t *dec;            // decision of every queued vertex (its community if it stays)
     double *gain_out;        // per-vertex gain numerator (hooks), or nullptr
-    int32_t *movers;         // movers of this sub-round
     int32_t *queue;          // queued vertices, bin b of this sub-round at qbase[b]
     int64_t qbase[kNumBins];
     int64_t qcap[kNumBins];  // bucket sizes (capacity of each queue)
@@ -84,10 +92,8 @@ struct MoveArgs {
     int64_t ch_first, ch_count;   // static chunk range of this sub-round's hubs
     const int64_t *hub_off;
     uint8_t *hub_act;
-    int *hcnt;               // per vertex: occupied slots of its hub table
     int *hkeys;
     double *hvals;
-    int *hlist;              // occupied-slot lists, parallel to the tables
     const int32_t *hub_ch0;  // per hub vertex: its first chunk id
     double *part_g, *part_kid;  // per chunk: best score and K_{i->d} share
     int *part_c;             // per chunk: best community
@@ -135,8 +141,10 @@ void launch_community_totals(const double *K, const int32_t *cm, int64_t n, doub
                              hipStream_t s);
 void launch_move_compact(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
 void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
-void launch_move_large(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
-void launch_move_hub(const MoveArgs &a, const WorkLists &wl, hipStream_t s);
+void launch_move_wave(const MoveArgs &a, hipStream_t s);
+void launch_move_block(const MoveArgs &a, hipStream_t s);
+void launch_move_hub_scan(const MoveArgs &a, hipStream_t s);
+void launch_move_hub_finish(const MoveArgs &a, hipStream_t s);
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
 
 // ---- k_split.hip ----
@@ -179,17 +187,17 @@ struct Scratch {
     int *err = nullptr;
     unsigned long long *u64 = nullptr;  // 16 counters
     double *f64 = nullptr;              // 16 scalars
-    // hub tables (grown on demand): keys, values and occupied-slot lists
+    // hub tables (grown on demand): keys and values
     int *hkeys = nullptr;
     double *hvals = nullptr;
-    int *hlist = nullptr;
     uint64_t hcap = 0;
-    // hub chunk lists (sized for the input graph): vertex hubs of a level,
-    // and hub communities of an aggregation
+    // chunk lists (sized for the input graph): vertex hubs of a level, hub
+    // communities of an aggregation (entry chunks and table segments), and
+    // per-chunk partial results of the hub decisions
     int32_t *ch_vert = nullptr;
     int64_t *ch_beg = nullptr;
-    int32_t *cch_comm = nullptr;
-    int64_t *cch_beg = nullptr;
+    int32_t *cch_comm = nullptr, *cseg_comm = nullptr;
+    int64_t *cch_beg = nullptr, *cseg_beg = nullptr;
     double *part_g = nullptr, *part_kid = nullptr;   // per chunk
     int *part_c = nullptr;
     int64_t ch_cap = 0;

@@ -29,33 +29,90 @@ inline unsigned grid1(int64_t n, int64_t cap = 8192) {
     return (unsigned)g;
 }
 
-// Community sizes and total degrees, with wave-aggregated atomics (a giant
-// community would otherwise serialise its members' atomics).
+// Community sizes and total degrees.  A tile of kCountTile vertices is
+// first reduced in an LDS table keyed by community, so a giant community
+// costs one global atomic per tile instead of one per member.
+constexpr int kCountTile = 4 * kBlock;
+constexpr int kCountTable = 2 * kCountTile;
+
 __global__ void __launch_bounds__(kBlock) k_agg_count(Level g, const int32_t *cm, int32_t *csz, int64_t *ctot) {
-    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < g.n; i0 += (int64_t)gridDim.x * kBlock) {
-        int64_t i = i0 + threadIdx.x;
-        bool ok = i < g.n;
-        int c = ok ? cm[i] : 0;
-        int d = ok ? g.deg[i] : 0;
-        wave_add_i32_by_key(csz, c, 1, ok);
-        wave_add_u64_by_key((unsigned long long *)ctot, c, (unsigned long long)d, ok && d > 0);
+    __shared__ int tk[kCountTable];
+    __shared__ int tc[kCountTable];
+    __shared__ unsigned long long td[kCountTable];
+    for (int s = threadIdx.x; s < kCountTable; s += kBlock) { tk[s] = kEmpty; tc[s] = 0; td[s] = 0; }
+    __syncthreads();
+    for (int64_t t0 = blockIdx.x * (int64_t)kCountTile; t0 < g.n; t0 += (int64_t)gridDim.x * kCountTile) {
+#pragma unroll
+        for (int r = 0; r < kCountTile / kBlock; r++) {
+            int64_t v = t0 + r * kBlock + threadIdx.x;
+            if (v < g.n) {
+                int slot = lds_table_slot(tk, kCountTable - 1, cm[v]);
+                atomicAdd(&tc[slot], 1);
+                int d = g.deg[v];
+                if (d) atomicAdd(&td[slot], (unsigned long long)d);
+            }
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < kCountTable; s += kBlock) {
+            int c = tk[s];
+            if (c == kEmpty) continue;
+            atomicAdd(&csz[c], tc[s]);
+            if (td[s]) atomicAdd((unsigned long long *)&ctot[c], td[s]);
+            tk[s] = kEmpty;
+            tc[s] = 0;
+            td[s] = 0;
+        }
+        __syncthreads();
     }
 }
 
 // Community vertices CSR: members with entries fill each community's range
 // from the front, members without entries from the back, so the first
-// members of a community all have at least one entry.
+// members of a community all have at least one entry.  Each tile reserves
+// its slots with one atomic per community and side.
 __global__ void __launch_bounds__(kBlock) k_agg_fill(Level g, const int32_t *cm, const int64_t *coff,
                                                     int32_t *front, int32_t *back, int32_t *members) {
-    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < g.n; i0 += (int64_t)gridDim.x * kBlock) {
-        int64_t i = i0 + threadIdx.x;
-        bool ok = i < g.n;
-        int c = ok ? cm[i] : 0;
-        bool has = ok && g.deg[i] > 0;
-        int pf = wave_reserve_by_key(front, c, has);
-        int pb = wave_reserve_by_key(back, c, ok && !has);
-        if (has) members[coff[c] + pf] = (int32_t)i;
-        if (ok && !has) members[coff[c + 1] - 1 - pb] = (int32_t)i;
+    __shared__ int tk[kCountTable];
+    __shared__ int nf[kCountTable], nb[kCountTable];
+    __shared__ int bf[kCountTable], bb[kCountTable];
+    for (int s = threadIdx.x; s < kCountTable; s += kBlock) { tk[s] = kEmpty; nf[s] = 0; nb[s] = 0; }
+    __syncthreads();
+    constexpr int R = kCountTile / kBlock;
+    for (int64_t t0 = blockIdx.x * (int64_t)kCountTile; t0 < g.n; t0 += (int64_t)gridDim.x * kCountTile) {
+        int slot[R], rank[R], comm[R];
+        bool has[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int64_t v = t0 + r * kBlock + threadIdx.x;
+            slot[r] = -1;
+            if (v < g.n) {
+                comm[r] = cm[v];
+                has[r] = g.deg[v] > 0;
+                slot[r] = lds_table_slot(tk, kCountTable - 1, comm[r]);
+                rank[r] = atomicAdd(has[r] ? &nf[slot[r]] : &nb[slot[r]], 1);
+            }
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < kCountTable; s += kBlock) {
+            int c = tk[s];
+            if (c == kEmpty) continue;
+            if (nf[s]) bf[s] = atomicAdd(&front[c], nf[s]);
+            if (nb[s]) bb[s] = atomicAdd(&back[c], nb[s]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (slot[r] < 0) continue;
+            int64_t v = t0 + r * kBlock + threadIdx.x;
+            int c = comm[r];
+            if (has[r])
+                members[coff[c] + bf[slot[r]] + rank[r]] = (int32_t)v;
+            else
+                members[coff[c + 1] - 1 - (bb[slot[r]] + rank[r])] = (int32_t)v;
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < kCountTable; s += kBlock) { tk[s] = kEmpty; nf[s] = 0; nb[s] = 0; }
+        __syncthreads();
     }
 }
 
@@ -101,16 +158,33 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_nchunks(const int32_t *bl, i
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_agg_hub_chunk_fill(const int32_t *bl, int64_t hb, int64_t H,
-                                                              const int64_t *eoff, const int64_t *choff,
-                                                              int32_t *cch_comm, int64_t *cch_beg) {
+// Fills a list of pieces: hub h (h < H, id bl[hb + h]) owns pieces
+// [poff[h], poff[h+1]); piece k of it starts at base(h) + (k - poff[h]) *
+// step.  One thread per piece (binary search for its hub).
+__global__ void __launch_bounds__(kBlock) k_fill_pieces(const int32_t *bl, int64_t hb, int64_t H,
+                                                       const int64_t *poff, const int64_t *base_of, int64_t step,
+                                                       int32_t *pid, int64_t *pbeg) {
+    int64_t total = poff[H];
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < total; k += (int64_t)gridDim.x * kBlock) {
+        int64_t lo = 0, hi = H - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) / 2;
+            if (poff[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        int c = bl[hb + lo];
+        pid[k] = c;
+        pbeg[k] = (base_of ? base_of[c] : 0) + (k - poff[lo]) * step;
+    }
+}
+
+constexpr int kEmitSeg = 4096;          // table slots per workgroup when emitting hub rows
+
+__global__ void __launch_bounds__(kBlock) k_agg_hub_nsegs(const int32_t *bl, int64_t hb, int64_t H,
+                                                         const int64_t *eoff, int64_t n2, int64_t *nseg) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
         int c = bl[hb + k];
-        int64_t nc = choff[k + 1] - choff[k];
-        for (int64_t j = 0; j < nc; j++) {
-            cch_comm[choff[k] + j] = c;
-            cch_beg[choff[k] + j] = eoff[c] + j * kAggChunk;
-        }
+        int64_t T = (int64_t)comm_table_size(eoff[c + 1] - eoff[c], n2);
+        nseg[k] = (T + kEmitSeg - 1) / kEmitSeg;
     }
 }
 
@@ -129,10 +203,8 @@ struct AggArgs {
     int64_t n2;
     const int64_t *ctab;     // hub community table offsets (-1: not a hub)
     const int64_t *mpre;     // exclusive scan of member degrees (flattened entry index)
-    int *hcnt;               // per community: occupied slots of its hub table
     int *hkeys;
     double *hvals;
-    int *hlist;
 };
 
 template <int W>
@@ -372,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_large(AggArgs a) {
 // community's flattened member rows (entry X of the level's member order is
 // entry X - mpre[k] of member k).  The chunk is reduced in LDS, then each
 // distinct (neighbour community, partial sum) goes to the community's global
-// table, whose occupied slots are listed.
+// table.
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_agg_hub_chunks(AggArgs a, const int32_t *cch_comm,
                                                           const int64_t *cch_beg, int64_t nchunks) {
@@ -425,41 +497,72 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_chunks(AggArgs a, const int3
             double v = tvals[s];
             tkeys[s] = kEmpty;
             tvals[s] = 0.0;
-            gbl_table_add_listed(a.hkeys + tb, a.hvals + tb, a.hlist + tb, a.hcnt + c, mask, key, v);
+            gbl_table_add(a.hkeys + tb, a.hvals + tb, mask, key, v);
         }
         __syncthreads();
     }
 }
 
-// One workgroup per hub community: its listed slots become row c of G''.
-__global__ void __launch_bounds__(kBlock) k_agg_hub_emit(AggArgs a) {
+// One workgroup per segment of kEmitSeg slots of a hub community's table:
+// the occupied slots become entries of row c of G'' (the block reserves its
+// range of the row with one atomic on deg''[c]) and are reset.
+__global__ void __launch_bounds__(kBlock) k_agg_hub_emit(AggArgs a, const int32_t *seg_comm, const int64_t *seg_beg,
+                                                        int64_t nseg) {
+    __shared__ int s_cnt[kBlock / kWave];
     __shared__ double s_sum[kBlock / kWave];
-    for (int64_t q = blockIdx.x; q < a.cn[BIN_HUB]; q += gridDim.x) {
-        int c = a.cbl[a.cbeg[BIN_HUB] + q];
+    __shared__ int s_base;
+    constexpr int R = kEmitSeg / kBlock;
+    for (int64_t q = blockIdx.x; q < nseg; q += gridDim.x) {
+        int c = seg_comm[q];
         int64_t tb = a.ctab[c];
-        int used = a.hcnt[c];
-        int64_t base = a.eoff[c];
+        int64_t T = (int64_t)comm_table_size(a.eoff[c + 1] - a.eoff[c], a.n2);
+        int64_t s0 = seg_beg[q];
+        int key[R];
+        double val[R];
+        int cnt = 0;
         double sum = 0.0;
-        for (int k = threadIdx.x; k < used; k += kBlock) {
-            int s = a.hlist[tb + k];
-            int key = a.hkeys[tb + s];
-            double v = a.hvals[tb + s];
-            a.hkeys[tb + s] = kEmpty;
-            a.hvals[tb + s] = 0.0;
-            a.gap_col[base + k] = key;
-            a.gap_w[base + k] = v;
-            sum += v;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int64_t s = s0 + (int64_t)r * kBlock + threadIdx.x;
+            key[r] = kEmpty;
+            val[r] = 0.0;
+            if (s < T) {
+                key[r] = a.hkeys[tb + s];
+                if (key[r] != kEmpty) {
+                    val[r] = a.hvals[tb + s];
+                    a.hkeys[tb + s] = kEmpty;
+                    a.hvals[tb + s] = 0.0;
+                    cnt++;
+                    sum += val[r];
+                }
+            }
         }
+        int wt;
+        int pos = group_excl_scan<kWave>(cnt, lane_id(), &wt);
         sum = group_sum<kWave>(sum);
-        if (lane_id() == 0) s_sum[threadIdx.x / kWave] = sum;
+        int w = threadIdx.x / kWave;
+        if (lane_id() == 0) { s_cnt[w] = wt; s_sum[w] = sum; }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < kBlock / kWave; w++) t += s_sum[w];
-            a.deg2[c] = used;
-            a.K2[c] = t;
-            a.hcnt[c] = 0;
+        int before = 0, all = 0;
+        double tsum = 0.0;
+        for (int x = 0; x < kBlock / kWave; x++) {
+            if (x < w) before += s_cnt[x];
+            all += s_cnt[x];
+            tsum += s_sum[x];
         }
+        if (threadIdx.x == 0) {
+            s_base = all ? atomicAdd(&a.deg2[c], all) : 0;
+            if (tsum != 0.0) unsafeAtomicAdd(&a.K2[c], tsum);
+        }
+        __syncthreads();
+        int64_t dst = a.eoff[c] + s_base + before + pos;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (key[r] != kEmpty) {
+                a.gap_col[dst] = key[r];
+                a.gap_w[dst] = val[r];
+                dst++;
+            }
         __syncthreads();
     }
 }
@@ -488,12 +591,12 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = sc.i64c, *mpre = sc.i64d, *ctab = sc.i64e, *tmp = sc.i64f;
     launch_fill_i32(csz, 0, n2, s);
     launch_fill_i64(ctot, 0, n2, s);
-    k_agg_count<<<grid1(g.n), kBlock, 0, s>>>(g, cm, csz, ctot);
+    k_agg_count<<<grid1((g.n + 3) / 4, 4096), kBlock, 0, s>>>(g, cm, csz, ctot);
     scan_exclusive_i32_to_i64(csz, coff, n2, sc.scan_tmp, s);
     scan_exclusive_i64(ctot, eoff, n2, sc.scan_tmp, s);
     launch_fill_i32(ccur, 0, n2, s);
     launch_fill_i32(csz, 0, n2, s);                  // csz becomes the back cursor
-    k_agg_fill<<<grid1(g.n), kBlock, 0, s>>>(g, cm, coff, ccur, csz, members);
+    k_agg_fill<<<grid1((g.n + 3) / 4, 4096), kBlock, 0, s>>>(g, cm, coff, ccur, csz, members);
     k_agg_cdeg<<<grid1(n2), kBlock, 0, s>>>(eoff, n2, cdeg);
     WorkLists cwl;
     cwl.bl = sc.bl2;
@@ -520,38 +623,46 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     a.n2 = n2;
     a.ctab = ctab;
     a.mpre = mpre;
-    a.hcnt = ccur;
 
-    // hub communities: table offsets in the global pool and entry chunks
-    int64_t H = a.cn[BIN_HUB], nchunks = 0;
+    // hub communities: table offsets in the global pool, entry chunks and
+    // table segments
+    int64_t H = a.cn[BIN_HUB], nchunks = 0, nsegs = 0;
     if (H > 0) {
         unsigned gr = grid1(H, 4096);
         int64_t hb = a.cbeg[BIN_HUB];
         k_agg_hub_sizes<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, n2, ctot);    // ctot is free now
         scan_exclusive_i64(ctot, tmp, H, sc.scan_tmp, s);
         k_agg_hub_off<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, tmp, ctab);
-        int64_t host[2] = {0, 0};
+        int64_t host[3] = {0, 0, 0};
         e = hipMemcpyAsync(&host[0], tmp + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         k_agg_hub_nchunks<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, ctot);
         scan_exclusive_i64(ctot, mpre, H, sc.scan_tmp, s);                        // mpre as temp
         e = hipMemcpyAsync(&host[1], mpre + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
+        k_agg_hub_nsegs<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, n2, ctot);
+        scan_exclusive_i64(ctot, tmp, H, sc.scan_tmp, s);
+        e = hipMemcpyAsync(&host[2], tmp + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         nchunks = host[1];
-        if (nchunks > sc.ch_cap) return hipErrorInvalidValue;
-        k_agg_hub_chunk_fill<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, mpre, sc.cch_comm, sc.cch_beg);
+        nsegs = host[2];
+        if (nchunks > sc.ch_cap || nsegs > sc.ch_cap) return hipErrorInvalidValue;
+        if (nchunks)
+            k_fill_pieces<<<grid1(nchunks, 8192), kBlock, 0, s>>>(cwl.bl, hb, H, mpre, eoff, kAggChunk, sc.cch_comm,
+                                                                  sc.cch_beg);
+        if (nsegs)
+            k_fill_pieces<<<grid1(nsegs, 8192), kBlock, 0, s>>>(cwl.bl, hb, H, tmp, nullptr, kEmitSeg, sc.cseg_comm,
+                                                                sc.cseg_beg);
         e = ensure_hub_tables(sc, (uint64_t)host[0], s);
         if (e != hipSuccess) return e;
         // flattened entry index of every member
         k_member_degrees<<<grid1(g.n), kBlock, 0, s>>>(members, g.n, g.deg, mdeg);
         scan_exclusive_i32_to_i64(mdeg, mpre, g.n, sc.scan_tmp, s);
-        launch_fill_i32(ccur, 0, n2, s);
     }
     a.hkeys = sc.hkeys;
     a.hvals = sc.hvals;
-    a.hlist = sc.hlist;
 
     int64_t us = 0;
     for (int b = 0; b < kNumSmallBins; b++) {
@@ -574,7 +685,7 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
         if (ul) k_agg_large<W_F64><<<gl, kBlock, 0, s>>>(a);
         if (nchunks) k_agg_hub_chunks<W_F64><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     }
-    if (H > 0) k_agg_hub_emit<<<(unsigned)(H < 4096 ? H : 4096), kBlock, 0, s>>>(a);
+    if (nsegs) k_agg_hub_emit<<<(unsigned)(nsegs < 8192 ? nsegs : 8192), kBlock, 0, s>>>(a, sc.cseg_comm, sc.cseg_beg, nsegs);
     // compact
     scan_exclusive_i32_to_i64(out.deg, out.off, n2, sc.scan_tmp, s);
     e = hipMemcpyAsync(nnz_out, out.off + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s);

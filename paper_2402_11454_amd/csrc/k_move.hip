@@ -30,29 +30,38 @@ constexpr int kIntMax = 0x7fffffff;
 
 struct Acc {          // per-thread counters, reduced per block at the end
     double gain = 0.0;
-    unsigned long long moved = 0, verts = 0, scanned = 0, keys = 0;
+    unsigned long long moved = 0, verts = 0, scanned = 0, keys = 0, ginserts = 0;
 };
 
 __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
     __shared__ double sg[kBlock / kWave];
-    __shared__ unsigned long long sm[kBlock / kWave], sv[kBlock / kWave], ss[kBlock / kWave], sk[kBlock / kWave];
+    __shared__ unsigned long long sv[5][kBlock / kWave];
     double g = group_sum<kWave>(acc.gain);
-    long long m = group_sum_ll<kWave>((long long)acc.moved);
-    long long v = group_sum_ll<kWave>((long long)acc.verts);
-    long long s = group_sum_ll<kWave>((long long)acc.scanned);
-    long long k = group_sum_ll<kWave>((long long)acc.keys);
+    long long v[5] = {(long long)acc.moved, (long long)acc.verts, (long long)acc.scanned, (long long)acc.keys,
+                      (long long)acc.ginserts};
+#pragma unroll
+    for (int f = 0; f < 5; f++) v[f] = group_sum_ll<kWave>(v[f]);
     int w = threadIdx.x / kWave;
-    if (lane_id() == 0) { sg[w] = g; sm[w] = m; sv[w] = v; ss[w] = s; sk[w] = k; }
+    if (lane_id() == 0) {
+        sg[w] = g;
+#pragma unroll
+        for (int f = 0; f < 5; f++) sv[f][w] = (unsigned long long)v[f];
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double tg = 0.0;
-        unsigned long long tm = 0, tv = 0, ts = 0, tk = 0;
-        for (int q = 0; q < kBlock / kWave; q++) { tg += sg[q]; tm += sm[q]; tv += sv[q]; ts += ss[q]; tk += sk[q]; }
-        if (tg != 0.0) unsafeAtomicAdd(&ctr->gain, tg);
-        if (tm) atomicAdd(&ctr->moved, tm);
-        if (tv) atomicAdd(&ctr->verts[cls], tv);
-        if (ts) atomicAdd(&ctr->scanned[cls], ts);
-        if (tk) atomicAdd(&ctr->keys[cls], tk);
+        unsigned long long t[5] = {0, 0, 0, 0, 0};
+        for (int q = 0; q < kBlock / kWave; q++) {
+            tg += sg[q];
+            for (int f = 0; f < 5; f++) t[f] += sv[f][q];
+        }
+        CounterStripe &st = ctr->st[blockIdx.x % kStripes];
+        if (tg != 0.0) unsafeAtomicAdd(&st.gain, tg);
+        if (t[0]) atomicAdd(&st.moved, t[0]);
+        if (t[1]) atomicAdd(&st.verts[cls], t[1]);
+        if (t[2]) atomicAdd(&st.scanned[cls], t[2]);
+        if (t[3]) atomicAdd(&st.keys[cls], t[3]);
+        if (t[4]) atomicAdd(&st.ginserts, t[4]);
     }
 }
 
@@ -89,7 +98,11 @@ __device__ __forceinline__ void take_slot(const MoveArgs &a, int *keys, double *
 
 // ---------------------------------------------------------------- compact
 
+// Unprocessed vertices of the sub-round's buckets -> per-bin queues; each
+// block reserves its queue slots with one atomic per bin.
 __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32_t *bl) {
+    __shared__ int lcnt[kNumBins];
+    __shared__ int lbase[kNumBins];
     int64_t pre[kNumBins + 1];
     pre[0] = 0;
 #pragma unroll
@@ -97,28 +110,26 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
     int64_t total = pre[kNumBins];
     int *qcnt = a.ctr->qcnt[a.round];
     for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < total; t0 += (int64_t)gridDim.x * kBlock) {
+        if (threadIdx.x < kNumBins) lcnt[threadIdx.x] = 0;
+        __syncthreads();
         int64_t t = t0 + threadIdx.x;
-        int b = -1, i = -1;
-        bool act = false;
+        int b = -1, i = -1, rank = -1;
         if (t < total) {
             b = 0;
             while (t >= pre[b + 1]) b++;
             i = bl[a.qbase[b] + (t - pre[b])];
-            act = a.flag[i] != 0;
-            if (act) {
+            if (a.flag[i]) {
                 a.flag[i] = 0;
                 if (b == BIN_HUB) a.hub_act[i] = 1;
+                rank = atomicAdd(&lcnt[b], 1);
             }
         }
-        unsigned long long pending = __ballot(act);
-        while (pending) {
-            int leader = __ffsll((long long)pending) - 1;
-            int lb = __shfl(b, leader);
-            bool mine = act && b == lb;
-            int slot = wave_append(mine, &qcnt[lb]);
-            if (mine) a.queue[a.qbase[lb] + slot] = i;
-            pending &= ~__ballot(mine);
-        }
+        __syncthreads();
+        if (threadIdx.x < kNumBins && lcnt[threadIdx.x] > 0)
+            lbase[threadIdx.x] = atomicAdd(&qcnt[threadIdx.x], lcnt[threadIdx.x]);
+        __syncthreads();
+        if (rank >= 0) a.queue[a.qbase[b] + lbase[b] + rank] = i;
+        __syncthreads();
     }
 }
 
@@ -192,15 +203,13 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     if (lead) {
         acc.verts++;
         acc.scanned += (unsigned long long)di;
+        a.dec[i] = mv ? bc : d;
         if (mv) {
-            a.dec[i] = bc;
             acc.gain += gain;
             acc.moved++;
         }
         if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
     }
-    int slot = wave_append(lead && mv, &a.ctr->nmov[a.round]);
-    if (slot >= 0) a.movers[slot] = i;
     wave_lds_sync();
 }
 
@@ -300,11 +309,10 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         if (lane == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
+            a.dec[i] = mv ? bc : d;
             if (mv) {
-                a.dec[i] = bc;
                 acc.gain += gain;
                 acc.moved++;
-                a.movers[atomicAdd(&a.ctr->nmov[a.round], 1)] = i;
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
@@ -352,17 +360,16 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         if (tid == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
+            a.dec[i] = mv ? bc : d;
             if (mv) {
-                a.dec[i] = bc;
                 acc.gain += gain;
                 acc.moved++;
-                a.movers[atomicAdd(&a.ctr->nmov[a.round], 1)] = i;
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
         __syncthreads();
     }
-    flush_acc(acc, a.ctr, 1);
+    flush_acc(acc, a.ctr, 2);
 }
 
 // ---------------------------------------------------------------- hubs
@@ -370,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
 // One workgroup per chunk of kHubChunk entries of an active hub: the chunk
 // is first reduced in an LDS table (so a community met many times in the
 // chunk costs one global atomic), then each distinct (community, partial
-// sum) goes into the hub's global table, whose occupied slots are listed.
+// sum) goes into the hub's global table.
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     __shared__ int tkeys[kBlockTable];
@@ -401,33 +408,37 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
             double v = tvals[s];
             tkeys[s] = kEmpty;
             tvals[s] = 0.0;
-            gbl_table_add_listed(a.hkeys + tb, a.hvals + tb, a.hlist + tb, a.hcnt + i, mask, key, v);
+            gbl_table_add(a.hkeys + tb, a.hvals + tb, mask, key, v);
+            acc.ginserts++;
         }
         if (threadIdx.x == 0) acc.scanned += (unsigned long long)(end - beg);
         __syncthreads();
     }
-    flush_acc(acc, a.ctr, 2);
+    flush_acc(acc, a.ctr, 3);
 }
 
-// One workgroup per chunk again: the chunk's segment [s*kHubChunk,
-// (s+1)*kHubChunk) of the hub's occupied-slot list is scored (the table is
-// complete now) and reset; the segment's best candidate and its share of
-// K_{i->d} go to part_*[chunk].
+// One workgroup per chunk again: chunk s of a hub with nch chunks scores and
+// resets the slice [s*seg, (s+1)*seg) of the hub's table (seg = ceil(T /
+// nch) <= 8192 slots; the table is complete now) and leaves the slice's best
+// candidate and its share of K_{i->d} in part_*[chunk].
 __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
     Acc acc;
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
         if (!a.hub_act[i]) continue;
-        int64_t seg0 = a.ch_beg[k] - a.g.off[i];
-        int used = a.hcnt[i];
-        int64_t seg1 = seg0 + kHubChunk < used ? seg0 + kHubChunk : used;
+        int di = a.g.deg[i];
+        int64_t T = (int64_t)hub_table_size(di);
+        int64_t nch = (di + kHubChunk - 1) / kHubChunk;
+        int64_t seg = (T + nch - 1) / nch;
+        int64_t sidx = (a.ch_beg[k] - a.g.off[i]) / kHubChunk;
+        int64_t s0 = sidx * seg, s1 = s0 + seg < T ? s0 + seg : T;
         int d = a.cm[i];
         double ki = a.K[i];
         int64_t tb = a.hub_off[i];
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int64_t q = seg0 + threadIdx.x; q < seg1; q += kBlock)
-            take_slot(a, a.hkeys + tb, a.hvals + tb, a.hlist[tb + q], d, ki, bg, bc, kid, acc.keys);
+        for (int64_t q = s0 + threadIdx.x; q < s1; q += kBlock)
+            take_slot(a, a.hkeys + tb, a.hvals + tb, q, d, ki, bg, bc, kid, acc.keys);
         block_argmax_sum(bg, bc, kid);
         if (threadIdx.x == 0) {
             a.part_g[k] = bg;
@@ -435,7 +446,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
             a.part_kid[k] = kid;
         }
     }
-    flush_acc(acc, a.ctr, 2);
+    flush_acc(acc, a.ctr, 4);
 }
 
 // One wavefront per active hub: combines its chunks' partial results,
@@ -473,31 +484,36 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         if (lane == 0) {
             acc.verts++;
             a.hub_act[i] = 0;
-            a.hcnt[i] = 0;
+            a.dec[i] = mv ? bc : d;
             if (mv) {
-                a.dec[i] = bc;
                 acc.gain += gain;
                 acc.moved++;
-                a.movers[atomicAdd(&a.ctr->nmov[a.round], 1)] = i;
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
     }
-    flush_acc(acc, a.ctr, 2);
+    flush_acc(acc, a.ctr, 4);
 }
 
 // ---------------------------------------------------------------- apply
 
-// Moves of the sub-round: C'[i] <- c*, Sigma and sizes updated.
+// Moves of the sub-round: every queued vertex whose decision differs from
+// its community moves (C'[i] <- c*), Sigma and sizes follow.
 __global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a) {
-    int n = a.ctr->nmov[a.round];
+    int64_t pre[kNumBins + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int b = 0; b < kNumBins; b++) pre[b + 1] = pre[b] + a.ctr->qcnt[a.round][b];
     int32_t *cm = const_cast<int32_t *>(a.cm);
     double *sig = const_cast<double *>(a.sig);
     int32_t *csize = const_cast<int32_t *>(a.csize);
-    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock) {
-        int i = a.movers[k];
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < pre[kNumBins]; t += (int64_t)gridDim.x * kBlock) {
+        int b = 0;
+        while (t >= pre[b + 1]) b++;
+        int i = a.queue[a.qbase[b] + (t - pre[b])];
         int c = a.dec[i];
         int d = cm[i];
+        if (c == d) continue;
         double ki = a.K[i];
         cm[i] = c;
         if (ki != 0.0) {
@@ -557,30 +573,29 @@ void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
         k_move_small<W_F64><<<gr, kBlock, 0, s>>>(a);
 }
 
-void launch_move_large(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
-    (void)wl;
-    if (a.qcap[BIN_WAVE]) {
-        unsigned gr = cap_grid((a.qcap[BIN_WAVE] + 3) / 4, 4096);
-        if (a.g.wt == W_UNIT)
-            k_move_wave<W_UNIT><<<gr, kBlock, 0, s>>>(a);
-        else if (a.g.wt == W_F32)
-            k_move_wave<W_F32><<<gr, kBlock, 0, s>>>(a);
-        else
-            k_move_wave<W_F64><<<gr, kBlock, 0, s>>>(a);
-    }
-    if (a.qcap[BIN_BLOCK]) {
-        unsigned gr = cap_grid(a.qcap[BIN_BLOCK], 2048);
-        if (a.g.wt == W_UNIT)
-            k_move_block<W_UNIT><<<gr, kBlock, 0, s>>>(a);
-        else if (a.g.wt == W_F32)
-            k_move_block<W_F32><<<gr, kBlock, 0, s>>>(a);
-        else
-            k_move_block<W_F64><<<gr, kBlock, 0, s>>>(a);
-    }
+void launch_move_wave(const MoveArgs &a, hipStream_t s) {
+    if (a.qcap[BIN_WAVE] == 0) return;
+    unsigned gr = cap_grid((a.qcap[BIN_WAVE] + 3) / 4, 4096);
+    if (a.g.wt == W_UNIT)
+        k_move_wave<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+    else if (a.g.wt == W_F32)
+        k_move_wave<W_F32><<<gr, kBlock, 0, s>>>(a);
+    else
+        k_move_wave<W_F64><<<gr, kBlock, 0, s>>>(a);
 }
 
-void launch_move_hub(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
-    (void)wl;
+void launch_move_block(const MoveArgs &a, hipStream_t s) {
+    if (a.qcap[BIN_BLOCK] == 0) return;
+    unsigned gr = cap_grid(a.qcap[BIN_BLOCK], 2048);
+    if (a.g.wt == W_UNIT)
+        k_move_block<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+    else if (a.g.wt == W_F32)
+        k_move_block<W_F32><<<gr, kBlock, 0, s>>>(a);
+    else
+        k_move_block<W_F64><<<gr, kBlock, 0, s>>>(a);
+}
+
+void launch_move_hub_scan(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
     unsigned gr = cap_grid(a.ch_count, 4096);
     if (a.g.wt == W_UNIT)
@@ -589,7 +604,11 @@ void launch_move_hub(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
         k_move_hub_insert<W_F32><<<gr, kBlock, 0, s>>>(a);
     else
         k_move_hub_insert<W_F64><<<gr, kBlock, 0, s>>>(a);
-    k_move_hub_part<<<gr, kBlock, 0, s>>>(a);
+}
+
+void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
+    if (a.qcap[BIN_HUB] == 0) return;
+    k_move_hub_part<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
     k_move_hub_final<<<cap_grid((a.qcap[BIN_HUB] + 3) / 4, 1024), kBlock, 0, s>>>(a);
 }
 
