@@ -76,6 +76,20 @@ __device__ __forceinline__ bool decide(const MoveArgs &a, int i, int d, double k
     return true;
 }
 
+// Folds the entry (key, v) of a scan table into (bg, bc, kid).
+__device__ __forceinline__ void fold_key(const MoveArgs &a, int key, double v, int d, double ki, double &bg, int &bc,
+                                         double &kid) {
+    if (key == d) {
+        kid = v;
+    } else {
+        double g = a.M2 * v - ki * a.sig[key];
+        if (better(g, key, bg, bc)) {
+            bg = g;
+            bc = key;
+        }
+    }
+}
+
 // Reads one table slot, resets it and folds it into (bg, bc, kid).
 __device__ __forceinline__ void take_slot(const MoveArgs &a, int *keys, double *vals, int64_t s, int d, double ki,
                                           double &bg, int &bc, double &kid, unsigned long long &nkeys) {
@@ -118,9 +132,10 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
             b = 0;
             while (t >= pre[b + 1]) b++;
             i = bl[a.qbase[b] + (t - pre[b])];
-            if (a.flag[i]) {
+            bool act = a.flag[i] != 0;
+            if (b == BIN_HUB) a.hub_act[i] = act ? 1 : 0;
+            if (act) {
                 a.flag[i] = 0;
-                if (b == BIN_HUB) a.hub_act[i] = 1;
                 rank = atomicAdd(&lcnt[b], 1);
             }
         }
@@ -288,15 +303,16 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
         double ki = a.K[i];
+        const int T = (int)hub_table_size(di);   // <= kWaveTable: at most half full
         for (int e = lane; e < di; e += kWave) {
             int j = load_col(a.g.col, beg + e);
             double wt = edge_weight<WT>(a.g.w, beg + e);
-            if (j != i) lds_table_add(keys, vals, kWaveTable - 1, a.cm[j], wt);
+            if (j != i) lds_table_add(keys, vals, T - 1, a.cm[j], wt);
         }
         wave_lds_sync();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int s = lane; s < kWaveTable; s += kWave) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        for (int s = lane; s < T; s += kWave) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
         group_argmax<kWave>(bg, bc);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
@@ -340,15 +356,16 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
         double ki = a.K[i];
+        const int T = (int)hub_table_size(di);   // <= kBlockTable: at most half full
         for (int e = tid; e < di; e += kBlock) {
             int j = load_col(a.g.col, beg + e);
             double wt = edge_weight<WT>(a.g.w, beg + e);
-            if (j != i) lds_table_add(keys, vals, kBlockTable - 1, a.cm[j], wt);
+            if (j != i) lds_table_add(keys, vals, T - 1, a.cm[j], wt);
         }
         __syncthreads();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int s = tid; s < kBlockTable; s += kBlock) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        for (int s = tid; s < T; s += kBlock) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
         block_argmax_sum(bg, bc, kid);
         double gain = 0.0;
         bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
@@ -402,14 +419,38 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
         __syncthreads();
         int64_t tb = a.hub_off[i];
         uint64_t mask = hub_table_size(a.g.deg[i]) - 1;
-        for (int s = threadIdx.x; s < kBlockTable; s += kBlock) {
-            int key = tkeys[s];
-            if (key == kEmpty) continue;
-            double v = tvals[s];
-            tkeys[s] = kEmpty;
-            tvals[s] = 0.0;
-            gbl_table_add(a.hkeys + tb, a.hvals + tb, mask, key, v);
-            acc.ginserts++;
+        int *gk = a.hkeys + tb;
+        double *gv = a.hvals + tb;
+        // batches of 4 slots: the first compare-and-swaps are issued together
+        for (int s0 = threadIdx.x; s0 < kBlockTable; s0 += 4 * kBlock) {
+            int key[4], prev[4];
+            double v[4];
+            uint64_t gs[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                int sl = s0 + u * kBlock;
+                key[u] = tkeys[sl];
+                v[u] = tvals[sl];
+                tkeys[sl] = kEmpty;
+                tvals[sl] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                prev[u] = kEmpty;
+                if (key[u] != kEmpty) {
+                    gs[u] = key_hash(key[u]) & mask;
+                    prev[u] = atomicCAS(&gk[gs[u]], kEmpty, key[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (key[u] == kEmpty) continue;
+                acc.ginserts++;
+                if (prev[u] == kEmpty || prev[u] == key[u])
+                    unsafeAtomicAdd(&gv[gs[u]], v[u]);
+                else
+                    gbl_table_add(gk, gv, mask, key[u], v[u]);
+            }
         }
         if (threadIdx.x == 0) acc.scanned += (unsigned long long)(end - beg);
         __syncthreads();
@@ -437,8 +478,31 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
         int64_t tb = a.hub_off[i];
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int64_t q = s0 + threadIdx.x; q < s1; q += kBlock)
-            take_slot(a, a.hkeys + tb, a.hvals + tb, q, d, ki, bg, bc, kid, acc.keys);
+        int *gk = a.hkeys + tb;
+        double *gv = a.hvals + tb;
+        for (int64_t q0 = s0 + threadIdx.x; q0 < s1; q0 += 4 * kBlock) {
+            int key[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                int64_t q = q0 + u * kBlock;
+                key[u] = q < s1 ? gk[q] : kEmpty;
+            }
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                v[u] = 0.0;
+                if (key[u] != kEmpty) {
+                    int64_t q = q0 + u * kBlock;
+                    v[u] = gv[q];
+                    gk[q] = kEmpty;
+                    gv[q] = 0.0;
+                    acc.keys++;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (key[u] != kEmpty) fold_key(a, key[u], v[u], d, ki, bg, bc, kid);
+        }
         block_argmax_sum(bg, bc, kid);
         if (threadIdx.x == 0) {
             a.part_g[k] = bg;
@@ -449,8 +513,8 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
     flush_acc(acc, a.ctr, 4);
 }
 
-// One wavefront per active hub: combines its chunks' partial results,
-// decides and marks the neighbours of a mover.
+// One wavefront per active hub: combines its chunks' partial results and
+// decides (the neighbours of a moving hub are marked by the apply kernel).
 __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int cnt = a.ctr->qcnt[a.round][BIN_HUB];
@@ -459,7 +523,6 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
     for (int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + w; qi < cnt; qi += nw) {
         int i = a.queue[a.qbase[BIN_HUB] + qi];
         int di = a.g.deg[i];
-        int64_t beg = a.g.off[i];
         int d = a.cm[i];
         double ki = a.K[i];
         int64_t c0 = a.hub_ch0[i];
@@ -476,14 +539,9 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
         bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
-        if (mv)
-            for (int64_t e = lane; e < di; e += kWave) {
-                int j = load_col(a.g.col, beg + e);
-                if (j != i) a.flag[j] = 1;
-            }
         if (lane == 0) {
             acc.verts++;
-            a.hub_act[i] = 0;
+            a.hub_act[i] = mv ? 2 : 0;   // 2: its neighbours are marked chunk by chunk in apply
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;
@@ -497,9 +555,38 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
 
 // ---------------------------------------------------------------- apply
 
-// Moves of the sub-round: every queued vertex whose decision differs from
-// its community moves (C'[i] <- c*), Sigma and sizes follow.
-__global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a) {
+// Moves of the sub-round.  Blocks [0, nq) walk the sub-round's queue: every
+// vertex whose decision differs from its community moves (C'[i] <- c*);
+// the Sigma and size changes of a tile are summed per community in LDS
+// first (movers crowd into a few popular communities).  Blocks [nq, ...)
+// take the sub-round's hub chunks and mark the chunk's neighbours of a hub
+// that moved.
+constexpr int kApplyTable = 4 * kBlock;
+
+__global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a, int nq) {
+    __shared__ int tk[kApplyTable];
+    __shared__ double tv[kApplyTable];
+    __shared__ int tc[kApplyTable];
+    if ((int)blockIdx.x >= nq) {
+        for (int64_t k = a.ch_first + (blockIdx.x - nq); k < a.ch_first + a.ch_count; k += gridDim.x - nq) {
+            int i = a.ch_vert[k];
+            if (a.hub_act[i] != 2) continue;
+            int64_t beg = a.ch_beg[k];
+            int64_t end = a.g.off[i] + a.g.deg[i];
+            if (end > beg + kHubChunk) end = beg + kHubChunk;
+            for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) {
+                int j = load_col(a.g.col, e);
+                if (j != i) a.flag[j] = 1;
+            }
+        }
+        return;
+    }
+    for (int s = threadIdx.x; s < kApplyTable; s += kBlock) {
+        tk[s] = kEmpty;
+        tv[s] = 0.0;
+        tc[s] = 0;
+    }
+    __syncthreads();
     int64_t pre[kNumBins + 1];
     pre[0] = 0;
 #pragma unroll
@@ -507,21 +594,38 @@ __global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a) {
     int32_t *cm = const_cast<int32_t *>(a.cm);
     double *sig = const_cast<double *>(a.sig);
     int32_t *csize = const_cast<int32_t *>(a.csize);
-    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < pre[kNumBins]; t += (int64_t)gridDim.x * kBlock) {
-        int b = 0;
-        while (t >= pre[b + 1]) b++;
-        int i = a.queue[a.qbase[b] + (t - pre[b])];
-        int c = a.dec[i];
-        int d = cm[i];
-        if (c == d) continue;
-        double ki = a.K[i];
-        cm[i] = c;
-        if (ki != 0.0) {
-            unsafeAtomicAdd(&sig[d], -ki);
-            unsafeAtomicAdd(&sig[c], ki);
+    for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < pre[kNumBins]; t0 += (int64_t)nq * kBlock) {
+        int64_t t = t0 + threadIdx.x;
+        if (t < pre[kNumBins]) {
+            int b = 0;
+            while (t >= pre[b + 1]) b++;
+            int i = a.queue[a.qbase[b] + (t - pre[b])];
+            int c = a.dec[i];
+            int d = cm[i];
+            if (c != d) {
+                double ki = a.K[i];
+                cm[i] = c;
+                int sd = lds_table_slot(tk, kApplyTable - 1, d);
+                int sc = lds_table_slot(tk, kApplyTable - 1, c);
+                if (ki != 0.0) {
+                    atomicAdd(&tv[sd], -ki);
+                    atomicAdd(&tv[sc], ki);
+                }
+                atomicSub(&tc[sd], 1);
+                atomicAdd(&tc[sc], 1);
+            }
         }
-        atomicSub(&csize[d], 1);
-        atomicAdd(&csize[c], 1);
+        __syncthreads();
+        for (int s = threadIdx.x; s < kApplyTable; s += kBlock) {
+            int key = tk[s];
+            if (key == kEmpty) continue;
+            if (tv[s] != 0.0) unsafeAtomicAdd(&sig[key], tv[s]);
+            if (tc[s] != 0) atomicAdd(&csize[key], tc[s]);
+            tk[s] = kEmpty;
+            tv[s] = 0.0;
+            tc[s] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -614,7 +718,9 @@ void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s) {
     if (cap == 0) return;
-    k_move_apply<<<cap_grid((cap + kBlock - 1) / kBlock, 2048), kBlock, 0, s>>>(a);
+    int nq = (int)cap_grid((cap + kBlock - 1) / kBlock, 2048);
+    int nh = a.qcap[BIN_HUB] ? (int)cap_grid(a.ch_count, 2048) : 0;
+    k_move_apply<<<nq + nh, kBlock, 0, s>>>(a, nq);
 }
 
 }  // namespace gsp
