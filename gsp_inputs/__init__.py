@@ -49,6 +49,8 @@ def _load():
     lib.gen_sbm.argtypes = [i64, i64, dbl, dbl, u64, i32, i32, dbl, dbl]
     lib.gen_rmat.restype = vp
     lib.gen_rmat.argtypes = [i32, i64, dbl, dbl, dbl, u64, i32, i32, dbl, dbl]
+    lib.gen_dcsbm.restype = vp
+    lib.gen_dcsbm.argtypes = [i64, dbl, i64, i64, dbl, i64, i64, dbl, u64, i32, i32, dbl, dbl]
     lib.gen_from_edges.restype = vp
     lib.gen_from_edges.argtypes = [i64, i64, vp, vp]
     lib.gen_free.argtypes = [vp]
@@ -126,6 +128,16 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int, 
     lo, hi = weights if weights is not None else (1.0, 1.0)
     samples = edge_factor << scale
     h = _load().gen_rmat(scale, samples, a, b, c, seed, int(permute), int(weights is not None), lo, hi)
+    return _take(h, name)
+
+
+def dcsbm(n: int, deg_alpha: float, kmin: int, kmax: int, size_alpha: float, smin: int, smax: int, mu: float,
+          seed: int, permute: bool = True, weights: Optional[tuple] = (1.0, 4.0), name: str = "dcsbm") -> Graph:
+    """Degree-corrected SBM with power-law degrees and community sizes (see
+    gen.c): ``block`` holds each vertex's planted community."""
+    lo, hi = weights if weights is not None else (1.0, 1.0)
+    h = _load().gen_dcsbm(n, deg_alpha, kmin, kmax, size_alpha, smin, smax, mu, seed, int(permute),
+                          int(weights is not None), lo, hi)
     return _take(h, name)
 
 
@@ -210,6 +222,19 @@ def rmat20(seed: int = 20) -> Graph:
 def rmat_small(scale: int, seed: int, edge_factor: int = 16, weights=None) -> Graph:
     """Smaller R-MAT of the same law, for parity tests."""
     return rmat(scale, edge_factor, *RMAT_ABC, seed, weights=weights, name=f"rmat-{scale}")
+
+
+def dcsbm_4m(seed: int, n: int = 4_000_000) -> Graph:
+    """The social-network-shaped workload: n vertices (4M), degrees power
+    law 2.5 on [5, 5000], community sizes power law 1.5 on [20, 50000],
+    mixing 0.3, weights uniform in [1, 4] (fp32).  Seeds 0-31 are the
+    training graphs of the pruning network, 1000-1007 the held-out ones."""
+    return dcsbm(n, 2.5, 5, 5000, 1.5, 20, 50_000, 0.3, seed, name=f"dcsbm-{n}-s{seed}")
+
+
+def dcsbm_small(n: int, seed: int, mu: float = 0.3, kmax: int = 500, smax: int = 2000) -> Graph:
+    """Smaller graph of the same law (tests, quick training)."""
+    return dcsbm(n, 2.5, 5, kmax, 1.5, 20, smax, mu, seed, name=f"dcsbm-{n}-s{seed}")
 
 
 def batch_sbm_params(count: int, master_seed: int = 4):

@@ -329,6 +329,224 @@ gen_graph *gen_rmat(int scale, int64_t samples, double a, double b, double c, ui
     return g;
 }
 
+/* Discrete power law on [lo, hi] with exponent alpha (P(k) ~ k^-alpha),
+ * drawn by inverting the continuous law on [lo, hi + 1) and flooring. */
+static int64_t powerlaw_draw(xoshiro *r, double alpha, int64_t lo, int64_t hi) {
+    double e = 1.0 - alpha;
+    double a = pow((double)lo, e), b = pow((double)(hi + 1), e);
+    double x = pow(a + (b - a) * xo_uniform(r), 1.0 / e);
+    int64_t k = (int64_t)floor(x);
+    return k < lo ? lo : (k > hi ? hi : k);
+}
+
+/* Fenwick tree over community capacities (sampling proportional to the
+ * remaining capacity of a prefix of communities). */
+static void fw_add(int64_t *t, int64_t m, int64_t i, int64_t v) {
+    for (i++; i <= m; i += i & -i) t[i] += v;
+}
+static int64_t fw_prefix(const int64_t *t, int64_t i) {  /* sum of [0, i) */
+    int64_t s = 0;
+    for (; i > 0; i -= i & -i) s += t[i];
+    return s;
+}
+static int64_t fw_find(const int64_t *t, int64_t m, int64_t x) {  /* smallest i: prefix(i+1) > x */
+    int64_t pos = 0, step = 1;
+    while (step * 2 <= m) step *= 2;
+    for (; step > 0; step >>= 1)
+        if (pos + step <= m && t[pos + step] <= x) { pos += step; x -= t[pos]; }
+    return pos;
+}
+
+/* Index of the first element of cum[0..len) (non-decreasing) exceeding x. */
+static int64_t upper_index(const double *cum, int64_t len, double x) {
+    int64_t lo = 0, hi = len - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (cum[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/* Degree-corrected SBM with power-law degrees and community sizes (LFR-like
+ * construction, Chung-Lu edges):
+ *   1. target degrees k_i ~ discrete power law (deg_alpha) on [kmin, kmax];
+ *   2. community sizes ~ power law (size_alpha) on [smin, smax] until they
+ *      cover n (the last one takes the rest; a rest below smin is merged
+ *      into the previous community);
+ *   3. vertices, highest degree first, join a community drawn with
+ *      probability proportional to its free places among the communities
+ *      with s - 1 >= (1 - mu) k_i (all communities if none has room);
+ *   4. community c receives round(sum_i (1-mu) k_i / 2) edges whose ends
+ *      are drawn inside c proportionally to (1-mu) k_i, and the graph
+ *      receives round(sum_i mu k_i / 2) edges whose ends are drawn over all
+ *      vertices proportionally to mu k_i, redrawn (up to 16 times) while
+ *      both ends share a community.
+ * Community c's edges come from the stream SplitMix64(seed, c); the mixing
+ * edges are drawn in blocks of 2^16, each from its own stream, so the
+ * result does not depend on the thread count.  block[v] = community of v. */
+gen_graph *gen_dcsbm(int64_t n, double deg_alpha, int64_t kmin, int64_t kmax, double size_alpha, int64_t smin,
+                     int64_t smax, double mu, uint64_t seed, int permute, int weighted, double wlo, double whi) {
+    if (n <= 1 || kmin < 1 || kmax < kmin || smin < 2 || smax < smin || mu < 0.0 || mu > 1.0) return NULL;
+    xoshiro r;
+    xo_seed(&r, seed);
+    int64_t *k = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *comm = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t ccap = 1024, nc = 0;
+    int64_t *size = (int64_t *)malloc((size_t)ccap * sizeof(int64_t));
+    if (!k || !comm || !size) { free(k); free(comm); free(size); return NULL; }
+    for (int64_t i = 0; i < n; i++) k[i] = powerlaw_draw(&r, deg_alpha, kmin, kmax);
+    int64_t covered = 0;
+    while (covered < n) {
+        int64_t sz = powerlaw_draw(&r, size_alpha, smin, smax);
+        if (sz > n - covered) sz = n - covered;
+        if (sz < smin && nc > 0) { size[nc - 1] += sz; covered += sz; break; }
+        if (nc == ccap) {
+            ccap *= 2;
+            int64_t *ns = (int64_t *)realloc(size, (size_t)ccap * sizeof(int64_t));
+            if (!ns) { free(k); free(comm); free(size); return NULL; }
+            size = ns;
+        }
+        size[nc++] = sz;
+        covered += sz;
+    }
+    /* communities by size, largest first; vertices by degree, largest first */
+    int64_t *corder = (int64_t *)malloc((size_t)nc * sizeof(int64_t));
+    int64_t *vorder = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *fw = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+    int64_t *bucket = (int64_t *)calloc((size_t)(kmax + 2), sizeof(int64_t));
+    if (!corder || !vorder || !fw || !bucket) {
+        free(k); free(comm); free(size); free(corder); free(vorder); free(fw); free(bucket);
+        return NULL;
+    }
+    for (int64_t c = 0; c < nc; c++) corder[c] = c;
+    for (int64_t a = 1; a < nc; a++) {  /* insertion sort on a nearly random list: few thousand items */
+        int64_t x = corder[a], b = a - 1;
+        while (b >= 0 && size[corder[b]] < size[x]) { corder[b + 1] = corder[b]; b--; }
+        corder[b + 1] = x;
+    }
+    for (int64_t i = 0; i < n; i++) bucket[kmax - k[i] + 1]++;
+    for (int64_t d = 0; d <= kmax; d++) bucket[d + 1] += bucket[d];
+    for (int64_t i = 0; i < n; i++) vorder[bucket[kmax - k[i]]++] = i;
+    free(bucket);
+    for (int64_t c = 0; c < nc; c++) fw_add(fw, nc, c, size[corder[c]]);
+    int64_t eligible = 0;  /* grows as degrees fall: prefix of corder with room for the vertex */
+    for (int64_t t = 0; t < n; t++) {
+        int64_t i = vorder[t];
+        double need = (1.0 - mu) * (double)k[i];
+        while (eligible < nc && (double)(size[corder[eligible]] - 1) >= need) eligible++;
+        int64_t pref = eligible > 0 ? eligible : nc;
+        int64_t room = fw_prefix(fw, pref);
+        if (room == 0) { pref = nc; room = fw_prefix(fw, nc); }
+        int64_t x = (int64_t)(xo_uniform(&r) * (double)room);
+        if (x >= room) x = room - 1;
+        int64_t pos = fw_find(fw, nc, x);
+        fw_add(fw, nc, pos, -1);
+        comm[i] = corder[pos];
+    }
+    free(fw);
+    free(vorder);
+    free(corder);
+    /* members of each community */
+    int64_t *moff = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+    int64_t *mem = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *eoff = (int64_t *)calloc((size_t)nc + 2, sizeof(int64_t));
+    double *cum = (double *)malloc((size_t)n * sizeof(double));
+    if (!moff || !mem || !eoff || !cum) {
+        free(k); free(comm); free(size); free(moff); free(mem); free(eoff); free(cum);
+        return NULL;
+    }
+    for (int64_t i = 0; i < n; i++) moff[comm[i] + 1]++;
+    for (int64_t c = 0; c < nc; c++) moff[c + 1] += moff[c];
+    {
+        int64_t *cur = (int64_t *)malloc((size_t)nc * sizeof(int64_t));
+        if (!cur) { free(k); free(comm); free(size); free(moff); free(mem); free(eoff); free(cum); return NULL; }
+        memcpy(cur, moff, (size_t)nc * sizeof(int64_t));
+        for (int64_t i = 0; i < n; i++) mem[cur[comm[i]]++] = i;
+        free(cur);
+    }
+    double tot_out = 0.0;
+    for (int64_t c = 0; c < nc; c++) {
+        double s_in = 0.0;
+        for (int64_t t = moff[c]; t < moff[c + 1]; t++) {
+            s_in += (1.0 - mu) * (double)k[mem[t]];
+            cum[t] = s_in;
+        }
+        eoff[c + 1] = eoff[c] + (moff[c + 1] - moff[c] > 1 ? (int64_t)llround(s_in / 2.0) : 0);
+    }
+    double *ocum = (double *)malloc((size_t)n * sizeof(double));
+    if (!ocum) { free(k); free(comm); free(size); free(moff); free(mem); free(eoff); free(cum); return NULL; }
+    for (int64_t i = 0; i < n; i++) {
+        tot_out += mu * (double)k[i];
+        ocum[i] = tot_out;
+    }
+    int64_t e_in = eoff[nc], e_out = tot_out > 0.0 ? (int64_t)llround(tot_out / 2.0) : 0;
+    int64_t m = e_in + e_out;
+    int32_t *eu = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t *ev = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    if (!eu || !ev) {
+        free(k); free(comm); free(size); free(moff); free(mem); free(eoff); free(cum); free(ocum); free(eu); free(ev);
+        return NULL;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < nc; c++) {
+        int64_t len = moff[c + 1] - moff[c];
+        if (len < 2) continue;
+        xoshiro rc;
+        xo_seed(&rc, splitmix64_hash(seed * 0x9e3779b97f4a7c15ULL + 0x632be59bd9b4e019ULL + (uint64_t)c));
+        const double *cc = cum + moff[c];
+        double tot = cc[len - 1];
+        for (int64_t e = eoff[c]; e < eoff[c + 1]; e++) {
+            int64_t a = upper_index(cc, len, xo_uniform(&rc) * tot);
+            int64_t b = upper_index(cc, len, xo_uniform(&rc) * tot);
+            eu[e] = (int32_t)mem[moff[c] + a];
+            ev[e] = (int32_t)mem[moff[c] + b];
+        }
+    }
+    const int64_t BLK = (int64_t)1 << 16;
+    int64_t nblk = (e_out + BLK - 1) / BLK;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t blk = 0; blk < nblk; blk++) {
+        xoshiro rb;
+        xo_seed(&rb, splitmix64_hash(seed * 0x9e3779b97f4a7c15ULL + 0x2545f4914f6cdd1dULL + (uint64_t)blk));
+        int64_t e0 = blk * BLK, e1 = e0 + BLK < e_out ? e0 + BLK : e_out;
+        for (int64_t e = e0; e < e1; e++) {
+            int64_t a = 0, b = 0;
+            for (int tries = 0; tries < 16; tries++) {
+                a = upper_index(ocum, n, xo_uniform(&rb) * tot_out);
+                b = upper_index(ocum, n, xo_uniform(&rb) * tot_out);
+                if (comm[a] != comm[b]) break;
+            }
+            eu[e_in + e] = (int32_t)a;
+            ev[e_in + e] = (int32_t)b;
+        }
+    }
+    free(cum);
+    free(ocum);
+    free(mem);
+    free(moff);
+    free(eoff);
+    free(size);
+    free(k);
+    int32_t *perm = NULL;
+    if (permute) {
+        perm = random_perm(n, seed);
+        if (!perm) { free(eu); free(ev); free(comm); return NULL; }
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < m; e++) { eu[e] = perm[eu[e]]; ev[e] = perm[ev[e]]; }
+    }
+    gen_graph *g = build_csr(n, m, eu, ev);
+    free(eu);
+    free(ev);
+    if (!g) { free(perm); free(comm); return NULL; }
+    g->block = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (g->block)
+        for (int64_t v = 0; v < n; v++) g->block[perm ? perm[v] : v] = comm[v];
+    free(perm);
+    free(comm);
+    if (weighted && attach_weights(g, seed, wlo, whi)) return NULL;
+    return g;
+}
+
 /* Graph from a caller's undirected edge list (used by hand-built test
  * graphs): symmetrised, deduplicated, self-loops dropped. */
 gen_graph *gen_from_edges(int64_t n, int64_t m, const int32_t *eu, const int32_t *ev) {

@@ -25,6 +25,7 @@ def _check_csr(g):
     lambda: gi.rmat_small(12, 1),
     lambda: gi.rmat_small(12, 2, weights=(1.0, 10.0)),
     lambda: gi.sbm(3000, 7, 0.05, 0.001, 5, weights=(1.0, 4.0)),
+    lambda: gi.dcsbm_small(5000, 3),
 ])
 def test_valid_and_deterministic(make):
     a, b = make(), make()
@@ -49,3 +50,33 @@ def test_batch_params():
     ps = gi.batch_sbm_params(512)
     ns = np.array([p["n"] for p in ps])
     assert ns.min() >= 1000 and ns.max() <= 200_000
+
+
+def test_dcsbm_shape():
+    """Power-law degrees and community sizes, mixing mu: the planted
+    communities hold about 1 - mu of the entries, community sizes respect
+    the size law's bounds, the degree law's bounds hold, and every vertex
+    sits in a community with room for its intra-community stubs."""
+    mu = 0.3
+    g = gi.dcsbm(30_000, 2.5, 5, 600, 1.5, 20, 3000, mu, 11)
+    _check_csr(g)
+    rows = np.repeat(np.arange(g.n), g.degrees())
+    intra = (g.block[rows] == g.block[g.cols]).mean()
+    assert abs(intra - (1 - mu)) < 0.03
+    sizes = np.bincount(g.block)
+    sizes = sizes[sizes > 0]
+    assert sizes.min() >= 20 and sizes.sum() == g.n
+    assert sizes.max() <= 3000 + 20                      # a merged remainder may exceed smax by < smin
+    d = g.degrees()
+    assert d.max() <= 600                                # duplicates only lower degrees
+    assert 8.0 < d.mean() < 16.0                         # law mean ~ 12.6 before dedup
+    # heavy tail: the top 1% of vertices hold far more than 1% of the entries
+    top = np.sort(d)[::-1][: g.n // 100].sum() / g.nnz
+    assert top > 0.05
+    full = np.bincount(g.block)                          # room for the intra stubs: (1-mu) k <= s - 1
+    assert np.all(full[g.block] - 1 >= (1 - mu) * d)
+
+
+def test_dcsbm_seeds_differ():
+    a, b = gi.dcsbm_small(4000, 0), gi.dcsbm_small(4000, 1)
+    assert a.nnz != b.nnz or not np.array_equal(a.cols, b.cols)
