@@ -1,12 +1,15 @@
 """TEST INFRASTRUCTURE ONLY: ctypes binding of the sequential CPU oracle.
 
 The oracle (``oracle.c``) is a plain, slow, fp64 rendering of GSP-Louvain
-(arXiv 2402.11454).  Only the tests, ``__graft_entry__.smoke()`` and the
+(arXiv 2402.11454); ``prune.c`` adds the learned pruning gate that runs
+beside its local-moving phase (features, the 8-64-64-1 network, its loss,
+gradients and Adam, and the gated synchronous phase).  Only the tests, ``__graft_entry__.smoke()`` and the
 bench's CPU-baseline leg may import this package; the GPU library never does.
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -15,15 +18,15 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "prune.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles oracle.c (always recompiles): -O2, no fast-math, no FMA."""
+    """Compiles oracle.c and prune.c (always recompiles): -O2, no fast-math, no FMA."""
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+           "-o", _LIB_PATH + ".tmp", *_SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -31,17 +34,25 @@ def build(verbose: bool = False) -> str:
     return _LIB_PATH
 
 
+class _Trace(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("threshold", ctypes.c_uint64), ("cap", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("vertex", ctypes.c_void_p),
+                ("meta", ctypes.c_void_p), ("rows", ctypes.c_int64), ("seen", ctypes.c_int64)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("tolerance", ctypes.c_double), ("max_passes", ctypes.c_int32),
                 ("max_iterations", ctypes.c_int32), ("tolerance_drop", ctypes.c_double),
                 ("aggregation_tolerance", ctypes.c_double), ("sync_moves", ctypes.c_int32),
-                ("sync_rounds", ctypes.c_int32), ("split_mode", ctypes.c_int32)]
+                ("sync_rounds", ctypes.c_int32), ("split_mode", ctypes.c_int32),
+                ("prune_params", ctypes.c_void_p), ("prune_theta_logit", ctypes.c_double),
+                ("trace", ctypes.POINTER(_Trace))]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("iterations", ctypes.c_int32 * 64),
                 ("communities", ctypes.c_int64 * 64), ("vertices", ctypes.c_int64 * 64),
-                ("modularity", ctypes.c_double)]
+                ("modularity", ctypes.c_double), ("counters", ctypes.c_int64 * 4)]
 
 
 def _load():
@@ -65,6 +76,17 @@ def _load():
         "orc_aggregate": (i64, [i64, vp, vp, vp, vp, i64, vp, vp, vp, i64]),
         "orc_disconnected": (i64, [i64, vp, vp, vp, vp]),
         "orc_louvain": (i32, [i64, vp, vp, vp, ctypes.POINTER(_Options), vp, ctypes.POINTER(_Stats)]),
+        "orc_bf16": (ctypes.c_float, [ctypes.c_float]),
+        "orc_plog2": (dbl, [dbl]),
+        "orc_gate_features": (None, [i64, dbl, dbl, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, i32, i32, vp]),
+        "orc_mlp_logits": (None, [vp, vp, i64, i32, vp]),
+        "orc_mlp_loss_grad": (dbl, [vp, vp, vp, i64, dbl, vp]),
+        "orc_mlp_loss_grad_f64": (dbl, [vp, vp, vp, i64, dbl, vp]),
+        "orc_mlp_loss_grad_f32": (ctypes.c_float, [vp, vp, vp, i64, ctypes.c_float, vp]),
+        "orc_mlp_train_adam": (i64, [vp, vp, vp, i64, i64, i32, dbl, dbl, vp]),
+        "orc_trace_keep": (i32, [ctypes.c_uint64, i32, i32, i64, ctypes.c_uint64]),
+        "orc_move_sync_gated": (i32, [i64, vp, vp, vp, dbl, vp, vp, dbl, i32, i32, vp, dbl, i32,
+                                      ctypes.POINTER(_Trace), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -231,18 +253,154 @@ class Result:
     modularity: float = 0.0
 
 
+MLP_PARAMS = 4801
+
+
+def _params(params):
+    if params is None:
+        return None
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.shape == (MLP_PARAMS,)
+    return p
+
+
+def logit_of(theta: float) -> float:
+    """Gate threshold on the probability -> threshold on the logit."""
+    return math.log(theta / (1.0 - theta))
+
+
+def bf16(x) -> np.ndarray:
+    """bf16 rounding (to nearest even) of fp32 values, elementwise."""
+    x = np.asarray(x, dtype=np.float32).ravel()
+    f = _load().orc_bf16
+    return np.array([f(float(v)) for v in x], dtype=np.float32)
+
+
+def plog2(x: float) -> float:
+    return float(_load().orc_plog2(float(x)))
+
+
+def gate_features(deg, ki, sig_d, hfrac, hgain, hbits, pass_index, iteration) -> np.ndarray:
+    x = np.empty(8, dtype=np.float32)
+    _load().orc_gate_features(int(deg), float(ki), float(sig_d), float(hfrac), float(hgain), int(hbits),
+                              int(pass_index), int(iteration), _p(x))
+    return x
+
+
+def mlp_logits(params, x, bf16_formats: bool = False) -> np.ndarray:
+    p = _params(params)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+    out = np.empty(x.shape[0], dtype=np.float64)
+    _load().orc_mlp_logits(_p(p), _p(x), x.shape[0], int(bf16_formats), _p(out))
+    return out
+
+
+def mlp_loss_grad(params, x, y, pos_weight: float = 1.0, fp32: bool = False):
+    """(loss, gradient[4801]) of the mean pos-weighted BCE."""
+    p = _params(params)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    if fp32:
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = _load().orc_mlp_loss_grad_f32(_p(p), _p(x), _p(y), x.shape[0], pos_weight, _p(g))
+    else:
+        g = np.empty(MLP_PARAMS, dtype=np.float64)
+        loss = _load().orc_mlp_loss_grad(_p(p), _p(x), _p(y), x.shape[0], pos_weight, _p(g))
+    return float(loss), g
+
+
+def mlp_loss_grad_f64(params, x, y, pos_weight: float = 1.0):
+    """Loss and gradient at fp64 parameters (for finite differences)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    assert p.shape == (MLP_PARAMS,)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    g = np.empty(MLP_PARAMS, dtype=np.float64)
+    loss = _load().orc_mlp_loss_grad_f64(_p(p), _p(x), _p(y), x.shape[0], pos_weight, _p(g))
+    return float(loss), g
+
+
+def mlp_train_adam(params, x, y, batch: int, epochs: int, lr: float, pos_weight: float = 1.0):
+    """Returns (trained params fp32, per-epoch mean batch loss)."""
+    p = _params(params).copy()
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    el = np.zeros(max(epochs, 1), dtype=np.float64)
+    t = _load().orc_mlp_train_adam(_p(p), _p(x), _p(y), x.shape[0], batch, epochs, lr, pos_weight, _p(el))
+    if t < 0:
+        raise ValueError("orc_mlp_train_adam failed")
+    return p, el[:epochs]
+
+
+def trace_keep(seed: int, pass_index: int, sweep: int, i: int, threshold: int) -> bool:
+    return bool(_load().orc_trace_keep(seed, pass_index, sweep, i, threshold))
+
+
+class Trace:
+    """Trace buffers: rows of (features, moved, vertex, pass * 256 + sweep)."""
+
+    def __init__(self, cap: int, seed: int = 0, rate: float = 1.0):
+        self.cap = int(cap)
+        self.x = np.zeros((self.cap, 8), dtype=np.float32)
+        self.y = np.zeros(self.cap, dtype=np.uint8)
+        self.vertex = np.zeros(self.cap, dtype=np.int32)
+        self.meta = np.zeros(self.cap, dtype=np.int32)
+        thr = 2 ** 64 - 1 if rate >= 1.0 else int(rate * 2 ** 64)
+        self.c = _Trace(seed, thr, self.cap, _p(self.x), _p(self.y), _p(self.vertex), _p(self.meta), 0, 0)
+
+    @property
+    def rows(self) -> int:
+        return int(self.c.rows)
+
+    @property
+    def seen(self) -> int:
+        return int(self.c.seen)
+
+    def arrays(self):
+        r = self.rows
+        return self.x[:r], self.y[:r], self.vertex[:r], self.meta[:r]
+
+
+def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, memb=None, tau: float = 0.0,
+                    max_iter: int = 20, rounds: int = 8, trace: Optional[Trace] = None, theta_logit=None):
+    """Returns (membership, l_i, dQ per counted iteration, movers per counted
+    iteration, counters dict)."""
+    g = CSR.of(g)
+    K, M2 = vertex_weights(g)
+    m = np.arange(g.n, dtype=np.int32) if memb is None else _memb(memb, g.n).copy()
+    dq = np.zeros(max(max_iter, 1), dtype=np.float64)
+    mv = np.zeros(max(max_iter, 1), dtype=np.int64)
+    c4 = np.zeros(4, dtype=np.int64)
+    p = _params(params)
+    tl = theta_logit if theta_logit is not None else logit_of(theta)
+    li = _load().orc_move_sync_gated(*g.args(), M2, _p(K), _p(m), tau, max_iter, rounds, _p(p), tl, pass_index,
+                                     ctypes.byref(trace.c) if trace is not None else None, _p(dq), _p(mv), _p(c4))
+    if li < 0:
+        raise ValueError("orc_move_sync_gated failed")
+    cnt = dict(scanned_vertices=int(c4[0]), scanned_entries=int(c4[1]), pruned=int(c4[2]), confirm_sweeps=int(c4[3]))
+    return m, li, dq[:li], mv[:li], cnt
+
+
 def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: int = 20,
             tolerance_drop: float = 10.0, aggregation_tolerance: float = 0.8,
-            sync: bool = False, rounds: int = 8, split_mode: int = 0) -> Result:
-    """The whole method; split_mode 0 = every pass, 1 = after the last, 2 = none."""
+            sync: bool = False, rounds: int = 8, split_mode: int = 0, prune_params=None, theta: float = 0.5,
+            trace: Optional[Trace] = None, theta_logit=None) -> Result:
+    """The whole method; split_mode 0 = every pass, 1 = after the last, 2 = none.
+    prune_params / trace need sync=True."""
     g = CSR.of(g)
+    p = _params(prune_params)
+    tl = theta_logit if theta_logit is not None else logit_of(theta)
     opt = _Options(tolerance, max_passes, max_iterations, tolerance_drop, aggregation_tolerance,
-                   int(sync), rounds, split_mode)
+                   int(sync), rounds, split_mode, _p(p), tl,
+                   ctypes.pointer(trace.c) if trace is not None else None)
     st = _Stats()
     memb = np.empty(g.n, dtype=np.int32)
     passes = _load().orc_louvain(*g.args(), ctypes.byref(opt), _p(memb), ctypes.byref(st))
     if passes < 0:
         raise ValueError("orc_louvain failed")
     k = min(passes, 64)
-    return Result(memb, passes, list(st.iterations[:k]), list(st.communities[:k]), list(st.vertices[:k]),
-                  float(st.modularity))
+    r = Result(memb, passes, list(st.iterations[:k]), list(st.communities[:k]), list(st.vertices[:k]),
+               float(st.modularity))
+    r.counters = dict(scanned_vertices=int(st.counters[0]), scanned_entries=int(st.counters[1]),
+                      pruned=int(st.counters[2]), confirm_sweeps=int(st.counters[3]))
+    return r

@@ -567,7 +567,13 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         orc_vertex_weights(gn, goff, gcol, gw, K);
         for (int64_t i = 0; i < gn; i++) { sigma[i] = K[i]; cm[i] = (int32_t)i; }
         int32_t li;
-        if (opt->sync_moves)
+        if (opt->sync_moves && (opt->prune_params || opt->trace)) {
+            int64_t c4[4];
+            li = orc_move_sync_gated(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds,
+                                     opt->prune_params, opt->prune_theta_logit, lp, opt->trace, NULL, NULL, c4);
+            if (stats)
+                for (int q = 0; q < 4; q++) stats->counters[q] += c4[q];
+        } else if (opt->sync_moves)
             li = orc_move_sync(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds, NULL, NULL);
         else
             li = orc_move_async(gn, goff, gcol, gw, M2, K, cm, sigma, tau, opt->max_iterations, NULL);

@@ -89,6 +89,58 @@ int64_t orc_aggregate(int64_t n, const int64_t *off, const int32_t *col, const d
  * has length n, may be NULL).  Returns the number of such communities. */
 int64_t orc_disconnected(int64_t n, const int64_t *off, const int32_t *col, const int32_t *memb, uint8_t *flags);
 
+/* ---- learned pruning gate (prune.c) ---- */
+
+#define ORC_MLP_PARAMS 4801  /* (8*64 + 64) + (64*64 + 64) + (64 + 1) */
+
+/* bf16 (round to nearest even) of an fp32 value, as fp32. */
+float orc_bf16(float x);
+
+/* Piecewise-linear log2 for x >= 1 (0 below): e + x / 2^e - 1. */
+double orc_plog2(double x);
+
+/* The gate's 8 features of a vertex (see prune.c), bf16 values as fp32. */
+void orc_gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain, uint8_t hbits, int32_t pass,
+                       int32_t iter, float *x);
+
+/* Logits of rows x[rows][8]; bf16 = 1 emulates the inference formats. */
+void orc_mlp_logits(const float *params, const float *x, int64_t rows, int32_t bf16, double *out);
+
+/* Mean pos-weighted BCE and its gradient (grad[ORC_MLP_PARAMS], may be
+ * NULL), fp64; _f64 takes fp64 parameters, _f32 computes in fp32. */
+double orc_mlp_loss_grad(const float *params, const float *x, const uint8_t *y, int64_t rows, double pos_weight,
+                         double *grad);
+double orc_mlp_loss_grad_f64(const double *params, const float *x, const uint8_t *y, int64_t rows,
+                             double pos_weight, double *grad);
+float orc_mlp_loss_grad_f32(const float *params, const float *x, const uint8_t *y, int64_t rows, float pos_weight,
+                            float *grad);
+
+/* Adam over contiguous mini-batches, `epochs` passes (fp64). */
+int64_t orc_mlp_train_adam(float *params, const float *x, const uint8_t *y, int64_t rows, int64_t batch,
+                           int32_t epochs, double lr, double pos_weight, double *epoch_loss);
+
+/* Trace sampling predicate: mix64(seed ^ pass<<56 ^ sweep<<48 ^ i) < threshold. */
+int32_t orc_trace_keep(uint64_t seed, int32_t pass, int32_t sweep, int64_t i, uint64_t threshold);
+
+typedef struct orc_trace {
+    uint64_t seed, threshold;  /* sampling (orc_trace_keep) */
+    int64_t cap;               /* rows the buffers hold */
+    float *x;                  /* [cap][8] features before the scan */
+    uint8_t *y;                /* [cap] 1 if the vertex moved */
+    int32_t *vertex;           /* [cap] vertex id at its level */
+    int32_t *meta;             /* [cap] pass * 256 + sweep */
+    int64_t rows;              /* rows written (<= cap) */
+    int64_t seen;              /* rows kept by the sampling (may exceed cap) */
+} orc_trace;
+
+/* Synchronous phase with the learned gate and confirming sweep (prune.c);
+ * params = NULL runs it plain.  counters (4, may be NULL): scanned
+ * vertices, scanned entries, pruned vertices, confirming sweeps. */
+int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
+                            const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
+                            const float *params, double theta_logit, int32_t pass, orc_trace *trace,
+                            double *dq_iter, int64_t *moved_iter, int64_t *counters);
+
 typedef struct orc_options {
     double tolerance;              /* tau for the first pass */
     int32_t max_passes;
@@ -98,6 +150,9 @@ typedef struct orc_options {
     int32_t sync_moves;            /* 0: asynchronous sequential, 1: synchronous sub-rounds */
     int32_t sync_rounds;           /* sub-rounds per iteration when sync_moves = 1 */
     int32_t split_mode;            /* 0: every pass (SP), 1: after the last pass (SL), 2: none */
+    const float *prune_params;     /* learned gate (sync_moves = 1 only), NULL = plain */
+    double prune_theta_logit;      /* scan iff logit >= this */
+    orc_trace *trace;              /* move traces (sync_moves = 1 only), may be NULL */
 } orc_options;
 
 typedef struct orc_stats {
@@ -106,6 +161,7 @@ typedef struct orc_stats {
     int64_t communities[64];       /* |Gamma| after each pass's split */
     int64_t vertices[64];          /* N' of each pass */
     double modularity;
+    int64_t counters[4];           /* gated phase: scanned vertices, scanned entries, pruned, confirming sweeps */
 } orc_stats;
 
 /* The whole method (Algorithm "louvain").  memb_out[n] gets the top-level
