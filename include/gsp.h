@@ -66,7 +66,12 @@ typedef struct gsp_options {
     int32_t split_mode;            /* GSP_SPLIT_PASS (default), GSP_SPLIT_LAST or GSP_SPLIT_NONE */
     int32_t timing;                /* 0: none; 1: per-phase HIP-event times; 2: also per-kernel times */
     uint64_t mem_limit_bytes;      /* refuse device allocations beyond this total (0 = no limit) */
+    int32_t prune_mode;            /* GSP_PRUNE_PLAIN (default) or GSP_PRUNE_LEARNED (network set by gsp_pruner_set) */
+    float prune_threshold;         /* learned gate: scan a vertex iff p = sigmoid(z) >= this (default 0.5) */
 } gsp_options;
+
+/* Vertex pruning of the local-moving phase (prune_mode). */
+enum { GSP_PRUNE_PLAIN = 0, GSP_PRUNE_LEARNED = 1 };
 
 /* Per-kernel counters (timing = 2), one class per kernel of the hot path. */
 enum {
@@ -79,6 +84,7 @@ enum {
     GSP_K_FRONTIER,        /* sub-round queue compaction */
     GSP_K_SPLIT,           /* split: union-find hooking and compression */
     GSP_K_AGGREGATE,       /* aggregation kernels */
+    GSP_K_GATE,            /* learned gate: features and the network (bf16 matrix cores) */
     GSP_K_COUNT
 };
 
@@ -98,6 +104,10 @@ typedef struct gsp_stats {
     int64_t scanned_entries;                   /* CSR entries scanned by the local-moving phase */
     double ms_move, ms_split, ms_aggregate, ms_other, ms_total;  /* timing >= 1 */
     gsp_kernel_stat kernels[GSP_K_COUNT];       /* timing = 2 */
+    int64_t scanned_vertices;                  /* vertices scanned by the local-moving phase, all passes */
+    int64_t pruned;                            /* unprocessed vertices the learned gate kept from the scan */
+    int32_t confirm_sweeps;                    /* confirming plain sweeps run after gated convergence */
+    int32_t sweeps;                            /* local-moving sweeps run, all passes (counted or not) */
 } gsp_stats;
 
 /* Fills *out with the defaults above. */
@@ -198,6 +208,89 @@ gsp_status gsp_step_split(gsp_ctx *ctx, const int32_t *membership, int where, in
  * otherwise offsets (n_out + 1), cols and weights (nnz_out) are filled. */
 gsp_status gsp_step_aggregate(gsp_ctx *ctx, const int32_t *membership, int where, int64_t *n_out,
                               int64_t *nnz_out, int64_t *offsets, int32_t *cols, double *weights);
+
+/* The local-moving phase alone with the run's options (learned gate
+ * included): as gsp_move_phase, with opt = NULL for the defaults and
+ * pass_index (0..255) the pass the phase stands for (a gate feature and the
+ * pass recorded in trace rows).  dq_iter / moved_iter have room for
+ * opt->max_iterations values and receive the counted iterations; counters
+ * (4 values, may be NULL): vertices scanned, CSR entries scanned, vertices
+ * pruned by the gate, confirming sweeps run. */
+gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance, int32_t pass_index,
+                             const gsp_options *opt, int32_t *iterations, double *dq_iter, int64_t *moved_iter,
+                             int64_t *counters);
+
+/* ---- learned vertex pruning ----
+ *
+ * Not part of the paper.  In a run with prune_mode = GSP_PRUNE_LEARNED every
+ * unprocessed vertex of a sweep (the vertices Algorithm "louvainMove" would
+ * scan after Section 4.1's pruning) first goes through a small network
+ * z = w3 . relu(W2 relu(W1 x + b1) + b2) + b3 (8 -> 64 -> 64 -> 1) on 8
+ * features that need no scan of its row:
+ *   x0 = plog2(1 + row length) / 16, with plog2(v) = e + v / 2^e - 1 for
+ *        2^e <= v < 2^(e+1);
+ *   x1 = K_{i->d} / K_i at the vertex's last scan in this pass (0 before);
+ *   x2 = (G(best) - G(stay)) / (M2 K_i) at that scan, clipped to [-1, 1]
+ *        (-1 with no candidate community, 0 for K_i = 0);
+ *   x3 = min(pass, 8) / 8;  x4 = min(l, 20) / 20 with l the iterations
+ *        counted so far in the pass;
+ *   x5 = K_i / Sigma_{C_i} (0 if either is 0);
+ *   x6 = 1 if it moved at its last scan; x7 = 1 if it was scanned before
+ *        in this pass;
+ * each computed in fp64 and rounded to fp32, then to bf16 (round to nearest
+ * even).  The vertex is scanned iff z >= log(theta / (1 - theta)), theta =
+ * prune_threshold; otherwise it keeps its community.  Inference uses bf16
+ * weights (W1, W2, w3) and bf16 first-layer outputs with fp32 accumulation.
+ * When a gated sweep's gain total is <= tau, a confirming sweep scans every
+ * vertex with no gate: if its total is <= tau as well the phase ends,
+ * otherwise plain sweeps continue until the usual test stops them.  A
+ * confirming sweep that moves no vertex does not count towards l_i or
+ * max_iterations.  Vertices with empty rows are never gated or scanned. */
+
+/* Parameters: 4801 fp32 values, W1 [64][8] row-major, b1[64], W2 [64][64]
+ * (row = output unit), b2[64], w3[64], b3.  The context keeps the network
+ * (in its inference formats) across loads until the next call.  Non-finite
+ * values give GSP_EINVAL. */
+gsp_status gsp_pruner_set(gsp_ctx *ctx, const float *params, int64_t count, int where);
+
+/* Logits of feature rows x[rows][8] (rounded to bf16 on the device) by the
+ * inference kernel, into logits[rows] (fp32).  Needs gsp_pruner_set. */
+gsp_status gsp_gate_logits(gsp_ctx *ctx, const float *x, int64_t rows, float *logits, int where);
+
+/* Mean pos-weighted binary cross-entropy of rows (x[rows][8], y[rows] in
+ * {0, 1}) at `params` and its gradient grad_out[4801], by the fp32 training
+ * kernels:  L = (1/B) sum_r [pw y_r log(1 + e^{-z_r}) + (1 - y_r) log(1 + e^{z_r})].
+ * All array pointers share `where`; *loss_out may be NULL. */
+gsp_status gsp_pruner_grad(gsp_ctx *ctx, const float *params, const float *x, const uint8_t *y, int64_t rows,
+                           float pos_weight, float *grad_out, double *loss_out, int where);
+
+/* Trains the network on the GPU: Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected) over mini-batches [k*batch, (k+1)*batch) of the rows in
+ * the order given, `epochs` passes, learning rate lr, fp32 throughout.
+ * params_inout (host, 4801 values) holds the starting point and receives the
+ * result; epoch_loss (host, `epochs` values, may be NULL) the mean batch loss
+ * of each epoch, each batch's loss taken before its update.  x and y live
+ * where `where` says. */
+gsp_status gsp_pruner_train(gsp_ctx *ctx, const float *x, const uint8_t *y, int64_t rows, int64_t batch,
+                            int32_t epochs, float lr, float pos_weight, float *params_inout, double *epoch_loss,
+                            int where);
+
+/* Move traces, the network's training data.  capacity > 0 starts recording
+ * (dropping earlier rows) in later gsp_run / gsp_move_phase_ex calls;
+ * capacity <= 0 stops and frees.  A scan of vertex i in sweep s of pass p is
+ * recorded with probability `rate`: iff SplitMix64's output step applied to
+ * seed ^ (p << 56) ^ (s << 48) ^ i is below rate * 2^64.  A row is the
+ * vertex's 8 features before the scan, 1 if it moved, its id at its level
+ * and p * 256 + s.  Rows land in 16 regions of capacity/16 rows (rounded up);
+ * a full region drops its further rows. */
+gsp_status gsp_capture_traces(gsp_ctx *ctx, int64_t capacity, double rate, uint64_t seed);
+
+/* Copies up to max_rows recorded rows (in no particular order) into x
+ * [rows][8], y, vertex, meta (any may be NULL; all NULL: only counts), all
+ * at `where`.  *rows receives the rows copied (or held, when all are
+ * NULL), *seen the scans the sampling kept, dropped ones included. */
+gsp_status gsp_get_traces(gsp_ctx *ctx, float *x, uint8_t *y, int32_t *vertex, int32_t *meta, int64_t max_rows,
+                          int64_t *rows, int64_t *seen, int where);
 
 #ifdef __cplusplus
 }

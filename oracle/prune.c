@@ -368,6 +368,9 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * the usual test stops it.  Every iteration counts towards l_i and
  * max_iter except a confirming sweep that moves no vertex.
  *
+ * A vertex with an empty row is never gated, scanned or traced (it cannot
+ * move).
+ *
  * History (both modes, used by the features): at a vertex's scan, bit 0 of
  * hbits (scanned), bit 1 (moved), hfrac and hgain (gate_history) are set;
  * all start at 0 in the phase.
@@ -432,6 +435,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                 scan[i] = 0;
                 if (!unproc[i] || sub_round(i, rounds) != p) continue;
                 unproc[i] = 0;
+                if (off[i + 1] == off[i]) continue;   /* an empty row: nothing to scan, never moves */
                 orc_gate_features(off[i + 1] - off[i], K[i], sigma[memb[i]], hfrac[i], hgain[i], hbits[i], pass, li,
                                   xf + i * NF);
                 if (mode == GATED && mlp_row(pd, xf + i * NF, 1, NULL, NULL) < theta_logit) {

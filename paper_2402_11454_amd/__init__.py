@@ -25,7 +25,9 @@ HOST, DEVICE = 0, 1
 SPLIT_PASS, SPLIT_LAST, SPLIT_NONE = 0, 1, 2
 MAX_PASSES_STATS = 64
 KERNEL_CLASSES = ("move_small", "move_wave", "move_block", "move_hub", "move_hub_finish", "move_apply", "frontier",
-                  "split", "aggregate")
+                  "split", "aggregate", "gate")
+PRUNE_PLAIN, PRUNE_LEARNED = 0, 1
+GATE_PARAMS = 4801  # (8*64 + 64) + (64*64 + 64) + (64 + 1)
 
 _STATUS = {GSP_EINVAL: "GSP_EINVAL", GSP_ENOMEM: "GSP_ENOMEM", GSP_EHIP: "GSP_EHIP",
            GSP_ESTATE: "GSP_ESTATE", GSP_EGRAPH: "GSP_EGRAPH"}
@@ -41,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("max_iterations", ctypes.c_int32), ("sub_rounds", ctypes.c_int32),
                 ("tolerance_drop", ctypes.c_double), ("aggregation_tolerance", ctypes.c_double),
                 ("split_mode", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("mem_limit_bytes", ctypes.c_uint64)]
+                ("mem_limit_bytes", ctypes.c_uint64), ("prune_mode", ctypes.c_int32),
+                ("prune_threshold", ctypes.c_float)]
 
 
 class KernelStat(ctypes.Structure):
@@ -56,7 +59,9 @@ class Stats(ctypes.Structure):
                 ("moves", ctypes.c_int64), ("scanned_entries", ctypes.c_int64),
                 ("ms_move", ctypes.c_double), ("ms_split", ctypes.c_double), ("ms_aggregate", ctypes.c_double),
                 ("ms_other", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("kernels", KernelStat * len(KERNEL_CLASSES))]
+                ("kernels", KernelStat * len(KERNEL_CLASSES)),
+                ("scanned_vertices", ctypes.c_int64), ("pruned", ctypes.c_int64),
+                ("confirm_sweeps", ctypes.c_int32), ("sweeps", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         k = self.passes
@@ -64,6 +69,8 @@ class Stats(ctypes.Structure):
                     communities=list(self.communities[:k]), moves=self.moves,
                     scanned_entries=self.scanned_entries, ms_move=self.ms_move, ms_split=self.ms_split,
                     ms_aggregate=self.ms_aggregate, ms_other=self.ms_other, ms_total=self.ms_total,
+                    scanned_vertices=self.scanned_vertices, pruned=self.pruned,
+                    confirm_sweeps=self.confirm_sweeps, sweeps=self.sweeps,
                     kernels={name: dict(launches=s.launches, ms=s.ms, bytes=s.bytes, items=s.items)
                              for name, s in zip(KERNEL_CLASSES, self.kernels)})
 
@@ -98,6 +105,14 @@ def lib():
         "gsp_move_phase": [vp, vp, ctypes.c_int, dbl, i32, i32, ctypes.POINTER(i32), vp, vp],
         "gsp_step_split": [vp, vp, ctypes.c_int, vp],
         "gsp_step_aggregate": [vp, vp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp],
+        "gsp_move_phase_ex": [vp, vp, ctypes.c_int, dbl, i32, ctypes.POINTER(Options), ctypes.POINTER(i32), vp, vp,
+                              vp],
+        "gsp_pruner_set": [vp, vp, i64, ctypes.c_int],
+        "gsp_gate_logits": [vp, vp, i64, vp, ctypes.c_int],
+        "gsp_pruner_grad": [vp, vp, vp, vp, i64, ctypes.c_float, vp, ctypes.POINTER(dbl), ctypes.c_int],
+        "gsp_pruner_train": [vp, vp, vp, i64, i64, i32, ctypes.c_float, ctypes.c_float, vp, vp, ctypes.c_int],
+        "gsp_capture_traces": [vp, i64, dbl, ctypes.c_uint64],
+        "gsp_get_traces": [vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -283,6 +298,84 @@ class Context:
         self._check(lib().gsp_move_phase(self._h, m.ctypes.data, HOST, tolerance, max_iterations, sub_rounds,
                                          ctypes.byref(li), dq.ctypes.data, mv.ctypes.data), "gsp_move_phase")
         return m, li.value, dq[:li.value], mv[:li.value]
+
+    def move_phase_ex(self, membership=None, tolerance: float = 0.0, pass_index: int = 0,
+                      options: Optional[Options] = None, **kw):
+        """The local-moving phase with the run's options (learned gate
+        included); returns (membership, l_i, dq per counted iteration,
+        movers per counted iteration, counters dict)."""
+        opt = options if options is not None else default_options(**kw)
+        m = np.arange(self.n, dtype=np.int32) if membership is None else np.array(membership, dtype=np.int32)
+        li = ctypes.c_int32()
+        mi = max(opt.max_iterations, 1)
+        dq = np.zeros(mi, dtype=np.float64)
+        mv = np.zeros(mi, dtype=np.int64)
+        c4 = np.zeros(4, dtype=np.int64)
+        self._check(lib().gsp_move_phase_ex(self._h, m.ctypes.data, HOST, tolerance, pass_index, ctypes.byref(opt),
+                                            ctypes.byref(li), dq.ctypes.data, mv.ctypes.data, c4.ctypes.data),
+                    "gsp_move_phase_ex")
+        cnt = dict(scanned_vertices=int(c4[0]), scanned_entries=int(c4[1]), pruned=int(c4[2]),
+                   confirm_sweeps=int(c4[3]))
+        return m, li.value, dq[:li.value], mv[:li.value], cnt
+
+    # ---------------------------------------------------- learned pruning
+    def pruner_set(self, params) -> None:
+        """Sets the gate's network (4801 fp32 parameters, see gsp.h)."""
+        p, w, keep = _ptr(params, np.float32)
+        self._check(lib().gsp_pruner_set(self._h, p, GATE_PARAMS, w), "gsp_pruner_set")
+
+    def gate_logits(self, x) -> np.ndarray:
+        """Logits of feature rows x[rows][8] by the inference kernel."""
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+        out = np.empty(x.shape[0], dtype=np.float32)
+        self._check(lib().gsp_gate_logits(self._h, x.ctypes.data, x.shape[0], out.ctypes.data, HOST),
+                    "gsp_gate_logits")
+        return out
+
+    def pruner_grad(self, params, x, y, pos_weight: float = 1.0):
+        """(loss, gradient[4801]) of the mean pos-weighted BCE, by the fp32
+        training kernels."""
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 8)
+        y = np.ascontiguousarray(y, dtype=np.uint8)
+        g = np.empty(GATE_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(lib().gsp_pruner_grad(self._h, p.ctypes.data, x.ctypes.data, y.ctypes.data, x.shape[0],
+                                          pos_weight, g.ctypes.data, ctypes.byref(loss), HOST), "gsp_pruner_grad")
+        return loss.value, g
+
+    def pruner_train(self, params, x, y, batch: int, epochs: int, lr: float, pos_weight: float = 1.0):
+        """Adam training on the GPU; returns (params fp32, per-epoch loss).
+        x, y may be numpy arrays or device tensors (float32 [rows, 8], uint8)."""
+        p = np.array(params, dtype=np.float32)
+        px, wx, kx = _ptr(x, np.float32)
+        py, wy, ky = _ptr(y, np.uint8)
+        if wx != wy:
+            raise ValueError("x and y must live in the same place")
+        rows = int(y.shape[0])
+        el = np.zeros(max(epochs, 1), dtype=np.float64)
+        self._check(lib().gsp_pruner_train(self._h, px, py, rows, batch, epochs, lr, pos_weight, p.ctypes.data,
+                                           el.ctypes.data, wx), "gsp_pruner_train")
+        return p, el[:epochs]
+
+    def capture_traces(self, capacity: int, rate: float = 1.0, seed: int = 0) -> None:
+        """Starts (capacity > 0, clearing earlier rows) or stops (0) recording
+        sampled scans of later runs."""
+        self._check(lib().gsp_capture_traces(self._h, capacity, rate, seed), "gsp_capture_traces")
+
+    def traces(self, max_rows: Optional[int] = None):
+        """(x float32[rows, 8], moved uint8, vertex int32, meta int32, seen)."""
+        rows, seen = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().gsp_get_traces(self._h, None, None, None, None, 0, ctypes.byref(rows),
+                                         ctypes.byref(seen), HOST), "gsp_get_traces")
+        k = rows.value if max_rows is None else min(rows.value, max_rows)
+        x = np.empty((k, 8), dtype=np.float32)
+        y = np.empty(k, dtype=np.uint8)
+        v = np.empty(k, dtype=np.int32)
+        m = np.empty(k, dtype=np.int32)
+        self._check(lib().gsp_get_traces(self._h, x.ctypes.data, y.ctypes.data, v.ctypes.data, m.ctypes.data, k,
+                                         ctypes.byref(rows), ctypes.byref(seen), HOST), "gsp_get_traces")
+        return x[:rows.value], y[:rows.value], v[:rows.value], m[:rows.value], seen.value
 
     def step_split(self, membership):
         p, w, keep = _ptr(membership, np.int32)

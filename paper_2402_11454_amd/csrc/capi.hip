@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <string>
 #include <type_traits>
+#include <cmath>
 #include <vector>
 
 #include "../../include/gsp.h"
@@ -111,6 +112,22 @@ struct gsp_ctx {
     int64_t *i64_h = nullptr;         // pinned host scalars
     double *f64_h = nullptr;
 
+    // learned gate: per-vertex history of the current pass and the gated
+    // sweeps' candidate lists (graph-sized, allocated on first use)
+    float *hfrac = nullptr, *hgain = nullptr;
+    uint8_t *hbits = nullptr;
+    int32_t *cand = nullptr;
+    // the network in its inference formats (kept across loads)
+    bool have_net = false;
+    uint16_t *net_w1 = nullptr, *net_w2 = nullptr;
+    float *net_f = nullptr;          // b1[64] b2[64] w3[64]
+    float net_b3 = 0.0f;
+    std::vector<float> net_params;   // fp32 parameters as given
+    // trace capture (kept across loads and runs until stopped)
+    bool tracing = false;
+    TraceArgs trace;
+    std::vector<void *> persist;     // device buffers that survive loads
+
     // last result
     bool have_result = false;
     bool have_q = false;
@@ -126,6 +143,23 @@ struct gsp_ctx {
     gsp_status fail_hip(hipError_t e, const char *what) {
         err = std::string(what) + ": " + hipGetErrorString(e);
         return e == hipErrorOutOfMemory ? GSP_ENOMEM : GSP_EHIP;
+    }
+    template <class T>
+    T *palloc(size_t count, hipError_t *e) {   // survives loads, freed by gsp_destroy
+        void *p = nullptr;
+        *e = hipMalloc(&p, (count ? count : 1) * sizeof(T));
+        if (*e != hipSuccess) return nullptr;
+        persist.push_back(p);
+        return (T *)p;
+    }
+    void pfree(void *p) {
+        if (!p) return;
+        for (size_t k = 0; k < persist.size(); k++)
+            if (persist[k] == p) {
+                (void)hipFree(p);
+                persist.erase(persist.begin() + (long)k);
+                return;
+            }
     }
     template <class T>
     T *dalloc(size_t count, hipError_t *e) {
@@ -155,6 +189,9 @@ struct gsp_ctx {
         gap_col = nullptr;
         gap_w = nullptr;
         ctr = nullptr;
+        hfrac = hgain = nullptr;
+        hbits = nullptr;
+        cand = nullptr;
         loaded = false;
         have_result = false;
         have_q = false;
@@ -275,17 +312,80 @@ double move_bytes(int cls, const CounterStripe &h, int wt) {
     }
 }
 
+// What one local-moving phase runs and what it reports.
+struct PhaseCfg {
+    double tau = 0.0;
+    int max_iter = 20;
+    bool timing_k = false;
+    bool gated = false;            // learned gate in front of the scan
+    float theta_logit = 0.0f;      // scan iff logit >= theta_logit
+    int pass = 0;                  // pass index (a feature, and trace rows)
+    double *dq_out = nullptr;      // per counted iteration (max_iter entries)
+    int64_t *moved_out = nullptr;
+    double *kernel_bytes = nullptr;
+    // out
+    int32_t li = 0;
+    int64_t scanned_vertices = 0, scanned_entries = 0, pruned = 0, confirm_sweeps = 0, sweeps = 0;
+};
+
+gsp_status ensure_gate_state(gsp_ctx *ctx) {
+    if (ctx->hbits) return GSP_OK;
+    hipError_t e = hipSuccess;
+    ctx->hfrac = ctx->dalloc<float>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
+    ctx->hgain = ctx->dalloc<float>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
+    ctx->hbits = ctx->dalloc<uint8_t>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
+    ctx->cand = ctx->dalloc<int32_t>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate candidates)");
+    return GSP_OK;
+}
+
+GateNet net_of(const gsp_ctx *ctx) {
+    GateNet net;
+    net.w1 = ctx->net_w1;
+    net.w2 = ctx->net_w2;
+    net.b1 = ctx->net_f;
+    net.b2 = ctx->net_f + kGateHidden;
+    net.w3 = ctx->net_f + 2 * kGateHidden;
+    net.b3 = ctx->net_b3;
+    return net;
+}
+
 // The local-moving phase on level g (Algorithm "louvainMove" in ordered
-// sub-rounds).  cm/sig/csize hold the starting state; returns l_i.
-gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkLists &wl, double tau,
-                      int max_iter, bool timing_k, double *dq_out, int64_t *moved_out, int32_t *li_out,
-                      double *kernel_bytes) {
+// sub-rounds).  cm/sig/csize hold the starting state.
+//
+// With the learned gate the phase starts with gated sweeps (compaction ->
+// gate -> scan of the kept vertices).  When a gated sweep's gain total is
+// <= tau, a confirming sweep follows with every vertex unprocessed and no
+// gate; if its total is <= tau too the phase ends, otherwise plain sweeps
+// continue until the usual test stops them.  Every sweep counts towards
+// l_i and max_iter except a confirming sweep that moves nothing.  With the
+// gate or trace capture on, each scan records the vertex's history (reset
+// at the start of the phase) for the features.
+gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkLists &wl, PhaseCfg &cfg) {
     hipStream_t s = ctx->stream;
     int P = wl.rounds;
+    const bool hist = cfg.gated || ctx->tracing;
+    if (hist) {
+        gsp_status st = ensure_gate_state(ctx);
+        if (st != GSP_OK) return st;
+        launch_fill_f32(ctx->hfrac, 0.0f, g.n, s);
+        launch_fill_f32(ctx->hgain, 0.0f, g.n, s);
+        launch_fill_u8(ctx->hbits, 0, g.n, s);
+    }
+    const GateNet net = cfg.gated ? net_of(ctx) : GateNet();
+    enum { GATED, CONFIRM, PLAIN } mode = cfg.gated ? GATED : PLAIN;
     launch_fill_u8(ctx->flag, 1, g.n, s);
     int li = 0;
-    for (int it = 0; it < max_iter; it++) {
-        IterCounters *ctr = ctx->ctr + (it & 1);
+    for (int sweep = 0; li < cfg.max_iter; sweep++) {
+        cfg.sweeps++;
+        if (mode == CONFIRM) {
+            launch_fill_u8(ctx->flag, 1, g.n, s);
+            cfg.confirm_sweeps++;
+        }
+        IterCounters *ctr = ctx->ctr + (sweep & 1);
         HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(IterCounters), s));
         for (int p = 0; p < P; p++) {
             MoveArgs a;
@@ -319,31 +419,48 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.part_g = ctx->sc.part_g;
             a.part_kid = ctx->sc.part_kid;
             a.part_c = ctx->sc.part_c;
+            if (hist) {
+                a.hfrac = ctx->hfrac;
+                a.hgain = ctx->hgain;
+                a.hbits = ctx->hbits;
+                a.pass = cfg.pass;
+                a.sweep = sweep;
+                a.iter = li;
+                if (ctx->tracing) a.tr = ctx->trace;
+            }
+            if (mode == GATED) a.cand = ctx->cand;
             if (cap == 0) continue;
+            const bool tk = cfg.timing_k;
             int t;
-            t = timing_k ? ctx->timer.begin(100 + GSP_K_FRONTIER) : -1;
+            t = tk ? ctx->timer.begin(100 + GSP_K_FRONTIER) : -1;
             launch_move_compact(a, wl, s);
             ctx->timer.end(t);
-            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL) : -1;
+            if (mode == GATED) {
+                t = tk ? ctx->timer.begin(100 + GSP_K_GATE) : -1;
+                launch_gate(a, net, cfg.theta_logit, cap, s);
+                ctx->timer.end(t);
+            }
+            t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL) : -1;
             launch_move_small(a, wl, s);
             ctx->timer.end(t);
-            t = timing_k && a.qcap[BIN_WAVE] ? ctx->timer.begin(100 + GSP_K_MOVE_WAVE) : -1;
+            t = tk && a.qcap[BIN_WAVE] ? ctx->timer.begin(100 + GSP_K_MOVE_WAVE) : -1;
             launch_move_wave(a, s);
             ctx->timer.end(t);
-            t = timing_k && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK) : -1;
+            t = tk && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK) : -1;
             launch_move_block(a, s);
             ctx->timer.end(t);
-            t = timing_k && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
+            t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
             launch_move_hub_scan(a, s);
             ctx->timer.end(t);
-            t = timing_k && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
+            t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
             launch_move_hub_finish(a, s);
             ctx->timer.end(t);
-            t = timing_k ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
+            t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
             launch_move_apply(a, cap, s);
             ctx->timer.end(t);
-            if (timing_k) {
+            if (tk) {
                 ctx->kernel_launches[GSP_K_FRONTIER]++;
+                ctx->kernel_launches[GSP_K_GATE] += mode == GATED;
                 ctx->kernel_launches[GSP_K_MOVE_SMALL] += cap - a.qcap[BIN_WAVE] - a.qcap[BIN_BLOCK] -
                                                           a.qcap[BIN_HUB] > 0;
                 ctx->kernel_launches[GSP_K_MOVE_WAVE] += a.qcap[BIN_WAVE] > 0;
@@ -363,6 +480,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             h.gain += x.gain;   // exact on integer weights, in any order
             h.moved += x.moved;
             h.ginserts += x.ginserts;
+            h.pruned += x.pruned;
             for (int c = 0; c < kMoveClasses; c++) {
                 h.verts[c] += x.verts[c];
                 h.scanned[c] += x.scanned[c];
@@ -370,18 +488,39 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             }
         }
         double dq = ctx->M2 > 0.0 ? (2.0 * h.gain) / (ctx->M2 * ctx->M2) : 0.0;
-        if (dq_out) dq_out[it] = dq;
-        if (moved_out) moved_out[it] = (int64_t)h.moved;
         ctx->stats.moves += (int64_t)h.moved;
+        cfg.pruned += (int64_t)h.pruned;
         for (int c = 0; c < kMoveClasses; c++) {
-            ctx->stats.scanned_entries += (int64_t)h.scanned[c];
+            cfg.scanned_entries += (int64_t)h.scanned[c];
+            cfg.scanned_vertices += (int64_t)h.verts[c];   // hubs: counted once, by the finish kernel
             ctx->stats.kernels[GSP_K_MOVE_SMALL + c].items += (int64_t)h.scanned[c];
-            if (kernel_bytes) kernel_bytes[GSP_K_MOVE_SMALL + c] += move_bytes(c, h, g.wt);
+            if (cfg.kernel_bytes) cfg.kernel_bytes[GSP_K_MOVE_SMALL + c] += move_bytes(c, h, g.wt);
         }
-        li = it + 1;
-        if (dq <= tau) break;
+        if (mode == GATED && cfg.kernel_bytes) {
+            // per candidate: vertex id, degree, K, membership, Sigma, history
+            // (9 B) in; queue slot out
+            int64_t nc = 0;
+            for (int p = 0; p < P; p++)
+                for (int b = 0; b < kNumBins; b++) nc += ctx->ctr_h->ccnt[p][b];
+            cfg.kernel_bytes[GSP_K_GATE] += 41.0 * (double)nc;
+            ctx->stats.kernels[GSP_K_GATE].items += nc;
+        }
+        const bool counted = mode != CONFIRM || h.moved > 0;
+        if (counted) {
+            if (cfg.dq_out) cfg.dq_out[li] = dq;
+            if (cfg.moved_out) cfg.moved_out[li] = (int64_t)h.moved;
+            li++;
+        }
+        if (dq <= cfg.tau) {
+            if (mode == GATED) {
+                mode = CONFIRM;
+                continue;
+            }
+            break;
+        }
+        if (mode == CONFIRM) mode = PLAIN;
     }
-    *li_out = li;
+    cfg.li = li;
     return GSP_OK;
 }
 
@@ -559,6 +698,27 @@ gsp_status modularity_of(gsp_ctx *ctx, const int32_t *m, double *out) {
 // C ABI
 // =====================================================================
 
+gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
+    if (opt.max_iterations < 0 || opt.max_iterations > 100 || !valid_rounds(opt.sub_rounds) ||
+        !(opt.tolerance_drop > 0.0) || opt.split_mode < 0 || opt.split_mode > 2)
+        return ctx->fail(GSP_EINVAL,
+                         "bad options (max_iterations in [0, 100]; sub_rounds a power of two in [1, 64])");
+    if (opt.prune_mode != GSP_PRUNE_PLAIN && opt.prune_mode != GSP_PRUNE_LEARNED)
+        return ctx->fail(GSP_EINVAL, "bad prune_mode");
+    if (opt.prune_mode == GSP_PRUNE_LEARNED) {
+        if (!(opt.prune_threshold > 0.0f && opt.prune_threshold < 1.0f))
+            return ctx->fail(GSP_EINVAL, "prune_threshold must lie in (0, 1)");
+        if (!ctx->have_net) return ctx->fail(GSP_ESTATE, "learned pruning needs a network (gsp_pruner_set)");
+    }
+    return GSP_OK;
+}
+
+// The gate compares the logit z with logit(theta) (p >= theta <=> z >= logit(theta)).
+float theta_logit(float theta) {
+    double t = (double)theta;
+    return (float)std::log(t / (1.0 - t));
+}
+
 extern "C" {
 
 gsp_status gsp_default_options(gsp_options *out) {
@@ -571,6 +731,8 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->split_mode = GSP_SPLIT_PASS;
     out->timing = 0;
     out->mem_limit_bytes = 0;
+    out->prune_mode = GSP_PRUNE_PLAIN;
+    out->prune_threshold = 0.5f;
     return GSP_OK;
 }
 
@@ -608,6 +770,8 @@ gsp_status gsp_destroy(gsp_ctx *ctx) {
     if (!ctx) return GSP_EINVAL;
     (void)hipSetDevice(ctx->device);
     ctx->free_graph();
+    for (void *p : ctx->persist) (void)hipFree(p);
+    ctx->persist.clear();
     if (ctx->ctr_h) (void)hipHostFree(ctx->ctr_h);
     if (ctx->i64_h) (void)hipHostFree(ctx->i64_h);
     if (ctx->f64_h) (void)hipHostFree(ctx->f64_h);
@@ -653,9 +817,8 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
     else
         gsp_default_options(&opt);
     if (!(tolerance >= 0.0) || max_passes < 0) return ctx->fail(GSP_EINVAL, "tolerance < 0 or max_passes < 0");
-    if (opt.max_iterations < 0 || !valid_rounds(opt.sub_rounds) || !(opt.tolerance_drop > 0.0) ||
-        opt.split_mode < 0 || opt.split_mode > 2)
-        return ctx->fail(GSP_EINVAL, "bad options (sub_rounds must be a power of two in [1, 64])");
+    gsp_status st0 = check_options(ctx, opt);
+    if (st0 != GSP_OK) return st0;
     ctx->mem_limit = opt.mem_limit_bytes;
     if (ctx->mem_limit && ctx->mem_used > ctx->mem_limit)
         return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
@@ -688,9 +851,22 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
         launch_fill_i32(ctx->csize, 1, g.n, s);
         ctx->timer.end(t);
         t = tphase ? ctx->timer.begin(PH_MOVE) : -1;
-        int32_t li = 0;
-        st = move_phase(ctx, g, K, wl, tau, opt.max_iterations, tk, nullptr, nullptr, &li, kbytes);
+        PhaseCfg pc;
+        pc.tau = tau;
+        pc.max_iter = opt.max_iterations;
+        pc.timing_k = tk;
+        pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
+        pc.theta_logit = theta_logit(opt.prune_threshold);
+        pc.pass = lp;
+        pc.kernel_bytes = kbytes;
+        st = move_phase(ctx, g, K, wl, pc);
         if (st != GSP_OK) return st;
+        const int32_t li = pc.li;
+        ctx->stats.scanned_entries += pc.scanned_entries;
+        ctx->stats.scanned_vertices += pc.scanned_vertices;
+        ctx->stats.pruned += pc.pruned;
+        ctx->stats.confirm_sweeps += (int32_t)pc.confirm_sweeps;
+        ctx->stats.sweeps += (int32_t)pc.sweeps;
         ctx->timer.end(t);
         const int32_t *labels = ctx->cm;
         if (opt.split_mode == GSP_SPLIT_PASS) {
@@ -918,14 +1094,21 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     return GSP_OK;
 }
 
-gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance,
-                          int32_t max_iterations, int32_t sub_rounds, int32_t *iterations, double *dq_iter,
-                          int64_t *moved_iter) {
+gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance, int32_t pass_index,
+                             const gsp_options *optp, int32_t *iterations, double *dq_iter, int64_t *moved_iter,
+                             int64_t *counters) {
     if (!ctx || !iterations) return GSP_EINVAL;
     (void)hipSetDevice(ctx->device);
-    if (max_iterations < 0 || !valid_rounds(sub_rounds) || !(tolerance >= 0.0))
-        return ctx->fail(GSP_EINVAL, "bad max_iterations, sub_rounds or tolerance");
-    gsp_status st = take_membership(ctx, membership_inout, where);
+    gsp_options opt;
+    if (optp)
+        opt = *optp;
+    else
+        gsp_default_options(&opt);
+    gsp_status st = check_options(ctx, opt);
+    if (st != GSP_OK) return st;
+    if (!(tolerance >= 0.0) || pass_index < 0 || pass_index > 255)
+        return ctx->fail(GSP_EINVAL, "bad tolerance or pass_index");
+    st = take_membership(ctx, membership_inout, where);
     if (st != GSP_OK) return st;
     hipStream_t s = ctx->stream;
     Level g = level0(ctx);
@@ -933,20 +1116,315 @@ gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, do
     launch_fill_i32(ctx->csize, 0, g.n, s);
     launch_community_totals(ctx->K0, ctx->cm, g.n, ctx->sig, ctx->csize, s);
     WorkLists wl = make_lists(ctx);
-    HIP_TRY(build_work_lists(g, sub_rounds, wl, ctx->sc, s));
-    std::vector<double> dq(max_iterations > 0 ? max_iterations : 1);
-    std::vector<int64_t> mv(max_iterations > 0 ? max_iterations : 1);
-    int32_t li = 0;
-    st = move_phase(ctx, g, ctx->K0, wl, tolerance, max_iterations, false, dq.data(), mv.data(), &li, nullptr);
+    HIP_TRY(build_work_lists(g, opt.sub_rounds, wl, ctx->sc, s));
+    int mi = opt.max_iterations;
+    std::vector<double> dq(mi > 0 ? mi : 1);
+    std::vector<int64_t> mv(mi > 0 ? mi : 1);
+    PhaseCfg pc;
+    pc.tau = tolerance;
+    pc.max_iter = mi;
+    pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
+    pc.theta_logit = theta_logit(opt.prune_threshold);
+    pc.pass = pass_index;
+    pc.dq_out = dq.data();
+    pc.moved_out = mv.data();
+    st = move_phase(ctx, g, ctx->K0, wl, pc);
     if (st != GSP_OK) return st;
     st = copy_out(ctx, membership_inout, ctx->cm, g.n, where);
     if (st != GSP_OK) return st;
     HIP_TRY(hipStreamSynchronize(s));
-    *iterations = li;
-    for (int k = 0; k < li; k++) {
+    *iterations = pc.li;
+    for (int k = 0; k < pc.li; k++) {
         if (dq_iter) dq_iter[k] = dq[k];
         if (moved_iter) moved_iter[k] = mv[k];
     }
+    if (counters) {
+        counters[0] = pc.scanned_vertices;
+        counters[1] = pc.scanned_entries;
+        counters[2] = pc.pruned;
+        counters[3] = pc.confirm_sweeps;
+    }
+    return GSP_OK;
+}
+
+gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance,
+                          int32_t max_iterations, int32_t sub_rounds, int32_t *iterations, double *dq_iter,
+                          int64_t *moved_iter) {
+    if (!ctx) return GSP_EINVAL;
+    gsp_options opt;
+    gsp_default_options(&opt);
+    opt.max_iterations = max_iterations;
+    opt.sub_rounds = sub_rounds;
+    return gsp_move_phase_ex(ctx, membership_inout, where, tolerance, 0, &opt, iterations, dq_iter, moved_iter,
+                             nullptr);
+}
+
+// ---- learned pruning gate ----
+
+gsp_status gsp_pruner_set(gsp_ctx *ctx, const float *params, int64_t count, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!params || count != kGateParams) return ctx->fail(GSP_EINVAL, "params must hold 4801 values");
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    std::vector<float> p(kGateParams);
+    if (where == GSP_DEVICE) {
+        HIP_TRY(hipMemcpyAsync(p.data(), params, kGateParams * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    } else {
+        memcpy(p.data(), params, kGateParams * sizeof(float));
+    }
+    for (float v : p)
+        if (!std::isfinite(v)) return ctx->fail(GSP_EINVAL, "params must be finite");
+    hipError_t e = hipSuccess;
+    if (!ctx->net_w1) {
+        ctx->net_w1 = ctx->palloc<uint16_t>(kGateHidden * kGateFeatures, &e);
+        if (e == hipSuccess) ctx->net_w2 = ctx->palloc<uint16_t>(kGateHidden * kGateHidden, &e);
+        if (e == hipSuccess) ctx->net_f = ctx->palloc<float>(3 * kGateHidden, &e);
+        if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(network)");
+    }
+    std::vector<uint16_t> w1(kGateHidden * kGateFeatures), w2(kGateHidden * kGateHidden);
+    std::vector<float> f(3 * kGateHidden);
+    for (int k = 0; k < kGateHidden * kGateFeatures; k++) w1[k] = bf16_bits(p[kPW1 + k]);
+    for (int k = 0; k < kGateHidden * kGateHidden; k++) w2[k] = bf16_bits(p[kPW2 + k]);
+    for (int k = 0; k < kGateHidden; k++) {
+        f[k] = p[kPB1 + k];
+        f[kGateHidden + k] = p[kPB2 + k];
+        f[2 * kGateHidden + k] = bf16_round(p[kPW3 + k]);
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->net_w1, w1.data(), w1.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->net_w2, w2.data(), w2.size() * 2, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->net_f, f.data(), f.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->net_b3 = p[kPB3];
+    ctx->net_params = p;
+    ctx->have_net = true;
+    return GSP_OK;
+}
+
+gsp_status gsp_gate_logits(gsp_ctx *ctx, const float *x, int64_t rows, float *logits, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->have_net) return ctx->fail(GSP_ESTATE, "no network (gsp_pruner_set)");
+    if (rows < 0 || (rows > 0 && (!x || !logits))) return ctx->fail(GSP_EINVAL, "bad rows or NULL buffer");
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    if (rows == 0) return GSP_OK;
+    hipStream_t s = ctx->stream;
+    const float *dx = x;
+    float *dz = logits;
+    float *tx = nullptr, *tz = nullptr;
+    if (where == GSP_HOST) {
+        HIP_TRY(hipMalloc(&tx, rows * kGateFeatures * sizeof(float)));
+        hipError_t e = hipMalloc(&tz, rows * sizeof(float));
+        if (e != hipSuccess) {
+            (void)hipFree(tx);
+            return ctx->fail_hip(e, "hipMalloc(logits)");
+        }
+        (void)hipMemcpyAsync(tx, x, rows * kGateFeatures * sizeof(float), hipMemcpyHostToDevice, s);
+        dx = tx;
+        dz = tz;
+    }
+    launch_gate_eval(net_of(ctx), dx, rows, dz, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && where == GSP_HOST)
+        e = hipMemcpyAsync(logits, dz, rows * sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (tx) (void)hipFree(tx);
+    if (tz) (void)hipFree(tz);
+    if (e != hipSuccess) return ctx->fail_hip(e, "gate logits");
+    return GSP_OK;
+}
+
+namespace {
+
+// Device copies of training rows (or the caller's device pointers).
+struct TrainRows {
+    const float *x = nullptr;
+    const uint8_t *y = nullptr;
+    float *tx = nullptr;
+    uint8_t *ty = nullptr;
+    ~TrainRows() {
+        if (tx) (void)hipFree(tx);
+        if (ty) (void)hipFree(ty);
+    }
+};
+
+gsp_status take_rows(gsp_ctx *ctx, const float *x, const uint8_t *y, int64_t rows, int where, TrainRows &r) {
+    if (rows <= 0 || !x || !y) return ctx->fail(GSP_EINVAL, "rows must be > 0 with x and y given");
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    if (where == GSP_DEVICE) {
+        r.x = x;
+        r.y = y;
+        return GSP_OK;
+    }
+    HIP_TRY(hipMalloc(&r.tx, rows * kGateFeatures * sizeof(float)));
+    HIP_TRY(hipMalloc(&r.ty, rows));
+    HIP_TRY(hipMemcpyAsync(r.tx, x, rows * kGateFeatures * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(r.ty, y, rows, hipMemcpyHostToDevice, ctx->stream));
+    r.x = r.tx;
+    r.y = r.ty;
+    return GSP_OK;
+}
+
+// Device scratch of one training call, freed on return.
+struct TrainScratch {
+    float *params = nullptr, *m = nullptr, *v = nullptr, *part = nullptr, *grad = nullptr;
+    double *ploss = nullptr, *loss = nullptr;
+    ~TrainScratch() {
+        for (void *p : {(void *)params, (void *)m, (void *)v, (void *)part, (void *)grad, (void *)ploss, (void *)loss})
+            if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+gsp_status gsp_pruner_grad(gsp_ctx *ctx, const float *params, const float *x, const uint8_t *y, int64_t rows,
+                           float pos_weight, float *grad_out, double *loss_out, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!params || !grad_out) return ctx->fail(GSP_EINVAL, "params and grad_out are required");
+    if (!(pos_weight > 0.0f) || !std::isfinite(pos_weight)) return ctx->fail(GSP_EINVAL, "pos_weight must be > 0");
+    TrainRows r;
+    gsp_status st = take_rows(ctx, x, y, rows, where, r);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    int nb = (int)((rows + kMlpRowsPerBlock - 1) / kMlpRowsPerBlock);
+    TrainScratch t;
+    HIP_TRY(hipMalloc(&t.params, kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.grad, kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.part, (size_t)nb * kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.ploss, (size_t)nb * sizeof(double)));
+    HIP_TRY(hipMalloc(&t.loss, sizeof(double)));
+    HIP_TRY(hipMemcpyAsync(t.params, params, kGateParams * sizeof(float),
+                           where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    launch_fill_f64(t.loss, 0.0, 1, s);
+    launch_mlp_grad(t.params, r.x, r.y, rows, pos_weight, 1.0f / (float)rows, t.part, t.ploss, s);
+    launch_mlp_reduce(t.part, t.ploss, nb, nullptr, nullptr, nullptr, false, 0.0f, 1.0f, 1.0f, t.grad, t.loss, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(grad_out, t.grad, kGateParams * sizeof(float),
+                           where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    double L = 0.0;
+    HIP_TRY(hipMemcpyAsync(&L, t.loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_out) *loss_out = L;
+    return GSP_OK;
+}
+
+gsp_status gsp_pruner_train(gsp_ctx *ctx, const float *x, const uint8_t *y, int64_t rows, int64_t batch,
+                            int32_t epochs, float lr, float pos_weight, float *params_inout, double *epoch_loss,
+                            int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!params_inout) return ctx->fail(GSP_EINVAL, "params_inout is NULL");
+    if (batch <= 0 || batch > (1 << 20) || epochs < 0 || !(lr > 0.0f) || !(pos_weight > 0.0f))
+        return ctx->fail(GSP_EINVAL, "bad batch (1..2^20), epochs, lr or pos_weight");
+    TrainRows r;
+    gsp_status st = take_rows(ctx, x, y, rows, where, r);
+    if (st != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    int64_t bmax = std::min<int64_t>(batch, rows);
+    int nbmax = (int)((bmax + kMlpRowsPerBlock - 1) / kMlpRowsPerBlock);
+    TrainScratch t;
+    HIP_TRY(hipMalloc(&t.params, kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.m, kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.v, kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.part, (size_t)nbmax * kGateParams * sizeof(float)));
+    HIP_TRY(hipMalloc(&t.ploss, (size_t)nbmax * sizeof(double)));
+    HIP_TRY(hipMalloc(&t.loss, (size_t)(epochs > 0 ? epochs : 1) * sizeof(double)));
+    HIP_TRY(hipMemcpyAsync(t.params, params_inout, kGateParams * sizeof(float), hipMemcpyHostToDevice, s));
+    launch_fill_f32(t.m, 0.0f, kGateParams, s);
+    launch_fill_f32(t.v, 0.0f, kGateParams, s);
+    launch_fill_f64(t.loss, 0.0, epochs > 0 ? epochs : 1, s);
+    int64_t step = 0, nbatches = (rows + batch - 1) / batch;
+    for (int ep = 0; ep < epochs; ep++) {
+        for (int64_t r0 = 0; r0 < rows; r0 += batch) {
+            int64_t len = std::min<int64_t>(batch, rows - r0);
+            int nb = (int)((len + kMlpRowsPerBlock - 1) / kMlpRowsPerBlock);
+            step++;
+            float c1 = (float)(1.0 - std::pow(0.9, (double)step));
+            float c2 = (float)(1.0 - std::pow(0.999, (double)step));
+            launch_mlp_grad(t.params, r.x + r0 * kGateFeatures, r.y + r0, len, pos_weight, 1.0f / (float)len, t.part,
+                            t.ploss, s);
+            launch_mlp_reduce(t.part, t.ploss, nb, t.params, t.m, t.v, true, lr, c1, c2, nullptr, t.loss + ep, s);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(params_inout, t.params, kGateParams * sizeof(float), hipMemcpyDeviceToHost, s));
+    std::vector<double> el(epochs > 0 ? epochs : 1);
+    HIP_TRY(hipMemcpyAsync(el.data(), t.loss, el.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (epoch_loss)
+        for (int ep = 0; ep < epochs; ep++) epoch_loss[ep] = el[ep] / (double)nbatches;
+    return GSP_OK;
+}
+
+// ---- move traces ----
+
+gsp_status gsp_capture_traces(gsp_ctx *ctx, int64_t capacity, double rate, uint64_t seed) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (void *p : {(void *)ctx->trace.x, (void *)ctx->trace.y, (void *)ctx->trace.v, (void *)ctx->trace.meta,
+                    (void *)ctx->trace.cnt})
+        ctx->pfree(p);
+    ctx->trace = TraceArgs();
+    ctx->tracing = false;
+    if (capacity <= 0) return GSP_OK;
+    if (!(rate > 0.0) || !(rate <= 1.0)) return ctx->fail(GSP_EINVAL, "rate must lie in (0, 1]");
+    int64_t scap = (capacity + kStripes - 1) / kStripes;
+    int64_t rows = scap * kStripes;
+    hipError_t e = hipSuccess;
+    TraceArgs t;
+    t.x = ctx->palloc<float>(rows * kGateFeatures, &e);
+    if (e == hipSuccess) t.y = ctx->palloc<uint8_t>(rows, &e);
+    if (e == hipSuccess) t.v = ctx->palloc<int32_t>(rows, &e);
+    if (e == hipSuccess) t.meta = ctx->palloc<int32_t>(rows, &e);
+    if (e == hipSuccess) t.cnt = ctx->palloc<unsigned long long>(kStripes, &e);
+    ctx->trace = t;   // owned through ctx->persist either way
+    if (e != hipSuccess) {
+        gsp_capture_traces(ctx, 0, 1.0, 0);
+        return ctx->fail_hip(e, "hipMalloc(traces)");
+    }
+    HIP_TRY(hipMemsetAsync(t.cnt, 0, kStripes * sizeof(unsigned long long), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->trace.scap = scap;
+    ctx->trace.seed = seed;
+    ctx->trace.thr = rate >= 1.0 ? ~0ull : (uint64_t)std::ldexp(rate, 64);
+    ctx->tracing = true;
+    return GSP_OK;
+}
+
+gsp_status gsp_get_traces(gsp_ctx *ctx, float *x, uint8_t *y, int32_t *vertex, int32_t *meta, int64_t max_rows,
+                          int64_t *rows, int64_t *seen, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->tracing) return ctx->fail(GSP_ESTATE, "trace capture is off (gsp_capture_traces)");
+    if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
+    hipStream_t s = ctx->stream;
+    unsigned long long cnt[kStripes];
+    HIP_TRY(hipMemcpyAsync(cnt, ctx->trace.cnt, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t tot = 0, kept = 0;
+    for (int q = 0; q < kStripes; q++) {
+        tot += (int64_t)cnt[q];
+        kept += std::min<int64_t>((int64_t)cnt[q], ctx->trace.scap);
+    }
+    if (seen) *seen = tot;
+    int64_t out = 0;
+    hipMemcpyKind kind = where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int q = 0; q < kStripes && out < max_rows; q++) {
+        int64_t k = std::min<int64_t>(std::min<int64_t>((int64_t)cnt[q], ctx->trace.scap), max_rows - out);
+        if (k <= 0) continue;
+        int64_t src = q * ctx->trace.scap;
+        if (x)
+            HIP_TRY(hipMemcpyAsync(x + out * kGateFeatures, ctx->trace.x + src * kGateFeatures,
+                                   k * kGateFeatures * sizeof(float), kind, s));
+        if (y) HIP_TRY(hipMemcpyAsync(y + out, ctx->trace.y + src, k, kind, s));
+        if (vertex) HIP_TRY(hipMemcpyAsync(vertex + out, ctx->trace.v + src, k * sizeof(int32_t), kind, s));
+        if (meta) HIP_TRY(hipMemcpyAsync(meta + out, ctx->trace.meta + src, k * sizeof(int32_t), kind, s));
+        out += k;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (rows) *rows = (x || y || vertex || meta) ? out : kept;
     return GSP_OK;
 }
 

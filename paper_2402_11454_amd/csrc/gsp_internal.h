@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "device_common.h"
+#include "gate_common.h"
 
 namespace gsp {
 
@@ -62,12 +63,28 @@ struct alignas(128) CounterStripe {
     unsigned long long scanned[kMoveClasses];  // CSR entries scanned
     unsigned long long keys[kMoveClasses];     // distinct neighbour communities scored
     unsigned long long ginserts;               // hub scan: (chunk, community) inserts into global tables
+    unsigned long long pruned;                 // vertices the learned gate kept from the scan
 };
 
 // Counters written by the kernels of one local-moving iteration.
 struct IterCounters {
     int qcnt[kMaxRounds][kNumBins];   // queued vertices per sub-round and bin
+    int ccnt[kMaxRounds][kNumBins];   // gated sweeps: candidates before the gate
     CounterStripe st[kStripes];
+};
+
+// Trace capture: rows (features before the scan, moved, vertex, pass * 256 +
+// sweep) of the sampled scans, in kStripes regions of scap rows; a block
+// appends to region blockIdx % kStripes (cnt[r] counts the region's rows,
+// also those beyond scap, which are dropped).
+struct TraceArgs {
+    float *x = nullptr;                 // [kStripes * scap][8]
+    uint8_t *y = nullptr;
+    int32_t *v = nullptr;
+    int32_t *meta = nullptr;
+    unsigned long long *cnt = nullptr;  // [kStripes]
+    int64_t scap = 0;
+    uint64_t seed = 0, thr = 0;
 };
 
 // Arguments of the local-moving kernels for one sub-round.
@@ -97,12 +114,19 @@ struct MoveArgs {
     const int32_t *hub_ch0;  // per hub vertex: its first chunk id
     double *part_g, *part_kid;  // per chunk: best score and K_{i->d} share
     int *part_c;             // per chunk: best community
+    // learned gate and traces (hbits == nullptr: neither)
+    float *hfrac = nullptr, *hgain = nullptr;   // history of the last scan in this pass
+    uint8_t *hbits = nullptr;
+    int32_t *cand = nullptr;                    // gated sweep: candidates (the gate fills `queue`)
+    int pass = 0, sweep = 0, iter = 0;          // feature and trace context
+    TraceArgs tr;                               // tr.x == nullptr: no capture
 };
 
 // ---- k_util.hip ----
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 void launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
 void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
@@ -146,6 +170,26 @@ void launch_move_block(const MoveArgs &a, hipStream_t s);
 void launch_move_hub_scan(const MoveArgs &a, hipStream_t s);
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s);
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
+
+// ---- k_gate.hip ----
+// Gated sweep: the candidates of every bin (cand, ctr->ccnt[round]) go
+// through the network; those with logit >= theta_logit are queued (queue,
+// ctr->qcnt[round]), the others counted as pruned (a pruned hub's hub_act
+// is cleared).
+void launch_gate(const MoveArgs &a, const GateNet &net, float theta_logit, int64_t cap, hipStream_t s);
+// Logits of feature rows x[rows][8] (fp32, rounded to bf16 here) by the
+// inference kernel.
+void launch_gate_eval(const GateNet &net, const float *x, int64_t rows, float *logit, hipStream_t s);
+// Training (fp32): per-block partial gradients of the mean pos-weighted BCE
+// over rows [0, rows) of (x, y) with the batch size `inv_batch` = 1/B, then
+// their sum in block order; with `adam` the sum is applied as one Adam step
+// (c1 = 1 - beta1^t, c2 = 1 - beta2^t), else written to grad.  The batch
+// loss (sum of the rows' losses * inv_batch) is added to *loss.
+constexpr int kMlpRowsPerBlock = 64;
+void launch_mlp_grad(const float *params, const float *x, const uint8_t *y, int64_t rows, float pos_weight,
+                     float inv_batch, float *part, double *part_loss, hipStream_t s);
+void launch_mlp_reduce(const float *part, const double *part_loss, int nblocks, float *params, float *m, float *v,
+                       bool adam, float lr, float c1, float c2, float *grad, double *loss, hipStream_t s);
 
 // ---- k_split.hip ----
 // labels[i] = smallest vertex of i's component among same-community edges.

@@ -76,6 +76,41 @@ __device__ __forceinline__ bool decide(const MoveArgs &a, int i, int d, double k
     return true;
 }
 
+// History of a scan (for the learned gate's features) and, if sampled, a
+// trace row with the features the vertex had before this scan and whether
+// it moves.  Called by one lane per decided vertex; no-op unless enabled.
+__device__ __noinline__ void record_scan(const MoveArgs &a, int i, int d, int di, double ki, double kid, double bg,
+                                        int bc, bool mv) {
+    uint8_t hb = a.hbits[i];
+    float hf = a.hfrac[i], hg = a.hgain[i];
+    if (a.tr.x && trace_keep(a.tr.seed, a.pass, a.sweep, i, a.tr.thr)) {
+        uint16_t x[kGateFeatures];
+        gate_features(di, ki, a.sig[d], hf, hg, hb, a.pass, a.iter, x);
+        int r = blockIdx.x % kStripes;
+        unsigned long long slot = atomicAdd(&a.tr.cnt[r], 1ull);
+        if ((int64_t)slot < a.tr.scap) {
+            int64_t row = r * a.tr.scap + (int64_t)slot;
+#pragma unroll
+            for (int f = 0; f < kGateFeatures; f++) a.tr.x[row * kGateFeatures + f] = bf16_value(x[f]);
+            a.tr.y[row] = mv ? 1 : 0;
+            a.tr.v[row] = i;
+            a.tr.meta[row] = a.pass * 256 + a.sweep;
+        }
+    }
+    float nf = 0.0f, ng = 0.0f;
+    if (ki > 0.0) {
+        nf = (float)(kid / ki);
+        double gstay = a.M2 * kid - ki * (a.sig[d] - ki);
+        double r = bc != kIntMax ? (bg - gstay) / (a.M2 * ki) : -1.0;
+        if (r > 1.0) r = 1.0;
+        if (r < -1.0) r = -1.0;
+        ng = (float)r;
+    }
+    a.hfrac[i] = nf;
+    a.hgain[i] = ng;
+    a.hbits[i] = kHistScanned | (mv ? kHistMoved : 0);
+}
+
 // Folds the entry (key, v) of a scan table into (bg, bc, kid).
 __device__ __forceinline__ void fold_key(const MoveArgs &a, int key, double v, int d, double ki, double &bg, int &bc,
                                          double &kid) {
@@ -112,8 +147,9 @@ __device__ __forceinline__ void take_slot(const MoveArgs &a, int *keys, double *
 
 // ---------------------------------------------------------------- compact
 
-// Unprocessed vertices of the sub-round's buckets -> per-bin queues; each
-// block reserves its queue slots with one atomic per bin.
+// Unprocessed vertices of the sub-round's buckets -> per-bin queues (or,
+// in a gated sweep, per-bin candidate lists for the gate); each block
+// reserves its slots with one atomic per bin.
 __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32_t *bl) {
     __shared__ int lcnt[kNumBins];
     __shared__ int lbase[kNumBins];
@@ -122,7 +158,9 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
 #pragma unroll
     for (int b = 0; b < kNumBins; b++) pre[b + 1] = pre[b] + a.qcap[b];
     int64_t total = pre[kNumBins];
-    int *qcnt = a.ctr->qcnt[a.round];
+    const bool gated = a.cand != nullptr;   // the gate fills the queue from the candidates
+    int *qcnt = gated ? a.ctr->ccnt[a.round] : a.ctr->qcnt[a.round];
+    int32_t *qout = gated ? a.cand : a.queue;
     for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < total; t0 += (int64_t)gridDim.x * kBlock) {
         if (threadIdx.x < kNumBins) lcnt[threadIdx.x] = 0;
         __syncthreads();
@@ -143,7 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
         if (threadIdx.x < kNumBins && lcnt[threadIdx.x] > 0)
             lbase[threadIdx.x] = atomicAdd(&qcnt[threadIdx.x], lcnt[threadIdx.x]);
         __syncthreads();
-        if (rank >= 0) a.queue[a.qbase[b] + lbase[b] + rank] = i;
+        if (rank >= 0) qout[a.qbase[b] + lbase[b] + rank] = i;
         __syncthreads();
     }
 }
@@ -218,6 +256,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     if (lead) {
         acc.verts++;
         acc.scanned += (unsigned long long)di;
+        if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
         a.dec[i] = mv ? bc : d;
         if (mv) {
             acc.gain += gain;
@@ -325,6 +364,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         if (lane == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
+            if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;
@@ -377,6 +417,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         if (tid == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
+            if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;
@@ -542,6 +583,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         if (lane == 0) {
             acc.verts++;
             a.hub_act[i] = mv ? 2 : 0;   // 2: its neighbours are marked chunk by chunk in apply
+            if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;

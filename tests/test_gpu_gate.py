@@ -1,0 +1,318 @@
+"""The learned pruning gate on the GPU against the oracle, through the C ABI.
+
+Bars:
+  * inference kernel: logits bit-identical to the oracle's fp64 value when
+    every intermediate is exact in fp32/bf16 (pins the matrix-core operand and
+    result layouts); otherwise within 2e-2 absolute of the oracle's
+    bf16-format logits, with the scan/prune decision identical wherever the
+    oracle's logit is farther than 2e-2 from the threshold;
+  * training kernels: fp32 gradient within 1e-4 relative (2-norm) of the
+    oracle's fp64 gradient, loss within 1e-5 relative; one Adam step within
+    lr * 1e-3 of the oracle's step wherever |g| > 1e-3 max|g|;
+  * traces: rows bit-identical to the oracle's (compared as sorted sets: the
+    GPU appends them in atomic order);
+  * gated phase and gated run: memberships, per-iteration gain totals and
+    counters identical to the oracle's, on inputs where no gate decision lies
+    within 1e-3 of the threshold (checked on the oracle by moving the
+    threshold by +-1e-3 and finding the same result);
+  * the trained network, on held-out graphs: fewer scanned entries than the
+    plain method, modularity within 0.005 of it, no disconnected community.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gsp_inputs as gi
+import oracle
+import paper_2402_11454_amd as gsp
+
+pytestmark = pytest.mark.gpu
+
+P = gsp.GATE_PARAMS
+W1, B1, W2, B2, W3, B3 = 0, 512, 576, 4672, 4736, 4800
+
+
+def _gpu_count():
+    try:
+        import torch
+        return torch.cuda.device_count()
+    except Exception:
+        return 0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if _gpu_count() == 0:
+        pytest.skip("no GPU")
+    c = gsp.Context(0)
+    yield c
+    c.close()
+
+
+def _params(seed, b3=0.0):
+    u = gi.uniform(seed, P)
+    p = (u * 2.0 - 1.0).astype(np.float32)
+    p[W1:B1] *= math.sqrt(6 / 8)
+    p[B1:W2] *= 0.1
+    p[W2:B2] *= math.sqrt(6 / 64)
+    p[B2:W3] *= 0.1
+    p[W3:B3] *= math.sqrt(6 / 64)
+    p[B3] = b3
+    return p
+
+
+def _rows(seed, rows, pos=0.4):
+    x = gi.uniform(seed, rows * 8).reshape(rows, 8).astype(np.float32)
+    y = (gi.uniform(seed + 1, rows) < pos).astype(np.uint8)
+    return x, y
+
+
+def _load(ctx, g):
+    ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+
+
+# ------------------------------------------------------------- inference
+
+def test_logits_exact_when_every_step_is_exact(ctx):
+    """Weights and biases on a 1/8 grid, integer features: every product and
+    sum is exact in fp32 and every first-layer output exact in bf16, so the
+    matrix-core result must equal the oracle's fp64 logit bit for bit (a
+    wrong operand or result layout cannot pass this)."""
+    u = gi.uniform(21, P)
+    p = np.zeros(P, np.float32)
+    p[W1:B1] = np.round((u[W1:B1] - 0.5) * 8) / 8             # [-1/2, 1/2]
+    p[B1:W2] = np.round((u[B1:W2] - 0.5) * 8) / 8
+    p[W2:B2] = np.round((u[W2:B2] - 0.5) * 4) / 8             # [-1/4, 1/4]
+    p[B2:W3] = np.round((u[B2:W3] - 0.5) * 8) / 8
+    p[W3:B3] = np.round((u[W3:B3] - 0.5) * 8) / 8
+    p[B3] = 0.375
+    x = np.floor(gi.uniform(22, 1000 * 8) * 3).reshape(1000, 8).astype(np.float32)   # {0, 1, 2}
+    ctx.pruner_set(p)
+    got = ctx.gate_logits(x)
+    want = oracle.mlp_logits(p, x, bf16_formats=True)
+    assert np.array_equal(got.astype(np.float64), want)
+    assert np.unique(want).size > 100
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 65, 1000, 40_000])
+def test_logits_close_to_oracle(ctx, rows):
+    p = _params(23)
+    x = gi.uniform(24 + rows, rows * 8).reshape(rows, 8).astype(np.float32) * 2 - 0.5
+    ctx.pruner_set(p)
+    got = ctx.gate_logits(x).astype(np.float64)
+    want = oracle.mlp_logits(p, x, bf16_formats=True)
+    assert np.max(np.abs(got - want)) <= 2e-2
+    theta = float(np.median(want))
+    far = np.abs(want - theta) > 2e-2
+    assert np.array_equal((got >= theta)[far], (want >= theta)[far])
+
+
+# -------------------------------------------------------------- training
+
+@pytest.mark.parametrize("rows", [1, 64, 100, 4097])
+def test_gradient_matches_oracle(ctx, rows):
+    x, y = _rows(30 + rows, rows)
+    p = _params(31)
+    for pw in (1.0, 2.3):
+        loss, g = ctx.pruner_grad(p, x, y, pw)
+        l64, g64 = oracle.mlp_loss_grad(p, x, y, pw)
+        assert math.isclose(loss, l64, rel_tol=1e-5)
+        assert np.linalg.norm(g.astype(np.float64) - g64) <= 1e-4 * np.linalg.norm(g64)
+
+
+def test_adam_step_matches_oracle(ctx):
+    x, y = _rows(40, 512)
+    p = _params(41)
+    lr = 1e-3
+    p_gpu, el_gpu = ctx.pruner_train(p, x, y, batch=512, epochs=1, lr=lr, pos_weight=1.5)
+    p_orc, el_orc = oracle.mlp_train_adam(p, x, y, batch=512, epochs=1, lr=lr, pos_weight=1.5)
+    _, g = oracle.mlp_loss_grad(p, x, y, 1.5)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert big.sum() > 1000
+    step_gpu = p_gpu.astype(np.float64) - p
+    step_orc = p_orc.astype(np.float64) - p
+    assert np.max(np.abs(step_gpu - step_orc)[big]) <= lr * 1e-3 + 2e-7
+    assert np.max(np.abs(step_gpu - step_orc)) <= 2 * lr + 1e-6
+    assert math.isclose(el_gpu[0], el_orc[0], rel_tol=1e-5)
+
+
+def test_training_follows_the_oracle(ctx):
+    """A few epochs of mini-batch Adam: the loss curves agree and fall."""
+    x = gi.uniform(42, 6000 * 8).reshape(6000, 8).astype(np.float32)
+    y = (x[:, 0] + x[:, 1] > 1.0).astype(np.uint8)
+    p0 = _params(43)
+    pg, elg = ctx.pruner_train(p0, x, y, batch=200, epochs=4, lr=3e-3)
+    po, elo = oracle.mlp_train_adam(p0, x, y, batch=200, epochs=4, lr=3e-3)
+    assert elg[-1] < 0.5 * elg[0]
+    assert np.allclose(elg, elo, rtol=5e-3)
+    zg = oracle.mlp_logits(pg, x)
+    assert np.mean((zg >= 0) == (y == 1)) > 0.95
+
+
+# ---------------------------------------------------------------- traces
+
+@pytest.mark.parametrize("make", [lambda: gi.planted_sbm_10k(), lambda: gi.dcsbm_small(8000, 5),
+                                  lambda: gi.rmat_small(13, 6)])
+def test_traces_match_oracle(ctx, make):
+    g = make()
+    _load(ctx, g)
+    ctx.capture_traces(400_000, rate=0.5, seed=77)
+    m, li, dq, mv, cnt = ctx.move_phase_ex(None, tolerance=1e-2, pass_index=2)
+    x, y, v, meta, seen = ctx.traces()
+    ctx.capture_traces(0)
+    tr = oracle.Trace(400_000, seed=77, rate=0.5)
+    mo, lio, dqo, mvo, cnto = oracle.move_sync_gated(g, None, tau=1e-2, trace=tr, pass_index=2)
+    assert np.array_equal(m, mo) and li == lio and cnt["scanned_vertices"] == cnto["scanned_vertices"]
+    xo, yo, vo, metao = tr.arrays()
+    assert seen == tr.seen and x.shape[0] == tr.rows > 1000
+    k1 = np.lexsort((v, meta))
+    k2 = np.lexsort((vo, metao))
+    assert np.array_equal(v[k1], vo[k2]) and np.array_equal(meta[k1], metao[k2])
+    assert np.array_equal(y[k1], yo[k2])
+    assert np.array_equal(x[k1].view(np.uint32), xo[k2].view(np.uint32))
+
+
+def test_trace_capacity_and_errors(ctx):
+    g = gi.planted_sbm_10k()
+    _load(ctx, g)
+    with pytest.raises(gsp.GspError):
+        ctx.traces()                                 # not capturing
+    ctx.capture_traces(160, rate=1.0)                # 16 regions of 10 rows
+    ctx.move_phase_ex(None, tolerance=1e-2)
+    x, y, v, meta, seen = ctx.traces()
+    assert x.shape[0] == 160 and seen > 1000
+    ctx.capture_traces(0)
+    with pytest.raises(gsp.GspError):
+        ctx.capture_traces(100, rate=0.0)
+
+
+# ------------------------------------------------------------ gated phase
+
+def _stable_theta(g, p, thetas, run):
+    """First threshold for which the oracle's result does not change when
+    the logit threshold moves by +-1e-3 (so no gate decision is near it)."""
+    for th in thetas:
+        tl = math.log(th / (1 - th))
+        a, b, c = run(tl), run(tl - 1e-3), run(tl + 1e-3)
+        if a == b == c:
+            return th
+    pytest.skip("no threshold with a margin on this input")
+
+
+@pytest.mark.parametrize("make,b3", [(lambda: gi.planted_sbm_10k(), 0.3), (lambda: gi.dcsbm_small(12000, 7), 0.3),
+                                     (lambda: gi.rmat_small(14, 8), -0.2)])
+def test_gated_phase_matches_oracle(ctx, make, b3):
+    g = make()
+    p = _params(50, b3)
+
+    def run(tl):
+        m, li, dq, mv, cnt = oracle.move_sync_gated(g, p, tau=1e-2, pass_index=1, theta_logit=tl)
+        return (m.tobytes(), li, dq.tobytes(), tuple(cnt.values()))
+
+    th = _stable_theta(g, p, [0.5, 0.55, 0.45, 0.6, 0.4], run)
+    mo, lio, dqo, mvo, cnto = oracle.move_sync_gated(g, p, theta=th, tau=1e-2, pass_index=1)
+    _load(ctx, g)
+    ctx.pruner_set(p)
+    m, li, dq, mv, cnt = ctx.move_phase_ex(None, tolerance=1e-2, pass_index=1, prune_mode=gsp.PRUNE_LEARNED,
+                                           prune_threshold=th)
+    assert cnto["pruned"] > 0 and cnto["confirm_sweeps"] >= 1
+    assert np.array_equal(m, mo) and li == lio and np.array_equal(mv, mvo)
+    assert np.array_equal(dq, dqo) if g.weights is None else np.allclose(dq, dqo, rtol=1e-12, atol=0)
+    assert cnt == cnto
+
+
+def test_gate_rejecting_everything_equals_plain(ctx):
+    g = gi.rmat_small(13, 9)
+    _load(ctx, g)
+    p = np.zeros(P, np.float32)
+    p[B3] = -30.0
+    ctx.pruner_set(p)
+    m, li, dq, mv, cnt = ctx.move_phase_ex(None, tolerance=1e-2, prune_mode=gsp.PRUNE_LEARNED)
+    m2, li2, dq2, mv2 = ctx.move_phase(None, tolerance=1e-2)
+    assert np.array_equal(m, m2) and li == li2 + 1 and np.array_equal(dq[1:], dq2)
+    assert cnt["pruned"] == int(np.count_nonzero(np.diff(g.offsets))) and cnt["confirm_sweeps"] == 1
+
+
+def test_gated_run_matches_oracle(ctx):
+    g = gi.dcsbm_small(8000, 9)
+    p = _params(61, 0.5)
+
+    def run(tl):
+        r = oracle.louvain(g, sync=True, prune_params=p, theta_logit=tl)
+        return (r.membership.tobytes(), tuple(r.iterations), tuple(r.counters.values()))
+
+    th = _stable_theta(g, p, [0.5, 0.55, 0.45, 0.6, 0.4], run)
+    ref = oracle.louvain(g, sync=True, prune_params=p, theta=th)
+    _load(ctx, g)
+    ctx.pruner_set(p)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th)
+    assert np.array_equal(res.membership, ref.membership)
+    assert res.stats["iterations"] == ref.iterations
+    assert res.stats["pruned"] == ref.counters["pruned"]
+    assert res.stats["scanned_entries"] == ref.counters["scanned_entries"]
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+
+
+def test_learned_mode_errors(ctx):
+    g = gi.planted_sbm_10k()
+    c = gsp.Context(0)
+    try:
+        _load(c, g)
+        with pytest.raises(gsp.GspError):
+            c.run(prune_mode=gsp.PRUNE_LEARNED)          # no network set
+        with pytest.raises(gsp.GspError):
+            c.pruner_set(np.zeros(10, np.float32))        # wrong size
+        bad = np.zeros(P, np.float32)
+        bad[7] = np.nan
+        with pytest.raises(gsp.GspError):
+            c.pruner_set(bad)
+        c.pruner_set(np.zeros(P, np.float32))
+        with pytest.raises(gsp.GspError):
+            c.run(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=1.0)
+        with pytest.raises(gsp.GspError):
+            c.run(prune_mode=7)
+    finally:
+        c.close()
+
+
+# ------------------------------------------------------- the network's gain
+
+def test_trained_network_gains_over_plain(ctx):
+    """Traces of plain runs on four training graphs -> GPU training -> the
+    gated method on two held-out graphs of the same law: fewer CSR entries
+    scanned than the plain method, modularity within 0.005 of it, no
+    internally-disconnected community."""
+    xs, ys = [], []
+    for seed in range(4):
+        g = gi.dcsbm_small(30_000, seed)
+        _load(ctx, g)
+        ctx.capture_traces(2_000_000, rate=0.5, seed=seed)
+        ctx.run(1e-2, 10)
+        x, y, v, meta, seen = ctx.traces()
+        xs.append(x)
+        ys.append(y)
+    ctx.capture_traces(0)
+    x = np.concatenate(xs)
+    y = np.concatenate(ys)
+    order = np.argsort(gi.uniform(99, y.shape[0]))
+    x, y = x[order], y[order]
+    pw = float((1 - y.mean()) / y.mean())
+    p0 = _params(70)
+    p0[B1:W2] = 0.0
+    p0[B2:W3] = 0.0
+    p, el = ctx.pruner_train(p0, x, y, batch=512, epochs=4, lr=2e-3, pos_weight=pw)
+    assert el[-1] < el[0]
+    ctx.pruner_set(p)
+    gains = []
+    for seed in (1000, 1001):
+        g = gi.dcsbm_small(30_000, seed)
+        _load(ctx, g)
+        plain = ctx.louvain(1e-2, 10)
+        learned = ctx.louvain(1e-2, 10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
+        assert learned.stats["pruned"] > 0
+        assert abs(learned.modularity - plain.modularity) <= 0.005
+        assert ctx.count_disconnected(learned.membership) == 0
+        gains.append(plain.stats["scanned_entries"] / learned.stats["scanned_entries"])
+    assert min(gains) > 1.1, gains
