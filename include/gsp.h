@@ -235,8 +235,10 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
  *   x3 = min(pass, 8) / 8;  x4 = min(l, 20) / 20 with l the iterations
  *        counted so far in the pass;
  *   x5 = K_i / Sigma_{C_i} (0 if either is 0);
- *   x6 = 1 if it moved at its last scan; x7 = 1 if it was scanned before
- *        in this pass;
+ *   x6 = 0 if not scanned yet in this pass, 1/2 if it stayed at its last
+ *        scan, 1 if it moved;
+ *   x7 = min(D_i / K_i, 1) with D_i the weight of the entries (i, j) whose
+ *        j moved since i's last scan (or since the pass began);
  * each computed in fp64 and rounded to fp32, then to bf16 (round to nearest
  * even).  The vertex is scanned iff z >= log(theta / (1 - theta)), theta =
  * prune_threshold; otherwise it keeps its community.  Inference uses bf16

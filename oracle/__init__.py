@@ -78,7 +78,8 @@ def _load():
         "orc_louvain": (i32, [i64, vp, vp, vp, ctypes.POINTER(_Options), vp, ctypes.POINTER(_Stats)]),
         "orc_bf16": (ctypes.c_float, [ctypes.c_float]),
         "orc_plog2": (dbl, [dbl]),
-        "orc_gate_features": (None, [i64, dbl, dbl, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, i32, i32, vp]),
+        "orc_gate_features": (None, [i64, dbl, dbl, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, dbl, i32, i32,
+                                     vp]),
         "orc_mlp_logits": (None, [vp, vp, i64, i32, vp]),
         "orc_mlp_loss_grad": (dbl, [vp, vp, vp, i64, dbl, vp]),
         "orc_mlp_loss_grad_f64": (dbl, [vp, vp, vp, i64, dbl, vp]),
@@ -280,10 +281,10 @@ def plog2(x: float) -> float:
     return float(_load().orc_plog2(float(x)))
 
 
-def gate_features(deg, ki, sig_d, hfrac, hgain, hbits, pass_index, iteration) -> np.ndarray:
+def gate_features(deg, ki, sig_d, hfrac, hgain, hbits, dmoved, pass_index, iteration) -> np.ndarray:
     x = np.empty(8, dtype=np.float32)
     _load().orc_gate_features(int(deg), float(ki), float(sig_d), float(hfrac), float(hgain), int(hbits),
-                              int(pass_index), int(iteration), _p(x))
+                              float(dmoved), int(pass_index), int(iteration), _p(x))
     return x
 
 

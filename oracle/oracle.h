@@ -100,8 +100,8 @@ float orc_bf16(float x);
 double orc_plog2(double x);
 
 /* The gate's 8 features of a vertex (see prune.c), bf16 values as fp32. */
-void orc_gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain, uint8_t hbits, int32_t pass,
-                       int32_t iter, float *x);
+void orc_gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain, uint8_t hbits, double dmoved,
+                       int32_t pass, int32_t iter, float *x);
 
 /* Logits of rows x[rows][8]; bf16 = 1 emulates the inference formats. */
 void orc_mlp_logits(const float *params, const float *x, int64_t rows, int32_t bf16, double *out);

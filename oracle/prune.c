@@ -69,19 +69,22 @@ static float feat(double v) { return orc_bf16((float)v); }
  *   x3 = min(pass, 8) / 8            pass index
  *   x4 = min(l, 20) / 20             counted iterations so far in the pass
  *   x5 = K_i / Sigma_d               i's share of its community's weight
- *   x6 = moved at the last scan (0/1)
- *   x7 = scanned before in this pass (0/1)
+ *   x6 = 0 never scanned in this pass, 1/2 stayed at its last scan, 1 moved
+ *   x7 = min(D_i / K_i, 1)           D_i = weight of the entries (i, j) whose
+ *                                    j moved since i's last scan (or since
+ *                                    the pass began)
  * Each value is computed in fp64, then rounded to fp32 and to bf16. */
-void orc_gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain, uint8_t hbits, int32_t pass,
-                       int32_t iter, float *x) {
+void orc_gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain, uint8_t hbits, double dmoved,
+                       int32_t pass, int32_t iter, float *x) {
     x[0] = feat(orc_plog2(1.0 + (double)deg) / 16.0);
     x[1] = feat((double)hfrac);
     x[2] = feat((double)hgain);
     x[3] = feat((double)(pass < 8 ? pass : 8) / 8.0);
     x[4] = feat((double)(iter < 20 ? iter : 20) / 20.0);
     x[5] = feat(ki > 0.0 && sig_d > 0.0 ? ki / sig_d : 0.0);
-    x[6] = feat((double)((hbits >> 1) & 1u));
-    x[7] = feat((double)(hbits & 1u));
+    x[6] = feat((hbits & 1u) ? ((hbits & 2u) ? 1.0 : 0.5) : 0.0);
+    double r = ki > 0.0 ? dmoved / ki : 0.0;
+    x[7] = feat(r < 1.0 ? r : 1.0);
 }
 
 /* History written at a scan: K_{i->d} / K_i and the normalised gain
@@ -372,8 +375,10 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * move).
  *
  * History (both modes, used by the features): at a vertex's scan, bit 0 of
- * hbits (scanned), bit 1 (moved), hfrac and hgain (gate_history) are set;
- * all start at 0 in the phase.
+ * hbits (scanned), bit 1 (moved), hfrac and hgain (gate_history) are set
+ * and D_i is cleared; when a sub-round's moves are applied, every entry
+ * (i, j), j != i, of a mover i adds w_ij to D_j.  All start at 0 in the
+ * phase.
  *
  * Traces (trace != NULL): every scan kept by orc_trace_keep(seed, pass,
  * sweep, i) appends (features before the scan, moved) to the trace; sweep
@@ -403,14 +408,15 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
     float *hfrac = (float *)calloc(N, sizeof(float));
     float *hgain = (float *)calloc(N, sizeof(float));
     uint8_t *hbits = (uint8_t *)calloc(N, 1);
+    double *dmv = (double *)calloc(N, sizeof(double));
     float *xf = (float *)malloc(N * NF * sizeof(float));
     double *acc = (double *)calloc(N, sizeof(double));   /* K_{i->c} accumulator, dense */
     uint8_t *seen = (uint8_t *)calloc(N, 1);
     int32_t *keys = (int32_t *)malloc(N * sizeof(int32_t));
-    if (!sigma || !csize || !unproc || !scan || !dec || !gain || !hfrac || !hgain || !hbits || !xf || !acc || !seen ||
-        !keys) {
+    if (!sigma || !csize || !unproc || !scan || !dec || !gain || !hfrac || !hgain || !hbits || !dmv || !xf || !acc ||
+        !seen || !keys) {
         free(sigma); free(csize); free(unproc); free(scan); free(dec); free(gain); free(hfrac); free(hgain);
-        free(hbits); free(xf); free(acc); free(seen); free(keys);
+        free(hbits); free(dmv); free(xf); free(acc); free(seen); free(keys);
         return -1;
     }
     memset(unproc, 1, N);
@@ -436,8 +442,8 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                 if (!unproc[i] || sub_round(i, rounds) != p) continue;
                 unproc[i] = 0;
                 if (off[i + 1] == off[i]) continue;   /* an empty row: nothing to scan, never moves */
-                orc_gate_features(off[i + 1] - off[i], K[i], sigma[memb[i]], hfrac[i], hgain[i], hbits[i], pass, li,
-                                  xf + i * NF);
+                orc_gate_features(off[i + 1] - off[i], K[i], sigma[memb[i]], hfrac[i], hgain[i], hbits[i], dmv[i],
+                                  pass, li, xf + i * NF);
                 if (mode == GATED && mlp_row(pd, xf + i * NF, 1, NULL, NULL) < theta_logit) {
                     cnt[2]++;
                     continue;
@@ -475,6 +481,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                     trace_put(trace, xf + i * NF, (uint8_t)mv, i, pass, sweep);
                 gate_history(ki, kid, M2, best >= 0, g_best, g_stay, &hfrac[i], &hgain[i]);
                 hbits[i] = (uint8_t)(1u | (mv ? 2u : 0u));
+                dmv[i] = 0.0;
                 if (mv) {
                     dec[i] = best;
                     gain[i] = g_best - g_stay;
@@ -485,7 +492,10 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                 if (dec[i] == memb[i]) continue;
                 gsum += gain[i];
                 for (int64_t e = off[i]; e < off[i + 1]; e++)
-                    if (col[e] != i) unproc[col[e]] = 1;
+                    if (col[e] != i) {
+                        unproc[col[e]] = 1;
+                        dmv[col[e]] += w ? w[e] : 1.0;
+                    }
             }
             for (int64_t i = 0; i < n; i++) memb[i] = dec[i];
         }
@@ -505,6 +515,6 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
     }
     if (counters) memcpy(counters, cnt, sizeof(cnt));
     free(sigma); free(csize); free(unproc); free(scan); free(dec); free(gain); free(hfrac); free(hgain);
-    free(hbits); free(xf); free(acc); free(seen); free(keys);
+    free(hbits); free(dmv); free(xf); free(acc); free(seen); free(keys);
     return li;
 }

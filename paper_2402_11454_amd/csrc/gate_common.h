@@ -14,7 +14,10 @@
 //   x3 = min(pass, 8) / 8
 //   x4 = min(l, 20) / 20           l = counted iterations so far in the pass
 //   x5 = K_i / Sigma_d             from the sub-round's snapshot
-//   x6 = moved at its last scan, x7 = scanned before in this pass
+//   x6 = 0 if not scanned yet in this pass, 1/2 if it stayed at its last
+//        scan, 1 if it moved
+//   x7 = min(D_i / K_i, 1), D_i = weight of the entries (i, j) whose j moved
+//        since i's last scan (or since the pass began)
 // each computed in fp64, rounded to fp32, then to bf16 (round to nearest
 // even).  Every step is an IEEE operation, so the values are reproducible
 // bit for bit.
@@ -59,15 +62,16 @@ __device__ __forceinline__ double plog2_int(uint64_t x) {
 }
 
 __device__ __forceinline__ void gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain,
-                                              uint8_t hbits, int pass, int iter, uint16_t *x) {
+                                              uint8_t hbits, double dmoved, int pass, int iter, uint16_t *x) {
     x[0] = feature_bits(plog2_int((uint64_t)deg + 1) / 16.0);
     x[1] = feature_bits((double)hfrac);
     x[2] = feature_bits((double)hgain);
     x[3] = feature_bits((double)(pass < 8 ? pass : 8) / 8.0);
     x[4] = feature_bits((double)(iter < 20 ? iter : 20) / 20.0);
     x[5] = feature_bits(ki > 0.0 && sig_d > 0.0 ? ki / sig_d : 0.0);
-    x[6] = feature_bits((double)((hbits >> 1) & 1u));
-    x[7] = feature_bits((double)(hbits & 1u));
+    x[6] = feature_bits((hbits & kHistScanned) ? ((hbits & kHistMoved) ? 1.0 : 0.5) : 0.0);
+    double r = ki > 0.0 ? dmoved / ki : 0.0;
+    x[7] = feature_bits(r < 1.0 ? r : 1.0);
 }
 
 // SplitMix64's output step (Steele, Lea and Flood, OOPSLA 2014).

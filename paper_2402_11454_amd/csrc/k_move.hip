@@ -85,7 +85,7 @@ __device__ __noinline__ void record_scan(const MoveArgs &a, int i, int d, int di
     float hf = a.hfrac[i], hg = a.hgain[i];
     if (a.tr.x && trace_keep(a.tr.seed, a.pass, a.sweep, i, a.tr.thr)) {
         uint16_t x[kGateFeatures];
-        gate_features(di, ki, a.sig[d], hf, hg, hb, a.pass, a.iter, x);
+        gate_features(di, ki, a.sig[d], hf, hg, hb, a.dmoved[i], a.pass, a.iter, x);
         int r = blockIdx.x % kStripes;
         unsigned long long slot = atomicAdd(&a.tr.cnt[r], 1ull);
         if ((int64_t)slot < a.tr.scap) {
@@ -109,6 +109,7 @@ __device__ __noinline__ void record_scan(const MoveArgs &a, int i, int d, int di
     a.hfrac[i] = nf;
     a.hgain[i] = ng;
     a.hbits[i] = kHistScanned | (mv ? kHistMoved : 0);
+    a.dmoved[i] = 0.0;
 }
 
 // Folds the entry (key, v) of a scan table into (bg, bc, kid).
@@ -683,6 +684,63 @@ __global__ void __launch_bounds__(kBlock) k_community_totals(const double *K, co
     }
 }
 
+// Gate history after a sub-round's scans: every entry (i, j), j != i, of a
+// vertex i that moves in this sub-round (decided, not yet applied) adds w_ij
+// to D_j.  Blocks [0, nsm): one thread per queued vertex of the bins up to
+// 64 entries; blocks [nsm, nsm + nwv): one wavefront per queued vertex of
+// the wave and block bins; the rest: one block per chunk of a moving hub.
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_move_delta(MoveArgs a, int nsm, int nwv) {
+    const int tid = threadIdx.x;
+    const int *qc = a.ctr->qcnt[a.round];
+    if ((int)blockIdx.x < nsm) {
+        int64_t pre[kNumSmallBins + 1];
+        pre[0] = 0;
+#pragma unroll
+        for (int b = 0; b < kNumSmallBins; b++) pre[b + 1] = pre[b] + qc[b];
+        for (int64_t t = (int64_t)blockIdx.x * kBlock + tid; t < pre[kNumSmallBins]; t += (int64_t)nsm * kBlock) {
+            int b = 0;
+            while (t >= pre[b + 1]) b++;
+            int i = a.queue[a.qbase[b] + (t - pre[b])];
+            if (a.dec[i] == a.cm[i]) continue;
+            int64_t beg = a.g.off[i], end = beg + a.g.deg[i];
+            for (int64_t e = beg; e < end; e++) {
+                int j = load_col(a.g.col, e);
+                if (j != i) unsafeAtomicAdd(&a.dmoved[j], edge_weight<WT>(a.g.w, e));
+            }
+        }
+        return;
+    }
+    if ((int)blockIdx.x < nsm + nwv) {
+        const int w = tid / kWave, lane = lane_id();
+        const int64_t c5 = qc[BIN_WAVE], c6 = qc[BIN_BLOCK];
+        for (int64_t q = (int64_t)(blockIdx.x - nsm) * (kBlock / kWave) + w; q < c5 + c6;
+             q += (int64_t)nwv * (kBlock / kWave)) {
+            int i = q < c5 ? a.queue[a.qbase[BIN_WAVE] + q] : a.queue[a.qbase[BIN_BLOCK] + (q - c5)];
+            if (a.dec[i] == a.cm[i]) continue;
+            int64_t beg = a.g.off[i];
+            int di = a.g.deg[i];
+            for (int e = lane; e < di; e += kWave) {
+                int j = load_col(a.g.col, beg + e);
+                if (j != i) unsafeAtomicAdd(&a.dmoved[j], edge_weight<WT>(a.g.w, beg + e));
+            }
+        }
+        return;
+    }
+    const int nh = gridDim.x - nsm - nwv;
+    for (int64_t k = a.ch_first + (blockIdx.x - nsm - nwv); k < a.ch_first + a.ch_count; k += nh) {
+        int i = a.ch_vert[k];
+        if (a.hub_act[i] != 2) continue;
+        int64_t beg = a.ch_beg[k];
+        int64_t end = a.g.off[i] + a.g.deg[i];
+        if (end > beg + kHubChunk) end = beg + kHubChunk;
+        for (int64_t e = beg + tid; e < end; e += kBlock) {
+            int j = load_col(a.g.col, e);
+            if (j != i) unsafeAtomicAdd(&a.dmoved[j], edge_weight<WT>(a.g.w, e));
+        }
+    }
+}
+
 inline unsigned cap_grid(int64_t units, int64_t cap) {
     if (units < 1) units = 1;
     return (unsigned)(units < cap ? units : cap);
@@ -756,6 +814,22 @@ void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
     k_move_hub_part<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
     k_move_hub_final<<<cap_grid((a.qcap[BIN_HUB] + 3) / 4, 1024), kBlock, 0, s>>>(a);
+}
+
+void launch_move_delta(const MoveArgs &a, hipStream_t s) {
+    int64_t small = 0;
+    for (int b = 0; b < kNumSmallBins; b++) small += a.qcap[b];
+    int64_t large = a.qcap[BIN_WAVE] + a.qcap[BIN_BLOCK];
+    int nsm = small ? (int)cap_grid((small + kBlock - 1) / kBlock, 2048) : 0;
+    int nwv = large ? (int)cap_grid((large + 3) / 4, 2048) : 0;
+    int nh = a.qcap[BIN_HUB] ? (int)cap_grid(a.ch_count, 1024) : 0;
+    if (nsm + nwv + nh == 0) return;
+    if (a.g.wt == W_UNIT)
+        k_move_delta<W_UNIT><<<nsm + nwv + nh, kBlock, 0, s>>>(a, nsm, nwv);
+    else if (a.g.wt == W_F32)
+        k_move_delta<W_F32><<<nsm + nwv + nh, kBlock, 0, s>>>(a, nsm, nwv);
+    else
+        k_move_delta<W_F64><<<nsm + nwv + nh, kBlock, 0, s>>>(a, nsm, nwv);
 }
 
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s) {

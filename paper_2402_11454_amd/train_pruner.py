@@ -1,0 +1,120 @@
+"""Trains the learned pruning gate's network from move traces, on the GPU.
+
+Recipe (the social-network-shaped workload): plain GSP-Louvain runs on the
+degree-corrected SBM graphs of seeds 0..31 (4M vertices, power-law degrees
+and community sizes, mixing 0.3, weights in [1, 4]) record a sample of their
+scans (features before the scan, moved or not); the rows are shuffled and
+the 8-64-64-1 network is trained by the library's fp32 training kernels
+(Adam, pos-weighted binary cross-entropy with pos_weight = negatives /
+positives).  Then, on held-out seeds, the gated method is run beside the
+plain one and the result is reported.  The parameters are written as a raw
+little-endian fp32 file of 4801 values (the layout of gsp_pruner_set).
+
+    python -m paper_2402_11454_amd.train_pruner --out paper_2402_11454_amd/pruner_dcsbm.f32
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "pruner_dcsbm.f32")
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases."""
+    import paper_2402_11454_amd as gsp
+    r = np.random.default_rng(seed)
+    p = np.zeros(gsp.GATE_PARAMS, np.float32)
+    p[0:512] = r.uniform(-1, 1, 512) * math.sqrt(6 / 8)
+    p[576:4672] = r.uniform(-1, 1, 4096) * math.sqrt(6 / 64)
+    p[4736:4800] = r.uniform(-1, 1, 64) * math.sqrt(6 / 64)
+    return p
+
+
+def load_params(path: str = DEFAULT_OUT) -> np.ndarray:
+    p = np.fromfile(path, dtype="<f4")
+    if p.shape[0] != 4801:
+        raise ValueError(f"{path}: expected 4801 fp32 values, found {p.shape[0]}")
+    return p
+
+
+def collect(ctx, graphs, rate: float, cap: int, log=print):
+    xs, ys = [], []
+    for k, make in enumerate(graphs):
+        t0 = time.time()
+        g = make()
+        t1 = time.time()
+        ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+        ctx.capture_traces(cap, rate=rate, seed=1234 + k)
+        ctx.run(1e-2, 10)
+        x, y, v, meta, seen = ctx.traces()
+        ctx.capture_traces(0)
+        xs.append(x)
+        ys.append(y)
+        log(f"[train] graph {k}: {g.name} n={g.n} nnz={g.nnz} gen {t1 - t0:.1f}s, rows {x.shape[0]} "
+            f"(seen {seen}), moved {y.mean():.3f}")
+    return np.concatenate(xs), np.concatenate(ys)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--n", type=int, default=4_000_000, help="vertices per graph")
+    ap.add_argument("--train-seeds", type=int, default=32)
+    ap.add_argument("--heldout", default="1000,1001")
+    ap.add_argument("--rate", type=float, default=1.0 / 16)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--threshold", type=float, default=0.5)
+    a = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    import gsp_inputs as gi
+    import paper_2402_11454_amd as gsp
+
+    log = lambda s: print(s, flush=True)
+    ctx = gsp.Context(0)
+    if a.n == 4_000_000:
+        makes = [lambda s=s: gi.dcsbm_4m(s) for s in range(a.train_seeds)]
+    else:
+        makes = [lambda s=s: gi.dcsbm(a.n, 2.5, 5, 5000, 1.5, 20, 50_000, 0.3, s) for s in range(a.train_seeds)]
+    x, y = collect(ctx, makes, a.rate, 8_000_000, log)
+    order = np.random.default_rng(a.seed).permutation(y.shape[0])
+    x, y = np.ascontiguousarray(x[order]), np.ascontiguousarray(y[order])
+    pw = float((1.0 - y.mean()) / max(y.mean(), 1e-9))
+    log(f"[train] {y.shape[0]} rows, moved fraction {y.mean():.4f}, pos_weight {pw:.3f}")
+    t0 = time.time()
+    p, el = ctx.pruner_train(init_params(a.seed), x, y, batch=a.batch, epochs=a.epochs, lr=a.lr, pos_weight=pw)
+    log(f"[train] {a.epochs} epochs in {time.time() - t0:.2f}s, loss per epoch {np.round(el, 4).tolist()}")
+    p.astype("<f4").tofile(a.out)
+    log(f"[train] wrote {a.out}")
+    ctx.pruner_set(p)
+    for s in [int(v) for v in a.heldout.split(",") if v]:
+        g = gi.dcsbm_4m(s) if a.n == 4_000_000 else gi.dcsbm(a.n, 2.5, 5, 5000, 1.5, 20, 50_000, 0.3, s)
+        ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+        out = {}
+        for mode in (gsp.PRUNE_PLAIN, gsp.PRUNE_LEARNED):
+            ctx.run(1e-2, 10, prune_mode=mode, prune_threshold=a.threshold)   # warm-up
+            t1 = time.perf_counter()   # gsp_run returns after its work has completed
+            ctx.run(1e-2, 10, prune_mode=mode, prune_threshold=a.threshold)
+            dt = time.perf_counter() - t1
+            st = ctx.stats()
+            m = ctx.membership()
+            out[mode] = (dt, ctx.result_modularity(), ctx.count_disconnected(m), st["scanned_entries"],
+                         st["iterations"], st["pruned"])
+        (tp, qp, dp, sp, ip, _), (tl, ql, dl, sl, il, pl) = out[0], out[1]
+        log(f"[heldout] seed {s}: plain {1e3 * tp:.2f} ms Q={qp:.6f} disc={dp} scanned={sp} it={ip} | "
+            f"learned {1e3 * tl:.2f} ms Q={ql:.6f} disc={dl} scanned={sl} it={il} pruned={pl} | "
+            f"speedup {tp / tl:.3f}, scanned ratio {sp / max(sl, 1):.3f}")
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -58,15 +58,20 @@ def test_plog2_exact_at_powers_and_linear_between():
 
 
 def test_gate_features_values():
-    # deg 3 -> plog2(4) / 16 = 0.125; pass 2 -> 0.25; iteration 5 -> 0.25
-    x = oracle.gate_features(3, 6.0, 24.0, 0.5, -0.25, 3, 2, 5)
-    assert list(x) == [0.125, 0.5, -0.25, 0.25, 0.25, 0.25, 1.0, 1.0]
+    # deg 3 -> plog2(4) / 16 = 0.125; pass 2 -> 0.25; iteration 5 -> 0.25;
+    # moved at its last scan -> 1; D = 1.5 of K = 6 -> 0.25
+    x = oracle.gate_features(3, 6.0, 24.0, 0.5, -0.25, 3, 1.5, 2, 5)
+    assert list(x) == [0.125, 0.5, -0.25, 0.25, 0.25, 0.25, 1.0, 0.25]
+    # stayed at its last scan -> 1/2; D above K is capped at 1
+    x = oracle.gate_features(3, 6.0, 24.0, 0.5, -0.25, 1, 9.0, 2, 5)
+    assert x[6] == 0.5 and x[7] == 1.0
     # capped pass and iteration, isolated vertex, never scanned
-    x = oracle.gate_features(0, 0.0, 0.0, 0.0, 0.0, 0, 30, 99)
+    x = oracle.gate_features(0, 0.0, 0.0, 0.0, 0.0, 0, 0.0, 30, 99)
     assert list(x) == [0.0, 0.0, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0]
     # values are bf16: 1/3 rounds to the bf16 nearest
-    x = oracle.gate_features(0, 1.0, 3.0, 0.0, 0.0, 0, 0, 0)
-    assert x[5] == torch.tensor(1.0 / 3.0, dtype=torch.float32).to(torch.bfloat16).float().item()
+    x = oracle.gate_features(0, 3.0, 9.0, 0.0, 0.0, 0, 1.0, 0, 0)
+    third = torch.tensor(1.0 / 3.0, dtype=torch.float32).to(torch.bfloat16).float().item()
+    assert x[5] == third and x[7] == third
 
 
 # ---------------------------------------------------------------- forward
@@ -247,13 +252,15 @@ def test_traces_of_a_plain_phase():
     for s in range(li):
         assert int(y[sweeps == s].sum()) == int(mv[s])
     first = sweeps == 0
-    assert np.all(x[first][:, 7] == 0) and np.all(x[first][:, 4] == 0) and np.all(x[first][:, 3] == 0.375)
+    assert np.all(x[first][:, 6] == 0) and np.all(x[first][:, 4] == 0) and np.all(x[first][:, 3] == 0.375)
     # vertices of the first sub-round see the initial singletons: K_i / Sigma_i = 1
     sub0 = np.array([((int(i) * 0x9E3779B97F4A7C15) % 2 ** 64) >> 61 == 0 for i in v]) & first
     deg = np.diff(g.offsets)[v[sub0]]
     assert sub0.sum() > 100 and np.all(x[sub0][:, 5] == np.where(deg > 0, 1.0, 0.0))
     later = sweeps > 0
-    assert np.any(x[later][:, 7] == 1)
+    assert np.any(x[later][:, 6] == 1) and np.any(x[later][:, 6] == 0.5)
+    # D_i: a vertex re-marked in a later sweep had a neighbour move, so D_i > 0
+    assert np.all(x[later][:, 7] > 0)
     # sampling: at rate 1/4 the kept rows are those the predicate selects
     tr2 = oracle.Trace(200_000, seed=5, rate=0.25)
     oracle.move_sync_gated(g, None, tau=1e-2, trace=tr2, pass_index=3)
