@@ -238,7 +238,8 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
  *   x6 = 0 if not scanned yet in this pass, 1/2 if it stayed at its last
  *        scan, 1 if it moved;
  *   x7 = min(D_i / K_i, 1) with D_i the weight of the entries (i, j) whose
- *        j moved since i's last scan (or since the pass began);
+ *        j moved since i was last taken from the unprocessed set (scanned
+ *        or pruned), or since the pass began;
  * each computed in fp64 and rounded to fp32, then to bf16 (round to nearest
  * even).  The vertex is scanned iff z >= log(theta / (1 - theta)), theta =
  * prune_threshold; otherwise it keeps its community.  Inference uses bf16

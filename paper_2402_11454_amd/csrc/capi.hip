@@ -116,7 +116,7 @@ struct gsp_ctx {
     // sweeps' candidate lists (graph-sized, allocated on first use)
     float *hfrac = nullptr, *hgain = nullptr;
     uint8_t *hbits = nullptr;
-    double *dmoved = nullptr;
+    double *dmoved = nullptr, *dsnap = nullptr;
     int32_t *cand = nullptr;
     // the network in its inference formats (kept across loads)
     bool have_net = false;
@@ -192,7 +192,7 @@ struct gsp_ctx {
         ctr = nullptr;
         hfrac = hgain = nullptr;
         hbits = nullptr;
-        dmoved = nullptr;
+        dmoved = dsnap = nullptr;
         cand = nullptr;
         loaded = false;
         have_result = false;
@@ -341,6 +341,8 @@ gsp_status ensure_gate_state(gsp_ctx *ctx) {
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
     ctx->dmoved = ctx->dalloc<double>(ctx->n, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
+    ctx->dsnap = ctx->dalloc<double>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
     ctx->cand = ctx->dalloc<int32_t>(ctx->n, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate candidates)");
     return GSP_OK;
@@ -429,6 +431,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 a.hgain = ctx->hgain;
                 a.hbits = ctx->hbits;
                 a.dmoved = ctx->dmoved;
+                a.dsnap = ctx->dsnap;
                 a.pass = cfg.pass;
                 a.sweep = sweep;
                 a.iter = li;
@@ -461,17 +464,12 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
             launch_move_hub_finish(a, s);
             ctx->timer.end(t);
-            if (hist) {
-                t = tk ? ctx->timer.begin(100 + GSP_K_GATE) : -1;
-                launch_move_delta(a, s);
-                ctx->timer.end(t);
-            }
             t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
             launch_move_apply(a, cap, s);
             ctx->timer.end(t);
             if (tk) {
                 ctx->kernel_launches[GSP_K_FRONTIER]++;
-                ctx->kernel_launches[GSP_K_GATE] += (mode == GATED) + hist;
+                ctx->kernel_launches[GSP_K_GATE] += mode == GATED;
                 ctx->kernel_launches[GSP_K_MOVE_SMALL] += cap - a.qcap[BIN_WAVE] - a.qcap[BIN_BLOCK] -
                                                           a.qcap[BIN_HUB] > 0;
                 ctx->kernel_launches[GSP_K_MOVE_WAVE] += a.qcap[BIN_WAVE] > 0;

@@ -117,7 +117,8 @@ struct MoveArgs {
     // learned gate and traces (hbits == nullptr: neither)
     float *hfrac = nullptr, *hgain = nullptr;   // history of the last scan in this pass
     uint8_t *hbits = nullptr;
-    double *dmoved = nullptr;                   // D_i: weight of i's entries to movers since i's last scan
+    double *dmoved = nullptr;                   // D_i: weight of i's entries to movers since i left the frontier
+    double *dsnap = nullptr;                    // D_i as compaction took it (the features' value)
     int32_t *cand = nullptr;                    // gated sweep: candidates (the gate fills `queue`)
     int pass = 0, sweep = 0, iter = 0;          // feature and trace context
     TraceArgs tr;                               // tr.x == nullptr: no capture
@@ -171,9 +172,6 @@ void launch_move_block(const MoveArgs &a, hipStream_t s);
 void launch_move_hub_scan(const MoveArgs &a, hipStream_t s);
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s);
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
-// Gate history: D_j += w_ij for every entry (i, j), j != i, of the
-// sub-round's movers (after the scans, before apply).
-void launch_move_delta(const MoveArgs &a, hipStream_t s);
 
 // ---- k_gate.hip ----
 // Gated sweep: the candidates of every bin (cand, ctr->ccnt[round]) go

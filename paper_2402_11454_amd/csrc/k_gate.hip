@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_gate(MoveArgs a, GateNet net, float 
         if (valid) {
             while (t >= pre[b + 1]) b++;
             i = a.cand[a.qbase[b] + (t - pre[b])];
-            gate_features(a.g.deg[i], a.K[i], a.sig[a.cm[i]], a.hfrac[i], a.hgain[i], a.hbits[i], a.dmoved[i], a.pass,
+            gate_features(a.g.deg[i], a.K[i], a.sig[a.cm[i]], a.hfrac[i], a.hgain[i], a.hbits[i], a.dsnap[i], a.pass,
                           a.iter, x);
         }
 #pragma unroll

@@ -79,13 +79,13 @@ __device__ __forceinline__ bool decide(const MoveArgs &a, int i, int d, double k
 // History of a scan (for the learned gate's features) and, if sampled, a
 // trace row with the features the vertex had before this scan and whether
 // it moves.  Called by one lane per decided vertex; no-op unless enabled.
-__device__ __noinline__ void record_scan(const MoveArgs &a, int i, int d, int di, double ki, double kid, double bg,
+__device__ __forceinline__ void record_scan(const MoveArgs &a, int i, int d, int di, double ki, double kid, double bg,
                                         int bc, bool mv) {
     uint8_t hb = a.hbits[i];
     float hf = a.hfrac[i], hg = a.hgain[i];
     if (a.tr.x && trace_keep(a.tr.seed, a.pass, a.sweep, i, a.tr.thr)) {
         uint16_t x[kGateFeatures];
-        gate_features(di, ki, a.sig[d], hf, hg, hb, a.dmoved[i], a.pass, a.iter, x);
+        gate_features(di, ki, a.sig[d], hf, hg, hb, a.dsnap[i], a.pass, a.iter, x);
         int r = blockIdx.x % kStripes;
         unsigned long long slot = atomicAdd(&a.tr.cnt[r], 1ull);
         if ((int64_t)slot < a.tr.scap) {
@@ -109,7 +109,13 @@ __device__ __noinline__ void record_scan(const MoveArgs &a, int i, int d, int di
     a.hfrac[i] = nf;
     a.hgain[i] = ng;
     a.hbits[i] = kHistScanned | (mv ? kHistMoved : 0);
-    a.dmoved[i] = 0.0;
+}
+
+// A mover's entry (i, j), j != i: j is unprocessed again and, with the
+// gate's history on, D_j grows by w_ij.
+__device__ __forceinline__ void mark_neighbour(const MoveArgs &a, int j, double w) {
+    a.flag[j] = 1;
+    if (a.dmoved) unsafeAtomicAdd(&a.dmoved[j], w);
 }
 
 // Folds the entry (key, v) of a scan table into (bg, bc, kid).
@@ -175,6 +181,10 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
             if (b == BIN_HUB) a.hub_act[i] = act ? 1 : 0;
             if (act) {
                 a.flag[i] = 0;
+                if (a.dmoved) {   // the features take D_i; it starts again now
+                    a.dsnap[i] = a.dmoved[i];
+                    a.dmoved[i] = 0.0;
+                }
                 rank = atomicAdd(&lcnt[b], 1);
             }
         }
@@ -228,7 +238,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     int *keys = wkeys + grp * kSlots;
     double *vals = wvals + grp * kSlots;
     int i = -1, di = 0, d = -1, j = -1;
-    double ki = 0.0;
+    double ki = 0.0, w = 0.0;
     if (valid) {
         i = a.queue[a.qbase[bin] + qi];
         di = a.g.deg[i];
@@ -237,7 +247,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
         if (gl < di) {
             int64_t e = a.g.off[i] + gl;
             j = load_col(a.g.col, e);
-            double w = edge_weight<WT>(a.g.w, e);
+            w = edge_weight<WT>(a.g.w, e);
             if (j != i) lds_table_add(keys, vals, kSlots - 1, a.cm[j], w);
         }
     }
@@ -252,7 +262,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     kid = group_sum_rt(kid, G);
     double gain = 0.0;
     bool mv = valid && decide(a, i, d, ki, kid, bg, bc, &gain);
-    if (mv && j >= 0 && j != i) a.flag[j] = 1;
+    if (mv && j >= 0 && j != i) mark_neighbour(a, j, w);
     bool lead = valid && gl == 0;
     if (lead) {
         acc.verts++;
@@ -360,7 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         if (mv)
             for (int e = lane; e < di; e += kWave) {
                 int j = load_col(a.g.col, beg + e);
-                if (j != i) a.flag[j] = 1;
+                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
             }
         if (lane == 0) {
             acc.verts++;
@@ -413,7 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         if (mv)
             for (int e = tid; e < di; e += kBlock) {
                 int j = load_col(a.g.col, beg + e);
-                if (j != i) a.flag[j] = 1;
+                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
             }
         if (tid == 0) {
             acc.verts++;
@@ -619,7 +629,12 @@ __global__ void __launch_bounds__(kBlock) k_move_apply(MoveArgs a, int nq) {
             if (end > beg + kHubChunk) end = beg + kHubChunk;
             for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) {
                 int j = load_col(a.g.col, e);
-                if (j != i) a.flag[j] = 1;
+                if (j == i) continue;
+                double w = 0.0;
+                if (a.dmoved)
+                    w = a.g.wt == W_UNIT ? 1.0
+                                         : (a.g.wt == W_F32 ? edge_weight<W_F32>(a.g.w, e) : edge_weight<W_F64>(a.g.w, e));
+                mark_neighbour(a, j, w);
             }
         }
         return;
@@ -681,63 +696,6 @@ __global__ void __launch_bounds__(kBlock) k_community_totals(const double *K, co
         double k = ok ? K[i] : 0.0;
         wave_add_f64_by_key(sig, c, k, ok && k != 0.0);
         if (csize) wave_add_i32_by_key(csize, c, 1, ok);
-    }
-}
-
-// Gate history after a sub-round's scans: every entry (i, j), j != i, of a
-// vertex i that moves in this sub-round (decided, not yet applied) adds w_ij
-// to D_j.  Blocks [0, nsm): one thread per queued vertex of the bins up to
-// 64 entries; blocks [nsm, nsm + nwv): one wavefront per queued vertex of
-// the wave and block bins; the rest: one block per chunk of a moving hub.
-template <int WT>
-__global__ void __launch_bounds__(kBlock) k_move_delta(MoveArgs a, int nsm, int nwv) {
-    const int tid = threadIdx.x;
-    const int *qc = a.ctr->qcnt[a.round];
-    if ((int)blockIdx.x < nsm) {
-        int64_t pre[kNumSmallBins + 1];
-        pre[0] = 0;
-#pragma unroll
-        for (int b = 0; b < kNumSmallBins; b++) pre[b + 1] = pre[b] + qc[b];
-        for (int64_t t = (int64_t)blockIdx.x * kBlock + tid; t < pre[kNumSmallBins]; t += (int64_t)nsm * kBlock) {
-            int b = 0;
-            while (t >= pre[b + 1]) b++;
-            int i = a.queue[a.qbase[b] + (t - pre[b])];
-            if (a.dec[i] == a.cm[i]) continue;
-            int64_t beg = a.g.off[i], end = beg + a.g.deg[i];
-            for (int64_t e = beg; e < end; e++) {
-                int j = load_col(a.g.col, e);
-                if (j != i) unsafeAtomicAdd(&a.dmoved[j], edge_weight<WT>(a.g.w, e));
-            }
-        }
-        return;
-    }
-    if ((int)blockIdx.x < nsm + nwv) {
-        const int w = tid / kWave, lane = lane_id();
-        const int64_t c5 = qc[BIN_WAVE], c6 = qc[BIN_BLOCK];
-        for (int64_t q = (int64_t)(blockIdx.x - nsm) * (kBlock / kWave) + w; q < c5 + c6;
-             q += (int64_t)nwv * (kBlock / kWave)) {
-            int i = q < c5 ? a.queue[a.qbase[BIN_WAVE] + q] : a.queue[a.qbase[BIN_BLOCK] + (q - c5)];
-            if (a.dec[i] == a.cm[i]) continue;
-            int64_t beg = a.g.off[i];
-            int di = a.g.deg[i];
-            for (int e = lane; e < di; e += kWave) {
-                int j = load_col(a.g.col, beg + e);
-                if (j != i) unsafeAtomicAdd(&a.dmoved[j], edge_weight<WT>(a.g.w, beg + e));
-            }
-        }
-        return;
-    }
-    const int nh = gridDim.x - nsm - nwv;
-    for (int64_t k = a.ch_first + (blockIdx.x - nsm - nwv); k < a.ch_first + a.ch_count; k += nh) {
-        int i = a.ch_vert[k];
-        if (a.hub_act[i] != 2) continue;
-        int64_t beg = a.ch_beg[k];
-        int64_t end = a.g.off[i] + a.g.deg[i];
-        if (end > beg + kHubChunk) end = beg + kHubChunk;
-        for (int64_t e = beg + tid; e < end; e += kBlock) {
-            int j = load_col(a.g.col, e);
-            if (j != i) unsafeAtomicAdd(&a.dmoved[j], edge_weight<WT>(a.g.w, e));
-        }
     }
 }
 
@@ -814,22 +772,6 @@ void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
     k_move_hub_part<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
     k_move_hub_final<<<cap_grid((a.qcap[BIN_HUB] + 3) / 4, 1024), kBlock, 0, s>>>(a);
-}
-
-void launch_move_delta(const MoveArgs &a, hipStream_t s) {
-    int64_t small = 0;
-    for (int b = 0; b < kNumSmallBins; b++) small += a.qcap[b];
-    int64_t large = a.qcap[BIN_WAVE] + a.qcap[BIN_BLOCK];
-    int nsm = small ? (int)cap_grid((small + kBlock - 1) / kBlock, 2048) : 0;
-    int nwv = large ? (int)cap_grid((large + 3) / 4, 2048) : 0;
-    int nh = a.qcap[BIN_HUB] ? (int)cap_grid(a.ch_count, 1024) : 0;
-    if (nsm + nwv + nh == 0) return;
-    if (a.g.wt == W_UNIT)
-        k_move_delta<W_UNIT><<<nsm + nwv + nh, kBlock, 0, s>>>(a, nsm, nwv);
-    else if (a.g.wt == W_F32)
-        k_move_delta<W_F32><<<nsm + nwv + nh, kBlock, 0, s>>>(a, nsm, nwv);
-    else
-        k_move_delta<W_F64><<<nsm + nwv + nh, kBlock, 0, s>>>(a, nsm, nwv);
 }
 
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s) {
