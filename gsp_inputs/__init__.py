@@ -251,5 +251,22 @@ def batch_sbm_params(count: int, master_seed: int = 4):
         s = n / k
         p_in = min(1.0, (1.0 - mu) * d / max(s - 1.0, 1.0))
         p_out = min(1.0, mu * d / max(n - s, 1.0)) if k > 1 else 0.0
-        out.append(dict(n=n, blocks=k, p_in=p_in, p_out=p_out, seed=master_seed * 1_000_003 + g))
+        out.append(dict(n=n, blocks=k, p_in=p_in, p_out=p_out, seed=master_seed * 1_000_003 + g, degree=d,
+                        mixing=mu))
     return out
+
+
+def batch_sbm(count: int, master_seed: int = 4, scale: float = 1.0):
+    """The batch's graphs (planted-partition SBMs, unit weights).  scale < 1
+    shrinks every n (at least 100 vertices) keeping its average degree,
+    mixing and block size of ~100 vertices."""
+    gs = []
+    for p in batch_sbm_params(count, master_seed):
+        n = max(100, int(round(p["n"] * scale)))
+        k = max(1, int(round(n / 100)))
+        s = n / k
+        d, mu = p["degree"], p["mixing"]
+        p_in = min(1.0, (1.0 - mu) * d / max(s - 1.0, 1.0))
+        p_out = min(1.0, mu * d / max(n - s, 1.0)) if k > 1 else 0.0
+        gs.append(sbm(n, k, p_in, p_out, p["seed"], name=f"batch-{p['seed']}"))
+    return gs

@@ -220,6 +220,38 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
                              const gsp_options *opt, int32_t *iterations, double *dq_iter, int64_t *moved_iter,
                              int64_t *counters);
 
+/* ---- batches of independent graphs ----
+ *
+ * Many graphs (e.g. hundreds of uneven sizes) are run together: every
+ * kernel of the method processes all of them in one launch, as one
+ * block-diagonal level, while each graph keeps its own 2m (Eq. 1 and 2 use
+ * it), its own per-iteration gain total and tolerance test, its own l_i and
+ * its own pass-level tests (Algorithm "louvain"); a graph that has finished
+ * stays still while the others go on.  Sub-rounds are taken by the vertex's
+ * id within its graph, so every graph's result is the one gsp_run gives for
+ * it alone.  Learned pruning is not available for batches. */
+
+/* Loads `graphs` host CSRs (graph k: n[k] >= 1 vertices, nnz[k] entries,
+ * offsets[k] int64 [n[k]+1], cols[k] int32 in [0, n[k]), weights[k] fp32 or
+ * NULL; weights itself may be NULL for all-unit weights).  The sum of n
+ * must stay below 2^31 - 1.  Replaces any graph loaded before. */
+gsp_status gsp_load_batch(gsp_ctx *ctx, int32_t graphs, const int64_t *n, const int64_t *nnz,
+                          const int64_t *const *offsets, const int32_t *const *cols, const float *const *weights);
+
+/* Runs the method on every graph of the loaded batch (arguments as gsp_run). */
+gsp_status gsp_run_batch(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *opt);
+
+/* Membership of graph `graph` (n[graph] values, communities numbered by
+ * ascending smallest vertex id within the graph). */
+gsp_status gsp_get_batch_membership(gsp_ctx *ctx, int32_t graph, int32_t *out, int where);
+
+/* Modularity (Eq. 1, the graph's own 2m) of every graph's result: q_out
+ * has one value per graph (host). */
+gsp_status gsp_get_batch_modularity(gsp_ctx *ctx, double *q_out);
+
+/* Passes each graph took part in (host, one value per graph). */
+gsp_status gsp_get_batch_passes(gsp_ctx *ctx, int32_t *passes_out);
+
 /* ---- learned vertex pruning ----
  *
  * Not part of the paper.  In a run with prune_mode = GSP_PRUNE_LEARNED every
@@ -238,8 +270,8 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
  *   x6 = 0 if not scanned yet in this pass, 1/2 if it stayed at its last
  *        scan, 1 if it moved;
  *   x7 = min(D_i / K_i, 1) with D_i the weight of the entries (i, j) whose
- *        j moved since i was last taken from the unprocessed set (scanned
- *        or pruned), or since the pass began;
+ *        j moved since the vertex's last scan (or since the pass began; a
+ *        pruned vertex keeps it);
  * each computed in fp64 and rounded to fp32, then to bf16 (round to nearest
  * even).  The vertex is scanned iff z >= log(theta / (1 - theta)), theta =
  * prune_threshold; otherwise it keeps its community.  Inference uses bf16

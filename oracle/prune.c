@@ -71,9 +71,8 @@ static float feat(double v) { return orc_bf16((float)v); }
  *   x5 = K_i / Sigma_d               i's share of its community's weight
  *   x6 = 0 never scanned in this pass, 1/2 stayed at its last scan, 1 moved
  *   x7 = min(D_i / K_i, 1)           D_i = weight of the entries (i, j) whose
- *                                    j moved since i was last taken from
- *                                    the unprocessed set (scanned or
- *                                    pruned), or since the pass began
+ *                                    j moved since i's last scan (or since
+ *                                    the pass began; pruning keeps it)
  * Each value is computed in fp64, then rounded to fp32 and to bf16. */
 void orc_gate_features(int64_t deg, double ki, double sig_d, float hfrac, float hgain, uint8_t hbits, double dmoved,
                        int32_t pass, int32_t iter, float *x) {
@@ -376,9 +375,9 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * move).
  *
  * History (both modes, used by the features): at a vertex's scan, bit 0 of
- * hbits (scanned), bit 1 (moved), hfrac and hgain (gate_history) are set;
- * D_i is read into the features and cleared when i is taken from the
- * unprocessed set (before the gate), and when a sub-round's moves are
+ * hbits (scanned), bit 1 (moved), hfrac and hgain (gate_history) are set
+ * and D_i is cleared (D_i is read into the features when i is taken from
+ * the unprocessed set, before the gate); when a sub-round's moves are
  * applied every entry (i, j), j != i, of a mover i adds w_ij to D_j.  All
  * start at 0 in the phase.
  *
@@ -446,7 +445,6 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                 if (off[i + 1] == off[i]) continue;   /* an empty row: nothing to scan, never moves */
                 orc_gate_features(off[i + 1] - off[i], K[i], sigma[memb[i]], hfrac[i], hgain[i], hbits[i], dmv[i],
                                   pass, li, xf + i * NF);
-                dmv[i] = 0.0;   /* taken from the frontier: D_i starts again */
                 if (mode == GATED && mlp_row(pd, xf + i * NF, 1, NULL, NULL) < theta_logit) {
                     cnt[2]++;
                     continue;
@@ -484,6 +482,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                     trace_put(trace, xf + i * NF, (uint8_t)mv, i, pass, sweep);
                 gate_history(ki, kid, M2, best >= 0, g_best, g_stay, &hfrac[i], &hgain[i]);
                 hbits[i] = (uint8_t)(1u | (mv ? 2u : 0u));
+                dmv[i] = 0.0;   /* scanned: D_i starts again */
                 if (mv) {
                     dec[i] = best;
                     gain[i] = g_best - g_stay;

@@ -111,6 +111,11 @@ def lib():
         "gsp_gate_logits": [vp, vp, i64, vp, ctypes.c_int],
         "gsp_pruner_grad": [vp, vp, vp, vp, i64, ctypes.c_float, vp, ctypes.POINTER(dbl), ctypes.c_int],
         "gsp_pruner_train": [vp, vp, vp, i64, i64, i32, ctypes.c_float, ctypes.c_float, vp, vp, ctypes.c_int],
+        "gsp_load_batch": [vp, i32, vp, vp, vp, vp, vp],
+        "gsp_run_batch": [vp, dbl, i32, ctypes.POINTER(Options)],
+        "gsp_get_batch_membership": [vp, i32, vp, ctypes.c_int],
+        "gsp_get_batch_modularity": [vp, vp],
+        "gsp_get_batch_passes": [vp, vp],
         "gsp_capture_traces": [vp, i64, dbl, ctypes.c_uint64],
         "gsp_get_traces": [vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int],
     }
@@ -317,6 +322,54 @@ class Context:
         cnt = dict(scanned_vertices=int(c4[0]), scanned_entries=int(c4[1]), pruned=int(c4[2]),
                    confirm_sweeps=int(c4[3]))
         return m, li.value, dq[:li.value], mv[:li.value], cnt
+
+    # -------------------------------------------------------------- batches
+    def load_batch(self, graphs) -> None:
+        """Loads a list of graphs (objects with n, offsets, cols, weights) as
+        one batch."""
+        G = len(graphs)
+        keep = []
+        n = np.array([g.n for g in graphs], dtype=np.int64)
+        nnz = np.array([int(g.cols.shape[0]) for g in graphs], dtype=np.int64)
+        offs = (ctypes.c_void_p * G)()
+        cols = (ctypes.c_void_p * G)()
+        any_w = any(g.weights is not None for g in graphs)
+        ws = (ctypes.c_void_p * G)() if any_w else None
+        for k, g in enumerate(graphs):
+            o = np.ascontiguousarray(g.offsets, dtype=np.int64)
+            c = np.ascontiguousarray(g.cols, dtype=np.int32)
+            keep += [o, c]
+            offs[k] = o.ctypes.data
+            cols[k] = c.ctypes.data
+            if any_w and g.weights is not None:
+                w = np.ascontiguousarray(g.weights, dtype=np.float32)
+                keep.append(w)
+                ws[k] = w.ctypes.data
+        self._check(lib().gsp_load_batch(self._h, G, n.ctypes.data, nnz.ctypes.data, offs, cols, ws),
+                    "gsp_load_batch")
+        self.batch_n = [int(x) for x in n]
+        self.n = int(n.sum())
+        self.nnz = int(nnz.sum())
+
+    def run_batch(self, tolerance: float = 1e-2, max_passes: int = 10, options: Optional[Options] = None,
+                  **kw) -> None:
+        opt = options if options is not None else default_options(**kw)
+        self._check(lib().gsp_run_batch(self._h, tolerance, max_passes, ctypes.byref(opt)), "gsp_run_batch")
+
+    def batch_membership(self, k: int) -> np.ndarray:
+        out = np.empty(self.batch_n[k], dtype=np.int32)
+        self._check(lib().gsp_get_batch_membership(self._h, k, out.ctypes.data, HOST), "gsp_get_batch_membership")
+        return out
+
+    def batch_modularity(self) -> np.ndarray:
+        q = np.empty(len(self.batch_n), dtype=np.float64)
+        self._check(lib().gsp_get_batch_modularity(self._h, q.ctypes.data), "gsp_get_batch_modularity")
+        return q
+
+    def batch_passes(self) -> np.ndarray:
+        p = np.empty(len(self.batch_n), dtype=np.int32)
+        self._check(lib().gsp_get_batch_passes(self._h, p.ctypes.data), "gsp_get_batch_passes")
+        return p
 
     # ---------------------------------------------------- learned pruning
     def pruner_set(self, params) -> None:

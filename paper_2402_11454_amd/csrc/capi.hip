@@ -124,6 +124,18 @@ struct gsp_ctx {
     float *net_f = nullptr;          // b1[64] b2[64] w3[64]
     float net_b3 = 0.0f;
     std::vector<float> net_params;   // fp32 parameters as given
+    // a batch of graphs side by side (batch_graphs > 0 after gsp_load_batch)
+    int64_t batch_graphs = 0;
+    std::vector<int64_t> vbase0_h;        // first vertex of each graph (+ total)
+    std::vector<double> M2g_h;            // 2m of each graph
+    int64_t *vbase0 = nullptr, *vbaseL[2] = {nullptr, nullptr}, *cfirst = nullptr;
+    int32_t *gid0 = nullptr, *gidL[2] = {nullptr, nullptr};
+    double *M2g = nullptr, *ggain = nullptr, *bq = nullptr, *bqin = nullptr;
+    unsigned long long *gmoved = nullptr;
+    uint8_t *gactive = nullptr;
+    bool have_batch_result = false;
+    std::vector<double> bq_h;             // modularity of each graph
+    std::vector<int32_t> bpasses_h;       // passes each graph took part in
     // trace capture (kept across loads and runs until stopped)
     bool tracing = false;
     TraceArgs trace;
@@ -192,6 +204,17 @@ struct gsp_ctx {
         ctr = nullptr;
         hfrac = hgain = nullptr;
         hbits = nullptr;
+        batch_graphs = 0;
+        vbase0_h.clear();
+        M2g_h.clear();
+        vbase0 = cfirst = nullptr;
+        vbaseL[0] = vbaseL[1] = nullptr;
+        gid0 = nullptr;
+        gidL[0] = gidL[1] = nullptr;
+        M2g = ggain = bq = bqin = nullptr;
+        gmoved = nullptr;
+        gactive = nullptr;
+        have_batch_result = false;
         dmoved = dsnap = nullptr;
         cand = nullptr;
         loaded = false;
@@ -325,6 +348,10 @@ struct PhaseCfg {
     double *dq_out = nullptr;      // per counted iteration (max_iter entries)
     int64_t *moved_out = nullptr;
     double *kernel_bytes = nullptr;
+    // batch (g.gid != nullptr): graphs already finished stay still; out:
+    // each graph's counted iterations
+    const uint8_t *gdone = nullptr;   // host, per graph
+    std::vector<int32_t> li_g;
     // out
     int32_t li = 0;
     int64_t scanned_vertices = 0, scanned_entries = 0, pruned = 0, confirm_sweeps = 0, sweeps = 0;
@@ -386,7 +413,30 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     enum { GATED, CONFIRM, PLAIN } mode = cfg.gated ? GATED : PLAIN;
     launch_fill_u8(ctx->flag, 1, g.n, s);
     int li = 0;
-    for (int sweep = 0; li < cfg.max_iter; sweep++) {
+    const bool batch = g.gid != nullptr;
+    const int64_t G = batch ? g.graphs : 0;
+    std::vector<uint8_t> act;
+    std::vector<double> gg;
+    std::vector<unsigned long long> gm;
+    if (batch) {
+        if (cfg.gated) return ctx->fail(GSP_EINVAL, "learned pruning is not available for batches");
+        act.assign(G, 1);
+        for (int64_t k = 0; k < G; k++) act[k] = cfg.gdone && cfg.gdone[k] ? 0 : 1;
+        cfg.li_g.assign(G, 0);
+        gg.resize(G);
+        gm.resize(G);
+    }
+    for (int sweep = 0;; sweep++) {
+        if (batch) {
+            bool any = false;
+            for (int64_t k = 0; k < G && !any; k++) any = act[k] != 0;
+            if (!any) break;
+            HIP_TRY(hipMemcpyAsync(ctx->gactive, act.data(), G, hipMemcpyHostToDevice, s));
+            launch_fill_f64(ctx->ggain, 0.0, G, s);
+            launch_fill_u64(ctx->gmoved, 0, G, s);
+        } else if (li >= cfg.max_iter) {
+            break;
+        }
         cfg.sweeps++;
         if (mode == CONFIRM) {
             launch_fill_u8(ctx->flag, 1, g.n, s);
@@ -438,6 +488,11 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 if (ctx->tracing) a.tr = ctx->trace;
             }
             if (mode == GATED) a.cand = ctx->cand;
+            if (batch) {
+                a.ggain = ctx->ggain;
+                a.gmoved = ctx->gmoved;
+                a.gactive = ctx->gactive;
+            }
             if (cap == 0) continue;
             const bool tk = cfg.timing_k;
             int t;
@@ -481,6 +536,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
+        if (batch) {
+            HIP_TRY(hipMemcpyAsync(gg.data(), ctx->ggain, G * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(gm.data(), ctx->gmoved, G * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        }
         HIP_TRY(hipStreamSynchronize(s));
         CounterStripe h;
         memset(&h, 0, sizeof(h));
@@ -513,6 +572,18 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 for (int b = 0; b < kNumBins; b++) nc += ctx->ctr_h->ccnt[p][b];
             cfg.kernel_bytes[GSP_K_GATE] += 41.0 * (double)nc;
             ctx->stats.kernels[GSP_K_GATE].items += nc;
+        }
+        if (batch) {
+            // each graph's own convergence test (its gain total over its 2m^2)
+            for (int64_t k = 0; k < G; k++) {
+                if (!act[k]) continue;
+                double m2 = ctx->M2g_h[k];
+                double dqk = m2 > 0.0 ? (2.0 * gg[k]) / (m2 * m2) : 0.0;
+                cfg.li_g[k]++;
+                if (dqk <= cfg.tau || cfg.li_g[k] >= cfg.max_iter) act[k] = 0;
+            }
+            li++;
+            continue;
         }
         const bool counted = mode != CONFIRM || h.moved > 0;
         if (counted) {
@@ -816,10 +887,17 @@ gsp_status gsp_load_csr_f64(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t 
     return load_impl(ctx, n, nnz, offsets, nullptr, cols, weights, weights ? W_F64 : W_UNIT, where);
 }
 
-gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *optp) {
-    if (!ctx) return GSP_EINVAL;
-    (void)hipSetDevice(ctx->device);
+}  // extern "C"
+
+namespace {
+
+// Algorithm "louvain" on the loaded graph, or on the loaded batch of graphs
+// (batch = true): then every graph keeps its own 2m, convergence tests,
+// iteration counts and passes, and a graph that has finished stays still
+// while the others go on; its levels are still aggregated with the rest.
+gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *optp, bool batch) {
     if (!ctx->loaded) return ctx->fail(GSP_ESTATE, "no graph loaded");
+    if (batch && ctx->batch_graphs == 0) return ctx->fail(GSP_ESTATE, "no batch loaded (gsp_load_batch)");
     gsp_options opt;
     if (optp)
         opt = *optp;
@@ -828,6 +906,8 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
     if (!(tolerance >= 0.0) || max_passes < 0) return ctx->fail(GSP_EINVAL, "tolerance < 0 or max_passes < 0");
     gsp_status st0 = check_options(ctx, opt);
     if (st0 != GSP_OK) return st0;
+    if (batch && opt.prune_mode != GSP_PRUNE_PLAIN)
+        return ctx->fail(GSP_EINVAL, "learned pruning is not available for batches");
     ctx->mem_limit = opt.mem_limit_bytes;
     if (ctx->mem_limit && ctx->mem_used > ctx->mem_limit)
         return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
@@ -835,6 +915,7 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
     if (st != GSP_OK) return st;
     hipStream_t s = ctx->stream;
     ctx->have_result = false;
+    ctx->have_batch_result = false;
     ctx->have_q = false;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->timer.reset();
@@ -843,8 +924,19 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
     for (int k = 0; k < GSP_K_COUNT; k++) ctx->kernel_launches[k] = 0;
     int t_all = tphase ? ctx->timer.begin(PH_COUNT) : -1;
 
+    const int64_t G = batch ? ctx->batch_graphs : 0;
+    std::vector<uint8_t> gdone(G, 0);
+    std::vector<int64_t> cfirst_h(G + 1, 0);
+    if (batch) ctx->bpasses_h.assign(G, 0);
+
     launch_iota_i32(ctx->top, ctx->n, s);
     Level g = level0(ctx);
+    if (batch) {
+        g.graphs = G;
+        g.gid = ctx->gid0;
+        g.vbase = ctx->vbase0;
+        g.M2g = ctx->M2g;
+    }
     const double *K = ctx->K0;
     double tau = tolerance;
     int next = 0;
@@ -868,9 +960,14 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
         pc.theta_logit = theta_logit(opt.prune_threshold);
         pc.pass = lp;
         pc.kernel_bytes = kbytes;
+        if (batch) pc.gdone = gdone.data();
         st = move_phase(ctx, g, K, wl, pc);
         if (st != GSP_OK) return st;
-        const int32_t li = pc.li;
+        int32_t li = pc.li;
+        if (batch) {
+            li = 0;
+            for (int64_t k = 0; k < G; k++) li = std::max(li, pc.li_g[k]);
+        }
         ctx->stats.scanned_entries += pc.scanned_entries;
         ctx->stats.scanned_vertices += pc.scanned_vertices;
         ctx->stats.pruned += pc.pruned;
@@ -895,14 +992,34 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
         st = renumber(ctx, labels, g.n, ctx->cm, &ncomm);
         if (st != GSP_OK) return st;
         launch_lookup(ctx->top, ctx->n, ctx->cm, s);
+        bool stop = false;
+        if (batch) {
+            // each graph's communities: [cfirst[k], cfirst[k+1])
+            launch_batch_cfirst(ctx->sc.i32b, g.vbase, G, ctx->sc.i64e, ctx->cfirst, s);
+            HIP_TRY(hipMemcpyAsync(cfirst_h.data(), ctx->cfirst, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            std::vector<int64_t> vb(G + 1);
+            HIP_TRY(hipMemcpyAsync(vb.data(), g.vbase, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            bool all = true;
+            for (int64_t k = 0; k < G; k++) {
+                if (gdone[k]) continue;
+                ctx->bpasses_h[k] = lp + 1;
+                int64_t nk = vb[k + 1] - vb[k], ck = cfirst_h[k + 1] - cfirst_h[k];
+                if (pc.li_g[k] <= 1 || (double)ck / (double)nk > opt.aggregation_tolerance) gdone[k] = 1;
+                all = all && gdone[k];
+            }
+            stop = all;
+        } else {
+            stop = li <= 1 ||                                                // globally converged
+                   (double)ncomm / (double)g.n > opt.aggregation_tolerance;    // low shrink
+        }
         ctx->timer.end(t);
         if (lp < GSP_MAX_PASSES_STATS) {
             ctx->stats.iterations[lp] = li;
             ctx->stats.vertices[lp] = g.n;
             ctx->stats.communities[lp] = ncomm;
         }
-        if (li <= 1) break;                                               // globally converged
-        if ((double)ncomm / (double)g.n > opt.aggregation_tolerance) break; // low shrink
+        if (stop) break;
         if (lp == max_passes - 1) break;                                   // G'' would be unused
         t = tphase ? ctx->timer.begin(PH_AGG) : -1;
         int tk2 = tk ? ctx->timer.begin(100 + GSP_K_AGGREGATE) : -1;
@@ -928,6 +1045,16 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
         g2.w = out.w;
         g2.wt = W_F64;
         g2.deg = out.deg;
+        if (batch) {
+            // super-vertex c of graph k: ids [cfirst[k], cfirst[k+1])
+            HIP_TRY(hipMemcpyAsync(ctx->vbaseL[next], ctx->cfirst, (G + 1) * sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice, s));
+            launch_batch_gid(ctx->vbaseL[next], G, ncomm, ctx->gidL[next], s);
+            g2.graphs = G;
+            g2.gid = ctx->gidL[next];
+            g2.vbase = ctx->vbaseL[next];
+            g2.M2g = ctx->M2g;
+        }
         g = g2;
         K = out.K;
         next ^= 1;
@@ -943,9 +1070,28 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
     if (opt.split_mode != GSP_SPLIT_PASS && ctx->n > 0) {
         // number communities by ascending smallest vertex id
         launch_canonical_labels(ctx->top, ctx->n, ctx->sc.i32c, ctx->lab, s);
-        int64_t G = 0;
-        st = renumber(ctx, ctx->lab, ctx->n, ctx->top, &G);
+        int64_t ncan = 0;
+        st = renumber(ctx, ctx->lab, ctx->n, ctx->top, &ncan);
         if (st != GSP_OK) return st;
+    }
+    if (batch) {
+        // each graph's modularity with its own 2m; communities of graph k are
+        // [top[vbase0[k]], top[vbase0[k + 1]]) after the numbering above
+        Level g0 = level0(ctx);
+        g0.graphs = G;
+        g0.gid = ctx->gid0;
+        g0.vbase = ctx->vbase0;
+        g0.M2g = ctx->M2g;
+        launch_fill_f64(ctx->sig, 0.0, ctx->n, s);
+        launch_fill_i32(ctx->csize, 0, ctx->n, s);
+        launch_community_totals(ctx->K0, ctx->top, ctx->n, ctx->sig, ctx->csize, s);
+        // the last renumbering left the community count in sc.i64e (none ran
+        // when max_passes = 0: then every vertex is its own community)
+        if (passes == 0) launch_fill_i64(ctx->sc.i64e, ctx->n, 1, s);
+        launch_batch_cfirst(ctx->top, ctx->vbase0, G, ctx->sc.i64e, ctx->cfirst, s);
+        launch_batch_modularity(g0, ctx->top, ctx->sig, ctx->cfirst, ctx->bqin, ctx->bq, s);
+        ctx->bq_h.assign(G, 0.0);
+        HIP_TRY(hipMemcpyAsync(ctx->bq_h.data(), ctx->bq, G * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     ctx->timer.end(t_all);
     HIP_TRY(hipStreamSynchronize(s));
@@ -966,6 +1112,135 @@ gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp
         }
     }
     ctx->have_result = true;
+    ctx->have_batch_result = batch;
+    return GSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsp_status gsp_run(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *optp) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return run_passes(ctx, tolerance, max_passes, optp, false);
+}
+
+// ---- batches of graphs ----
+
+gsp_status gsp_load_batch(gsp_ctx *ctx, int32_t graphs, const int64_t *n, const int64_t *nnz,
+                          const int64_t *const *offsets, const int32_t *const *cols, const float *const *weights) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (graphs <= 0 || !n || !nnz || !offsets || !cols) return ctx->fail(GSP_EINVAL, "bad batch arguments");
+    int64_t N = 0, E = 0;
+    bool any_w = false;
+    for (int32_t k = 0; k < graphs; k++) {
+        if (n[k] <= 0 || nnz[k] < 0 || !offsets[k] || (nnz[k] > 0 && !cols[k]))
+            return ctx->fail(GSP_EINVAL, "every graph of a batch needs n >= 1, nnz >= 0, offsets and columns");
+        if (offsets[k][0] != 0 || offsets[k][n[k]] != nnz[k])
+            return ctx->fail(GSP_EGRAPH, "a graph's offsets must start at 0 and end at its nnz");
+        N += n[k];
+        E += nnz[k];
+        any_w = any_w || (weights && weights[k]);
+        if (N > 0x7fffffffLL - 1) return ctx->fail(GSP_EINVAL, "a batch must hold fewer than 2^31 - 1 vertices");
+    }
+    // one block-diagonal CSR: graph k's vertex v is vertex vbase[k] + v
+    std::vector<int64_t> off(N + 1);
+    std::vector<int32_t> col(E);
+    std::vector<float> w(any_w ? E : 0);
+    std::vector<int64_t> vbase(graphs + 1);
+    int64_t vb = 0, eb = 0;
+    for (int32_t k = 0; k < graphs; k++) {
+        vbase[k] = vb;
+        for (int64_t v = 0; v < n[k]; v++) off[vb + v] = eb + offsets[k][v];
+        for (int64_t e = 0; e < nnz[k]; e++) {
+            int32_t c = cols[k][e];
+            if (c < 0 || c >= n[k]) return ctx->fail(GSP_EGRAPH, "a column lies outside its graph");
+            col[eb + e] = (int32_t)(vb + c);
+        }
+        if (any_w)
+            for (int64_t e = 0; e < nnz[k]; e++) w[eb + e] = weights[k] ? weights[k][e] : 1.0f;
+        vb += n[k];
+        eb += nnz[k];
+    }
+    off[N] = E;
+    vbase[graphs] = N;
+    gsp_status st = load_impl(ctx, N, E, off.data(), nullptr, col.data(), any_w ? (const void *)w.data() : nullptr,
+                              any_w ? W_F32 : W_UNIT, GSP_HOST);
+    if (st != GSP_OK) return st;
+    hipError_t e = hipSuccess;
+    const int64_t G = graphs;
+    ctx->vbase0 = ctx->dalloc<int64_t>(G + 1, &e);
+    for (int k = 0; k < 2 && e == hipSuccess; k++) {
+        ctx->vbaseL[k] = ctx->dalloc<int64_t>(G + 1, &e);
+        if (e == hipSuccess) ctx->gidL[k] = ctx->dalloc<int32_t>(N, &e);
+    }
+    if (e == hipSuccess) ctx->cfirst = ctx->dalloc<int64_t>(G + 1, &e);
+    if (e == hipSuccess) ctx->gid0 = ctx->dalloc<int32_t>(N, &e);
+    if (e == hipSuccess) ctx->M2g = ctx->dalloc<double>(G, &e);
+    if (e == hipSuccess) ctx->ggain = ctx->dalloc<double>(G, &e);
+    if (e == hipSuccess) ctx->bq = ctx->dalloc<double>(G, &e);
+    if (e == hipSuccess) ctx->bqin = ctx->dalloc<double>(G, &e);
+    if (e == hipSuccess) ctx->gmoved = ctx->dalloc<unsigned long long>(G, &e);
+    if (e == hipSuccess) ctx->gactive = ctx->dalloc<uint8_t>(G, &e);
+    if (e != hipSuccess) {
+        ctx->free_graph();
+        return ctx->fail_hip(e, "hipMalloc(batch state)");
+    }
+    hipStream_t s = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(ctx->vbase0, vbase.data(), (G + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_batch_gid(ctx->vbase0, G, N, ctx->gid0, s);
+    launch_batch_m2(ctx->K0, ctx->vbase0, G, ctx->M2g, s);
+    ctx->M2g_h.assign(G, 0.0);
+    HIP_TRY(hipMemcpyAsync(ctx->M2g_h.data(), ctx->M2g, G * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    ctx->vbase0_h = vbase;
+    ctx->batch_graphs = G;
+    return GSP_OK;
+}
+
+gsp_status gsp_run_batch(gsp_ctx *ctx, double tolerance, int32_t max_passes, const gsp_options *opt) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    return run_passes(ctx, tolerance, max_passes, opt, true);
+}
+
+gsp_status gsp_get_batch_membership(gsp_ctx *ctx, int32_t graph, int32_t *out, int where) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->have_batch_result) return ctx->fail(GSP_ESTATE, "no batch result (call gsp_run_batch)");
+    if (graph < 0 || graph >= ctx->batch_graphs || !out) return ctx->fail(GSP_EINVAL, "bad graph index or NULL out");
+    if (check_where(ctx, where) != GSP_OK) return GSP_EINVAL;
+    hipStream_t s = ctx->stream;
+    int64_t b = ctx->vbase0_h[graph], len = ctx->vbase0_h[graph + 1] - b;
+    int32_t first = 0;
+    HIP_TRY(hipMemcpyAsync(&first, ctx->top + b, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (where == GSP_DEVICE) {
+        HIP_TRY(hipMemcpyAsync(out, ctx->top + b, len * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        launch_add_i32(out, len, -first, s);
+    } else {
+        HIP_TRY(hipMemcpyAsync(out, ctx->top + b, len * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (where == GSP_HOST)
+        for (int64_t v = 0; v < len; v++) out[v] -= first;
+    return GSP_OK;
+}
+
+gsp_status gsp_get_batch_modularity(gsp_ctx *ctx, double *q_out) {
+    if (!ctx || !q_out) return GSP_EINVAL;
+    if (!ctx->have_batch_result) return ctx->fail(GSP_ESTATE, "no batch result (call gsp_run_batch)");
+    for (int64_t k = 0; k < ctx->batch_graphs; k++) q_out[k] = ctx->bq_h[k];
+    return GSP_OK;
+}
+
+gsp_status gsp_get_batch_passes(gsp_ctx *ctx, int32_t *passes_out) {
+    if (!ctx || !passes_out) return GSP_EINVAL;
+    if (!ctx->have_batch_result) return ctx->fail(GSP_ESTATE, "no batch result (call gsp_run_batch)");
+    for (int64_t k = 0; k < ctx->batch_graphs; k++) passes_out[k] = ctx->bpasses_h[k];
     return GSP_OK;
 }
 

@@ -17,8 +17,7 @@
 //   x6 = 0 if not scanned yet in this pass, 1/2 if it stayed at its last
 //        scan, 1 if it moved
 //   x7 = min(D_i / K_i, 1), D_i = weight of the entries (i, j) whose j moved
-//        since i was last taken from the unprocessed set (scanned or
-//        pruned), or since the pass began
+//        since i's last scan (or since the pass began; pruning keeps it)
 // each computed in fp64, rounded to fp32, then to bf16 (round to nearest
 // even).  Every step is an IEEE operation, so the values are reproducible
 // bit for bit.

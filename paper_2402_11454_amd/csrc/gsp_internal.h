@@ -22,6 +22,11 @@ struct Level {
     const void *w = nullptr;
     int wt = W_UNIT;
     const int32_t *deg = nullptr;
+    // a batch of independent graphs side by side (gid == nullptr: one graph)
+    int64_t graphs = 0;
+    const int32_t *gid = nullptr;     // graph of each vertex
+    const int64_t *vbase = nullptr;   // first vertex of each graph (graphs + 1 entries)
+    const double *M2g = nullptr;      // 2m of each graph
 };
 
 // Vertex work lists of a level: every vertex with deg > 0 sits in bucket
@@ -122,6 +127,11 @@ struct MoveArgs {
     int32_t *cand = nullptr;                    // gated sweep: candidates (the gate fills `queue`)
     int pass = 0, sweep = 0, iter = 0;          // feature and trace context
     TraceArgs tr;                               // tr.x == nullptr: no capture
+    // batch of graphs (g.gid != nullptr): per-graph totals of the sweep and
+    // the graphs still iterating
+    double *ggain = nullptr;
+    unsigned long long *gmoved = nullptr;
+    const uint8_t *gactive = nullptr;
 };
 
 // ---- k_util.hip ----
@@ -129,6 +139,7 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+void launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
 void launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
 void launch_copy_i32(int32_t *dst, const int32_t *src, int64_t n, hipStream_t s);
@@ -160,7 +171,8 @@ struct Scratch;
 hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s);
 // Only the buckets (no hub chunks or tables): items with deg[i] > 0 into
 // wl.bl by (bin of deg[i], sub-round of i).
-hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s);
+hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s,
+                        const int32_t *gid = nullptr, const int64_t *vbase = nullptr);
 
 // ---- k_move.hip ----
 void launch_community_totals(const double *K, const int32_t *cm, int64_t n, double *sig, int32_t *csize,
@@ -192,6 +204,21 @@ void launch_mlp_grad(const float *params, const float *x, const uint8_t *y, int6
                      float inv_batch, float *part, double *part_loss, hipStream_t s);
 void launch_mlp_reduce(const float *part, const double *part_loss, int nblocks, float *params, float *m, float *v,
                        bool adam, float lr, float c1, float c2, float *grad, double *loss, hipStream_t s);
+
+// ---- k_batch.hip ----
+// gid[v] = graph of vertex v for a level with graph bases vbase[0..G].
+void launch_batch_gid(const int64_t *vbase, int64_t G, int64_t n, int32_t *gid, hipStream_t s);
+// 2m of each graph (sum of K over its vertices, reproducible order).
+void launch_batch_m2(const double *K, const int64_t *vbase, int64_t G, double *M2g, hipStream_t s);
+// cfirst[g] = rank[vbase[g]] (g < G), cfirst[G] = *count: first community
+// id of each graph after a renumbering with rank = exclusive scan of flags.
+void launch_batch_cfirst(const int32_t *rank, const int64_t *vbase, int64_t G, const int64_t *count,
+                         int64_t *cfirst, hipStream_t s);
+// q[g] = modularity of graph g (level g holds the batch; memb values are
+// community ids, graph g's in [cfirst[g], cfirst[g+1]); sig = Sigma_c).
+void launch_batch_modularity(const Level &g, const int32_t *memb, const double *sig, const int64_t *cfirst,
+                             double *qin, double *q, hipStream_t s);
+void launch_add_i32(int32_t *p, int64_t n, int32_t delta, hipStream_t s);
 
 // ---- k_split.hip ----
 // labels[i] = smallest vertex of i's component among same-community edges.

@@ -65,11 +65,21 @@ __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
     }
 }
 
+// Batch: a mover's gain and count into its graph's totals (one lane).
+__device__ __forceinline__ void graph_totals(const MoveArgs &a, int i, double gain) {
+    int gk = a.g.gid[i];
+    unsafeAtomicAdd(&a.ggain[gk], gain);
+    atomicAdd(&a.gmoved[gk], 1ull);
+}
+
+// 2m of vertex i's graph (the level's 2m unless it holds a batch).
+__device__ __forceinline__ double m2_of(const MoveArgs &a, int i) { return a.g.M2g ? a.g.M2g[a.g.gid[i]] : a.M2; }
+
 // Decision from the group's best candidate; identical on every lane.
-__device__ __forceinline__ bool decide(const MoveArgs &a, int i, int d, double ki, double kid, double bg, int bc,
-                                       double *gain) {
+__device__ __forceinline__ bool decide(const MoveArgs &a, double m2, int i, int d, double ki, double kid, double bg,
+                                       int bc, double *gain) {
     if (bc == kIntMax) return false;
-    double gstay = a.M2 * kid - ki * (a.sig[d] - ki);
+    double gstay = m2 * kid - ki * (a.sig[d] - ki);
     if (!(bg > gstay)) return false;
     if (a.csize[d] == 1 && a.csize[bc] == 1 && bc > d) return false;
     *gain = bg - gstay;
@@ -79,8 +89,8 @@ __device__ __forceinline__ bool decide(const MoveArgs &a, int i, int d, double k
 // History of a scan (for the learned gate's features) and, if sampled, a
 // trace row with the features the vertex had before this scan and whether
 // it moves.  Called by one lane per decided vertex; no-op unless enabled.
-__device__ __forceinline__ void record_scan(const MoveArgs &a, int i, int d, int di, double ki, double kid, double bg,
-                                        int bc, bool mv) {
+__device__ __forceinline__ void record_scan(const MoveArgs &a, double m2, int i, int d, int di, double ki, double kid,
+                                           double bg, int bc, bool mv) {
     uint8_t hb = a.hbits[i];
     float hf = a.hfrac[i], hg = a.hgain[i];
     if (a.tr.x && trace_keep(a.tr.seed, a.pass, a.sweep, i, a.tr.thr)) {
@@ -100,8 +110,8 @@ __device__ __forceinline__ void record_scan(const MoveArgs &a, int i, int d, int
     float nf = 0.0f, ng = 0.0f;
     if (ki > 0.0) {
         nf = (float)(kid / ki);
-        double gstay = a.M2 * kid - ki * (a.sig[d] - ki);
-        double r = bc != kIntMax ? (bg - gstay) / (a.M2 * ki) : -1.0;
+        double gstay = m2 * kid - ki * (a.sig[d] - ki);
+        double r = bc != kIntMax ? (bg - gstay) / (m2 * ki) : -1.0;
         if (r > 1.0) r = 1.0;
         if (r < -1.0) r = -1.0;
         ng = (float)r;
@@ -109,6 +119,11 @@ __device__ __forceinline__ void record_scan(const MoveArgs &a, int i, int d, int
     a.hfrac[i] = nf;
     a.hgain[i] = ng;
     a.hbits[i] = kHistScanned | (mv ? kHistMoved : 0);
+    // D_i starts again at a scan.  Movers of this sub-round may be adding to
+    // it right now; taking away exactly the value the features saw (which is
+    // all D_i held before this sub-round's moves) leaves just their adds, in
+    // any order, as the sums are exact.
+    if (a.dsnap[i] != 0.0) unsafeAtomicAdd(&a.dmoved[i], -a.dsnap[i]);
 }
 
 // A mover's entry (i, j), j != i: j is unprocessed again and, with the
@@ -119,12 +134,12 @@ __device__ __forceinline__ void mark_neighbour(const MoveArgs &a, int j, double 
 }
 
 // Folds the entry (key, v) of a scan table into (bg, bc, kid).
-__device__ __forceinline__ void fold_key(const MoveArgs &a, int key, double v, int d, double ki, double &bg, int &bc,
-                                         double &kid) {
+__device__ __forceinline__ void fold_key(const MoveArgs &a, double m2, int key, double v, int d, double ki, double &bg,
+                                         int &bc, double &kid) {
     if (key == d) {
         kid = v;
     } else {
-        double g = a.M2 * v - ki * a.sig[key];
+        double g = m2 * v - ki * a.sig[key];
         if (better(g, key, bg, bc)) {
             bg = g;
             bc = key;
@@ -133,8 +148,8 @@ __device__ __forceinline__ void fold_key(const MoveArgs &a, int key, double v, i
 }
 
 // Reads one table slot, resets it and folds it into (bg, bc, kid).
-__device__ __forceinline__ void take_slot(const MoveArgs &a, int *keys, double *vals, int64_t s, int d, double ki,
-                                          double &bg, int &bc, double &kid, unsigned long long &nkeys) {
+__device__ __forceinline__ void take_slot(const MoveArgs &a, double m2, int *keys, double *vals, int64_t s, int d,
+                                          double ki, double &bg, int &bc, double &kid, unsigned long long &nkeys) {
     int key = keys[s];
     if (key == kEmpty) return;
     double v = vals[s];
@@ -144,7 +159,7 @@ __device__ __forceinline__ void take_slot(const MoveArgs &a, int *keys, double *
     if (key == d) {
         kid = v;
     } else {
-        double g = a.M2 * v - ki * a.sig[key];
+        double g = m2 * v - ki * a.sig[key];
         if (better(g, key, bg, bc)) {
             bg = g;
             bc = key;
@@ -177,14 +192,11 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
             b = 0;
             while (t >= pre[b + 1]) b++;
             i = bl[a.qbase[b] + (t - pre[b])];
-            bool act = a.flag[i] != 0;
+            bool act = a.flag[i] != 0 && (!a.gactive || a.gactive[a.g.gid[i]]);
             if (b == BIN_HUB) a.hub_act[i] = act ? 1 : 0;
             if (act) {
                 a.flag[i] = 0;
-                if (a.dmoved) {   // the features take D_i; it starts again now
-                    a.dsnap[i] = a.dmoved[i];
-                    a.dmoved[i] = 0.0;
-                }
+                if (a.dmoved) a.dsnap[i] = a.dmoved[i];   // the features' D_i
                 rank = atomicAdd(&lcnt[b], 1);
             }
         }
@@ -238,9 +250,10 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     int *keys = wkeys + grp * kSlots;
     double *vals = wvals + grp * kSlots;
     int i = -1, di = 0, d = -1, j = -1;
-    double ki = 0.0, w = 0.0;
+    double ki = 0.0, w = 0.0, m2 = a.M2;
     if (valid) {
         i = a.queue[a.qbase[bin] + qi];
+        m2 = m2_of(a, i);
         di = a.g.deg[i];
         d = a.cm[i];
         ki = a.K[i];
@@ -255,19 +268,24 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     double bg = -INFINITY, kid = 0.0;
     int bc = kIntMax;
     if (valid) {
-        take_slot(a, keys, vals, gl, d, ki, bg, bc, kid, acc.keys);
-        take_slot(a, keys, vals, gl + G, d, ki, bg, bc, kid, acc.keys);
+        take_slot(a, m2, keys, vals, gl, d, ki, bg, bc, kid, acc.keys);
+        take_slot(a, m2, keys, vals, gl + G, d, ki, bg, bc, kid, acc.keys);
     }
     group_argmax_rt(bg, bc, G);
     kid = group_sum_rt(kid, G);
     double gain = 0.0;
-    bool mv = valid && decide(a, i, d, ki, kid, bg, bc, &gain);
+    bool mv = valid && decide(a, m2, i, d, ki, kid, bg, bc, &gain);
     if (mv && j >= 0 && j != i) mark_neighbour(a, j, w);
     bool lead = valid && gl == 0;
+    if (a.ggain) {   // batch: per-graph totals, one atomic per graph met by the wavefront
+        int gk = valid ? a.g.gid[i] : 0;
+        wave_add_f64_by_key(a.ggain, gk, gain, lead && mv);
+        wave_add_u64_by_key(a.gmoved, gk, 1ull, lead && mv);
+    }
     if (lead) {
         acc.verts++;
         acc.scanned += (unsigned long long)di;
-        if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
+        if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
         a.dec[i] = mv ? bc : d;
         if (mv) {
             acc.gain += gain;
@@ -349,6 +367,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
     Acc acc;
     for (int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + w; qi < cnt; qi += nw) {
         int i = a.queue[a.qbase[BIN_WAVE] + qi];
+        const double m2 = m2_of(a, i);
         int di = a.g.deg[i];
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
@@ -362,11 +381,11 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         wave_lds_sync();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int s = lane; s < T; s += kWave) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        for (int s = lane; s < T; s += kWave) take_slot(a, m2, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
         group_argmax<kWave>(bg, bc);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
-        bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
+        bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (mv)
             for (int e = lane; e < di; e += kWave) {
                 int j = load_col(a.g.col, beg + e);
@@ -375,11 +394,12 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         if (lane == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
-            if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
+            if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;
                 acc.moved++;
+                if (a.ggain) graph_totals(a, i, gain);
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
@@ -403,6 +423,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
     Acc acc;
     for (int64_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
         int i = a.queue[a.qbase[BIN_BLOCK] + qi];
+        const double m2 = m2_of(a, i);
         int di = a.g.deg[i];
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
@@ -416,10 +437,10 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         __syncthreads();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int s = tid; s < T; s += kBlock) take_slot(a, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        for (int s = tid; s < T; s += kBlock) take_slot(a, m2, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
         block_argmax_sum(bg, bc, kid);
         double gain = 0.0;
-        bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
+        bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (mv)
             for (int e = tid; e < di; e += kBlock) {
                 int j = load_col(a.g.col, beg + e);
@@ -428,11 +449,12 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         if (tid == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
-            if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
+            if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;
                 acc.moved++;
+                if (a.ggain) graph_totals(a, i, gain);
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
@@ -527,6 +549,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
         int64_t s0 = sidx * seg, s1 = s0 + seg < T ? s0 + seg : T;
         int d = a.cm[i];
         double ki = a.K[i];
+        const double m2 = m2_of(a, i);
         int64_t tb = a.hub_off[i];
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
@@ -553,7 +576,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < 4; u++)
-                if (key[u] != kEmpty) fold_key(a, key[u], v[u], d, ki, bg, bc, kid);
+                if (key[u] != kEmpty) fold_key(a, m2, key[u], v[u], d, ki, bg, bc, kid);
         }
         block_argmax_sum(bg, bc, kid);
         if (threadIdx.x == 0) {
@@ -574,6 +597,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
     Acc acc;
     for (int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + w; qi < cnt; qi += nw) {
         int i = a.queue[a.qbase[BIN_HUB] + qi];
+        const double m2 = m2_of(a, i);
         int di = a.g.deg[i];
         int d = a.cm[i];
         double ki = a.K[i];
@@ -590,15 +614,16 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         group_argmax<kWave>(bg, bc);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
-        bool mv = decide(a, i, d, ki, kid, bg, bc, &gain);
+        bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (lane == 0) {
             acc.verts++;
             a.hub_act[i] = mv ? 2 : 0;   // 2: its neighbours are marked chunk by chunk in apply
-            if (a.hbits) record_scan(a, i, d, di, ki, kid, bg, bc, mv);
+            if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
                 acc.gain += gain;
                 acc.moved++;
+                if (a.ggain) graph_totals(a, i, gain);
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }

@@ -244,6 +244,9 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
     if (n > 0) k_fill<float><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
 }
+void launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n > 0) k_fill<unsigned long long><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
+}
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
     if (n > 0) k_fill<int64_t><<<grid_for(n, kBlock * 4, 8192), kBlock, 0, s>>>(p, v, n);
 }

@@ -1,0 +1,129 @@
+"""Batches of independent graphs on the GPU against the oracle run on each
+graph alone (through the C ABI).
+
+Bar: every graph's membership bit-identical to the oracle's synchronous
+result for that graph alone (gsp_run's contract), its modularity within
+1e-9, and its pass count equal; the batch result equals gsp_run on each
+graph; zero internally-disconnected communities.
+"""
+import numpy as np
+import pytest
+
+import gsp_inputs as gi
+import oracle
+import paper_2402_11454_amd as gsp
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_count():
+    try:
+        import torch
+        return torch.cuda.device_count()
+    except Exception:
+        return 0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if _gpu_count() == 0:
+        pytest.skip("no GPU")
+    c = gsp.Context(0)
+    yield c
+    c.close()
+
+
+def _mixed_batch():
+    gs = [
+        gi.planted_sbm_10k(),
+        gi.rmat_small(11, 3),
+        gi.from_edges(1, []),                                   # one isolated vertex
+        gi.from_edges(5, []),                                   # no edges
+        gi.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)]),
+        gi.sbm(3000, 20, 0.05, 0.001, 4),
+        gi.rmat_small(12, 9),
+        gi.from_edges(2, [(0, 1)]),
+    ]
+    gs += gi.batch_sbm(12, master_seed=11, scale=0.02)
+    return gs
+
+
+def _check_batch(ctx, gs, **kw):
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10, **kw)
+    q = ctx.batch_modularity()
+    passes = ctx.batch_passes()
+    split = {"split_mode": kw.get("split_mode", 0)}
+    for k, g in enumerate(gs):
+        m = ctx.batch_membership(k)
+        ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, **split)
+        assert np.array_equal(m, ref.membership), f"graph {k} ({g.name}, n={g.n})"
+        assert abs(q[k] - ref.modularity) <= 1e-9, (k, q[k], ref.modularity)
+        assert passes[k] == ref.passes, (k, passes[k], ref.passes)
+    return q
+
+
+def test_mixed_batch_matches_each_graph_alone(ctx):
+    _check_batch(ctx, _mixed_batch())
+
+
+@pytest.mark.parametrize("split_mode", [1, 2])
+def test_batch_split_modes(ctx, split_mode):
+    _check_batch(ctx, _mixed_batch()[:10], split_mode=split_mode)
+
+
+def test_weighted_batch(ctx):
+    gs = [gi.dcsbm_small(3000, s) for s in range(3)] + [gi.rmat_small(10, 4, weights=(1.0, 4.0))]
+    gs.append(gi.sbm(800, 8, 0.1, 0.005, 2))          # unit weights inside a weighted batch
+    _check_batch(ctx, gs)
+
+
+def test_batch_equals_single_runs(ctx):
+    gs = _mixed_batch()[:9]
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10)
+    got = [ctx.batch_membership(k) for k in range(len(gs))]
+    q = ctx.batch_modularity()
+    for k, g in enumerate(gs):
+        ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+        res = ctx.louvain(1e-2, 10)
+        assert np.array_equal(got[k], res.membership)
+        assert abs(q[k] - res.modularity) <= 1e-12
+        assert ctx.count_disconnected(res.membership) == 0
+
+
+def test_batch_of_shaped_sbms(ctx):
+    """The uneven-size SBM batch law (n log-uniform, degree and mixing
+    uniform), shrunk tenfold: 48 graphs, every seventh checked against the
+    oracle, all checked for connected communities."""
+    gs = gi.batch_sbm(48, master_seed=4, scale=0.1)
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10)
+    q = ctx.batch_modularity()
+    for k in range(0, len(gs), 7):
+        ref = oracle.louvain(gs[k], tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+        assert np.array_equal(ctx.batch_membership(k), ref.membership), k
+        assert abs(q[k] - ref.modularity) <= 1e-9
+    for k, g in enumerate(gs):
+        cnt, _ = oracle.disconnected(g, ctx.batch_membership(k))
+        assert cnt == 0
+
+
+def test_batch_errors(ctx):
+    with pytest.raises(gsp.GspError):
+        ctx.load_batch([gi.from_edges(3, [(0, 1)]), gi.Graph(n=0, offsets=np.zeros(1, np.int64),
+                                                              cols=np.zeros(0, np.int32))])
+    g = gi.from_edges(3, [(0, 1)])
+    bad = gi.Graph(n=3, offsets=g.offsets.copy(), cols=np.array([1, 5], np.int32))
+    with pytest.raises(gsp.GspError):
+        ctx.load_batch([g, bad])
+    ctx.load_batch([g, gi.from_edges(4, [(1, 2)])])
+    with pytest.raises(gsp.GspError):
+        ctx.run_batch(prune_mode=gsp.PRUNE_LEARNED)
+    c = gsp.Context(0)
+    try:
+        c.load_graph(g)
+        with pytest.raises(gsp.GspError):
+            c.run_batch()                                   # no batch loaded
+    finally:
+        c.close()

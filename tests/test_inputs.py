@@ -80,3 +80,20 @@ def test_dcsbm_shape():
 def test_dcsbm_seeds_differ():
     a, b = gi.dcsbm_small(4000, 0), gi.dcsbm_small(4000, 1)
     assert a.nnz != b.nnz or not np.array_equal(a.cols, b.cols)
+
+
+def test_batch_sbm_shape():
+    """The batch law at a tenth of its size: n >= 100, degree and mixing of
+    each graph close to its parameters, deterministic."""
+    ps = gi.batch_sbm_params(40, master_seed=4)
+    gs = gi.batch_sbm(40, master_seed=4, scale=0.1)
+    for p, g in zip(ps, gs):
+        _check_csr(g)
+        assert g.n == max(100, int(round(p["n"] * 0.1)))
+        if g.n >= 2000:
+            assert abs(g.nnz / g.n - p["degree"]) < 0.15 * p["degree"] + 1
+            rows = np.repeat(np.arange(g.n), g.degrees())
+            inter = (g.block[rows] != g.block[g.cols]).mean()
+            assert abs(inter - p["mixing"]) < 0.06
+    gs2 = gi.batch_sbm(40, master_seed=4, scale=0.1)
+    assert all(np.array_equal(a.cols, b.cols) for a, b in zip(gs, gs2))
