@@ -68,6 +68,7 @@ typedef struct gsp_options {
     uint64_t mem_limit_bytes;      /* refuse device allocations beyond this total (0 = no limit) */
     int32_t prune_mode;            /* GSP_PRUNE_PLAIN (default) or GSP_PRUNE_LEARNED (network set by gsp_pruner_set) */
     float prune_threshold;         /* learned gate: scan a vertex iff p = sigmoid(z) >= this (default 0.5) */
+    int32_t use_graphs;            /* 1 (default): replay each pass's plain sweeps from a captured HIP graph */
 } gsp_options;
 
 /* Vertex pruning of the local-moving phase (prune_mode). */

@@ -73,6 +73,18 @@ struct gsp_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t cap_stream = nullptr;   // where sweeps are captured into graphs
+    // instantiated sweep graphs, reused while the level and its work lists
+    // (everything a sweep's launches take as arguments) are the same
+    struct SweepGraph {
+        std::vector<int64_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<SweepGraph> sweep_graphs;
+    void drop_sweep_graphs() {
+        for (auto &x : sweep_graphs) (void)hipGraphExecDestroy(x.exec);
+        sweep_graphs.clear();
+    }
     std::string err;
     std::vector<void *> allocs;
     uint64_t mem_used = 0;
@@ -186,6 +198,7 @@ struct gsp_ctx {
     }
     void free_graph() {
         if (stream) (void)hipStreamSynchronize(stream);
+        drop_sweep_graphs();
         for (void *p : allocs) (void)hipFree(p);
         allocs.clear();
         mem_used = 0;
@@ -343,6 +356,7 @@ struct PhaseCfg {
     int max_iter = 20;
     bool timing_k = false;
     bool gated = false;            // learned gate in front of the scan
+    bool use_graphs = false;       // replay plain sweeps from a captured graph
     float theta_logit = 0.0f;      // scan iff logit >= theta_logit
     int pass = 0;                  // pass index (a feature, and trace rows)
     double *dq_out = nullptr;      // per counted iteration (max_iter entries)
@@ -426,24 +440,14 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         gg.resize(G);
         gm.resize(G);
     }
-    for (int sweep = 0;; sweep++) {
+    // One sweep: clear its counters (a fill kernel, so that the sweep can be
+    // captured), then every sub-round's kernels, on stream cs.
+    auto enqueue_sweep = [&](int sweep, IterCounters *ctr, hipStream_t cs) {
+        launch_fill_u64(reinterpret_cast<unsigned long long *>(ctr), 0, sizeof(IterCounters) / 8, cs);
         if (batch) {
-            bool any = false;
-            for (int64_t k = 0; k < G && !any; k++) any = act[k] != 0;
-            if (!any) break;
-            HIP_TRY(hipMemcpyAsync(ctx->gactive, act.data(), G, hipMemcpyHostToDevice, s));
-            launch_fill_f64(ctx->ggain, 0.0, G, s);
-            launch_fill_u64(ctx->gmoved, 0, G, s);
-        } else if (li >= cfg.max_iter) {
-            break;
+            launch_fill_f64(ctx->ggain, 0.0, G, cs);
+            launch_fill_u64(ctx->gmoved, 0, G, cs);
         }
-        cfg.sweeps++;
-        if (mode == CONFIRM) {
-            launch_fill_u8(ctx->flag, 1, g.n, s);
-            cfg.confirm_sweeps++;
-        }
-        IterCounters *ctr = ctx->ctr + (sweep & 1);
-        HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(IterCounters), s));
         for (int p = 0; p < P; p++) {
             MoveArgs a;
             a.g = g;
@@ -494,33 +498,33 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 a.gactive = ctx->gactive;
             }
             if (cap == 0) continue;
-            const bool tk = cfg.timing_k;
+            const bool tk = cfg.timing_k && cs == s;
             int t;
             t = tk ? ctx->timer.begin(100 + GSP_K_FRONTIER) : -1;
-            launch_move_compact(a, wl, s);
+            launch_move_compact(a, wl, cs);
             ctx->timer.end(t);
             if (mode == GATED) {
                 t = tk ? ctx->timer.begin(100 + GSP_K_GATE) : -1;
-                launch_gate(a, net, cfg.theta_logit, cap, s);
+                launch_gate(a, net, cfg.theta_logit, cap, cs);
                 ctx->timer.end(t);
             }
             t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL) : -1;
-            launch_move_small(a, wl, s);
+            launch_move_small(a, wl, cs);
             ctx->timer.end(t);
             t = tk && a.qcap[BIN_WAVE] ? ctx->timer.begin(100 + GSP_K_MOVE_WAVE) : -1;
-            launch_move_wave(a, s);
+            launch_move_wave(a, cs);
             ctx->timer.end(t);
             t = tk && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK) : -1;
-            launch_move_block(a, s);
+            launch_move_block(a, cs);
             ctx->timer.end(t);
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
-            launch_move_hub_scan(a, s);
+            launch_move_hub_scan(a, cs);
             ctx->timer.end(t);
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
-            launch_move_hub_finish(a, s);
+            launch_move_hub_finish(a, cs);
             ctx->timer.end(t);
             t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
-            launch_move_apply(a, cap, s);
+            launch_move_apply(a, cap, cs);
             ctx->timer.end(t);
             if (tk) {
                 ctx->kernel_launches[GSP_K_FRONTIER]++;
@@ -533,6 +537,58 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 ctx->kernel_launches[GSP_K_MOVE_HUB_FINISH] += 2 * (a.qcap[BIN_HUB] > 0);
                 ctx->kernel_launches[GSP_K_MOVE_APPLY]++;
             }
+        }
+    };
+    // Plain sweeps repeat the same launches with the same arguments within a
+    // phase: capture them once as a graph and replay it (timing and the
+    // gate's state change per sweep, so those run launch by launch).
+    const bool capture = cfg.use_graphs && !hist && !cfg.timing_k;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> key;
+    if (capture) {
+        if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        auto ptr = [](const void *q) { return (int64_t)(intptr_t)q; };
+        key = {g.n, g.nnz, g.wt, g.graphs, ptr(g.off), ptr(g.col), ptr(g.w), ptr(g.deg), ptr(g.gid), ptr(g.vbase),
+               ptr(K), P, ptr(wl.bl), ptr(wl.ch_vert), ptr(wl.ch_beg), ptr(wl.hub_off), ptr(ctx->sc.hkeys),
+               ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), (int64_t)(batch ? 1 : 0)};
+        for (int k = 0; k <= kNumBins * P; k++) key.push_back(wl.boff[k]);
+        for (int p = 0; p <= P; p++) key.push_back(wl.ch_poff[p]);
+        int64_t m2bits;
+        memcpy(&m2bits, &ctx->M2, sizeof(m2bits));
+        key.push_back(m2bits);
+        for (auto &x : ctx->sweep_graphs)
+            if (x.key == key) exec = x.exec;
+    }
+    for (int sweep = 0;; sweep++) {
+        if (batch) {
+            bool any = false;
+            for (int64_t k = 0; k < G && !any; k++) any = act[k] != 0;
+            if (!any) break;
+            HIP_TRY(hipMemcpyAsync(ctx->gactive, act.data(), G, hipMemcpyHostToDevice, s));
+        } else if (li >= cfg.max_iter) {
+            break;
+        }
+        cfg.sweeps++;
+        if (mode == CONFIRM) {
+            launch_fill_u8(ctx->flag, 1, g.n, s);
+            cfg.confirm_sweeps++;
+        }
+        IterCounters *ctr = capture ? ctx->ctr : ctx->ctr + (sweep & 1);
+        if (capture) {
+            if (!exec) {
+                HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+                enqueue_sweep(sweep, ctr, ctx->cap_stream);
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return ctx->fail_hip(e, "sweep graph capture");
+                if (ctx->sweep_graphs.size() >= 64) ctx->drop_sweep_graphs();
+                ctx->sweep_graphs.push_back({key, exec});
+            }
+            HIP_TRY(hipGraphLaunch(exec, s));
+        } else {
+            enqueue_sweep(sweep, ctr, s);
         }
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
@@ -813,6 +869,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->mem_limit_bytes = 0;
     out->prune_mode = GSP_PRUNE_PLAIN;
     out->prune_threshold = 0.5f;
+    out->use_graphs = 1;
     return GSP_OK;
 }
 
@@ -856,6 +913,8 @@ gsp_status gsp_destroy(gsp_ctx *ctx) {
     if (ctx->i64_h) (void)hipHostFree(ctx->i64_h);
     if (ctx->f64_h) (void)hipHostFree(ctx->f64_h);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    ctx->drop_sweep_graphs();
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return GSP_OK;
 }
@@ -959,6 +1018,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
         pc.theta_logit = theta_logit(opt.prune_threshold);
         pc.pass = lp;
+        pc.use_graphs = opt.use_graphs != 0;
         pc.kernel_bytes = kbytes;
         if (batch) pc.gdone = gdone.data();
         st = move_phase(ctx, g, K, wl, pc);
@@ -1410,6 +1470,7 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
     pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
     pc.theta_logit = theta_logit(opt.prune_threshold);
     pc.pass = pass_index;
+    pc.use_graphs = opt.use_graphs != 0;
     pc.dq_out = dq.data();
     pc.moved_out = mv.data();
     st = move_phase(ctx, g, ctx->K0, wl, pc);
