@@ -1,18 +1,22 @@
 """Benchmark: full GSP-Louvain runs on one MI355X.
 
 Workload: R-MAT scale 20 (2^20 vertices, 16 samples per vertex, a/b/c/d =
-.57/.19/.19/.05, symmetrised, deduplicated, no self-loops, unit weights),
-the graph the headline metric is quoted on.  The graph is generated (seeded),
-loaded once into the library's device memory, then `warmup` untimed runs and
-`steps` timed runs of gsp_run (tolerance 1e-2, at most 10 passes) follow.
+.57/.19/.19/.05, symmetrised, deduplicated, no self-loops, unit weights).
+The graph is generated (seeded) and loaded once into the library's device
+memory; `warmup` untimed runs and `steps` timed runs of gsp_run (tolerance
+1e-2, at most 10 passes) follow.
 
-Prints ONE JSON line: edges/s = directed CSR entries / seconds per run, the
-per-run time, a roofline object for the dominant kernel (algorithmic bytes
-from the library's counters over its HIP-event time in the timed region)
-and a CPU baseline: the sequential oracle timed on one host core on the same
+Prints ONE JSON line: edges/s = directed CSR entries / seconds per run of the
+plain method; a roofline object for the dominant single-kernel class (its
+algorithmic bytes from the library's counters over its HIP-event time,
+events recorded around that class only, inside the timed region); the
+learned-pruned method on the same graph (its edges/s, modularity and ratio
+to plain, the network trained on the degree-corrected SBM workload); and a
+CPU baseline: the sequential oracle timed on one host core on the same
 graph.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,17 +27,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edges/s per full GSP-Louvain run; learned-pruned vs plain at equal modularity"
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {  # kernel class -> its kernel (as rocprof names it)
+# single-kernel classes (the roofline names one kernel) -> the kernel
+KERNEL_NAMES = {
     "move_small": "k_move_small",
     "move_wave": "k_move_wave",
     "move_block": "k_move_block",
     "move_hub": "k_move_hub_insert",
-    "move_hub_finish": "k_move_hub_part + k_move_hub_final",
     "move_apply": "k_move_apply",
     "frontier": "k_move_compact",
-    "split": "k_split_hook + k_split_compress",
-    "aggregate": "aggregation kernels",
+    "gate": "k_gate",
 }
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def parse():
@@ -45,9 +49,50 @@ def parse():
     p.add_argument("--seed", type=int, default=20)
     p.add_argument("--tolerance", type=float, default=1e-2)
     p.add_argument("--max-passes", type=int, default=10)
+    p.add_argument("--theta", type=float, default=0.5, help="learned gate threshold on p")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--timing", type=int, default=2, help="0 none, 1 phases, 2 phases+kernels")
+    p.add_argument("--no-learned", action="store_true")
+    p.add_argument("--timing", type=int, default=2, help="0: no per-kernel events (no roofline)")
     return p.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2402_11454_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def timed_runs(ctx, gsp, a, steps, **kw):
+    kstats = {k: dict(launches=0, ms=0.0, bytes=0.0, items=0) for k in gsp.KERNEL_CLASSES}
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.run(a.tolerance, a.max_passes, **kw)
+        st = ctx.stats()
+        for name, v in st["kernels"].items():
+            for f in ("launches", "ms", "bytes", "items"):
+                kstats[name][f] += v[f]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, kstats
 
 
 def main():
@@ -70,52 +115,63 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = gsp.Context(0, stream=stream)
     ctx.load_graph(g)
-    opt = gsp.default_options(timing=a.timing)
     for w in range(a.warmup):
-        ctx.run(a.tolerance, a.max_passes, options=opt)
-        print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
+        ctx.run(a.tolerance, a.max_passes)
+    print(f"[bench] {a.warmup} warm-up runs done", file=sys.stderr, flush=True)
 
-    # timed region: `steps` whole runs, the graph already resident in HBM
-    kstats = {k: dict(launches=0, ms=0.0, bytes=0.0, items=0) for k in gsp.KERNEL_CLASSES}
-    phase = dict(ms_move=0.0, ms_split=0.0, ms_aggregate=0.0, ms_other=0.0)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(a.steps):
-        ctx.run(a.tolerance, a.max_passes, options=opt)
-        st = ctx.stats()
-        for name, v in st["kernels"].items():
-            for f in ("launches", "ms", "bytes", "items"):
-                kstats[name][f] += v[f]
-        for f in phase:
-            phase[f] += st[f]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    # which single-kernel class dominates (one probe run, every class timed)
+    dom = None
+    if a.timing >= 2:
+        ctx.run(a.tolerance, a.max_passes, timing=2)
+        st = ctx.stats()["kernels"]
+        cand = {k: v["ms"] for k, v in st.items() if k in KERNEL_NAMES and v["ms"] > 0}
+        dom = max(cand, key=cand.get) if cand else None
+    mask = (1 << gsp.KERNEL_CLASSES.index(dom)) if dom else 0
+
+    # timed region: `steps` whole runs of the plain method, graph resident in HBM
+    elapsed, kstats = timed_runs(ctx, gsp, a, a.steps, timing=2 if dom else 0, timing_mask=mask)
     ms_per_step = 1000.0 * elapsed / a.steps
     value = g.nnz / (elapsed / a.steps)
-
     memb = ctx.membership()
     q = ctx.result_modularity()
     disc = ctx.count_disconnected(memb)
     st = ctx.stats()
-    print(f"[bench] {a.steps} runs: {ms_per_step:.3f} ms/run, Q={q:.6f}, disconnected={disc}, "
-          f"passes={st['passes']} iterations={st['iterations']} communities={st['communities']}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] plain: {a.steps} runs, {ms_per_step:.3f} ms/run, Q={q:.6f}, disconnected={disc}, "
+          f"passes={st['passes']} iterations={st['iterations']}", file=sys.stderr, flush=True)
 
     roofline = None
-    if a.timing >= 2:
-        cand = {k: v for k, v in kstats.items() if v["ms"] > 0 and v["bytes"] > 0}
-        if cand:
-            dom = max(cand, key=lambda k: cand[k]["ms"])
-            v = cand[dom]
-            achieved = v["bytes"] / (v["ms"] * 1e-3) / 1e9
-            roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "kernel": KERNEL_NAMES.get(dom, dom), "kernel_class": dom,
-                        "launches": v["launches"], "avg_launch_us": round(1000.0 * v["ms"] / max(v["launches"], 1), 3),
-                        "bytes_per_launch": round(v["bytes"] / max(v["launches"], 1), 1)}
-        print("[bench] kernel classes over the timed region: " +
-              ", ".join(f"{k}={v['ms']:.2f}ms/{v['launches']}" for k, v in kstats.items()), file=sys.stderr,
-              flush=True)
+    if dom:
+        v = kstats[dom]
+        achieved = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        kern = KERNEL_NAMES[dom]
+        per_launch = v["bytes"] / max(v["launches"], 1)
+        tb = measured_traffic(kern)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
+                    "kernel": kern, "kernel_class": dom, "launches": v["launches"],
+                    "avg_launch_us": round(1000.0 * v["ms"] / max(v["launches"], 1), 3),
+                    "bytes_per_launch": round(per_launch, 1)}
+
+    learned = None
+    if not a.no_learned:
+        from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, load_params
+        if os.path.exists(DEFAULT_OUT):
+            ctx.pruner_set(load_params(DEFAULT_OUT))
+            kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=a.theta)
+            for _ in range(a.warmup):
+                ctx.run(a.tolerance, a.max_passes, **kw)
+            el, _ = timed_runs(ctx, gsp, a, a.steps, **kw)
+            ql = ctx.result_modularity()
+            dl = ctx.count_disconnected(ctx.membership())
+            sl = ctx.stats()
+            learned = {"value": round(g.nnz / (el / a.steps), 1), "ms_per_step": round(1000.0 * el / a.steps, 4),
+                       "vs_plain": round((g.nnz / (el / a.steps)) / value, 4), "modularity": round(ql, 6),
+                       "modularity_minus_plain": round(ql - q, 6), "disconnected": dl, "theta": a.theta,
+                       "scanned_entries": sl["scanned_entries"], "plain_scanned_entries": st["scanned_entries"],
+                       "pruned": sl["pruned"], "iterations": sl["iterations"],
+                       "network": "8-64-64-1, trained on degree-corrected SBM traces (seeds 0-31)"}
+            print(f"[bench] learned: {learned['ms_per_step']:.3f} ms/run, Q={ql:.6f}, ratio {learned['vs_plain']}",
+                  file=sys.stderr, flush=True)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -134,11 +190,10 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"rmat{a.scale}: R-MAT scale {a.scale}, 16 samples/vertex, a/b/c/d .57/.19/.19/.05, "
-                               f"symmetrised, dedup, unit weights; plain GSP-Louvain tol {a.tolerance}, "
-                               f"<= {a.max_passes} passes, 8 sub-rounds",
+                               f"symmetrised, dedup, unit weights; GSP-Louvain tol {a.tolerance}, "
+                               f"<= {a.max_passes} passes, 8 sub-rounds; value = plain method",
                    "n": g.n, "nnz": g.nnz, "modularity": round(q, 6), "disconnected": disc,
-                   "passes": st["passes"], "prune": "plain",
-                   "phase_ms_per_run": {k: round(v / a.steps, 3) for k, v in phase.items()}},
+                   "passes": st["passes"], "prune": "plain", "learned": learned},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

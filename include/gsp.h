@@ -69,6 +69,7 @@ typedef struct gsp_options {
     int32_t prune_mode;            /* GSP_PRUNE_PLAIN (default) or GSP_PRUNE_LEARNED (network set by gsp_pruner_set) */
     float prune_threshold;         /* learned gate: scan a vertex iff p = sigmoid(z) >= this (default 0.5) */
     int32_t use_graphs;            /* 1 (default): replay each pass's plain sweeps from a captured HIP graph */
+    uint32_t timing_mask;          /* timing = 2: bit k times kernel class k only (0 = every class) */
 } gsp_options;
 
 /* Vertex pruning of the local-moving phase (prune_mode). */

@@ -42,7 +42,9 @@ struct Timer {
         used = 0;
         open.clear();
     }
+    uint32_t kmask = 0;   // kernel classes (100 + k) to time; 0 = all
     int begin(int cls) {
+        if (cls >= 100 && kmask && !((kmask >> (cls - 100)) & 1u)) return -1;
         hipEvent_t a = get(), b = get();
         if (!a || !b) return -1;
         (void)hipEventRecord(a, s);
@@ -870,6 +872,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->prune_mode = GSP_PRUNE_PLAIN;
     out->prune_threshold = 0.5f;
     out->use_graphs = 1;
+    out->timing_mask = 0;
     return GSP_OK;
 }
 
@@ -978,6 +981,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     ctx->have_q = false;
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->timer.reset();
+    ctx->timer.kmask = opt.timing_mask;
     bool tphase = opt.timing >= 1, tk = opt.timing >= 2;
     double kbytes[GSP_K_COUNT] = {0};
     for (int k = 0; k < GSP_K_COUNT; k++) ctx->kernel_launches[k] = 0;
