@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--scale", type=int, default=20)
     p.add_argument("--seed", type=int, default=20)
+    p.add_argument("--weights", default="", help="lo,hi: symmetric fp32 weights U[lo,hi) (e.g. 1,10 at scale 26)")
     p.add_argument("--tolerance", type=float, default=1e-2)
     p.add_argument("--max-passes", type=int, default=10)
     p.add_argument("--theta", type=float, default=0.5, help="learned gate threshold on p")
@@ -108,7 +109,9 @@ def main():
     import paper_2402_11454_amd as gsp
 
     t0 = time.time()
-    g = gi.rmat(a.scale, 16, *gi.RMAT_ABC, a.seed, name=f"rmat-{a.scale}")
+    wts = tuple(float(x) for x in a.weights.split(",")) if a.weights else None
+    gi.set_verbose(a.scale > 22)
+    g = gi.rmat(a.scale, 16, *gi.RMAT_ABC, a.seed, weights=wts, name=f"rmat-{a.scale}")
     print(f"[bench] generated R-MAT scale {a.scale}: n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
     torch.cuda.init()
@@ -190,7 +193,8 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"rmat{a.scale}: R-MAT scale {a.scale}, 16 samples/vertex, a/b/c/d .57/.19/.19/.05, "
-                               f"symmetrised, dedup, unit weights; GSP-Louvain tol {a.tolerance}, "
+                               f"symmetrised, dedup, {'weights U' + str(wts) if wts else 'unit weights'}; "
+                               f"GSP-Louvain tol {a.tolerance}, "
                                f"<= {a.max_passes} passes, 8 sub-rounds; value = plain method",
                    "n": g.n, "nnz": g.nnz, "modularity": round(q, 6), "disconnected": disc,
                    "passes": st["passes"], "prune": "plain", "learned": learned},

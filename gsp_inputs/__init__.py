@@ -64,6 +64,7 @@ def _load():
     lib.gen_has_blocks.argtypes = [vp]
     lib.gen_copy.argtypes = [vp, vp, vp, vp, vp]
     lib.gen_uniform.argtypes = [u64, i64, vp]
+    lib.gen_set_verbose.argtypes = [i32]
     _lib = lib
     return lib
 
@@ -183,6 +184,11 @@ def with_self_loops(g: Graph, loops: dict) -> Graph:
     col = np.concatenate([np.asarray(c, dtype=np.int32) for c, _ in rows]) if off[-1] else np.zeros(0, np.int32)
     w = np.concatenate([np.asarray(x, dtype=np.float32) for _, x in rows]) if off[-1] else np.zeros(0, np.float32)
     return Graph(n=g.n, offsets=off, cols=col, weights=w, block=g.block, name=g.name + "+loops")
+
+
+def set_verbose(on: bool) -> None:
+    """Progress lines on stderr from the generators (for long generations)."""
+    _load().gen_set_verbose(int(on))
 
 
 def uniform(seed: int, count: int) -> np.ndarray:

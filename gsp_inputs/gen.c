@@ -38,6 +38,16 @@ typedef struct gen_graph {
     int64_t *block; /* planted block of each vertex (after relabelling), or NULL */
 } gen_graph;
 
+/* Progress lines on stderr for long generations (gen_set_verbose). */
+#include <stdio.h>
+static int gen_verbose = 0;
+void gen_set_verbose(int v) { gen_verbose = v; }
+static void progress(const char *what, int64_t count) {
+    if (!gen_verbose) return;
+    fprintf(stderr, "[gen] %s: %lld\n", what, (long long)count);
+    fflush(stderr);
+}
+
 /* ---------------- PRNGs ---------------- */
 
 static inline uint64_t splitmix64_next(uint64_t *x) {
@@ -136,6 +146,7 @@ static gen_graph *build_csr(int64_t n, int64_t m, const int32_t *eu, const int32
     }
     for (int64_t i = 0; i < n; i++) cnt[i + 1] += cnt[i];
     int64_t raw = cnt[n];
+    progress("csr: entries counted", raw);
     int32_t *col = (int32_t *)malloc((size_t)(raw > 0 ? raw : 1) * sizeof(int32_t));
     int64_t *cur = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     if (!col || !cur) { free(cnt); free(col); free(cur); free(g); return NULL; }
@@ -147,6 +158,7 @@ static gen_graph *build_csr(int64_t n, int64_t m, const int32_t *eu, const int32
         col[cur[b]++] = a;
     }
     free(cur);
+    progress("csr: entries placed", raw);
     /* sort + dedupe each row in place; new lengths in deg[] */
     int64_t *deg = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     if (!deg) { free(cnt); free(col); free(g); return NULL; }
@@ -170,6 +182,7 @@ static gen_graph *build_csr(int64_t n, int64_t m, const int32_t *eu, const int32
     free(cnt);
     free(deg);
     g->nnz = off[n];
+    progress("csr: rows sorted, duplicates dropped", g->nnz);
     int32_t *shrunk = (int32_t *)realloc(col, (size_t)(g->nnz > 0 ? g->nnz : 1) * sizeof(int32_t));
     g->col = shrunk ? shrunk : col;
     g->off = off;
@@ -314,18 +327,21 @@ gen_graph *gen_rmat(int scale, int64_t samples, double a, double b, double c, ui
             ev[e] = (int32_t)v;
         }
     }
+    progress("rmat: samples drawn", samples);
     if (permute) {
         int32_t *perm = random_perm(n, seed);
         if (!perm) { free(eu); free(ev); return NULL; }
 #pragma omp parallel for schedule(static)
         for (int64_t e = 0; e < samples; e++) { eu[e] = perm[eu[e]]; ev[e] = perm[ev[e]]; }
         free(perm);
+        progress("rmat: vertices relabelled", n);
     }
     gen_graph *g = build_csr(n, samples, eu, ev);
     free(eu);
     free(ev);
     if (!g) return NULL;
     if (weighted && attach_weights(g, seed, wlo, whi)) return NULL;
+    if (weighted) progress("weights attached", g->nnz);
     return g;
 }
 
@@ -544,6 +560,7 @@ gen_graph *gen_dcsbm(int64_t n, double deg_alpha, int64_t kmin, int64_t kmax, do
     free(perm);
     free(comm);
     if (weighted && attach_weights(g, seed, wlo, whi)) return NULL;
+    if (weighted) progress("weights attached", g->nnz);
     return g;
 }
 

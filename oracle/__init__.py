@@ -76,6 +76,7 @@ def _load():
         "orc_aggregate": (i64, [i64, vp, vp, vp, vp, i64, vp, vp, vp, i64]),
         "orc_disconnected": (i64, [i64, vp, vp, vp, vp]),
         "orc_louvain": (i32, [i64, vp, vp, vp, ctypes.POINTER(_Options), vp, ctypes.POINTER(_Stats)]),
+        "orc_decide_row": (i32, [i64, i64, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]),
         "orc_bf16": (ctypes.c_float, [ctypes.c_float]),
         "orc_plog2": (dbl, [dbl]),
         "orc_gate_features": (None, [i64, dbl, dbl, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, dbl, i32, i32,
@@ -194,6 +195,18 @@ def move_sync(g, memb=None, tau: float = 0.0, max_iter: int = 20, rounds: int = 
     if li < 0:
         raise ValueError("orc_move_sync failed")
     return m, li, dq[:li], mv[:li]
+
+
+def decide_row(i, cols, weights, memb, sigma, csize, ki, M2):
+    """Synchronous decision of vertex i from its row alone: (community,
+    gain numerator, [best, second, stay] scores)."""
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    gain = ctypes.c_double()
+    sc = np.empty(3, dtype=np.float64)
+    d = _load().orc_decide_row(int(i), c.shape[0], _p(c), _p(w), _p(memb), _p(sigma), _p(csize), float(ki),
+                               float(M2), ctypes.byref(gain), _p(sc))
+    return int(d), gain.value, sc
 
 
 def split_bfs(g, memb) -> np.ndarray:

@@ -272,6 +272,56 @@ int64_t orc_move_sync_step(int64_t n, const int64_t *off, const int32_t *col, co
     return moved;
 }
 
+/* The synchronous decision of one vertex from its row alone (the rule of
+ * orc_move_sync_step): cols/w are the row of vertex i (deg entries, w NULL
+ * for unit weights), memb/sigma/csize the snapshot.  Writes G(best) -
+ * G(stay) to *gain (0 if it stays) and, for margin checks, the two best
+ * candidate scores and G(stay) to scores[0..2] (-inf where absent).
+ * Returns the chosen community. */
+int32_t orc_decide_row(int64_t i, int64_t deg, const int32_t *cols, const double *w, const int32_t *memb,
+                       const double *sigma, const int32_t *csize, double ki, double M2, double *gain,
+                       double *scores) {
+    int32_t d = memb[i];
+    /* K_{i->c} over the row's distinct communities (a short list: rows are scanned once) */
+    int32_t *keys = (int32_t *)malloc((size_t)(deg > 0 ? deg : 1) * sizeof(int32_t));
+    double *vals = (double *)malloc((size_t)(deg > 0 ? deg : 1) * sizeof(double));
+    int64_t nk = 0;
+    for (int64_t e = 0; e < deg; e++) {
+        if (cols[e] == i) continue;
+        int32_t c = memb[cols[e]];
+        int64_t k = 0;
+        while (k < nk && keys[k] != c) k++;
+        if (k == nk) { keys[nk] = c; vals[nk] = 0.0; nk++; }
+        vals[k] += w ? w[e] : 1.0;
+    }
+    double kid = 0.0;
+    for (int64_t k = 0; k < nk; k++)
+        if (keys[k] == d) kid = vals[k];
+    double g_stay = M2 * kid - ki * (sigma[d] - ki);
+    int32_t best = -1;
+    double g_best = -INFINITY, g_second = -INFINITY;
+    for (int64_t k = 0; k < nk; k++) {
+        int32_t c = keys[k];
+        if (c == d) continue;
+        double g = M2 * vals[k] - ki * sigma[c];
+        if (best < 0 || g > g_best || (g == g_best && c < best)) {
+            if (best >= 0) g_second = g_best > g_second ? g_best : g_second;
+            best = c;
+            g_best = g;
+        } else if (g > g_second) {
+            g_second = g;
+        }
+    }
+    free(keys);
+    free(vals);
+    if (scores) { scores[0] = g_best; scores[1] = g_second; scores[2] = g_stay; }
+    *gain = 0.0;
+    if (best < 0 || !(g_best > g_stay)) return d;
+    if (csize[d] == 1 && csize[best] == 1 && best > d) return d;
+    *gain = g_best - g_stay;
+    return best;
+}
+
 /* Group of a vertex for the ordered sub-rounds of the synchronous phase:
  * the top log2(rounds) bits of the 64-bit product i * 0x9E3779B97F4A7C15
  * (Fibonacci hashing); rounds is a power of two. */

@@ -51,6 +51,13 @@ int64_t orc_move_sync_step(int64_t n, const int64_t *off, const int32_t *col, co
                            const double *K, const int32_t *memb, const double *sigma, const int32_t *csize,
                            const uint8_t *active, int32_t *dec, double *gain);
 
+/* The synchronous decision of vertex i from its row alone (rule of
+ * orc_move_sync_step); scores[3] (may be NULL) receives the best and second
+ * candidate scores and G(stay).  Returns the chosen community. */
+int32_t orc_decide_row(int64_t i, int64_t deg, const int32_t *cols, const double *w, const int32_t *memb,
+                       const double *sigma, const int32_t *csize, double ki, double M2, double *gain,
+                       double *scores);
+
 /* Synchronous local-moving phase in `rounds` ordered sub-rounds (a power of
  * two, 1..64): vertex i belongs to sub-round (i * 0x9E3779B97F4A7C15) >> (64 -
  * log2 rounds).  Each sub-round is one snapshot step over the unprocessed

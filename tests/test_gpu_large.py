@@ -1,0 +1,112 @@
+"""The large case on the GPU: R-MAT scale 26 (2^26 vertices, 2^30 samples,
+weights U[1,10], about 2e9 directed entries, int64 offsets).
+
+The oracle cannot run a whole pass at this size, so the checks are:
+  * one synchronous step from a non-trivial membership: the decisions of
+    4,096 sampled vertices equal the oracle's decision from each vertex's
+    row alone, wherever the decision is not within 1e-9 (relative) of a tie
+    (2m is a sum of 2e9 inexact fp64 terms, so its last bits depend on the
+    summation order);
+  * a whole run: modularity equal (1e-9 relative) to Eq. 1 recomputed with
+    numpy on the host from the returned membership; no internally
+    disconnected community; the split of the result is the result.
+
+Needs about 40 GB of host memory and 150 GB of device memory; runs only
+with GSP_LARGE=1 (a few minutes, most of it generating the graph).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import gsp_inputs as gi
+import oracle
+import paper_2402_11454_amd as gsp
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("GSP_LARGE") != "1",
+                                 reason="R-MAT scale 26 needs GSP_LARGE=1 (40 GB host, minutes)")]
+
+
+@pytest.fixture(scope="module")
+def big():
+    gi.set_verbose(True)
+    g = gi.rmat(26, 16, *gi.RMAT_ABC, 26, weights=(1.0, 10.0), name="rmat-26")
+    gi.set_verbose(False)
+    print(f"[large] R-MAT 26: n={g.n} nnz={g.nnz}", flush=True)
+    c = gsp.Context(0)
+    c.load(g.offsets, g.cols, g.weights, n=g.n)
+    yield g, c
+    c.close()
+
+
+def _exact_k_and_m2(g):
+    """K_i and 2m exactly: fp32 weights in [1, 10) are integer multiples of
+    2^-23, so integer sums (in chunks of rows) are exact; K_i (< 2^53 units)
+    and 2m convert to fp64 with one rounding."""
+    K_units = np.empty(g.n, dtype=np.int64)
+    step = 1 << 22
+    for r0 in range(0, g.n, step):
+        r1 = min(g.n, r0 + step)
+        s, e = int(g.offsets[r0]), int(g.offsets[r1])
+        u = (g.weights[s:e].astype(np.float64) * 2.0 ** 23).astype(np.int64)
+        cs = np.concatenate([[0], np.cumsum(u)])
+        K_units[r0:r1] = cs[g.offsets[r0 + 1:r1 + 1] - s] - cs[g.offsets[r0:r1] - s]
+    K = K_units.astype(np.float64) / 2.0 ** 23
+    M2 = float(int(K_units.sum())) / 2.0 ** 23
+    return K, M2, K_units
+
+
+def test_sampled_step_decisions(big):
+    g, ctx = big
+    assert g.nnz > 2 ** 30 and g.offsets.dtype == np.int64
+    memb = (np.arange(g.n, dtype=np.int64) // 4).astype(np.int32)
+    dec, gain, moved = ctx.step_move(memb)
+    K, M2, K_units = _exact_k_and_m2(g)
+    sig_units = np.bincount(memb, weights=K_units.astype(np.float64), minlength=g.n)
+    sigma = sig_units / 2.0 ** 23
+    csize = np.bincount(memb, minlength=g.n).astype(np.int32)
+    picks = np.unique((gi.uniform(261, 4096) * g.n).astype(np.int64))
+    w = g.weights
+    checked = 0
+    for i in picks:
+        s, e = g.offsets[i], g.offsets[i + 1]
+        d, gn, sc = oracle.decide_row(i, g.cols[s:e], w[s:e].astype(np.float64), memb, sigma, csize, K[i], M2)
+        scale = max(abs(sc[0]), abs(sc[2]), 1.0)
+        near = (np.isfinite(sc[1]) and abs(sc[0] - sc[1]) <= 1e-9 * scale) or abs(sc[0] - sc[2]) <= 1e-9 * scale
+        if near:
+            continue
+        assert dec[i] == d, (int(i), int(dec[i]), d, sc)
+        checked += 1
+    assert checked > 3000 and moved > 0
+
+
+def test_whole_run_properties(big):
+    g, ctx = big
+    res = ctx.louvain(tolerance=1e-2, max_passes=10)
+    m = res.membership
+    assert m.min() >= 0 and m.max() < g.n
+    assert ctx.count_disconnected(m) == 0
+    lab = ctx.step_split(m)
+    # the split of the result leaves it whole: every vertex's split label is
+    # the smallest vertex of its community (communities are numbered by
+    # ascending smallest vertex, so the first occurrence of c is that vertex)
+    cs, first = np.unique(m, return_index=True)
+    assert np.array_equal(cs, np.arange(cs.shape[0]))
+    assert np.array_equal(lab, first[m].astype(np.int32))
+    # Eq. 1 on the host: Q = sum_c [sigma_c / 2m - (Sigma_c / 2m)^2], by rows in chunks
+    K, M2, _ = _exact_k_and_m2(g)
+    inside = 0.0
+    step = 1 << 22
+    for r0 in range(0, g.n, step):
+        r1 = min(g.n, r0 + step)
+        s, e = g.offsets[r0], g.offsets[r1]
+        rows = np.repeat(np.arange(r0, r1, dtype=np.int64), np.diff(g.offsets[r0:r1 + 1]))
+        same = m[rows] == m[g.cols[s:e]]
+        inside += float(g.weights[s:e][same].astype(np.float64).sum())
+    Sig = np.bincount(m, weights=K, minlength=g.n)
+    q = inside / M2 - float(np.sum((Sig / M2) ** 2))
+    assert abs(res.modularity - q) <= 1e-9 * max(1.0, abs(q))
+    assert res.modularity > 0.05
+    print(f"[large] passes={res.stats['passes']} iterations={res.stats['iterations']} Q={res.modularity:.6f}",
+          flush=True)

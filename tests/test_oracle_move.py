@@ -206,3 +206,19 @@ def test_clique_collapses_to_one_community():
     g = gi.from_edges(6, clique_edges(6))
     for m in (oracle.move_sync(g, tau=0.0)[0], oracle.move_async(g, tau=0.0)[0]):
         assert len(set(m.tolist())) == 1
+
+
+def test_decide_row_equals_the_step():
+    """The per-row decision (used for sampled checks on graphs too large for
+    a whole step) equals the whole synchronous step vertex by vertex."""
+    g = gi.rmat_small(11, 4, weights=(1.0, 10.0))
+    m = gi.random_membership(g.n, 300, 3)
+    dec, gain, _ = oracle.move_sync_step(g, m)
+    K, M2 = oracle.vertex_weights(g)
+    sigma = np.bincount(m, weights=K, minlength=g.n)
+    csize = np.bincount(m, minlength=g.n).astype(np.int32)
+    w = g.weights_f64()
+    for i in range(0, g.n, 3):
+        s, e = g.offsets[i], g.offsets[i + 1]
+        d, gn, sc = oracle.decide_row(i, g.cols[s:e], w[s:e], m, sigma, csize, K[i], M2)
+        assert d == dec[i] and gn == gain[i]
