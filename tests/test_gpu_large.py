@@ -72,8 +72,10 @@ def test_sampled_step_decisions(big):
     for i in picks:
         s, e = g.offsets[i], g.offsets[i + 1]
         d, gn, sc = oracle.decide_row(i, g.cols[s:e], w[s:e].astype(np.float64), memb, sigma, csize, K[i], M2)
-        scale = max(abs(sc[0]), abs(sc[2]), 1.0)
-        near = (np.isfinite(sc[1]) and abs(sc[0] - sc[1]) <= 1e-9 * scale) or abs(sc[0] - sc[2]) <= 1e-9 * scale
+        fin = [abs(x) for x in sc if np.isfinite(x)]
+        scale = max(fin + [1.0])
+        near = np.isfinite(sc[0]) and ((np.isfinite(sc[1]) and abs(sc[0] - sc[1]) <= 1e-9 * scale)
+                                       or abs(sc[0] - sc[2]) <= 1e-9 * scale)
         if near:
             continue
         assert dec[i] == d, (int(i), int(dec[i]), d, sc)
