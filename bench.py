@@ -67,15 +67,16 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+    if it was taken on this workload and the current kernel sources (else
+    None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash():
+    if t.get("source_hash") != source_hash() or t.get("workload") != workload:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -148,7 +149,7 @@ def main():
         achieved = v["bytes"] / (v["ms"] * 1e-3) / 1e9
         kern = KERNEL_NAMES[dom]
         per_launch = v["bytes"] / max(v["launches"], 1)
-        tb = measured_traffic(kern)
+        tb = measured_traffic(kern, f"rmat{a.scale}" + (f"-w{a.weights}" if a.weights else ""))
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
                     "kernel": kern, "kernel_class": dom, "launches": v["launches"],

@@ -94,7 +94,7 @@ def summarize(fetch_db, write_db, cmd):
             kernels[k] = {"dispatches": n, "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
                           "bytes_per_launch": round(b, 1)}
         rows.append((short(name), n, f_kib, w_kib, b))
-    out = {"source_hash": source_hash(), "command": cmd, "copy_kernel": short(copy),
+    out = {"source_hash": source_hash(), "workload": "rmat20", "command": cmd, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
     with open(os.path.join(prof, "traffic.json"), "w") as f:
