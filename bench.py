@@ -32,7 +32,8 @@ KERNEL_NAMES = {
     "move_small": "k_move_small",
     "move_wave": "k_move_wave",
     "move_block": "k_move_block",
-    "move_hub": "k_move_hub_insert",
+    "move_hub": "k_hub_bucket",
+    "move_hub_gather": "k_hub_gather",
     "move_apply": "k_move_apply",
     "frontier": "k_move_compact",
     "gate": "k_gate",

@@ -70,6 +70,8 @@ typedef struct gsp_options {
     float prune_threshold;         /* learned gate: scan a vertex iff p = sigmoid(z) >= this (default 0.5) */
     int32_t use_graphs;            /* 1 (default): replay each pass's plain sweeps from a captured HIP graph */
     uint32_t timing_mask;          /* timing = 2: bit k times kernel class k only (0 = every class) */
+    int32_t hub_global;            /* 1: score every hub through global hash tables (default 0: LDS hash
+                                      partitions, global tables only for hubs that do not fit them) */
 } gsp_options;
 
 /* Vertex pruning of the local-moving phase (prune_mode). */
@@ -80,13 +82,15 @@ enum {
     GSP_K_MOVE_SMALL = 0,  /* local-move scan+decide, degree <= 64 (lane groups) */
     GSP_K_MOVE_WAVE,       /* local-move scan+decide, 64 < degree <= 512 (a wavefront per vertex) */
     GSP_K_MOVE_BLOCK,      /* local-move scan+decide, 512 < degree <= 2048 (a workgroup per vertex) */
-    GSP_K_MOVE_HUB,        /* local-move scan of hubs (degree > 2048): chunks into global tables */
-    GSP_K_MOVE_HUB_FINISH, /* hub decisions: table slices scored, then combined */
+    GSP_K_MOVE_HUB,        /* local-move scan of hubs (degree > 2048): each chunk reduced in LDS and its
+                              pairs staged by hash partition (or inserted into global tables) */
+    GSP_K_MOVE_HUB_FINISH, /* hub decisions: partial results combined (and the global-table path) */
     GSP_K_MOVE_APPLY,      /* apply moves, community totals */
     GSP_K_FRONTIER,        /* sub-round queue compaction */
     GSP_K_SPLIT,           /* split: union-find hooking and compression */
     GSP_K_AGGREGATE,       /* aggregation kernels */
     GSP_K_GATE,            /* learned gate: features and the network (bf16 matrix cores) */
+    GSP_K_MOVE_HUB_GATHER, /* hub partitions: each partition's pairs merged in LDS and scored */
     GSP_K_COUNT
 };
 

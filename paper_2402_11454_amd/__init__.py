@@ -25,7 +25,7 @@ HOST, DEVICE = 0, 1
 SPLIT_PASS, SPLIT_LAST, SPLIT_NONE = 0, 1, 2
 MAX_PASSES_STATS = 64
 KERNEL_CLASSES = ("move_small", "move_wave", "move_block", "move_hub", "move_hub_finish", "move_apply", "frontier",
-                  "split", "aggregate", "gate")
+                  "split", "aggregate", "gate", "move_hub_gather")
 PRUNE_PLAIN, PRUNE_LEARNED = 0, 1
 GATE_PARAMS = 4801  # (8*64 + 64) + (64*64 + 64) + (64 + 1)
 
@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("split_mode", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("mem_limit_bytes", ctypes.c_uint64), ("prune_mode", ctypes.c_int32),
                 ("prune_threshold", ctypes.c_float), ("use_graphs", ctypes.c_int32),
-                ("timing_mask", ctypes.c_uint32)]
+                ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

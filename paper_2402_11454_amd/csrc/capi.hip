@@ -76,6 +76,7 @@ struct gsp_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;   // where sweeps are captured into graphs
+    bool hub_parts = true;              // hubs by hash partitions (else global tables only); per run
     // instantiated sweep graphs, reused while the level and its work lists
     // (everything a sweep's launches take as arguments) are the same
     struct SweepGraph {
@@ -118,7 +119,7 @@ struct gsp_ctx {
     int32_t *lab = nullptr, *top = nullptr, *bl = nullptr, *tmp32 = nullptr;
     uint8_t *flag = nullptr, *hub_act = nullptr;
     int32_t *hub_ch0 = nullptr;
-    int64_t *hub_off = nullptr;
+    int64_t *hub_off = nullptr, *hub_b0 = nullptr;
     double *gain_tmp = nullptr;
     Scratch sc;
     IterCounters *ctr = nullptr;      // device, 2 slots
@@ -206,6 +207,7 @@ struct gsp_ctx {
         mem_used = 0;
         if (sc.hkeys) (void)hipFree(sc.hkeys);
         if (sc.hvals) (void)hipFree(sc.hvals);
+        if (sc.hbuck) (void)hipFree(sc.hbuck);
         sc = Scratch();
         for (int k = 0; k < 2; k++) {
             offL[k] = nullptr;
@@ -261,6 +263,20 @@ hipError_t ensure_hub_tables(Scratch &sc, uint64_t slots, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t ensure_hub_buckets(Scratch &sc, uint64_t words, hipStream_t s) {
+    if (words <= sc.hbcap) return hipSuccess;
+    uint64_t cap = std::max<uint64_t>(words, sc.hbcap + sc.hbcap / 2);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (sc.hbuck) (void)hipFree(sc.hbuck);
+    sc.hbuck = nullptr;
+    sc.hbcap = 0;
+    e = hipMalloc(&sc.hbuck, cap * sizeof(uint32_t));
+    if (e != hipSuccess) return e;
+    sc.hbcap = cap;
+    return hipSuccess;
+}
+
 }  // namespace gsp
 
 #define HIP_TRY(expr)                                         \
@@ -288,6 +304,7 @@ WorkLists make_lists(gsp_ctx *ctx) {
     wl.bl = ctx->bl;
     wl.hub_off = ctx->hub_off;
     wl.hub_ch0 = ctx->hub_ch0;
+    wl.hub_b0 = ctx->hub_b0;
     return wl;
 }
 
@@ -334,23 +351,32 @@ gsp_status renumber(gsp_ctx *ctx, const int32_t *labels, int64_t n, int32_t *out
     return GSP_OK;
 }
 
-// Algorithmic bytes of the local-moving kernels, per kernel class.
+// Algorithmic bytes of the local-moving kernels, per counter class.
 //  scan+decide (small, wave, block): per vertex decided 36 B (offset, degree,
 //    membership, K, Sigma and size of its community, decision); per entry
 //    4 B column + 4 B neighbour membership + the weight (0 / 4 / 8 B); per
 //    distinct neighbour community 8 B (its Sigma);
-//  hub scan: per entry as above; per (chunk, community) insert into a global
-//    table 12 B (key compare-and-swap, value add);
-//  hub finish: per distinct community 20 B (key, value, Sigma); per hub 36 B.
+//  hub chunk scan: per entry as above; per staged (chunk, community) pair or
+//    global-table insert 12 B (key, value); per partition word 4 B;
+//  hub gather: per staged pair read 12 B, per partition word 4 B, per
+//    distinct community scored 8 B (its Sigma), per chunk 20 B partial out;
+//  hub decisions: per global-table slot scored 20 B (key, value, Sigma);
+//    per chunk partial read 20 B; per hub 36 B.
 double move_bytes(int cls, const CounterStripe &h, int wt) {
     int ws = wt == W_UNIT ? 0 : (wt == W_F32 ? 4 : 8);
     double v = (double)h.verts[cls], e = (double)h.scanned[cls], k = (double)h.keys[cls];
+    double gi = (double)h.ginserts[cls], ax = (double)h.aux[cls];
     switch (cls) {
-        case 3: return (8.0 + ws) * e + 12.0 * (double)h.ginserts;
-        case 4: return 20.0 * k + 36.0 * v;
+        case 3: return (8.0 + ws) * e + 12.0 * gi + 4.0 * ax;
+        case 4: return 20.0 * k + 20.0 * ax + 36.0 * v;
+        case 5: return 12.0 * gi + 4.0 * ax + 8.0 * k + 20.0 * v;
         default: return 36.0 * v + (8.0 + ws) * e + 8.0 * k;
     }
 }
+
+// the kernel class each counter class is timed under
+constexpr int kClassKernel[kMoveClasses] = {GSP_K_MOVE_SMALL, GSP_K_MOVE_WAVE, GSP_K_MOVE_BLOCK,
+                                            GSP_K_MOVE_HUB, GSP_K_MOVE_HUB_FINISH, GSP_K_MOVE_HUB_GATHER};
 
 // What one local-moving phase runs and what it reports.
 struct PhaseCfg {
@@ -482,6 +508,11 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.part_g = ctx->sc.part_g;
             a.part_kid = ctx->sc.part_kid;
             a.part_c = ctx->sc.part_c;
+            a.hub_parts = ctx->hub_parts && ctx->gap_col;
+            a.skey = ctx->gap_col;
+            a.sval = ctx->gap_w;
+            a.hbuck = ctx->sc.hbuck;
+            a.hub_b0 = wl.hub_b0;
             if (hist) {
                 a.hfrac = ctx->hfrac;
                 a.hgain = ctx->hgain;
@@ -519,10 +550,19 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             t = tk && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK) : -1;
             launch_move_block(a, cs);
             ctx->timer.end(t);
+            // one timed class per kernel on the partition path: chunk scan,
+            // gather; the finish class holds the global-table kernels (they
+            // return at once unless a hub overflowed) and the decisions
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
-            launch_move_hub_scan(a, cs);
+            if (a.hub_parts) launch_move_hub_parts(a, cs); else launch_move_hub_scan(a, cs);
             ctx->timer.end(t);
+            if (a.hub_parts) {
+                t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_GATHER) : -1;
+                launch_move_hub_gather(a, cs);
+                ctx->timer.end(t);
+            }
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
+            if (a.hub_parts) launch_move_hub_scan(a, cs);
             launch_move_hub_finish(a, cs);
             ctx->timer.end(t);
             t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
@@ -536,7 +576,8 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 ctx->kernel_launches[GSP_K_MOVE_WAVE] += a.qcap[BIN_WAVE] > 0;
                 ctx->kernel_launches[GSP_K_MOVE_BLOCK] += a.qcap[BIN_BLOCK] > 0;
                 ctx->kernel_launches[GSP_K_MOVE_HUB] += a.qcap[BIN_HUB] > 0;
-                ctx->kernel_launches[GSP_K_MOVE_HUB_FINISH] += 2 * (a.qcap[BIN_HUB] > 0);
+                ctx->kernel_launches[GSP_K_MOVE_HUB_GATHER] += a.hub_parts && a.qcap[BIN_HUB] > 0;
+                ctx->kernel_launches[GSP_K_MOVE_HUB_FINISH] += (2 + a.hub_parts) * (a.qcap[BIN_HUB] > 0);
                 ctx->kernel_launches[GSP_K_MOVE_APPLY]++;
             }
         }
@@ -605,12 +646,13 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             const CounterStripe &x = ctx->ctr_h->st[q];
             h.gain += x.gain;   // exact on integer weights, in any order
             h.moved += x.moved;
-            h.ginserts += x.ginserts;
             h.pruned += x.pruned;
             for (int c = 0; c < kMoveClasses; c++) {
                 h.verts[c] += x.verts[c];
                 h.scanned[c] += x.scanned[c];
                 h.keys[c] += x.keys[c];
+                h.ginserts[c] += x.ginserts[c];
+                h.aux[c] += x.aux[c];
             }
         }
         double dq = ctx->M2 > 0.0 ? (2.0 * h.gain) / (ctx->M2 * ctx->M2) : 0.0;
@@ -618,9 +660,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         cfg.pruned += (int64_t)h.pruned;
         for (int c = 0; c < kMoveClasses; c++) {
             cfg.scanned_entries += (int64_t)h.scanned[c];
-            cfg.scanned_vertices += (int64_t)h.verts[c];   // hubs: counted once, by the finish kernel
-            ctx->stats.kernels[GSP_K_MOVE_SMALL + c].items += (int64_t)h.scanned[c];
-            if (cfg.kernel_bytes) cfg.kernel_bytes[GSP_K_MOVE_SMALL + c] += move_bytes(c, h, g.wt);
+            // hubs are counted once, by the decision kernel (class 5 counts chunks)
+            if (c != 5) cfg.scanned_vertices += (int64_t)h.verts[c];
+            ctx->stats.kernels[kClassKernel[c]].items += (int64_t)(c == 5 ? h.ginserts[c] : h.scanned[c]);
+            if (cfg.kernel_bytes) cfg.kernel_bytes[kClassKernel[c]] += move_bytes(c, h, g.wt);
         }
         if (mode == GATED && cfg.kernel_bytes) {
             // per candidate: vertex id, degree, K, membership, Sigma, history
@@ -738,6 +781,7 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(ctx->hub_act, n, "hipMalloc(hub flags)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_off, n, "hipMalloc(hub offsets)")) != GSP_OK) return st;
     if ((st = A(ctx->hub_ch0, n, "hipMalloc(hub chunk ids)")) != GSP_OK) return st;
+    if ((st = A(ctx->hub_b0, n, "hipMalloc(hub partition offsets)")) != GSP_OK) return st;
     if ((st = A(ctx->gain_tmp, n, "hipMalloc(gains)")) != GSP_OK) return st;
     Scratch &sc = ctx->sc;
     sc.n_cap = n;
@@ -746,8 +790,9 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     char *stmp = nullptr;
     if ((st = A(stmp, sc.scan_tmp_bytes, "hipMalloc(scan)")) != GSP_OK) return st;
     sc.scan_tmp = stmp;
-    for (int64_t **p : {&sc.i64a, &sc.i64b, &sc.i64c, &sc.i64d, &sc.i64e, &sc.i64f})
+    for (int64_t **p : {&sc.i64a, &sc.i64b, &sc.i64c, &sc.i64d, &sc.i64e, &sc.i64f, &sc.i64g})
         if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
+    if ((st = A(sc.u8a, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
     for (int32_t **p : {&sc.i32a, &sc.i32b, &sc.i32c, &sc.i32d, &sc.i32e, &sc.bl2})
         if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
     if ((st = A(sc.err, 4, "hipMalloc(err)")) != GSP_OK) return st;
@@ -873,6 +918,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->prune_threshold = 0.5f;
     out->use_graphs = 1;
     out->timing_mask = 0;
+    out->hub_global = 0;
     return GSP_OK;
 }
 
@@ -982,6 +1028,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     memset(&ctx->stats, 0, sizeof(ctx->stats));
     ctx->timer.reset();
     ctx->timer.kmask = opt.timing_mask;
+    ctx->hub_parts = opt.hub_global == 0;
     bool tphase = opt.timing >= 1, tk = opt.timing >= 2;
     double kbytes[GSP_K_COUNT] = {0};
     for (int k = 0; k < GSP_K_COUNT; k++) ctx->kernel_launches[k] = 0;
@@ -1089,7 +1136,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         int tk2 = tk ? ctx->timer.begin(100 + GSP_K_AGGREGATE) : -1;
         AggOut out{ctx->offL[next], ctx->colL[next], ctx->wL[next], ctx->KL[next], ctx->degL[next]};
         int64_t nnz2 = 0;
-        HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s));
+        HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s, ctx->hub_parts));
         ctx->timer.end(tk2);
         {
             // read every entry (column, weight, neighbour membership), write
@@ -1372,6 +1419,8 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     if (!ctx || !moved) return GSP_EINVAL;
     (void)hipSetDevice(ctx->device);
     if (!dec_out && ctx->n) return ctx->fail(GSP_EINVAL, "dec_out is NULL");
+    gsp_status st0 = ensure_levels(ctx);   // the hub staging lives in the aggregation buffers
+    if (st0 != GSP_OK) return st0;
     gsp_status st = take_membership(ctx, membership, where);
     if (st != GSP_OK) return st;
     hipStream_t s = ctx->stream;
@@ -1421,10 +1470,19 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     a.part_g = ctx->sc.part_g;
     a.part_kid = ctx->sc.part_kid;
     a.part_c = ctx->sc.part_c;
+    a.hub_parts = ctx->hub_parts && ctx->gap_col;
+    a.skey = ctx->gap_col;
+    a.sval = ctx->gap_w;
+    a.hbuck = ctx->sc.hbuck;
+    a.hub_b0 = wl.hub_b0;
     launch_move_compact(a, wl, s);
     launch_move_small(a, wl, s);
     launch_move_wave(a, s);
     launch_move_block(a, s);
+    if (a.hub_parts) {
+        launch_move_hub_parts(a, s);
+        launch_move_hub_gather(a, s);
+    }
     launch_move_hub_scan(a, s);
     launch_move_hub_finish(a, s);
     HIP_TRY(hipGetLastError());
@@ -1456,6 +1514,9 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
     if (st != GSP_OK) return st;
     if (!(tolerance >= 0.0) || pass_index < 0 || pass_index > 255)
         return ctx->fail(GSP_EINVAL, "bad tolerance or pass_index");
+    st = ensure_levels(ctx);   // the hub staging lives in the aggregation buffers
+    if (st != GSP_OK) return st;
+    ctx->hub_parts = opt.hub_global == 0;
     st = take_membership(ctx, membership_inout, where);
     if (st != GSP_OK) return st;
     hipStream_t s = ctx->stream;

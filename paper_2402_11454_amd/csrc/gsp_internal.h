@@ -48,6 +48,10 @@ struct WorkLists {
     int64_t *hub_off = nullptr;
     int32_t *hub_ch0 = nullptr;
     uint64_t hub_table_total = 0;
+    // hash partitions of hub i: as many as its chunks (P_i); chunk s of the
+    // hub leaves P_i packed (start, count) pairs at hub_b0[i] + s * P_i
+    int64_t *hub_b0 = nullptr;
+    uint64_t bucket_total = 0;
 
     int64_t bucket_begin(int b, int p) const { return boff[b * rounds + p]; }
     int64_t bucket_size(int b, int p) const { return boff[b * rounds + p + 1] - boff[b * rounds + p]; }
@@ -60,14 +64,17 @@ struct WorkLists {
 // block adds to stripe blockIdx % kStripes) so thousands of blocks do not
 // serialise on one address; the host sums the stripes.
 constexpr int kStripes = 16;
-constexpr int kMoveClasses = 5;
+// counter classes: 0-2 small / wave / block scan+decide, 3 hub chunk scan,
+// 4 hub decisions (and the global-table slices), 5 hub partition gather
+constexpr int kMoveClasses = 6;
 struct alignas(128) CounterStripe {
     double gain;                               // sum of gain numerators G(c*) - G(stay)
     unsigned long long moved;                  // movers
     unsigned long long verts[kMoveClasses];    // vertices decided
     unsigned long long scanned[kMoveClasses];  // CSR entries scanned
     unsigned long long keys[kMoveClasses];     // distinct neighbour communities scored
-    unsigned long long ginserts;               // hub scan: (chunk, community) inserts into global tables
+    unsigned long long ginserts[kMoveClasses]; // hub pairs: staged or inserted (3), read back (5)
+    unsigned long long aux[kMoveClasses];      // partition words written (3) / read (5); chunk partials (4)
     unsigned long long pruned;                 // vertices the learned gate kept from the scan
 };
 
@@ -75,6 +82,8 @@ struct alignas(128) CounterStripe {
 struct IterCounters {
     int qcnt[kMaxRounds][kNumBins];   // queued vertices per sub-round and bin
     int ccnt[kMaxRounds][kNumBins];   // gated sweeps: candidates before the gate
+    int hub_fallback;                 // some hub of this sweep needs the global-table path
+    int pad[31];
     CounterStripe st[kStripes];
 };
 
@@ -119,6 +128,15 @@ struct MoveArgs {
     const int32_t *hub_ch0;  // per hub vertex: its first chunk id
     double *part_g, *part_kid;  // per chunk: best score and K_{i->d} share
     int *part_c;             // per chunk: best community
+    // hubs by hash partitions (hub_parts): staging of each chunk's distinct
+    // (community, weight) pairs at the chunk's own entry positions, and the
+    // per (chunk, partition) packed start/count words; hub_act[i] = 3 marks
+    // a hub sent to the global-table path instead
+    bool hub_parts = false;
+    int32_t *skey = nullptr;
+    double *sval = nullptr;
+    uint32_t *hbuck = nullptr;
+    const int64_t *hub_b0 = nullptr;
     // learned gate and traces (hbits == nullptr: neither)
     float *hfrac = nullptr, *hgain = nullptr;   // history of the last scan in this pass
     uint8_t *hbits = nullptr;
@@ -183,6 +201,16 @@ void launch_move_wave(const MoveArgs &a, hipStream_t s);
 void launch_move_block(const MoveArgs &a, hipStream_t s);
 void launch_move_hub_scan(const MoveArgs &a, hipStream_t s);
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s);
+// Hubs by hash partitions: chunk -> LDS reduction -> pairs sorted by
+// partition (staging); partition -> LDS table over all chunks -> the
+// partition's best candidate and K_{i->d} share (part_* of the chunk with
+// the partition's index).  Hubs with more than kMaxParts chunks, or a
+// partition with more than kPartCap distinct communities, get hub_act = 3
+// and go through the global-table kernels.
+constexpr int kMaxParts = 4096;
+constexpr int kPartCap = 3072;
+void launch_move_hub_parts(const MoveArgs &a, hipStream_t s);    // phase 1: chunk reduce, staged pairs
+void launch_move_hub_gather(const MoveArgs &a, hipStream_t s);   // phase 2: partitions merged and scored
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
 
 // ---- k_gate.hip ----
@@ -246,8 +274,12 @@ struct AggOut {
 };
 // Aggregates g by cm (values in [0, n2)) into the compact CSR `out`.
 // gap_* are scratch of capacity nnz (gapped rows before compaction).
+// hub_parts: giant communities through LDS hash partitions (staging in
+// out.col / out.w before the compaction), global tables only for those that
+// do not fit; otherwise global tables for all.
 hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int64_t n2, AggOut out,
-                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s);
+                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
+                     bool hub_parts = true);
 
 // Device scratch owned by the context (sized at load).
 struct Scratch {
@@ -255,6 +287,8 @@ struct Scratch {
     void *scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
     int64_t *i64a = nullptr, *i64b = nullptr, *i64c = nullptr, *i64d = nullptr, *i64e = nullptr, *i64f = nullptr;
+    int64_t *i64g = nullptr;   // n_cap + 1
+    uint8_t *u8a = nullptr;    // n_cap + 1
     int32_t *i32a = nullptr, *i32b = nullptr, *i32c = nullptr, *i32d = nullptr, *i32e = nullptr;  // n_cap + 1
     int32_t *bl2 = nullptr;  // n_cap: community work lists
     int *err = nullptr;
@@ -264,6 +298,9 @@ struct Scratch {
     int *hkeys = nullptr;
     double *hvals = nullptr;
     uint64_t hcap = 0;
+    // hub partition words (grown on demand)
+    uint32_t *hbuck = nullptr;
+    uint64_t hbcap = 0;
     // chunk lists (sized for the input graph): vertex hubs of a level, hub
     // communities of an aggregation (entry chunks and table segments), and
     // per-chunk partial results of the hub decisions
@@ -279,5 +316,7 @@ struct Scratch {
 
 // Grows the hub-table pool of sc to at least `slots` (keys empty, values 0).
 hipError_t ensure_hub_tables(Scratch &sc, uint64_t slots, hipStream_t s);
+// Grows the hub partition words of sc to at least `words`.
+hipError_t ensure_hub_buckets(Scratch &sc, uint64_t words, hipStream_t s);
 
 }  // namespace gsp

@@ -585,8 +585,10 @@ __global__ void __launch_bounds__(kBlock) k_agg_copy(const int64_t *eoff, const 
 }  // namespace
 
 hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int64_t n2, AggOut out,
-                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s) {
+                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
+                     bool hub_parts) {
     (void)wl;
+    (void)hub_parts;
     int32_t *csz = sc.i32a, *ccur = sc.i32b, *members = sc.i32c, *cdeg = sc.i32d, *mdeg = sc.i32e;
     int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = sc.i64c, *mpre = sc.i64d, *ctab = sc.i64e, *tmp = sc.i64f;
     launch_fill_i32(csz, 0, n2, s);

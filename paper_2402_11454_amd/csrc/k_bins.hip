@@ -86,21 +86,24 @@ __global__ void __launch_bounds__(kBlock) k_bin_fill(const int32_t *deg, int64_t
 }
 
 __global__ void __launch_bounds__(kBlock) k_hub_sizes(const int32_t *bl, int64_t hb, int64_t H, const int32_t *deg,
-                                                     int64_t *tsize, int64_t *nch) {
+                                                     int64_t *tsize, int64_t *nch, int64_t *bsz) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
         int d = deg[bl[hb + k]];
         tsize[k] = (int64_t)hub_table_size(d);
-        nch[k] = (d + kHubChunk - 1) / kHubChunk;
+        int64_t c = (d + kHubChunk - 1) / kHubChunk;
+        nch[k] = c;
+        bsz[k] = c <= kMaxParts ? c * c : 0;   // partition words of the hub
     }
 }
 
 __global__ void __launch_bounds__(kBlock) k_hub_fill(const int32_t *bl, int64_t hb, int64_t H, const int32_t *deg,
                                                     const int64_t *off, const int64_t *toff, const int64_t *coff,
-                                                    int64_t *hub_off, int32_t *hub_ch0, int32_t *ch_vert,
-                                                    int64_t *ch_beg) {
+                                                    const int64_t *boff, int64_t *hub_off, int32_t *hub_ch0,
+                                                    int64_t *hub_b0, int32_t *ch_vert, int64_t *ch_beg) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
         int32_t i = bl[hb + k];
         hub_off[i] = toff[k];
+        hub_b0[i] = boff[k];
         hub_ch0[i] = (int32_t)coff[k];
         int64_t nc = coff[k + 1] - coff[k];
         for (int64_t c = 0; c < nc; c++) {
@@ -165,12 +168,15 @@ hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &
         unsigned gr = (unsigned)((H + kBlock - 1) / kBlock);
         if (gr > 4096) gr = 4096;
         // table sizes -> offsets
-        k_hub_sizes<<<gr, kBlock, 0, s>>>(wl.bl, hb, H, g.deg, sc.i64a, sc.i64c);
+        k_hub_sizes<<<gr, kBlock, 0, s>>>(wl.bl, hb, H, g.deg, sc.i64a, sc.i64c, sc.i64d);
         scan_exclusive_i64(sc.i64a, sc.i64b, H, sc.scan_tmp, s);   // i64b = table offsets
         scan_exclusive_i64(sc.i64c, sc.i64a, H, sc.scan_tmp, s);   // i64a = chunk offsets
+        scan_exclusive_i64(sc.i64d, sc.i64e, H, sc.scan_tmp, s);   // i64e = partition word offsets
         std::vector<int64_t> tmp(H + 1);
-        int64_t ttot = 0;
+        int64_t ttot = 0, btot = 0;
         e = hipMemcpyAsync(&ttot, sc.i64b + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(&btot, sc.i64e + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(tmp.data(), sc.i64a, sizeof(int64_t) * (H + 1), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
@@ -178,6 +184,7 @@ hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &
         if (e != hipSuccess) return e;
         wl.nchunks = tmp[H];
         wl.hub_table_total = (uint64_t)ttot;
+        wl.bucket_total = (uint64_t)btot;
         if (wl.nchunks > sc.ch_cap) return hipErrorInvalidValue;
         for (int p = 0; p <= rounds; p++) {
             int64_t pos = (p < rounds ? wl.bucket_begin(BIN_HUB, p) : wl.bin_begin(BIN_HUB) + H) - hb;
@@ -185,8 +192,10 @@ hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &
         }
         e = ensure_hub_tables(sc, wl.hub_table_total, s);
         if (e != hipSuccess) return e;
-        k_hub_fill<<<gr, kBlock, 0, s>>>(wl.bl, hb, H, g.deg, g.off, sc.i64b, sc.i64a, wl.hub_off, wl.hub_ch0,
-                                         sc.ch_vert, sc.ch_beg);
+        e = ensure_hub_buckets(sc, wl.bucket_total, s);
+        if (e != hipSuccess) return e;
+        k_hub_fill<<<gr, kBlock, 0, s>>>(wl.bl, hb, H, g.deg, g.off, sc.i64b, sc.i64a, sc.i64e, wl.hub_off,
+                                         wl.hub_ch0, wl.hub_b0, sc.ch_vert, sc.ch_beg);
     }
     wl.ch_vert = sc.ch_vert;
     wl.ch_beg = sc.ch_beg;

@@ -30,30 +30,31 @@ constexpr int kIntMax = 0x7fffffff;
 
 struct Acc {          // per-thread counters, reduced per block at the end
     double gain = 0.0;
-    unsigned long long moved = 0, verts = 0, scanned = 0, keys = 0, ginserts = 0;
+    unsigned long long moved = 0, verts = 0, scanned = 0, keys = 0, ginserts = 0, aux = 0;
 };
 
 __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
+    constexpr int F = 6;
     __shared__ double sg[kBlock / kWave];
-    __shared__ unsigned long long sv[5][kBlock / kWave];
+    __shared__ unsigned long long sv[F][kBlock / kWave];
     double g = group_sum<kWave>(acc.gain);
-    long long v[5] = {(long long)acc.moved, (long long)acc.verts, (long long)acc.scanned, (long long)acc.keys,
-                      (long long)acc.ginserts};
+    long long v[F] = {(long long)acc.moved, (long long)acc.verts, (long long)acc.scanned, (long long)acc.keys,
+                      (long long)acc.ginserts, (long long)acc.aux};
 #pragma unroll
-    for (int f = 0; f < 5; f++) v[f] = group_sum_ll<kWave>(v[f]);
+    for (int f = 0; f < F; f++) v[f] = group_sum_ll<kWave>(v[f]);
     int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
         sg[w] = g;
 #pragma unroll
-        for (int f = 0; f < 5; f++) sv[f][w] = (unsigned long long)v[f];
+        for (int f = 0; f < F; f++) sv[f][w] = (unsigned long long)v[f];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double tg = 0.0;
-        unsigned long long t[5] = {0, 0, 0, 0, 0};
+        unsigned long long t[F] = {0, 0, 0, 0, 0, 0};
         for (int q = 0; q < kBlock / kWave; q++) {
             tg += sg[q];
-            for (int f = 0; f < 5; f++) t[f] += sv[f][q];
+            for (int f = 0; f < F; f++) t[f] += sv[f][q];
         }
         CounterStripe &st = ctr->st[blockIdx.x % kStripes];
         if (tg != 0.0) unsafeAtomicAdd(&st.gain, tg);
@@ -61,7 +62,8 @@ __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
         if (t[1]) atomicAdd(&st.verts[cls], t[1]);
         if (t[2]) atomicAdd(&st.scanned[cls], t[2]);
         if (t[3]) atomicAdd(&st.keys[cls], t[3]);
-        if (t[4]) atomicAdd(&st.ginserts, t[4]);
+        if (t[4]) atomicAdd(&st.ginserts[cls], t[4]);
+        if (t[5]) atomicAdd(&st.aux[cls], t[5]);
     }
 }
 
@@ -479,9 +481,10 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     }
     __syncthreads();
     Acc acc;
+    if (a.hub_parts && !a.ctr->hub_fallback) return;   // every hub went through the partitions
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
-        if (!a.hub_act[i]) continue;
+        if (a.hub_parts ? a.hub_act[i] != 3 : !a.hub_act[i]) continue;
         int64_t beg = a.ch_beg[k];
         int64_t end = a.g.off[i] + a.g.deg[i];
         if (end > beg + kHubChunk) end = beg + kHubChunk;
@@ -532,15 +535,232 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     flush_acc(acc, a.ctr, 3);
 }
 
+// ---------------------------------------------------------------- hubs by hash partitions
+//
+// A hub's distinct neighbour communities are split into P hash partitions
+// (P = its number of chunks).  Phase 1, per chunk: reduce the chunk's entries
+// in LDS and write the distinct (community, weight) pairs to staging at the
+// chunk's own entry positions, grouped by partition, plus one word per
+// partition (start << 16 | count).  Phase 2, per partition: gather that
+// partition's pairs from every chunk of the hub into one LDS table and score
+// it.  Each (chunk, community) pair is written once and read once; nothing
+// goes through a global hash table.
+
+// Partition of community c among P (high bits of a second mix, independent
+// of the LDS slot hash).
+__device__ __forceinline__ int part_of(int c, int P) {
+    uint32_t h = (uint32_t)c;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return (int)(((uint64_t)h * (uint64_t)(uint32_t)P) >> 32);
+}
+
+// Exclusive scan of v[0..P) in place over the block, v[P] = total.
+__device__ void block_scan_excl(int *v, int P) {
+    __shared__ int part[kBlock + 1];
+    const int tid = threadIdx.x;
+    const int per = (P + kBlock - 1) / kBlock;
+    const int b0 = tid * per, b1 = b0 + per < P ? b0 + per : P;
+    int sum = 0;
+    for (int b = b0; b < b1; b++) sum += v[b];
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int q = 0; q < kBlock; q++) {
+            int x = part[q];
+            part[q] = run;
+            run += x;
+        }
+        part[kBlock] = run;
+    }
+    __syncthreads();
+    int run = part[tid];
+    for (int b = b0; b < b1; b++) {
+        int x = v[b];
+        v[b] = run;
+        run += x;
+    }
+    if (tid == 0) v[P] = part[kBlock];
+    __syncthreads();
+}
+
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
+    __shared__ int tkeys[kBlockTable];
+    __shared__ double tvals[kBlockTable];
+    __shared__ int pcnt[kMaxParts + 1];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kBlockTable; k += kBlock) {
+        tkeys[k] = kEmpty;
+        tvals[k] = 0.0;
+    }
+    __syncthreads();
+    Acc acc;
+    for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
+        int i = a.ch_vert[k];
+        if (a.hub_act[i] != 1) continue;
+        int di = a.g.deg[i];
+        int P = (di + kHubChunk - 1) / kHubChunk;
+        if (P > kMaxParts) {   // too many partitions: the global-table path
+            if (tid == 0) {
+                a.hub_act[i] = 3;
+                a.ctr->hub_fallback = 1;
+            }
+            continue;
+        }
+        int64_t beg = a.ch_beg[k];
+        int64_t end = a.g.off[i] + di;
+        if (end > beg + kHubChunk) end = beg + kHubChunk;
+        int s = (int)((beg - a.g.off[i]) / kHubChunk);
+        for (int64_t e = beg + tid; e < end; e += kBlock) {
+            int j = load_col(a.g.col, e);
+            double wt = edge_weight<WT>(a.g.w, e);
+            if (j != i) lds_table_add(tkeys, tvals, kBlockTable - 1, a.cm[j], wt);
+        }
+        for (int b = tid; b <= P; b += kBlock) pcnt[b] = 0;
+        __syncthreads();
+        for (int sl = tid; sl < kBlockTable; sl += kBlock) {
+            int key = tkeys[sl];
+            if (key != kEmpty) atomicAdd(&pcnt[part_of(key, P)], 1);
+        }
+        __syncthreads();
+        block_scan_excl(pcnt, P);
+        uint32_t *words = a.hbuck + a.hub_b0[i] + (int64_t)s * P;
+        for (int b = tid; b < P; b += kBlock) words[b] = ((uint32_t)pcnt[b] << 16) | (uint32_t)(pcnt[b + 1] - pcnt[b]);
+        if (tid == 0) acc.aux += (unsigned long long)P;
+        __syncthreads();
+        for (int sl = tid; sl < kBlockTable; sl += kBlock) {
+            int key = tkeys[sl];
+            if (key == kEmpty) continue;
+            double v = tvals[sl];
+            tkeys[sl] = kEmpty;
+            tvals[sl] = 0.0;
+            int pos = atomicAdd(&pcnt[part_of(key, P)], 1);
+            a.skey[beg + pos] = key;
+            a.sval[beg + pos] = v;
+            acc.ginserts++;
+        }
+        if (tid == 0) acc.scanned += (unsigned long long)(end - beg);
+        __syncthreads();
+    }
+    flush_acc(acc, a.ctr, 3);
+}
+
+// Largest s in [0, n) with v[s] <= t (v non-decreasing, v[0] = 0 <= t).
+__device__ __forceinline__ int last_le(const int *v, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (v[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
+    __shared__ int tkeys[kBlockTable];
+    __shared__ double tvals[kBlockTable];
+    __shared__ int pst[kMaxParts + 1];
+    __shared__ short srcst[kMaxParts];   // this partition's start within each source chunk
+    __shared__ int nkeys, ovf;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kBlockTable; k += kBlock) {
+        tkeys[k] = kEmpty;
+        tvals[k] = 0.0;
+    }
+    __syncthreads();
+    Acc acc;
+    for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
+        int i = a.ch_vert[k];
+        if (a.hub_act[i] != 1) continue;
+        int di = a.g.deg[i];
+        int P = (di + kHubChunk - 1) / kHubChunk;
+        int p = (int)((a.ch_beg[k] - a.g.off[i]) / kHubChunk);
+        const uint32_t *words = a.hbuck + a.hub_b0[i];
+        for (int s = tid; s < P; s += kBlock) {
+            uint32_t wd = words[(int64_t)s * P + p];
+            pst[s] = (int)(wd & 0xFFFFu);
+            srcst[s] = (short)(wd >> 16);
+        }
+        if (tid == 0) {
+            nkeys = 0;
+            ovf = 0;
+        }
+        __syncthreads();
+        block_scan_excl(pst, P);
+        const int total = pst[P];
+        const int64_t base = a.g.off[i];
+        if (tid == 0) {
+            acc.verts++;   // chunks (partitions) gathered
+            acc.ginserts += (unsigned long long)total;
+            acc.aux += (unsigned long long)P;
+        }
+        for (int t = tid; t < total; t += kBlock) {
+            if (*(volatile int *)&ovf) break;
+            int s = last_le(pst, P, t);
+            int64_t idx = base + (int64_t)s * kHubChunk + (int64_t)srcst[s] + (t - pst[s]);
+            int key = a.skey[idx];
+            double v = a.sval[idx];
+            // insert, counting distinct keys; past kPartCap the partition
+            // stops (at most kBlock inserts overshoot: the table never fills)
+            uint32_t sl = key_hash(key) & (kBlockTable - 1);
+            while (true) {
+                int prev = atomicCAS(&tkeys[sl], kEmpty, key);
+                if (prev == kEmpty) {
+                    if (atomicAdd(&nkeys, 1) >= kPartCap) ovf = 1;
+                    atomicAdd(&tvals[sl], v);
+                    break;
+                }
+                if (prev == key) {
+                    atomicAdd(&tvals[sl], v);
+                    break;
+                }
+                sl = (sl + 1) & (kBlockTable - 1);
+            }
+        }
+        __syncthreads();
+        if (ovf) {   // rare: this hub goes through the global-table path
+            for (int q = tid; q < kBlockTable; q += kBlock) {
+                tkeys[q] = kEmpty;
+                tvals[q] = 0.0;
+            }
+            if (tid == 0) {
+                a.hub_act[i] = 3;
+                a.ctr->hub_fallback = 1;
+            }
+            __syncthreads();
+            continue;
+        }
+        int d = a.cm[i];
+        double ki = a.K[i];
+        const double m2 = m2_of(a, i);
+        double bg = -INFINITY, kid = 0.0;
+        int bc = kIntMax;
+        for (int q = tid; q < kBlockTable; q += kBlock) take_slot(a, m2, tkeys, tvals, q, d, ki, bg, bc, kid, acc.keys);
+        block_argmax_sum(bg, bc, kid);
+        if (tid == 0) {
+            a.part_g[k] = bg;
+            a.part_c[k] = bc;
+            a.part_kid[k] = kid;
+        }
+        __syncthreads();
+    }
+    flush_acc(acc, a.ctr, 5);
+}
+
 // One workgroup per chunk again: chunk s of a hub with nch chunks scores and
 // resets the slice [s*seg, (s+1)*seg) of the hub's table (seg = ceil(T /
 // nch) <= 8192 slots; the table is complete now) and leaves the slice's best
 // candidate and its share of K_{i->d} in part_*[chunk].
 __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
     Acc acc;
+    if (a.hub_parts && !a.ctr->hub_fallback) return;
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
-        if (!a.hub_act[i]) continue;
+        if (a.hub_parts ? a.hub_act[i] != 3 : !a.hub_act[i]) continue;
         int di = a.g.deg[i];
         int64_t T = (int64_t)hub_table_size(di);
         int64_t nch = (di + kHubChunk - 1) / kHubChunk;
@@ -617,6 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (lane == 0) {
             acc.verts++;
+            acc.aux += (unsigned long long)nch;
             a.hub_act[i] = mv ? 2 : 0;   // 2: its neighbours are marked chunk by chunk in apply
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
@@ -791,6 +1012,22 @@ void launch_move_hub_scan(const MoveArgs &a, hipStream_t s) {
         k_move_hub_insert<W_F32><<<gr, kBlock, 0, s>>>(a);
     else
         k_move_hub_insert<W_F64><<<gr, kBlock, 0, s>>>(a);
+}
+
+void launch_move_hub_parts(const MoveArgs &a, hipStream_t s) {
+    if (a.qcap[BIN_HUB] == 0) return;
+    unsigned gr = cap_grid(a.ch_count, 4096);
+    if (a.g.wt == W_UNIT)
+        k_hub_bucket<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+    else if (a.g.wt == W_F32)
+        k_hub_bucket<W_F32><<<gr, kBlock, 0, s>>>(a);
+    else
+        k_hub_bucket<W_F64><<<gr, kBlock, 0, s>>>(a);
+}
+
+void launch_move_hub_gather(const MoveArgs &a, hipStream_t s) {
+    if (a.qcap[BIN_HUB] == 0) return;
+    k_hub_gather<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
 }
 
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {

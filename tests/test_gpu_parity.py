@@ -294,3 +294,50 @@ def test_graph_replay_equals_direct_launches(ctx, name):
     m, li, dq, mv = ctx.move_phase(None, tolerance=1e-2)
     ref = oracle.move_sync(g, tau=1e-2)
     assert np.array_equal(m, ref[0]) and li == ref[1]
+
+
+@pytest.mark.parametrize("name", ["rmat15", "agg_rmat14", "sbm_w10"])
+def test_global_hub_tables_equal_partitions(ctx, name):
+    """Hubs scored through global hash tables only (hub_global = 1) and
+    through LDS hash partitions (the default) give the same runs."""
+    g = _graph(name)
+    _load(ctx, g)
+    a = ctx.louvain(tolerance=1e-2, max_passes=10)
+    b = ctx.louvain(tolerance=1e-2, max_passes=10, hub_global=1)
+    assert np.array_equal(a.membership, b.membership)
+    assert a.stats["iterations"] == b.stats["iterations"]
+
+
+def _part_of(c, P):
+    """The library's partition of community c among P (a murmur-style
+    finaliser, high bits scaled to P), used here only to build an input
+    whose hub overflows one partition."""
+    h = c & 0xFFFFFFFF
+    h ^= h >> 16
+    h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+    h ^= h >> 13
+    h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+    h ^= h >> 16
+    return (h * P) >> 32
+
+
+def test_hub_partition_overflow_falls_back(ctx):
+    """A hub whose neighbours (singleton communities) all fall in one hash
+    partition overflows that partition's LDS table: the hub is scored by the
+    global-table path instead, with the oracle's decisions."""
+    n = 20000
+    P = 3                                            # hub degree 4097..6144 -> 3 chunks
+    nb = [j for j in range(1, n) if _part_of(j, P) == 0][:4200]
+    assert len(nb) == 4200
+    edges = [(0, j) for j in nb]
+    # some structure around: a ring so the other vertices have neighbours too
+    edges += [(j, j + 1) for j in range(1, n - 1)]
+    g = gi.from_edges(n, edges)
+    _load(ctx, g)
+    memb = np.arange(n, dtype=np.int32)
+    dec, gain, moved = ctx.step_move(memb)
+    rdec, rgain, rmoved = oracle.move_sync_step(g, memb)
+    assert np.array_equal(dec, rdec) and moved == rmoved
+    m, li, dq, mv = ctx.move_phase(None, tolerance=0.0)
+    ref = oracle.move_sync(g, tau=0.0)
+    assert np.array_equal(m, ref[0]) and li == ref[1]
