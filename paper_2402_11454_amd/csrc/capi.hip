@@ -593,7 +593,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         auto ptr = [](const void *q) { return (int64_t)(intptr_t)q; };
         key = {g.n, g.nnz, g.wt, g.graphs, ptr(g.off), ptr(g.col), ptr(g.w), ptr(g.deg), ptr(g.gid), ptr(g.vbase),
                ptr(K), P, ptr(wl.bl), ptr(wl.ch_vert), ptr(wl.ch_beg), ptr(wl.hub_off), ptr(ctx->sc.hkeys),
-               ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), (int64_t)(batch ? 1 : 0)};
+               ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), ptr(ctx->sc.hbuck), (int64_t)(batch ? 1 : 0)};
         for (int k = 0; k <= kNumBins * P; k++) key.push_back(wl.boff[k]);
         for (int p = 0; p <= P; p++) key.push_back(wl.ch_poff[p]);
         int64_t m2bits;
@@ -805,6 +805,7 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(sc.ch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
     if ((st = A(sc.cch_comm, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
     if ((st = A(sc.cch_beg, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
+    if ((st = A(sc.cch_k0, sc.ch_cap, "hipMalloc(chunks)")) != GSP_OK) return st;
     if ((st = A(sc.cseg_comm, sc.ch_cap, "hipMalloc(segments)")) != GSP_OK) return st;
     if ((st = A(sc.cseg_beg, sc.ch_cap, "hipMalloc(segments)")) != GSP_OK) return st;
     if ((st = A(sc.part_g, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
@@ -1874,7 +1875,7 @@ gsp_status gsp_step_aggregate(gsp_ctx *ctx, const int32_t *membership, int where
     HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
     AggOut out{ctx->offL[0], ctx->colL[0], ctx->wL[0], ctx->KL[0], ctx->degL[0]};
     int64_t nnz2 = 0;
-    HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s));
+    HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s, ctx->hub_parts));
     *n_out = ncomm;
     *nnz_out = nnz2;
     if (offsets) {

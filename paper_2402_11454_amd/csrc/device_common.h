@@ -117,6 +117,62 @@ __device__ __forceinline__ void gbl_table_add(int *keys, double *vals, uint64_t 
     }
 }
 
+// Partition of community c among P (high bits of a second mix, independent
+// of the LDS slot hash).
+__device__ __forceinline__ int part_of(int c, int P) {
+    uint32_t h = (uint32_t)c;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return (int)(((uint64_t)h * (uint64_t)(uint32_t)P) >> 32);
+}
+
+// Exclusive scan of v[0..P) in place over a block of kBlock threads, v[P] =
+// total: each thread sums a run of ceil(P / kBlock) entries, the run sums
+// are scanned across each wavefront with shuffles and across the
+// wavefronts through LDS, then each thread rewrites its run.
+__device__ __forceinline__ void block_scan_excl(int *v, int P) {
+    __shared__ int wtot[kBlock / kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    const int per = (P + kBlock - 1) / kBlock;
+    const int b0 = tid * per, b1 = b0 + per < P ? b0 + per : P;
+    int sum = 0;
+    for (int b = b0; b < b1; b++) sum += v[b];
+    int inc = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        int y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) wtot[w] = inc;
+    __syncthreads();
+    int run = inc - sum, all = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / kWave; q++) {
+        if (q < w) run += wtot[q];
+        all += wtot[q];
+    }
+    for (int b = b0; b < b1; b++) {
+        int x = v[b];
+        v[b] = run;
+        run += x;
+    }
+    if (tid == 0) v[P] = all;
+    __syncthreads();
+}
+
+// Largest s in [0, n) with v[s] <= t (v non-decreasing, v[0] = 0 <= t).
+__device__ __forceinline__ int last_le(const int *v, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (v[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // (g, c) beats (g2, c2): larger score, ties to the lower community id.
 __device__ __forceinline__ bool better(double g, int c, double g2, int c2) {
     return g > g2 || (g == g2 && c < c2);

@@ -308,6 +308,7 @@ struct Scratch {
     int64_t *ch_beg = nullptr;
     int32_t *cch_comm = nullptr, *cseg_comm = nullptr;
     int64_t *cch_beg = nullptr, *cseg_beg = nullptr;
+    int64_t *cch_k0 = nullptr;   // first member position of each chunk
     double *part_g = nullptr, *part_kid = nullptr;   // per chunk
     int *part_c = nullptr;
     int64_t ch_cap = 0;

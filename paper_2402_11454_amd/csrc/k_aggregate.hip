@@ -203,8 +203,15 @@ struct AggArgs {
     int64_t n2;
     const int64_t *ctab;     // hub community table offsets (-1: not a hub)
     const int64_t *mpre;     // exclusive scan of member degrees (flattened entry index)
+    const int64_t *ck0;      // per hub chunk: the member position holding its first entry
     int *hkeys;
     double *hvals;
+    // hub partitions (null stage_col: every hub community through its global table)
+    int32_t *stage_col;      // staged pairs at flattened entry positions
+    double *stage_w;
+    uint32_t *words;         // per chunk and partition: start << 16 | count
+    const int64_t *woff;     // community c's words begin at words + woff[c]
+    uint8_t *spill;          // community c has a partition in its global table
 };
 
 template <int W>
@@ -440,6 +447,82 @@ __global__ void __launch_bounds__(kBlock) k_agg_large(AggArgs a) {
 
 // ---------------------------------------------------------------- hubs
 
+// First member of every hub chunk: the last position k among c's members
+// with mpre[k] <= X0 (one thread per chunk).
+__global__ void __launch_bounds__(kBlock) k_agg_chunk_k0(const int32_t *cch_comm, const int64_t *cch_beg,
+                                                        int64_t nchunks, const int64_t *coff, const int64_t *mpre,
+                                                        int64_t *k0) {
+    for (int64_t ch = blockIdx.x * (int64_t)kBlock + threadIdx.x; ch < nchunks; ch += (int64_t)gridDim.x * kBlock) {
+        int c = cch_comm[ch];
+        int64_t X0 = cch_beg[ch];
+        int64_t lo = coff[c], hi = coff[c + 1] - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) / 2;
+            if (mpre[mid] <= X0) lo = mid; else hi = mid - 1;
+        }
+        k0[ch] = lo;
+    }
+}
+
+// Reduces hub chunk ch (entries [X0, X1) of community c's flattened member
+// rows) into the LDS table.  The window holds, for the chunk's candidate
+// members k0 .. k0 + nm - 1, the offset of each one's first entry relative to
+// X0 (win, at least -2^31 + 1 as a row has fewer than 2^31 entries) and its
+// row start (moff); win[nm] = X1 - X0.  Ends with a barrier (the window is
+// free again).  The candidates end
+// at the member holding the next chunk's first entry (or at c's last
+// member); members with entries come first, so there are at most kAggChunk.
+// Each thread resolves its four entries first and then issues their loads
+// together.
+template <int WT>
+__device__ __forceinline__ void reduce_hub_chunk(const AggArgs &a, const int32_t *cch_comm, int64_t nchunks,
+                                                 int64_t ch, int c, int64_t X0, int64_t X1, int *tkeys,
+                                                 double *tvals, int *win, int64_t *moff) {
+    const int tid = threadIdx.x;
+    const int64_t k0 = a.ck0[ch];
+    const int64_t m_end = a.coff[c + 1];
+    int64_t k1 = (ch + 1 < nchunks && cch_comm[ch + 1] == c) ? a.ck0[ch + 1] + 1 : m_end;
+    if (k1 > k0 + kAggChunk) k1 = k0 + kAggChunk;
+    const int nm = (int)(k1 - k0);
+    for (int t = tid; t < nm; t += kBlock) {
+        win[t] = (int)(a.mpre[k0 + t] - X0);
+        moff[t] = a.g.off[a.members[k0 + t]];
+    }
+    if (tid == 0) win[nm] = (int)(X1 - X0);
+    __syncthreads();
+    constexpr int R = kAggChunk / kBlock;
+    int64_t e[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int x = r * kBlock + tid;
+        ok[r] = X0 + x < X1;
+        e[r] = 0;
+        if (ok[r]) {
+            int lo = 0, hi = nm - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (win[mid] <= x) lo = mid; else hi = mid - 1;
+            }
+            e[r] = moff[lo] + (x - win[lo]);
+        }
+    }
+    int32_t j[R];
+    double w[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        j[r] = ok[r] ? load_col(a.g.col, e[r]) : 0;
+        w[r] = ok[r] ? edge_weight<WT>(a.g.w, e[r]) : 0.0;
+    }
+    int cj[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) cj[r] = ok[r] ? a.cm[j[r]] : 0;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (ok[r]) lds_table_add(tkeys, tvals, kAggChunkTable - 1, cj[r], w[r]);
+    __syncthreads();
+}
+
 // Hub communities, one workgroup per chunk of kAggChunk entries of the
 // community's flattened member rows (entry X of the level's member order is
 // entry X - mpre[k] of member k).  The chunk is reduced in LDS, then each
@@ -450,8 +533,8 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_chunks(AggArgs a, const int3
                                                           const int64_t *cch_beg, int64_t nchunks) {
     __shared__ int tkeys[kAggChunkTable];
     __shared__ double tvals[kAggChunkTable];
-    __shared__ int64_t win[kAggChunk + 1];
-    __shared__ int64_t s_k0;
+    __shared__ int win[kAggChunk + 1];
+    __shared__ int64_t moff[kAggChunk];
     for (int k = threadIdx.x; k < kAggChunkTable; k += kBlock) {
         tkeys[k] = kEmpty;
         tvals[k] = 0.0;
@@ -460,35 +543,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_chunks(AggArgs a, const int3
         int c = cch_comm[ch];
         int64_t X0 = cch_beg[ch];
         int64_t X1 = X0 + kAggChunk < a.eoff[c + 1] ? X0 + kAggChunk : a.eoff[c + 1];
-        int64_t m_end = a.coff[c + 1];
-        if (threadIdx.x == 0) {
-            // last member position k with mpre[k] <= X0 among c's members
-            int64_t lo = a.coff[c], hi = m_end - 1;
-            while (lo < hi) {
-                int64_t mid = (lo + hi + 1) / 2;
-                if (a.mpre[mid] <= X0) lo = mid; else hi = mid - 1;
-            }
-            s_k0 = lo;
-        }
-        __syncthreads();
-        int64_t k0 = s_k0;
-        // members with entries come first, so the chunk's members lie in
-        // [k0, k0 + kAggChunk); the window holds their prefix values
-        for (int t = threadIdx.x; t <= kAggChunk; t += kBlock)
-            win[t] = (k0 + t < m_end) ? a.mpre[k0 + t] : a.eoff[c + 1];
-        __syncthreads();
-        for (int64_t X = X0 + threadIdx.x; X < X1; X += kBlock) {
-            int lo = 0, hi = kAggChunk - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) / 2;
-                if (win[mid] <= X) lo = mid; else hi = mid - 1;
-            }
-            int v = a.members[k0 + lo];
-            int64_t e = a.g.off[v] + (X - win[lo]);
-            int32_t j = load_col(a.g.col, e);
-            lds_table_add(tkeys, tvals, kAggChunkTable - 1, a.cm[j], edge_weight<WT>(a.g.w, e));
-        }
-        __syncthreads();
+        reduce_hub_chunk<WT>(a, cch_comm, nchunks, ch, c, X0, X1, tkeys, tvals, win, moff);
         int64_t tb = a.ctab[c];
         uint64_t mask = comm_table_size(a.eoff[c + 1] - a.eoff[c], a.n2) - 1;
         for (int s = threadIdx.x; s < kAggChunkTable; s += kBlock) {
@@ -514,6 +569,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_emit(AggArgs a, const int32_
     constexpr int R = kEmitSeg / kBlock;
     for (int64_t q = blockIdx.x; q < nseg; q += gridDim.x) {
         int c = seg_comm[q];
+        if (a.stage_col && !a.spill[c]) continue;   // its table is empty
         int64_t tb = a.ctab[c];
         int64_t T = (int64_t)comm_table_size(a.eoff[c + 1] - a.eoff[c], a.n2);
         int64_t s0 = seg_beg[q];
@@ -567,6 +623,243 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_emit(AggArgs a, const int32_
     }
 }
 
+// ---------------------------------------------------------------- hub partitions
+
+// Giant communities without global tables.  Community c's distinct
+// neighbour communities are split into P_c hash partitions.  Phase 1, per
+// chunk of kAggChunk entries: reduce the chunk in LDS and stage its distinct
+// (community, weight) pairs, grouped by partition, at the chunk's own
+// positions of the staging arrays, with one word per partition (start << 16
+// | count).  Phase 2, per partition: merge that partition's pairs from every
+// chunk of c in one LDS table and append the table to row c.  Each pair is
+// written once and read once.  A partition with more than kPartCap distinct
+// communities (its table would not fit) spills its pairs into c's global
+// table instead; the emit kernel appends those.
+
+constexpr int kAggPartTarget = 1536;   // distinct communities aimed at per partition
+constexpr int kAggMaxParts = 4086;     // partition counts (+1) fit the bucket kernel's 40 KB of LDS
+constexpr int kGatherWin = 2048;       // source chunks per window of the gather
+
+// P_c: one partition per kAggPartTarget possible distinct neighbours (at most
+// min(total degree, n2)); at most kAggMaxParts and at most the chunk count.
+__device__ __forceinline__ int agg_parts(int64_t tot, int64_t n2) {
+    int64_t d = tot < n2 ? tot : n2;
+    int64_t p = (d + kAggPartTarget - 1) / kAggPartTarget;
+    if (p < 1) p = 1;
+    return (int)(p < kAggMaxParts ? p : kAggMaxParts);
+}
+
+__global__ void __launch_bounds__(kBlock) k_agg_part_words(const int32_t *bl, int64_t hb, int64_t H,
+                                                          const int64_t *eoff, int64_t n2, int64_t *nw) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock) {
+        int c = bl[hb + k];
+        int64_t tot = eoff[c + 1] - eoff[c];
+        nw[k] = (tot + kAggChunk - 1) / kAggChunk * (int64_t)agg_parts(tot, n2);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_agg_part_scatter(const int32_t *bl, int64_t hb, int64_t H,
+                                                            const int64_t *wk, int64_t *woff) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < H; k += (int64_t)gridDim.x * kBlock)
+        woff[bl[hb + k]] = wk[k];
+}
+
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_agg_part_bucket(AggArgs a, const int32_t *cch_comm,
+                                                           const int64_t *cch_beg, int64_t nchunks) {
+    __shared__ int tkeys[kAggChunkTable];
+    __shared__ double tvals[kAggChunkTable];
+    // the window (during the reduce) and the partition counts (after it)
+    // share one LDS region: the block stays at 40 KB, four blocks per CU
+    __shared__ int64_t wm[kAggMaxParts / 2 + 1];
+    static_assert(sizeof(int64_t) * kAggChunk + sizeof(int) * (kAggChunk + 1) <= sizeof(wm), "window");
+    int64_t *moff = wm;
+    int *win = (int *)(wm + kAggChunk);
+    int *pcnt = (int *)wm;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kAggChunkTable; k += kBlock) {
+        tkeys[k] = kEmpty;
+        tvals[k] = 0.0;
+    }
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        int c = cch_comm[ch];
+        int64_t X0 = cch_beg[ch];
+        int64_t X1 = X0 + kAggChunk < a.eoff[c + 1] ? X0 + kAggChunk : a.eoff[c + 1];
+        reduce_hub_chunk<WT>(a, cch_comm, nchunks, ch, c, X0, X1, tkeys, tvals, win, moff);
+        const int64_t tot = a.eoff[c + 1] - a.eoff[c];
+        const int P = agg_parts(tot, a.n2);
+        const int64_t s = (X0 - a.eoff[c]) / kAggChunk;
+        for (int b = tid; b <= P; b += kBlock) pcnt[b] = 0;
+        __syncthreads();
+        for (int sl = tid; sl < kAggChunkTable; sl += kBlock) {
+            int key = tkeys[sl];
+            if (key != kEmpty) atomicAdd(&pcnt[part_of(key, P)], 1);
+        }
+        __syncthreads();
+        block_scan_excl(pcnt, P);
+        uint32_t *wd = a.words + a.woff[c] + s * P;
+        for (int b = tid; b < P; b += kBlock) wd[b] = ((uint32_t)pcnt[b] << 16) | (uint32_t)(pcnt[b + 1] - pcnt[b]);
+        __syncthreads();
+        for (int sl = tid; sl < kAggChunkTable; sl += kBlock) {
+            int key = tkeys[sl];
+            if (key == kEmpty) continue;
+            double v = tvals[sl];
+            tkeys[sl] = kEmpty;
+            tvals[sl] = 0.0;
+            int pos = atomicAdd(&pcnt[part_of(key, P)], 1);
+            a.stage_col[X0 + pos] = key;
+            a.stage_w[X0 + pos] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Loads the words of source chunks [w0, w0 + nw) for partition p into
+// (count -> exclusive offsets in pst, starts in srcst); returns the pair total.
+__device__ __forceinline__ int load_window(const uint32_t *wd, int P, int p, int64_t w0, int nw, int *pst,
+                                           short *srcst) {
+    for (int s = threadIdx.x; s < nw; s += kBlock) {
+        uint32_t x = wd[(w0 + s) * P + p];
+        pst[s] = (int)(x & 0xFFFFu);
+        srcst[s] = (short)(x >> 16);
+    }
+    __syncthreads();
+    block_scan_excl(pst, nw);
+    return pst[nw];
+}
+
+// One workgroup per (hub community, partition): the pieces are the chunk
+// list again, chunk s of community c standing for partition s (chunks with
+// s >= P_c have nothing to do).
+__global__ void __launch_bounds__(kBlock) k_agg_part_gather(AggArgs a, const int32_t *cch_comm,
+                                                           const int64_t *cch_beg, int64_t nchunks) {
+    __shared__ int tkeys[kBlockTable];
+    __shared__ double tvals[kBlockTable];
+    __shared__ int pst[kGatherWin + 1];
+    __shared__ short srcst[kGatherWin];
+    __shared__ int s_cnt[kBlock / kWave];
+    __shared__ double s_sum[kBlock / kWave];
+    __shared__ int nkeys, ovf, s_base;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kBlockTable; k += kBlock) {
+        tkeys[k] = kEmpty;
+        tvals[k] = 0.0;
+    }
+    __syncthreads();
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int c = cch_comm[ch];
+        const int64_t e0 = a.eoff[c], tot = a.eoff[c + 1] - e0;
+        const int P = agg_parts(tot, a.n2);
+        const int p = (int)((cch_beg[ch] - e0) / kAggChunk);
+        if (p >= P) continue;
+        const int64_t nch = (tot + kAggChunk - 1) / kAggChunk;
+        const uint32_t *wd = a.words + a.woff[c];
+        if (tid == 0) {
+            nkeys = 0;
+            ovf = 0;
+        }
+        for (int64_t w0 = 0; w0 < nch; w0 += kGatherWin) {
+            int nw = (int)(nch - w0 < kGatherWin ? nch - w0 : kGatherWin);
+            int total = load_window(wd, P, p, w0, nw, pst, srcst);
+            for (int t = tid; t < total; t += kBlock) {
+                if (*(volatile int *)&ovf) break;
+                int s = last_le(pst, nw, t);
+                int64_t idx = e0 + (w0 + s) * kAggChunk + (int64_t)srcst[s] + (t - pst[s]);
+                int key = a.stage_col[idx];
+                double v = a.stage_w[idx];
+                // at most kPartCap distinct keys (plus fewer than kBlock in
+                // flight): the table never fills
+                uint32_t sl = key_hash(key) & (kBlockTable - 1);
+                while (true) {
+                    int prev = atomicCAS(&tkeys[sl], kEmpty, key);
+                    if (prev == kEmpty) {
+                        if (atomicAdd(&nkeys, 1) >= kPartCap) ovf = 1;
+                        atomicAdd(&tvals[sl], v);
+                        break;
+                    }
+                    if (prev == key) {
+                        atomicAdd(&tvals[sl], v);
+                        break;
+                    }
+                    sl = (sl + 1) & (kBlockTable - 1);
+                }
+            }
+            __syncthreads();
+            if (ovf) break;
+        }
+        if (ovf) {
+            // spill: the partition's pairs go to c's global table
+            for (int q = tid; q < kBlockTable; q += kBlock) {
+                tkeys[q] = kEmpty;
+                tvals[q] = 0.0;
+            }
+            if (tid == 0) a.spill[c] = 1;
+            const int64_t tb = a.ctab[c];
+            const uint64_t mask = comm_table_size(tot, a.n2) - 1;
+            for (int64_t w0 = 0; w0 < nch; w0 += kGatherWin) {
+                int nw = (int)(nch - w0 < kGatherWin ? nch - w0 : kGatherWin);
+                int total = load_window(wd, P, p, w0, nw, pst, srcst);
+                for (int t = tid; t < total; t += kBlock) {
+                    int s = last_le(pst, nw, t);
+                    int64_t idx = e0 + (w0 + s) * kAggChunk + (int64_t)srcst[s] + (t - pst[s]);
+                    gbl_table_add(a.hkeys + tb, a.hvals + tb, mask, a.stage_col[idx], a.stage_w[idx]);
+                }
+                __syncthreads();
+            }
+            continue;
+        }
+        // append the table to row c: one reservation on deg''[c] per block
+        constexpr int R = kBlockTable / kBlock;
+        int key[R];
+        double val[R];
+        int cnt = 0;
+        double sum = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int sl = r * kBlock + tid;
+            key[r] = tkeys[sl];
+            val[r] = 0.0;
+            if (key[r] != kEmpty) {
+                val[r] = tvals[sl];
+                tkeys[sl] = kEmpty;
+                tvals[sl] = 0.0;
+                cnt++;
+                sum += val[r];
+            }
+        }
+        int wt;
+        int pos = group_excl_scan<kWave>(cnt, lane_id(), &wt);
+        sum = group_sum<kWave>(sum);
+        const int w = tid / kWave;
+        if (lane_id() == 0) {
+            s_cnt[w] = wt;
+            s_sum[w] = sum;
+        }
+        __syncthreads();
+        int before = 0, all = 0;
+        double tsum = 0.0;
+        for (int x = 0; x < kBlock / kWave; x++) {
+            if (x < w) before += s_cnt[x];
+            all += s_cnt[x];
+            tsum += s_sum[x];
+        }
+        if (tid == 0) {
+            s_base = all ? atomicAdd(&a.deg2[c], all) : 0;
+            if (tsum != 0.0) unsafeAtomicAdd(&a.K2[c], tsum);
+        }
+        __syncthreads();
+        int64_t dst = e0 + s_base + before + pos;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (key[r] != kEmpty) {
+                a.gap_col[dst] = key[r];
+                a.gap_w[dst] = val[r];
+                dst++;
+            }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- compact
 
 __global__ void __launch_bounds__(kBlock) k_agg_copy(const int64_t *eoff, const int64_t *off2, int64_t n2,
@@ -588,7 +881,6 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
                      int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
                      bool hub_parts) {
     (void)wl;
-    (void)hub_parts;
     int32_t *csz = sc.i32a, *ccur = sc.i32b, *members = sc.i32c, *cdeg = sc.i32d, *mdeg = sc.i32e;
     int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = sc.i64c, *mpre = sc.i64d, *ctab = sc.i64e, *tmp = sc.i64f;
     launch_fill_i32(csz, 0, n2, s);
@@ -625,6 +917,12 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     a.n2 = n2;
     a.ctab = ctab;
     a.mpre = mpre;
+    a.ck0 = sc.cch_k0;
+    a.stage_col = nullptr;
+    a.stage_w = nullptr;
+    a.words = nullptr;
+    a.woff = nullptr;
+    a.spill = nullptr;
 
     // hub communities: table offsets in the global pool, entry chunks and
     // table segments
@@ -635,7 +933,7 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
         k_agg_hub_sizes<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, n2, ctot);    // ctot is free now
         scan_exclusive_i64(ctot, tmp, H, sc.scan_tmp, s);
         k_agg_hub_off<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, tmp, ctab);
-        int64_t host[3] = {0, 0, 0};
+        int64_t host[4] = {0, 0, 0, 0};
         e = hipMemcpyAsync(&host[0], tmp + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         k_agg_hub_nchunks<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, ctot);
@@ -646,6 +944,12 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
         scan_exclusive_i64(ctot, tmp, H, sc.scan_tmp, s);
         e = hipMemcpyAsync(&host[2], tmp + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
+        if (hub_parts) {   // partition words per hub community (scan by hub index in i64g)
+            k_agg_part_words<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, eoff, n2, ctot);
+            scan_exclusive_i64(ctot, sc.i64g, H, sc.scan_tmp, s);
+            e = hipMemcpyAsync(&host[3], sc.i64g + H, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+        }
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         nchunks = host[1];
@@ -659,9 +963,23 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
                                                                 sc.cseg_beg);
         e = ensure_hub_tables(sc, (uint64_t)host[0], s);
         if (e != hipSuccess) return e;
+        if (hub_parts) {
+            e = ensure_hub_buckets(sc, (uint64_t)host[3], s);
+            if (e != hipSuccess) return e;
+            k_agg_part_scatter<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, sc.i64g, ctot);   // ctot: words offset by community
+            launch_fill_u8(sc.u8a, 0, n2, s);
+            a.stage_col = out.col;   // free until the compaction at the end
+            a.stage_w = out.w;
+            a.words = sc.hbuck;
+            a.woff = ctot;
+            a.spill = sc.u8a;
+        }
         // flattened entry index of every member
         k_member_degrees<<<grid1(g.n), kBlock, 0, s>>>(members, g.n, g.deg, mdeg);
         scan_exclusive_i32_to_i64(mdeg, mpre, g.n, sc.scan_tmp, s);
+        if (nchunks)
+            k_agg_chunk_k0<<<grid1(nchunks, 8192), kBlock, 0, s>>>(sc.cch_comm, sc.cch_beg, nchunks, coff, mpre,
+                                                                   sc.cch_k0);
     }
     a.hkeys = sc.hkeys;
     a.hvals = sc.hvals;
@@ -674,19 +992,24 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     int64_t ul = (a.cn[BIN_WAVE] + 3) / 4 + a.cn[BIN_BLOCK];
     unsigned gs = (unsigned)(us < 8192 ? us : 8192), gl = (unsigned)(ul < 2048 ? ul : 2048);
     unsigned gh = (unsigned)(nchunks < 4096 ? nchunks : 4096);
+    const bool parts = a.stage_col != nullptr;
     if (g.wt == W_UNIT) {
         if (us) k_agg_small<W_UNIT><<<gs, kBlock, 0, s>>>(a);
         if (ul) k_agg_large<W_UNIT><<<gl, kBlock, 0, s>>>(a);
-        if (nchunks) k_agg_hub_chunks<W_UNIT><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
+        if (nchunks && parts) k_agg_part_bucket<W_UNIT><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
+        if (nchunks && !parts) k_agg_hub_chunks<W_UNIT><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     } else if (g.wt == W_F32) {
         if (us) k_agg_small<W_F32><<<gs, kBlock, 0, s>>>(a);
         if (ul) k_agg_large<W_F32><<<gl, kBlock, 0, s>>>(a);
-        if (nchunks) k_agg_hub_chunks<W_F32><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
+        if (nchunks && parts) k_agg_part_bucket<W_F32><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
+        if (nchunks && !parts) k_agg_hub_chunks<W_F32><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     } else {
         if (us) k_agg_small<W_F64><<<gs, kBlock, 0, s>>>(a);
         if (ul) k_agg_large<W_F64><<<gl, kBlock, 0, s>>>(a);
-        if (nchunks) k_agg_hub_chunks<W_F64><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
+        if (nchunks && parts) k_agg_part_bucket<W_F64><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
+        if (nchunks && !parts) k_agg_hub_chunks<W_F64><<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     }
+    if (nchunks && parts) k_agg_part_gather<<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     if (nsegs) k_agg_hub_emit<<<(unsigned)(nsegs < 8192 ? nsegs : 8192), kBlock, 0, s>>>(a, sc.cseg_comm, sc.cseg_beg, nsegs);
     // compact
     scan_exclusive_i32_to_i64(out.deg, out.off, n2, sc.scan_tmp, s);

@@ -546,48 +546,6 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
 // it.  Each (chunk, community) pair is written once and read once; nothing
 // goes through a global hash table.
 
-// Partition of community c among P (high bits of a second mix, independent
-// of the LDS slot hash).
-__device__ __forceinline__ int part_of(int c, int P) {
-    uint32_t h = (uint32_t)c;
-    h ^= h >> 16;
-    h *= 0x85EBCA6Bu;
-    h ^= h >> 13;
-    h *= 0xC2B2AE35u;
-    h ^= h >> 16;
-    return (int)(((uint64_t)h * (uint64_t)(uint32_t)P) >> 32);
-}
-
-// Exclusive scan of v[0..P) in place over the block, v[P] = total.
-__device__ void block_scan_excl(int *v, int P) {
-    __shared__ int part[kBlock + 1];
-    const int tid = threadIdx.x;
-    const int per = (P + kBlock - 1) / kBlock;
-    const int b0 = tid * per, b1 = b0 + per < P ? b0 + per : P;
-    int sum = 0;
-    for (int b = b0; b < b1; b++) sum += v[b];
-    part[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-        int run = 0;
-        for (int q = 0; q < kBlock; q++) {
-            int x = part[q];
-            part[q] = run;
-            run += x;
-        }
-        part[kBlock] = run;
-    }
-    __syncthreads();
-    int run = part[tid];
-    for (int b = b0; b < b1; b++) {
-        int x = v[b];
-        v[b] = run;
-        run += x;
-    }
-    if (tid == 0) v[P] = part[kBlock];
-    __syncthreads();
-}
-
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
     __shared__ int tkeys[kBlockTable];
@@ -648,16 +606,6 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
         __syncthreads();
     }
     flush_acc(acc, a.ctr, 3);
-}
-
-// Largest s in [0, n) with v[s] <= t (v non-decreasing, v[0] = 0 <= t).
-__device__ __forceinline__ int last_le(const int *v, int n, int t) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (v[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
 }
 
 __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {

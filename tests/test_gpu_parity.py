@@ -341,3 +341,44 @@ def test_hub_partition_overflow_falls_back(ctx):
     m, li, dq, mv = ctx.move_phase(None, tolerance=0.0)
     ref = oracle.move_sync(g, tau=0.0)
     assert np.array_equal(m, ref[0]) and li == ref[1]
+
+
+def _check_aggregate(ctx, g, m):
+    mr, G = oracle.renumber(m)
+    ref = oracle.aggregate(g, mr, G)
+    n2, off, col, w = ctx.step_aggregate(m)
+    assert n2 == G
+    np.testing.assert_array_equal(off, ref.off)
+    for (c1, w1), (c2, w2) in zip(_canonical_rows(n2, off, col, w), _canonical_rows(G, ref.off, ref.col, ref.w)):
+        np.testing.assert_array_equal(c1, c2)
+        np.testing.assert_array_equal(w1, w2)
+
+
+def test_aggregate_giant_communities(ctx):
+    """Giant communities with many distinct neighbour communities go through
+    hash partitions: 70% of the vertices in one community and the rest
+    singletons (about 26 partitions, more than 2048 chunks, so the gather
+    takes its source chunks in several windows), and eight giant communities
+    beside singletons; rows bit-exact against the oracle."""
+    g = gi.rmat_small(17, 5)
+    _load(ctx, g)
+    n = g.n
+    cut = (7 * n) // 10
+    big = np.where(np.arange(n) < cut, 0, np.arange(n)).astype(np.int32)
+    assert int(g.offsets[cut]) > 2048 * 1024          # > 2048 chunks of 1024 entries
+    _check_aggregate(ctx, g, big)
+    eight = np.where(np.arange(n) % 3 == 0, (np.arange(n) % 8), np.arange(n)).astype(np.int32)
+    _check_aggregate(ctx, g, eight)
+
+
+def test_aggregate_partition_spill(ctx):
+    """A giant community whose neighbour communities all fall in one hash
+    partition overflows that partition's LDS table: its pairs go through the
+    community's global table instead, with the same row."""
+    n = 20000
+    P = 3                                            # total degree 4200, n2 = n -> 3 partitions
+    nb = [j for j in range(1, n) if _part_of(j, P) == 0][:4200]
+    edges = [(0, j) for j in nb] + [(j, j + 1) for j in range(1, n - 1)]
+    g = gi.from_edges(n, edges)
+    _load(ctx, g)
+    _check_aggregate(ctx, g, np.arange(n, dtype=np.int32))
