@@ -149,14 +149,39 @@ __device__ __forceinline__ void fold_key(const MoveArgs &a, double m2, int key, 
     }
 }
 
+// Value type of the wave and workgroup LDS tables: on unit weights every
+// K_{i->c} is a count (< 2^31), kept as an int (8-byte slots, a quarter
+// more resident waves); otherwise the fp64 sum.
+template <int WT> struct TabVal { using T = double; };
+template <> struct TabVal<W_UNIT> { using T = int; };
+
+__device__ __forceinline__ void lds_count_add(int *keys, int *vals, uint32_t mask, int key) {
+    uint32_t s = key_hash(key) & mask;
+    while (true) {
+        int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            atomicAdd(&vals[s], 1);
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+__device__ __forceinline__ void lds_table_put(int *keys, int *vals, uint32_t mask, int key, double) {
+    lds_count_add(keys, vals, mask, key);
+}
+__device__ __forceinline__ void lds_table_put(int *keys, double *vals, uint32_t mask, int key, double w) {
+    lds_table_add(keys, vals, mask, key, w);
+}
+
 // Reads one table slot, resets it and folds it into (bg, bc, kid).
-__device__ __forceinline__ void take_slot(const MoveArgs &a, double m2, int *keys, double *vals, int64_t s, int d,
+template <typename V>
+__device__ __forceinline__ void take_slot(const MoveArgs &a, double m2, int *keys, V *vals, int64_t s, int d,
                                           double ki, double &bg, int &bc, double &kid, unsigned long long &nkeys) {
     int key = keys[s];
     if (key == kEmpty) return;
-    double v = vals[s];
+    double v = (double)vals[s];
     keys[s] = kEmpty;
-    vals[s] = 0.0;
+    vals[s] = 0;
     nkeys++;
     if (key == d) {
         kid = v;
@@ -299,7 +324,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
 }
 
 template <int WT>
-__global__ void __launch_bounds__(kBlock) k_move_small(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, 5) k_move_small(MoveArgs a) {
     __shared__ int tkeys[2 * kBlock];
     __shared__ double tvals[2 * kBlock];
     const int w = threadIdx.x / kWave;
@@ -354,14 +379,15 @@ __device__ void block_argmax_sum(double &bg, int &bc, double &x) {
 // One wavefront per vertex of 65..512 entries, 1024-slot table in its LDS.
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
+    using V = typename TabVal<WT>::T;
     __shared__ int tkeys[kBlock / kWave * kWaveTable];
-    __shared__ double tvals[kBlock / kWave * kWaveTable];
+    __shared__ V tvals[kBlock / kWave * kWaveTable];
     const int w = threadIdx.x / kWave, lane = lane_id();
     int *keys = tkeys + w * kWaveTable;
-    double *vals = tvals + w * kWaveTable;
+    V *vals = tvals + w * kWaveTable;
     for (int k = lane; k < kWaveTable; k += kWave) {
         keys[k] = kEmpty;
-        vals[k] = 0.0;
+        vals[k] = 0;
     }
     wave_lds_sync();
     const int cnt = a.ctr->qcnt[a.round][BIN_WAVE];
@@ -375,11 +401,23 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         int d = a.cm[i];
         double ki = a.K[i];
         const int T = (int)hub_table_size(di);   // <= kWaveTable: at most half full
-        for (int e = lane; e < di; e += kWave) {
-            int j = load_col(a.g.col, beg + e);
-            double wt = edge_weight<WT>(a.g.w, beg + e);
-            if (j != i) lds_table_add(keys, vals, T - 1, a.cm[j], wt);
+        // the lane's entries (at most R) are loaded together, then their
+        // memberships: two round trips to memory instead of 2R
+        constexpr int R = kWaveMaxDeg / kWave;
+        int jj[R];
+        double ww[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int e = lane + r * kWave;
+            jj[r] = e < di ? load_col(a.g.col, beg + e) : i;
+            ww[r] = e < di ? edge_weight<WT>(a.g.w, beg + e) : 0.0;
         }
+        int cj[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) cj[r] = jj[r] != i ? a.cm[jj[r]] : kEmpty;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (cj[r] != kEmpty) lds_table_put(keys, vals, T - 1, cj[r], ww[r]);
         wave_lds_sync();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
@@ -389,10 +427,9 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         double gain = 0.0;
         bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (mv)
-            for (int e = lane; e < di; e += kWave) {
-                int j = load_col(a.g.col, beg + e);
-                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
-            }
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (jj[r] != i) mark_neighbour(a, jj[r], ww[r]);
         if (lane == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
@@ -413,12 +450,13 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
 // One workgroup per vertex of 513..2048 entries, 4096-slot table in LDS.
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
+    using V = typename TabVal<WT>::T;
     __shared__ int keys[kBlockTable];
-    __shared__ double vals[kBlockTable];
+    __shared__ V vals[kBlockTable];
     const int tid = threadIdx.x;
     for (int k = tid; k < kBlockTable; k += kBlock) {
         keys[k] = kEmpty;
-        vals[k] = 0.0;
+        vals[k] = 0;
     }
     __syncthreads();
     const int cnt = a.ctr->qcnt[a.round][BIN_BLOCK];
@@ -431,11 +469,21 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         int d = a.cm[i];
         double ki = a.K[i];
         const int T = (int)hub_table_size(di);   // <= kBlockTable: at most half full
-        for (int e = tid; e < di; e += kBlock) {
-            int j = load_col(a.g.col, beg + e);
-            double wt = edge_weight<WT>(a.g.w, beg + e);
-            if (j != i) lds_table_add(keys, vals, T - 1, a.cm[j], wt);
+        constexpr int R = kBlockMaxDeg / kBlock;   // entries per thread, loaded together
+        int jj[R];
+        double ww[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int e = tid + r * kBlock;
+            jj[r] = e < di ? load_col(a.g.col, beg + e) : i;
+            ww[r] = e < di ? edge_weight<WT>(a.g.w, beg + e) : 0.0;
         }
+        int cj[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) cj[r] = jj[r] != i ? a.cm[jj[r]] : kEmpty;
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (cj[r] != kEmpty) lds_table_put(keys, vals, T - 1, cj[r], ww[r]);
         __syncthreads();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
@@ -444,10 +492,9 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         double gain = 0.0;
         bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (mv)
-            for (int e = tid; e < di; e += kBlock) {
-                int j = load_col(a.g.col, beg + e);
-                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
-            }
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (jj[r] != i) mark_neighbour(a, jj[r], ww[r]);
         if (tid == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;

@@ -11,6 +11,19 @@
 // one-thread BFS from the lowest unvisited vertex gives.  Parent pointers
 // only decrease, so path halving with plain (agent-scope) stores is safe
 // while hooking; the final compression walks without halving (see there).
+//
+// Most of a community is usually one component, so the edges are taken in
+// the order of the sampling scheme of Sutton et al. ("Optimizing parallel
+// graph connectivity computation via subgraph sampling", IPDPS 2018): each
+// vertex first links to those of its first kSample neighbours that share its
+// community,
+// the forest is compressed, and one root per community is picked by a
+// vertex of it at random (usually that of its largest component).  A vertex
+// already in the picked root's tree then skips its row: an edge from it to
+// a vertex outside that tree is linked from the other end, whose row is
+// scanned in full (every edge is stored in both rows); an edge inside the
+// tree joins nothing new.  The components, hence the labels, are the same
+// as with every edge linked.
 #include "gsp_internal.h"
 
 namespace gsp {
@@ -49,7 +62,44 @@ __device__ void unite(int32_t *parent, int a, int b) {
 }
 
 __device__ __forceinline__ void hook_entry(int32_t *parent, const int32_t *cm, int i, int ci, int j) {
-    if (j < i && cm[j] == ci) unite(parent, i, j);
+    if (j != i && cm[j] == ci) unite(parent, i, j);
+}
+
+// Sampling: every vertex links to those of its first kSample neighbours that
+// share its community.  (With few entries inside communities, as on
+// power-law graphs after a first local-moving phase, eight leave about 5 %
+// of the vertices outside the picked trees.)
+constexpr int kSample = 8;
+
+__global__ void __launch_bounds__(kBlock) k_split_sample(Level g, const int32_t *cm, int32_t *parent) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * kBlock) {
+        const int d = g.deg[i] < kSample ? g.deg[i] : kSample;
+        if (d == 0) continue;
+        const int ci = cm[i];
+        const int64_t b = g.off[i];
+        int j[kSample];
+#pragma unroll
+        for (int r = 0; r < kSample; r++) j[r] = r < d ? g.col[b + r] : (int)i;
+        int c[kSample];
+#pragma unroll
+        for (int r = 0; r < kSample; r++) c[r] = j[r] != (int)i ? cm[j[r]] : -1;
+        for (int r = 0; r < d; r++)
+            if (c[r] == ci) unite(parent, (int)i, j[r]);
+    }
+}
+
+// The picked root of each community: that of some vertex of it (racing
+// plain stores; any winner will do).
+__global__ void __launch_bounds__(kBlock) k_split_pick(const int32_t *parent, const int32_t *cm, int64_t n,
+                                                      int32_t *dom) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dom[cm[i]] = parent[i];
+}
+
+// Vertex i may skip its row: it hangs directly under its community's picked
+// root (parents only move to ancestors, so it stays in that tree).
+__device__ __forceinline__ bool settled(const int32_t *parent, const int32_t *dom, int i, int ci) {
+    return ld(parent + i) == dom[ci];
 }
 
 // All vertices of the level through its work lists: groups of G lanes for
@@ -62,7 +112,7 @@ struct BinRanges {
 __global__ void __launch_bounds__(kBlock) k_split_hook(Level g, const int32_t *bl, BinRanges br,
                                                       const int32_t *ch_vert,
                                                       const int64_t *ch_beg, int64_t nchunks, const int32_t *cm,
-                                                      int32_t *parent) {
+                                                      const int32_t *dom, int32_t *parent) {
     const int64_t *binb = br.beg, *binn = br.n;
     int64_t pre[kNumSmallBins + 1];
     pre[0] = 0;
@@ -83,7 +133,8 @@ __global__ void __launch_bounds__(kBlock) k_split_hook(Level g, const int32_t *b
             int gl = threadIdx.x % G;
             if (qi < binn[b]) {
                 int i = bl[binb[b] + qi];
-                if (gl < g.deg[i]) hook_entry(parent, cm, i, cm[i], g.col[g.off[i] + gl]);
+                int ci = cm[i];
+                if (gl < g.deg[i] && !settled(parent, dom, i, ci)) hook_entry(parent, cm, i, ci, g.col[g.off[i] + gl]);
             }
         } else if (u < pre[kNumSmallBins] + uw) {
             int64_t qi = (u - pre[kNumSmallBins]) * (kBlock / kWave) + threadIdx.x / kWave;
@@ -92,7 +143,8 @@ __global__ void __launch_bounds__(kBlock) k_split_hook(Level g, const int32_t *b
                 int i = bl[binb[BIN_WAVE] + qi];
                 int ci = cm[i];
                 int64_t beg = g.off[i];
-                for (int e = lane_id(); e < g.deg[i]; e += kWave) hook_entry(parent, cm, i, ci, g.col[beg + e]);
+                if (!settled(parent, dom, i, ci))
+                    for (int e = lane_id(); e < g.deg[i]; e += kWave) hook_entry(parent, cm, i, ci, g.col[beg + e]);
             }
         } else {
             int64_t k = u - pre[kNumSmallBins] - uw;
@@ -101,7 +153,8 @@ __global__ void __launch_bounds__(kBlock) k_split_hook(Level g, const int32_t *b
             int64_t beg = ch_beg[k];
             int64_t end = g.off[i] + g.deg[i];
             if (end > beg + kHubChunk) end = beg + kHubChunk;
-            for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) hook_entry(parent, cm, i, ci, g.col[e]);
+            if (!settled(parent, dom, i, ci))
+                for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) hook_entry(parent, cm, i, ci, g.col[e]);
         }
     }
 }
@@ -177,9 +230,13 @@ inline unsigned grid1(int64_t n) {
 
 }  // namespace
 
-void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, hipStream_t s) {
+void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, int32_t *dom,
+                  hipStream_t s) {
     if (g.n == 0) return;
     launch_iota_i32(labels, g.n, s);
+    k_split_sample<<<grid1(g.n), kBlock, 0, s>>>(g, cm, labels);
+    k_split_compress<<<grid1(g.n), kBlock, 0, s>>>(labels, g.n);
+    k_split_pick<<<grid1(g.n), kBlock, 0, s>>>(labels, cm, g.n, dom);
     // per-bin begin/size over all sub-rounds (buckets of a bin are adjacent)
     BinRanges br;
     for (int b = 0; b < kNumBins; b++) {
@@ -194,7 +251,7 @@ void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_
     units += (wl.bin_size(BIN_WAVE) + wl.bin_size(BIN_BLOCK) + 3) / 4 + wl.nchunks;
     if (units > 0) {
         unsigned gr = (unsigned)(units < 65536 ? units : 65536);
-        k_split_hook<<<gr, kBlock, 0, s>>>(g, wl.bl, br, wl.ch_vert, wl.ch_beg, wl.nchunks, cm, labels);
+        k_split_hook<<<gr, kBlock, 0, s>>>(g, wl.bl, br, wl.ch_vert, wl.ch_beg, wl.nchunks, cm, dom, labels);
     }
     k_split_compress<<<grid1(g.n), kBlock, 0, s>>>(labels, g.n);
 }
