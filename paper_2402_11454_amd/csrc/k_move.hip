@@ -194,6 +194,47 @@ __device__ __forceinline__ void take_slot(const MoveArgs &a, double m2, int *key
     }
 }
 
+// Scores a whole table of T slots with NT threads (t = this thread's
+// index), resetting it: each thread reads CH slots, then the Sigma of their
+// communities together, then folds them.  The argmax does not depend on the
+// order of the slots.
+template <int NT, int CH, typename V>
+__device__ __forceinline__ void fold_table(const MoveArgs &a, double m2, int *keys, V *vals, int T, int t, int d,
+                                           double ki, double &bg, int &bc, double &kid,
+                                           unsigned long long &nkeys) {
+    for (int s0 = 0; s0 < T; s0 += NT * CH) {
+        int key[CH];
+        double v[CH], sg[CH];
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int sl = s0 + u * NT + t;
+            key[u] = sl < T ? keys[sl] : kEmpty;
+            v[u] = 0.0;
+            if (key[u] != kEmpty) {
+                v[u] = (double)vals[sl];
+                keys[sl] = kEmpty;
+                vals[sl] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u++) sg[u] = (key[u] != kEmpty && key[u] != d) ? a.sig[key[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            if (key[u] == kEmpty) continue;
+            nkeys++;
+            if (key[u] == d) {
+                kid = v[u];
+            } else {
+                double g = m2 * v[u] - ki * sg[u];
+                if (better(g, key[u], bg, bc)) {
+                    bg = g;
+                    bc = key[u];
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- compact
 
 // Unprocessed vertices of the sub-round's buckets -> per-bin queues (or,
@@ -378,7 +419,7 @@ __device__ void block_argmax_sum(double &bg, int &bc, double &x) {
 
 // One wavefront per vertex of 65..512 entries, 1024-slot table in its LDS.
 template <int WT>
-__global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, 4) k_move_wave(MoveArgs a) {
     using V = typename TabVal<WT>::T;
     __shared__ int tkeys[kBlock / kWave * kWaveTable];
     __shared__ V tvals[kBlock / kWave * kWaveTable];
@@ -421,15 +462,16 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
         wave_lds_sync();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int s = lane; s < T; s += kWave) take_slot(a, m2, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        fold_table<kWave, 4>(a, m2, keys, vals, T, lane, d, ki, bg, bc, kid, acc.keys);
         group_argmax<kWave>(bg, bc);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
         bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
-        if (mv)
-#pragma unroll
-            for (int r = 0; r < R; r++)
-                if (jj[r] != i) mark_neighbour(a, jj[r], ww[r]);
+        if (mv)   // entries reloaded: keeping them would cost registers across the scoring
+            for (int e = lane; e < di; e += kWave) {
+                int j = load_col(a.g.col, beg + e);
+                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
+            }
         if (lane == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
@@ -449,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(MoveArgs a) {
 
 // One workgroup per vertex of 513..2048 entries, 4096-slot table in LDS.
 template <int WT>
-__global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, 4) k_move_block(MoveArgs a) {
     using V = typename TabVal<WT>::T;
     __shared__ int keys[kBlockTable];
     __shared__ V vals[kBlockTable];
@@ -487,14 +529,15 @@ __global__ void __launch_bounds__(kBlock) k_move_block(MoveArgs a) {
         __syncthreads();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int s = tid; s < T; s += kBlock) take_slot(a, m2, keys, vals, s, d, ki, bg, bc, kid, acc.keys);
+        fold_table<kBlock, 4>(a, m2, keys, vals, T, tid, d, ki, bg, bc, kid, acc.keys);
         block_argmax_sum(bg, bc, kid);
         double gain = 0.0;
         bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
         if (mv)
-#pragma unroll
-            for (int r = 0; r < R; r++)
-                if (jj[r] != i) mark_neighbour(a, jj[r], ww[r]);
+            for (int e = tid; e < di; e += kBlock) {
+                int j = load_col(a.g.col, beg + e);
+                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
+            }
         if (tid == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
@@ -595,13 +638,14 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
 
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
+    using V = typename TabVal<WT>::T;
     __shared__ int tkeys[kBlockTable];
-    __shared__ double tvals[kBlockTable];
+    __shared__ V tvals[kBlockTable];
     __shared__ int pcnt[kMaxParts + 1];
     const int tid = threadIdx.x;
     for (int k = tid; k < kBlockTable; k += kBlock) {
         tkeys[k] = kEmpty;
-        tvals[k] = 0.0;
+        tvals[k] = 0;
     }
     __syncthreads();
     Acc acc;
@@ -621,10 +665,22 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
         int64_t end = a.g.off[i] + di;
         if (end > beg + kHubChunk) end = beg + kHubChunk;
         int s = (int)((beg - a.g.off[i]) / kHubChunk);
-        for (int64_t e = beg + tid; e < end; e += kBlock) {
-            int j = load_col(a.g.col, e);
-            double wt = edge_weight<WT>(a.g.w, e);
-            if (j != i) lds_table_add(tkeys, tvals, kBlockTable - 1, a.cm[j], wt);
+        {
+            constexpr int R = kHubChunk / kBlock;   // entries per thread, loaded together
+            int jj[R];
+            double ww[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int64_t e = beg + tid + r * kBlock;
+                jj[r] = e < end ? load_col(a.g.col, e) : i;
+                ww[r] = e < end ? edge_weight<WT>(a.g.w, e) : 0.0;
+            }
+            int cj[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) cj[r] = jj[r] != i ? a.cm[jj[r]] : kEmpty;
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (cj[r] != kEmpty) lds_table_put(tkeys, tvals, kBlockTable - 1, cj[r], ww[r]);
         }
         for (int b = tid; b <= P; b += kBlock) pcnt[b] = 0;
         __syncthreads();
@@ -641,9 +697,9 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
         for (int sl = tid; sl < kBlockTable; sl += kBlock) {
             int key = tkeys[sl];
             if (key == kEmpty) continue;
-            double v = tvals[sl];
+            double v = (double)tvals[sl];
             tkeys[sl] = kEmpty;
-            tvals[sl] = 0.0;
+            tvals[sl] = 0;
             int pos = atomicAdd(&pcnt[part_of(key, P)], 1);
             a.skey[beg + pos] = key;
             a.sval[beg + pos] = v;
@@ -655,16 +711,23 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
     flush_acc(acc, a.ctr, 3);
 }
 
+// Per partition of an active hub: merges the partition's pairs from every
+// chunk of the hub (source chunks taken kHubWin at a time) in one LDS table
+// and scores it.  On unit weights the values are counts (int slots).
+constexpr int kHubWin = 512;
+
+template <int WT>
 __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
+    using V = typename TabVal<WT>::T;
     __shared__ int tkeys[kBlockTable];
-    __shared__ double tvals[kBlockTable];
-    __shared__ int pst[kMaxParts + 1];
-    __shared__ short srcst[kMaxParts];   // this partition's start within each source chunk
+    __shared__ V tvals[kBlockTable];
+    __shared__ int pst[kHubWin + 1];
+    __shared__ short srcst[kHubWin];   // this partition's start within each source chunk
     __shared__ int nkeys, ovf;
     const int tid = threadIdx.x;
     for (int k = tid; k < kBlockTable; k += kBlock) {
         tkeys[k] = kEmpty;
-        tvals[k] = 0.0;
+        tvals[k] = 0;
     }
     __syncthreads();
     Acc acc;
@@ -675,52 +738,54 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
         int P = (di + kHubChunk - 1) / kHubChunk;
         int p = (int)((a.ch_beg[k] - a.g.off[i]) / kHubChunk);
         const uint32_t *words = a.hbuck + a.hub_b0[i];
-        for (int s = tid; s < P; s += kBlock) {
-            uint32_t wd = words[(int64_t)s * P + p];
-            pst[s] = (int)(wd & 0xFFFFu);
-            srcst[s] = (short)(wd >> 16);
-        }
+        const int64_t base = a.g.off[i];
         if (tid == 0) {
             nkeys = 0;
             ovf = 0;
-        }
-        __syncthreads();
-        block_scan_excl(pst, P);
-        const int total = pst[P];
-        const int64_t base = a.g.off[i];
-        if (tid == 0) {
             acc.verts++;   // chunks (partitions) gathered
-            acc.ginserts += (unsigned long long)total;
             acc.aux += (unsigned long long)P;
         }
-        for (int t = tid; t < total; t += kBlock) {
-            if (*(volatile int *)&ovf) break;
-            int s = last_le(pst, P, t);
-            int64_t idx = base + (int64_t)s * kHubChunk + (int64_t)srcst[s] + (t - pst[s]);
-            int key = a.skey[idx];
-            double v = a.sval[idx];
-            // insert, counting distinct keys; past kPartCap the partition
-            // stops (at most kBlock inserts overshoot: the table never fills)
-            uint32_t sl = key_hash(key) & (kBlockTable - 1);
-            while (true) {
-                int prev = atomicCAS(&tkeys[sl], kEmpty, key);
-                if (prev == kEmpty) {
-                    if (atomicAdd(&nkeys, 1) >= kPartCap) ovf = 1;
-                    atomicAdd(&tvals[sl], v);
-                    break;
-                }
-                if (prev == key) {
-                    atomicAdd(&tvals[sl], v);
-                    break;
-                }
-                sl = (sl + 1) & (kBlockTable - 1);
+        for (int w0 = 0; w0 < P; w0 += kHubWin) {
+            const int nw = P - w0 < kHubWin ? P - w0 : kHubWin;
+            for (int s = tid; s < nw; s += kBlock) {
+                uint32_t wd = words[(int64_t)(w0 + s) * P + p];
+                pst[s] = (int)(wd & 0xFFFFu);
+                srcst[s] = (short)(wd >> 16);
             }
+            __syncthreads();
+            block_scan_excl(pst, nw);
+            const int total = pst[nw];
+            if (tid == 0) acc.ginserts += (unsigned long long)total;
+            for (int t = tid; t < total; t += kBlock) {
+                if (*(volatile int *)&ovf) break;
+                int s = last_le(pst, nw, t);
+                int64_t idx = base + (int64_t)(w0 + s) * kHubChunk + (int64_t)srcst[s] + (t - pst[s]);
+                int key = a.skey[idx];
+                double v = a.sval[idx];
+                // insert, counting distinct keys; past kPartCap the partition
+                // stops (at most kBlock inserts overshoot: the table never fills)
+                uint32_t sl = key_hash(key) & (kBlockTable - 1);
+                while (true) {
+                    int prev = atomicCAS(&tkeys[sl], kEmpty, key);
+                    if (prev == kEmpty) {
+                        if (atomicAdd(&nkeys, 1) >= kPartCap) ovf = 1;
+                        atomicAdd(&tvals[sl], (V)v);
+                        break;
+                    }
+                    if (prev == key) {
+                        atomicAdd(&tvals[sl], (V)v);
+                        break;
+                    }
+                    sl = (sl + 1) & (kBlockTable - 1);
+                }
+            }
+            __syncthreads();
+            if (ovf) break;
         }
-        __syncthreads();
         if (ovf) {   // rare: this hub goes through the global-table path
             for (int q = tid; q < kBlockTable; q += kBlock) {
                 tkeys[q] = kEmpty;
-                tvals[q] = 0.0;
+                tvals[q] = 0;
             }
             if (tid == 0) {
                 a.hub_act[i] = 3;
@@ -734,7 +799,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
         const double m2 = m2_of(a, i);
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
-        for (int q = tid; q < kBlockTable; q += kBlock) take_slot(a, m2, tkeys, tvals, q, d, ki, bg, bc, kid, acc.keys);
+        fold_table<kBlock, 8>(a, m2, tkeys, tvals, kBlockTable, tid, d, ki, bg, bc, kid, acc.keys);
         block_argmax_sum(bg, bc, kid);
         if (tid == 0) {
             a.part_g[k] = bg;
@@ -1022,7 +1087,11 @@ void launch_move_hub_parts(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_hub_gather(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    k_hub_gather<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
+    unsigned gr = cap_grid(a.ch_count, 4096);
+    if (a.g.wt == W_UNIT)
+        k_hub_gather<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+    else
+        k_hub_gather<W_F64><<<gr, kBlock, 0, s>>>(a);   // staged values are fp64 sums
 }
 
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
