@@ -72,19 +72,13 @@ __device__ __forceinline__ void hook_entry(int32_t *parent, const int32_t *cm, i
 constexpr int kSample = 8;
 
 __global__ void __launch_bounds__(kBlock) k_split_sample(Level g, const int32_t *cm, int32_t *parent) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * kBlock) {
-        const int d = g.deg[i] < kSample ? g.deg[i] : kSample;
-        if (d == 0) continue;
-        const int ci = cm[i];
-        const int64_t b = g.off[i];
-        int j[kSample];
-#pragma unroll
-        for (int r = 0; r < kSample; r++) j[r] = r < d ? g.col[b + r] : (int)i;
-        int c[kSample];
-#pragma unroll
-        for (int r = 0; r < kSample; r++) c[r] = j[r] != (int)i ? cm[j[r]] : -1;
-        for (int r = 0; r < d; r++)
-            if (c[r] == ci) unite(parent, (int)i, j[r]);
+    // one thread per (vertex, sample): the unions of a vertex run side by side
+    const int64_t total = g.n * kSample;
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < total; t += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(t / kSample), r = (int)(t % kSample);
+        if (r >= g.deg[i]) continue;
+        const int j = g.col[g.off[i] + r];
+        if (j != i && cm[j] == cm[i]) unite(parent, i, j);
     }
 }
 
@@ -234,7 +228,7 @@ void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_
                   hipStream_t s) {
     if (g.n == 0) return;
     launch_iota_i32(labels, g.n, s);
-    k_split_sample<<<grid1(g.n), kBlock, 0, s>>>(g, cm, labels);
+    k_split_sample<<<grid1(g.n * kSample), kBlock, 0, s>>>(g, cm, labels);
     k_split_compress<<<grid1(g.n), kBlock, 0, s>>>(labels, g.n);
     k_split_pick<<<grid1(g.n), kBlock, 0, s>>>(labels, cm, g.n, dom);
     // per-bin begin/size over all sub-rounds (buckets of a bin are adjacent)
