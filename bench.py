@@ -9,7 +9,9 @@ memory; `warmup` untimed runs and `steps` timed runs of gsp_run (tolerance
 Prints ONE JSON line: edges/s = directed CSR entries / seconds per run of the
 plain method; a roofline object for the dominant single-kernel class (its
 algorithmic bytes from the library's counters over its HIP-event time,
-events recorded around that class only, inside the timed region); the
+events recorded around that class only, inside the timed region; with
+per-kernel events on, a sweep's scans run one after another); the same runs
+without events (scans side by side) as config.untimed; the
 learned-pruned method on the same graph (its edges/s, modularity and ratio
 to plain, the network trained on the degree-corrected SBM workload); and a
 CPU baseline: the sequential oracle timed on one host core on the same
@@ -55,6 +57,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-learned", action="store_true")
     p.add_argument("--timing", type=int, default=2, help="0: no per-kernel events (no roofline)")
+    p.add_argument("--no-untimed", action="store_true", help="skip the runs without per-kernel events")
     return p.parse_args()
 
 
@@ -124,13 +127,20 @@ def main():
         ctx.run(a.tolerance, a.max_passes)
     print(f"[bench] {a.warmup} warm-up runs done", file=sys.stderr, flush=True)
 
-    # which single-kernel class dominates (one probe run, every class timed)
+    # which single-kernel class dominates: one probe run per class with only
+    # that class's events (events around every kernel would slow the host and
+    # inflate the short kernels' times)
     dom = None
     if a.timing >= 2:
-        ctx.run(a.tolerance, a.max_passes, timing=2)
-        st = ctx.stats()["kernels"]
-        cand = {k: v["ms"] for k, v in st.items() if k in KERNEL_NAMES and v["ms"] > 0}
+        cand = {}
+        for k in KERNEL_NAMES:
+            ctx.run(a.tolerance, a.max_passes, timing=2, timing_mask=1 << gsp.KERNEL_CLASSES.index(k))
+            ms = ctx.stats()["kernels"][k]["ms"]
+            if ms > 0:
+                cand[k] = ms
         dom = max(cand, key=cand.get) if cand else None
+        print("[bench] probe ms per class: " + ", ".join(f"{k} {v:.3f}" for k, v in sorted(cand.items())),
+              file=sys.stderr, flush=True)
     mask = (1 << gsp.KERNEL_CLASSES.index(dom)) if dom else 0
 
     # timed region: `steps` whole runs of the plain method, graph resident in HBM
@@ -143,6 +153,14 @@ def main():
     st = ctx.stats()
     print(f"[bench] plain: {a.steps} runs, {ms_per_step:.3f} ms/run, Q={q:.6f}, disconnected={disc}, "
           f"passes={st['passes']} iterations={st['iterations']}", file=sys.stderr, flush=True)
+
+    # the same runs without per-kernel events (the scans of a sub-round then
+    # run side by side on four streams): context beside the timed value
+    untimed = None
+    if dom and not a.no_untimed:
+        el0, _ = timed_runs(ctx, gsp, a, a.steps, timing=0)
+        untimed = {"ms_per_step": round(1000.0 * el0 / a.steps, 4), "value": round(g.nnz / (el0 / a.steps), 1)}
+        print(f"[bench] plain, no per-kernel events: {untimed['ms_per_step']:.3f} ms/run", file=sys.stderr, flush=True)
 
     roofline = None
     if dom:
@@ -199,7 +217,7 @@ def main():
                                f"GSP-Louvain tol {a.tolerance}, "
                                f"<= {a.max_passes} passes, 8 sub-rounds; value = plain method",
                    "n": g.n, "nnz": g.nnz, "modularity": round(q, 6), "disconnected": disc,
-                   "passes": st["passes"], "prune": "plain", "learned": learned},
+                   "passes": st["passes"], "prune": "plain", "learned": learned, "untimed": untimed},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -22,6 +22,7 @@ namespace {
 struct EventPair {
     int cls;
     hipEvent_t a, b;
+    hipStream_t st;
 };
 
 // Records HIP events around phases / kernel classes and sums them later.
@@ -33,7 +34,9 @@ struct Timer {
     hipEvent_t get() {
         if (used == pool.size()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // timing only (read after a stream synchronisation): no system
+            // fence, which would write back and invalidate the caches
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             pool.push_back(e);
         }
         return pool[used++];
@@ -43,16 +46,18 @@ struct Timer {
         open.clear();
     }
     uint32_t kmask = 0;   // kernel classes (100 + k) to time; 0 = all
-    int begin(int cls) {
+    // st: the stream the timed work goes to (default: the context's)
+    int begin(int cls, hipStream_t st = nullptr) {
         if (cls >= 100 && kmask && !((kmask >> (cls - 100)) & 1u)) return -1;
         hipEvent_t a = get(), b = get();
         if (!a || !b) return -1;
-        (void)hipEventRecord(a, s);
-        open.push_back({cls, a, b});
+        if (!st) st = s;
+        (void)hipEventRecord(a, st);
+        open.push_back({cls, a, b, st});
         return (int)open.size() - 1;
     }
     void end(int k) {
-        if (k >= 0) (void)hipEventRecord(open[k].b, s);
+        if (k >= 0) (void)hipEventRecord(open[k].b, open[k].st);
     }
     // Adds elapsed ms per class into out[cls].
     void collect(double *out, int ncls) {
@@ -76,6 +81,11 @@ struct gsp_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;   // where sweeps are captured into graphs
+    // the independent scans of a sub-round (wave bin, workgroup bin, hubs)
+    // run on side streams beside the small-bin scan; fork / join events per
+    // sub-round and side stream
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> fork_ev, join_ev;
     bool hub_parts = true;              // hubs by hash partitions (else global tables only); per run
     // instantiated sweep graphs, reused while the level and its work lists
     // (everything a sweep's launches take as arguments) are the same
@@ -428,6 +438,23 @@ GateNet net_of(const gsp_ctx *ctx) {
     return net;
 }
 
+// Side streams (default priority) and the fork / join events of P sub-rounds.
+gsp_status ensure_side(gsp_ctx *ctx, int P) {
+    for (hipStream_t &q : ctx->side)
+        if (!q) HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    while ((int)ctx->fork_ev.size() < P) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->fork_ev.push_back(e);
+    }
+    while ((int)ctx->join_ev.size() < 3 * P) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->join_ev.push_back(e);
+    }
+    return GSP_OK;
+}
+
 // The local-moving phase on level g (Algorithm "louvainMove" in ordered
 // sub-rounds).  cm/sig/csize hold the starting state.
 //
@@ -442,6 +469,10 @@ GateNet net_of(const gsp_ctx *ctx) {
 gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkLists &wl, PhaseCfg &cfg) {
     hipStream_t s = ctx->stream;
     int P = wl.rounds;
+    {
+        gsp_status st = ensure_side(ctx, P);
+        if (st != GSP_OK) return st;
+    }
     const bool hist = cfg.gated || ctx->tracing;
     if (hist) {
         gsp_status st = ensure_gate_state(ctx);
@@ -471,6 +502,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     // One sweep: clear its counters (a fill kernel, so that the sweep can be
     // captured), then every sub-round's kernels, on stream cs.
     auto enqueue_sweep = [&](int sweep, IterCounters *ctr, hipStream_t cs) {
+        int64_t *launches = ctx->kernel_launches;
         launch_fill_u64(reinterpret_cast<unsigned long long *>(ctr), 0, sizeof(IterCounters) / 8, cs);
         if (batch) {
             launch_fill_f64(ctx->ggain, 0.0, G, cs);
@@ -533,52 +565,69 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             if (cap == 0) continue;
             const bool tk = cfg.timing_k && cs == s;
             int t;
-            t = tk ? ctx->timer.begin(100 + GSP_K_FRONTIER) : -1;
+            t = tk ? ctx->timer.begin(100 + GSP_K_FRONTIER, cs) : -1;
             launch_move_compact(a, wl, cs);
             ctx->timer.end(t);
             if (mode == GATED) {
-                t = tk ? ctx->timer.begin(100 + GSP_K_GATE) : -1;
+                t = tk ? ctx->timer.begin(100 + GSP_K_GATE, cs) : -1;
                 launch_gate(a, net, cfg.theta_logit, cap, cs);
                 ctx->timer.end(t);
             }
-            t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL) : -1;
+            // the four scans read the same state and write disjoint
+            // decisions: the wave-bin, workgroup-bin and hub scans fork onto
+            // side streams and join before the moves are applied.  Timed
+            // sweeps stay on one stream, so that an event pair around a
+            // kernel holds that kernel alone.
+            const bool fork = !cfg.timing_k;
+            hipStream_t sw = fork ? ctx->side[0] : cs, sb = fork ? ctx->side[1] : cs, sh = fork ? ctx->side[2] : cs;
+            if (fork) {
+                hipEvent_t fe = ctx->fork_ev[p];
+                (void)hipEventRecord(fe, cs);
+                for (hipStream_t q : ctx->side) (void)hipStreamWaitEvent(q, fe, 0);
+            }
+            t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_SMALL, cs) : -1;
             launch_move_small(a, wl, cs);
             ctx->timer.end(t);
-            t = tk && a.qcap[BIN_WAVE] ? ctx->timer.begin(100 + GSP_K_MOVE_WAVE) : -1;
-            launch_move_wave(a, cs);
+            t = tk && a.qcap[BIN_WAVE] ? ctx->timer.begin(100 + GSP_K_MOVE_WAVE, sw) : -1;
+            launch_move_wave(a, sw);
             ctx->timer.end(t);
-            t = tk && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK) : -1;
-            launch_move_block(a, cs);
+            t = tk && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK, sb) : -1;
+            launch_move_block(a, sb);
             ctx->timer.end(t);
             // one timed class per kernel on the partition path: chunk scan,
             // gather; the finish class holds the global-table kernels (they
             // return at once unless a hub overflowed) and the decisions
-            t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB) : -1;
-            if (a.hub_parts) launch_move_hub_parts(a, cs); else launch_move_hub_scan(a, cs);
+            t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB, sh) : -1;
+            if (a.hub_parts) launch_move_hub_parts(a, sh); else launch_move_hub_scan(a, sh);
             ctx->timer.end(t);
             if (a.hub_parts) {
-                t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_GATHER) : -1;
-                launch_move_hub_gather(a, cs);
+                t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_GATHER, sh) : -1;
+                launch_move_hub_gather(a, sh);
                 ctx->timer.end(t);
             }
-            t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH) : -1;
-            if (a.hub_parts) launch_move_hub_scan(a, cs);
-            launch_move_hub_finish(a, cs);
+            t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH, sh) : -1;
+            if (a.hub_parts) launch_move_hub_scan(a, sh);
+            launch_move_hub_finish(a, sh);
             ctx->timer.end(t);
-            t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY) : -1;
+            for (int q = 0; fork && q < 3; q++) {
+                hipEvent_t je = ctx->join_ev[3 * p + q];
+                (void)hipEventRecord(je, ctx->side[q]);
+                (void)hipStreamWaitEvent(cs, je, 0);
+            }
+            t = tk ? ctx->timer.begin(100 + GSP_K_MOVE_APPLY, cs) : -1;
             launch_move_apply(a, cap, cs);
             ctx->timer.end(t);
             if (tk) {
-                ctx->kernel_launches[GSP_K_FRONTIER]++;
-                ctx->kernel_launches[GSP_K_GATE] += mode == GATED;
-                ctx->kernel_launches[GSP_K_MOVE_SMALL] += cap - a.qcap[BIN_WAVE] - a.qcap[BIN_BLOCK] -
+                launches[GSP_K_FRONTIER]++;
+                launches[GSP_K_GATE] += mode == GATED;
+                launches[GSP_K_MOVE_SMALL] += cap - a.qcap[BIN_WAVE] - a.qcap[BIN_BLOCK] -
                                                           a.qcap[BIN_HUB] > 0;
-                ctx->kernel_launches[GSP_K_MOVE_WAVE] += a.qcap[BIN_WAVE] > 0;
-                ctx->kernel_launches[GSP_K_MOVE_BLOCK] += a.qcap[BIN_BLOCK] > 0;
-                ctx->kernel_launches[GSP_K_MOVE_HUB] += a.qcap[BIN_HUB] > 0;
-                ctx->kernel_launches[GSP_K_MOVE_HUB_GATHER] += a.hub_parts && a.qcap[BIN_HUB] > 0;
-                ctx->kernel_launches[GSP_K_MOVE_HUB_FINISH] += (2 + a.hub_parts) * (a.qcap[BIN_HUB] > 0);
-                ctx->kernel_launches[GSP_K_MOVE_APPLY]++;
+                launches[GSP_K_MOVE_WAVE] += a.qcap[BIN_WAVE] > 0;
+                launches[GSP_K_MOVE_BLOCK] += a.qcap[BIN_BLOCK] > 0;
+                launches[GSP_K_MOVE_HUB] += a.qcap[BIN_HUB] > 0;
+                launches[GSP_K_MOVE_HUB_GATHER] += a.hub_parts && a.qcap[BIN_HUB] > 0;
+                launches[GSP_K_MOVE_HUB_FINISH] += (2 + a.hub_parts) * (a.qcap[BIN_HUB] > 0);
+                launches[GSP_K_MOVE_APPLY]++;
             }
         }
     };
@@ -965,6 +1014,10 @@ gsp_status gsp_destroy(gsp_ctx *ctx) {
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     ctx->drop_sweep_graphs();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (hipStream_t q : ctx->side)
+        if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : ctx->fork_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->join_ev) (void)hipEventDestroy(e);
     delete ctx;
     return GSP_OK;
 }

@@ -78,14 +78,23 @@ __device__ __forceinline__ void graph_totals(const MoveArgs &a, int i, double ga
 __device__ __forceinline__ double m2_of(const MoveArgs &a, int i) { return a.g.M2g ? a.g.M2g[a.g.gid[i]] : a.M2; }
 
 // Decision from the group's best candidate; identical on every lane.
-__device__ __forceinline__ bool decide(const MoveArgs &a, double m2, int i, int d, double ki, double kid, double bg,
-                                       int bc, double *gain) {
+// sig_d = Sigma_d and csz_d = |d| are loaded early by the callers;
+// bc_single says whether the best community bc is a singleton (see
+// best_single: looked up only when the rule can apply).
+__device__ __forceinline__ bool decide(double m2, int d, double ki, double kid, double bg, int bc, double sig_d,
+                                       int csz_d, int bc_single, double *gain) {
     if (bc == kIntMax) return false;
-    double gstay = m2 * kid - ki * (a.sig[d] - ki);
+    double gstay = m2 * kid - ki * (sig_d - ki);
     if (!(bg > gstay)) return false;
-    if (a.csize[d] == 1 && a.csize[bc] == 1 && bc > d) return false;
+    if (csz_d == 1 && bc_single && bc > d) return false;
     *gain = bg - gstay;
     return true;
+}
+
+// Whether community bc is a singleton, read only where the singleton rule
+// can reject the move (d a singleton, bc > d).
+__device__ __forceinline__ int best_single(const MoveArgs &a, int d, int csz_d, int bc) {
+    return (csz_d == 1 && bc != kIntMax && bc > d) ? a.csize[bc] == 1 : 0;
 }
 
 // History of a scan (for the learned gate's features) and, if sampled, a
@@ -317,14 +326,16 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     const bool valid = qi < cnt;
     int *keys = wkeys + grp * kSlots;
     double *vals = wvals + grp * kSlots;
-    int i = -1, di = 0, d = -1, j = -1;
-    double ki = 0.0, w = 0.0, m2 = a.M2;
+    int i = -1, di = 0, d = -1, j = -1, csd = 0;
+    double ki = 0.0, w = 0.0, m2 = a.M2, sgd = 0.0;
     if (valid) {
         i = a.queue[a.qbase[bin] + qi];
         m2 = m2_of(a, i);
         di = a.g.deg[i];
         d = a.cm[i];
         ki = a.K[i];
+        sgd = a.sig[d];
+        csd = a.csize[d];
         if (gl < di) {
             int64_t e = a.g.off[i] + gl;
             j = load_col(a.g.col, e);
@@ -342,7 +353,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     group_argmax_rt(bg, bc, G);
     kid = group_sum_rt(kid, G);
     double gain = 0.0;
-    bool mv = valid && decide(a, m2, i, d, ki, kid, bg, bc, &gain);
+    bool mv = valid && decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
     if (mv && j >= 0 && j != i) mark_neighbour(a, j, w);
     bool lead = valid && gl == 0;
     if (a.ggain) {   // batch: per-graph totals, one atomic per graph met by the wavefront
@@ -441,6 +452,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_move_wave(MoveArgs a) {
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
         double ki = a.K[i];
+        const double sgd = a.sig[d];
+        const int csd = a.csize[d];
         const int T = (int)hub_table_size(di);   // <= kWaveTable: at most half full
         // the lane's entries (at most R) are loaded together, then their
         // memberships: two round trips to memory instead of 2R
@@ -466,7 +479,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_move_wave(MoveArgs a) {
         group_argmax<kWave>(bg, bc);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
-        bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
+        bool mv = decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
         if (mv)   // entries reloaded: keeping them would cost registers across the scoring
             for (int e = lane; e < di; e += kWave) {
                 int j = load_col(a.g.col, beg + e);
@@ -510,6 +523,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_move_block(MoveArgs a) {
         int64_t beg = a.g.off[i];
         int d = a.cm[i];
         double ki = a.K[i];
+        const double sgd = a.sig[d];
+        const int csd = a.csize[d];
         const int T = (int)hub_table_size(di);   // <= kBlockTable: at most half full
         constexpr int R = kBlockMaxDeg / kBlock;   // entries per thread, loaded together
         int jj[R];
@@ -532,7 +547,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_move_block(MoveArgs a) {
         fold_table<kBlock, 4>(a, m2, keys, vals, T, tid, d, ki, bg, bc, kid, acc.keys);
         block_argmax_sum(bg, bc, kid);
         double gain = 0.0;
-        bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
+        bool mv = decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
         if (mv)
             for (int e = tid; e < di; e += kBlock) {
                 int j = load_col(a.g.col, beg + e);
@@ -565,13 +580,13 @@ template <int WT>
 __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     __shared__ int tkeys[kBlockTable];
     __shared__ double tvals[kBlockTable];
+    if (a.hub_parts && !a.ctr->hub_fallback) return;   // every hub went through the partitions
     for (int k = threadIdx.x; k < kBlockTable; k += kBlock) {
         tkeys[k] = kEmpty;
         tvals[k] = 0.0;
     }
     __syncthreads();
     Acc acc;
-    if (a.hub_parts && !a.ctr->hub_fallback) return;   // every hub went through the partitions
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
         if (a.hub_parts ? a.hub_act[i] != 3 : !a.hub_act[i]) continue;
@@ -894,7 +909,8 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         group_argmax<kWave>(bg, bc);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
-        bool mv = decide(a, m2, i, d, ki, kid, bg, bc, &gain);
+        const int csd = a.csize[d];
+        bool mv = decide(m2, d, ki, kid, bg, bc, a.sig[d], csd, best_single(a, d, csd, bc), &gain);
         if (lane == 0) {
             acc.verts++;
             acc.aux += (unsigned long long)nch;
@@ -1063,9 +1079,13 @@ void launch_move_block(const MoveArgs &a, hipStream_t s) {
         k_move_block<W_F64><<<gr, kBlock, 0, s>>>(a);
 }
 
+// On the partition path these kernels serve only hubs that overflowed
+// (rare) and return at once otherwise: a small grid keeps that cheap.
+constexpr int64_t kFallbackGrid = 256;
+
 void launch_move_hub_scan(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    unsigned gr = cap_grid(a.ch_count, 4096);
+    unsigned gr = cap_grid(a.ch_count, a.hub_parts ? kFallbackGrid : 4096);
     if (a.g.wt == W_UNIT)
         k_move_hub_insert<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1096,7 +1116,7 @@ void launch_move_hub_gather(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    k_move_hub_part<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
+    k_move_hub_part<<<cap_grid(a.ch_count, a.hub_parts ? kFallbackGrid : 4096), kBlock, 0, s>>>(a);
     k_move_hub_final<<<cap_grid((a.qcap[BIN_HUB] + 3) / 4, 1024), kBlock, 0, s>>>(a);
 }
 

@@ -296,6 +296,26 @@ def test_graph_replay_equals_direct_launches(ctx, name):
     assert np.array_equal(m, ref[0]) and li == ref[1]
 
 
+def test_timed_runs_equal_untimed(ctx):
+    """Per-kernel timing (the scans of a sub-round then run one after
+    another, launch by launch) gives the result of the untimed runs (scans
+    side by side on four streams, replayed graphs); a class mask times only
+    that class."""
+    g = _graph("rmat15")
+    _load(ctx, g)
+    fast = ctx.louvain(tolerance=1e-2, max_passes=10)
+    timed = ctx.louvain(tolerance=1e-2, max_passes=10, timing=2)
+    assert np.array_equal(timed.membership, fast.membership)
+    k = timed.stats["kernels"]
+    for name in gsp.KERNEL_CLASSES:
+        assert (k[name]["ms"] > 0) == (k[name]["launches"] > 0), name
+    small = gsp.KERNEL_CLASSES.index("move_small")
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, timing=2, timing_mask=1 << small)
+    k = res.stats["kernels"]
+    assert k["move_small"]["ms"] > 0 and k["move_wave"]["ms"] == 0
+    assert np.array_equal(res.membership, fast.membership)
+
+
 @pytest.mark.parametrize("name", ["rmat15", "agg_rmat14", "sbm_w10"])
 def test_global_hub_tables_equal_partitions(ctx, name):
     """Hubs scored through global hash tables only (hub_global = 1) and
