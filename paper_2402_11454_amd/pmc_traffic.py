@@ -87,13 +87,19 @@ def summarize(fetch_db, write_db, cmd):
             continue
         w_kib = wr.get(name, (0, 0.0))[1]
         b = f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale
-        k = short(name)
-        k = k.split("<")[0]
-        prev = kernels.get(k)
-        if prev is None or prev["dispatches"] < n:
-            kernels[k] = {"dispatches": n, "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
-                          "bytes_per_launch": round(b, 1)}
+        # every instantiation of a kernel together (bench times them as one
+        # class): dispatch-weighted means
+        k = short(name).split("<")[0]
+        acc = kernels.setdefault(k, {"dispatches": 0, "fetch_kib": 0.0, "write_kib": 0.0, "bytes_per_launch": 0.0})
+        acc["dispatches"] += n
+        acc["fetch_kib"] += f_kib * n
+        acc["write_kib"] += w_kib * n
+        acc["bytes_per_launch"] += b * n
         rows.append((short(name), n, f_kib, w_kib, b))
+    for acc in kernels.values():
+        n = max(acc["dispatches"], 1)
+        for f in ("fetch_kib", "write_kib", "bytes_per_launch"):
+            acc[f] = round(acc[f] / n, 1)
     out = {"source_hash": source_hash(), "workload": "rmat20", "command": cmd, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
