@@ -74,6 +74,8 @@ typedef struct gsp_options {
     uint32_t timing_mask;          /* timing = 2: bit k times kernel class k only (0 = every class) */
     int32_t hub_global;            /* 1: score every hub through global hash tables (default 0: LDS hash
                                       partitions, global tables only for hubs that do not fit them) */
+    int32_t hub_max_parts;         /* hubs with more chunks of 2048 entries than this go through their
+                                      global table (0 = the limit, 4096; values in [0, 4096]) */
 } gsp_options;
 
 /* Vertex pruning of the local-moving phase (prune_mode). */

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("split_mode", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("mem_limit_bytes", ctypes.c_uint64), ("prune_mode", ctypes.c_int32),
                 ("prune_threshold", ctypes.c_float), ("use_graphs", ctypes.c_int32),
-                ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32)]
+                ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32),
+                ("hub_max_parts", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

@@ -87,6 +87,7 @@ struct gsp_ctx {
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> fork_ev, join_ev;
     bool hub_parts = true;              // hubs by hash partitions (else global tables only); per run
+    int hub_max_parts = kMaxParts;      // hubs with more chunks take their global table; per run
     // instantiated sweep graphs, reused while the level and its work lists
     // (everything a sweep's launches take as arguments) are the same
     struct SweepGraph {
@@ -541,6 +542,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.part_kid = ctx->sc.part_kid;
             a.part_c = ctx->sc.part_c;
             a.hub_parts = ctx->hub_parts && ctx->gap_col;
+            a.max_parts = ctx->hub_max_parts;
             a.skey = ctx->gap_col;
             a.sval = ctx->gap_w;
             a.hbuck = ctx->sc.hbuck;
@@ -594,9 +596,9 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             t = tk && a.qcap[BIN_BLOCK] ? ctx->timer.begin(100 + GSP_K_MOVE_BLOCK, sb) : -1;
             launch_move_block(a, sb);
             ctx->timer.end(t);
-            // one timed class per kernel on the partition path: chunk scan,
-            // gather; the finish class holds the global-table kernels (they
-            // return at once unless a hub overflowed) and the decisions
+            // hubs: on the partition path the chunk scan and the gather (whose
+            // last workgroup per hub decides); on the global-table path the
+            // chunk scan, then the table slices and the decisions
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB, sh) : -1;
             if (a.hub_parts) launch_move_hub_parts(a, sh); else launch_move_hub_scan(a, sh);
             ctx->timer.end(t);
@@ -606,8 +608,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 ctx->timer.end(t);
             }
             t = tk && a.qcap[BIN_HUB] ? ctx->timer.begin(100 + GSP_K_MOVE_HUB_FINISH, sh) : -1;
-            if (a.hub_parts) launch_move_hub_scan(a, sh);
-            launch_move_hub_finish(a, sh);
+            if (a.hub_parts) launch_move_hub_decide(a, sh); else launch_move_hub_finish(a, sh);
             ctx->timer.end(t);
             for (int q = 0; fork && q < 3; q++) {
                 hipEvent_t je = ctx->join_ev[3 * p + q];
@@ -626,7 +627,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 launches[GSP_K_MOVE_BLOCK] += a.qcap[BIN_BLOCK] > 0;
                 launches[GSP_K_MOVE_HUB] += a.qcap[BIN_HUB] > 0;
                 launches[GSP_K_MOVE_HUB_GATHER] += a.hub_parts && a.qcap[BIN_HUB] > 0;
-                launches[GSP_K_MOVE_HUB_FINISH] += (2 + a.hub_parts) * (a.qcap[BIN_HUB] > 0);
+                launches[GSP_K_MOVE_HUB_FINISH] += (a.hub_parts ? 1 : 2) * (a.qcap[BIN_HUB] > 0);
                 launches[GSP_K_MOVE_APPLY]++;
             }
         }
@@ -938,6 +939,8 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
                          "bad options (max_iterations in [0, 100]; sub_rounds a power of two in [1, 64])");
     if (opt.prune_mode != GSP_PRUNE_PLAIN && opt.prune_mode != GSP_PRUNE_LEARNED)
         return ctx->fail(GSP_EINVAL, "bad prune_mode");
+    if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
+        return ctx->fail(GSP_EINVAL, "hub_max_parts must lie in [0, 4096]");
     if (opt.prune_mode == GSP_PRUNE_LEARNED) {
         if (!(opt.prune_threshold > 0.0f && opt.prune_threshold < 1.0f))
             return ctx->fail(GSP_EINVAL, "prune_threshold must lie in (0, 1)");
@@ -969,6 +972,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->use_graphs = 1;
     out->timing_mask = 0;
     out->hub_global = 0;
+    out->hub_max_parts = 0;
     return GSP_OK;
 }
 
@@ -1083,6 +1087,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     ctx->timer.reset();
     ctx->timer.kmask = opt.timing_mask;
     ctx->hub_parts = opt.hub_global == 0;
+    ctx->hub_max_parts = opt.hub_max_parts ? opt.hub_max_parts : kMaxParts;
     bool tphase = opt.timing >= 1, tk = opt.timing >= 2;
     double kbytes[GSP_K_COUNT] = {0};
     for (int k = 0; k < GSP_K_COUNT; k++) ctx->kernel_launches[k] = 0;
@@ -1525,6 +1530,7 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     a.part_kid = ctx->sc.part_kid;
     a.part_c = ctx->sc.part_c;
     a.hub_parts = ctx->hub_parts && ctx->gap_col;
+    a.max_parts = ctx->hub_max_parts;
     a.skey = ctx->gap_col;
     a.sval = ctx->gap_w;
     a.hbuck = ctx->sc.hbuck;
@@ -1536,9 +1542,11 @@ gsp_status gsp_step_move(gsp_ctx *ctx, const int32_t *membership, const uint8_t 
     if (a.hub_parts) {
         launch_move_hub_parts(a, s);
         launch_move_hub_gather(a, s);
+        launch_move_hub_decide(a, s);
+    } else {
+        launch_move_hub_scan(a, s);
+        launch_move_hub_finish(a, s);
     }
-    launch_move_hub_scan(a, s);
-    launch_move_hub_finish(a, s);
     HIP_TRY(hipGetLastError());
     st = copy_out(ctx, dec_out, ctx->dec, g.n, where);
     if (st != GSP_OK) return st;
@@ -1571,6 +1579,7 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
     st = ensure_levels(ctx);   // the hub staging lives in the aggregation buffers
     if (st != GSP_OK) return st;
     ctx->hub_parts = opt.hub_global == 0;
+    ctx->hub_max_parts = opt.hub_max_parts ? opt.hub_max_parts : kMaxParts;
     st = take_membership(ctx, membership_inout, where);
     if (st != GSP_OK) return st;
     hipStream_t s = ctx->stream;

@@ -82,8 +82,7 @@ struct alignas(128) CounterStripe {
 struct IterCounters {
     int qcnt[kMaxRounds][kNumBins];   // queued vertices per sub-round and bin
     int ccnt[kMaxRounds][kNumBins];   // gated sweeps: candidates before the gate
-    int hub_fallback;                 // some hub of this sweep needs the global-table path
-    int pad[31];
+    int pad[32];
     CounterStripe st[kStripes];
 };
 
@@ -102,6 +101,9 @@ struct TraceArgs {
 };
 
 // Arguments of the local-moving kernels for one sub-round.
+constexpr int kMaxParts = 4096;   // hash partitions (chunks) per hub at most
+constexpr int kPartCap = 3072;    // distinct communities per partition at most
+
 struct MoveArgs {
     Level g;
     const double *K;
@@ -131,8 +133,9 @@ struct MoveArgs {
     // hubs by hash partitions (hub_parts): staging of each chunk's distinct
     // (community, weight) pairs at the chunk's own entry positions, and the
     // per (chunk, partition) packed start/count words; hub_act[i] = 3 marks
-    // a hub sent to the global-table path instead
+    // a hub sent to its global table instead (by the decision kernel)
     bool hub_parts = false;
+    int max_parts = kMaxParts;   // hubs with more chunks: hub_act = 3
     int32_t *skey = nullptr;
     double *sval = nullptr;
     uint32_t *hbuck = nullptr;
@@ -204,13 +207,13 @@ void launch_move_hub_finish(const MoveArgs &a, hipStream_t s);
 // Hubs by hash partitions: chunk -> LDS reduction -> pairs sorted by
 // partition (staging); partition -> LDS table over all chunks -> the
 // partition's best candidate and K_{i->d} share (part_* of the chunk with
-// the partition's index).  Hubs with more than kMaxParts chunks, or a
-// partition with more than kPartCap distinct communities, get hub_act = 3
-// and go through the global-table kernels.
-constexpr int kMaxParts = 4096;
-constexpr int kPartCap = 3072;
+// the partition's index); a workgroup per hub combines them and decides.
+// Hubs with more than max_parts (<= kMaxParts) chunks, or a partition with
+// more than kPartCap distinct communities, get hub_act = 3: the decision
+// workgroup then takes the hub through its global table.
 void launch_move_hub_parts(const MoveArgs &a, hipStream_t s);    // phase 1: chunk reduce, staged pairs
 void launch_move_hub_gather(const MoveArgs &a, hipStream_t s);   // phase 2: partitions merged and scored
+void launch_move_hub_decide(const MoveArgs &a, hipStream_t s);   // phase 3: a workgroup per hub decides
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
 
 // ---- k_gate.hip ----

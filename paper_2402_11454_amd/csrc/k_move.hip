@@ -580,7 +580,6 @@ template <int WT>
 __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     __shared__ int tkeys[kBlockTable];
     __shared__ double tvals[kBlockTable];
-    if (a.hub_parts && !a.ctr->hub_fallback) return;   // every hub went through the partitions
     for (int k = threadIdx.x; k < kBlockTable; k += kBlock) {
         tkeys[k] = kEmpty;
         tvals[k] = 0.0;
@@ -589,7 +588,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
     Acc acc;
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
-        if (a.hub_parts ? a.hub_act[i] != 3 : !a.hub_act[i]) continue;
+        if (!a.hub_act[i]) continue;
         int64_t beg = a.ch_beg[k];
         int64_t end = a.g.off[i] + a.g.deg[i];
         if (end > beg + kHubChunk) end = beg + kHubChunk;
@@ -669,11 +668,8 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
         if (a.hub_act[i] != 1) continue;
         int di = a.g.deg[i];
         int P = (di + kHubChunk - 1) / kHubChunk;
-        if (P > kMaxParts) {   // too many partitions: the global-table path
-            if (tid == 0) {
-                a.hub_act[i] = 3;
-                a.ctr->hub_fallback = 1;
-            }
+        if (P > a.max_parts) {   // too many partitions: the hub's global table
+            if (tid == 0) a.hub_act[i] = 3;
             continue;
         }
         int64_t beg = a.ch_beg[k];
@@ -726,6 +722,93 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
     flush_acc(acc, a.ctr, 3);
 }
 
+// A hub's decision from (bg, bc, kid) (block-uniform): records it, counts
+// it in acc (class of the hub decisions) and leaves hub_act = 2 (moves: its
+// neighbours are marked chunk by chunk in apply) or 0.  Thread 0 writes.
+__device__ __forceinline__ void hub_decide(const MoveArgs &a, int i, double bg, int bc, double kid, int nch,
+                                           Acc &acc) {
+    if (threadIdx.x != 0) return;
+    const double m2 = m2_of(a, i);
+    const int d = a.cm[i], di = a.g.deg[i];
+    const double ki = a.K[i];
+    const int csd = a.csize[d];
+    double gain = 0.0;
+    bool mv = decide(m2, d, ki, kid, bg, bc, a.sig[d], csd, best_single(a, d, csd, bc), &gain);
+    acc.verts++;
+    acc.aux += (unsigned long long)nch;
+    a.hub_act[i] = mv ? 2 : 0;
+    if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
+    a.dec[i] = mv ? bc : d;
+    if (mv) {
+        acc.gain += gain;
+        acc.moved++;
+        if (a.ggain) graph_totals(a, i, gain);
+    }
+    if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
+}
+
+// A hub's decision after its partitions (all results in part_*): combine
+// the P partitions' best candidates and decide.  If a partition overflowed
+// or the hub has more than max_parts chunks (hub_act = 3), the workgroup
+// takes the whole hub through its global table instead: insert every entry,
+// then score and reset the table (rare; slow for enormous hubs, but exact).
+template <int WT>
+__device__ void hub_finish_block(const MoveArgs &a, int i, int P, Acc &acc) {
+    const int tid = threadIdx.x;
+    const int d = a.cm[i];
+    const double ki = a.K[i];
+    const double m2 = m2_of(a, i);
+    double bg = -INFINITY, kid = 0.0;
+    int bc = kIntMax;
+    if (a.hub_act[i] == 3) {
+        const int di = a.g.deg[i];
+        const int64_t beg = a.g.off[i], T = (int64_t)hub_table_size(di), tb = a.hub_off[i];
+        int *gk = a.hkeys + tb;
+        double *gv = a.hvals + tb;
+        for (int64_t e = beg + tid; e < beg + di; e += kBlock) {
+            int j = load_col(a.g.col, e);
+            if (j != i) gbl_table_add(gk, gv, (uint64_t)(T - 1), a.cm[j], edge_weight<WT>(a.g.w, e));
+        }
+        __threadfence();   // the table was built with device-scope atomics
+        __syncthreads();
+        for (int64_t q = tid; q < T; q += kBlock) {
+            int key = __hip_atomic_load(gk + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (key == kEmpty) continue;
+            double v = __hip_atomic_load(gv + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gk[q] = kEmpty;
+            gv[q] = 0.0;
+            acc.keys++;
+            fold_key(a, m2, key, v, d, ki, bg, bc, kid);
+        }
+    } else {
+        const int64_t c0 = a.hub_ch0[i];
+        for (int q = tid; q < P; q += kBlock) {
+            double g = a.part_g[c0 + q];
+            int c = a.part_c[c0 + q];
+            if (better(g, c, bg, bc)) {
+                bg = g;
+                bc = c;
+            }
+            kid += a.part_kid[c0 + q];
+        }
+    }
+    block_argmax_sum(bg, bc, kid);
+    hub_decide(a, i, bg, bc, kid, P, acc);
+    __syncthreads();
+}
+
+// One workgroup per active hub of the sub-round (partition path).
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_hub_decide(MoveArgs a) {
+    const int cnt = a.ctr->qcnt[a.round][BIN_HUB];
+    Acc acc;
+    for (int64_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+        int i = a.queue[a.qbase[BIN_HUB] + qi];
+        hub_finish_block<WT>(a, i, (a.g.deg[i] + kHubChunk - 1) / kHubChunk, acc);
+    }
+    flush_acc(acc, a.ctr, 4);
+}
+
 // Per partition of an active hub: merges the partition's pairs from every
 // chunk of the hub (source chunks taken kHubWin at a time) in one LDS table
 // and scores it.  On unit weights the values are counts (int slots).
@@ -748,9 +831,13 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
     Acc acc;
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
+        // 0: not in this sub-round's frontier; 3: the hub goes through its
+        // global table (set by the chunk kernel, or by a partition that
+        // overflowed: the decision kernel takes it)
         if (a.hub_act[i] != 1) continue;
         int di = a.g.deg[i];
         int P = (di + kHubChunk - 1) / kHubChunk;
+        {
         int p = (int)((a.ch_beg[k] - a.g.off[i]) / kHubChunk);
         const uint32_t *words = a.hbuck + a.hub_b0[i];
         const int64_t base = a.g.off[i];
@@ -797,29 +884,26 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
             __syncthreads();
             if (ovf) break;
         }
-        if (ovf) {   // rare: this hub goes through the global-table path
+        if (ovf) {   // rare: this hub goes through its global table
             for (int q = tid; q < kBlockTable; q += kBlock) {
                 tkeys[q] = kEmpty;
                 tvals[q] = 0;
             }
+            if (tid == 0) a.hub_act[i] = 3;
+        } else {
+            int d = a.cm[i];
+            double ki = a.K[i];
+            const double m2 = m2_of(a, i);
+            double bg = -INFINITY, kid = 0.0;
+            int bc = kIntMax;
+            fold_table<kBlock, 8>(a, m2, tkeys, tvals, kBlockTable, tid, d, ki, bg, bc, kid, acc.keys);
+            block_argmax_sum(bg, bc, kid);
             if (tid == 0) {
-                a.hub_act[i] = 3;
-                a.ctr->hub_fallback = 1;
+                a.part_g[k] = bg;
+                a.part_c[k] = bc;
+                a.part_kid[k] = kid;
             }
-            __syncthreads();
-            continue;
         }
-        int d = a.cm[i];
-        double ki = a.K[i];
-        const double m2 = m2_of(a, i);
-        double bg = -INFINITY, kid = 0.0;
-        int bc = kIntMax;
-        fold_table<kBlock, 8>(a, m2, tkeys, tvals, kBlockTable, tid, d, ki, bg, bc, kid, acc.keys);
-        block_argmax_sum(bg, bc, kid);
-        if (tid == 0) {
-            a.part_g[k] = bg;
-            a.part_c[k] = bc;
-            a.part_kid[k] = kid;
         }
         __syncthreads();
     }
@@ -832,10 +916,9 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
 // candidate and its share of K_{i->d} in part_*[chunk].
 __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
     Acc acc;
-    if (a.hub_parts && !a.ctr->hub_fallback) return;
     for (int64_t k = a.ch_first + blockIdx.x; k < a.ch_first + a.ch_count; k += gridDim.x) {
         int i = a.ch_vert[k];
-        if (a.hub_parts ? a.hub_act[i] != 3 : !a.hub_act[i]) continue;
+        if (!a.hub_act[i]) continue;
         int di = a.g.deg[i];
         int64_t T = (int64_t)hub_table_size(di);
         int64_t nch = (di + kHubChunk - 1) / kHubChunk;
@@ -1079,13 +1162,9 @@ void launch_move_block(const MoveArgs &a, hipStream_t s) {
         k_move_block<W_F64><<<gr, kBlock, 0, s>>>(a);
 }
 
-// On the partition path these kernels serve only hubs that overflowed
-// (rare) and return at once otherwise: a small grid keeps that cheap.
-constexpr int64_t kFallbackGrid = 256;
-
 void launch_move_hub_scan(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    unsigned gr = cap_grid(a.ch_count, a.hub_parts ? kFallbackGrid : 4096);
+    unsigned gr = cap_grid(a.ch_count, 4096);
     if (a.g.wt == W_UNIT)
         k_move_hub_insert<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1114,9 +1193,20 @@ void launch_move_hub_gather(const MoveArgs &a, hipStream_t s) {
         k_hub_gather<W_F64><<<gr, kBlock, 0, s>>>(a);   // staged values are fp64 sums
 }
 
+void launch_move_hub_decide(const MoveArgs &a, hipStream_t s) {
+    if (a.qcap[BIN_HUB] == 0) return;
+    unsigned gr = cap_grid(a.qcap[BIN_HUB], 2048);
+    if (a.g.wt == W_UNIT)
+        k_hub_decide<W_UNIT><<<gr, kBlock, 0, s>>>(a);
+    else if (a.g.wt == W_F32)
+        k_hub_decide<W_F32><<<gr, kBlock, 0, s>>>(a);
+    else
+        k_hub_decide<W_F64><<<gr, kBlock, 0, s>>>(a);
+}
+
 void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    k_move_hub_part<<<cap_grid(a.ch_count, a.hub_parts ? kFallbackGrid : 4096), kBlock, 0, s>>>(a);
+    k_move_hub_part<<<cap_grid(a.ch_count, 4096), kBlock, 0, s>>>(a);
     k_move_hub_final<<<cap_grid((a.qcap[BIN_HUB] + 3) / 4, 1024), kBlock, 0, s>>>(a);
 }
 

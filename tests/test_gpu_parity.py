@@ -326,6 +326,11 @@ def test_global_hub_tables_equal_partitions(ctx, name):
     b = ctx.louvain(tolerance=1e-2, max_passes=10, hub_global=1)
     assert np.array_equal(a.membership, b.membership)
     assert a.stats["iterations"] == b.stats["iterations"]
+    # every hub of more than one chunk through the partition kernels' own
+    # fallback (its last workgroup takes the hub through its global table)
+    c = ctx.louvain(tolerance=1e-2, max_passes=10, hub_max_parts=1)
+    assert np.array_equal(a.membership, c.membership)
+    assert a.stats["iterations"] == c.stats["iterations"]
 
 
 def _part_of(c, P):
