@@ -61,29 +61,35 @@ def parse():
     return p.parse_args()
 
 
-def source_hash():
-    h = hashlib.sha256()
+def kernel_source_hash(kernel):
+    """Hash of what decides a kernel's memory traffic: the source file that
+    defines it, the shared headers and the host code that launches it."""
+    import re
     csrc = os.path.join(ROOT, "paper_2402_11454_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    names = sorted(os.listdir(csrc))
+    pat = re.compile(r"__global__\s+void\s+(__launch_bounds__\([^)]*\)\s+)?" + re.escape(kernel) + r"\s*\(")
+    files = [f for f in names if f.endswith(".hip") and pat.search(open(os.path.join(csrc, f)).read())]
+    files += [f for f in names if f.endswith(".h")] + ["capi.hip"]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on this workload and the current kernel sources (else
-    None)."""
+    if it was taken on this workload and on the kernel's current sources
+    (else None)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != source_hash() or t.get("workload") != workload:
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    if t.get("workload") != workload or k is None or k.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def timed_runs(ctx, gsp, a, steps, **kw):

@@ -5,7 +5,7 @@ then WRITE_SIZE, in KiB per dispatch), each also covering an elementwise
 kernel of known traffic (y = 2x over 1 GiB: reads 1 GiB, writes 1 GiB);
 its counters give the scale from counter KiB to bytes.  The summary (per kernel: dispatches, mean KiB read and written,
 scaled bytes per dispatch) goes to profiles/traffic.json with a hash of the
-kernel sources, and a readable table to profiles/traffic_rmat20.md.
+kernel's sources (its file, the headers, the host code), and a readable table to profiles/traffic_rmat20.md.
 
     python -m paper_2402_11454_amd.pmc_traffic --run            # the workload (under rocprofv3)
     python -m paper_2402_11454_amd.pmc_traffic --summarize FETCH_DB WRITE_DB --cmd "..."
@@ -72,7 +72,7 @@ def short(name: str) -> str:
 
 def summarize(fetch_db, write_db, cmd):
     sys.path.insert(0, ROOT)
-    from bench import source_hash
+    from bench import kernel_source_hash
     fe = per_kernel(fetch_db, "FETCH_SIZE")
     wr = per_kernel(write_db, "WRITE_SIZE")
     copy = [k for k in fe if "MulFunctor" in k]
@@ -96,11 +96,12 @@ def summarize(fetch_db, write_db, cmd):
         acc["write_kib"] += w_kib * n
         acc["bytes_per_launch"] += b * n
         rows.append((short(name), n, f_kib, w_kib, b))
-    for acc in kernels.values():
+    for name, acc in kernels.items():
         n = max(acc["dispatches"], 1)
         for f in ("fetch_kib", "write_kib", "bytes_per_launch"):
             acc[f] = round(acc[f] / n, 1)
-    out = {"source_hash": source_hash(), "workload": "rmat20", "command": cmd, "copy_kernel": short(copy),
+        acc["source_hash"] = kernel_source_hash(name)
+    out = {"workload": "rmat20", "command": cmd, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
     with open(os.path.join(prof, "traffic.json"), "w") as f:
