@@ -143,6 +143,7 @@ struct gsp_ctx {
     float *hfrac = nullptr, *hgain = nullptr;
     uint8_t *hbits = nullptr;
     double *dmoved = nullptr, *dsnap = nullptr;
+    int64_t *iter_dev = nullptr;   // l_i of the current sweep, for replayed gated sweeps
     int32_t *cand = nullptr;
     // the network in its inference formats (kept across loads)
     bool have_net = false;
@@ -423,6 +424,8 @@ gsp_status ensure_gate_state(gsp_ctx *ctx) {
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
     ctx->dsnap = ctx->dalloc<double>(ctx->n, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
+    ctx->iter_dev = ctx->dalloc<int64_t>(1, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
     ctx->cand = ctx->dalloc<int32_t>(ctx->n, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate candidates)");
     return GSP_OK;
@@ -502,6 +505,12 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     }
     // One sweep: clear its counters (a fill kernel, so that the sweep can be
     // captured), then every sub-round's kernels, on stream cs.
+    // Sweeps repeat the same launches with the same arguments within a pass
+    // (per mode: plain, gated, confirming): each is captured once as a graph
+    // and replayed; l_i, the one argument that changes, is read from device
+    // memory in replays.  Trace capture and per-kernel timing run launch by
+    // launch.
+    const bool capture = cfg.use_graphs && !ctx->tracing && !cfg.timing_k;
     auto enqueue_sweep = [&](int sweep, IterCounters *ctr, hipStream_t cs) {
         int64_t *launches = ctx->kernel_launches;
         launch_fill_u64(reinterpret_cast<unsigned long long *>(ctr), 0, sizeof(IterCounters) / 8, cs);
@@ -556,6 +565,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 a.pass = cfg.pass;
                 a.sweep = sweep;
                 a.iter = li;
+                a.iter_dev = capture ? ctx->iter_dev : nullptr;   // replays read l_i from memory
                 if (ctx->tracing) a.tr = ctx->trace;
             }
             if (mode == GATED) a.cand = ctx->cand;
@@ -632,11 +642,6 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             }
         }
     };
-    // Plain sweeps repeat the same launches with the same arguments within a
-    // phase: capture them once as a graph and replay it (timing and the
-    // gate's state change per sweep, so those run launch by launch).
-    const bool capture = cfg.use_graphs && !hist && !cfg.timing_k;
-    hipGraphExec_t exec = nullptr;
     std::vector<int64_t> key;
     if (capture) {
         if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -649,8 +654,11 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         int64_t m2bits;
         memcpy(&m2bits, &ctx->M2, sizeof(m2bits));
         key.push_back(m2bits);
-        for (auto &x : ctx->sweep_graphs)
-            if (x.key == key) exec = x.exec;
+        // the gate's inputs: its network, the pass (a feature) and theta
+        int32_t thbits;
+        memcpy(&thbits, &cfg.theta_logit, sizeof(thbits));
+        key.insert(key.end(), {(int64_t)hist, (int64_t)cfg.pass, (int64_t)thbits, ptr(net.w1), ptr(net.w2),
+                               ptr(net.b1), ptr(ctx->hbits)});
     }
     for (int sweep = 0;; sweep++) {
         if (batch) {
@@ -668,6 +676,15 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         }
         IterCounters *ctr = capture ? ctx->ctr : ctx->ctr + (sweep & 1);
         if (capture) {
+            std::vector<int64_t> km = key;
+            km.push_back((int64_t)mode);
+            hipGraphExec_t exec = nullptr;
+            for (auto &x : ctx->sweep_graphs)
+                if (x.key == km) exec = x.exec;
+            if (hist) {   // l_i for the gate's features
+                ctx->i64_h[7] = li;
+                HIP_TRY(hipMemcpyAsync(ctx->iter_dev, &ctx->i64_h[7], sizeof(int64_t), hipMemcpyHostToDevice, s));
+            }
             if (!exec) {
                 HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
                 enqueue_sweep(sweep, ctr, ctx->cap_stream);
@@ -677,7 +694,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 if (graph) (void)hipGraphDestroy(graph);
                 if (e != hipSuccess) return ctx->fail_hip(e, "sweep graph capture");
                 if (ctx->sweep_graphs.size() >= 64) ctx->drop_sweep_graphs();
-                ctx->sweep_graphs.push_back({key, exec});
+                ctx->sweep_graphs.push_back({km, exec});
             }
             HIP_TRY(hipGraphLaunch(exec, s));
         } else {

@@ -147,6 +147,7 @@ struct MoveArgs {
     double *dsnap = nullptr;                    // D_i as compaction took it (the features' value)
     int32_t *cand = nullptr;                    // gated sweep: candidates (the gate fills `queue`)
     int pass = 0, sweep = 0, iter = 0;          // feature and trace context
+    const int64_t *iter_dev = nullptr;          // iter from device memory (sweeps replayed from a graph)
     TraceArgs tr;                               // tr.x == nullptr: no capture
     // batch of graphs (g.gid != nullptr): per-graph totals of the sweep and
     // the graphs still iterating

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_gate(MoveArgs a, GateNet net, float 
             while (t >= pre[b + 1]) b++;
             i = a.cand[a.qbase[b] + (t - pre[b])];
             gate_features(a.g.deg[i], a.K[i], a.sig[a.cm[i]], a.hfrac[i], a.hgain[i], a.hbits[i], a.dsnap[i], a.pass,
-                          a.iter, x);
+                          a.iter_dev ? (int)*a.iter_dev : a.iter, x);
         }
 #pragma unroll
         for (int f = 0; f < kGateFeatures; f++) fx[w][lane][f] = x[f];
