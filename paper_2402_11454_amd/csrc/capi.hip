@@ -1216,10 +1216,10 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         ctx->timer.end(tk2);
         {
             // read every entry (column, weight, neighbour membership), write
-            // the gapped rows and copy them compact; per vertex membership,
+            // the gapped rows of G'' (12 B per entry); per vertex membership,
             // degree, offset and the member list
             int ws = g.wt == W_UNIT ? 0 : (g.wt == W_F32 ? 4 : 8);
-            kbytes[GSP_K_AGGREGATE] += (8.0 + ws) * (double)g.nnz + 36.0 * (double)nnz2 + 28.0 * (double)g.n +
+            kbytes[GSP_K_AGGREGATE] += (8.0 + ws) * (double)g.nnz + 12.0 * (double)nnz2 + 28.0 * (double)g.n +
                                        40.0 * (double)ncomm;
             if (tk) ctx->kernel_launches[GSP_K_AGGREGATE] += 1;
         }
@@ -1959,11 +1959,14 @@ gsp_status gsp_step_aggregate(gsp_ctx *ctx, const int32_t *membership, int where
     *nnz_out = nnz2;
     if (offsets) {
         if ((nnz2 && (!cols || !weights))) return ctx->fail(GSP_EINVAL, "cols/weights NULL");
-        st = copy_out(ctx, offsets, out.off, ncomm + 1, where);
+        // the gapped rows packed into a plain CSR (in the staging arrays)
+        int64_t *off_c = ctx->sc.i64f;
+        HIP_TRY(compact_rows(out.off, out.deg, ncomm, out.col, out.w, off_c, ctx->gap_col, ctx->gap_w, ctx->sc, s));
+        st = copy_out(ctx, offsets, off_c, ncomm + 1, where);
         if (st != GSP_OK) return st;
-        st = copy_out(ctx, cols, out.col, nnz2, where);
+        st = copy_out(ctx, cols, ctx->gap_col, nnz2, where);
         if (st != GSP_OK) return st;
-        st = copy_out(ctx, weights, out.w, nnz2, where);
+        st = copy_out(ctx, weights, ctx->gap_w, nnz2, where);
         if (st != GSP_OK) return st;
     }
     HIP_TRY(hipStreamSynchronize(s));

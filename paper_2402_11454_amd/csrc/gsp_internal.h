@@ -278,14 +278,18 @@ struct AggOut {
     double *K;        // K'' (row sums of G'')
     int32_t *deg;     // deg''
 };
-// Aggregates g by cm (values in [0, n2)) into the compact CSR `out`.
-// gap_* are scratch of capacity nnz (gapped rows before compaction).
-// hub_parts: giant communities through LDS hash partitions (staging in
-// out.col / out.w before the compaction), global tables only for those that
-// do not fit; otherwise global tables for all.
+// Aggregates g by cm (values in [0, n2)) into `out`, a gapped CSR: row c
+// is [out.off[c], out.off[c] + out.deg[c]) (out.off has n2 + 1 entries: the
+// row capacities' prefix sums, at most g's entries in all).  *nnz_out = the
+// entries written.  stage_* (capacity nnz, not out's arrays) take the giant
+// communities' partition pairs when hub_parts; without it every giant
+// community goes through a global table.
 hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int64_t n2, AggOut out,
-                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
+                     int32_t *stage_col, double *stage_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
                      bool hub_parts = true);
+// Packs a gapped CSR (eoff, deg) into a plain one (off_out: n2 + 1 entries).
+hipError_t compact_rows(const int64_t *eoff, const int32_t *deg, int64_t n2, const int32_t *col, const double *w,
+                        int64_t *off_out, int32_t *col_out, double *w_out, Scratch &sc, hipStream_t s);
 
 // Device scratch owned by the context (sized at load).
 struct Scratch {

@@ -9,8 +9,10 @@
 //    a workgroup (<= 2048) -- all in LDS -- or, beyond, a table in global
 //    memory filled vertex by vertex;
 // 3. each table is emitted as row c of G'' (fp64 weights, order of the
-//    table), with deg''[c] and K''[c] = row sum;
-// 4. deg'' is scanned into compact offsets and the rows are copied.
+//    table), with deg''[c] and K''[c] = row sum.
+// G'' stays gapped ("holey"): row c is [eoff[c], eoff[c] + deg''[c]) of the
+// output arrays, the paper's layout; no kernel reads past deg''.
+// compact_rows packs it for callers that want a plain CSR.
 // Sums are fp64; on integer weights (and fp32 weights whose totals stay
 // below 2^30 in units of their spacing) they are exact, so G'' does not
 // depend on the order of the atomics.
@@ -878,11 +880,11 @@ __global__ void __launch_bounds__(kBlock) k_agg_copy(const int64_t *eoff, const 
 }  // namespace
 
 hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int64_t n2, AggOut out,
-                     int32_t *gap_col, double *gap_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
+                     int32_t *stage_col, double *stage_w, Scratch &sc, int64_t *nnz_out, hipStream_t s,
                      bool hub_parts) {
     (void)wl;
     int32_t *csz = sc.i32a, *ccur = sc.i32b, *members = sc.i32c, *cdeg = sc.i32d, *mdeg = sc.i32e;
-    int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = sc.i64c, *mpre = sc.i64d, *ctab = sc.i64e, *tmp = sc.i64f;
+    int64_t *coff = sc.i64a, *ctot = sc.i64b, *eoff = out.off, *mpre = sc.i64d, *ctab = sc.i64e, *tmp = sc.i64f;
     launch_fill_i32(csz, 0, n2, s);
     launch_fill_i64(ctot, 0, n2, s);
     k_agg_count<<<grid1((g.n + 3) / 4, 4096), kBlock, 0, s>>>(g, cm, csz, ctot);
@@ -905,8 +907,8 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     a.coff = coff;
     a.members = members;
     a.eoff = eoff;
-    a.gap_col = gap_col;
-    a.gap_w = gap_w;
+    a.gap_col = out.col;   // rows written in place: the gapped level
+    a.gap_w = out.w;
     a.deg2 = out.deg;
     a.K2 = out.K;
     a.cbl = cwl.bl;
@@ -968,8 +970,8 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
             if (e != hipSuccess) return e;
             k_agg_part_scatter<<<gr, kBlock, 0, s>>>(cwl.bl, hb, H, sc.i64g, ctot);   // ctot: words offset by community
             launch_fill_u8(sc.u8a, 0, n2, s);
-            a.stage_col = out.col;   // free until the compaction at the end
-            a.stage_w = out.w;
+            a.stage_col = stage_col;
+            a.stage_w = stage_w;
             a.words = sc.hbuck;
             a.woff = ctot;
             a.spill = sc.u8a;
@@ -1011,13 +1013,19 @@ hipError_t aggregate(const Level &g, const WorkLists &wl, const int32_t *cm, int
     }
     if (nchunks && parts) k_agg_part_gather<<<gh, kBlock, 0, s>>>(a, sc.cch_comm, sc.cch_beg, nchunks);
     if (nsegs) k_agg_hub_emit<<<(unsigned)(nsegs < 8192 ? nsegs : 8192), kBlock, 0, s>>>(a, sc.cseg_comm, sc.cseg_beg, nsegs);
-    // compact
-    scan_exclusive_i32_to_i64(out.deg, out.off, n2, sc.scan_tmp, s);
-    e = hipMemcpyAsync(nnz_out, out.off + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    // entries of G'' (the row lengths' total)
+    scan_exclusive_i32_to_i64(out.deg, tmp, n2, sc.scan_tmp, s);
+    e = hipMemcpyAsync(nnz_out, tmp + n2, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
-    if (n2 > 0) k_agg_copy<<<grid1(n2 * kWave, 65536), kBlock, 0, s>>>(eoff, out.off, n2, gap_col, gap_w, out.col, out.w);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t compact_rows(const int64_t *eoff, const int32_t *deg, int64_t n2, const int32_t *col, const double *w,
+                        int64_t *off_out, int32_t *col_out, double *w_out, Scratch &sc, hipStream_t s) {
+    scan_exclusive_i32_to_i64(deg, off_out, n2, sc.scan_tmp, s);
+    if (n2 > 0) k_agg_copy<<<grid1(n2 * kWave, 65536), kBlock, 0, s>>>(eoff, off_out, n2, col, w, col_out, w_out);
     return hipGetLastError();
 }
 

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_qin(Level g, const int32_t *me
             }
             int32_t c = memb[i];
             double s = 0.0;
-            for (int64_t k = g.off[i] + lane; k < g.off[i + 1]; k += kWave)
+            for (int64_t k = g.off[i] + lane; k < g.off[i] + g.deg[i]; k += kWave)
                 if (memb[g.col[k]] == c) s += edge_weight<WT>(g.w, k);
             run += group_sum<kWave>(s);
         }

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, d
     int lane = lane_id(), w = threadIdx.x / kWave;
     double blk = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + w; i < g.n; i += (int64_t)gridDim.x * (kBlock / kWave)) {
-        int64_t b = g.off[i], e = g.off[i + 1];
+        int64_t b = g.off[i], e = b + g.deg[i];   // rows may be gapped
         double s = 0.0;
         for (int64_t k = b + lane; k < e; k += kWave) s += edge_weight<WT>(g.w, k);
         s = group_sum<kWave>(s);
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_modularity_parts(Level g, const int3
     int lane = lane_id(), w = threadIdx.x / kWave;
     double blk = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + w; i < g.n; i += (int64_t)gridDim.x * (kBlock / kWave)) {
-        int64_t b = g.off[i], e = g.off[i + 1];
+        int64_t b = g.off[i], e = b + g.deg[i];   // rows may be gapped
         int32_t c = memb[i];
         double s = 0.0;
         for (int64_t k = b + lane; k < e; k += kWave)
