@@ -253,19 +253,36 @@ __device__ void insert_member_chunk(const AggArgs &a, int64_t m0, int64_t m1, in
     }
     int incl = group_incl_scan<W>(dm, gl);
     int total = __shfl(incl, W - 1, W);
-    for (int x0 = 0; x0 < total; x0 += W) {
-        int x = x0 + gl;
-        int k = group_search<W>(incl, x);
-        int ik = __shfl(incl, k, W), dk = __shfl(dm, k, W);
-        int64_t bk = __shfl(bm, k, W);
-        if (x < total) {
-            int64_t e = bk + (x - (ik - dk));
-            int32_t j = load_col(a.g.col, e);
-            double w = edge_weight<WT>(a.g.w, e);
+    // R rounds of W entries at a time: positions first, then their columns,
+    // then the memberships, so the loads of a batch are in flight together
+    constexpr int R = 4;
+    for (int x0 = 0; x0 < total; x0 += W * R) {
+        int64_t e[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            int x = x0 + r * W + gl;
+            int k = group_search<W>(incl, x);
+            int ik = __shfl(incl, k, W), dk = __shfl(dm, k, W);
+            int64_t bk = __shfl(bm, k, W);
+            e[r] = x < total ? bk + (x - (ik - dk)) : -1;
+        }
+        int32_t j[R];
+        double w[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            j[r] = e[r] >= 0 ? load_col(a.g.col, e[r]) : 0;
+            w[r] = e[r] >= 0 ? edge_weight<WT>(a.g.w, e[r]) : 0.0;
+        }
+        int c[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) c[r] = e[r] >= 0 ? a.cm[j[r]] : 0;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (e[r] < 0) continue;
             if constexpr (GLOBAL)
-                gbl_table_add(keys, vals, mask, a.cm[j], w);
+                gbl_table_add(keys, vals, mask, c[r], w[r]);
             else
-                lds_table_add(keys, vals, (uint32_t)mask, a.cm[j], w);
+                lds_table_add(keys, vals, (uint32_t)mask, c[r], w[r]);
         }
     }
 }
