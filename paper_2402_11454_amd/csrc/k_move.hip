@@ -313,21 +313,33 @@ __device__ __forceinline__ double group_sum_rt(double x, int G) {
     return x;
 }
 
-// One wavefront handles 64/G vertices of one small bin: a group of G lanes
-// per vertex, one entry per lane, a table of 2G slots in the wave's LDS.
-// G is a runtime value, so the five bins share one code path.
+// Small bins (degree <= G = 4, 8, ..., 64): a group of L = max(G /
+// kSmallE, 1) lanes per vertex, up to kSmallE entries per lane (loaded
+// together), a table of 2G slots per vertex in the wave's LDS; a wavefront
+// takes 64 / L vertices.  G is a runtime value, so the five bins share one
+// code path.
+constexpr int kSmallE = 4;
+__host__ __device__ inline int small_lanes(int G) { return G > kSmallE ? G / kSmallE : 1; }
+
 template <int WT>
 __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int cnt, int *wkeys, double *wvals,
                            Acc &acc) {
-    const int kSlots = 2 * G;
+    const int kSlots = 2 * G, L = small_lanes(G);
     const int lane = lane_id();
-    const int grp = lane / G, gl = lane & (G - 1);
-    const int64_t qi = unit * (kWave / G) + grp;
+    const int grp = lane / L, gl = lane & (L - 1);
+    const int64_t qi = unit * (kWave / L) + grp;
     const bool valid = qi < cnt;
     int *keys = wkeys + grp * kSlots;
     double *vals = wvals + grp * kSlots;
-    int i = -1, di = 0, d = -1, j = -1, csd = 0;
-    double ki = 0.0, w = 0.0, m2 = a.M2, sgd = 0.0;
+    int i = -1, di = 0, d = -1, csd = 0;
+    int j[kSmallE];
+    double w[kSmallE];
+    double ki = 0.0, m2 = a.M2, sgd = 0.0;
+#pragma unroll
+    for (int r = 0; r < kSmallE; r++) {
+        j[r] = -1;
+        w[r] = 0.0;
+    }
     if (valid) {
         i = a.queue[a.qbase[bin] + qi];
         m2 = m2_of(a, i);
@@ -336,25 +348,38 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
         ki = a.K[i];
         sgd = a.sig[d];
         csd = a.csize[d];
-        if (gl < di) {
-            int64_t e = a.g.off[i] + gl;
-            j = load_col(a.g.col, e);
-            w = edge_weight<WT>(a.g.w, e);
-            if (j != i) lds_table_add(keys, vals, kSlots - 1, a.cm[j], w);
+        const int64_t b0 = a.g.off[i];
+#pragma unroll
+        for (int r = 0; r < kSmallE; r++) {
+            const int e = gl + r * L;
+            if (e < di) {
+                j[r] = load_col(a.g.col, b0 + e);
+                w[r] = edge_weight<WT>(a.g.w, b0 + e);
+            }
         }
+        int c[kSmallE];
+#pragma unroll
+        for (int r = 0; r < kSmallE; r++) c[r] = (j[r] >= 0 && j[r] != i) ? a.cm[j[r]] : kEmpty;
+#pragma unroll
+        for (int r = 0; r < kSmallE; r++)
+            if (c[r] != kEmpty) lds_table_add(keys, vals, kSlots - 1, c[r], w[r]);
     }
     wave_lds_sync();
     double bg = -INFINITY, kid = 0.0;
     int bc = kIntMax;
     if (valid) {
-        take_slot(a, m2, keys, vals, gl, d, ki, bg, bc, kid, acc.keys);
-        take_slot(a, m2, keys, vals, gl + G, d, ki, bg, bc, kid, acc.keys);
+#pragma unroll
+        for (int q = 0; q < 2 * kSmallE; q++)
+            if (gl + q * L < kSlots) take_slot(a, m2, keys, vals, gl + q * L, d, ki, bg, bc, kid, acc.keys);
     }
-    group_argmax_rt(bg, bc, G);
-    kid = group_sum_rt(kid, G);
+    group_argmax_rt(bg, bc, L);
+    kid = group_sum_rt(kid, L);
     double gain = 0.0;
     bool mv = valid && decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
-    if (mv && j >= 0 && j != i) mark_neighbour(a, j, w);
+    if (mv)
+#pragma unroll
+        for (int r = 0; r < kSmallE; r++)
+            if (j[r] >= 0 && j[r] != i) mark_neighbour(a, j[r], w[r]);
     bool lead = valid && gl == 0;
     if (a.ggain) {   // batch: per-graph totals, one atomic per graph met by the wavefront
         int gk = valid ? a.g.gid[i] : 0;
@@ -375,14 +400,18 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
     wave_lds_sync();
 }
 
+// vertices of small bin b per wavefront
+__host__ __device__ inline int small_vpw(int b) { return kWave / small_lanes(4 << b); }
+
 template <int WT>
-__global__ void __launch_bounds__(kBlock, 5) k_move_small(MoveArgs a) {
-    __shared__ int tkeys[2 * kBlock];
-    __shared__ double tvals[2 * kBlock];
+__global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 5 : 4) k_move_small(MoveArgs a) {
+    constexpr int kWaveSlots = 2 * kWave * kSmallE;   // (64 / L) vertices x 2G slots, at most
+    __shared__ int tkeys[kWaveSlots * (kBlock / kWave)];
+    __shared__ double tvals[kWaveSlots * (kBlock / kWave)];
     const int w = threadIdx.x / kWave;
-    int *wkeys = tkeys + w * 2 * kWave;
-    double *wvals = tvals + w * 2 * kWave;
-    for (int k = lane_id(); k < 2 * kWave; k += kWave) {
+    int *wkeys = tkeys + w * kWaveSlots;
+    double *wvals = tvals + w * kWaveSlots;
+    for (int k = lane_id(); k < kWaveSlots; k += kWave) {
         wkeys[k] = kEmpty;
         wvals[k] = 0.0;
     }
@@ -393,7 +422,7 @@ __global__ void __launch_bounds__(kBlock, 5) k_move_small(MoveArgs a) {
 #pragma unroll
     for (int b = 0; b < kNumSmallBins; b++) {
         cnt[b] = a.ctr->qcnt[a.round][b];
-        int vpw = kWave / (4 << b);
+        int vpw = small_vpw(b);
         pre[b + 1] = pre[b] + (cnt[b] + vpw - 1) / vpw;
     }
     Acc acc;
@@ -430,7 +459,7 @@ __device__ void block_argmax_sum(double &bg, int &bc, double &x) {
 
 // One wavefront per vertex of 65..512 entries, 1024-slot table in its LDS.
 template <int WT>
-__global__ void __launch_bounds__(kBlock, 4) k_move_wave(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(MoveArgs a) {
     using V = typename TabVal<WT>::T;
     __shared__ int tkeys[kBlock / kWave * kWaveTable];
     __shared__ V tvals[kBlock / kWave * kWaveTable];
@@ -504,7 +533,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_move_wave(MoveArgs a) {
 
 // One workgroup per vertex of 513..2048 entries, 4096-slot table in LDS.
 template <int WT>
-__global__ void __launch_bounds__(kBlock, 4) k_move_block(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(MoveArgs a) {
     using V = typename TabVal<WT>::T;
     __shared__ int keys[kBlockTable];
     __shared__ V vals[kBlockTable];
@@ -1127,7 +1156,7 @@ void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
     (void)wl;
     int64_t units = 0;   // wave units
     for (int b = 0; b < kNumSmallBins; b++) {
-        int vpw = kWave / (4 << b);
+        int vpw = small_vpw(b);
         units += (a.qcap[b] + vpw - 1) / vpw;
     }
     if (units == 0) return;
