@@ -57,6 +57,8 @@ def _graph(name):
     if name not in _cache:
         if name == "agg_rmat14":
             _cache[name] = _aggregated(gi.rmat_small(14, 2), 3000, 1)
+        elif name == "rmat15w":   # fp32 weights with hubs of several chunks
+            _cache[name] = gi.rmat_small(15, 3, weights=(1.0, 4.0))
         else:
             _cache[name] = GRAPHS[name]()
     return _cache[name]
@@ -316,7 +318,7 @@ def test_timed_runs_equal_untimed(ctx):
     assert np.array_equal(res.membership, fast.membership)
 
 
-@pytest.mark.parametrize("name", ["rmat15", "agg_rmat14", "sbm_w10"])
+@pytest.mark.parametrize("name", ["rmat15", "rmat15w", "agg_rmat14", "sbm_w10"])
 def test_global_hub_tables_equal_partitions(ctx, name):
     """Hubs scored through global hash tables only (hub_global = 1) and
     through LDS hash partitions (the default) give the same runs."""
@@ -327,10 +329,13 @@ def test_global_hub_tables_equal_partitions(ctx, name):
     assert np.array_equal(a.membership, b.membership)
     assert a.stats["iterations"] == b.stats["iterations"]
     # every hub of more than one chunk through the partition kernels' own
-    # fallback (its last workgroup takes the hub through its global table)
+    # fallback (the hub's decision workgroup takes it through its global table)
     c = ctx.louvain(tolerance=1e-2, max_passes=10, hub_max_parts=1)
     assert np.array_equal(a.membership, c.membership)
     assert a.stats["iterations"] == c.stats["iterations"]
+    if name == "rmat15w":
+        ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+        assert np.array_equal(a.membership, ref.membership)
 
 
 def _part_of(c, P):
