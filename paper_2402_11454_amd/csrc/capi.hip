@@ -1165,7 +1165,8 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         if (opt.split_mode == GSP_SPLIT_PASS) {
             t = tphase ? ctx->timer.begin(PH_SPLIT) : -1;
             int tk1 = tk ? ctx->timer.begin(100 + GSP_K_SPLIT) : -1;
-            launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, s);
+            launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
+                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
             ctx->timer.end(tk1);
             if (tk) ctx->kernel_launches[GSP_K_SPLIT] += 6;
             // one pass over the level: column + membership of both ends per
@@ -1251,7 +1252,8 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         Level g0 = level0(ctx);
         WorkLists wl = make_lists(ctx);
         HIP_TRY(build_work_lists(g0, 1, wl, ctx->sc, s));
-        launch_split(g0, wl, ctx->top, ctx->lab, ctx->sc.i32c, s);
+        launch_split(g0, wl, ctx->top, ctx->lab, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
+                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
         HIP_TRY(hipMemcpyAsync(ctx->top, ctx->lab, ctx->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     if (opt.split_mode != GSP_SPLIT_PASS && ctx->n > 0) {
@@ -1480,7 +1482,8 @@ gsp_status gsp_count_disconnected(gsp_ctx *ctx, const int32_t *membership, int w
     Level g = level0(ctx);
     WorkLists wl = make_lists(ctx);
     HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
-    launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, s);
+    launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
+                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
     HIP_TRY(hipMemsetAsync(ctx->sc.u64, 0, sizeof(unsigned long long), s));
     launch_count_disconnected(ctx->lab, ctx->cm, ctx->n, ctx->sc.i32a, ctx->sc.u64, s);
     HIP_TRY(hipMemcpyAsync(ctx->i64_h, ctx->sc.u64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1928,7 +1931,8 @@ gsp_status gsp_step_split(gsp_ctx *ctx, const int32_t *membership, int where, in
     Level g = level0(ctx);
     WorkLists wl = make_lists(ctx);
     HIP_TRY(build_work_lists(g, 1, wl, ctx->sc, s));
-    launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, s);
+    launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
+                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
     HIP_TRY(hipGetLastError());
     st = copy_out(ctx, labels_out, ctx->lab, g.n, where);
     if (st != GSP_OK) return st;

@@ -254,9 +254,10 @@ void launch_add_i32(int32_t *p, int64_t n, int32_t delta, hipStream_t s);
 
 // ---- k_split.hip ----
 // labels[i] = smallest vertex of i's component among same-community edges.
-// dom: scratch of n ints (one picked root per community)
+// dom, vote_cnt, vote_best: scratch of n entries each (the picked root per
+// community and its vote)
 void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, int32_t *dom,
-                  hipStream_t s);
+                  uint32_t *vote_cnt, unsigned long long *vote_best, hipStream_t s);
 // Renumber labels (values in [0, n)) by ascending label: flag[l] = label l
 // in use, rank = exclusive scan of flag, out[i] = rank[labels[i]], *count =
 // number of labels in use.  flag/rank are n+1-sized temps.

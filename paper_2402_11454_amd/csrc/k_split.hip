@@ -82,12 +82,87 @@ __global__ void __launch_bounds__(kBlock) k_split_sample(Level g, const int32_t 
     }
 }
 
-// The picked root of each community: that of some vertex of it (racing
-// plain stores; any winner will do).
+// The picked root of each community: first that of some vertex of it
+// (racing plain stores; any winner will do), then, where a sampled vertex of
+// the community votes, the root whose tree holds the most sampled degree
+// (vote below).
 __global__ void __launch_bounds__(kBlock) k_split_pick(const int32_t *parent, const int32_t *cm, int64_t n,
                                                       int32_t *dom) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
         dom[cm[i]] = parent[i];
+}
+
+// Vote for the picked roots: every kVoteStride-th vertex adds deg + 1 to
+// its root's count (summed per tile in LDS first: big trees draw many
+// votes); then each sampled vertex offers (count of its root, root) for its
+// community and the largest wins (packed in 64 bits, summed per tile in LDS
+// first; a tie goes to the larger root id); then the winners become the
+// picked roots.  Counts below 2^32: a vertex's deg + 1 summed over at most
+// all vertices.
+constexpr int kVoteStride = 16;
+constexpr int kVoteTile = 4 * kBlock;
+constexpr int kVoteTable = 2 * kVoteTile;
+
+__global__ void __launch_bounds__(kBlock) k_split_vote_count(Level g, const int32_t *parent, uint32_t *cnt) {
+    __shared__ int tk[kVoteTable];
+    __shared__ unsigned tv[kVoteTable];
+    for (int q = threadIdx.x; q < kVoteTable; q += kBlock) {
+        tk[q] = kEmpty;
+        tv[q] = 0;
+    }
+    __syncthreads();
+    const int64_t ns = (g.n + kVoteStride - 1) / kVoteStride;
+    for (int64_t t0 = blockIdx.x * (int64_t)kVoteTile; t0 < ns; t0 += (int64_t)gridDim.x * kVoteTile) {
+        for (int64_t t = t0 + threadIdx.x; t < t0 + kVoteTile && t < ns; t += kBlock) {
+            const int64_t i = t * kVoteStride;
+            int sl = lds_table_slot(tk, kVoteTable - 1, parent[i]);
+            atomicAdd(&tv[sl], (unsigned)g.deg[i] + 1u);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < kVoteTable; q += kBlock) {
+            if (tk[q] != kEmpty) atomicAdd(&cnt[tk[q]], tv[q]);
+            tk[q] = kEmpty;
+            tv[q] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_split_vote_best(int64_t n, const int32_t *parent, const int32_t *cm,
+                                                           const uint32_t *cnt, unsigned long long *best) {
+    __shared__ int tk[kVoteTable];
+    __shared__ unsigned long long tv[kVoteTable];
+    for (int q = threadIdx.x; q < kVoteTable; q += kBlock) {
+        tk[q] = kEmpty;
+        tv[q] = 0;
+    }
+    __syncthreads();
+    const int64_t ns = (n + kVoteStride - 1) / kVoteStride;
+    for (int64_t t0 = blockIdx.x * (int64_t)kVoteTile; t0 < ns; t0 += (int64_t)gridDim.x * kVoteTile) {
+        for (int64_t t = t0 + threadIdx.x; t < t0 + kVoteTile && t < ns; t += kBlock) {
+            const int64_t i = t * kVoteStride;
+            const int r = parent[i];
+            const unsigned long long v = ((unsigned long long)cnt[r] << 32) | (unsigned)r;
+            int sl = lds_table_slot(tk, kVoteTable - 1, cm[i]);
+            atomicMax(&tv[sl], v);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < kVoteTable; q += kBlock) {
+            if (tk[q] != kEmpty) atomicMax(&best[tk[q]], tv[q]);
+            tk[q] = kEmpty;
+            tv[q] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_split_vote_apply(int64_t n, const int32_t *cm,
+                                                            const unsigned long long *best, int32_t *dom) {
+    const int64_t ns = (n + kVoteStride - 1) / kVoteStride;
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < ns; t += (int64_t)gridDim.x * kBlock) {
+        const int c = cm[t * kVoteStride];
+        dom[c] = (int32_t)(best[c] & 0xffffffffull);
+    }
 }
 
 // Vertex i may skip its row: it hangs directly under its community's picked
@@ -225,12 +300,19 @@ inline unsigned grid1(int64_t n) {
 }  // namespace
 
 void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, int32_t *dom,
-                  hipStream_t s) {
+                  uint32_t *vote_cnt, unsigned long long *vote_best, hipStream_t s) {
     if (g.n == 0) return;
     launch_iota_i32(labels, g.n, s);
     k_split_sample<<<grid1(g.n * kSample), kBlock, 0, s>>>(g, cm, labels);
     k_split_compress<<<grid1(g.n), kBlock, 0, s>>>(labels, g.n);
     k_split_pick<<<grid1(g.n), kBlock, 0, s>>>(labels, cm, g.n, dom);
+    const int64_t ns = (g.n + kVoteStride - 1) / kVoteStride;
+    const unsigned gv = (unsigned)std::min<int64_t>((ns + kVoteTile - 1) / kVoteTile, 4096);
+    launch_fill_i32(reinterpret_cast<int32_t *>(vote_cnt), 0, g.n, s);
+    launch_fill_u64(vote_best, 0, g.n, s);
+    k_split_vote_count<<<gv, kBlock, 0, s>>>(g, labels, vote_cnt);
+    k_split_vote_best<<<gv, kBlock, 0, s>>>(g.n, labels, cm, vote_cnt, vote_best);
+    k_split_vote_apply<<<grid1(ns), kBlock, 0, s>>>(g.n, cm, vote_best, dom);
     // per-bin begin/size over all sub-rounds (buckets of a bin are adjacent)
     BinRanges br;
     for (int b = 0; b < kNumBins; b++) {
