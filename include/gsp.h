@@ -239,7 +239,8 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
  * its own pass-level tests (Algorithm "louvain"); a graph that has finished
  * stays still while the others go on.  Sub-rounds are taken by the vertex's
  * id within its graph, so every graph's result is the one gsp_run gives for
- * it alone.  Learned pruning is not available for batches. */
+ * it alone, with or without learned pruning (each graph runs its own gated,
+ * confirming and plain sweeps). */
 
 /* Loads `graphs` host CSRs (graph k: n[k] >= 1 vertices, nnz[k] entries,
  * offsets[k] int64 [n[k]+1], cols[k] int32 in [0, n[k]), weights[k] fp32 or

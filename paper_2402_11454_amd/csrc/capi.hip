@@ -160,6 +160,8 @@ struct gsp_ctx {
     double *M2g = nullptr, *ggain = nullptr, *bq = nullptr, *bqin = nullptr;
     unsigned long long *gmoved = nullptr;
     uint8_t *gactive = nullptr;
+    uint8_t *ggated = nullptr, *gconfirm = nullptr;   // learned batches: per graph, this sweep's mode
+    int32_t *giter = nullptr;                         // learned batches: per graph l_i
     bool have_batch_result = false;
     std::vector<double> bq_h;             // modularity of each graph
     std::vector<int32_t> bpasses_h;       // passes each graph took part in
@@ -243,6 +245,9 @@ struct gsp_ctx {
         M2g = ggain = bq = bqin = nullptr;
         gmoved = nullptr;
         gactive = nullptr;
+        ggated = nullptr;
+        gconfirm = nullptr;
+        giter = nullptr;
         have_batch_result = false;
         dmoved = dsnap = nullptr;
         cand = nullptr;
@@ -495,8 +500,15 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     std::vector<uint8_t> act;
     std::vector<double> gg;
     std::vector<unsigned long long> gm;
+    // batches: each graph runs the single graph's sweep sequence (gated,
+    // confirming, plain) on its own; gmode holds its current mode
+    std::vector<uint8_t> gmode, ggated_h, gconfirm_h;
+    std::vector<int32_t> giter_h;
     if (batch) {
-        if (cfg.gated) return ctx->fail(GSP_EINVAL, "learned pruning is not available for batches");
+        gmode.assign(G, cfg.gated ? (uint8_t)GATED : (uint8_t)PLAIN);
+        ggated_h.assign(G, 0);
+        gconfirm_h.assign(G, 0);
+        giter_h.assign(G, 0);
         act.assign(G, 1);
         for (int64_t k = 0; k < G; k++) act[k] = cfg.gdone && cfg.gdone[k] ? 0 : 1;
         cfg.li_g.assign(G, 0);
@@ -573,6 +585,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 a.ggain = ctx->ggain;
                 a.gmoved = ctx->gmoved;
                 a.gactive = ctx->gactive;
+                if (mode == GATED) {
+                    a.ggated = ctx->ggated;
+                    a.giter = ctx->giter;
+                }
             }
             if (cap == 0) continue;
             const bool tk = cfg.timing_k && cs == s;
@@ -648,7 +664,8 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         auto ptr = [](const void *q) { return (int64_t)(intptr_t)q; };
         key = {g.n, g.nnz, g.wt, g.graphs, ptr(g.off), ptr(g.col), ptr(g.w), ptr(g.deg), ptr(g.gid), ptr(g.vbase),
                ptr(K), P, ptr(wl.bl), ptr(wl.ch_vert), ptr(wl.ch_beg), ptr(wl.hub_off), ptr(ctx->sc.hkeys),
-               ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), ptr(ctx->sc.hbuck), (int64_t)(batch ? 1 : 0)};
+               ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), ptr(ctx->sc.hbuck), (int64_t)(batch ? 1 : 0),
+               ptr(ctx->ggated), ptr(ctx->giter)};
         for (int k = 0; k <= kNumBins * P; k++) key.push_back(wl.boff[k]);
         for (int p = 0; p <= P; p++) key.push_back(wl.ch_poff[p]);
         int64_t m2bits;
@@ -662,15 +679,33 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     }
     for (int sweep = 0;; sweep++) {
         if (batch) {
-            bool any = false;
-            for (int64_t k = 0; k < G && !any; k++) any = act[k] != 0;
+            bool any = false, any_gated = false, any_confirm = false;
+            for (int64_t k = 0; k < G; k++) {
+                any = any || act[k] != 0;
+                ggated_h[k] = act[k] && gmode[k] == GATED;
+                gconfirm_h[k] = act[k] && gmode[k] == CONFIRM;
+                giter_h[k] = cfg.li_g[k];
+                any_gated = any_gated || ggated_h[k];
+                any_confirm = any_confirm || gconfirm_h[k];
+            }
             if (!any) break;
             HIP_TRY(hipMemcpyAsync(ctx->gactive, act.data(), G, hipMemcpyHostToDevice, s));
+            if (cfg.gated) {
+                HIP_TRY(hipMemcpyAsync(ctx->ggated, ggated_h.data(), G, hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(ctx->giter, giter_h.data(), G * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            }
+            if (any_confirm) {
+                HIP_TRY(hipMemcpyAsync(ctx->gconfirm, gconfirm_h.data(), G, hipMemcpyHostToDevice, s));
+                launch_batch_flag_confirm(g.gid, ctx->gconfirm, g.n, ctx->flag, s);
+                cfg.confirm_sweeps++;
+            }
+            // the sweep runs the gate if any graph is in its gated sweeps
+            mode = any_gated ? GATED : PLAIN;
         } else if (li >= cfg.max_iter) {
             break;
         }
         cfg.sweeps++;
-        if (mode == CONFIRM) {
+        if (!batch && mode == CONFIRM) {
             launch_fill_u8(ctx->flag, 1, g.n, s);
             cfg.confirm_sweeps++;
         }
@@ -747,8 +782,16 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 if (!act[k]) continue;
                 double m2 = ctx->M2g_h[k];
                 double dqk = m2 > 0.0 ? (2.0 * gg[k]) / (m2 * m2) : 0.0;
-                cfg.li_g[k]++;
-                if (dqk <= cfg.tau || cfg.li_g[k] >= cfg.max_iter) act[k] = 0;
+                if (gmode[k] != CONFIRM || gm[k] > 0) cfg.li_g[k]++;   // as counted for one graph
+                if (dqk <= cfg.tau) {
+                    if (gmode[k] == GATED)
+                        gmode[k] = CONFIRM;
+                    else
+                        act[k] = 0;
+                } else if (gmode[k] == CONFIRM) {
+                    gmode[k] = PLAIN;
+                }
+                if (cfg.li_g[k] >= cfg.max_iter) act[k] = 0;
             }
             li++;
             continue;
@@ -1089,8 +1132,6 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     if (!(tolerance >= 0.0) || max_passes < 0) return ctx->fail(GSP_EINVAL, "tolerance < 0 or max_passes < 0");
     gsp_status st0 = check_options(ctx, opt);
     if (st0 != GSP_OK) return st0;
-    if (batch && opt.prune_mode != GSP_PRUNE_PLAIN)
-        return ctx->fail(GSP_EINVAL, "learned pruning is not available for batches");
     ctx->mem_limit = opt.mem_limit_bytes;
     if (ctx->mem_limit && ctx->mem_used > ctx->mem_limit)
         return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
@@ -1373,6 +1414,9 @@ gsp_status gsp_load_batch(gsp_ctx *ctx, int32_t graphs, const int64_t *n, const 
     if (e == hipSuccess) ctx->bqin = ctx->dalloc<double>(G, &e);
     if (e == hipSuccess) ctx->gmoved = ctx->dalloc<unsigned long long>(G, &e);
     if (e == hipSuccess) ctx->gactive = ctx->dalloc<uint8_t>(G, &e);
+    if (e == hipSuccess) ctx->ggated = ctx->dalloc<uint8_t>(G, &e);
+    if (e == hipSuccess) ctx->gconfirm = ctx->dalloc<uint8_t>(G, &e);
+    if (e == hipSuccess) ctx->giter = ctx->dalloc<int32_t>(G, &e);
     if (e != hipSuccess) {
         ctx->free_graph();
         return ctx->fail_hip(e, "hipMalloc(batch state)");

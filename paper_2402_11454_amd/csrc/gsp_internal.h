@@ -148,6 +148,10 @@ struct MoveArgs {
     int32_t *cand = nullptr;                    // gated sweep: candidates (the gate fills `queue`)
     int pass = 0, sweep = 0, iter = 0;          // feature and trace context
     const int64_t *iter_dev = nullptr;          // iter from device memory (sweeps replayed from a graph)
+    // batches: per graph, whether the gate applies in this sweep (a graph in
+    // its confirming or plain sweeps keeps every candidate) and its l_i
+    const uint8_t *ggated = nullptr;
+    const int32_t *giter = nullptr;
     TraceArgs tr;                               // tr.x == nullptr: no capture
     // batch of graphs (g.gid != nullptr): per-graph totals of the sweep and
     // the graphs still iterating
@@ -251,6 +255,8 @@ void launch_batch_cfirst(const int32_t *rank, const int64_t *vbase, int64_t G, c
 void launch_batch_modularity(const Level &g, const int32_t *memb, const double *sig, const int64_t *cfirst,
                              double *qin, double *q, hipStream_t s);
 void launch_add_i32(int32_t *p, int64_t n, int32_t delta, hipStream_t s);
+// flag[v] = 1 for every vertex of a graph with gconfirm set (its confirming sweep)
+void launch_batch_flag_confirm(const int32_t *gid, const uint8_t *gconfirm, int64_t n, uint8_t *flag, hipStream_t s);
 
 // ---- k_split.hip ----
 // labels[i] = smallest vertex of i's component among same-community edges.

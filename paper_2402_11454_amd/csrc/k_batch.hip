@@ -104,6 +104,13 @@ __global__ void __launch_bounds__(kBlock) k_batch_q(const double *sig, const int
     }
 }
 
+// A graph's confirming sweep starts with every vertex unprocessed.
+__global__ void __launch_bounds__(kBlock) k_batch_flag_confirm(const int32_t *gid, const uint8_t *gconfirm, int64_t n,
+                                                              uint8_t *flag) {
+    for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+        if (gconfirm[gid[v]]) flag[v] = 1;
+}
+
 __global__ void __launch_bounds__(kBlock) k_add_i32(int32_t *p, int64_t n, int32_t delta) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] += delta;
 }
@@ -142,6 +149,10 @@ void launch_batch_modularity(const Level &g, const int32_t *memb, const double *
             k_batch_qin<W_F64><<<gr, kBlock, 0, s>>>(g, memb, qin);
     }
     k_batch_q<<<grid_of(g.graphs, 1, 4096), kBlock, 0, s>>>(sig, cfirst, g.graphs, g.M2g, qin, q);
+}
+
+void launch_batch_flag_confirm(const int32_t *gid, const uint8_t *gconfirm, int64_t n, uint8_t *flag, hipStream_t s) {
+    if (n > 0) k_batch_flag_confirm<<<grid_of(n, kBlock * 4, 4096), kBlock, 0, s>>>(gid, gconfirm, n, flag);
 }
 
 void launch_add_i32(int32_t *p, int64_t n, int32_t delta, hipStream_t s) {

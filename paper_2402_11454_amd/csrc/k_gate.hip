@@ -136,14 +136,16 @@ __global__ void __launch_bounds__(kBlock) k_gate(MoveArgs a, GateNet net, float 
         if (valid) {
             while (t >= pre[b + 1]) b++;
             i = a.cand[a.qbase[b] + (t - pre[b])];
+            const int li = a.giter ? a.giter[a.g.gid[i]] : (a.iter_dev ? (int)*a.iter_dev : a.iter);
             gate_features(a.g.deg[i], a.K[i], a.sig[a.cm[i]], a.hfrac[i], a.hgain[i], a.hbits[i], a.dsnap[i], a.pass,
-                          a.iter_dev ? (int)*a.iter_dev : a.iter, x);
+                          li, x);
         }
 #pragma unroll
         for (int f = 0; f < kGateFeatures; f++) fx[w][lane][f] = x[f];
         __syncthreads();
         float z = mlp_rows64(r, fx[w], sb1, sb2, sw3, net.b3);
-        bool keep = valid && z >= theta;
+        // a batch graph outside its gated sweeps keeps every candidate
+        bool keep = valid && (z >= theta || (a.ggated && !a.ggated[a.g.gid[i]]));
         int rank = -1;
         if (keep) {
             rank = atomicAdd(&lcnt[b], 1);

@@ -4,8 +4,14 @@ graph alone (through the C ABI).
 Bar: every graph's membership bit-identical to the oracle's synchronous
 result for that graph alone (gsp_run's contract), its modularity within
 1e-9, and its pass count equal; the batch result equals gsp_run on each
-graph; zero internally-disconnected communities.
+graph; zero internally-disconnected communities.  With learned pruning
+on: each graph's membership and modularity equal gsp_run's for it alone with
+the same network and threshold, the pruned and scanned totals equal the sums
+of those runs', and, on graphs where no gate decision lies within 1e-3 of the
+threshold, the memberships equal the oracle's gated run.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -117,13 +123,85 @@ def test_batch_errors(ctx):
     bad = gi.Graph(n=3, offsets=g.offsets.copy(), cols=np.array([1, 5], np.int32))
     with pytest.raises(gsp.GspError):
         ctx.load_batch([g, bad])
-    ctx.load_batch([g, gi.from_edges(4, [(1, 2)])])
-    with pytest.raises(gsp.GspError):
-        ctx.run_batch(prune_mode=gsp.PRUNE_LEARNED)
     c = gsp.Context(0)
     try:
         c.load_graph(g)
         with pytest.raises(gsp.GspError):
             c.run_batch()                                   # no batch loaded
+        c.load_batch([g, gi.from_edges(4, [(1, 2)])])
+        with pytest.raises(gsp.GspError):
+            c.run_batch(prune_mode=gsp.PRUNE_LEARNED)       # no network set
     finally:
         c.close()
+
+
+# ------------------------------------------------------- learned pruning
+
+def _gate_params(seed, b3, sharp=1.0):
+    """A random gate network (layer widths 8 -> 64 -> 64 -> 1, Glorot-sized
+    uniform weights, small biases) whose output bias b3 sets how much the
+    gate prunes; `sharp` scales the output layer, which spreads the logits so
+    that fewer of them lie near a threshold."""
+    w1, b1, w2, b2, w3, b3_at = 0, 512, 576, 4672, 4736, 4800
+    p = (gi.uniform(seed, gsp.GATE_PARAMS) * 2.0 - 1.0).astype(np.float32)
+    p[w1:b1] *= math.sqrt(6 / 8)
+    p[b1:w2] *= 0.1
+    p[w2:b2] *= math.sqrt(6 / 64)
+    p[b2:w3] *= 0.1
+    p[w3:b3_at] *= math.sqrt(6 / 64) * sharp
+    p[b3_at] = b3 * sharp
+    return p
+
+
+@pytest.mark.parametrize("b3", [0.5, -0.2])
+def test_learned_batch_equals_single_runs(ctx, b3):
+    gs = _mixed_batch()[:14]
+    p = _gate_params(61, b3)
+    ctx.pruner_set(p)
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
+    got = [ctx.batch_membership(k) for k in range(len(gs))]
+    q = ctx.batch_modularity()
+    passes = ctx.batch_passes()
+    st = ctx.stats()
+    pruned = scanned = 0
+    for k, g in enumerate(gs):
+        ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+        res = ctx.louvain(1e-2, 10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
+        assert np.array_equal(got[k], res.membership), f"graph {k} ({g.name}, n={g.n})"
+        assert abs(q[k] - res.modularity) <= 1e-12
+        assert passes[k] == res.stats["passes"]
+        pruned += res.stats["pruned"]
+        scanned += res.stats["scanned_entries"]
+    assert st["pruned"] == pruned and pruned > 0
+    assert st["scanned_entries"] == scanned
+
+
+def test_learned_batch_matches_oracle(ctx):
+    gs = [gi.dcsbm_small(3000, 1), gi.sbm(800, 8, 0.1, 0.005, 2), gi.rmat_small(11, 3),
+          gi.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)]), gi.from_edges(3, [])]
+    p = _gate_params(61, 0.5, sharp=32.0)
+
+    def run(g, tl):
+        r = oracle.louvain(g, sync=True, prune_params=p, theta_logit=tl)
+        return (r.membership.tobytes(), tuple(r.iterations), tuple(r.counters.values()))
+
+    th = None
+    for cand in [0.5, 0.55, 0.45, 0.6, 0.4]:
+        tl = math.log(cand / (1 - cand))
+        if all(run(g, tl) == run(g, tl - 1e-3) == run(g, tl + 1e-3) for g in gs):
+            th = cand
+            break
+    if th is None:
+        pytest.skip("no threshold with a margin on these graphs")
+    ctx.pruner_set(p)
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th)
+    q = ctx.batch_modularity()
+    pruned = 0
+    for k, g in enumerate(gs):
+        ref = oracle.louvain(g, sync=True, prune_params=p, theta=th)
+        assert np.array_equal(ctx.batch_membership(k), ref.membership), k
+        assert abs(q[k] - ref.modularity) <= 1e-9
+        pruned += ref.counters["pruned"]
+    assert ctx.stats()["pruned"] == pruned > 0

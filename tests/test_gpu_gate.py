@@ -50,15 +50,17 @@ def ctx():
     c.close()
 
 
-def _params(seed, b3=0.0):
+def _params(seed, b3=0.0, sharp=1.0):
+    """Random network; `sharp` scales the output layer (w3 and b3), which
+    spreads the logits so that fewer of them lie near a threshold."""
     u = gi.uniform(seed, P)
     p = (u * 2.0 - 1.0).astype(np.float32)
     p[W1:B1] *= math.sqrt(6 / 8)
     p[B1:W2] *= 0.1
     p[W2:B2] *= math.sqrt(6 / 64)
     p[B2:W3] *= 0.1
-    p[W3:B3] *= math.sqrt(6 / 64)
-    p[B3] = b3
+    p[W3:B3] *= math.sqrt(6 / 64) * sharp
+    p[B3] = b3 * sharp
     return p
 
 
@@ -236,7 +238,7 @@ def test_gate_rejecting_everything_equals_plain(ctx):
 
 def test_gated_run_matches_oracle(ctx):
     g = gi.dcsbm_small(8000, 9)
-    p = _params(61, 0.5)
+    p = _params(61, 0.5, sharp=64.0)
 
     def run(tl):
         r = oracle.louvain(g, sync=True, prune_params=p, theta_logit=tl)
