@@ -9,9 +9,11 @@ memory; `warmup` untimed runs and `steps` timed runs of gsp_run (tolerance
 Prints ONE JSON line: edges/s = directed CSR entries / seconds per run of the
 plain method; a roofline object for the dominant single-kernel class (its
 algorithmic bytes from the library's counters over its HIP-event time,
-events recorded around that class only, inside the timed region; with
-per-kernel events on, a sweep's scans run one after another); the same runs
-without events (scans side by side) as config.untimed; the
+events recorded around that class only, on the stream it runs on, inside the
+timed region; a sub-round's scans then run one after another, so that an
+event pair holds one kernel; --timing 3 keeps them side by side, each pair
+on its kernel's stream); the same runs without events (scans side by side,
+sweeps replayed from captured graphs) as config.untimed; the
 learned-pruned method on the same graph (its edges/s, modularity and ratio
 to plain, the network trained on the degree-corrected SBM workload); and a
 CPU baseline: the sequential oracle timed on one host core on the same
@@ -56,7 +58,9 @@ def parse():
     p.add_argument("--theta", type=float, default=0.5, help="learned gate threshold on p")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-learned", action="store_true")
-    p.add_argument("--timing", type=int, default=2, help="0: no per-kernel events (no roofline)")
+    p.add_argument("--timing", type=int, default=2, choices=(0, 2, 3),
+                   help="0: no per-kernel events (no roofline); 2: events with the scans of a sub-round one "
+                        "after another; 3: events on each kernel's own stream, scans side by side")
     p.add_argument("--no-untimed", action="store_true", help="skip the runs without per-kernel events")
     return p.parse_args()
 
@@ -140,7 +144,7 @@ def main():
     if a.timing >= 2:
         cand = {}
         for k in KERNEL_NAMES:
-            ctx.run(a.tolerance, a.max_passes, timing=2, timing_mask=1 << gsp.KERNEL_CLASSES.index(k))
+            ctx.run(a.tolerance, a.max_passes, timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(k))
             ms = ctx.stats()["kernels"][k]["ms"]
             if ms > 0:
                 cand[k] = ms
@@ -150,7 +154,7 @@ def main():
     mask = (1 << gsp.KERNEL_CLASSES.index(dom)) if dom else 0
 
     # timed region: `steps` whole runs of the plain method, graph resident in HBM
-    elapsed, kstats = timed_runs(ctx, gsp, a, a.steps, timing=2 if dom else 0, timing_mask=mask)
+    elapsed, kstats = timed_runs(ctx, gsp, a, a.steps, timing=a.timing if dom else 0, timing_mask=mask)
     ms_per_step = 1000.0 * elapsed / a.steps
     value = g.nnz / (elapsed / a.steps)
     memb = ctx.membership()
@@ -160,8 +164,8 @@ def main():
     print(f"[bench] plain: {a.steps} runs, {ms_per_step:.3f} ms/run, Q={q:.6f}, disconnected={disc}, "
           f"passes={st['passes']} iterations={st['iterations']}", file=sys.stderr, flush=True)
 
-    # the same runs without per-kernel events (the scans of a sub-round then
-    # run side by side on four streams): context beside the timed value
+    # the same runs without per-kernel events (sweeps then replayed from
+    # captured graphs): context beside the timed value
     untimed = None
     if dom and not a.no_untimed:
         el0, _ = timed_runs(ctx, gsp, a, a.steps, timing=0)

@@ -66,7 +66,9 @@ typedef struct gsp_options {
     int32_t split_mode;            /* GSP_SPLIT_PASS (default), GSP_SPLIT_LAST or GSP_SPLIT_NONE */
     int32_t timing;                /* 0: none; 1: per-phase HIP-event times; 2: also per-kernel times
                                       (then a sweep's independent scans run one after another instead of
-                                      side by side on four streams, so each event pair times one kernel) */
+                                      side by side on four streams, so each event pair times one kernel);
+                                      3: per-kernel times with the scans side by side (each event pair on
+                                      its kernel's stream: the kernel's time as it runs beside the others) */
     uint64_t mem_limit_bytes;      /* refuse device allocations beyond this total (0 = no limit) */
     int32_t prune_mode;            /* GSP_PRUNE_PLAIN (default) or GSP_PRUNE_LEARNED (network set by gsp_pruner_set) */
     float prune_threshold;         /* learned gate: scan a vertex iff p = sigmoid(z) >= this (default 0.5) */

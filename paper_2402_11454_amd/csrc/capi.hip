@@ -400,6 +400,7 @@ struct PhaseCfg {
     double tau = 0.0;
     int max_iter = 20;
     bool timing_k = false;
+    bool timing_side = false;   // timed scans stay side by side (timing = 3)
     bool gated = false;            // learned gate in front of the scan
     bool use_graphs = false;       // replay plain sweeps from a captured graph
     float theta_logit = 0.0f;      // scan iff logit >= theta_logit
@@ -604,9 +605,11 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             // the four scans read the same state and write disjoint
             // decisions: the wave-bin, workgroup-bin and hub scans fork onto
             // side streams and join before the moves are applied.  Timed
-            // sweeps stay on one stream, so that an event pair around a
-            // kernel holds that kernel alone.
-            const bool fork = !cfg.timing_k;
+            // sweeps stay on one stream (timing = 2), so that an event pair
+            // around a kernel holds that kernel alone, or keep the side
+            // streams (timing = 3): each pair is then on its kernel's own
+            // stream and times it as it runs beside the others.
+            const bool fork = !cfg.timing_k || cfg.timing_side;
             hipStream_t sw = fork ? ctx->side[0] : cs, sb = fork ? ctx->side[1] : cs, sh = fork ? ctx->side[2] : cs;
             if (fork) {
                 hipEvent_t fe = ctx->fork_ev[p];
@@ -999,6 +1002,7 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
                          "bad options (max_iterations in [0, 100]; sub_rounds a power of two in [1, 64])");
     if (opt.prune_mode != GSP_PRUNE_PLAIN && opt.prune_mode != GSP_PRUNE_LEARNED)
         return ctx->fail(GSP_EINVAL, "bad prune_mode");
+    if (opt.timing < 0 || opt.timing > 3) return ctx->fail(GSP_EINVAL, "timing must lie in [0, 3]");
     if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
         return ctx->fail(GSP_EINVAL, "hub_max_parts must lie in [0, 4096]");
     if (opt.prune_mode == GSP_PRUNE_LEARNED) {
@@ -1183,6 +1187,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         pc.tau = tau;
         pc.max_iter = opt.max_iterations;
         pc.timing_k = tk;
+        pc.timing_side = opt.timing == 3;
         pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
         pc.theta_logit = theta_logit(opt.prune_threshold);
         pc.pass = lp;

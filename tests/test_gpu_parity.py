@@ -299,10 +299,10 @@ def test_graph_replay_equals_direct_launches(ctx, name):
 
 
 def test_timed_runs_equal_untimed(ctx):
-    """Per-kernel timing (the scans of a sub-round then run one after
-    another, launch by launch) gives the result of the untimed runs (scans
-    side by side on four streams, replayed graphs); a class mask times only
-    that class."""
+    """Per-kernel timing (the scans of a sub-round run one after another,
+    launch by launch, or side by side with timing = 3) gives the result of the
+    untimed runs (scans side by side on four streams, replayed graphs); a
+    class mask times only that class."""
     g = _graph("rmat15")
     _load(ctx, g)
     fast = ctx.louvain(tolerance=1e-2, max_passes=10)
@@ -316,6 +316,15 @@ def test_timed_runs_equal_untimed(ctx):
     k = res.stats["kernels"]
     assert k["move_small"]["ms"] > 0 and k["move_wave"]["ms"] == 0
     assert np.array_equal(res.membership, fast.membership)
+    # timing = 3: events on each kernel's own stream, scans side by side
+    wave = gsp.KERNEL_CLASSES.index("move_wave")
+    for mask in (0, 1 << wave):
+        res = ctx.louvain(tolerance=1e-2, max_passes=10, timing=3, timing_mask=mask)
+        k = res.stats["kernels"]
+        assert k["move_wave"]["ms"] > 0 and (k["move_small"]["ms"] > 0) == (mask == 0)
+        assert np.array_equal(res.membership, fast.membership)
+    with pytest.raises(gsp.GspError):
+        ctx.run(timing=4)
 
 
 @pytest.mark.parametrize("name", ["rmat15", "rmat15w", "agg_rmat14", "sbm_w10"])
