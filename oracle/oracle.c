@@ -340,7 +340,17 @@ static int32_t sub_round_of(int64_t i, int32_t rounds) {
  * Within a group every decision comes from one snapshot (orc_move_sync_step);
  * its moves are then applied together, Sigma and the sizes recomputed, and
  * every neighbour j != i of a mover marked unprocessed, so a later group sees
- * them in the same iteration and earlier groups in the next one. */
+ * them in the same iteration and earlier groups in the next one.
+ *
+ * Return moves.  Moves decided from one snapshot can undo each other (two
+ * adjacent vertices of one group each joining the other's community); the
+ * next iteration then swaps them back, and so on, each time with positive
+ * predicted gains while the modularity does not change.  A move of i back
+ * into the community it left at its move in the immediately preceding
+ * iteration is made, but its gain is not added to the iteration's total, so
+ * the tolerance test sees the gain that such a cycle does not deliver.
+ * (The paper's loop moves vertices one at a time, where every reported gain
+ * is real.) */
 int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
                       const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
                       double *dq_iter, int64_t *moved_iter) {
@@ -357,6 +367,14 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
         free(sigma); free(csize); free(unprocessed); free(active); free(dec); free(gain);
         return -1;
     }
+    /* per vertex: the community it left at its last move, and that move's iteration */
+    int32_t *left = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int32_t *left_it = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!left || !left_it) {
+        free(sigma); free(csize); free(unprocessed); free(active); free(dec); free(gain); free(left); free(left_it);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) { left[i] = -1; left_it[i] = -2; }
     memset(unprocessed, 1, (size_t)n);
     double scale = M2 * M2;
     int32_t li = 0;
@@ -374,7 +392,10 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
             moved += orc_move_sync_step(n, off, col, w, M2, K, memb, sigma, csize, active, dec, gain);
             for (int64_t i = 0; i < n; i++) {
                 if (dec[i] == memb[i]) continue;
-                gsum += gain[i];
+                int back = dec[i] == left[i] && left_it[i] == it - 1;   /* a return move */
+                if (!back) gsum += gain[i];
+                left[i] = memb[i];
+                left_it[i] = it;
                 for (int64_t e = off[i]; e < off[i + 1]; e++)
                     if (col[e] != i) unprocessed[col[e]] = 1;
             }
@@ -387,7 +408,7 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
         li = it + 1;
         if (dq <= tau) break;
     }
-    free(sigma); free(csize); free(unprocessed); free(active); free(dec); free(gain);
+    free(sigma); free(csize); free(unprocessed); free(active); free(dec); free(gain); free(left); free(left_it);
     return li;
 }
 

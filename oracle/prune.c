@@ -381,6 +381,10 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * applied every entry (i, j), j != i, of a mover i adds w_ij to D_j.  All
  * start at 0 in the phase.
  *
+ * Return moves (as in orc_move_sync, by sweep index): a move of i back into
+ * the community it left at its move in the preceding sweep is made, but its
+ * gain is not added to the sweep's total.
+ *
  * Traces (trace != NULL): every scan kept by orc_trace_keep(seed, pass,
  * sweep, i) appends (features before the scan, moved) to the trace; sweep
  * is the 0-based sweep index of the phase (confirming sweeps included).
@@ -414,12 +418,15 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
     double *acc = (double *)calloc(N, sizeof(double));   /* K_{i->c} accumulator, dense */
     uint8_t *seen = (uint8_t *)calloc(N, 1);
     int32_t *keys = (int32_t *)malloc(N * sizeof(int32_t));
+    int32_t *left = (int32_t *)malloc(N * sizeof(int32_t));      /* community left at the last move */
+    int32_t *left_sw = (int32_t *)malloc(N * sizeof(int32_t));   /* and that move's sweep */
     if (!sigma || !csize || !unproc || !scan || !dec || !gain || !hfrac || !hgain || !hbits || !dmv || !xf || !acc ||
-        !seen || !keys) {
+        !seen || !keys || !left || !left_sw) {
         free(sigma); free(csize); free(unproc); free(scan); free(dec); free(gain); free(hfrac); free(hgain);
-        free(hbits); free(dmv); free(xf); free(acc); free(seen); free(keys);
+        free(hbits); free(dmv); free(xf); free(acc); free(seen); free(keys); free(left); free(left_sw);
         return -1;
     }
+    for (size_t i = 0; i < N; i++) { left[i] = -1; left_sw[i] = -2; }
     memset(unproc, 1, N);
     double pd[ORC_MLP_PARAMS];
     if (params) widen(params, pd);
@@ -491,7 +498,9 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
             }
             for (int64_t i = 0; i < n; i++) {
                 if (dec[i] == memb[i]) continue;
-                gsum += gain[i];
+                if (!(dec[i] == left[i] && left_sw[i] == sweep - 1)) gsum += gain[i];   /* not a return move */
+                left[i] = memb[i];
+                left_sw[i] = sweep;
                 for (int64_t e = off[i]; e < off[i + 1]; e++)
                     if (col[e] != i) {
                         unproc[col[e]] = 1;
@@ -516,6 +525,6 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
     }
     if (counters) memcpy(counters, cnt, sizeof(cnt));
     free(sigma); free(csize); free(unproc); free(scan); free(dec); free(gain); free(hfrac); free(hgain);
-    free(hbits); free(dmv); free(xf); free(acc); free(seen); free(keys);
+    free(hbits); free(dmv); free(xf); free(acc); free(seen); free(keys); free(left); free(left_sw);
     return li;
 }

@@ -145,15 +145,21 @@ def test_sync_step_matches_bruteforce(seed, loops):
         np.testing.assert_array_equal(ggain, [float(x) for x in gains])
 
 
-def _sync_replay(g, tau, max_iter, rounds):
+def _sync_replay(g, tau, max_iter, rounds, trail=None):
+    """The synchronous phase in exact arithmetic.  A move back into the
+    community the vertex left at its move of the previous iteration does not
+    add its gain to the iteration's total.  `trail` collects each iteration's
+    membership and its actual modularity change."""
     A = dense(g)
     n = g.n
     M2 = sum(sum(r) for r in A)
     memb = list(range(n))
     unproc = [True] * n
+    last = {}          # vertex -> (community it left, iteration of that move)
     li, dqs = 0, []
     for it in range(max_iter):
         gs = Fraction(0)
+        q0 = modularity_allpairs(A, memb)
         for p in range(rounds):
             active = [unproc[i] and _group(i, rounds) == p for i in range(n)]
             for i in range(n):
@@ -162,13 +168,17 @@ def _sync_replay(g, tau, max_iter, rounds):
             dec, gains = _sync_decide(g, A, memb, active)
             for i in range(n):
                 if dec[i] != memb[i]:
-                    gs += gains[i]
+                    if last.get(i) != (dec[i], it - 1):
+                        gs += gains[i]
+                    last[i] = (memb[i], it)
                     for j in g.cols[g.offsets[i]:g.offsets[i + 1]]:
                         if j != i:
                             unproc[int(j)] = True
             memb = dec
         dq = 2 * gs / (M2 * M2)
         dqs.append(dq)
+        if trail is not None:
+            trail.append((list(memb), modularity_allpairs(A, memb) - q0))
         li = it + 1
         if dq <= tau:
             break
@@ -184,6 +194,32 @@ def test_sync_phase_matches_replay(seed, rounds):
     assert list(got) == memb
     assert gli == li
     np.testing.assert_allclose(gdq, [float(x) for x in dqs], atol=1e-13)
+
+
+def test_swap_cycle_stops_at_the_first_all_return_iteration():
+    """Six vertices, one group: from iteration 2 on the two communities
+    trade their labels back and forth (every other membership repeats, the
+    actual modularity does not change), which without the return rule would
+    run to max_iter with a positive predicted total each time.  The phase
+    stops at the first iteration whose moves all return (its total is 0), as
+    the exact replay does."""
+    g = gi.from_edges(6, [(0, 1), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4), (1, 5), (2, 3), (2, 4), (3, 4), (3, 5),
+                          (4, 5)])
+    trail = []
+    memb, li, dqs = _sync_replay(g, 0.0, 12, 1, trail)
+    got, gli, gdq, gmv = oracle.move_sync(g, tau=0.0, max_iter=12, rounds=1)
+    assert list(got) == memb and gli == li == 4
+    assert gdq[li - 1] == 0.0 and gmv[li - 1] > 0
+    np.testing.assert_allclose(gdq, [float(x) for x in dqs], atol=1e-13)
+    # the cycle: iteration 4 restores iteration 2's labels, and iterations 3
+    # and 4 leave the modularity where it was
+    assert trail[1][0] == trail[3][0] != trail[2][0] and trail[2][1] == 0 and trail[3][1] == 0
+    # without the rule the replay would not stop: iterations 3 and 4 repeat
+    # the positive predicted totals (checked on the replay's own decisions)
+    A = dense(g)
+    m2 = trail[2][0]
+    dec, gains = _sync_decide(g, A, m2, [True] * g.n)
+    assert dec == trail[3][0] and sum(gains) > 0
 
 
 def test_singleton_rule_pair():
