@@ -143,7 +143,8 @@ struct gsp_ctx {
     float *hfrac = nullptr, *hgain = nullptr;
     uint8_t *hbits = nullptr;
     double *dmoved = nullptr, *dsnap = nullptr;
-    int64_t *iter_dev = nullptr;   // l_i of the current sweep, for replayed gated sweeps
+    int64_t *iter_dev = nullptr;   // [0] l_i, [1] sweep index of the current sweep (kernels read them)
+    int64_t *mhist = nullptr;      // per vertex: community left at its last move, and that move's sweep
     int32_t *cand = nullptr;
     // the network in its inference formats (kept across loads)
     bool have_net = false;
@@ -232,6 +233,7 @@ struct gsp_ctx {
         }
         gap_col = nullptr;
         gap_w = nullptr;
+        mhist = iter_dev = nullptr;
         ctr = nullptr;
         hfrac = hgain = nullptr;
         hbits = nullptr;
@@ -430,8 +432,6 @@ gsp_status ensure_gate_state(gsp_ctx *ctx) {
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
     ctx->dsnap = ctx->dalloc<double>(ctx->n, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
-    ctx->iter_dev = ctx->dalloc<int64_t>(1, &e);
-    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate history)");
     ctx->cand = ctx->dalloc<int32_t>(ctx->n, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gate candidates)");
     return GSP_OK;
@@ -494,7 +494,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     }
     const GateNet net = cfg.gated ? net_of(ctx) : GateNet();
     enum { GATED, CONFIRM, PLAIN } mode = cfg.gated ? GATED : PLAIN;
+    if (!ctx->mhist || !ctx->iter_dev) return ctx->fail(GSP_ESTATE, "level buffers are not allocated");
     launch_fill_u8(ctx->flag, 1, g.n, s);
+    // no vertex has moved: community -1, sweep -2
+    launch_fill_u64(reinterpret_cast<unsigned long long *>(ctx->mhist), 0xFFFFFFFFFFFFFFFEull, g.n, s);
     int li = 0;
     const bool batch = g.gid != nullptr;
     const int64_t G = batch ? g.graphs : 0;
@@ -582,6 +585,8 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 if (ctx->tracing) a.tr = ctx->trace;
             }
             if (mode == GATED) a.cand = ctx->cand;
+            a.mhist = ctx->mhist;
+            a.sweep_dev = ctx->iter_dev + 1;
             if (batch) {
                 a.ggain = ctx->ggain;
                 a.gmoved = ctx->gmoved;
@@ -713,16 +718,16 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             cfg.confirm_sweeps++;
         }
         IterCounters *ctr = capture ? ctx->ctr : ctx->ctr + (sweep & 1);
+        // l_i (the gate's feature) and the sweep index, read by the kernels
+        ctx->i64_h[6] = li;
+        ctx->i64_h[7] = sweep;
+        HIP_TRY(hipMemcpyAsync(ctx->iter_dev, &ctx->i64_h[6], 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
         if (capture) {
             std::vector<int64_t> km = key;
             km.push_back((int64_t)mode);
             hipGraphExec_t exec = nullptr;
             for (auto &x : ctx->sweep_graphs)
                 if (x.key == km) exec = x.exec;
-            if (hist) {   // l_i for the gate's features
-                ctx->i64_h[7] = li;
-                HIP_TRY(hipMemcpyAsync(ctx->iter_dev, &ctx->i64_h[7], sizeof(int64_t), hipMemcpyHostToDevice, s));
-            }
             if (!exec) {
                 HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
                 enqueue_sweep(sweep, ctr, ctx->cap_stream);
@@ -821,7 +826,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
 gsp_status ensure_levels(gsp_ctx *ctx) {
     if (ctx->offL[0]) return GSP_OK;
     if (ctx->mem_limit) {
-        uint64_t need = 2 * ((ctx->n + 1) * 8 + ctx->nnz * 12 + ctx->n * 12) + ctx->nnz * 12;
+        uint64_t need = 2 * ((ctx->n + 1) * 8 + ctx->nnz * 12 + ctx->n * 12) + ctx->nnz * 12 + ctx->n * 8 + 16;
         if (ctx->mem_used + need > ctx->mem_limit)
             return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
     }
@@ -842,6 +847,10 @@ gsp_status ensure_levels(gsp_ctx *ctx) {
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gap columns)");
     ctx->gap_w = ctx->dalloc<double>(ctx->nnz, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(gap weights)");
+    ctx->mhist = ctx->dalloc<int64_t>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(move records)");
+    ctx->iter_dev = ctx->dalloc<int64_t>(2, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(sweep index)");
     return GSP_OK;
 }
 
@@ -1059,7 +1068,7 @@ gsp_status gsp_create(int device, void *hip_stream, gsp_ctx **out) {
         ctx->own_stream = true;
     }
     if (hipHostMalloc((void **)&ctx->ctr_h, sizeof(IterCounters), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->i64_h, 8 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->i64_h, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->f64_h, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         gsp_destroy(ctx);
         return GSP_ENOMEM;

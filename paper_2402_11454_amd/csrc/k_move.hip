@@ -74,6 +74,19 @@ __device__ __forceinline__ void graph_totals(const MoveArgs &a, int i, double ga
     atomicAdd(&a.gmoved[gk], 1ull);
 }
 
+// The part of a mover's gain (i: d -> bc) that counts towards the sweep's
+// total.  A move back into the community i left at its move of the
+// preceding sweep undoes a swap made from one snapshot, and its gain is not
+// counted (the move is still made).  Records this move.  One lane per mover.
+__device__ __forceinline__ double counted_gain(const MoveArgs &a, int i, int d, int bc, double gain) {
+    if (!a.mhist) return gain;
+    const int32_t sw = (int32_t)*a.sweep_dev;
+    const uint64_t h = (uint64_t)a.mhist[i];
+    a.mhist[i] = (int64_t)(((uint64_t)(uint32_t)d << 32) | (uint32_t)sw);
+    const bool back = (int32_t)(h >> 32) == bc && (int32_t)(uint32_t)h == sw - 1;
+    return back ? 0.0 : gain;
+}
+
 // 2m of vertex i's graph (the level's 2m unless it holds a batch).
 __device__ __forceinline__ double m2_of(const MoveArgs &a, int i) { return a.g.M2g ? a.g.M2g[a.g.gid[i]] : a.M2; }
 
@@ -381,9 +394,10 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
         for (int r = 0; r < kSmallE; r++)
             if (j[r] >= 0 && j[r] != i) mark_neighbour(a, j[r], w[r]);
     bool lead = valid && gl == 0;
+    const double cg = lead && mv ? counted_gain(a, i, d, bc, gain) : 0.0;
     if (a.ggain) {   // batch: per-graph totals, one atomic per graph met by the wavefront
         int gk = valid ? a.g.gid[i] : 0;
-        wave_add_f64_by_key(a.ggain, gk, gain, lead && mv);
+        wave_add_f64_by_key(a.ggain, gk, cg, lead && mv);
         wave_add_u64_by_key(a.gmoved, gk, 1ull, lead && mv);
     }
     if (lead) {
@@ -392,7 +406,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
         if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
         a.dec[i] = mv ? bc : d;
         if (mv) {
-            acc.gain += gain;
+            acc.gain += cg;
             acc.moved++;
         }
         if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
@@ -520,9 +534,10 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
-                acc.gain += gain;
+                const double cg = counted_gain(a, i, d, bc, gain);
+                acc.gain += cg;
                 acc.moved++;
-                if (a.ggain) graph_totals(a, i, gain);
+                if (a.ggain) graph_totals(a, i, cg);
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
@@ -588,9 +603,10 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(Mov
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
-                acc.gain += gain;
+                const double cg = counted_gain(a, i, d, bc, gain);
+                acc.gain += cg;
                 acc.moved++;
-                if (a.ggain) graph_totals(a, i, gain);
+                if (a.ggain) graph_totals(a, i, cg);
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }
@@ -769,9 +785,10 @@ __device__ __forceinline__ void hub_decide(const MoveArgs &a, int i, double bg, 
     if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
     a.dec[i] = mv ? bc : d;
     if (mv) {
-        acc.gain += gain;
+        const double cg = counted_gain(a, i, d, bc, gain);
+        acc.gain += cg;
         acc.moved++;
-        if (a.ggain) graph_totals(a, i, gain);
+        if (a.ggain) graph_totals(a, i, cg);
     }
     if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
 }
@@ -1030,9 +1047,10 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
-                acc.gain += gain;
+                const double cg = counted_gain(a, i, d, bc, gain);
+                acc.gain += cg;
                 acc.moved++;
-                if (a.ggain) graph_totals(a, i, gain);
+                if (a.ggain) graph_totals(a, i, cg);
             }
             if (a.gain_out) a.gain_out[i] = mv ? gain : 0.0;
         }

@@ -169,6 +169,22 @@ def test_move_phase_bit_exact(ctx, name, rounds):
             np.testing.assert_allclose(dq, rdq, rtol=1e-12, atol=0)
 
 
+def test_swap_cycle_return_moves(ctx):
+    """One group of six vertices whose two communities trade labels back
+    and forth from the second iteration on: the phase stops at the first
+    iteration made only of return moves (its gain total 0), as the oracle's
+    does, instead of running to max_iterations."""
+    g = gi.from_edges(6, [(0, 1), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4), (1, 5), (2, 3), (2, 4), (3, 4), (3, 5),
+                          (4, 5)])
+    _load(ctx, g)
+    m, li, dq, mv = ctx.move_phase(None, tolerance=0.0, max_iterations=12, sub_rounds=1)
+    rm, rli, rdq, rmv = oracle.move_sync(g, None, tau=0.0, max_iter=12, rounds=1)
+    assert li == rli == 4 and dq[3] == 0.0 and mv[3] > 0
+    np.testing.assert_array_equal(m, rm)
+    np.testing.assert_array_equal(dq, rdq)
+    np.testing.assert_array_equal(mv, rmv)
+
+
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_run_bit_exact_and_quality(ctx, name):
     g = _graph(name)
