@@ -1,0 +1,124 @@
+"""Full-size parity on the GPU: the 4M-vertex degree-corrected SBM (the
+learned-pruning workload, held-out seed 1000) and the batch of 512 SBM graphs
+(the batch workload), through the C ABI.
+
+Bars:
+  * 4M graph, whole runs: plain and learned-pruned (a seeded random network,
+    see tests/golden/make_dcsbm4m.py) equal to the oracle's stored runs:
+    membership digest, iterations and communities per pass, the pruning
+    counters, Q within 1e-9; no disconnected community;
+  * batch: every 16th graph's membership bit-identical to the oracle's run of
+    that graph alone, Q within 1e-9, passes equal; no graph with a
+    disconnected community; with learned pruning (the trained network), every
+    32nd graph equal to its single-graph GPU run.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gsp_inputs as gi
+import oracle
+import paper_2402_11454_amd as gsp
+from golden import make_dcsbm4m as mk
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dcsbm4m_oracle.json")
+
+
+def _gpu_count():
+    try:
+        import torch
+        return torch.cuda.device_count()
+    except Exception:
+        return 0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if _gpu_count() == 0:
+        pytest.skip("no GPU")
+    c = gsp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def g4m():
+    return gi.dcsbm_4m(mk.SEED)
+
+
+@pytest.fixture(scope="module")
+def gold():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _digest(m):
+    return hashlib.sha1(np.ascontiguousarray(m, dtype=np.int32).tobytes()).hexdigest()
+
+
+def test_dcsbm4m_plain_equals_oracle(ctx, g4m, gold):
+    assert (g4m.n, g4m.nnz) == (gold["n"], gold["nnz"])
+    ctx.load(g4m.offsets, g4m.cols, g4m.weights, n=g4m.n)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10)
+    ref = gold["plain"]
+    assert _digest(res.membership) == ref["membership_sha1"]
+    assert res.stats["iterations"] == ref["iterations"]
+    assert res.stats["communities"] == ref["communities"]
+    assert abs(res.modularity - ref["modularity"]) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+
+
+def test_dcsbm4m_learned_equals_oracle(ctx, g4m, gold):
+    ctx.load(g4m.offsets, g4m.cols, g4m.weights, n=g4m.n)
+    ctx.pruner_set(mk.gate_params())
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=gold["theta"])
+    ref = gold["learned"]
+    assert res.stats["iterations"] == ref["iterations"]
+    for k in ("scanned_vertices", "scanned_entries", "pruned", "confirm_sweeps"):
+        assert res.stats[k] == ref["counters"][k], k
+    assert res.stats["communities"] == ref["communities"]
+    assert _digest(res.membership) == ref["membership_sha1"]
+    assert abs(res.modularity - ref["modularity"]) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return gi.batch_sbm(512, master_seed=4, scale=1.0)
+
+
+def test_batch512_plain_full_size(ctx, batch):
+    ctx.load_batch(batch)
+    ctx.run_batch(1e-2, 10)
+    q = ctx.batch_modularity()
+    passes = ctx.batch_passes()
+    for k, g in enumerate(batch):
+        m = ctx.batch_membership(k)
+        if k % 16 == 0:
+            ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+            assert np.array_equal(m, ref.membership), f"graph {k} (n={g.n})"
+            assert abs(q[k] - ref.modularity) <= 1e-9
+            assert passes[k] == ref.passes
+        cnt, _ = oracle.disconnected(g, m)
+        assert cnt == 0, k
+
+
+def test_batch512_learned_equals_single_runs(ctx, batch):
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, load_params
+    ctx.pruner_set(load_params(DEFAULT_OUT))
+    kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
+    ctx.load_batch(batch)
+    ctx.run_batch(1e-2, 10, **kw)
+    q = ctx.batch_modularity()
+    got = {k: ctx.batch_membership(k) for k in range(0, len(batch), 32)}
+    for k, m in got.items():
+        g = batch[k]
+        ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+        res = ctx.louvain(1e-2, 10, **kw)
+        assert np.array_equal(m, res.membership), k
+        assert abs(q[k] - res.modularity) <= 1e-12
