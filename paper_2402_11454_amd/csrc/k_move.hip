@@ -259,43 +259,58 @@ __device__ __forceinline__ void fold_table(const MoveArgs &a, double m2, int *ke
 
 // ---------------------------------------------------------------- compact
 
+constexpr int kCompactSpan = 4096;   // entries of the buckets per compaction workgroup, at most
+
 // Unprocessed vertices of the sub-round's buckets -> per-bin queues (or,
-// in a gated sweep, per-bin candidate lists for the gate); each block
-// reserves its slots with one atomic per bin.
-__global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32_t *bl) {
+// in a gated sweep, per-bin candidate lists for the gate).  Workgroup k
+// takes the contiguous range [k span, (k + 1) span) of the buckets (span <=
+// kCompactSpan), stages its active vertices in LDS with their rank in their
+// bin, reserves their queue slots with one atomic per bin, then writes them.
+// The queue counters are shared by every workgroup, so their atomics, not
+// the reads, bound this kernel on large levels: one per bin per workgroup
+// (not per 256 entries) keeps them few.
+__global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32_t *bl, int64_t span) {
     __shared__ int lcnt[kNumBins];
     __shared__ int lbase[kNumBins];
+    __shared__ int32_t sv[kCompactSpan];      // staged vertex
+    __shared__ uint32_t sbr[kCompactSpan];    // its bin (top 4 bits) and rank in the bin
     int64_t pre[kNumBins + 1];
     pre[0] = 0;
 #pragma unroll
     for (int b = 0; b < kNumBins; b++) pre[b + 1] = pre[b] + a.qcap[b];
-    int64_t total = pre[kNumBins];
+    const int64_t total = pre[kNumBins];
     const bool gated = a.cand != nullptr;   // the gate fills the queue from the candidates
     int *qcnt = gated ? a.ctr->ccnt[a.round] : a.ctr->qcnt[a.round];
     int32_t *qout = gated ? a.cand : a.queue;
-    for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < total; t0 += (int64_t)gridDim.x * kBlock) {
-        if (threadIdx.x < kNumBins) lcnt[threadIdx.x] = 0;
-        __syncthreads();
-        int64_t t = t0 + threadIdx.x;
-        int b = -1, i = -1, rank = -1;
-        if (t < total) {
-            b = 0;
-            while (t >= pre[b + 1]) b++;
-            i = bl[a.qbase[b] + (t - pre[b])];
-            bool act = a.flag[i] != 0 && (!a.gactive || a.gactive[a.g.gid[i]]);
-            if (b == BIN_HUB) a.hub_act[i] = act ? 1 : 0;
-            if (act) {
-                a.flag[i] = 0;
-                if (a.dmoved) a.dsnap[i] = a.dmoved[i];   // the features' D_i
-                rank = atomicAdd(&lcnt[b], 1);
-            }
+    const int64_t lo = blockIdx.x * span;
+    const int64_t hi = lo + span < total ? lo + span : total;
+    if (threadIdx.x < kNumBins) lcnt[threadIdx.x] = 0;
+    __shared__ int nst;
+    if (threadIdx.x == 0) nst = 0;
+    __syncthreads();
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kBlock) {
+        int b = 0;
+        while (t >= pre[b + 1]) b++;
+        const int i = bl[a.qbase[b] + (t - pre[b])];
+        const bool act = a.flag[i] != 0 && (!a.gactive || a.gactive[a.g.gid[i]]);
+        if (b == BIN_HUB) a.hub_act[i] = act ? 1 : 0;
+        if (act) {
+            a.flag[i] = 0;
+            if (a.dmoved) a.dsnap[i] = a.dmoved[i];   // the features' D_i
+            const int rank = atomicAdd(&lcnt[b], 1);
+            const int slot = atomicAdd(&nst, 1);
+            sv[slot] = i;
+            sbr[slot] = ((uint32_t)b << 28) | (uint32_t)rank;
         }
-        __syncthreads();
-        if (threadIdx.x < kNumBins && lcnt[threadIdx.x] > 0)
-            lbase[threadIdx.x] = atomicAdd(&qcnt[threadIdx.x], lcnt[threadIdx.x]);
-        __syncthreads();
-        if (rank >= 0) qout[a.qbase[b] + lbase[b] + rank] = i;
-        __syncthreads();
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBins && lcnt[threadIdx.x] > 0)
+        lbase[threadIdx.x] = atomicAdd(&qcnt[threadIdx.x], lcnt[threadIdx.x]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nst; k += kBlock) {
+        const uint32_t br = sbr[k];
+        const int b = (int)(br >> 28);
+        qout[a.qbase[b] + lbase[b] + (int64_t)(br & 0x0FFFFFFFu)] = sv[k];
     }
 }
 
@@ -1167,7 +1182,15 @@ void launch_move_compact(const MoveArgs &a, const WorkLists &wl, hipStream_t s) 
     int64_t total = 0;
     for (int b = 0; b < kNumBins; b++) total += a.qcap[b];
     if (total == 0) return;
-    k_move_compact<<<cap_grid((total + kBlock - 1) / kBlock, 4096), kBlock, 0, s>>>(a, wl.bl);
+    // one pass of 256 entries per workgroup while that gives at most 1024
+    // workgroups, then longer ranges (at most kCompactSpan entries)
+    int64_t blocks = (total + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < (total + kCompactSpan - 1) / kCompactSpan) blocks = (total + kCompactSpan - 1) / kCompactSpan;
+    int64_t span = (total + blocks - 1) / blocks;
+    span = (span + kBlock - 1) / kBlock * kBlock;
+    blocks = (total + span - 1) / span;
+    k_move_compact<<<(unsigned)blocks, kBlock, 0, s>>>(a, wl.bl, span);
 }
 
 void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
