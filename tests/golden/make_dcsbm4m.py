@@ -7,7 +7,7 @@ network is not a trained one: gate_params() draws it from a seeded uniform
 law (Glorot-sized layers, output layer scaled by `sharp` so that few logits
 lie near the threshold), so no input of the oracle comes from the GPU path.
 
-    python tests/golden/make_dcsbm4m.py      # about 10 minutes on one core
+    python tests/golden/make_dcsbm4m.py      # about 4 minutes on one core
 """
 import hashlib
 import json
