@@ -259,7 +259,8 @@ gsp_status gsp_run_batch(gsp_ctx *ctx, double tolerance, int32_t max_passes, con
 gsp_status gsp_get_batch_membership(gsp_ctx *ctx, int32_t graph, int32_t *out, int where);
 
 /* Modularity (Eq. 1, the graph's own 2m) of every graph's result: q_out
- * has one value per graph (host). */
+ * has one value per graph (host).  Computed on the device at the first call
+ * after a run (an evaluation, not part of gsp_run_batch). */
 gsp_status gsp_get_batch_modularity(gsp_ctx *ctx, double *q_out);
 
 /* Passes each graph took part in (host, one value per graph). */

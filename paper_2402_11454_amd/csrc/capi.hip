@@ -165,6 +165,8 @@ struct gsp_ctx {
     int32_t *giter = nullptr;                         // learned batches: per graph l_i
     bool have_batch_result = false;
     std::vector<double> bq_h;             // modularity of each graph
+    bool bq_pending = false;              // bq_h not computed yet for the last batch run
+    int64_t batch_ncomm = 0;              // communities of the last batch run (all graphs)
     std::vector<int32_t> bpasses_h;       // passes each graph took part in
     // trace capture (kept across loads and runs until stopped)
     bool tracing = false;
@@ -1319,27 +1321,19 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         if (st != GSP_OK) return st;
     }
     if (batch) {
-        // each graph's modularity with its own 2m; communities of graph k are
-        // [top[vbase0[k]], top[vbase0[k + 1]]) after the numbering above
-        Level g0 = level0(ctx);
-        g0.graphs = G;
-        g0.gid = ctx->gid0;
-        g0.vbase = ctx->vbase0;
-        g0.M2g = ctx->M2g;
-        launch_fill_f64(ctx->sig, 0.0, ctx->n, s);
-        launch_fill_i32(ctx->csize, 0, ctx->n, s);
-        launch_community_totals(ctx->K0, ctx->top, ctx->n, ctx->sig, ctx->csize, s);
         // the last renumbering left the community count in sc.i64e (none ran
-        // when max_passes = 0: then every vertex is its own community)
+        // when max_passes = 0: then every vertex is its own community); the
+        // graphs' modularities are computed when first asked for
         if (passes == 0) launch_fill_i64(ctx->sc.i64e, ctx->n, 1, s);
-        launch_batch_cfirst(ctx->top, ctx->vbase0, G, ctx->sc.i64e, ctx->cfirst, s);
-        launch_batch_modularity(g0, ctx->top, ctx->sig, ctx->cfirst, ctx->bqin, ctx->bq, s);
-        ctx->bq_h.assign(G, 0.0);
-        HIP_TRY(hipMemcpyAsync(ctx->bq_h.data(), ctx->bq, G * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&ctx->i64_h[8], ctx->sc.i64e, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     }
     ctx->timer.end(t_all);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
+    if (batch) {
+        ctx->batch_ncomm = ctx->i64_h[8];
+        ctx->bq_pending = true;
+    }
     ctx->stats.passes = passes;
     if (tphase) {
         double acc[100 + GSP_K_COUNT] = {0};
@@ -1480,6 +1474,31 @@ gsp_status gsp_get_batch_membership(gsp_ctx *ctx, int32_t graph, int32_t *out, i
 gsp_status gsp_get_batch_modularity(gsp_ctx *ctx, double *q_out) {
     if (!ctx || !q_out) return GSP_EINVAL;
     if (!ctx->have_batch_result) return ctx->fail(GSP_ESTATE, "no batch result (call gsp_run_batch)");
+    (void)hipSetDevice(ctx->device);
+    if (ctx->bq_pending) {
+        // each graph's modularity (Eq. 1) with its own 2m; communities of
+        // graph k are [top[vbase0[k]], top[vbase0[k + 1]]) in the final
+        // numbering
+        hipStream_t s = ctx->stream;
+        const int64_t G = ctx->batch_graphs;
+        Level g0 = level0(ctx);
+        g0.graphs = G;
+        g0.gid = ctx->gid0;
+        g0.vbase = ctx->vbase0;
+        g0.M2g = ctx->M2g;
+        launch_fill_f64(ctx->sig, 0.0, ctx->n, s);
+        launch_fill_i32(ctx->csize, 0, ctx->n, s);
+        launch_community_totals(ctx->K0, ctx->top, ctx->n, ctx->sig, ctx->csize, s);
+        ctx->i64_h[8] = ctx->batch_ncomm;
+        HIP_TRY(hipMemcpyAsync(ctx->sc.i64e, &ctx->i64_h[8], sizeof(int64_t), hipMemcpyHostToDevice, s));
+        launch_batch_cfirst(ctx->top, ctx->vbase0, G, ctx->sc.i64e, ctx->cfirst, s);
+        launch_batch_modularity(g0, ctx->top, ctx->sig, ctx->cfirst, ctx->bqin, ctx->bq, s);
+        ctx->bq_h.assign(G, 0.0);
+        HIP_TRY(hipMemcpyAsync(ctx->bq_h.data(), ctx->bq, G * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipGetLastError());
+        ctx->bq_pending = false;
+    }
     for (int64_t k = 0; k < ctx->batch_graphs; k++) q_out[k] = ctx->bq_h[k];
     return GSP_OK;
 }

@@ -110,12 +110,20 @@ __device__ __forceinline__ void load_biases(const GateNet &net, float *b1, float
     }
 }
 
+constexpr int kGateSpan = 4096;   // candidates per workgroup, at most
+
 // Gated sweep of one sub-round: candidates -> features -> network -> queue.
+// Workgroup k takes the k-th of gridDim.x equal ranges of the candidates (at
+// most kGateSpan), stages the vertices it keeps in LDS with their rank in
+// their bin and reserves their queue slots with one atomic per bin.
 __global__ void __launch_bounds__(kBlock) k_gate(MoveArgs a, GateNet net, float theta) {
     __shared__ float sb1[kGateHidden], sb2[kGateHidden], sw3[kGateHidden];
     __shared__ uint16_t fx[kBlock / kWave][kWave][kGateFeatures];
     __shared__ int lcnt[kNumBins], lbase[kNumBins];
     __shared__ unsigned long long spr[kBlock / kWave];
+    __shared__ int32_t sv[kGateSpan];      // kept vertex
+    __shared__ uint32_t sbr[kGateSpan];    // its bin (top 4 bits) and rank in the bin
+    __shared__ int nst;
     load_biases(net, sb1, sb2, sw3);
     NetRegs r;
     load_net(net, r);
@@ -124,13 +132,18 @@ __global__ void __launch_bounds__(kBlock) k_gate(MoveArgs a, GateNet net, float 
 #pragma unroll
     for (int b = 0; b < kNumBins; b++) pre[b + 1] = pre[b] + a.ctr->ccnt[a.round][b];
     const int64_t total = pre[kNumBins];
+    int64_t span = (total + gridDim.x - 1) / gridDim.x;
+    span = (span + kBlock - 1) / kBlock * kBlock;
+    const int64_t lo = blockIdx.x * span;
+    const int64_t hi = lo + span < total ? lo + span : total;
     const int w = threadIdx.x / kWave, lane = lane_id();
     unsigned long long pruned = 0;
+    if (threadIdx.x < kNumBins) lcnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) nst = 0;
     __syncthreads();
-    for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < total; t0 += (int64_t)gridDim.x * kBlock) {
-        if (threadIdx.x < kNumBins) lcnt[threadIdx.x] = 0;
+    for (int64_t t0 = lo; t0 < hi; t0 += kBlock) {   // uniform over the workgroup
         int64_t t = t0 + threadIdx.x;
-        bool valid = t < total;
+        bool valid = t < hi;
         int b = 0, i = -1;
         uint16_t x[kGateFeatures] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (valid) {
@@ -146,18 +159,24 @@ __global__ void __launch_bounds__(kBlock) k_gate(MoveArgs a, GateNet net, float 
         float z = mlp_rows64(r, fx[w], sb1, sb2, sw3, net.b3);
         // a batch graph outside its gated sweeps keeps every candidate
         bool keep = valid && (z >= theta || (a.ggated && !a.ggated[a.g.gid[i]]));
-        int rank = -1;
         if (keep) {
-            rank = atomicAdd(&lcnt[b], 1);
+            const int rank = atomicAdd(&lcnt[b], 1);
+            const int slot = atomicAdd(&nst, 1);
+            sv[slot] = i;
+            sbr[slot] = ((uint32_t)b << 28) | (uint32_t)rank;
         } else if (valid) {
             pruned++;
             if (b == BIN_HUB) a.hub_act[i] = 0;
         }
-        __syncthreads();
-        if (threadIdx.x < kNumBins && lcnt[threadIdx.x] > 0)
-            lbase[threadIdx.x] = atomicAdd(&a.ctr->qcnt[a.round][threadIdx.x], lcnt[threadIdx.x]);
-        __syncthreads();
-        if (rank >= 0) a.queue[a.qbase[b] + lbase[b] + rank] = i;
+        __syncthreads();   // fx is rewritten by the next pass
+    }
+    if (threadIdx.x < kNumBins && lcnt[threadIdx.x] > 0)
+        lbase[threadIdx.x] = atomicAdd(&a.ctr->qcnt[a.round][threadIdx.x], lcnt[threadIdx.x]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nst; k += kBlock) {
+        const uint32_t br = sbr[k];
+        const int b = (int)(br >> 28);
+        a.queue[a.qbase[b] + lbase[b] + (int64_t)(br & 0x0FFFFFFFu)] = sv[k];
     }
     long long pw = group_sum_ll<kWave>((long long)pruned);
     if (lane == 0) spr[w] = (unsigned long long)pw;
@@ -333,7 +352,12 @@ inline unsigned grid_cap(int64_t units, int64_t cap) {
 
 void launch_gate(const MoveArgs &a, const GateNet &net, float theta_logit, int64_t cap, hipStream_t s) {
     if (cap == 0) return;
-    k_gate<<<grid_cap((cap + kBlock - 1) / kBlock, 4096), kBlock, 0, s>>>(a, net, theta_logit);
+    // the candidates (at most cap) are split over the grid in equal ranges of
+    // at most kGateSpan
+    int64_t blocks = (cap + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < (cap + kGateSpan - 1) / kGateSpan) blocks = (cap + kGateSpan - 1) / kGateSpan;
+    k_gate<<<(unsigned)blocks, kBlock, 0, s>>>(a, net, theta_logit);
 }
 
 void launch_gate_eval(const GateNet &net, const float *x, int64_t rows, float *logit, hipStream_t s) {
