@@ -9,6 +9,10 @@ kernel's sources (its file, the headers, the host code), and a readable table to
 
     python -m paper_2402_11454_amd.pmc_traffic --run            # the workload (under rocprofv3)
     python -m paper_2402_11454_amd.pmc_traffic --summarize FETCH_DB WRITE_DB --cmd "..."
+
+--scale/--seed/--weights choose another R-MAT graph (as bench.py builds
+it); its summary goes to profiles/traffic_rmat<scale>.json and .md (the
+R-MAT 20 one, which bench.py reads, to profiles/traffic.json).
 """
 import argparse
 import json
@@ -21,7 +25,7 @@ ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 30
 
 
-def run_workload(runs: int):
+def run_workload(runs: int, scale: int = 20, seed: int = 20, weights=None):
     sys.path.insert(0, ROOT)
     import torch
     import gsp_inputs as gi
@@ -32,7 +36,11 @@ def run_workload(runs: int):
     for _ in range(3):
         torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
-    g = gi.rmat20()
+    if scale == 20 and seed == 20 and weights is None:
+        g = gi.rmat20()
+    else:
+        g = gi.rmat(scale, 16, *gi.RMAT_ABC, seed, weights=weights, name=f"rmat-{scale}")
+    print(f"[pmc] graph ready: n={g.n} nnz={g.nnz}", flush=True)
     ctx = gsp.Context(0, stream=torch.cuda.current_stream())
     ctx.load_graph(g)
     for k in range(runs):
@@ -70,7 +78,7 @@ def short(name: str) -> str:
     return s.replace("void ", "")
 
 
-def summarize(fetch_db, write_db, cmd):
+def summarize(fetch_db, write_db, cmd, scale: int = 20):
     sys.path.insert(0, ROOT)
     from bench import kernel_source_hash
     fe = per_kernel(fetch_db, "FETCH_SIZE")
@@ -101,13 +109,13 @@ def summarize(fetch_db, write_db, cmd):
         for f in ("fetch_kib", "write_kib", "bytes_per_launch"):
             acc[f] = round(acc[f] / n, 1)
         acc["source_hash"] = kernel_source_hash(name)
-    out = {"workload": "rmat20", "command": cmd, "copy_kernel": short(copy),
+    out = {"workload": f"rmat{scale}", "command": cmd, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
-    with open(os.path.join(prof, "traffic.json"), "w") as f:
+    with open(os.path.join(prof, "traffic.json" if scale == 20 else f"traffic_rmat{scale}.json"), "w") as f:
         json.dump(out, f, indent=1)
-    with open(os.path.join(prof, "traffic_rmat20.md"), "w") as f:
-        f.write("# HBM traffic per dispatch: plain GSP-Louvain on R-MAT scale 20\n\n")
+    with open(os.path.join(prof, f"traffic_rmat{scale}.md"), "w") as f:
+        f.write(f"# HBM traffic per dispatch: plain GSP-Louvain on R-MAT scale {scale}\n\n")
         f.write(f"Command (two passes, one counter each):\n\n```\n{cmd}\n```\n\n")
         f.write(f"Scale: y = 2x over {COPY_BYTES} bytes (`{short(copy)[:60]}`) reads {fe[copy][1]:.0f} KiB "
                 f"(FETCH_SIZE) -> factor {f_scale:.4f}; write factor {w_scale:.4f}.\n\n")
@@ -123,8 +131,12 @@ if __name__ == "__main__":
     ap.add_argument("--runs", type=int, default=2)
     ap.add_argument("--summarize", nargs=2)
     ap.add_argument("--cmd", default="")
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=20)
+    ap.add_argument("--weights", default="", help="lo,hi: symmetric fp32 weights U[lo,hi)")
     a = ap.parse_args()
     if a.run:
-        run_workload(a.runs)
+        wts = tuple(float(v) for v in a.weights.split(",")) if a.weights else None
+        run_workload(a.runs, a.scale, a.seed, wts)
     if a.summarize:
-        summarize(a.summarize[0], a.summarize[1], a.cmd)
+        summarize(a.summarize[0], a.summarize[1], a.cmd, a.scale)
