@@ -54,6 +54,12 @@ def _mixed_batch():
     return gs
 
 
+def _weighted_batch():
+    gs = [gi.dcsbm_small(3000, s) for s in range(3)] + [gi.rmat_small(10, 4, weights=(1.0, 4.0))]
+    gs.append(gi.sbm(800, 8, 0.1, 0.005, 2))          # unit weights inside a weighted batch
+    return gs
+
+
 def _check_batch(ctx, gs, **kw):
     ctx.load_batch(gs)
     ctx.run_batch(1e-2, 10, **kw)
@@ -79,9 +85,7 @@ def test_batch_split_modes(ctx, split_mode):
 
 
 def test_weighted_batch(ctx):
-    gs = [gi.dcsbm_small(3000, s) for s in range(3)] + [gi.rmat_small(10, 4, weights=(1.0, 4.0))]
-    gs.append(gi.sbm(800, 8, 0.1, 0.005, 2))          # unit weights inside a weighted batch
-    _check_batch(ctx, gs)
+    _check_batch(ctx, _weighted_batch())
 
 
 def test_batch_equals_single_runs(ctx):
@@ -153,9 +157,10 @@ def _gate_params(seed, b3, sharp=1.0):
     return p
 
 
-@pytest.mark.parametrize("b3", [0.5, -0.2])
-def test_learned_batch_equals_single_runs(ctx, b3):
-    gs = _mixed_batch()[:14]
+@pytest.mark.parametrize("b3,make", [(0.5, lambda: _mixed_batch()[:14]), (-0.2, lambda: _mixed_batch()[:14]),
+                                     (0.5, _weighted_batch)])
+def test_learned_batch_equals_single_runs(ctx, b3, make):
+    gs = make()
     p = _gate_params(61, b3)
     ctx.pruner_set(p)
     ctx.load_batch(gs)
