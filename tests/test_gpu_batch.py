@@ -88,6 +88,31 @@ def test_weighted_batch(ctx):
     _check_batch(ctx, _weighted_batch())
 
 
+def _hub_batch():
+    # R-MAT 15 and 14 hold vertices of more than 2048 entries (the hub path)
+    return [gi.rmat_small(15, 3), gi.from_edges(3, [(0, 1), (1, 2)]), gi.rmat_small(14, 8),
+            gi.sbm(2000, 10, 0.05, 0.002, 5), gi.rmat_small(15, 5, weights=(1.0, 4.0))]
+
+
+def test_batch_with_hubs(ctx):
+    _check_batch(ctx, _hub_batch())
+
+
+def test_learned_batch_with_hubs_equals_single_runs(ctx):
+    gs = _hub_batch()
+    ctx.pruner_set(_gate_params(61, 0.5))
+    kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10, **kw)
+    got = [ctx.batch_membership(k) for k in range(len(gs))]
+    q = ctx.batch_modularity()
+    for k, g in enumerate(gs):
+        ctx.load(g.offsets, g.cols, g.weights, n=g.n)
+        res = ctx.louvain(1e-2, 10, **kw)
+        assert np.array_equal(got[k], res.membership), k
+        assert abs(q[k] - res.modularity) <= 1e-12
+
+
 def test_batch_equals_single_runs(ctx):
     gs = _mixed_batch()[:9]
     ctx.load_batch(gs)
