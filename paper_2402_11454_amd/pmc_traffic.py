@@ -13,6 +13,14 @@ kernel's sources (its file, the headers, the host code), and a readable table to
 --scale/--seed/--weights choose another R-MAT graph (as bench.py builds
 it); its summary goes to profiles/traffic_rmat<scale>.json and .md (the
 R-MAT 20 one, which bench.py reads, to profiles/traffic.json).
+
+Per phase: the counters' bytes of one run, phase by phase (local moving,
+split, aggregation, the rest), over the phases' wall times from HIP events
+(timing = 1: scans side by side, sweeps replayed from graphs, as in untimed
+runs):
+
+    python -m paper_2402_11454_amd.pmc_traffic --phase-times OUT.json [--scale ...]   # on the GPU
+    python -m paper_2402_11454_amd.pmc_traffic --phases TRAFFIC.json OUT.json --cmd "..."
 """
 import argparse
 import json
@@ -36,10 +44,7 @@ def run_workload(runs: int, scale: int = 20, seed: int = 20, weights=None):
     for _ in range(3):
         torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
-    if scale == 20 and seed == 20 and weights is None:
-        g = gi.rmat20()
-    else:
-        g = gi.rmat(scale, 16, *gi.RMAT_ABC, seed, weights=weights, name=f"rmat-{scale}")
+    g = _graph(scale, seed, weights)
     print(f"[pmc] graph ready: n={g.n} nnz={g.nnz}", flush=True)
     ctx = gsp.Context(0, stream=torch.cuda.current_stream())
     ctx.load_graph(g)
@@ -78,7 +83,7 @@ def short(name: str) -> str:
     return s.replace("void ", "")
 
 
-def summarize(fetch_db, write_db, cmd, scale: int = 20):
+def summarize(fetch_db, write_db, cmd, scale: int = 20, runs: int = 2):
     sys.path.insert(0, ROOT)
     from bench import kernel_source_hash
     fe = per_kernel(fetch_db, "FETCH_SIZE")
@@ -109,7 +114,7 @@ def summarize(fetch_db, write_db, cmd, scale: int = 20):
         for f in ("fetch_kib", "write_kib", "bytes_per_launch"):
             acc[f] = round(acc[f] / n, 1)
         acc["source_hash"] = kernel_source_hash(name)
-    out = {"workload": f"rmat{scale}", "command": cmd, "copy_kernel": short(copy),
+    out = {"workload": f"rmat{scale}", "command": cmd, "runs": runs, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
     with open(os.path.join(prof, "traffic.json" if scale == 20 else f"traffic_rmat{scale}.json"), "w") as f:
@@ -125,6 +130,74 @@ def summarize(fetch_db, write_db, cmd, scale: int = 20):
     print(json.dumps(out)[:400])
 
 
+def _graph(scale, seed, weights):
+    import gsp_inputs as gi
+    if scale == 20 and seed == 20 and weights is None:
+        return gi.rmat20()
+    return gi.rmat(scale, 16, *gi.RMAT_ABC, seed, weights=weights, name=f"rmat-{scale}")
+
+
+def phase_times(out_path: str, runs: int, scale: int, seed: int, weights):
+    """Mean phase wall times (ms) of `runs` runs after two warm-up runs."""
+    sys.path.insert(0, ROOT)
+    import paper_2402_11454_amd as gsp
+    g = _graph(scale, seed, weights)
+    ctx = gsp.Context(0)
+    ctx.load_graph(g)
+    for _ in range(2):
+        ctx.run(1e-2, 10, timing=1)
+    acc = {k: 0.0 for k in ("ms_move", "ms_split", "ms_aggregate", "ms_other", "ms_total")}
+    for k in range(runs):
+        ctx.run(1e-2, 10, timing=1)
+        st = ctx.stats()
+        for f in acc:
+            acc[f] += st[f] / runs
+        print(f"[phases] run {k + 1}/{runs}: {st['ms_total']:.3f} ms", flush=True)
+    ctx.close()
+    out = {"workload": f"rmat{scale}", "n": int(g.n), "nnz": int(g.nnz), "runs": runs, **acc}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+# kernels that belong to one phase only (by name prefix); the fills, scans
+# and renumbering kernels that every phase shares are not attributed, so a
+# phase's bytes are a lower bound while its time includes them
+PHASE_OF = (("move", ("k_move", "k_hub", "k_gate")), ("split", ("k_split",)),
+            ("aggregate", ("k_agg", "k_member_degrees")))
+
+
+def phases(traffic_json: str, times_json: str, cmd: str):
+    with open(traffic_json) as f:
+        tr = json.load(f)
+    with open(times_json) as f:
+        tm = json.load(f)
+    runs = tr.get("runs", 1)
+    byts = {"move": 0.0, "split": 0.0, "aggregate": 0.0}
+    for name, v in tr["kernels"].items():
+        ph = next((p for p, pre in PHASE_OF if name.startswith(pre)), None)
+        if ph:
+            byts[ph] += v["bytes_per_launch"] * v["dispatches"] / runs
+    ms = {"move": tm["ms_move"], "split": tm["ms_split"], "aggregate": tm["ms_aggregate"]}
+    w = tm["workload"]
+    path = os.path.join(ROOT, "profiles", f"phases_{w}.md")
+    with open(path, "w") as f:
+        f.write(f"# HBM traffic per phase: plain GSP-Louvain on R-MAT scale {w[4:]} "
+                f"(n={tm['n']}, {tm['nnz']} entries)\n\n")
+        f.write(f"Commands:\n\n```\n{cmd}\n```\n\n")
+        f.write(f"Bytes: the counters' FETCH + WRITE bytes of one run ({traffic_json}, {runs} run(s) under counters) "
+                f"of the kernels that belong to one phase (fills, scans and renumbering shared by the phases are "
+                f"left out); FETCH_SIZE / WRITE_SIZE count the L2's traffic to memory, i.e. HBM and the Infinity "
+                f"Cache in front of it.  Time: the phases' wall times from HIP events, mean of {tm['runs']} runs "
+                f"with timing = 1 (scans side by side, sweeps replayed from graphs); whole run "
+                f"{tm['ms_total']:.3f} ms (other steps {tm['ms_other']:.3f} ms).  Peak: HBM 8000 GB/s.\n\n")
+        f.write("| phase | GB per run | ms per run | GB/s | of HBM peak |\n|---|---:|---:|---:|---:|\n")
+        for p in ("move", "split", "aggregate"):
+            gbs = byts[p] / 1e9 / (ms[p] * 1e-3) if ms[p] > 0 else 0.0
+            f.write(f"| {p} | {byts[p] / 1e9:.3f} | {ms[p]:.3f} | {gbs:.0f} | {gbs / 8000.0:.1%} |\n")
+    print(open(path).read())
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--run", action="store_true")
@@ -134,9 +207,15 @@ if __name__ == "__main__":
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--seed", type=int, default=20)
     ap.add_argument("--weights", default="", help="lo,hi: symmetric fp32 weights U[lo,hi)")
+    ap.add_argument("--phase-times", default="", help="write the phases' mean wall times to this JSON")
+    ap.add_argument("--phases", nargs=2, help="TRAFFIC_JSON TIMES_JSON: per-phase summary")
     a = ap.parse_args()
+    wts = tuple(float(v) for v in a.weights.split(",")) if a.weights else None
     if a.run:
-        wts = tuple(float(v) for v in a.weights.split(",")) if a.weights else None
         run_workload(a.runs, a.scale, a.seed, wts)
     if a.summarize:
-        summarize(a.summarize[0], a.summarize[1], a.cmd, a.scale)
+        summarize(a.summarize[0], a.summarize[1], a.cmd, a.scale, a.runs)
+    if a.phase_times:
+        phase_times(a.phase_times, 3, a.scale, a.seed, wts)
+    if a.phases:
+        phases(a.phases[0], a.phases[1], a.cmd)
