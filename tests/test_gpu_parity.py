@@ -200,6 +200,36 @@ def test_run_bit_exact_and_quality(ctx, name):
     assert res.modularity >= qa - 0.005
 
 
+def _random_graph(seed):
+    """A planted-partition graph of random size and density with dyadic
+    weights (exact sums in fp64) and a few self-loops."""
+    u = gi.uniform(1000 + seed, 8)
+    n = int(50 + u[0] * 4000)
+    blocks = max(1, int(n / (20 + u[1] * 200)))
+    base = gi.sbm(n, blocks, 0.05 + 0.3 * u[2], 0.0005 + 0.005 * u[3], 77 + seed)
+    rows = np.repeat(np.arange(n), np.diff(base.offsets))
+    keep = rows < base.cols
+    ew = gi.uniform(2000 + seed, int(keep.sum()))
+    edges = list(zip(rows[keep].tolist(), base.cols[keep].tolist()))
+    weights = {e: 0.25 * (1 + int(x * 15)) for e, x in zip(edges, ew)} if seed % 2 else None
+    g = gi.from_edges(n, edges, weights=weights)
+    lv = gi.uniform(3000 + seed, 4)
+    return gi.with_self_loops(g, {int(lv[0] * n): 0.5, int(lv[1] * n): 2.0})
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_graphs_match_oracle(ctx, seed):
+    g = _random_graph(seed)
+    _load(ctx, g)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+    np.testing.assert_array_equal(res.membership, ref.membership)
+    assert res.stats["iterations"] == ref.iterations
+    assert res.stats["communities"] == ref.communities
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+
+
 def test_run_rmat20_full_size(ctx):
     """R-MAT scale 20 (the bench workload): whole run bit-exact vs the
     oracle's synchronous run, 0 disconnected, within 0.005 of async."""
