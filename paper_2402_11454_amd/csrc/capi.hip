@@ -574,7 +574,11 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.sval = ctx->gap_w;
             a.hbuck = ctx->sc.hbuck;
             a.hub_b0 = wl.hub_b0;
-            if (hist) {
+            // the history feeds the gate's features: once a pass has left its
+            // gated sweeps it never returns to them, so later sweeps skip it
+            // (the history's per-entry adds to D_j cost most of it); trace
+            // capture keeps it in every sweep
+            if (hist && (ctx->tracing || mode == GATED)) {
                 a.hfrac = ctx->hfrac;
                 a.hgain = ctx->hgain;
                 a.hbits = ctx->hbits;
