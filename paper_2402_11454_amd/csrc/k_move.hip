@@ -538,11 +538,10 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
         bool mv = decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
-        if (mv)   // entries reloaded: keeping them would cost registers across the scoring
-            for (int e = lane; e < di; e += kWave) {
-                int j = load_col(a.g.col, beg + e);
-                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
-            }
+        if (mv)   // the lane's columns are still in registers (weights reloaded)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (jj[r] != i) mark_neighbour(a, jj[r], a.dmoved ? edge_weight<WT>(a.g.w, beg + lane + r * kWave) : 0.0);
         if (lane == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
@@ -607,11 +606,10 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(Mov
         block_argmax_sum(bg, bc, kid);
         double gain = 0.0;
         bool mv = decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
-        if (mv)
-            for (int e = tid; e < di; e += kBlock) {
-                int j = load_col(a.g.col, beg + e);
-                if (j != i) mark_neighbour(a, j, a.dmoved ? edge_weight<WT>(a.g.w, beg + e) : 0.0);
-            }
+        if (mv)   // the thread's columns are still in registers (weights reloaded)
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (jj[r] != i) mark_neighbour(a, jj[r], a.dmoved ? edge_weight<WT>(a.g.w, beg + tid + r * kBlock) : 0.0);
         if (tid == 0) {
             acc.verts++;
             acc.scanned += (unsigned long long)di;
