@@ -78,6 +78,11 @@ typedef struct gsp_options {
                                       partitions, global tables only for hubs that do not fit them) */
     int32_t hub_max_parts;         /* hubs with more chunks of 2048 entries than this go through their
                                       global table (0 = the limit, 4096; values in [0, 4096]) */
+    int32_t return_moves;          /* 0 (default): every mover's gain counts towards the iteration's total,
+                                      the tolerance test of Algorithm louvainMove as written; 1: a move back
+                                      into the community the vertex left at its move of the preceding sweep
+                                      is made but adds nothing, so swap cycles of synchronous moves do not
+                                      hold a pass at max_iterations */
 } gsp_options;
 
 /* Vertex pruning of the local-moving phase (prune_mode). */

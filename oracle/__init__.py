@@ -46,7 +46,7 @@ class _Options(ctypes.Structure):
                 ("aggregation_tolerance", ctypes.c_double), ("sync_moves", ctypes.c_int32),
                 ("sync_rounds", ctypes.c_int32), ("split_mode", ctypes.c_int32),
                 ("prune_params", ctypes.c_void_p), ("prune_theta_logit", ctypes.c_double),
-                ("trace", ctypes.POINTER(_Trace))]
+                ("trace", ctypes.POINTER(_Trace)), ("return_moves", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -69,7 +69,7 @@ def _load():
         "orc_delta_modularity": (dbl, [i64, vp, vp, vp, vp, i64, i32]),
         "orc_move_async": (i32, [i64, vp, vp, vp, dbl, vp, vp, vp, dbl, i32, vp]),
         "orc_move_sync_step": (i64, [i64, vp, vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]),
-        "orc_move_sync": (i32, [i64, vp, vp, vp, dbl, vp, vp, dbl, i32, i32, vp, vp]),
+        "orc_move_sync": (i32, [i64, vp, vp, vp, dbl, vp, vp, dbl, i32, i32, vp, vp, i32]),
         "orc_split_bfs": (i32, [i64, vp, vp, vp, vp]),
         "orc_split_lp": (i32, [i64, vp, vp, vp, i32, vp]),
         "orc_renumber": (i64, [i64, vp, vp]),
@@ -88,7 +88,7 @@ def _load():
         "orc_mlp_train_adam": (i64, [vp, vp, vp, i64, i64, i32, dbl, dbl, vp]),
         "orc_trace_keep": (i32, [ctypes.c_uint64, i32, i32, i64, ctypes.c_uint64]),
         "orc_move_sync_gated": (i32, [i64, vp, vp, vp, dbl, vp, vp, dbl, i32, i32, vp, dbl, i32,
-                                      ctypes.POINTER(_Trace), vp, vp, vp]),
+                                      ctypes.POINTER(_Trace), vp, vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -184,14 +184,15 @@ def move_sync_step(g, memb, active=None, K=None, M2=None):
     return dec, gain, int(moved)
 
 
-def move_sync(g, memb=None, tau: float = 0.0, max_iter: int = 20, rounds: int = 8):
-    """Returns (membership, l_i, per-iteration dQ, per-iteration movers)."""
+def move_sync(g, memb=None, tau: float = 0.0, max_iter: int = 20, rounds: int = 8, returns: bool = False):
+    """Returns (membership, l_i, per-iteration dQ, per-iteration movers);
+    returns=True leaves return moves out of the gain totals."""
     g = CSR.of(g)
     K, M2 = vertex_weights(g)
     m = np.arange(g.n, dtype=np.int32) if memb is None else _memb(memb, g.n).copy()
     dq = np.zeros(max(max_iter, 1), dtype=np.float64)
     mv = np.zeros(max(max_iter, 1), dtype=np.int64)
-    li = _load().orc_move_sync(*g.args(), M2, _p(K), _p(m), tau, max_iter, rounds, _p(dq), _p(mv))
+    li = _load().orc_move_sync(*g.args(), M2, _p(K), _p(m), tau, max_iter, rounds, _p(dq), _p(mv), int(returns))
     if li < 0:
         raise ValueError("orc_move_sync failed")
     return m, li, dq[:li], mv[:li]
@@ -376,7 +377,8 @@ class Trace:
 
 
 def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, memb=None, tau: float = 0.0,
-                    max_iter: int = 20, rounds: int = 8, trace: Optional[Trace] = None, theta_logit=None):
+                    max_iter: int = 20, rounds: int = 8, trace: Optional[Trace] = None, theta_logit=None,
+                    returns: bool = False):
     """Returns (membership, l_i, dQ per counted iteration, movers per counted
     iteration, counters dict)."""
     g = CSR.of(g)
@@ -388,7 +390,8 @@ def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, mem
     p = _params(params)
     tl = theta_logit if theta_logit is not None else logit_of(theta)
     li = _load().orc_move_sync_gated(*g.args(), M2, _p(K), _p(m), tau, max_iter, rounds, _p(p), tl, pass_index,
-                                     ctypes.byref(trace.c) if trace is not None else None, _p(dq), _p(mv), _p(c4))
+                                     ctypes.byref(trace.c) if trace is not None else None, _p(dq), _p(mv), _p(c4),
+                                     int(returns))
     if li < 0:
         raise ValueError("orc_move_sync_gated failed")
     cnt = dict(scanned_vertices=int(c4[0]), scanned_entries=int(c4[1]), pruned=int(c4[2]), confirm_sweeps=int(c4[3]))
@@ -398,15 +401,15 @@ def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, mem
 def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: int = 20,
             tolerance_drop: float = 10.0, aggregation_tolerance: float = 0.8,
             sync: bool = False, rounds: int = 8, split_mode: int = 0, prune_params=None, theta: float = 0.5,
-            trace: Optional[Trace] = None, theta_logit=None) -> Result:
+            trace: Optional[Trace] = None, theta_logit=None, return_moves: bool = False) -> Result:
     """The whole method; split_mode 0 = every pass, 1 = after the last, 2 = none.
-    prune_params / trace need sync=True."""
+    prune_params / trace / return_moves need sync=True."""
     g = CSR.of(g)
     p = _params(prune_params)
     tl = theta_logit if theta_logit is not None else logit_of(theta)
     opt = _Options(tolerance, max_passes, max_iterations, tolerance_drop, aggregation_tolerance,
                    int(sync), rounds, split_mode, _p(p), tl,
-                   ctypes.pointer(trace.c) if trace is not None else None)
+                   ctypes.pointer(trace.c) if trace is not None else None, int(return_moves))
     st = _Stats()
     memb = np.empty(g.n, dtype=np.int32)
     passes = _load().orc_louvain(*g.args(), ctypes.byref(opt), _p(memb), ctypes.byref(st))

@@ -342,18 +342,19 @@ static int32_t sub_round_of(int64_t i, int32_t rounds) {
  * every neighbour j != i of a mover marked unprocessed, so a later group sees
  * them in the same iteration and earlier groups in the next one.
  *
- * Return moves.  Moves decided from one snapshot can undo each other (two
- * adjacent vertices of one group each joining the other's community); the
- * next iteration then swaps them back, and so on, each time with positive
- * predicted gains while the modularity does not change.  A move of i back
- * into the community it left at its move in the immediately preceding
- * iteration is made, but its gain is not added to the iteration's total, so
- * the tolerance test sees the gain that such a cycle does not deliver.
- * (The paper's loop moves vertices one at a time, where every reported gain
- * is real.) */
+ * Return moves (returns != 0, an option; by default every mover's gain
+ * counts, the tolerance test as written).  Moves decided from one snapshot
+ * can undo each other (two adjacent vertices of one group each joining the
+ * other's community); the next iteration then swaps them back, and so on,
+ * each time with positive predicted gains while the modularity does not
+ * change.  With the option, a move of i back into the community it left at
+ * its move in the immediately preceding iteration is made, but its gain is
+ * not added to the iteration's total, so the tolerance test sees the gain
+ * that such a cycle does not deliver.  (The paper's loop moves vertices one
+ * at a time, where every reported gain is real.) */
 int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
                       const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
-                      double *dq_iter, int64_t *moved_iter) {
+                      double *dq_iter, int64_t *moved_iter, int32_t returns) {
     if (n < 0 || max_iter < 0 || rounds < 1 || rounds > 64 || (rounds & (rounds - 1)) || !valid_memb(n, memb))
         return -1;
     if (n == 0 || max_iter == 0) return 0;
@@ -392,7 +393,7 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
             moved += orc_move_sync_step(n, off, col, w, M2, K, memb, sigma, csize, active, dec, gain);
             for (int64_t i = 0; i < n; i++) {
                 if (dec[i] == memb[i]) continue;
-                int back = dec[i] == left[i] && left_it[i] == it - 1;   /* a return move */
+                int back = returns && dec[i] == left[i] && left_it[i] == it - 1;   /* a return move */
                 if (!back) gsum += gain[i];
                 left[i] = memb[i];
                 left_it[i] = it;
@@ -641,11 +642,13 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         if (opt->sync_moves && (opt->prune_params || opt->trace)) {
             int64_t c4[4];
             li = orc_move_sync_gated(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds,
-                                     opt->prune_params, opt->prune_theta_logit, lp, opt->trace, NULL, NULL, c4);
+                                     opt->prune_params, opt->prune_theta_logit, lp, opt->trace, NULL, NULL, c4,
+                                     opt->return_moves);
             if (stats)
                 for (int q = 0; q < 4; q++) stats->counters[q] += c4[q];
         } else if (opt->sync_moves)
-            li = orc_move_sync(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds, NULL, NULL);
+            li = orc_move_sync(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds, NULL, NULL,
+                               opt->return_moves);
         else
             li = orc_move_async(gn, goff, gcol, gw, M2, K, cm, sigma, tau, opt->max_iterations, NULL);
         if (opt->split_mode == 0) {                                   /* C' <- split(G', C') */

@@ -67,7 +67,8 @@ int32_t orc_decide_row(int64_t i, int64_t deg, const int32_t *cols, const double
  * counts. */
 int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
                       const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
-                      double *dq_iter, int64_t *moved_iter);
+                      double *dq_iter, int64_t *moved_iter,
+                      int32_t returns);
 
 /* Split of internally-disconnected communities by BFS (Algorithm
  * "splitDisconnectedBfs", one thread, lowest unvisited source):
@@ -146,7 +147,8 @@ typedef struct orc_trace {
 int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
                             const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
                             const float *params, double theta_logit, int32_t pass, orc_trace *trace,
-                            double *dq_iter, int64_t *moved_iter, int64_t *counters);
+                            double *dq_iter, int64_t *moved_iter, int64_t *counters,
+                            int32_t returns);
 
 typedef struct orc_options {
     double tolerance;              /* tau for the first pass */
@@ -160,6 +162,7 @@ typedef struct orc_options {
     const float *prune_params;     /* learned gate (sync_moves = 1 only), NULL = plain */
     double prune_theta_logit;      /* scan iff logit >= this */
     orc_trace *trace;              /* move traces (sync_moves = 1 only), may be NULL */
+    int32_t return_moves;          /* sync_moves = 1: return moves add nothing to the gain total (option) */
 } orc_options;
 
 typedef struct orc_stats {

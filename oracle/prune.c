@@ -381,9 +381,9 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * applied every entry (i, j), j != i, of a mover i adds w_ij to D_j.  All
  * start at 0 in the phase.
  *
- * Return moves (as in orc_move_sync, by sweep index): a move of i back into
- * the community it left at its move in the preceding sweep is made, but its
- * gain is not added to the sweep's total.
+ * Return moves (returns != 0, as in orc_move_sync, by sweep index): a move
+ * of i back into the community it left at its move in the preceding sweep
+ * is made, but its gain is not added to the sweep's total.
  *
  * Traces (trace != NULL): every scan kept by orc_trace_keep(seed, pass,
  * sweep, i) appends (features before the scan, moved) to the trace; sweep
@@ -394,7 +394,7 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
 int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
                             const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
                             const float *params, double theta_logit, int32_t pass, orc_trace *trace,
-                            double *dq_iter, int64_t *moved_iter, int64_t *counters) {
+                            double *dq_iter, int64_t *moved_iter, int64_t *counters, int32_t returns) {
     if (n < 0 || max_iter < 0 || rounds < 1 || rounds > 64 || (rounds & (rounds - 1))) return -1;
     for (int64_t i = 0; i < n; i++)
         if (memb[i] < 0 || memb[i] >= n) return -1;
@@ -498,7 +498,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
             }
             for (int64_t i = 0; i < n; i++) {
                 if (dec[i] == memb[i]) continue;
-                if (!(dec[i] == left[i] && left_sw[i] == sweep - 1)) gsum += gain[i];   /* not a return move */
+                if (!(returns && dec[i] == left[i] && left_sw[i] == sweep - 1)) gsum += gain[i];   /* not a return move */
                 left[i] = memb[i];
                 left_sw[i] = sweep;
                 for (int64_t e = off[i]; e < off[i + 1]; e++)

@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("mem_limit_bytes", ctypes.c_uint64), ("prune_mode", ctypes.c_int32),
                 ("prune_threshold", ctypes.c_float), ("use_graphs", ctypes.c_int32),
                 ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32),
-                ("hub_max_parts", ctypes.c_int32)]
+                ("hub_max_parts", ctypes.c_int32), ("return_moves", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -296,8 +296,13 @@ class Context:
         self._check(lib().gsp_step_move(self._h, p, pa, w, pd, pg, ctypes.byref(moved)), "gsp_step_move")
         return dec, gain, moved.value
 
-    def move_phase(self, membership=None, tolerance: float = 0.0, max_iterations: int = 20, sub_rounds: int = 8):
-        """The local-moving phase; returns (membership, l_i, dq per iteration, movers per iteration)."""
+    def move_phase(self, membership=None, tolerance: float = 0.0, max_iterations: int = 20, sub_rounds: int = 8,
+                   return_moves: int = 0):
+        """The local-moving phase; returns (membership, l_i, dq per iteration, movers per iteration).
+        return_moves = 1 goes through gsp_move_phase_ex with that option."""
+        if return_moves:
+            return self.move_phase_ex(membership, tolerance, max_iterations=max_iterations, sub_rounds=sub_rounds,
+                                      return_moves=return_moves)[:4]
         m = np.arange(self.n, dtype=np.int32) if membership is None else np.array(membership, dtype=np.int32)
         li = ctypes.c_int32()
         dq = np.zeros(max(max_iterations, 1), dtype=np.float64)

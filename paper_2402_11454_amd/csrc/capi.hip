@@ -405,6 +405,7 @@ struct PhaseCfg {
     int max_iter = 20;
     bool timing_k = false;
     bool timing_side = false;   // timed scans stay side by side (timing = 3)
+    bool return_moves = false;  // return moves add nothing to the gain totals
     bool gated = false;            // learned gate in front of the scan
     bool use_graphs = false;       // replay plain sweeps from a captured graph
     float theta_logit = 0.0f;      // scan iff logit >= theta_logit
@@ -499,7 +500,8 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     if (!ctx->mhist || !ctx->iter_dev) return ctx->fail(GSP_ESTATE, "level buffers are not allocated");
     launch_fill_u8(ctx->flag, 1, g.n, s);
     // no vertex has moved: community -1, sweep -2
-    launch_fill_u64(reinterpret_cast<unsigned long long *>(ctx->mhist), 0xFFFFFFFFFFFFFFFEull, g.n, s);
+    if (cfg.return_moves)
+        launch_fill_u64(reinterpret_cast<unsigned long long *>(ctx->mhist), 0xFFFFFFFFFFFFFFFEull, g.n, s);
     int li = 0;
     const bool batch = g.gid != nullptr;
     const int64_t G = batch ? g.graphs : 0;
@@ -591,8 +593,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 if (ctx->tracing) a.tr = ctx->trace;
             }
             if (mode == GATED) a.cand = ctx->cand;
-            a.mhist = ctx->mhist;
-            a.sweep_dev = ctx->iter_dev + 1;
+            if (cfg.return_moves) {
+                a.mhist = ctx->mhist;
+                a.sweep_dev = ctx->iter_dev + 1;
+            }
             if (batch) {
                 a.ggain = ctx->ggain;
                 a.gmoved = ctx->gmoved;
@@ -691,6 +695,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         // the gate's inputs: its network, the pass (a feature) and theta
         int32_t thbits;
         memcpy(&thbits, &cfg.theta_logit, sizeof(thbits));
+        key.push_back((int64_t)cfg.return_moves);   // the kernels' move records (or none)
         key.insert(key.end(), {(int64_t)hist, (int64_t)cfg.pass, (int64_t)thbits, ptr(net.w1), ptr(net.w2),
                                ptr(net.b1), ptr(ctx->hbits)});
     }
@@ -1021,6 +1026,7 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
     if (opt.prune_mode != GSP_PRUNE_PLAIN && opt.prune_mode != GSP_PRUNE_LEARNED)
         return ctx->fail(GSP_EINVAL, "bad prune_mode");
     if (opt.timing < 0 || opt.timing > 3) return ctx->fail(GSP_EINVAL, "timing must lie in [0, 3]");
+    if (opt.return_moves != 0 && opt.return_moves != 1) return ctx->fail(GSP_EINVAL, "return_moves must be 0 or 1");
     if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
         return ctx->fail(GSP_EINVAL, "hub_max_parts must lie in [0, 4096]");
     if (opt.prune_mode == GSP_PRUNE_LEARNED) {
@@ -1055,6 +1061,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->timing_mask = 0;
     out->hub_global = 0;
     out->hub_max_parts = 0;
+    out->return_moves = 0;
     return GSP_OK;
 }
 
@@ -1206,6 +1213,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         pc.max_iter = opt.max_iterations;
         pc.timing_k = tk;
         pc.timing_side = opt.timing == 3;
+        pc.return_moves = opt.return_moves != 0;
         pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
         pc.theta_logit = theta_logit(opt.prune_threshold);
         pc.pass = lp;
@@ -1698,6 +1706,7 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
     std::vector<int64_t> mv(mi > 0 ? mi : 1);
     PhaseCfg pc;
     pc.tau = tolerance;
+    pc.return_moves = opt.return_moves != 0;
     pc.max_iter = mi;
     pc.gated = opt.prune_mode == GSP_PRUNE_LEARNED;
     pc.theta_logit = theta_logit(opt.prune_threshold);

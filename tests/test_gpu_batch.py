@@ -65,7 +65,7 @@ def _check_batch(ctx, gs, **kw):
     ctx.run_batch(1e-2, 10, **kw)
     q = ctx.batch_modularity()
     passes = ctx.batch_passes()
-    split = {"split_mode": kw.get("split_mode", 0)}
+    split = {"split_mode": kw.get("split_mode", 0), "return_moves": bool(kw.get("return_moves", 0))}
     for k, g in enumerate(gs):
         m = ctx.batch_membership(k)
         ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, **split)
@@ -96,6 +96,12 @@ def _hub_batch():
 
 def test_batch_with_hubs(ctx):
     _check_batch(ctx, _hub_batch())
+
+
+def test_batch_return_moves(ctx):
+    """The return-move option in a batch (each graph's own move records and
+    gain totals) against the oracle's run of each graph with the option."""
+    _check_batch(ctx, _mixed_batch() + _hub_batch()[:2], return_moves=1)
 
 
 def test_learned_batch_with_hubs_equals_single_runs(ctx):

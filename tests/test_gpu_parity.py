@@ -152,12 +152,14 @@ def test_step_move_bit_exact(ctx, name):
 
 @pytest.mark.parametrize("name", ALL)
 @pytest.mark.parametrize("rounds", [1, 8])
-def test_move_phase_bit_exact(ctx, name, rounds):
+@pytest.mark.parametrize("returns", [0, 1])
+def test_move_phase_bit_exact(ctx, name, rounds, returns):
     g = _graph(name)
     _load(ctx, g)
     for tol in (0.0, 1e-2):
-        m, li, dq, mv = ctx.move_phase(None, tolerance=tol, max_iterations=20, sub_rounds=rounds)
-        rm, rli, rdq, rmv = oracle.move_sync(g, None, tau=tol, max_iter=20, rounds=rounds)
+        m, li, dq, mv = ctx.move_phase(None, tolerance=tol, max_iterations=20, sub_rounds=rounds,
+                                       return_moves=returns)
+        rm, rli, rdq, rmv = oracle.move_sync(g, None, tau=tol, max_iter=20, rounds=rounds, returns=bool(returns))
         np.testing.assert_array_equal(m, rm)
         assert li == rli
         np.testing.assert_array_equal(mv, rmv)
@@ -171,14 +173,19 @@ def test_move_phase_bit_exact(ctx, name, rounds):
 
 def test_swap_cycle_return_moves(ctx):
     """One group of six vertices whose two communities trade labels back
-    and forth from the second iteration on: the phase stops at the first
-    iteration made only of return moves (its gain total 0), as the oracle's
-    does, instead of running to max_iterations."""
+    and forth from the second iteration on: as written the phase runs to
+    max_iterations; with return_moves = 1 it stops at the first iteration
+    made only of return moves (its gain total 0).  Both as the oracle's."""
     g = gi.from_edges(6, [(0, 1), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4), (1, 5), (2, 3), (2, 4), (3, 4), (3, 5),
                           (4, 5)])
     _load(ctx, g)
     m, li, dq, mv = ctx.move_phase(None, tolerance=0.0, max_iterations=12, sub_rounds=1)
     rm, rli, rdq, rmv = oracle.move_sync(g, None, tau=0.0, max_iter=12, rounds=1)
+    assert li == rli == 12
+    np.testing.assert_array_equal(m, rm)
+    np.testing.assert_array_equal(dq, rdq)
+    m, li, dq, mv = ctx.move_phase(None, tolerance=0.0, max_iterations=12, sub_rounds=1, return_moves=1)
+    rm, rli, rdq, rmv = oracle.move_sync(g, None, tau=0.0, max_iter=12, rounds=1, returns=True)
     assert li == rli == 4 and dq[3] == 0.0 and mv[3] > 0
     np.testing.assert_array_equal(m, rm)
     np.testing.assert_array_equal(dq, rdq)
@@ -221,8 +228,9 @@ def _random_graph(seed):
 def test_random_graphs_match_oracle(ctx, seed):
     g = _random_graph(seed)
     _load(ctx, g)
-    res = ctx.louvain(tolerance=1e-2, max_passes=10)
-    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+    returns = seed % 3 == 2   # a third of them with the return-move option
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, return_moves=int(returns))
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, return_moves=returns)
     np.testing.assert_array_equal(res.membership, ref.membership)
     assert res.stats["iterations"] == ref.iterations
     assert res.stats["communities"] == ref.communities

@@ -145,11 +145,11 @@ def test_sync_step_matches_bruteforce(seed, loops):
         np.testing.assert_array_equal(ggain, [float(x) for x in gains])
 
 
-def _sync_replay(g, tau, max_iter, rounds, trail=None):
-    """The synchronous phase in exact arithmetic.  A move back into the
-    community the vertex left at its move of the previous iteration does not
-    add its gain to the iteration's total.  `trail` collects each iteration's
-    membership and its actual modularity change."""
+def _sync_replay(g, tau, max_iter, rounds, trail=None, returns=False):
+    """The synchronous phase in exact arithmetic.  With `returns`, a move back
+    into the community the vertex left at its move of the previous iteration
+    does not add its gain to the iteration's total.  `trail` collects each
+    iteration's membership and its actual modularity change."""
     A = dense(g)
     n = g.n
     M2 = sum(sum(r) for r in A)
@@ -168,7 +168,7 @@ def _sync_replay(g, tau, max_iter, rounds, trail=None):
             dec, gains = _sync_decide(g, A, memb, active)
             for i in range(n):
                 if dec[i] != memb[i]:
-                    if last.get(i) != (dec[i], it - 1):
+                    if not (returns and last.get(i) == (dec[i], it - 1)):
                         gs += gains[i]
                     last[i] = (memb[i], it)
                     for j in g.cols[g.offsets[i]:g.offsets[i + 1]]:
@@ -187,27 +187,32 @@ def _sync_replay(g, tau, max_iter, rounds, trail=None):
 
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("rounds", [1, 2, 8])
-def test_sync_phase_matches_replay(seed, rounds):
+@pytest.mark.parametrize("returns", [False, True])
+def test_sync_phase_matches_replay(seed, rounds, returns):
     g = _small(300 + seed, n=11, loops=bool(seed % 2))
-    memb, li, dqs = _sync_replay(g, 0.0, 12, rounds)
-    got, gli, gdq, _ = oracle.move_sync(g, tau=0.0, max_iter=12, rounds=rounds)
+    memb, li, dqs = _sync_replay(g, 0.0, 12, rounds, returns=returns)
+    got, gli, gdq, _ = oracle.move_sync(g, tau=0.0, max_iter=12, rounds=rounds, returns=returns)
     assert list(got) == memb
     assert gli == li
     np.testing.assert_allclose(gdq, [float(x) for x in dqs], atol=1e-13)
 
 
-def test_swap_cycle_stops_at_the_first_all_return_iteration():
+def test_swap_cycle_and_return_moves():
     """Six vertices, one group: from iteration 2 on the two communities
     trade their labels back and forth (every other membership repeats, the
-    actual modularity does not change), which without the return rule would
-    run to max_iter with a positive predicted total each time.  The phase
-    stops at the first iteration whose moves all return (its total is 0), as
-    the exact replay does."""
+    actual modularity does not change).  As written, the tolerance test sees
+    a positive predicted total each time and the phase runs to max_iter;
+    with the return-move option it stops at the first iteration whose moves
+    all return (its total is 0).  Both as the exact replay does."""
     g = gi.from_edges(6, [(0, 1), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4), (1, 5), (2, 3), (2, 4), (3, 4), (3, 5),
                           (4, 5)])
-    trail = []
-    memb, li, dqs = _sync_replay(g, 0.0, 12, 1, trail)
+    m0, li0, dq0 = _sync_replay(g, 0.0, 12, 1)
     got, gli, gdq, gmv = oracle.move_sync(g, tau=0.0, max_iter=12, rounds=1)
+    assert list(got) == m0 and gli == li0 == 12 and min(gdq) > 0
+    np.testing.assert_allclose(gdq, [float(x) for x in dq0], atol=1e-13)
+    trail = []
+    memb, li, dqs = _sync_replay(g, 0.0, 12, 1, trail, returns=True)
+    got, gli, gdq, gmv = oracle.move_sync(g, tau=0.0, max_iter=12, rounds=1, returns=True)
     assert list(got) == memb and gli == li == 4
     assert gdq[li - 1] == 0.0 and gmv[li - 1] > 0
     np.testing.assert_allclose(gdq, [float(x) for x in dqs], atol=1e-13)
