@@ -66,9 +66,26 @@ def parse():
     return p.parse_args()
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and blank lines (comments do not
+    change the compiled code)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = []
+    for line in text.splitlines():
+        # a // inside a string literal is no comment: mask literals, same length
+        q = re.sub(r'"(\\.|[^"\\])*"', lambda m: '"' + "x" * (len(m.group(0)) - 2) + '"', line)
+        cut = q.find("//")
+        line = line[:cut] if cut >= 0 else line
+        if line.strip():
+            lines.append(line.rstrip())
+    return "\n".join(lines)
+
+
 def kernel_source_hash(kernel):
-    """Hash of what decides a kernel's memory traffic: the source file that
-    defines it, the shared headers and the host code that launches it."""
+    """Hash of what decides a kernel's memory traffic: the code (comments
+    left out) of the source file that defines it, the shared headers and
+    the host code that launches it."""
     import re
     csrc = os.path.join(ROOT, "paper_2402_11454_amd", "csrc")
     names = sorted(os.listdir(csrc))
@@ -77,8 +94,8 @@ def kernel_source_hash(kernel):
     files += [f for f in names if f.endswith(".h")] + ["capi.hip"]
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(f.encode() + b"\0" + _code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

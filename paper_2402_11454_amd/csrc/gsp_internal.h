@@ -148,9 +148,9 @@ struct MoveArgs {
     int32_t *cand = nullptr;                    // gated sweep: candidates (the gate fills `queue`)
     int pass = 0, sweep = 0, iter = 0;          // feature and trace context
     const int64_t *iter_dev = nullptr;          // iter from device memory (sweeps replayed from a graph)
-    // return moves: per vertex, the community it left at its last move (high
-    // 32 bits) and that move's sweep (low 32 bits); the sweep index comes
-    // from device memory.  mhist == nullptr: every gain counts.
+    // return-move option: per vertex, the community it left at its last
+    // move (high 32 bits) and that move's sweep (low 32 bits); the sweep
+    // index comes from device memory.  mhist == nullptr: every gain counts.
     int64_t *mhist = nullptr;
     const int64_t *sweep_dev = nullptr;
     // batches: per graph, whether the gate applies in this sweep (a graph in

@@ -75,9 +75,11 @@ __device__ __forceinline__ void graph_totals(const MoveArgs &a, int i, double ga
 }
 
 // The part of a mover's gain (i: d -> bc) that counts towards the sweep's
-// total.  A move back into the community i left at its move of the
-// preceding sweep undoes a swap made from one snapshot, and its gain is not
-// counted (the move is still made).  Records this move.  One lane per mover.
+// total: all of it, unless the return-move option gives move records
+// (mhist).  Then a move back into the community i left at its move of the
+// preceding sweep, which undoes a swap made from one snapshot, counts
+// nothing (the move is still made), and this move is recorded.  One lane
+// per mover.
 __device__ __forceinline__ double counted_gain(const MoveArgs &a, int i, int d, int bc, double gain) {
     if (!a.mhist) return gain;
     const int32_t sw = (int32_t)*a.sweep_dev;
