@@ -236,19 +236,21 @@ def test_gate_rejecting_everything_equals_plain(ctx):
     assert cnt["pruned"] == int(np.count_nonzero(np.diff(g.offsets))) and cnt["confirm_sweeps"] == 1
 
 
-def test_gated_run_matches_oracle(ctx):
+@pytest.mark.parametrize("returns", [0, 1])
+def test_gated_run_matches_oracle(ctx, returns):
     g = gi.dcsbm_small(8000, 9)
     p = _params(61, 0.5, sharp=64.0)
 
     def run(tl):
-        r = oracle.louvain(g, sync=True, prune_params=p, theta_logit=tl)
+        r = oracle.louvain(g, sync=True, prune_params=p, theta_logit=tl, return_moves=bool(returns))
         return (r.membership.tobytes(), tuple(r.iterations), tuple(r.counters.values()))
 
     th = _stable_theta(g, p, [0.5, 0.55, 0.45, 0.6, 0.4], run)
-    ref = oracle.louvain(g, sync=True, prune_params=p, theta=th)
+    ref = oracle.louvain(g, sync=True, prune_params=p, theta=th, return_moves=bool(returns))
     _load(ctx, g)
     ctx.pruner_set(p)
-    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th,
+                      return_moves=returns)
     assert np.array_equal(res.membership, ref.membership)
     assert res.stats["iterations"] == ref.iterations
     assert res.stats["pruned"] == ref.counters["pruned"]

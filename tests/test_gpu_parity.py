@@ -282,6 +282,8 @@ def test_edge_cases(ctx):
 
 
 def test_error_paths(ctx):
+    with pytest.raises(gsp.GspError):
+        ctx.run(return_moves=2)                         # an option of 0 or 1
     with pytest.raises(gsp.GspError) as e:
         ctx.load(np.array([0, 2, 1], np.int64), np.array([1, 0], np.int32))
     assert e.value.status == gsp.GSP_EGRAPH
