@@ -52,7 +52,8 @@ class _Options(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("iterations", ctypes.c_int32 * 64),
                 ("communities", ctypes.c_int64 * 64), ("vertices", ctypes.c_int64 * 64),
-                ("modularity", ctypes.c_double), ("counters", ctypes.c_int64 * 4)]
+                ("modularity", ctypes.c_double), ("counters", ctypes.c_int64 * 4),
+                ("tau", ctypes.c_double * 64)]
 
 
 def _load():
@@ -77,6 +78,8 @@ def _load():
         "orc_disconnected": (i64, [i64, vp, vp, vp, vp]),
         "orc_louvain": (i32, [i64, vp, vp, vp, ctypes.POINTER(_Options), vp, ctypes.POINTER(_Stats)]),
         "orc_decide_row": (i32, [i64, i64, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]),
+        "orc_weight_grid": (i32, [i64, vp, vp]),
+        "orc_gain_fixed": (i64, [dbl, dbl]),
         "orc_bf16": (ctypes.c_float, [ctypes.c_float]),
         "orc_plog2": (dbl, [dbl]),
         "orc_gate_features": (None, [i64, dbl, dbl, ctypes.c_float, ctypes.c_float, ctypes.c_uint8, dbl, i32, i32,
@@ -117,9 +120,16 @@ class CSR:
 
     @classmethod
     def of(cls, g) -> "CSR":
+        """A generator graph in the oracle's types, its weights taken on the
+        grid of exact sums (:func:`weight_grid`; a no-op for unit weights and
+        for every workload but the largest)."""
         if isinstance(g, CSR):
             return g
-        return cls(g.n, g.offsets, g.cols, None if g.weights is None else g.weights.astype(np.float64))
+        if g.weights is None:
+            return cls(g.n, g.offsets, g.cols, None)
+        w = g.weights.astype(np.float64)
+        weight_grid(w)
+        return cls(g.n, g.offsets, g.cols, w)
 
     @property
     def nnz(self) -> int:
@@ -133,6 +143,20 @@ def _memb(m, n) -> np.ndarray:
     m = np.ascontiguousarray(m, dtype=np.int32)
     assert m.shape[0] == n
     return m
+
+
+def weight_grid(w: np.ndarray):
+    """Takes fp64 weights (in place) on the grid of multiples of 2^-S that
+    makes every sum of them exact; returns (S, weights that moved)."""
+    assert w.dtype == np.float64 and w.flags.c_contiguous
+    ch = ctypes.c_int64()
+    S = _load().orc_weight_grid(w.shape[0], _p(w), ctypes.byref(ch))
+    return int(S), int(ch.value)
+
+
+def gain_fixed(gain: float, M2: float) -> int:
+    """A mover's share of the iteration's gain total, in units of 2^-61."""
+    return int(_load().orc_gain_fixed(float(gain), float(M2)))
 
 
 def vertex_weights(g):
@@ -420,4 +444,5 @@ def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: in
                float(st.modularity))
     r.counters = dict(scanned_vertices=int(st.counters[0]), scanned_entries=int(st.counters[1]),
                       pruned=int(st.counters[2]), confirm_sweeps=int(st.counters[3]))
+    r.tau = list(st.tau[:k])
     return r

@@ -88,6 +88,65 @@ static int valid_memb(int64_t n, const int32_t *memb) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Exact sums: the weight grid                                          */
+/* ------------------------------------------------------------------ */
+
+/* Number of bits of x (0 for x = 0). */
+static int bit_length(uint64_t x) {
+    int b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+/* Section 5.1.2 stores edge weights in fp32 and computes in fp64.  A sum of
+ * fp32 weights is exact in fp64 only while it stays below 2^53 units of its
+ * finest weight, which the largest graphs pass, and a parallel sum beyond
+ * that depends on its order.  Reading taken: every weight is replaced by the
+ * nearest multiple of 2^-S (ties to even), S the largest integer (kept in
+ * [-1000, 1022]) with U 2^S < 2^52, where U >= 2m is an upper bound of the
+ * weight total computed exactly:
+ *   e with wmax < 2^e (wmax the largest weight), b with nnz < 2^b,
+ *   T = 62 - b - e, U_int = sum of max(1, ceil(w 2^T)) over the positive
+ *   weights (an exact integer below 2^63), U = U_int 2^-T <= 2^(len - T)
+ *   with len the bit length of U_int, so S = 52 - len + T.
+ * Then every weight, and every sum or difference of weights the method
+ * takes (K_i, 2m, Sigma_c and its updates, K_{i->c}, super-vertex weights)
+ * is a multiple of 2^-S of magnitude below 2^52 2^-S: exact in fp64, in any
+ * order.  For integer weights, and for fp32 weights of a few units on
+ * graphs below about 2^28 entries, nothing changes.  Returns S (0 for a
+ * graph without a positive weight); *changed (may be NULL) receives the
+ * number of weights that moved. */
+int32_t orc_weight_grid(int64_t nnz, double *w, int64_t *changed) {
+    if (changed) *changed = 0;
+    if (nnz < 0) return -2000;
+    double wmax = 0.0;
+    for (int64_t e = 0; e < nnz; e++)
+        if (w[e] > wmax) wmax = w[e];
+    if (!(wmax > 0.0)) return 0;
+    int ew;
+    frexp(wmax, &ew);                       /* wmax = m 2^ew, 1/2 <= m < 1 */
+    int b = bit_length((uint64_t)nnz);
+    int T = 62 - b - ew;
+    uint64_t U = 0;
+    for (int64_t e = 0; e < nnz; e++) {
+        if (!(w[e] > 0.0)) continue;
+        double t = ceil(ldexp(w[e], T));
+        U += t < 1.0 ? 1u : (uint64_t)t;
+    }
+    int S = 52 - bit_length(U) + T;
+    if (S > 1022) S = 1022;
+    if (S < -1000) S = -1000;
+    int64_t moved = 0;
+    for (int64_t e = 0; e < nnz; e++) {
+        double q = ldexp(nearbyint(ldexp(w[e], S)), -S);
+        if (q != w[e]) moved++;
+        w[e] = q;
+    }
+    if (changed) *changed = moved;
+    return S;
+}
+
+/* ------------------------------------------------------------------ */
 /* Section 3: weights and modularity                                    */
 /* ------------------------------------------------------------------ */
 
@@ -322,6 +381,18 @@ int32_t orc_decide_row(int64_t i, int64_t deg, const int32_t *cols, const double
     return best;
 }
 
+/* A mover's gain in the iteration's total (reading of the tolerance test
+ * of Algorithm "louvainMove" for simultaneous moves): its delta-modularity
+ * 2 (G(c*) - G(stay)) / M2^2 in fixed point, rounded to the nearest
+ * multiple of 2^-61 (ties to even).  The total is the exact integer sum of
+ * these, so it does not depend on the order in which movers are added; a
+ * mover's delta-modularity is at most 2 K_i / M2, so the total of one
+ * iteration stays below 2^62 units. */
+int64_t orc_gain_fixed(double gain, double M2) {
+    if (!(M2 > 0.0)) return 0;
+    return (int64_t)llrint(ldexp((2.0 * gain) / (M2 * M2), 61));
+}
+
 /* Group of a vertex for the ordered sub-rounds of the synchronous phase:
  * the top log2(rounds) bits of the 64-bit product i * 0x9E3779B97F4A7C15
  * (Fibonacci hashing); rounds is a power of two. */
@@ -377,10 +448,9 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
     }
     for (int64_t i = 0; i < n; i++) { left[i] = -1; left_it[i] = -2; }
     memset(unprocessed, 1, (size_t)n);
-    double scale = M2 * M2;
     int32_t li = 0;
     for (int32_t it = 0; it < max_iter; it++) {
-        double gsum = 0.0;
+        int64_t gsum = 0;   /* units of 2^-61 of delta-modularity (orc_gain_fixed) */
         int64_t moved = 0;
         for (int32_t p = 0; p < rounds; p++) {
             /* snapshot: Sigma_c = sum of K_i over c, and the size of c */
@@ -394,7 +464,7 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
             for (int64_t i = 0; i < n; i++) {
                 if (dec[i] == memb[i]) continue;
                 int back = returns && dec[i] == left[i] && left_it[i] == it - 1;   /* a return move */
-                if (!back) gsum += gain[i];
+                if (!back) gsum += orc_gain_fixed(gain[i], M2);
                 left[i] = memb[i];
                 left_it[i] = it;
                 for (int64_t e = off[i]; e < off[i + 1]; e++)
@@ -402,8 +472,7 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
             }
             for (int64_t i = 0; i < n; i++) memb[i] = dec[i];
         }
-        /* dQ = sum of gains / (M2^2 / 2) */
-        double dq = scale > 0.0 ? (2.0 * gsum) / scale : 0.0;
+        double dq = ldexp((double)gsum, -61);
         if (dq_iter) dq_iter[it] = dq;
         if (moved_iter) moved_iter[it] = moved;
         li = it + 1;
@@ -657,6 +726,7 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         }
         int64_t ng = orc_renumber(gn, cm, lab);                       /* |Gamma| */
         if (stats && lp < 64) {
+            stats->tau[lp] = tau;
             stats->iterations[lp] = li;
             stats->communities[lp] = ng;
             stats->vertices[lp] = gn;

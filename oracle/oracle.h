@@ -58,6 +58,15 @@ int32_t orc_decide_row(int64_t i, int64_t deg, const int32_t *cols, const double
                        const double *sigma, const int32_t *csize, double ki, double M2, double *gain,
                        double *scores);
 
+/* Weight grid (exact sums): every weight becomes the nearest multiple of
+ * 2^-S, S the largest integer with (an exact upper bound of 2m) * 2^S <
+ * 2^52; returns S, *changed = weights that moved (may be NULL). */
+int32_t orc_weight_grid(int64_t nnz, double *w, int64_t *changed);
+
+/* A mover's gain numerator as its share of the iteration's gain total:
+ * round(2^61 * 2 gain / M2^2) (the total is the exact sum of these). */
+int64_t orc_gain_fixed(double gain, double M2);
+
 /* Synchronous local-moving phase in `rounds` ordered sub-rounds (a power of
  * two, 1..64): vertex i belongs to sub-round (i * 0x9E3779B97F4A7C15) >> (64 -
  * log2 rounds).  Each sub-round is one snapshot step over the unprocessed
@@ -172,6 +181,7 @@ typedef struct orc_stats {
     int64_t vertices[64];          /* N' of each pass */
     double modularity;
     int64_t counters[4];           /* gated phase: scanned vertices, scanned entries, pruned, confirming sweeps */
+    double tau[64];                /* the iteration tolerance each pass ran with (threshold scaling) */
 } orc_stats;
 
 /* The whole method (Algorithm "louvain").  memb_out[n] gets the top-level

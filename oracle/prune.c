@@ -369,7 +369,12 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * every vertex unprocessed, no gate.  If its delta-modularity is <= tau the
  * phase ends, otherwise it continues with plain iterations (no gate) until
  * the usual test stops it.  Every iteration counts towards l_i and
- * max_iter except a confirming sweep that moves no vertex.
+ * max_iter except a confirming sweep that moves no vertex.  The last
+ * iteration the phase may count (l_i = max_iter - 1) is always a
+ * confirming sweep, so a phase that reaches max_iter in gated mode still
+ * ends with one sweep of the plain method over every vertex.  An
+ * iteration's gain total is the exact sum of the movers' gains in fixed
+ * point (orc_gain_fixed).
  *
  * A vertex with an empty row is never gated, scanned or traced (it cannot
  * move).
@@ -433,11 +438,15 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
     enum { GATED, CONFIRM, PLAIN } mode = params ? GATED : PLAIN;
     int32_t li = 0;
     for (int32_t sweep = 0; li < max_iter; sweep++) {
+        /* the last iteration the phase may count is a confirming sweep: a
+         * phase never ends on gated sweeps alone, so every vertex the gate
+         * kept from its scans is judged by the plain method once more */
+        if (mode == GATED && li + 1 >= max_iter) mode = CONFIRM;
         if (mode == CONFIRM) {
             memset(unproc, 1, N);
             cnt[3]++;
         }
-        double gsum = 0.0;
+        int64_t gsum = 0;   /* units of 2^-61 of delta-modularity (orc_gain_fixed) */
         int64_t moved = 0;
         for (int32_t p = 0; p < rounds; p++) {
             for (int64_t c = 0; c < n; c++) { sigma[c] = 0.0; csize[c] = 0; }
@@ -498,7 +507,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
             }
             for (int64_t i = 0; i < n; i++) {
                 if (dec[i] == memb[i]) continue;
-                if (!(returns && dec[i] == left[i] && left_sw[i] == sweep - 1)) gsum += gain[i];   /* not a return move */
+                if (!(returns && dec[i] == left[i] && left_sw[i] == sweep - 1)) gsum += orc_gain_fixed(gain[i], M2);   /* not a return move */
                 left[i] = memb[i];
                 left_sw[i] = sweep;
                 for (int64_t e = off[i]; e < off[i + 1]; e++)
@@ -509,8 +518,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
             }
             for (int64_t i = 0; i < n; i++) memb[i] = dec[i];
         }
-        double scale = M2 * M2;
-        double dq = scale > 0.0 ? (2.0 * gsum) / scale : 0.0;
+        double dq = ldexp((double)gsum, -61);
         int counted = mode != CONFIRM || moved > 0;
         if (counted) {
             if (dq_iter) dq_iter[li] = dq;

@@ -179,6 +179,55 @@ def test_adam_first_step_is_signed_lr():
     assert np.allclose(p1, want.astype(np.float32), rtol=0, atol=2e-7 + 1e-7 * np.abs(p).max())
 
 
+def _adam_by_hand(b3, batches, pw, lr, epochs):
+    """Adam on the output bias alone, written out: with every weight zero
+    the network's logit is b3 for every row, so the gradient of the mean
+    pos-weighted BCE is [pw P (sigmoid(z) - 1) + N sigmoid(z)] / B for a
+    batch of P positive and N negative rows (the other parameters' gradients
+    are 0 and they never move).  The gradient is taken at b3 rounded to
+    fp32 (the network's storage format).  Returns (b3, per-epoch losses)."""
+    m = v = 0.0
+    t = 0
+    losses = []
+    for _ in range(epochs):
+        ls = []
+        for P, N in batches:
+            z = float(np.float32(b3))
+            s = 1.0 / (1.0 + math.exp(-z))
+            B = P + N
+            g = (pw * P * (s - 1.0) + N * s) / B
+            ls.append((pw * P * math.log1p(math.exp(-z)) + N * math.log1p(math.exp(z))) / B)
+            t += 1
+            m = 0.9 * m + 0.1 * g
+            v = 0.999 * v + 0.001 * g * g
+            b3 -= lr * (m / (1.0 - 0.9 ** t)) / (math.sqrt(v / (1.0 - 0.999 ** t)) + 1e-8)
+        losses.append(sum(ls) / len(ls))
+    return b3, losses
+
+
+@pytest.mark.parametrize("batches,epochs,lr", [([(30, 70)], 3, 0.3), ([(10, 54), (50, 14)], 2, 0.05),
+                                               ([(3, 125)], 5, 1.0)])
+def test_adam_steps_by_hand(batches, epochs, lr):
+    """Several Adam steps (moments, bias correction at every t, t counted
+    over the batches in order) against the update written out by hand."""
+    rows = []
+    for P, N in batches:
+        rows += [1] * P + [0] * N
+    y = np.array(rows, dtype=np.uint8)
+    x = gi.uniform(40, y.shape[0] * 8).reshape(-1, 8).astype(np.float32)
+    p = np.zeros(oracle.MLP_PARAMS, np.float32)
+    p[-1] = 0.25
+    pw = 1.5
+    want, wl = _adam_by_hand(0.25, batches, pw, lr, epochs)
+    got, el = oracle.mlp_train_adam(p, x, y, batch=batches[0][0] + batches[0][1], epochs=epochs, lr=lr,
+                                    pos_weight=pw)
+    assert np.count_nonzero(got[:-1]) == 0
+    assert got[-1] == np.float32(want)
+    np.testing.assert_allclose(el, wl, rtol=1e-12)
+    # a bias correction missing from the later steps would land far away
+    assert abs(want - 0.25) > 10 * abs(float(np.float32(want)) - want)
+
+
 def test_training_learns_a_separable_rule():
     """Labels y = [x0 + x1 > 1]: Adam drives the loss down and the network
     classifies held-out rows."""
