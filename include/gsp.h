@@ -151,6 +151,21 @@ const char *gsp_last_error(const gsp_ctx *ctx);
 gsp_status gsp_load_csr(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
                         const float *weights, int where);
 
+/* Exact sums.  Section 5.1.2 keeps edge weights in fp32 and computes in
+ * fp64; a sum of fp32 weights is exact in fp64 only while it stays below
+ * 2^53 units of its finest weight, and beyond that a parallel sum depends on
+ * its order.  Every load therefore takes the weights onto a grid: each
+ * weight becomes the nearest multiple of 2^-S (ties to even), with S the
+ * largest integer (in [-1000, 1022]) such that an exact upper bound U of the
+ * weight total has U 2^S < 2^52 (U = 2^-T sum of max(1, ceil(w 2^T)) over
+ * the positive weights, T = 62 - bits(nnz) - e, max weight < 2^e).  Every
+ * sum or difference of weights the method forms (K_i, 2m, Sigma_c and its
+ * updates, K_{i->c}, super-vertex weights) is then exact, so results do not
+ * depend on the order of the GPU's atomics.  Unit weights, and fp32
+ * weights of a few units on graphs below about 2^28 entries, do not move;
+ * weights in [1, 10) on 2^31 entries move by at most 2^-19.  A batch takes
+ * one grid per graph (its own total). */
+
 /* Same with int32 offsets (graphs below 2^31 entries). */
 gsp_status gsp_load_csr32(gsp_ctx *ctx, int32_t n, int32_t nnz, const int32_t *offsets, const int32_t *cols,
                           const float *weights, int where);
@@ -177,6 +192,11 @@ gsp_status gsp_get_membership(gsp_ctx *ctx, int32_t *out, int where);
 
 /* Modularity (Eq. 1) of the last run's membership. */
 gsp_status gsp_get_modularity(gsp_ctx *ctx, double *out);
+
+/* The loaded graph's weight grid: weights are multiples of 2^-*scale_exp
+ * (the smallest exponent over a batch's graphs; 0 for unit weights), and
+ * *moved weights were rounded onto it. */
+gsp_status gsp_get_weight_grid(gsp_ctx *ctx, int32_t *scale_exp, int64_t *moved);
 
 /* Statistics of the last run. */
 gsp_status gsp_get_stats(gsp_ctx *ctx, gsp_stats *out);

@@ -120,6 +120,7 @@ def lib():
         "gsp_get_batch_passes": [vp, vp],
         "gsp_capture_traces": [vp, i64, dbl, ctypes.c_uint64],
         "gsp_get_traces": [vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int],
+        "gsp_get_weight_grid": [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -257,6 +258,13 @@ class Context:
         s = Stats()
         self._check(lib().gsp_get_stats(self._h, ctypes.byref(s)), "gsp_get_stats")
         return s.as_dict()
+
+    def weight_grid(self):
+        """(S, moved): the loaded weights are multiples of 2^-S; `moved` of
+        them were rounded onto that grid at load."""
+        S, mv = ctypes.c_int32(), ctypes.c_int64()
+        self._check(lib().gsp_get_weight_grid(self._h, ctypes.byref(S), ctypes.byref(mv)), "gsp_get_weight_grid")
+        return S.value, mv.value
 
     def louvain(self, tolerance: float = 1e-2, max_passes: int = 10, **kw) -> RunResult:
         self.run(tolerance, max_passes, **kw)

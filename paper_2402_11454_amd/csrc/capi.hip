@@ -114,6 +114,10 @@ struct gsp_ctx {
     int32_t *deg0 = nullptr;
     double *K0 = nullptr;
     double M2 = 0.0;
+    // weight grid of the loaded graph (exact sums): weights are multiples of
+    // 2^-grid_S; grid_moved weights were rounded onto it at load
+    int32_t grid_S = 0;
+    int64_t grid_moved = 0;
 
     // super-vertex levels (ping-pong) and the gapped aggregation rows
     int64_t *offL[2] = {nullptr, nullptr};
@@ -158,7 +162,8 @@ struct gsp_ctx {
     std::vector<double> M2g_h;            // 2m of each graph
     int64_t *vbase0 = nullptr, *vbaseL[2] = {nullptr, nullptr}, *cfirst = nullptr;
     int32_t *gid0 = nullptr, *gidL[2] = {nullptr, nullptr};
-    double *M2g = nullptr, *ggain = nullptr, *bq = nullptr, *bqin = nullptr;
+    double *M2g = nullptr, *bq = nullptr, *bqin = nullptr;
+    unsigned long long *ggain = nullptr;   // per graph: the sweep's gain total (units of 2^-61)
     unsigned long long *gmoved = nullptr;
     uint8_t *gactive = nullptr;
     uint8_t *ggated = nullptr, *gconfirm = nullptr;   // learned batches: per graph, this sweep's mode
@@ -246,7 +251,8 @@ struct gsp_ctx {
         vbaseL[0] = vbaseL[1] = nullptr;
         gid0 = nullptr;
         gidL[0] = gidL[1] = nullptr;
-        M2g = ggain = bq = bqin = nullptr;
+        M2g = bq = bqin = nullptr;
+        ggain = nullptr;
         gmoved = nullptr;
         gactive = nullptr;
         ggated = nullptr;
@@ -506,8 +512,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
     const bool batch = g.gid != nullptr;
     const int64_t G = batch ? g.graphs : 0;
     std::vector<uint8_t> act;
-    std::vector<double> gg;
-    std::vector<unsigned long long> gm;
+    std::vector<unsigned long long> gg, gm;
     // batches: each graph runs the single graph's sweep sequence (gated,
     // confirming, plain) on its own; gmode holds its current mode
     std::vector<uint8_t> gmode, ggated_h, gconfirm_h;
@@ -535,7 +540,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         int64_t *launches = ctx->kernel_launches;
         launch_fill_u64(reinterpret_cast<unsigned long long *>(ctr), 0, sizeof(IterCounters) / 8, cs);
         if (batch) {
-            launch_fill_f64(ctx->ggain, 0.0, G, cs);
+            launch_fill_u64(ctx->ggain, 0, G, cs);
             launch_fill_u64(ctx->gmoved, 0, G, cs);
         }
         for (int p = 0; p < P; p++) {
@@ -692,17 +697,22 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         int64_t m2bits;
         memcpy(&m2bits, &ctx->M2, sizeof(m2bits));
         key.push_back(m2bits);
-        // the gate's inputs: its network, the pass (a feature) and theta
-        int32_t thbits;
+        // the gate's inputs: its network (b3 is a kernel argument), the pass
+        // (a feature) and theta; the hub paths the sweep launches
+        int32_t thbits, b3bits;
         memcpy(&thbits, &cfg.theta_logit, sizeof(thbits));
+        memcpy(&b3bits, &net.b3, sizeof(b3bits));
         key.push_back((int64_t)cfg.return_moves);   // the kernels' move records (or none)
-        key.insert(key.end(), {(int64_t)hist, (int64_t)cfg.pass, (int64_t)thbits, ptr(net.w1), ptr(net.w2),
-                               ptr(net.b1), ptr(ctx->hbits)});
+        key.insert(key.end(), {(int64_t)hist, (int64_t)cfg.pass, (int64_t)thbits, (int64_t)b3bits, ptr(net.w1),
+                               ptr(net.w2), ptr(net.b1), ptr(ctx->hbits), (int64_t)ctx->hub_parts,
+                               (int64_t)ctx->hub_max_parts});
     }
     for (int sweep = 0;; sweep++) {
         if (batch) {
             bool any = false, any_gated = false, any_confirm = false;
             for (int64_t k = 0; k < G; k++) {
+                // a graph's last countable iteration is a confirming sweep
+                if (act[k] && gmode[k] == GATED && cfg.li_g[k] + 1 >= cfg.max_iter) gmode[k] = CONFIRM;
                 any = any || act[k] != 0;
                 ggated_h[k] = act[k] && gmode[k] == GATED;
                 gconfirm_h[k] = act[k] && gmode[k] == CONFIRM;
@@ -725,6 +735,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             mode = any_gated ? GATED : PLAIN;
         } else if (li >= cfg.max_iter) {
             break;
+        } else if (mode == GATED && li + 1 >= cfg.max_iter) {
+            // the last iteration the phase may count is a confirming sweep:
+            // a phase never ends on gated sweeps alone
+            mode = CONFIRM;
         }
         cfg.sweeps++;
         if (!batch && mode == CONFIRM) {
@@ -760,7 +774,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(ctx->ctr_h, ctr, sizeof(IterCounters), hipMemcpyDeviceToHost, s));
         if (batch) {
-            HIP_TRY(hipMemcpyAsync(gg.data(), ctx->ggain, G * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(gg.data(), ctx->ggain, G * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipMemcpyAsync(gm.data(), ctx->gmoved, G * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
@@ -768,7 +782,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         memset(&h, 0, sizeof(h));
         for (int q = 0; q < kStripes; q++) {
             const CounterStripe &x = ctx->ctr_h->st[q];
-            h.gain += x.gain;   // exact on integer weights, in any order
+            h.gain += x.gain;   // integer units: exact, in any order
             h.moved += x.moved;
             h.pruned += x.pruned;
             for (int c = 0; c < kMoveClasses; c++) {
@@ -779,7 +793,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
                 h.aux[c] += x.aux[c];
             }
         }
-        double dq = ctx->M2 > 0.0 ? (2.0 * h.gain) / (ctx->M2 * ctx->M2) : 0.0;
+        const double dq = ldexp((double)h.gain, -61);   // the movers' delta-modularity (gain_units)
         ctx->stats.moves += (int64_t)h.moved;
         cfg.pruned += (int64_t)h.pruned;
         for (int c = 0; c < kMoveClasses; c++) {
@@ -799,11 +813,10 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             ctx->stats.kernels[GSP_K_GATE].items += nc;
         }
         if (batch) {
-            // each graph's own convergence test (its gain total over its 2m^2)
+            // each graph's own convergence test (its movers' delta-modularity)
             for (int64_t k = 0; k < G; k++) {
                 if (!act[k]) continue;
-                double m2 = ctx->M2g_h[k];
-                double dqk = m2 > 0.0 ? (2.0 * gg[k]) / (m2 * m2) : 0.0;
+                const double dqk = ldexp((double)gg[k], -61);
                 if (gmode[k] != CONFIRM || gm[k] > 0) cfg.li_g[k]++;   // as counted for one graph
                 if (dqk <= cfg.tau) {
                     if (gmode[k] == GATED)
@@ -868,9 +881,50 @@ gsp_status ensure_levels(gsp_ctx *ctx) {
     return GSP_OK;
 }
 
+int bit_length(uint64_t x) {
+    int b = 0;
+    while (x) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+// The grid of exact sums for weights w[0..nnz) (host copy, fp32): returns S
+// with every weight rounded to the nearest multiple of 2^-S (ties to even)
+// in place, *moved = weights that changed.  Same rule as the device kernels
+// (launch_weight_grid): S = 52 - bits(U) + T, U = sum of max(1, ceil(w 2^T))
+// over the positive weights, T = 62 - bits(nnz) - e with max(w) < 2^e.
+int32_t host_weight_grid(float *w, int64_t nnz, int64_t *moved) {
+    *moved = 0;
+    double wmax = 0.0;
+    for (int64_t e = 0; e < nnz; e++) wmax = std::max(wmax, (double)w[e]);
+    if (!(wmax > 0.0)) return 0;
+    int ew = 0;
+    (void)std::frexp(wmax, &ew);
+    const int T = 62 - bit_length((uint64_t)nnz) - ew;
+    uint64_t U = 0;
+    for (int64_t e = 0; e < nnz; e++) {
+        if (!(w[e] > 0.0f)) continue;
+        const double t = std::ceil(std::ldexp((double)w[e], T));
+        U += t < 1.0 ? 1u : (uint64_t)t;
+    }
+    const int S = std::min(1022, std::max(-1000, 52 - bit_length(U) + T));
+    for (int64_t e = 0; e < nnz; e++) {
+        const double q = std::ldexp(std::nearbyint(std::ldexp((double)w[e], S)), -S);
+        if (q != (double)w[e]) {
+            w[e] = (float)q;
+            (*moved)++;
+        }
+    }
+    return S;
+}
+
 // Loads a CSR given as int64 offsets (off64) or int32 offsets (off32).
+// grid = false when the caller has taken the weights onto their grids
+// already (a batch: one grid per graph).
 gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64, const int32_t *off32,
-                     const int32_t *cols, const void *weights, int wt, int where) {
+                     const int32_t *cols, const void *weights, int wt, int where, bool grid = true) {
     if (n < 0 || nnz < 0) return ctx->fail(GSP_EINVAL, "negative size");
     if (n > 0x7fffffffLL - 1) return ctx->fail(GSP_EINVAL, "n must be below 2^31 - 1 (int32 vertex ids)");
     if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
@@ -977,6 +1031,33 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     ctx->nnz = nnz;
     ctx->wt0 = wt;
     launch_degrees(ctx->off0, ctx->deg0, n, s);
+    // the weight grid (exact sums): the largest weight, the exact bound of
+    // the total, then the rounding (a no-op unless the total needs it)
+    ctx->grid_S = 0;
+    ctx->grid_moved = 0;
+    if (grid && wt != W_UNIT && nnz > 0) {
+        unsigned long long *u = sc.u64;
+        launch_fill_u64(u, 0, 3, s);
+        launch_weight_max(ctx->w0, wt, nnz, u, s);
+        HIP_TRY(hipMemcpyAsync(ctx->i64_h, u, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double wmax = 0.0;
+        memcpy(&wmax, ctx->i64_h, sizeof(double));
+        if (wmax > 0.0) {
+            int ew = 0;
+            (void)std::frexp(wmax, &ew);
+            const int T = 62 - bit_length((uint64_t)nnz) - ew;
+            launch_weight_bound(ctx->w0, wt, nnz, T, u + 1, s);
+            HIP_TRY(hipMemcpyAsync(ctx->i64_h, u + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            const int S = std::min(1022, std::max(-1000, 52 - bit_length((uint64_t)ctx->i64_h[0]) + T));
+            launch_weight_grid(ctx->w0, wt, nnz, S, u + 2, s);
+            HIP_TRY(hipMemcpyAsync(ctx->i64_h, u + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ctx->grid_S = S;
+            ctx->grid_moved = ctx->i64_h[0];
+        }
+    }
     HIP_TRY(hipMemsetAsync(sc.f64, 0, sizeof(double), s));
     Level g = level0(ctx);
     launch_vertex_weights(g, ctx->K0, sc.f64, s);
@@ -1001,14 +1082,16 @@ gsp_status modularity_of(gsp_ctx *ctx, const int32_t *m, double *out) {
         return GSP_OK;
     }
     launch_fill_f64(ctx->sig, 0.0, ctx->n, s);
-    HIP_TRY(hipMemsetAsync(ctx->sc.f64, 0, 2 * sizeof(double), s));
+    launch_fill_f64(ctx->sc.f64, 0.0, 1, s);
+    launch_fill_u64(ctx->sc.u64, 0, 1, s);
     launch_community_totals(ctx->K0, m, ctx->n, ctx->sig, nullptr, s);
     launch_modularity_parts(level0(ctx), m, ctx->K0, ctx->sig, ctx->sc.f64, s);
-    launch_sum_squares(ctx->sig, ctx->n, ctx->M2, ctx->sc.f64 + 1, s);
-    HIP_TRY(hipMemcpyAsync(ctx->f64_h, ctx->sc.f64, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    launch_sum_squares(ctx->sig, ctx->n, ctx->M2, ctx->sc.u64, s);
+    HIP_TRY(hipMemcpyAsync(ctx->f64_h, ctx->sc.f64, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->i64_h, ctx->sc.u64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
-    *out = ctx->f64_h[0] / ctx->M2 - ctx->f64_h[1];
+    *out = ctx->f64_h[0] / ctx->M2 - ldexp((double)(uint64_t)ctx->i64_h[0], -62);
     return GSP_OK;
 }
 
@@ -1192,6 +1275,20 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         g.gid = ctx->gid0;
         g.vbase = ctx->vbase0;
         g.M2g = ctx->M2g;
+    }
+    {
+        // the reset step's vertexWeights of the first pass (Algorithm
+        // louvain) and 2m, inside the run (later passes take K'' from the
+        // aggregation); exact sums, so equal to the load's values
+        int t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
+        launch_fill_f64(ctx->sc.f64, 0.0, 1, s);
+        launch_vertex_weights(g, ctx->K0, ctx->sc.f64, s);
+        if (batch) launch_batch_m2(ctx->K0, ctx->vbase0, G, ctx->M2g, s);
+        HIP_TRY(hipMemcpyAsync(ctx->f64_h, ctx->sc.f64, sizeof(double), hipMemcpyDeviceToHost, s));
+        if (batch) HIP_TRY(hipMemcpyAsync(ctx->M2g_h.data(), ctx->M2g, G * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        ctx->M2 = ctx->f64_h[0];
+        ctx->timer.end(t);
     }
     const double *K = ctx->K0;
     double tau = tolerance;
@@ -1404,6 +1501,8 @@ gsp_status gsp_load_batch(gsp_ctx *ctx, int32_t graphs, const int64_t *n, const 
     std::vector<float> w(any_w ? E : 0);
     std::vector<int64_t> vbase(graphs + 1);
     int64_t vb = 0, eb = 0;
+    int32_t grid_S = 1022;
+    int64_t grid_moved = 0;
     for (int32_t k = 0; k < graphs; k++) {
         vbase[k] = vb;
         for (int64_t v = 0; v < n[k]; v++) off[vb + v] = eb + offsets[k][v];
@@ -1412,16 +1511,24 @@ gsp_status gsp_load_batch(gsp_ctx *ctx, int32_t graphs, const int64_t *n, const 
             if (c < 0 || c >= n[k]) return ctx->fail(GSP_EGRAPH, "a column lies outside its graph");
             col[eb + e] = (int32_t)(vb + c);
         }
-        if (any_w)
+        if (any_w) {
             for (int64_t e = 0; e < nnz[k]; e++) w[eb + e] = weights[k] ? weights[k][e] : 1.0f;
+            // each graph on the grid of its own total: every sum of one graph's
+            // weights is then exact (no sum mixes graphs)
+            int64_t mv = 0;
+            grid_S = std::min(grid_S, host_weight_grid(w.data() + eb, nnz[k], &mv));
+            grid_moved += mv;
+        }
         vb += n[k];
         eb += nnz[k];
     }
     off[N] = E;
     vbase[graphs] = N;
     gsp_status st = load_impl(ctx, N, E, off.data(), nullptr, col.data(), any_w ? (const void *)w.data() : nullptr,
-                              any_w ? W_F32 : W_UNIT, GSP_HOST);
+                              any_w ? W_F32 : W_UNIT, GSP_HOST, false);
     if (st != GSP_OK) return st;
+    ctx->grid_S = any_w ? grid_S : 0;
+    ctx->grid_moved = grid_moved;
     hipError_t e = hipSuccess;
     const int64_t G = graphs;
     ctx->vbase0 = ctx->dalloc<int64_t>(G + 1, &e);
@@ -1432,7 +1539,7 @@ gsp_status gsp_load_batch(gsp_ctx *ctx, int32_t graphs, const int64_t *n, const 
     if (e == hipSuccess) ctx->cfirst = ctx->dalloc<int64_t>(G + 1, &e);
     if (e == hipSuccess) ctx->gid0 = ctx->dalloc<int32_t>(N, &e);
     if (e == hipSuccess) ctx->M2g = ctx->dalloc<double>(G, &e);
-    if (e == hipSuccess) ctx->ggain = ctx->dalloc<double>(G, &e);
+    if (e == hipSuccess) ctx->ggain = ctx->dalloc<unsigned long long>(G, &e);
     if (e == hipSuccess) ctx->bq = ctx->dalloc<double>(G, &e);
     if (e == hipSuccess) ctx->bqin = ctx->dalloc<double>(G, &e);
     if (e == hipSuccess) ctx->gmoved = ctx->dalloc<unsigned long long>(G, &e);
@@ -1547,6 +1654,14 @@ gsp_status gsp_get_modularity(gsp_ctx *ctx, double *out) {
         ctx->have_q = true;
     }
     *out = ctx->q;
+    return GSP_OK;
+}
+
+gsp_status gsp_get_weight_grid(gsp_ctx *ctx, int32_t *scale_exp, int64_t *moved) {
+    if (!ctx || !scale_exp || !moved) return GSP_EINVAL;
+    if (!ctx->loaded) return ctx->fail(GSP_ESTATE, "no graph loaded");
+    *scale_exp = ctx->grid_S;
+    *moved = ctx->grid_moved;
     return GSP_OK;
 }
 
@@ -1784,6 +1899,7 @@ gsp_status gsp_pruner_set(gsp_ctx *ctx, const float *params, int64_t count, int 
     ctx->net_b3 = p[kPB3];
     ctx->net_params = p;
     ctx->have_net = true;
+    ctx->drop_sweep_graphs();   // captured gated sweeps hold the old network's arguments
     return GSP_OK;
 }
 

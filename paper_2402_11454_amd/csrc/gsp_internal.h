@@ -68,7 +68,7 @@ constexpr int kStripes = 16;
 // 4 hub decisions (and the global-table slices), 5 hub partition gather
 constexpr int kMoveClasses = 6;
 struct alignas(128) CounterStripe {
-    double gain;                               // sum of gain numerators G(c*) - G(stay)
+    unsigned long long gain;                   // gain total in units of 2^-61 of delta-modularity (gain_units)
     unsigned long long moved;                  // movers
     unsigned long long verts[kMoveClasses];    // vertices decided
     unsigned long long scanned[kMoveClasses];  // CSR entries scanned
@@ -160,7 +160,7 @@ struct MoveArgs {
     TraceArgs tr;                               // tr.x == nullptr: no capture
     // batch of graphs (g.gid != nullptr): per-graph totals of the sweep and
     // the graphs still iterating
-    double *ggain = nullptr;
+    unsigned long long *ggain = nullptr;        // per graph, units of gain_units
     unsigned long long *gmoved = nullptr;
     const uint8_t *gactive = nullptr;
 };
@@ -189,11 +189,29 @@ void launch_weights_to_f64(const float *in, double *out, int64_t nnz, hipStream_
 // K_i = row sums (one wavefront per row) and *M2 += sum K_i.
 void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s);
 // Modularity parts: *sigma_in += sum of entries inside communities,
-// sig[c] += K_i; then q = sigma_in/M2 - sum_c (sig[c]/M2)^2.
+// sig[c] += K_i; then q = sigma_in/M2 - sum_c (sig[c]/M2)^2, the second sum
+// in units of 2^-62 (*out of launch_sum_squares), exact in any order.
 void launch_modularity_parts(const Level &g, const int32_t *memb, const double *K, double *sig, double *sigma_in,
                              hipStream_t s);
-void launch_sum_squares(const double *sig, int64_t n, double M2, double *out, hipStream_t s);
+void launch_sum_squares(const double *sig, int64_t n, double M2, unsigned long long *out, hipStream_t s);
 void launch_check_labels(const int32_t *memb, int64_t n, int *err, hipStream_t s);
+// Weight grid (exact sums): every weight becomes the nearest multiple of
+// 2^-S with S the largest integer (in [-1000, 1022]) such that an exact
+// upper bound U of the weight total has U 2^S < 2^52; then every sum or
+// difference of weights the method forms is exact in fp64, in any order.
+// The host takes S from the largest weight (*out, as fp64 bits) and the
+// integer bound *U = sum of max(1, ceil(w 2^T)), T = 62 - bits(nnz) - e with
+// wmax < 2^e.
+void launch_weight_max(const void *w, int wt, int64_t nnz, unsigned long long *out, hipStream_t s);
+void launch_weight_bound(const void *w, int wt, int64_t nnz, int T, unsigned long long *U, hipStream_t s);
+void launch_weight_grid(void *w, int wt, int64_t nnz, int S, unsigned long long *moved, hipStream_t s);
+// A mover's share of an iteration's gain total: its delta-modularity
+// 2 (G(c*) - G(stay)) / M2^2 rounded to the nearest multiple of 2^-61; the
+// total is the exact (order-free) integer sum of these.
+__device__ __forceinline__ unsigned long long gain_units(double gain, double m2) {
+    if (!(m2 > 0.0)) return 0ull;
+    return (unsigned long long)(long long)rint(ldexp((2.0 * gain) / (m2 * m2), 61));
+}
 
 // ---- k_bins.hip ----
 // Builds the work lists of a level (all buckets of all sub-rounds).

@@ -29,15 +29,15 @@ namespace {
 constexpr int kIntMax = 0x7fffffff;
 
 struct Acc {          // per-thread counters, reduced per block at the end
-    double gain = 0.0;
+    unsigned long long gain = 0;   // units of 2^-61 of delta-modularity (gain_units)
     unsigned long long moved = 0, verts = 0, scanned = 0, keys = 0, ginserts = 0, aux = 0;
 };
 
 __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
     constexpr int F = 6;
-    __shared__ double sg[kBlock / kWave];
+    __shared__ unsigned long long sg[kBlock / kWave];
     __shared__ unsigned long long sv[F][kBlock / kWave];
-    double g = group_sum<kWave>(acc.gain);
+    const unsigned long long g = (unsigned long long)group_sum_ll<kWave>((long long)acc.gain);
     long long v[F] = {(long long)acc.moved, (long long)acc.verts, (long long)acc.scanned, (long long)acc.keys,
                       (long long)acc.ginserts, (long long)acc.aux};
 #pragma unroll
@@ -50,14 +50,14 @@ __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tg = 0.0;
+        unsigned long long tg = 0;
         unsigned long long t[F] = {0, 0, 0, 0, 0, 0};
         for (int q = 0; q < kBlock / kWave; q++) {
             tg += sg[q];
             for (int f = 0; f < F; f++) t[f] += sv[f][q];
         }
         CounterStripe &st = ctr->st[blockIdx.x % kStripes];
-        if (tg != 0.0) unsafeAtomicAdd(&st.gain, tg);
+        if (tg) atomicAdd(&st.gain, tg);
         if (t[0]) atomicAdd(&st.moved, t[0]);
         if (t[1]) atomicAdd(&st.verts[cls], t[1]);
         if (t[2]) atomicAdd(&st.scanned[cls], t[2]);
@@ -68,25 +68,27 @@ __device__ void flush_acc(const Acc &acc, IterCounters *ctr, int cls) {
 }
 
 // Batch: a mover's gain and count into its graph's totals (one lane).
-__device__ __forceinline__ void graph_totals(const MoveArgs &a, int i, double gain) {
+__device__ __forceinline__ void graph_totals(const MoveArgs &a, int i, unsigned long long gain) {
     int gk = a.g.gid[i];
-    unsafeAtomicAdd(&a.ggain[gk], gain);
+    atomicAdd(&a.ggain[gk], gain);
     atomicAdd(&a.gmoved[gk], 1ull);
 }
 
 // The part of a mover's gain (i: d -> bc) that counts towards the sweep's
-// total: all of it, unless the return-move option gives move records
-// (mhist).  Then a move back into the community i left at its move of the
-// preceding sweep, which undoes a swap made from one snapshot, counts
-// nothing (the move is still made), and this move is recorded.  One lane
-// per mover.
-__device__ __forceinline__ double counted_gain(const MoveArgs &a, int i, int d, int bc, double gain) {
-    if (!a.mhist) return gain;
-    const int32_t sw = (int32_t)*a.sweep_dev;
-    const uint64_t h = (uint64_t)a.mhist[i];
-    a.mhist[i] = (int64_t)(((uint64_t)(uint32_t)d << 32) | (uint32_t)sw);
-    const bool back = (int32_t)(h >> 32) == bc && (int32_t)(uint32_t)h == sw - 1;
-    return back ? 0.0 : gain;
+// total, in fixed point (gain_units): all of it, unless the return-move
+// option gives move records (mhist).  Then a move back into the community i
+// left at its move of the preceding sweep, which undoes a swap made from one
+// snapshot, counts nothing (the move is still made), and this move is
+// recorded.  One lane per mover.
+__device__ __forceinline__ unsigned long long counted_gain(const MoveArgs &a, int i, int d, int bc, double gain,
+                                                           double m2) {
+    if (a.mhist) {
+        const int32_t sw = (int32_t)*a.sweep_dev;
+        const uint64_t h = (uint64_t)a.mhist[i];
+        a.mhist[i] = (int64_t)(((uint64_t)(uint32_t)d << 32) | (uint32_t)sw);
+        if ((int32_t)(h >> 32) == bc && (int32_t)(uint32_t)h == sw - 1) return 0ull;
+    }
+    return gain_units(gain, m2);
 }
 
 // 2m of vertex i's graph (the level's 2m unless it holds a batch).
@@ -411,10 +413,10 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
         for (int r = 0; r < kSmallE; r++)
             if (j[r] >= 0 && j[r] != i) mark_neighbour(a, j[r], w[r]);
     bool lead = valid && gl == 0;
-    const double cg = lead && mv ? counted_gain(a, i, d, bc, gain) : 0.0;
+    const unsigned long long cg = lead && mv ? counted_gain(a, i, d, bc, gain, m2) : 0ull;
     if (a.ggain) {   // batch: per-graph totals, one atomic per graph met by the wavefront
         int gk = valid ? a.g.gid[i] : 0;
-        wave_add_f64_by_key(a.ggain, gk, cg, lead && mv);
+        wave_add_u64_by_key(a.ggain, gk, cg, lead && mv);
         wave_add_u64_by_key(a.gmoved, gk, 1ull, lead && mv);
     }
     if (lead) {
@@ -550,7 +552,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
-                const double cg = counted_gain(a, i, d, bc, gain);
+                const unsigned long long cg = counted_gain(a, i, d, bc, gain, m2);
                 acc.gain += cg;
                 acc.moved++;
                 if (a.ggain) graph_totals(a, i, cg);
@@ -618,7 +620,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(Mov
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
-                const double cg = counted_gain(a, i, d, bc, gain);
+                const unsigned long long cg = counted_gain(a, i, d, bc, gain, m2);
                 acc.gain += cg;
                 acc.moved++;
                 if (a.ggain) graph_totals(a, i, cg);
@@ -800,7 +802,7 @@ __device__ __forceinline__ void hub_decide(const MoveArgs &a, int i, double bg, 
     if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
     a.dec[i] = mv ? bc : d;
     if (mv) {
-        const double cg = counted_gain(a, i, d, bc, gain);
+        const unsigned long long cg = counted_gain(a, i, d, bc, gain, m2);
         acc.gain += cg;
         acc.moved++;
         if (a.ggain) graph_totals(a, i, cg);
@@ -1062,7 +1064,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
             if (a.hbits) record_scan(a, m2, i, d, di, ki, kid, bg, bc, mv);
             a.dec[i] = mv ? bc : d;
             if (mv) {
-                const double cg = counted_gain(a, i, d, bc, gain);
+                const unsigned long long cg = counted_gain(a, i, d, bc, gain, m2);
                 acc.gain += cg;
                 acc.moved++;
                 if (a.ggain) graph_totals(a, i, cg);

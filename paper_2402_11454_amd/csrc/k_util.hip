@@ -206,21 +206,70 @@ __global__ void __launch_bounds__(kBlock) k_modularity_parts(Level g, const int3
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sum_squares(const double *sig, int64_t n, double M2, double *out) {
-    __shared__ double part[kBlock / kWave];
-    double s = 0.0;
+// *out += sum_c (Sigma_c / M2)^2 in fixed point: each term rounded to the
+// nearest multiple of 2^-62 (the sum of the terms is at most 1), so the
+// total is an exact integer sum, the same in any order of the atomics.
+__global__ void __launch_bounds__(kBlock) k_sum_squares(const double *sig, int64_t n, double M2,
+                                                       unsigned long long *out) {
+    unsigned long long s = 0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        double x = sig[i] / M2;
-        s += x * x;
+        const double x = sig[i] / M2;
+        s += (unsigned long long)(long long)rint(ldexp(x * x, 62));
     }
-    s = group_sum<kWave>(s);
-    if (lane_id() == 0) part[threadIdx.x / kWave] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int k = 0; k < kBlock / kWave; k++) t += part[k];
-        unsafeAtomicAdd(out, t);
+    s = (unsigned long long)group_sum_ll<kWave>((long long)s);
+    if (lane_id() == 0 && s) atomicAdd(out, s);
+}
+
+// Weight grid (exact sums).  Non-negative doubles order like their bit
+// patterns, so the largest weight is an atomic max over the bits.
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_weight_max(const void *w, int64_t nnz, unsigned long long *out) {
+    double m = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
+        const double x = edge_weight<WT>(w, e);
+        m = x > m ? x : m;
     }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// *U += max(1, ceil(w 2^T)) over the positive weights: an exact integer
+// bound of 2^T times the weight total (T chosen so that it stays below 2^63).
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_weight_bound(const void *w, int64_t nnz, int T, unsigned long long *U) {
+    unsigned long long s = 0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
+        const double x = edge_weight<WT>(w, e);
+        if (!(x > 0.0)) continue;
+        const double t = ceil(ldexp(x, T));
+        s += t < 1.0 ? 1ull : (unsigned long long)t;
+    }
+    s = (unsigned long long)group_sum_ll<kWave>((long long)s);
+    if (lane_id() == 0 && s) atomicAdd(U, s);
+}
+
+// w <- nearest multiple of 2^-S (ties to even), in place; *moved counts the
+// weights that changed.  A weight rounded to a coarser grid needs no more
+// significand bits than it had, so an fp32 weight stays exact in fp32.
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_weight_grid(void *w, int64_t nnz, int S, unsigned long long *moved) {
+    unsigned long long c = 0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock) {
+        const double x = edge_weight<WT>(w, e);
+        const double q = ldexp(rint(ldexp(x, S)), -S);
+        if (q == x) continue;
+        c++;
+        if constexpr (WT == W_F32)
+            ((float *)w)[e] = (float)q;
+        else
+            ((double *)w)[e] = q;
+    }
+    c = (unsigned long long)group_sum_ll<kWave>((long long)c);
+    if (lane_id() == 0 && c) atomicAdd(moved, c);
 }
 
 __global__ void __launch_bounds__(kBlock) k_check_labels(const int32_t *memb, int64_t n, int *err) {
@@ -317,8 +366,35 @@ void launch_modularity_parts(const Level &g, const int32_t *memb, const double *
         k_modularity_parts<W_F64><<<gr, kBlock, 0, s>>>(g, memb, K, sig, sigma_in);
 }
 
-void launch_sum_squares(const double *sig, int64_t n, double M2, double *out, hipStream_t s) {
+void launch_sum_squares(const double *sig, int64_t n, double M2, unsigned long long *out, hipStream_t s) {
     if (n > 0) k_sum_squares<<<grid_for(n, kBlock * 4, 4096), kBlock, 0, s>>>(sig, n, M2, out);
+}
+
+void launch_weight_max(const void *w, int wt, int64_t nnz, unsigned long long *out, hipStream_t s) {
+    if (nnz == 0 || wt == W_UNIT) return;
+    unsigned gr = grid_for(nnz, kBlock * 8, 8192);
+    if (wt == W_F32)
+        k_weight_max<W_F32><<<gr, kBlock, 0, s>>>(w, nnz, out);
+    else
+        k_weight_max<W_F64><<<gr, kBlock, 0, s>>>(w, nnz, out);
+}
+
+void launch_weight_bound(const void *w, int wt, int64_t nnz, int T, unsigned long long *U, hipStream_t s) {
+    if (nnz == 0 || wt == W_UNIT) return;
+    unsigned gr = grid_for(nnz, kBlock * 8, 8192);
+    if (wt == W_F32)
+        k_weight_bound<W_F32><<<gr, kBlock, 0, s>>>(w, nnz, T, U);
+    else
+        k_weight_bound<W_F64><<<gr, kBlock, 0, s>>>(w, nnz, T, U);
+}
+
+void launch_weight_grid(void *w, int wt, int64_t nnz, int S, unsigned long long *moved, hipStream_t s) {
+    if (nnz == 0 || wt == W_UNIT) return;
+    unsigned gr = grid_for(nnz, kBlock * 8, 8192);
+    if (wt == W_F32)
+        k_weight_grid<W_F32><<<gr, kBlock, 0, s>>>(w, nnz, S, moved);
+    else
+        k_weight_grid<W_F64><<<gr, kBlock, 0, s>>>(w, nnz, S, moved);
 }
 
 void launch_check_labels(const int32_t *memb, int64_t n, int *err, hipStream_t s) {

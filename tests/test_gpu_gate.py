@@ -220,7 +220,7 @@ def test_gated_phase_matches_oracle(ctx, make, b3):
                                            prune_threshold=th)
     assert cnto["pruned"] > 0 and cnto["confirm_sweeps"] >= 1
     assert np.array_equal(m, mo) and li == lio and np.array_equal(mv, mvo)
-    assert np.array_equal(dq, dqo) if g.weights is None else np.allclose(dq, dqo, rtol=1e-12, atol=0)
+    assert np.array_equal(dq, dqo)
     assert cnt == cnto
 
 
@@ -257,6 +257,51 @@ def test_gated_run_matches_oracle(ctx, returns):
     assert res.stats["scanned_entries"] == ref.counters["scanned_entries"]
     assert abs(res.modularity - ref.modularity) <= 1e-9
     assert ctx.count_disconnected(res.membership) == 0
+
+
+def test_second_network_on_a_warm_context(ctx):
+    """Two networks in a row on one loaded graph (the first run's gated
+    sweeps captured and cached): the second run is the oracle's run with the
+    second network, output bias included."""
+    g = gi.dcsbm_small(8000, 9)
+    p1 = _params(61, 0.5, sharp=64.0)
+    p2 = p1.copy()
+    p2[B3] = -0.25 * 64.0                       # same layers, another output bias
+
+    def run(tl):
+        r = oracle.louvain(g, sync=True, prune_params=p2, theta_logit=tl)
+        return (r.membership.tobytes(), tuple(r.iterations), tuple(r.counters.values()))
+
+    th = _stable_theta(g, p2, [0.5, 0.55, 0.45, 0.6, 0.4], run)
+    ref = oracle.louvain(g, sync=True, prune_params=p2, theta=th)
+    ref1 = oracle.louvain(g, sync=True, prune_params=p1, theta=th)
+    assert ref.counters["pruned"] != ref1.counters["pruned"]
+    _load(ctx, g)
+    ctx.pruner_set(p1)
+    ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th)
+    ctx.pruner_set(p2)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th)
+    assert np.array_equal(res.membership, ref.membership)
+    assert res.stats["iterations"] == ref.iterations
+    assert res.stats["pruned"] == ref.counters["pruned"]
+
+
+@pytest.mark.parametrize("max_iter", [1, 2, 3])
+def test_gated_phase_last_iteration_confirms(ctx, max_iter):
+    """A gate that keeps every vertex, and a phase cut at a small
+    max_iterations: the last countable iteration is a confirming sweep over
+    every vertex, as in the oracle."""
+    g = gi.rmat_small(12, 9)
+    p = np.zeros(P, np.float32)
+    p[B3] = 10.0
+    mo, lio, dqo, mvo, cnto = oracle.move_sync_gated(g, p, pass_index=0, tau=0.0, max_iter=max_iter)
+    _load(ctx, g)
+    ctx.pruner_set(p)
+    m, li, dq, mv, cnt = ctx.move_phase_ex(None, tolerance=0.0, prune_mode=gsp.PRUNE_LEARNED,
+                                           max_iterations=max_iter)
+    assert cnto["confirm_sweeps"] == 1
+    assert np.array_equal(m, mo) and li == lio and np.array_equal(dq, dqo) and np.array_equal(mv, mvo)
+    assert cnt == cnto
 
 
 def test_learned_mode_errors(ctx):

@@ -4,9 +4,10 @@ Bars (stated per test): modularity within 1e-9 in fp64; split labels,
 aggregated graphs (rows canonicalised by column), synchronous move decisions,
 gain numerators, whole local-moving phases and whole runs bit-exact.  All
 graphs here have integer weights or fp32 weights whose fp64 sums are exact,
-so the GPU's atomics cannot change a membership, a table value or a score;
-only the per-iteration total of fp32-weight gains (a sum of inexact
-products, taken in atomic order) is compared with a relative 1e-12.
+so the GPU's atomics cannot change a membership, a table value or a score
+(other weights are taken onto the grid of exact sums at load, as the
+oracle takes them); the per-iteration gain totals are exact sums of
+fixed-point shares and compared bit for bit too.
 """
 import numpy as np
 import pytest
@@ -163,12 +164,8 @@ def test_move_phase_bit_exact(ctx, name, rounds, returns):
         np.testing.assert_array_equal(m, rm)
         assert li == rli
         np.testing.assert_array_equal(mv, rmv)
-        if _integer_weights(g):
-            np.testing.assert_array_equal(dq, rdq)
-        else:
-            # gain numerators of fp32 weights are not exact; their sum depends
-            # on the order of the GPU's atomics
-            np.testing.assert_allclose(dq, rdq, rtol=1e-12, atol=0)
+        # the gain totals are exact sums of fixed-point shares on any weights
+        np.testing.assert_array_equal(dq, rdq)
 
 
 def test_swap_cycle_return_moves(ctx):
@@ -258,6 +255,37 @@ def test_split_modes(ctx, mode):
     res = ctx.louvain(tolerance=1e-2, max_passes=10, split_mode=mode)
     ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, split_mode=mode)
     np.testing.assert_array_equal(res.membership, ref.membership)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_weight_grid_equals_oracle(ctx, seed):
+    """fp64 weights whose fp64 sums depend on their order: the load takes
+    them onto the grid of exact sums with the oracle's S, and the whole run
+    then equals the oracle's (which takes the same grid)."""
+    g0 = gi.rmat_small(13, 40 + seed, weights=(1.0, 4.0))
+    # symmetric fp64 weights: the generator's weight of the undirected edge
+    # times 1 + (a hash of the edge) 2^-30, which needs all 53 bits
+    rows = np.repeat(np.arange(g0.n, dtype=np.uint64), np.diff(g0.offsets))
+    cols = g0.cols.astype(np.uint64)
+    key = np.minimum(rows, cols) * np.uint64(g0.n) + np.maximum(rows, cols) + np.uint64(seed)
+    frac = ((key * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    w_sym = g0.weights.astype(np.float64) * (1.0 + frac * 2.0 ** -30)
+    h = oracle.CSR(g0.n, g0.offsets, g0.cols, w_sym)
+    wg = w_sym.copy()
+    S, moved = oracle.weight_grid(wg)
+    assert moved > 0
+    ctx.load(h.off, h.col, h.w, n=h.n)
+    assert ctx.weight_grid() == (S, moved)
+    hg = oracle.CSR(g0.n, g0.offsets, g0.cols, wg)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10)
+    ref = oracle.louvain(hg, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+    np.testing.assert_array_equal(res.membership, ref.membership)
+    assert res.stats["iterations"] == ref.iterations
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+    m, li, dq, mv = ctx.move_phase(None, tolerance=1e-2)
+    rm, rli, rdq, rmv = oracle.move_sync(hg, None, tau=1e-2)
+    np.testing.assert_array_equal(m, rm)
+    np.testing.assert_array_equal(dq, rdq)
 
 
 def test_edge_cases(ctx):
@@ -389,15 +417,26 @@ def test_global_hub_tables_equal_partitions(ctx, name):
     through LDS hash partitions (the default) give the same runs."""
     g = _graph(name)
     _load(ctx, g)
+    # the runs share the context, so b and c would replay a's captured sweeps
+    # if the hub options were not part of their key: the pairs read back by
+    # the partition gather (class move_hub_gather) show which path ran
     a = ctx.louvain(tolerance=1e-2, max_passes=10)
     b = ctx.louvain(tolerance=1e-2, max_passes=10, hub_global=1)
     assert np.array_equal(a.membership, b.membership)
     assert a.stats["iterations"] == b.stats["iterations"]
+    off = g.off if isinstance(g, oracle.CSR) else g.offsets
+    hubs = int(np.diff(off).max()) > 2048
+    if hubs:
+        assert a.stats["kernels"]["move_hub_gather"]["items"] > 0
+    assert b.stats["kernels"]["move_hub_gather"]["items"] == 0
     # every hub of more than one chunk through the partition kernels' own
     # fallback (the hub's decision workgroup takes it through its global table)
     c = ctx.louvain(tolerance=1e-2, max_passes=10, hub_max_parts=1)
     assert np.array_equal(a.membership, c.membership)
     assert a.stats["iterations"] == c.stats["iterations"]
+    assert c.stats["kernels"]["move_hub_gather"]["items"] == 0
+    a2 = ctx.louvain(tolerance=1e-2, max_passes=10)          # back to the partitions
+    assert a2.stats["kernels"]["move_hub_gather"]["items"] == a.stats["kernels"]["move_hub_gather"]["items"]
     if name == "rmat15w":
         ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
         assert np.array_equal(a.membership, ref.membership)
