@@ -209,6 +209,28 @@ gsp_status gsp_modularity(gsp_ctx *ctx, const int32_t *membership, int where, do
  * (Algorithm "disconnectedCommunities"). */
 gsp_status gsp_count_disconnected(gsp_ctx *ctx, const int32_t *membership, int where, int64_t *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count
+ * of gsp_count_disconnected for a CSR and a membership given in device
+ * memory, with no context and no allocation.  offsets (int64, n + 1),
+ * cols (int32, nnz), membership (int32, n) and count_out (one int64) are
+ * device pointers on the current device; the work is enqueued on
+ * hip_stream (NULL: the null stream) and *count_out is written when the
+ * stream reaches it (the call does not wait).  The inputs are not
+ * validated on the host: an offset, column or label out of range gives
+ * *count_out = -1 (every access is checked on the device).
+ * Scratch is a fixed 64 MiB array in device memory (8 bytes per vertex),
+ * held by each GPU the library runs on until the process ends and shared
+ * by every call on that GPU: calls that overlap on one GPU race (order them
+ * on one stream).  n above gsp_noalloc_max_vertices() (8,388,576) gives
+ * GSP_EINVAL, as do negative sizes and NULL pointers; a launch failure
+ * gives GSP_EHIP.  No context, so there is no gsp_last_error message. */
+gsp_status gsp_count_disconnected_noalloc(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                                          const int32_t *membership, int64_t *count_out, void *hip_stream);
+
+/* The largest n gsp_count_disconnected_noalloc accepts. */
+int64_t gsp_noalloc_max_vertices(void);
+
 /* ---- stepwise hooks on the loaded graph (used to check each step) ---- */
 
 /* One synchronous local-moving step (Algorithm "louvainMove", gains by

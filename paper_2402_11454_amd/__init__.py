@@ -121,6 +121,7 @@ def lib():
         "gsp_capture_traces": [vp, i64, dbl, ctypes.c_uint64],
         "gsp_get_traces": [vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int],
         "gsp_get_weight_grid": [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
+        "gsp_count_disconnected_noalloc": [i64, i64, vp, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -128,8 +129,29 @@ def lib():
         f.restype = st
     L.gsp_last_error.argtypes = [vp]
     L.gsp_last_error.restype = ctypes.c_char_p
+    L.gsp_noalloc_max_vertices.argtypes = []
+    L.gsp_noalloc_max_vertices.restype = i64
     _lib = L
     return L
+
+
+def count_disconnected_noalloc(offsets, cols, membership, out, stream=None) -> None:
+    """gsp_count_disconnected_noalloc on torch device tensors (int64
+    offsets, int32 cols and membership, one-element int64 out); enqueued on
+    `stream` (a torch stream, default: the current one), no allocation."""
+    import torch
+    n = int(membership.numel())
+    st = stream if stream is not None else torch.cuda.current_stream()
+    for t, dt in ((offsets, torch.int64), (cols, torch.int32), (membership, torch.int32), (out, torch.int64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("device tensors: int64 offsets, int32 cols and membership, int64 out")
+    if offsets.numel() != n + 1 or out.numel() < 1:
+        raise ValueError("offsets must hold n + 1 values and out one")
+    status = lib().gsp_count_disconnected_noalloc(n, int(cols.numel()), offsets.data_ptr(), cols.data_ptr(),
+                                                  membership.data_ptr(), out.data_ptr(),
+                                                  ctypes.c_void_p(st.cuda_stream))
+    if status != GSP_OK:
+        raise GspError(status, "gsp_count_disconnected_noalloc failed")
 
 
 def default_options(**kw) -> Options:

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <cmath>
@@ -1859,6 +1860,66 @@ gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, do
     return gsp_move_phase_ex(ctx, membership_inout, where, tolerance, 0, &opt, iterations, dq_iter, moved_iter,
                              nullptr);
 }
+
+// ---- the disconnected count without allocation ----
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of gsp_count_disconnected_noalloc: a fixed array in device memory
+// (each GPU holds its own copy for the life of the process).  Layout: two
+// 64-bit counters in the first 256 bytes, then parent[n] and roots[n]
+// (int32).  Host code never passes `scratch` itself to a kernel (in host
+// code it is a stand-in, not a device address): it takes the device
+// address of this GPU's copy from hipGetSymbolAddress once per device.
+constexpr size_t kNoallocBytes = (size_t)64 << 20;
+constexpr int64_t kNoallocMaxN = (int64_t)((kNoallocBytes - 256) / 8);
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {nullptr};
+
+// This device's address of `scratch` (looked up on the first call per
+// device, with that device current).
+hipError_t noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsp_status gsp_count_disconnected_noalloc(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                                          const int32_t *membership, int64_t *count_out, void *hip_stream) {
+    if (n < 0 || nnz < 0 || n > kNoallocMaxN || !offsets || !count_out || (n > 0 && !membership) ||
+        (nnz > 0 && !cols))
+        return GSP_EINVAL;
+    void *base = nullptr;
+    if (noalloc_scratch(&base) != hipSuccess) return GSP_EHIP;
+    unsigned char *b = static_cast<unsigned char *>(base);
+    unsigned long long *flags = reinterpret_cast<unsigned long long *>(b);
+    int32_t *parent = reinterpret_cast<int32_t *>(b + 256);
+    int32_t *roots = parent + n;
+    hipStream_t s = (hipStream_t)hip_stream;
+    launch_count_disconnected_csr(offsets, cols, n, nnz, membership, parent, roots, flags, count_out, s);
+    return hipGetLastError() == hipSuccess ? GSP_OK : GSP_EHIP;
+}
+
+int64_t gsp_noalloc_max_vertices(void) { return kNoallocMaxN; }
 
 // ---- learned pruning gate ----
 

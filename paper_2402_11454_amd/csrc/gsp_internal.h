@@ -296,6 +296,14 @@ void launch_lookup(int32_t *top, int64_t n, const int32_t *cm, hipStream_t s);
 // Counts communities (of memb) with more than one component (labels).
 void launch_count_disconnected(const int32_t *labels, const int32_t *memb, int64_t n, int32_t *roots_per_comm,
                                unsigned long long *out, hipStream_t s);
+// The disconnected count of a caller's CSR (device pointers, unvalidated)
+// with caller-provided scratch: parent and roots of n entries, flags of 2.
+// Union-find over every same-community entry (no work lists), then
+// communities with more than one root; *out (device) = that count, or -1 if
+// an offset, column or label lies out of range (every access is checked).
+void launch_count_disconnected_csr(const int64_t *off, const int32_t *col, int64_t n, int64_t nnz,
+                                   const int32_t *memb, int32_t *parent, int32_t *roots, unsigned long long *flags,
+                                   int64_t *out, hipStream_t s);
 // lab[v] = smallest vertex of v's community (then renumber gives the
 // numbering by ascending smallest vertex).  first is an n-sized temp.
 void launch_canonical_labels(const int32_t *memb, int64_t n, int32_t *first, int32_t *lab, hipStream_t s);

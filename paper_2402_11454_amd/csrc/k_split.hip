@@ -290,6 +290,56 @@ __global__ void __launch_bounds__(kBlock) k_gather(const int32_t *tab, const int
         out[v] = tab[idx[v]];
 }
 
+// ---- the context-free disconnected count (caller's CSR, fixed scratch) ----
+//
+// flags[0]: communities with more than one component; flags[1]: nonzero if
+// the input was malformed (an offset, a column or a label out of range).
+// Every kernel checks what it indexes, so a malformed input gives -1 and no
+// access outside the caller's arrays or the scratch.
+
+__global__ void __launch_bounds__(kBlock) k_na_init(int32_t *parent, int32_t *roots, int64_t n,
+                                                   unsigned long long *flags) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        parent[i] = (int32_t)i;
+        roots[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 2) flags[threadIdx.x] = 0;
+}
+
+// One wavefront per row: unite i with every neighbour in its community.
+__global__ void __launch_bounds__(kBlock) k_na_hook(const int64_t *off, const int32_t *col, int64_t n, int64_t nnz,
+                                                   const int32_t *memb, int32_t *parent,
+                                                   unsigned long long *flags) {
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < n; i += nw) {
+        const int64_t beg = off[i], end = off[i + 1];
+        const int ci = memb[i];
+        bool bad = beg < 0 || end < beg || end > nnz || ci < 0 || (int64_t)ci >= n;
+        if (!bad)
+            for (int64_t e = beg + lane_id(); e < end; e += kWave) {
+                const int j = col[e];
+                if (j < 0 || (int64_t)j >= n) {
+                    bad = true;
+                    continue;
+                }
+                if (j != (int)i && memb[j] == ci) unite(parent, (int)i, j);
+            }
+        if (bad) atomicOr(&flags[1], 1ull);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_na_roots(const int32_t *parent, const int32_t *memb, int64_t n,
+                                                    int32_t *roots) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const int c = memb[i];
+        if (c >= 0 && (int64_t)c < n && parent[i] == (int32_t)i) atomicAdd(&roots[c], 1);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_na_finish(const unsigned long long *flags, int64_t *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = flags[1] ? -1 : (int64_t)flags[0];
+}
+
 inline unsigned grid1(int64_t n) {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
@@ -349,6 +399,20 @@ void launch_count_disconnected(const int32_t *labels, const int32_t *memb, int64
     launch_fill_i32(roots_per_comm, 0, n, s);
     k_roots_per_comm<<<grid1(n), kBlock, 0, s>>>(labels, memb, n, roots_per_comm);
     k_count_gt1<<<grid1(n), kBlock, 0, s>>>(roots_per_comm, n, out);
+}
+
+void launch_count_disconnected_csr(const int64_t *off, const int32_t *col, int64_t n, int64_t nnz,
+                                   const int32_t *memb, int32_t *parent, int32_t *roots, unsigned long long *flags,
+                                   int64_t *out, hipStream_t s) {
+    k_na_init<<<grid1(n), kBlock, 0, s>>>(parent, roots, n, flags);
+    if (n > 0) {
+        const int64_t wg = (n + kBlock / kWave - 1) / (kBlock / kWave);
+        k_na_hook<<<(unsigned)std::min<int64_t>(wg, 65536), kBlock, 0, s>>>(off, col, n, nnz, memb, parent, flags);
+        k_split_compress<<<grid1(n), kBlock, 0, s>>>(parent, n);
+        k_na_roots<<<grid1(n), kBlock, 0, s>>>(parent, memb, n, roots);
+        k_count_gt1<<<grid1(n), kBlock, 0, s>>>(roots, n, flags);
+    }
+    k_na_finish<<<1, kBlock, 0, s>>>(flags, out);
 }
 
 void launch_canonical_labels(const int32_t *memb, int64_t n, int32_t *first, int32_t *lab, hipStream_t s) {
