@@ -1,26 +1,26 @@
-"""HBM traffic of the library's kernels from rocprofv3 hardware counters.
+"""HBM traffic of the library's kernels from rocprofv3 hardware counters,
+for bench.py's roofline (its `traffic` field).
 
 Two profiling passes over the same workload, one per counter (FETCH_SIZE,
 then WRITE_SIZE, in KiB per dispatch), each also covering an elementwise
 kernel of known traffic (y = 2x over 1 GiB: reads 1 GiB, writes 1 GiB);
-its counters give the scale from counter KiB to bytes.  The summary (per kernel: dispatches, mean KiB read and written,
-scaled bytes per dispatch) goes to profiles/traffic.json with a hash of the
-kernel's sources (its file, the headers, the host code), and a readable table to profiles/traffic_rmat20.md.
+its counters give the scale from counter KiB to bytes.  The summary (per
+kernel: dispatches, mean KiB read and written, scaled bytes per dispatch)
+goes to profiles/traffic_<workload>.json with a hash of the kernel's sources
+(its file, the headers, the host code), and a readable table to
+profiles/traffic_<workload>.md.  Workloads as bench.py names them
+(rmat26, rmat20, dcsbm4m); --learned profiles learned-pruned runs.
 
-    python -m paper_2402_11454_amd.pmc_traffic --run            # the workload (under rocprofv3)
-    python -m paper_2402_11454_amd.pmc_traffic --summarize FETCH_DB WRITE_DB --cmd "..."
-
---scale/--seed/--weights choose another R-MAT graph (as bench.py builds
-it); its summary goes to profiles/traffic_rmat<scale>.json and .md (the
-R-MAT 20 one, which bench.py reads, to profiles/traffic.json).
+    python bench_traffic.py --run --workload rmat26            # the workload (under rocprofv3)
+    python bench_traffic.py --summarize FETCH_DB WRITE_DB --workload rmat26 --cmd "..."
 
 Per phase: the counters' bytes of one run, phase by phase (local moving,
 split, aggregation, the rest), over the phases' wall times from HIP events
-(timing = 1: scans side by side, sweeps replayed from graphs, as in untimed
-runs):
+(timing = 1: scans side by side, sweeps replayed from graphs, as in runs
+without events):
 
-    python -m paper_2402_11454_amd.pmc_traffic --phase-times OUT.json [--scale ...]   # on the GPU
-    python -m paper_2402_11454_amd.pmc_traffic --phases TRAFFIC.json OUT.json --cmd "..."
+    python bench_traffic.py --phase-times OUT.json --workload rmat26        # on the GPU
+    python bench_traffic.py --phases TRAFFIC.json OUT.json --cmd "..."
 """
 import argparse
 import json
@@ -28,28 +28,32 @@ import os
 import sqlite3
 import sys
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
+ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 
 
-def run_workload(runs: int, scale: int = 20, seed: int = 20, weights=None):
+def run_workload(runs: int, workload: str, learned: bool):
     sys.path.insert(0, ROOT)
     import torch
-    import gsp_inputs as gi
     import paper_2402_11454_amd as gsp
+    from bench import make_graph
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, load_params
     torch.cuda.init()
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
         torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
-    g = _graph(scale, seed, weights)
+    g = make_graph(workload)
     print(f"[pmc] graph ready: n={g.n} nnz={g.nnz}", flush=True)
     ctx = gsp.Context(0, stream=torch.cuda.current_stream())
     ctx.load_graph(g)
+    kw = {}
+    if learned:
+        ctx.pruner_set(load_params(DEFAULT_OUT))
+        kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
     for k in range(runs):
-        ctx.run(1e-2, 10)
+        ctx.run(1e-2, 10, **kw)
         print(f"[pmc] run {k + 1}/{runs}", flush=True)
     ctx.close()
 
@@ -83,7 +87,7 @@ def short(name: str) -> str:
     return s.replace("void ", "")
 
 
-def summarize(fetch_db, write_db, cmd, scale: int = 20, runs: int = 2):
+def summarize(fetch_db, write_db, cmd, workload: str, runs: int = 2):
     sys.path.insert(0, ROOT)
     from bench import kernel_source_hash
     fe = per_kernel(fetch_db, "FETCH_SIZE")
@@ -114,13 +118,13 @@ def summarize(fetch_db, write_db, cmd, scale: int = 20, runs: int = 2):
         for f in ("fetch_kib", "write_kib", "bytes_per_launch"):
             acc[f] = round(acc[f] / n, 1)
         acc["source_hash"] = kernel_source_hash(name)
-    out = {"workload": f"rmat{scale}", "command": cmd, "runs": runs, "copy_kernel": short(copy),
+    out = {"workload": workload, "command": cmd, "runs": runs, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
-    with open(os.path.join(prof, "traffic.json" if scale == 20 else f"traffic_rmat{scale}.json"), "w") as f:
+    with open(os.path.join(prof, f"traffic_{workload}.json"), "w") as f:
         json.dump(out, f, indent=1)
-    with open(os.path.join(prof, f"traffic_rmat{scale}.md"), "w") as f:
-        f.write(f"# HBM traffic per dispatch: plain GSP-Louvain on R-MAT scale {scale}\n\n")
+    with open(os.path.join(prof, f"traffic_{workload}.md"), "w") as f:
+        f.write(f"# Memory traffic per dispatch (FETCH_SIZE / WRITE_SIZE): GSP-Louvain on {workload}\n\n")
         f.write(f"Command (two passes, one counter each):\n\n```\n{cmd}\n```\n\n")
         f.write(f"Scale: y = 2x over {COPY_BYTES} bytes (`{short(copy)[:60]}`) reads {fe[copy][1]:.0f} KiB "
                 f"(FETCH_SIZE) -> factor {f_scale:.4f}; write factor {w_scale:.4f}.\n\n")
@@ -130,18 +134,12 @@ def summarize(fetch_db, write_db, cmd, scale: int = 20, runs: int = 2):
     print(json.dumps(out)[:400])
 
 
-def _graph(scale, seed, weights):
-    import gsp_inputs as gi
-    if scale == 20 and seed == 20 and weights is None:
-        return gi.rmat20()
-    return gi.rmat(scale, 16, *gi.RMAT_ABC, seed, weights=weights, name=f"rmat-{scale}")
-
-
-def phase_times(out_path: str, runs: int, scale: int, seed: int, weights):
+def phase_times(out_path: str, runs: int, workload: str):
     """Mean phase wall times (ms) of `runs` runs after two warm-up runs."""
     sys.path.insert(0, ROOT)
     import paper_2402_11454_amd as gsp
-    g = _graph(scale, seed, weights)
+    from bench import make_graph
+    g = make_graph(workload)
     ctx = gsp.Context(0)
     ctx.load_graph(g)
     for _ in range(2):
@@ -154,7 +152,7 @@ def phase_times(out_path: str, runs: int, scale: int, seed: int, weights):
             acc[f] += st[f] / runs
         print(f"[phases] run {k + 1}/{runs}: {st['ms_total']:.3f} ms", flush=True)
     ctx.close()
-    out = {"workload": f"rmat{scale}", "n": int(g.n), "nnz": int(g.nnz), "runs": runs, **acc}
+    out = {"workload": workload, "n": int(g.n), "nnz": int(g.nnz), "runs": runs, **acc}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out), flush=True)
@@ -182,7 +180,7 @@ def phases(traffic_json: str, times_json: str, cmd: str):
     w = tm["workload"]
     path = os.path.join(ROOT, "profiles", f"phases_{w}.md")
     with open(path, "w") as f:
-        f.write(f"# HBM traffic per phase: plain GSP-Louvain on R-MAT scale {w[4:]} "
+        f.write(f"# Memory traffic per phase: plain GSP-Louvain on {w} "
                 f"(n={tm['n']}, {tm['nnz']} entries)\n\n")
         f.write(f"Commands:\n\n```\n{cmd}\n```\n\n")
         f.write(f"Bytes: the counters' FETCH + WRITE bytes of one run ({traffic_json}, {runs} run(s) under counters) "
@@ -204,18 +202,16 @@ if __name__ == "__main__":
     ap.add_argument("--runs", type=int, default=2)
     ap.add_argument("--summarize", nargs=2)
     ap.add_argument("--cmd", default="")
-    ap.add_argument("--scale", type=int, default=20)
-    ap.add_argument("--seed", type=int, default=20)
-    ap.add_argument("--weights", default="", help="lo,hi: symmetric fp32 weights U[lo,hi)")
+    ap.add_argument("--workload", default="rmat26")
+    ap.add_argument("--learned", action="store_true", help="learned-pruned runs (bench.py's timed runs)")
     ap.add_argument("--phase-times", default="", help="write the phases' mean wall times to this JSON")
     ap.add_argument("--phases", nargs=2, help="TRAFFIC_JSON TIMES_JSON: per-phase summary")
     a = ap.parse_args()
-    wts = tuple(float(v) for v in a.weights.split(",")) if a.weights else None
     if a.run:
-        run_workload(a.runs, a.scale, a.seed, wts)
+        run_workload(a.runs, a.workload, a.learned)
     if a.summarize:
-        summarize(a.summarize[0], a.summarize[1], a.cmd, a.scale, a.runs)
+        summarize(a.summarize[0], a.summarize[1], a.cmd, a.workload, a.runs)
     if a.phase_times:
-        phase_times(a.phase_times, 3, a.scale, a.seed, wts)
+        phase_times(a.phase_times, 3, a.workload)
     if a.phases:
         phases(a.phases[0], a.phases[1], a.cmd)

@@ -1,18 +1,17 @@
-"""Timings of the other workloads (beside bench.py's R-MAT 20): the batch of
+"""Timings of the other workloads (beside bench.py's R-MAT 26): the batch of
 512 planted-partition SBMs and the 4M-vertex degree-corrected SBM, plain
 and learned-pruned, with the return-move option off (the tolerance test as
 written) and on.  Whole runs, graph resident in device memory, best of
 `--reps` runs after one warm-up run; prints one line per case.
 
-    python -m paper_2402_11454_amd.workloads [--batch] [--dcsbm] [--reps 3]
+    python bench_workloads.py [--batch] [--dcsbm] [--reps 3]
 """
 import argparse
 import os
 import sys
 import time
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-sys.path.insert(0, os.path.dirname(HERE))
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 
 def _best(run, reps):

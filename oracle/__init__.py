@@ -196,8 +196,7 @@ def move_sync_step(g, memb, active=None, K=None, M2=None):
     if K is None:
         K, M2 = vertex_weights(g)
     m = _memb(memb, g.n)
-    sigma = np.zeros(g.n, dtype=np.float64)
-    np.add.at(sigma, m, K)
+    sigma = np.bincount(m, weights=K, minlength=g.n).astype(np.float64)
     csize = np.bincount(m, minlength=g.n).astype(np.int32)
     act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
     dec = np.empty(g.n, dtype=np.int32)
