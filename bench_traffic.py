@@ -196,6 +196,41 @@ def phases(traffic_json: str, times_json: str, cmd: str):
     print(open(path).read())
 
 
+def kernel_summary(db: str, cmd: str, title: str, out_md: str, bench_out: str = ""):
+    """Per-kernel durations (all instantiations of a kernel together) from a
+    rocprofv3 --kernel-trace database, as a markdown table."""
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    rows = {}
+    for name, dur in cur.execute("select name, duration from kernels"):
+        k = short(name).split("<")[0]
+        r = rows.setdefault(k, [0, 0.0, float("inf"), 0.0])
+        d = float(dur) / 1e3   # ns -> us
+        r[0] += 1
+        r[1] += d
+        r[2] = min(r[2], d)
+        r[3] = max(r[3], d)
+    total = sum(r[1] for r in rows.values())
+    line = ""
+    if bench_out and os.path.exists(bench_out):
+        last = [x for x in open(bench_out).read().splitlines() if x.startswith("{")]
+        if last:
+            b = json.loads(last[-1])
+            line = (f"Bench line of this command: {b['ms_per_step']} ms per learned-pruned run "
+                    f"({b['value'] / 1e9:.3f} G entries/s), plain {b['config']['plain']['ms_per_step']} ms; roofline "
+                    f"kernel `{b['roofline']['kernel']}` {b['roofline']['avg_launch_us']} us per launch by events, "
+                    f"{b['roofline']['bytes_per_launch']:.0f} algorithmic bytes per launch.\n\n")
+    with open(out_md, "w") as f:
+        f.write(f"# Kernel trace: {title}\n\nCommand:\n\n```\n{cmd}\n```\n\n")
+        f.write(f"Kernel time summed over kernels (overlapping kernels on concurrent streams counted each): "
+                f"{total / 1e3:.3f} ms, warm-up and probe runs included.\n\n{line}")
+        f.write("| kernel | calls | total ms | avg us | min us | max us | share |\n"
+                "|---|---:|---:|---:|---:|---:|---:|\n")
+        for k, (n, t, lo, hi) in sorted(rows.items(), key=lambda kv: -kv[1][1])[:30]:
+            f.write(f"| `{k}` | {n} | {t / 1e3:.3f} | {t / n:.2f} | {lo:.2f} | {hi:.2f} | {t / total:.1%} |\n")
+    print(open(out_md).read())
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--run", action="store_true")
@@ -206,7 +241,13 @@ if __name__ == "__main__":
     ap.add_argument("--learned", action="store_true", help="learned-pruned runs (bench.py's timed runs)")
     ap.add_argument("--phase-times", default="", help="write the phases' mean wall times to this JSON")
     ap.add_argument("--phases", nargs=2, help="TRAFFIC_JSON TIMES_JSON: per-phase summary")
+    ap.add_argument("--kernel-summary", nargs=2, metavar=("DB", "OUT_MD"),
+                    help="per-kernel durations of a --kernel-trace database into a markdown table")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--bench-out", default="", help="stdout of the profiled bench.py run (its JSON line)")
     a = ap.parse_args()
+    if a.kernel_summary:
+        kernel_summary(a.kernel_summary[0], a.cmd, a.title, a.kernel_summary[1], a.bench_out)
     if a.run:
         run_workload(a.runs, a.workload, a.learned)
     if a.summarize:
