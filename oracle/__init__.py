@@ -46,14 +46,15 @@ class _Options(ctypes.Structure):
                 ("aggregation_tolerance", ctypes.c_double), ("sync_moves", ctypes.c_int32),
                 ("sync_rounds", ctypes.c_int32), ("split_mode", ctypes.c_int32),
                 ("prune_params", ctypes.c_void_p), ("prune_theta_logit", ctypes.c_double),
-                ("trace", ctypes.POINTER(_Trace)), ("return_moves", ctypes.c_int32)]
+                ("trace", ctypes.POINTER(_Trace)), ("return_moves", ctypes.c_int32),
+                ("confirm_final", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("iterations", ctypes.c_int32 * 64),
                 ("communities", ctypes.c_int64 * 64), ("vertices", ctypes.c_int64 * 64),
                 ("modularity", ctypes.c_double), ("counters", ctypes.c_int64 * 4),
-                ("tau", ctypes.c_double * 64)]
+                ("tau", ctypes.c_double * 64), ("final_iterations", ctypes.c_int32)]
 
 
 def _load():
@@ -91,7 +92,7 @@ def _load():
         "orc_mlp_train_adam": (i64, [vp, vp, vp, i64, i64, i32, dbl, dbl, vp]),
         "orc_trace_keep": (i32, [ctypes.c_uint64, i32, i32, i64, ctypes.c_uint64]),
         "orc_move_sync_gated": (i32, [i64, vp, vp, vp, dbl, vp, vp, dbl, i32, i32, vp, dbl, i32,
-                                      ctypes.POINTER(_Trace), vp, vp, vp, i32]),
+                                      ctypes.POINTER(_Trace), vp, vp, vp, i32, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -401,7 +402,7 @@ class Trace:
 
 def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, memb=None, tau: float = 0.0,
                     max_iter: int = 20, rounds: int = 8, trace: Optional[Trace] = None, theta_logit=None,
-                    returns: bool = False):
+                    returns: bool = False, confirm: bool = True):
     """Returns (membership, l_i, dQ per counted iteration, movers per counted
     iteration, counters dict)."""
     g = CSR.of(g)
@@ -414,7 +415,7 @@ def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, mem
     tl = theta_logit if theta_logit is not None else logit_of(theta)
     li = _load().orc_move_sync_gated(*g.args(), M2, _p(K), _p(m), tau, max_iter, rounds, _p(p), tl, pass_index,
                                      ctypes.byref(trace.c) if trace is not None else None, _p(dq), _p(mv), _p(c4),
-                                     int(returns))
+                                     int(returns), int(confirm))
     if li < 0:
         raise ValueError("orc_move_sync_gated failed")
     cnt = dict(scanned_vertices=int(c4[0]), scanned_entries=int(c4[1]), pruned=int(c4[2]), confirm_sweeps=int(c4[3]))
@@ -424,7 +425,8 @@ def move_sync_gated(g, params=None, theta: float = 0.5, pass_index: int = 0, mem
 def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: int = 20,
             tolerance_drop: float = 10.0, aggregation_tolerance: float = 0.8,
             sync: bool = False, rounds: int = 8, split_mode: int = 0, prune_params=None, theta: float = 0.5,
-            trace: Optional[Trace] = None, theta_logit=None, return_moves: bool = False) -> Result:
+            trace: Optional[Trace] = None, theta_logit=None, return_moves: bool = False,
+            confirm_final: bool = False) -> Result:
     """The whole method; split_mode 0 = every pass, 1 = after the last, 2 = none.
     prune_params / trace / return_moves need sync=True."""
     g = CSR.of(g)
@@ -432,7 +434,7 @@ def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: in
     tl = theta_logit if theta_logit is not None else logit_of(theta)
     opt = _Options(tolerance, max_passes, max_iterations, tolerance_drop, aggregation_tolerance,
                    int(sync), rounds, split_mode, _p(p), tl,
-                   ctypes.pointer(trace.c) if trace is not None else None, int(return_moves))
+                   ctypes.pointer(trace.c) if trace is not None else None, int(return_moves), int(confirm_final))
     st = _Stats()
     memb = np.empty(g.n, dtype=np.int32)
     passes = _load().orc_louvain(*g.args(), ctypes.byref(opt), _p(memb), ctypes.byref(st))
@@ -444,4 +446,5 @@ def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: in
     r.counters = dict(scanned_vertices=int(st.counters[0]), scanned_entries=int(st.counters[1]),
                       pruned=int(st.counters[2]), confirm_sweeps=int(st.counters[3]))
     r.tau = list(st.tau[:k])
+    r.final_iterations = int(st.final_iterations)
     return r

@@ -712,7 +712,7 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
             int64_t c4[4];
             li = orc_move_sync_gated(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds,
                                      opt->prune_params, opt->prune_theta_logit, lp, opt->trace, NULL, NULL, c4,
-                                     opt->return_moves);
+                                     opt->return_moves, !(opt->prune_params && opt->confirm_final));
             if (stats)
                 for (int q = 0; q < 4; q++) stats->counters[q] += c4[q];
         } else if (opt->sync_moves)
@@ -744,6 +744,32 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         double *tw = gw; gw = nw; nw = tw;
         gn = ng;
         tau = tau / opt->tolerance_drop;                               /* threshold scaling */
+    }
+    if (passes > 0 && opt->sync_moves && opt->prune_params && opt->confirm_final) {
+        /* the learned gate's confirmation, once per run: one plain
+         * local-moving phase (no gate, every vertex unprocessed) over G from
+         * the passes' result, with the last pass's tolerance; its first
+         * sweep is the final full plain sweep, and further plain sweeps
+         * follow while they gain more than tau.  Moves of single vertices
+         * can disconnect a community, so the split (split_mode 0) follows,
+         * then the renumbering. */
+        int64_t c4[4];
+        double *K0 = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        orc_vertex_weights(n, off, col, w, K0);
+        double tau_last = opt->tolerance;
+        for (int32_t k = 1; k < passes; k++) tau_last = tau_last / opt->tolerance_drop;
+        int32_t fi = orc_move_sync_gated(n, off, col, w, M2, K0, memb_out, tau_last, opt->max_iterations,
+                                         opt->sync_rounds, NULL, 0.0, passes, opt->trace, NULL, NULL, c4,
+                                         opt->return_moves, 1);
+        if (stats) {
+            stats->final_iterations = fi;
+            for (int q = 0; q < 4; q++) stats->counters[q] += c4[q];
+        }
+        if (opt->split_mode == 0) {
+            orc_split_bfs(n, off, col, memb_out, lab);
+            memcpy(memb_out, lab, (size_t)n * sizeof(int32_t));
+        }
+        free(K0);
     }
     if (passes >= 0 && opt->split_mode == 1) {                         /* split last */
         orc_split_bfs(n, off, col, memb_out, lab);

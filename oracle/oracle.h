@@ -157,7 +157,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
                             const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
                             const float *params, double theta_logit, int32_t pass, orc_trace *trace,
                             double *dq_iter, int64_t *moved_iter, int64_t *counters,
-                            int32_t returns);
+                            int32_t returns, int32_t confirm);
 
 typedef struct orc_options {
     double tolerance;              /* tau for the first pass */
@@ -172,6 +172,8 @@ typedef struct orc_options {
     double prune_theta_logit;      /* scan iff logit >= this */
     orc_trace *trace;              /* move traces (sync_moves = 1 only), may be NULL */
     int32_t return_moves;          /* sync_moves = 1: return moves add nothing to the gain total (option) */
+    int32_t confirm_final;         /* with prune_params: no confirming sweep per pass; after the passes one
+                                      plain local-moving phase over G from the result, then the split */
 } orc_options;
 
 typedef struct orc_stats {
@@ -182,6 +184,7 @@ typedef struct orc_stats {
     double modularity;
     int64_t counters[4];           /* gated phase: scanned vertices, scanned entries, pruned, confirming sweeps */
     double tau[64];                /* the iteration tolerance each pass ran with (threshold scaling) */
+    int32_t final_iterations;      /* confirm_final: iterations of the final plain phase over G */
 } orc_stats;
 
 /* The whole method (Algorithm "louvain").  memb_out[n] gets the top-level

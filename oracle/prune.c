@@ -395,11 +395,16 @@ static void trace_put(orc_trace *t, const float *x, uint8_t label, int64_t i, in
  * is the 0-based sweep index of the phase (confirming sweeps included).
  *
  * Counters (may be NULL): out[0] scanned vertices, out[1] scanned entries,
- * out[2] pruned vertices, out[3] confirming sweeps. */
+ * out[2] pruned vertices, out[3] confirming sweeps.
+ *
+ * confirm = 0 drops the confirming sweeps: the gated sweeps run until the
+ * usual test stops them (the whole run is then confirmed once, at its end:
+ * orc_louvain's final phase). */
 int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
                             const double *K, int32_t *memb, double tau, int32_t max_iter, int32_t rounds,
                             const float *params, double theta_logit, int32_t pass, orc_trace *trace,
-                            double *dq_iter, int64_t *moved_iter, int64_t *counters, int32_t returns) {
+                            double *dq_iter, int64_t *moved_iter, int64_t *counters, int32_t returns,
+                            int32_t confirm) {
     if (n < 0 || max_iter < 0 || rounds < 1 || rounds > 64 || (rounds & (rounds - 1))) return -1;
     for (int64_t i = 0; i < n; i++)
         if (memb[i] < 0 || memb[i] >= n) return -1;
@@ -441,7 +446,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
         /* the last iteration the phase may count is a confirming sweep: a
          * phase never ends on gated sweeps alone, so every vertex the gate
          * kept from its scans is judged by the plain method once more */
-        if (mode == GATED && li + 1 >= max_iter) mode = CONFIRM;
+        if (confirm && mode == GATED && li + 1 >= max_iter) mode = CONFIRM;
         if (mode == CONFIRM) {
             memset(unproc, 1, N);
             cnt[3]++;
@@ -526,7 +531,7 @@ int32_t orc_move_sync_gated(int64_t n, const int64_t *off, const int32_t *col, c
             li++;
         }
         if (dq <= tau) {
-            if (mode == GATED) { mode = CONFIRM; continue; }
+            if (mode == GATED && confirm) { mode = CONFIRM; continue; }
             break;
         }
         if (mode == CONFIRM) mode = PLAIN;

@@ -265,3 +265,36 @@ def test_gated_phase_ends_with_a_confirming_sweep(max_iter):
     np.testing.assert_array_equal(got, m2)
     assert cnt["confirm_sweeps"] == 1
     assert gli == li0 + (1 if mv1[0] > 0 else 0)
+
+
+# ---------------------------------------------------------------- gate confirmed once per run
+
+def test_final_confirmation_replays_its_steps():
+    """confirm_final: gated passes without confirming sweeps, then one plain
+    local-moving phase over G from their result (tolerance of the last
+    pass), then the split and the canonical numbering."""
+    from test_oracle_prune import _rand_params
+    g = gi.dcsbm_small(6000, 11)
+    p = _rand_params(21)
+    p[-65:-1] *= 16.0
+    p[-1] = -8.0                                      # prunes a part of the vertices
+    r = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, prune_params=p, confirm_final=True)
+    assert r.counters["pruned"] > 0 and r.final_iterations >= 1
+    # replay: the same passes (gated sweeps, no confirmation) ...
+    top = np.arange(g.n, dtype=np.int32)
+    level = oracle.CSR.of(g)
+    tau = 1e-2
+    for lp in range(r.passes):
+        memb, li, _, _, _ = oracle.move_sync_gated(level, p, pass_index=lp, tau=tau, confirm=False)
+        assert li == r.iterations[lp]
+        cm, ncomm = oracle.renumber(oracle.split_bfs(level, memb))
+        top = cm[top]
+        if lp < r.passes - 1:
+            level = oracle.aggregate(level, cm, ncomm)
+            tau /= 10.0
+    # ... then the plain phase over G and the split
+    m, fi, _, _, _ = oracle.move_sync_gated(g, None, pass_index=r.passes, memb=top, tau=tau)
+    assert fi == r.final_iterations
+    m = oracle.split_bfs(g, m)
+    np.testing.assert_array_equal(r.membership, _canonical(m))
+    assert oracle.disconnected(g, r.membership)[0] == 0
