@@ -51,6 +51,8 @@ def _load():
     lib.gen_rmat.argtypes = [i32, i64, dbl, dbl, dbl, u64, i32, i32, dbl, dbl]
     lib.gen_dcsbm.restype = vp
     lib.gen_dcsbm.argtypes = [i64, dbl, i64, i64, dbl, i64, i64, dbl, u64, i32, i32, dbl, dbl]
+    lib.gen_road.restype = vp
+    lib.gen_road.argtypes = [i64, dbl, i32, u64, i32]
     lib.gen_from_edges.restype = vp
     lib.gen_from_edges.argtypes = [i64, i64, vp, vp]
     lib.gen_free.argtypes = [vp]
@@ -140,6 +142,13 @@ def dcsbm(n: int, deg_alpha: float, kmin: int, kmax: int, size_alpha: float, smi
     h = _load().gen_dcsbm(n, deg_alpha, kmin, kmax, size_alpha, smin, smax, mu, seed, int(permute),
                           int(weights is not None), lo, hi)
     return _take(h, name)
+
+
+def road(side: int, keep: float, max_inner: int, seed: int, permute: bool = True, name: str = "road") -> Graph:
+    """Road-like graph: a side x side lattice of intersections, each lattice
+    edge kept with probability `keep` and subdivided into a chain of 0 ..
+    max_inner degree-2 vertices (see gen.c); unit weights."""
+    return _take(_load().gen_road(side, keep, max_inner, seed, int(permute)), name)
 
 
 def from_edges(n: int, edges, weights=None, name: str = "edges") -> Graph:
@@ -241,6 +250,19 @@ def dcsbm_4m(seed: int, n: int = 4_000_000) -> Graph:
 def dcsbm_small(n: int, seed: int, mu: float = 0.3, kmax: int = 500, smax: int = 2000) -> Graph:
     """Smaller graph of the same law (tests, quick training)."""
     return dcsbm(n, 2.5, 5, kmax, 1.5, 20, smax, mu, seed, name=f"dcsbm-{n}-s{seed}")
+
+
+def road_network(seed: int = 7, side: int = 3000) -> Graph:
+    """The low-degree, high-diameter workload (the road / k-mer class of the
+    paper's graphs, average degree about 2.1): a 3000 x 3000 lattice of
+    intersections, 70 % of its edges kept, each subdivided into 0 .. 8
+    degree-2 vertices: about 34 M vertices, 37 M undirected edges."""
+    return road(side, 0.7, 8, seed, name=f"road-{side}-s{seed}")
+
+
+def road_small(side: int, seed: int) -> Graph:
+    """Smaller graph of the same law, for parity tests."""
+    return road(side, 0.7, 8, seed, name=f"road-{side}-s{seed}")
 
 
 def batch_sbm_params(count: int, master_seed: int = 4):

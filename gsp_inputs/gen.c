@@ -564,6 +564,53 @@ gen_graph *gen_dcsbm(int64_t n, double deg_alpha, int64_t kmin, int64_t kmax, do
     return g;
 }
 
+/* Road-like graph (the low-degree, high-diameter class of road networks
+ * and k-mer graphs): a side x side lattice of intersections; each of its
+ * 2 side (side - 1) lattice edges is kept with probability `keep` and, when
+ * kept, subdivided into a chain with a uniform number of inner vertices in
+ * [0, max_inner] (degree-2 vertices, like the road segments between
+ * junctions).  Vertex ids: intersections first, then the chains' inner
+ * vertices in edge order, then (permute) a random relabelling.  The
+ * average degree is 2 E / n, close to 2 when chains are long.  Lattice
+ * edges are visited in a fixed order from one xoshiro stream, so the graph
+ * depends on the seed only. */
+gen_graph *gen_road(int64_t side, double keep, int max_inner, uint64_t seed, int permute) {
+    if (side < 2 || max_inner < 0 || !(keep >= 0.0 && keep <= 1.0)) return NULL;
+    int64_t ni = side * side;
+    xoshiro r;
+    xo_seed(&r, seed);
+    edge_list el = {0, 0, NULL, NULL};
+    int64_t next = ni;
+    for (int64_t y = 0; y < side; y++)
+        for (int64_t x = 0; x < side; x++)
+            for (int dir = 0; dir < 2; dir++) {
+                int64_t x2 = x + (dir == 0), y2 = y + (dir == 1);
+                if (x2 >= side || y2 >= side) continue;
+                double u = xo_uniform(&r);
+                int inner = (int)(xo_uniform(&r) * (double)(max_inner + 1));
+                if (inner > max_inner) inner = max_inner;
+                if (u >= keep) continue;
+                if (next + inner > 0x7ffffffe) { el_free(&el); return NULL; }
+                int64_t prev = y * side + x;
+                for (int k = 0; k < inner; k++) {
+                    if (el_push(&el, (int32_t)prev, (int32_t)next)) { el_free(&el); return NULL; }
+                    prev = next++;
+                }
+                if (el_push(&el, (int32_t)prev, (int32_t)(y2 * side + x2))) { el_free(&el); return NULL; }
+            }
+    int64_t n = next;
+    progress("road: chains drawn", el.len);
+    if (permute) {
+        int32_t *perm = random_perm(n, seed);
+        if (!perm) { el_free(&el); return NULL; }
+        for (int64_t e = 0; e < el.len; e++) { el.u[e] = perm[el.u[e]]; el.v[e] = perm[el.v[e]]; }
+        free(perm);
+    }
+    gen_graph *g = build_csr(n, el.len, el.u, el.v);
+    el_free(&el);
+    return g;
+}
+
 /* Graph from a caller's undirected edge list (used by hand-built test
  * graphs): symmetrised, deduplicated, self-loops dropped. */
 gen_graph *gen_from_edges(int64_t n, int64_t m, const int32_t *eu, const int32_t *ev) {

@@ -83,7 +83,14 @@ typedef struct gsp_options {
                                       into the community the vertex left at its move of the preceding sweep
                                       is made but adds nothing, so swap cycles of synchronous moves do not
                                       hold a pass at max_iterations */
+    int32_t split_algo;            /* how the split (Section 4.1) finds the components: GSP_SPLIT_UF
+                                      (default: concurrent union-find) or GSP_SPLIT_LPP (minimum-label
+                                      propagation with pruning, Algorithm splitDisconnectedLp, plus pointer
+                                      jumping); both give the same labels */
 } gsp_options;
+
+/* split_algo values. */
+enum { GSP_SPLIT_UF = 0, GSP_SPLIT_LPP = 1 };
 
 /* Vertex pruning of the local-moving phase (prune_mode). */
 enum { GSP_PRUNE_PLAIN = 0, GSP_PRUNE_LEARNED = 1 };
@@ -125,6 +132,7 @@ typedef struct gsp_stats {
     int64_t pruned;                            /* unprocessed vertices the learned gate kept from the scan */
     int32_t confirm_sweeps;                    /* confirming plain sweeps run after gated convergence */
     int32_t sweeps;                            /* local-moving sweeps run, all passes (counted or not) */
+    int32_t split_rounds;                      /* split_algo = GSP_SPLIT_LPP: propagation rounds, all splits */
 } gsp_stats;
 
 /* Fills *out with the defaults above. */
@@ -258,6 +266,12 @@ gsp_status gsp_move_phase(gsp_ctx *ctx, int32_t *membership_inout, int where, do
  * = smallest vertex id of i's connected component in the subgraph of edges
  * whose ends share a community. */
 gsp_status gsp_step_split(gsp_ctx *ctx, const int32_t *membership, int where, int32_t *labels_out);
+
+/* The same split by minimum-label propagation with pruning (Algorithm
+ * "splitDisconnectedLp" with its pruning, plus pointer jumping: see
+ * split_algo); *rounds (may be NULL) receives the propagation rounds. */
+gsp_status gsp_step_split_lp(gsp_ctx *ctx, const int32_t *membership, int where, int32_t *labels_out,
+                             int32_t *rounds);
 
 /* Aggregation (Algorithm "louvainAggregate") of the loaded graph by
  * `membership` after renumbering its labels in ascending order: super-vertex

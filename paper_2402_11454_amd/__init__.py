@@ -27,6 +27,7 @@ MAX_PASSES_STATS = 64
 KERNEL_CLASSES = ("move_small", "move_wave", "move_block", "move_hub", "move_hub_finish", "move_apply", "frontier",
                   "split", "aggregate", "gate", "move_hub_gather")
 PRUNE_PLAIN, PRUNE_LEARNED = 0, 1
+SPLIT_UF, SPLIT_LPP = 0, 1
 GATE_PARAMS = 4801  # (8*64 + 64) + (64*64 + 64) + (64 + 1)
 
 _STATUS = {GSP_EINVAL: "GSP_EINVAL", GSP_ENOMEM: "GSP_ENOMEM", GSP_EHIP: "GSP_EHIP",
@@ -46,7 +47,8 @@ class Options(ctypes.Structure):
                 ("mem_limit_bytes", ctypes.c_uint64), ("prune_mode", ctypes.c_int32),
                 ("prune_threshold", ctypes.c_float), ("use_graphs", ctypes.c_int32),
                 ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32),
-                ("hub_max_parts", ctypes.c_int32), ("return_moves", ctypes.c_int32)]
+                ("hub_max_parts", ctypes.c_int32), ("return_moves", ctypes.c_int32),
+                ("split_algo", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -63,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("ms_other", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("kernels", KernelStat * len(KERNEL_CLASSES)),
                 ("scanned_vertices", ctypes.c_int64), ("pruned", ctypes.c_int64),
-                ("confirm_sweeps", ctypes.c_int32), ("sweeps", ctypes.c_int32)]
+                ("confirm_sweeps", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("split_rounds", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         k = self.passes
@@ -72,7 +75,7 @@ class Stats(ctypes.Structure):
                     scanned_entries=self.scanned_entries, ms_move=self.ms_move, ms_split=self.ms_split,
                     ms_aggregate=self.ms_aggregate, ms_other=self.ms_other, ms_total=self.ms_total,
                     scanned_vertices=self.scanned_vertices, pruned=self.pruned,
-                    confirm_sweeps=self.confirm_sweeps, sweeps=self.sweeps,
+                    confirm_sweeps=self.confirm_sweeps, sweeps=self.sweeps, split_rounds=self.split_rounds,
                     kernels={name: dict(launches=s.launches, ms=s.ms, bytes=s.bytes, items=s.items)
                              for name, s in zip(KERNEL_CLASSES, self.kernels)})
 
@@ -122,6 +125,7 @@ def lib():
         "gsp_get_traces": [vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.c_int],
         "gsp_get_weight_grid": [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "gsp_count_disconnected_noalloc": [i64, i64, vp, vp, vp, vp, vp],
+        "gsp_step_split_lp": [vp, vp, ctypes.c_int, vp, ctypes.POINTER(i32)],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -476,6 +480,14 @@ class Context:
         po, _, _ = _ptr(out, np.int32)
         self._check(lib().gsp_step_split(self._h, p, w, po), "gsp_step_split")
         return out
+
+    def step_split_lp(self, membership):
+        """The split by label propagation; returns (labels, rounds)."""
+        p, w, keep = _ptr(membership, np.int32)
+        lab = np.empty(self.n, dtype=np.int32)
+        r = ctypes.c_int32()
+        self._check(lib().gsp_step_split_lp(self._h, p, w, lab.ctypes.data, ctypes.byref(r)), "gsp_step_split_lp")
+        return lab, r.value
 
     def step_aggregate(self, membership):
         """Returns (n2, offsets int64, cols int32, weights fp64) on the host."""

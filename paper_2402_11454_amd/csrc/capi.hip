@@ -119,6 +119,7 @@ struct gsp_ctx {
     // 2^-grid_S; grid_moved weights were rounded onto it at load
     int32_t grid_S = 0;
     int64_t grid_moved = 0;
+    int *lp_counts = nullptr;   // queue sizes of the label-propagation split (4 ints)
 
     // super-vertex levels (ping-pong) and the gapped aggregation rows
     int64_t *offL[2] = {nullptr, nullptr};
@@ -241,6 +242,7 @@ struct gsp_ctx {
         }
         gap_col = nullptr;
         gap_w = nullptr;
+        lp_counts = nullptr;
         mhist = iter_dev = nullptr;
         ctr = nullptr;
         hfrac = hgain = nullptr;
@@ -1003,6 +1005,7 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     if ((st = A(sc.part_kid, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
     if ((st = A(sc.part_c, sc.ch_cap, "hipMalloc(hub partials)")) != GSP_OK) return st;
     if ((st = A(ctx->ctr, 2, "hipMalloc(iteration counters)")) != GSP_OK) return st;
+    if ((st = A(ctx->lp_counts, 4, "hipMalloc(split counters)")) != GSP_OK) return st;
 
     // copy in
     hipMemcpyKind kind = where == GSP_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1111,6 +1114,8 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
         return ctx->fail(GSP_EINVAL, "bad prune_mode");
     if (opt.timing < 0 || opt.timing > 3) return ctx->fail(GSP_EINVAL, "timing must lie in [0, 3]");
     if (opt.return_moves != 0 && opt.return_moves != 1) return ctx->fail(GSP_EINVAL, "return_moves must be 0 or 1");
+    if (opt.split_algo != GSP_SPLIT_UF && opt.split_algo != GSP_SPLIT_LPP)
+        return ctx->fail(GSP_EINVAL, "split_algo must be GSP_SPLIT_UF or GSP_SPLIT_LPP");
     if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
         return ctx->fail(GSP_EINVAL, "hub_max_parts must lie in [0, 4096]");
     if (opt.prune_mode == GSP_PRUNE_LEARNED) {
@@ -1146,6 +1151,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->hub_global = 0;
     out->hub_max_parts = 0;
     out->return_moves = 0;
+    out->split_algo = GSP_SPLIT_UF;
     return GSP_OK;
 }
 
@@ -1229,6 +1235,23 @@ gsp_status gsp_load_csr_f64(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t 
 }  // extern "C"
 
 namespace {
+
+// The split of level g by membership cm into labels: union-find, or
+// minimum-label propagation (split_algo).  *rounds += the propagation rounds.
+gsp_status run_split(gsp_ctx *ctx, const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels,
+                     int algo, int32_t *rounds) {
+    hipStream_t s = ctx->stream;
+    if (algo == GSP_SPLIT_LPP) {
+        int r = launch_split_lp(g, cm, labels, ctx->sc.u8a, ctx->sc.i32d, ctx->sc.i32e, ctx->lp_counts,
+                                reinterpret_cast<int *>(ctx->i64_h + 12), s);
+        if (r < 0) return ctx->fail_hip(hipGetLastError(), "split by label propagation");
+        if (rounds) *rounds += r;
+        return GSP_OK;
+    }
+    launch_split(g, wl, cm, labels, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
+                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
+    return GSP_OK;
+}
 
 // Algorithm "louvain" on the loaded graph, or on the loaded batch of graphs
 // (batch = true): then every graph keeps its own 2m, convergence tests,
@@ -1335,8 +1358,8 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         if (opt.split_mode == GSP_SPLIT_PASS) {
             t = tphase ? ctx->timer.begin(PH_SPLIT) : -1;
             int tk1 = tk ? ctx->timer.begin(100 + GSP_K_SPLIT) : -1;
-            launch_split(g, wl, ctx->cm, ctx->lab, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
-                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
+            st = run_split(ctx, g, wl, ctx->cm, ctx->lab, opt.split_algo, &ctx->stats.split_rounds);
+            if (st != GSP_OK) return st;
             ctx->timer.end(tk1);
             if (tk) ctx->kernel_launches[GSP_K_SPLIT] += 6;
             // one pass over the level: column + membership of both ends per
@@ -1422,8 +1445,8 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         Level g0 = level0(ctx);
         WorkLists wl = make_lists(ctx);
         HIP_TRY(build_work_lists(g0, 1, wl, ctx->sc, s));
-        launch_split(g0, wl, ctx->top, ctx->lab, ctx->sc.i32c, reinterpret_cast<uint32_t *>(ctx->sc.i32a),
-                 reinterpret_cast<unsigned long long *>(ctx->sc.i64a), s);
+        st = run_split(ctx, g0, wl, ctx->top, ctx->lab, opt.split_algo, &ctx->stats.split_rounds);
+        if (st != GSP_OK) return st;
         HIP_TRY(hipMemcpyAsync(ctx->top, ctx->lab, ctx->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     if (opt.split_mode != GSP_SPLIT_PASS && ctx->n > 0) {
@@ -2207,6 +2230,26 @@ gsp_status gsp_step_split(gsp_ctx *ctx, const int32_t *membership, int where, in
     st = copy_out(ctx, labels_out, ctx->lab, g.n, where);
     if (st != GSP_OK) return st;
     HIP_TRY(hipStreamSynchronize(s));
+    return GSP_OK;
+}
+
+gsp_status gsp_step_split_lp(gsp_ctx *ctx, const int32_t *membership, int where, int32_t *labels_out,
+                             int32_t *rounds) {
+    if (!ctx) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (!labels_out && ctx->n) return ctx->fail(GSP_EINVAL, "labels_out is NULL");
+    gsp_status st = take_membership(ctx, membership, where);
+    if (st != GSP_OK) return st;
+    Level g = level0(ctx);
+    WorkLists wl = make_lists(ctx);
+    int32_t r = 0;
+    st = run_split(ctx, g, wl, ctx->cm, ctx->lab, GSP_SPLIT_LPP, &r);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipGetLastError());
+    st = copy_out(ctx, labels_out, ctx->lab, g.n, where);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (rounds) *rounds = r;
     return GSP_OK;
 }
 

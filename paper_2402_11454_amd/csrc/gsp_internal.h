@@ -287,6 +287,13 @@ void launch_batch_flag_confirm(const int32_t *gid, const uint8_t *gconfirm, int6
 // community and its vote)
 void launch_split(const Level &g, const WorkLists &wl, const int32_t *cm, int32_t *labels, int32_t *dom,
                   uint32_t *vote_cnt, unsigned long long *vote_best, hipStream_t s);
+// The same labels by minimum-label propagation with pruning (Algorithm
+// splitDisconnectedLp with its pruning) and pointer jumping: next (n flags,
+// zero on return), q_small / q_large (n each) the rounds' queues, counts (4
+// ints, device) and counts_h (2 ints, pinned host) their sizes.  Returns the
+// number of rounds (one host read per round), -1 on a HIP error.
+int launch_split_lp(const Level &g, const int32_t *cm, int32_t *labels, uint8_t *next, int32_t *q_small,
+                    int32_t *q_large, int *counts, int *counts_h, hipStream_t s);
 // Renumber labels (values in [0, n)) by ascending label: flag[l] = label l
 // in use, rank = exclusive scan of flag, out[i] = rank[labels[i]], *count =
 // number of labels in use.  flag/rank are n+1-sized temps.

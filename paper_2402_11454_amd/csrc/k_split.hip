@@ -290,6 +290,102 @@ __global__ void __launch_bounds__(kBlock) k_gather(const int32_t *tab, const int
         out[v] = tab[idx[v]];
 }
 
+// ---- split by minimum-label propagation with pruning (LPP) ----
+//
+// Algorithm "splitDisconnectedLp" with its pruning: labels start as the
+// vertex ids, and a vertex whose label dropped pushes it to its neighbours
+// in the same community, which become active when theirs drops in turn;
+// at the fixed point every label is the smallest id of its component (the
+// same labels as the BFS and union-find).  A round is one push from every
+// active vertex (all of them in the first round), then a pointer jump
+// lab[i] <- lab[lab[i]] for the vertices that changed: a label is always the
+// id of a vertex of the same component (a push copies one along a
+// same-community edge, a jump copies the label of such a vertex), so the
+// jump keeps that and shortens long chains (road-like graphs) from their
+// diameter to far fewer rounds.  Active vertices are queued in two lists:
+// rows of at most kLpThreadDeg entries are pushed by one thread, longer rows
+// by a wavefront (a hub's row is long but rare).
+
+constexpr int kLpThreadDeg = 32;
+
+// Round r: push from the queued vertices.  lab_now is read and lowered with
+// atomicMin; a neighbour whose label dropped is flagged (next[j] = 1).
+__global__ void __launch_bounds__(kBlock) k_lp_push(Level g, const int32_t *cm, int32_t *lab, const int32_t *q_small,
+                                                   const int *n_small, const int32_t *q_large, const int *n_large,
+                                                   uint8_t *next) {
+    const int ns = *n_small, nl = *n_large;
+    const int64_t nthr = (int64_t)gridDim.x * kBlock;
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < ns; t += nthr) {
+        const int i = q_small[t];
+        const int li = ld(lab + i), ci = cm[i];
+        const int64_t b = g.off[i], e = b + g.deg[i];
+        for (int64_t k = b; k < e; k++) {
+            const int j = g.col[k];
+            if (j == i || cm[j] != ci) continue;
+            if (ld(lab + j) > li && atomicMin(lab + j, li) > li) next[j] = 1;
+        }
+    }
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; t < nl; t += nw) {
+        const int i = q_large[t];
+        const int li = ld(lab + i), ci = cm[i];
+        const int64_t b = g.off[i], e = b + g.deg[i];
+        for (int64_t k = b + lane_id(); k < e; k += kWave) {
+            const int j = g.col[k];
+            if (j == i || cm[j] != ci) continue;
+            if (ld(lab + j) > li && atomicMin(lab + j, li) > li) next[j] = 1;
+        }
+    }
+}
+
+// After a round: every flagged vertex jumps (lab[i] <- lab[lab[i]] while that
+// is smaller) and is queued for the next round; flags cleared.
+__global__ void __launch_bounds__(kBlock) k_lp_collect(const int32_t *deg, int64_t n, int32_t *lab, uint8_t *next,
+                                                      int32_t *q_small, int *n_small, int32_t *q_large,
+                                                      int *n_large) {
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < n; i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        bool act = false;
+        int d = 0;
+        if (i < n && next[i]) {
+            next[i] = 0;
+            int l = ld(lab + i);
+            int l2 = ld(lab + l);
+            while (l2 < l) {   // labels only decrease: the walk ends
+                l = l2;
+                l2 = ld(lab + l);
+            }
+            atomicMin(lab + i, l);
+            d = deg[i];
+            act = d > 0;
+        }
+        const bool small = act && d <= kLpThreadDeg, large = act && d > kLpThreadDeg;
+        const int ps = wave_append(small, n_small);
+        const int pl = wave_append(large, n_large);
+        if (small) q_small[ps] = (int32_t)i;
+        if (large) q_large[pl] = (int32_t)i;
+    }
+}
+
+// First round's queues: every vertex with a non-empty row.
+__global__ void __launch_bounds__(kBlock) k_lp_init(const int32_t *deg, int64_t n, int32_t *lab, uint8_t *next,
+                                                   int32_t *q_small, int *n_small, int32_t *q_large, int *n_large) {
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock; i0 < n; i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        int d = 0;
+        if (i < n) {
+            lab[i] = (int32_t)i;
+            next[i] = 0;
+            d = deg[i];
+        }
+        const bool small = i < n && d > 0 && d <= kLpThreadDeg, large = i < n && d > kLpThreadDeg;
+        const int ps = wave_append(small, n_small);
+        const int pl = wave_append(large, n_large);
+        if (small) q_small[ps] = (int32_t)i;
+        if (large) q_large[pl] = (int32_t)i;
+    }
+}
+
 // ---- the context-free disconnected count (caller's CSR, fixed scratch) ----
 //
 // flags[0]: communities with more than one component; flags[1]: nonzero if
@@ -399,6 +495,32 @@ void launch_count_disconnected(const int32_t *labels, const int32_t *memb, int64
     launch_fill_i32(roots_per_comm, 0, n, s);
     k_roots_per_comm<<<grid1(n), kBlock, 0, s>>>(labels, memb, n, roots_per_comm);
     k_count_gt1<<<grid1(n), kBlock, 0, s>>>(roots_per_comm, n, out);
+}
+
+int launch_split_lp(const Level &g, const int32_t *cm, int32_t *labels, uint8_t *next, int32_t *q_small,
+                    int32_t *q_large, int *counts, int *counts_h, hipStream_t s) {
+    if (g.n == 0) return 0;
+    const unsigned gn = grid1(g.n);
+    launch_fill_i32(counts, 0, 4, s);
+    k_lp_init<<<gn, kBlock, 0, s>>>(g.deg, g.n, labels, next, q_small, counts, q_large, counts + 1);
+    int rounds = 0;
+    for (int cur = 0;; cur ^= 1) {
+        // queues of this round: counts[2 cur], counts[2 cur + 1]; the next
+        // round's counters are cleared before its collection
+        if (hipMemcpyAsync(counts_h, counts + 2 * cur, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return -1;
+        const int ns = counts_h[0], nl = counts_h[1];
+        if (ns + nl == 0) break;
+        rounds++;
+        const int64_t units = std::max<int64_t>((ns + kBlock - 1) / kBlock, (nl + 3) / 4);
+        k_lp_push<<<(unsigned)std::min<int64_t>(std::max<int64_t>(units, 1), 65536), kBlock, 0, s>>>(
+            g, cm, labels, q_small, counts + 2 * cur, q_large + 0, counts + 2 * cur + 1, next);
+        launch_fill_i32(counts + 2 * (cur ^ 1), 0, 2, s);
+        k_lp_collect<<<gn, kBlock, 0, s>>>(g.deg, g.n, labels, next, q_small, counts + 2 * (cur ^ 1), q_large,
+                                           counts + 2 * (cur ^ 1) + 1);
+    }
+    return rounds;
 }
 
 void launch_count_disconnected_csr(const int64_t *off, const int32_t *col, int64_t n, int64_t nnz,

@@ -49,6 +49,7 @@ GRAPHS = {
     "rmat13w": lambda: gi.rmat_small(13, 5, weights=(1.0, 4.0)),
     "rmat15": lambda: gi.rmat_small(15, 3),
     "sbm_w10": lambda: gi.sbm(4000, 25, 0.08, 0.002, 9, weights=(1.0, 10.0)),
+    "road60": lambda: gi.road_small(60, 3),
 }
 
 _cache = {}
@@ -104,6 +105,32 @@ def test_split_bit_exact(ctx, name):
     for m in _memberships(g.n, 21):
         lab = ctx.step_split(m)
         np.testing.assert_array_equal(lab, oracle.split_bfs(g, m))
+
+
+@pytest.mark.parametrize("name", ALL)
+def test_split_lp_bit_exact(ctx, name):
+    """The split by label propagation (LPP with pointer jumping) gives the
+    labels of the oracle's one-thread LPP (Algorithm splitDisconnectedLp)."""
+    g = _graph(name)
+    _load(ctx, g)
+    for m in _memberships(g.n, 23):
+        lab, rounds = ctx.step_split_lp(m)
+        ref, sweeps = oracle.split_lp(g, m, pruned=True)
+        np.testing.assert_array_equal(lab, ref)
+        assert rounds >= 1
+
+
+@pytest.mark.parametrize("name", ["rmat15", "road300", "rmat13w"])
+def test_split_algorithms_give_the_same_runs(ctx, name):
+    g = gi.road_small(300, 3) if name == "road300" else _graph(name)
+    _load(ctx, g)
+    a = ctx.louvain(tolerance=1e-2, max_passes=10)
+    b = ctx.louvain(tolerance=1e-2, max_passes=10, split_algo=gsp.SPLIT_LPP)
+    np.testing.assert_array_equal(a.membership, b.membership)
+    assert a.stats["iterations"] == b.stats["iterations"] and b.stats["split_rounds"] > 0
+    c = ctx.louvain(tolerance=1e-2, max_passes=10, split_algo=gsp.SPLIT_LPP, split_mode=gsp.SPLIT_LAST)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, split_mode=gsp.SPLIT_LAST)
+    np.testing.assert_array_equal(c.membership, ref.membership)
 
 
 @pytest.mark.parametrize("name", ALL)
@@ -233,6 +260,24 @@ def test_random_graphs_match_oracle(ctx, seed):
     assert res.stats["communities"] == ref.communities
     assert abs(res.modularity - ref.modularity) <= 1e-9
     assert ctx.count_disconnected(res.membership) == 0
+
+
+@pytest.mark.parametrize("returns", [0, 1])
+def test_road_network_runs(ctx, returns):
+    """The low-degree, high-diameter class (road / k-mer graphs, average
+    degree about 2.1): 594 K vertices whose communities are long chains and
+    grids, many passes; whole runs equal to the oracle's, with and without
+    the return-move option."""
+    g = gi.road_small(300, 3)
+    _load(ctx, g)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, return_moves=returns)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, return_moves=bool(returns))
+    np.testing.assert_array_equal(res.membership, ref.membership)
+    assert res.stats["iterations"] == ref.iterations
+    assert res.stats["communities"] == ref.communities
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+    assert res.stats["passes"] >= 6
 
 
 def test_run_rmat20_full_size(ctx):

@@ -26,6 +26,7 @@ def _check_csr(g):
     lambda: gi.rmat_small(12, 2, weights=(1.0, 10.0)),
     lambda: gi.sbm(3000, 7, 0.05, 0.001, 5, weights=(1.0, 4.0)),
     lambda: gi.dcsbm_small(5000, 3),
+    lambda: gi.road_small(80, 5),
 ])
 def test_valid_and_deterministic(make):
     a, b = make(), make()
@@ -97,3 +98,18 @@ def test_batch_sbm_shape():
             assert abs(inter - p["mixing"]) < 0.06
     gs2 = gi.batch_sbm(40, master_seed=4, scale=0.1)
     assert all(np.array_equal(a.cols, b.cols) for a, b in zip(gs, gs2))
+
+
+def test_road_shape():
+    """The road-like law: degrees at most 4 (lattice junctions), mostly 2
+    (chain vertices), average degree near the paper's road and k-mer graphs
+    (about 2.1); the lattice edges kept and the chain lengths follow the
+    parameters."""
+    g = gi.road(200, 0.7, 8, 11, permute=False)
+    d = g.degrees()
+    assert d.max() <= 4 and 2.05 < g.nnz / g.n < 2.2
+    assert np.mean(d == 2) > 0.85
+    kept = 2 * 200 * 199 * 0.7
+    inner = g.n - 200 * 200
+    assert abs(inner / kept - 4.0) < 0.1                   # mean chain length (0..8 uniform)
+    assert abs((g.nnz // 2 - inner) / kept - 1.0) < 0.02   # edges = kept lattice edges + inner vertices
