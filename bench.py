@@ -79,7 +79,7 @@ def parse():
     p.add_argument("--timing", type=int, default=2, choices=(2, 3),
                    help="2: events with a sub-round's scans one after another; 3: events on each kernel's own "
                         "stream, scans side by side")
-    p.add_argument("--cpu-sample", type=int, default=16, help="the CPU baseline scans every k-th vertex")
+    p.add_argument("--cpu-sample", type=int, default=4, help="the CPU baseline scans every k-th vertex")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-untimed", action="store_true", help="skip the runs without events")
     return p.parse_args()

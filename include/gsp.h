@@ -87,6 +87,9 @@ typedef struct gsp_options {
                                       (default: concurrent union-find) or GSP_SPLIT_LPP (minimum-label
                                       propagation with pruning, Algorithm splitDisconnectedLp, plus pointer
                                       jumping); both give the same labels */
+    int32_t grid_cap;              /* launch schedule: the local-moving scans and apply take at most this many
+                                      workgroups each (0, the default: each kernel's own cap, 2048-8192);
+                                      results do not depend on it */
 } gsp_options;
 
 /* split_algo values. */

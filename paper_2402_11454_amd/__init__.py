@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("prune_threshold", ctypes.c_float), ("use_graphs", ctypes.c_int32),
                 ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32),
                 ("hub_max_parts", ctypes.c_int32), ("return_moves", ctypes.c_int32),
-                ("split_algo", ctypes.c_int32)]
+                ("split_algo", ctypes.c_int32), ("grid_cap", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

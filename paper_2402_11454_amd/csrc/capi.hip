@@ -417,6 +417,7 @@ struct PhaseCfg {
     bool return_moves = false;  // return moves add nothing to the gain totals
     bool gated = false;            // learned gate in front of the scan
     bool use_graphs = false;       // replay plain sweeps from a captured graph
+    int grid_cap = 0;              // launch schedule (MoveArgs::grid_cap)
     float theta_logit = 0.0f;      // scan iff logit >= theta_logit
     int pass = 0;                  // pass index (a feature, and trace rows)
     double *dq_out = nullptr;      // per counted iteration (max_iter entries)
@@ -584,6 +585,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.sval = ctx->gap_w;
             a.hbuck = ctx->sc.hbuck;
             a.hub_b0 = wl.hub_b0;
+            a.grid_cap = cfg.grid_cap;
             // the history feeds the gate's features: once a pass has left its
             // gated sweeps it never returns to them, so later sweeps skip it
             // (the history's per-entry adds to D_j cost most of it); trace
@@ -692,7 +694,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         auto ptr = [](const void *q) { return (int64_t)(intptr_t)q; };
         key = {g.n, g.nnz, g.wt, g.graphs, ptr(g.off), ptr(g.col), ptr(g.w), ptr(g.deg), ptr(g.gid), ptr(g.vbase),
-               ptr(K), P, ptr(wl.bl), ptr(wl.ch_vert), ptr(wl.ch_beg), ptr(wl.hub_off), ptr(ctx->sc.hkeys),
+               ptr(K), P, (int64_t)cfg.grid_cap, ptr(wl.bl), ptr(wl.ch_vert), ptr(wl.ch_beg), ptr(wl.hub_off), ptr(ctx->sc.hkeys),
                ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), ptr(ctx->sc.hbuck), (int64_t)(batch ? 1 : 0),
                ptr(ctx->ggated), ptr(ctx->giter)};
         for (int k = 0; k <= kNumBins * P; k++) key.push_back(wl.boff[k]);
@@ -1114,6 +1116,7 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
         return ctx->fail(GSP_EINVAL, "bad prune_mode");
     if (opt.timing < 0 || opt.timing > 3) return ctx->fail(GSP_EINVAL, "timing must lie in [0, 3]");
     if (opt.return_moves != 0 && opt.return_moves != 1) return ctx->fail(GSP_EINVAL, "return_moves must be 0 or 1");
+    if (opt.grid_cap < 0) return ctx->fail(GSP_EINVAL, "grid_cap must be >= 0");
     if (opt.split_algo != GSP_SPLIT_UF && opt.split_algo != GSP_SPLIT_LPP)
         return ctx->fail(GSP_EINVAL, "split_algo must be GSP_SPLIT_UF or GSP_SPLIT_LPP");
     if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
@@ -1339,6 +1342,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         pc.theta_logit = theta_logit(opt.prune_threshold);
         pc.pass = lp;
         pc.use_graphs = opt.use_graphs != 0;
+        pc.grid_cap = opt.grid_cap;
         pc.kernel_bytes = kbytes;
         if (batch) pc.gdone = gdone.data();
         st = move_phase(ctx, g, K, wl, pc);
@@ -1851,6 +1855,7 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
     pc.theta_logit = theta_logit(opt.prune_threshold);
     pc.pass = pass_index;
     pc.use_graphs = opt.use_graphs != 0;
+    pc.grid_cap = opt.grid_cap;
     pc.dq_out = dq.data();
     pc.moved_out = mv.data();
     st = move_phase(ctx, g, ctx->K0, wl, pc);

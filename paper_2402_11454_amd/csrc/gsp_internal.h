@@ -158,6 +158,10 @@ struct MoveArgs {
     const uint8_t *ggated = nullptr;
     const int32_t *giter = nullptr;
     TraceArgs tr;                               // tr.x == nullptr: no capture
+    // launch schedule: the scans' and apply's grids are at most grid_cap
+    // workgroups (0: each kernel's own cap); their loops stride over the
+    // grid, so any cap gives the same results
+    int grid_cap = 0;
     // batch of graphs (g.gid != nullptr): per-graph totals of the sweep and
     // the graphs still iterating
     unsigned long long *ggain = nullptr;        // per graph, units of gain_units

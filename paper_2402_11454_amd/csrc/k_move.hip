@@ -1173,6 +1173,9 @@ inline unsigned cap_grid(int64_t units, int64_t cap) {
     return (unsigned)(units < cap ? units : cap);
 }
 
+// A kernel's cap under the run's launch schedule.
+inline int64_t sched_cap(const MoveArgs &a, int64_t cap) { return a.grid_cap > 0 && a.grid_cap < cap ? a.grid_cap : cap; }
+
 }  // namespace
 
 void launch_community_totals(const double *K, const int32_t *cm, int64_t n, double *sig, int32_t *csize,
@@ -1203,7 +1206,7 @@ void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
         units += (a.qcap[b] + vpw - 1) / vpw;
     }
     if (units == 0) return;
-    unsigned gr = cap_grid((units + 3) / 4, 8192);
+    unsigned gr = cap_grid((units + 3) / 4, sched_cap(a, 8192));
     if (a.g.wt == W_UNIT)
         k_move_small<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1214,7 +1217,7 @@ void launch_move_small(const MoveArgs &a, const WorkLists &wl, hipStream_t s) {
 
 void launch_move_wave(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_WAVE] == 0) return;
-    unsigned gr = cap_grid((a.qcap[BIN_WAVE] + 3) / 4, 4096);
+    unsigned gr = cap_grid((a.qcap[BIN_WAVE] + 3) / 4, sched_cap(a, 4096));
     if (a.g.wt == W_UNIT)
         k_move_wave<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1225,7 +1228,7 @@ void launch_move_wave(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_block(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_BLOCK] == 0) return;
-    unsigned gr = cap_grid(a.qcap[BIN_BLOCK], 2048);
+    unsigned gr = cap_grid(a.qcap[BIN_BLOCK], sched_cap(a, 2048));
     if (a.g.wt == W_UNIT)
         k_move_block<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1247,7 +1250,7 @@ void launch_move_hub_scan(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_hub_parts(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    unsigned gr = cap_grid(a.ch_count, 4096);
+    unsigned gr = cap_grid(a.ch_count, sched_cap(a, 4096));
     if (a.g.wt == W_UNIT)
         k_hub_bucket<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1258,7 +1261,7 @@ void launch_move_hub_parts(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_hub_gather(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    unsigned gr = cap_grid(a.ch_count, 4096);
+    unsigned gr = cap_grid(a.ch_count, sched_cap(a, 4096));
     if (a.g.wt == W_UNIT)
         k_hub_gather<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else
@@ -1267,7 +1270,7 @@ void launch_move_hub_gather(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_hub_decide(const MoveArgs &a, hipStream_t s) {
     if (a.qcap[BIN_HUB] == 0) return;
-    unsigned gr = cap_grid(a.qcap[BIN_HUB], 2048);
+    unsigned gr = cap_grid(a.qcap[BIN_HUB], sched_cap(a, 2048));
     if (a.g.wt == W_UNIT)
         k_hub_decide<W_UNIT><<<gr, kBlock, 0, s>>>(a);
     else if (a.g.wt == W_F32)
@@ -1284,8 +1287,8 @@ void launch_move_hub_finish(const MoveArgs &a, hipStream_t s) {
 
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s) {
     if (cap == 0) return;
-    int nq = (int)cap_grid((cap + kBlock - 1) / kBlock, 2048);
-    int nh = a.qcap[BIN_HUB] ? (int)cap_grid(a.ch_count, 2048) : 0;
+    int nq = (int)cap_grid((cap + kBlock - 1) / kBlock, sched_cap(a, 2048));
+    int nh = a.qcap[BIN_HUB] ? (int)cap_grid(a.ch_count, sched_cap(a, 2048)) : 0;
     k_move_apply<<<nq + nh, kBlock, 0, s>>>(a, nq);
 }
 

@@ -157,19 +157,42 @@ __global__ void __launch_bounds__(kBlock) k_weights_to_f64(const float *in, doub
         out[i] = (double)in[i];
 }
 
-// One wavefront per row: K_i = sum of the row, *M2 += sum_i K_i.
+// K_i = sum of row i, *M2 += sum_i K_i.  A wavefront takes 64 consecutive
+// rows: each lane sums its own row if it has at most kShortRow entries (most
+// rows of sparse graphs), then the wavefront sums the longer ones together,
+// one at a time.  Sums of weights are exact (weight grid), so the order of
+// the additions does not matter.
+constexpr int kShortRow = 32;
+
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, double *M2) {
     __shared__ double part[kBlock / kWave];
-    int lane = lane_id(), w = threadIdx.x / kWave;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
     double blk = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + w; i < g.n; i += (int64_t)gridDim.x * (kBlock / kWave)) {
-        int64_t b = g.off[i], e = b + g.deg[i];   // rows may be gapped
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t r0 = (int64_t)blockIdx.x * kBlock + w * kWave; r0 < g.n; r0 += stride) {
+        const int64_t i = r0 + lane;
+        int64_t b = 0, d = 0;
+        if (i < g.n) {
+            b = g.off[i];
+            d = g.deg[i];   // rows may be gapped
+        }
         double s = 0.0;
-        for (int64_t k = b + lane; k < e; k += kWave) s += edge_weight<WT>(g.w, k);
-        s = group_sum<kWave>(s);
-        if (lane == 0) K[i] = s;
-        blk += s;
+        const bool shortrow = d <= kShortRow;
+        if (shortrow)
+            for (int64_t k = b; k < b + d; k++) s += edge_weight<WT>(g.w, k);
+        unsigned long long longs = __ballot(!shortrow);
+        while (longs) {
+            const int src = __ffsll((long long)longs) - 1;
+            longs &= longs - 1;
+            const int64_t lb = __shfl(b, src), ld = __shfl(d, src);
+            double t = 0.0;
+            for (int64_t k = lb + lane; k < lb + ld; k += kWave) t += edge_weight<WT>(g.w, k);
+            t = group_sum<kWave>(t);
+            if (lane == src) s = t;
+        }
+        if (i < g.n) K[i] = s;
+        blk += group_sum<kWave>(s);
     }
     if (lane == 0) part[w] = blk;
     __syncthreads();
@@ -345,7 +368,7 @@ void launch_weights_to_f64(const float *in, double *out, int64_t nnz, hipStream_
 
 void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s) {
     if (g.n == 0) return;
-    unsigned gr = grid_for(g.n, kBlock / kWave, 65536);
+    unsigned gr = grid_for(g.n, kBlock, 8192);
     if (g.wt == W_UNIT)
         k_vertex_weights<W_UNIT><<<gr, kBlock, 0, s>>>(g, K, M2);
     else if (g.wt == W_F32)
