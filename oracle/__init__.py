@@ -80,6 +80,7 @@ def _load():
         "orc_louvain": (i32, [i64, vp, vp, vp, ctypes.POINTER(_Options), vp, ctypes.POINTER(_Stats)]),
         "orc_decide_row": (i32, [i64, i64, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]),
         "orc_weight_grid": (i32, [i64, vp, vp]),
+        "orc_set_verbose": (None, [i32]),
         "orc_gain_fixed": (i64, [dbl, dbl]),
         "orc_bf16": (ctypes.c_float, [ctypes.c_float]),
         "orc_plog2": (dbl, [dbl]),
@@ -144,6 +145,11 @@ def _memb(m, n) -> np.ndarray:
     m = np.ascontiguousarray(m, dtype=np.int32)
     assert m.shape[0] == n
     return m
+
+
+def set_verbose(on: bool) -> None:
+    """Progress lines on stderr from long oracle runs."""
+    _load().orc_set_verbose(int(on))
 
 
 def weight_grid(w: np.ndarray):

@@ -15,8 +15,13 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Progress lines on stderr (per iteration and per pass) for long runs. */
+static int orc_verbose = 0;
+void orc_set_verbose(int32_t on) { orc_verbose = on; }
 
 /* ------------------------------------------------------------------ */
 /* helpers                                                              */
@@ -278,6 +283,7 @@ int32_t orc_move_async(int64_t n, const int64_t *off, const int32_t *col, const 
         }
         if (dq_iter) dq_iter[it] = dq;
         li = it + 1;
+        if (orc_verbose) fprintf(stderr, "[oracle] async iteration %d: dQ %.6g\n", (int)li, dq);
         if (dq <= tau) break;
     }
     table_free(&h);
@@ -734,6 +740,9 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         /* renumber, then dendrogram lookup C <- C'[C] */
         memcpy(cm, lab, (size_t)gn * sizeof(int32_t));
         for (int64_t v = 0; v < n; v++) memb_out[v] = cm[memb_out[v]];
+        if (orc_verbose)
+            fprintf(stderr, "[oracle] pass %d: %lld vertices, %d iterations, %lld communities\n", (int)lp,
+                    (long long)gn, (int)li, (long long)ng);
         if (li <= 1) break;                                           /* globally converged */
         if ((double)ng / (double)gn > opt->aggregation_tolerance) break; /* low shrink */
         if (lp == opt->max_passes - 1) break;                          /* G'' would be unused */

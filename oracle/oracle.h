@@ -23,6 +23,9 @@
 extern "C" {
 #endif
 
+/* Progress lines on stderr (iterations of the asynchronous phase, passes). */
+void orc_set_verbose(int32_t on);
+
 /* K_i = sum of row i (self-loop included), returns M2 = sum_i K_i. */
 double orc_vertex_weights(int64_t n, const int64_t *off, const int32_t *col, const double *w, double *K);
 

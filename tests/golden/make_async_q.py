@@ -6,7 +6,7 @@ without rerunning that loop in every test.
 Only the oracle and the seeded input generators are used.
 
     python tests/golden/make_async_q.py              # R-MAT 20, DC-SBM 4M (seed 1000): a few minutes
-    python tests/golden/make_async_q.py rmat26       # adds R-MAT 26 (needs ~80 GB of host memory, ~15 min)
+    python tests/golden/make_async_q.py rmat26       # only R-MAT 26 (needs ~80 GB of host memory, ~15 min)
 """
 import json
 import os
@@ -34,7 +34,7 @@ def graphs(names):
 def main():
     sys.path.insert(0, ROOT)
     import oracle
-    names = ["sbm10k", "rmat20", "dcsbm4m_s1000"] + [a for a in sys.argv[1:] if a == "rmat26"]
+    names = ["rmat26"] if "rmat26" in sys.argv[1:] else ["sbm10k", "rmat20", "dcsbm4m_s1000"]
     out = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
@@ -44,7 +44,9 @@ def main():
         g = make()
         print(f"{name}: n={g.n} nnz={g.nnz} generated in {time.time() - t:.0f}s", flush=True)
         t = time.time()
+        oracle.set_verbose(True)
         r = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=False)
+        oracle.set_verbose(False)
         dt = time.time() - t
         out[name] = {"n": int(g.n), "nnz": int(g.nnz), "modularity": r.modularity, "passes": r.passes,
                      "iterations": list(r.iterations), "communities": list(r.communities),
