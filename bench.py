@@ -82,6 +82,11 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=4, help="the CPU baseline scans every k-th vertex")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-untimed", action="store_true", help="skip the runs without events")
+    p.add_argument("--kernel-class", default="", choices=[""] + sorted(KERNEL_NAMES),
+                   help="time this kernel class (no probe runs)")
+    p.add_argument("--only-timed", action="store_true",
+                   help="warm-up and timed learned-pruned runs only, all with the same events (for a kernel "
+                        "trace whose per-kernel averages are those of the timed region)")
     return p.parse_args()
 
 
@@ -248,6 +253,20 @@ def main():
     grid = ctx.weight_grid()
     ctx.pruner_set(load_params(DEFAULT_OUT))
     learned_kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=a.theta)
+    if a.only_timed:
+        if not a.kernel_class:
+            sys.exit("--only-timed needs --kernel-class")
+        ev = dict(timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(a.kernel_class))
+        for _ in range(a.warmup):
+            ctx.run(a.tolerance, a.max_passes, **ev, **learned_kw)
+        elapsed, kst, _, st_l = timed_runs(ctx, gsp, a, a.steps, **ev, **learned_kw)
+        v = kst[a.kernel_class]
+        print(json.dumps({"workload": a.workload, "ms_per_step": round(1000.0 * elapsed / a.steps, 4),
+                          "kernel": KERNEL_NAMES[a.kernel_class], "launches": v["launches"],
+                          "avg_launch_us": round(1000.0 * v["ms"] / max(v["launches"], 1), 3),
+                          "bytes_per_launch": round(v["bytes"] / max(v["launches"], 1), 1)}), flush=True)
+        ctx.close()
+        return
     for _ in range(a.warmup):
         ctx.run(a.tolerance, a.max_passes)
         ctx.run(a.tolerance, a.max_passes, **learned_kw)
@@ -256,14 +275,18 @@ def main():
     # the dominant single-kernel class of the learned runs: one probe run per
     # class with only that class's events (events around every kernel would
     # slow the host and inflate the short kernels' times)
-    cand = {}
-    for k in KERNEL_NAMES:
-        ctx.run(a.tolerance, a.max_passes, timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(k), **learned_kw)
-        ms = ctx.stats()["kernels"][k]["ms"]
-        if ms > 0:
-            cand[k] = ms
-    dom = max(cand, key=cand.get)
-    log("probe ms per class: " + ", ".join(f"{k} {v:.3f}" for k, v in sorted(cand.items())))
+    if a.kernel_class:
+        dom = a.kernel_class
+    else:
+        cand = {}
+        for k in KERNEL_NAMES:
+            ctx.run(a.tolerance, a.max_passes, timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(k),
+                    **learned_kw)
+            ms = ctx.stats()["kernels"][k]["ms"]
+            if ms > 0:
+                cand[k] = ms
+        dom = max(cand, key=cand.get)
+        log("probe ms per class: " + ", ".join(f"{k} {v:.3f}" for k, v in sorted(cand.items())))
     ev = dict(timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(dom))
 
     # timed region: `steps` learned-pruned runs, graph resident in HBM

@@ -71,6 +71,9 @@ def test_dcsbm4m_plain_equals_oracle(ctx, g4m, gold):
     assert res.stats["communities"] == ref["communities"]
     assert abs(res.modularity - ref["modularity"]) <= 1e-9
     assert ctx.count_disconnected(res.membership) == 0
+    # the asynchronous oracle's quality (stored): Q >= Q_async - 0.005
+    asy = json.load(open(os.path.join(os.path.dirname(GOLDEN), "async_q.json")))["dcsbm4m_s1000"]
+    assert asy["nnz"] == g4m.nnz and res.modularity >= asy["modularity"] - 0.005
 
 
 def test_dcsbm4m_learned_equals_oracle(ctx, g4m, gold):

@@ -281,8 +281,10 @@ def test_road_network_runs(ctx, returns):
 
 
 def test_run_rmat20_full_size(ctx):
-    """R-MAT scale 20 (the bench workload): whole run bit-exact vs the
-    oracle's synchronous run, 0 disconnected, within 0.005 of async."""
+    """R-MAT scale 20: whole run bit-exact vs the oracle's synchronous run,
+    0 disconnected, Q within 0.005 of the asynchronous oracle's (stored)."""
+    import json
+    import os
     g = gi.rmat20()
     _load(ctx, g)
     ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
@@ -291,6 +293,9 @@ def test_run_rmat20_full_size(ctx):
         np.testing.assert_array_equal(res.membership, ref.membership)
         assert abs(res.modularity - ref.modularity) <= 1e-9
     assert ctx.count_disconnected(res.membership) == 0
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "async_q.json")))["rmat20"]
+    assert gold["nnz"] == g.nnz
+    assert res.modularity >= gold["modularity"] - 0.005
 
 
 @pytest.mark.parametrize("mode", [gsp.SPLIT_LAST, gsp.SPLIT_NONE])
