@@ -75,7 +75,7 @@ def parse():
     p.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
     p.add_argument("--tolerance", type=float, default=1e-2)
     p.add_argument("--max-passes", type=int, default=10)
-    p.add_argument("--theta", type=float, default=0.5, help="learned gate threshold on p")
+    p.add_argument("--theta", type=float, default=None, help="learned gate threshold on p (default: the shipped network's)")
     p.add_argument("--timing", type=int, default=2, choices=(2, 3),
                    help="2: events with a sub-round's scans one after another; 3: events on each kernel's own "
                         "stream, scans side by side")
@@ -241,8 +241,10 @@ def main():
     import torch
 
     import paper_2402_11454_amd as gsp
-    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, load_params
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, DEFAULT_THETA, load_params
 
+    if a.theta is None:
+        a.theta = DEFAULT_THETA
     t0 = time.time()
     g = make_graph(a.workload)
     log(f"generated {a.workload}: n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s")

@@ -37,7 +37,7 @@ def run_workload(runs: int, workload: str, learned: bool):
     import torch
     import paper_2402_11454_amd as gsp
     from bench import make_graph
-    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, load_params
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, DEFAULT_THETA, load_params
     torch.cuda.init()
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
@@ -51,7 +51,7 @@ def run_workload(runs: int, workload: str, learned: bool):
     kw = {}
     if learned:
         ctx.pruner_set(load_params(DEFAULT_OUT))
-        kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)
+        kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=DEFAULT_THETA)
     for k in range(runs):
         ctx.run(1e-2, 10, **kw)
         print(f"[pmc] run {k + 1}/{runs}", flush=True)
@@ -196,6 +196,41 @@ def phases(traffic_json: str, times_json: str, cmd: str):
     print(open(path).read())
 
 
+def counter_summary(dbs, cmd: str, title: str, out_md: str, kernels):
+    """Per-kernel means of every counter found in one or more rocprofv3
+    --pmc databases (all instantiations of a kernel together), as a
+    markdown table restricted to `kernels` (short names; empty: all)."""
+    vals = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        cur = con.cursor()
+        cols = [r[1] for r in cur.execute("pragma table_info(counters_collection)")]
+        name_col = next(c for c in ("kernel_name", "name") if c in cols)
+        cnt_col = next(c for c in ("counter_name", "counter") if c in cols)
+        val_col = next(c for c in ("value", "counter_value") if c in cols)
+        disp_col = next((c for c in ("dispatch_id", "correlation_id", "id") if c in cols), None)
+        q = (f"select {name_col}, {cnt_col}, count(distinct {disp_col}), sum({val_col}) from counters_collection "
+             f"group by {name_col}, {cnt_col}")
+        for name, ctr, n, tot in cur.execute(q):
+            k = short(name).split("<")[0]
+            if kernels and k not in kernels:
+                continue
+            d = vals.setdefault(k, {})
+            a = d.setdefault(ctr, [0, 0.0])
+            a[0] += int(n)
+            a[1] += float(tot)
+    ctrs = sorted({c for d in vals.values() for c in d})
+    with open(out_md, "w") as f:
+        f.write(f"# Hardware counters per dispatch: {title}\n\nCommand (one pass per counter group):\n\n```\n{cmd}\n```\n\n")
+        f.write("Mean per dispatch over every dispatch of the kernel (all instantiations).\n\n")
+        f.write("| kernel | dispatches | " + " | ".join(ctrs) + " |\n|---|---:|" + "---:|" * len(ctrs) + "\n")
+        for k in sorted(vals):
+            n = max(a[0] for a in vals[k].values())
+            row = [f"{vals[k][c][1] / max(vals[k][c][0], 1):.4g}" if c in vals[k] else "" for c in ctrs]
+            f.write(f"| `{k}` | {n} | " + " | ".join(row) + " |\n")
+    print(open(out_md).read())
+
+
 def kernel_summary(db: str, cmd: str, title: str, out_md: str, bench_out: str = ""):
     """Per-kernel durations (all instantiations of a kernel together) from a
     rocprofv3 --kernel-trace database, as a markdown table."""
@@ -245,7 +280,13 @@ if __name__ == "__main__":
                     help="per-kernel durations of a --kernel-trace database into a markdown table")
     ap.add_argument("--title", default="")
     ap.add_argument("--bench-out", default="", help="stdout of the profiled bench.py run (its JSON line)")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DB_OR_OUT",
+                    help="DB [DB ...] OUT_MD: per-kernel means of the counters of --pmc databases")
+    ap.add_argument("--kernels", default="", help="comma list of kernels for --counter-summary")
     a = ap.parse_args()
+    if a.counter_summary:
+        counter_summary(a.counter_summary[:-1], a.cmd, a.title, a.counter_summary[-1],
+                        [k for k in a.kernels.split(",") if k])
     if a.kernel_summary:
         kernel_summary(a.kernel_summary[0], a.cmd, a.title, a.kernel_summary[1], a.bench_out)
     if a.run:

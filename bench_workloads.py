@@ -70,11 +70,11 @@ def main():
         a.batch = a.dcsbm = a.road = True
     import gsp_inputs as gi
     import paper_2402_11454_amd as gsp
-    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, load_params
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, DEFAULT_THETA, load_params
 
     ctx = gsp.Context(0)
     ctx.pruner_set(load_params(DEFAULT_OUT))
-    modes = (("plain", {}), ("learned", dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=0.5)))
+    modes = (("plain", {}), ("learned", dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=DEFAULT_THETA)))
     if a.batch:
         gs = gi.batch_sbm(512, 4, 1.0)
         entries = sum(g.nnz for g in gs)

@@ -25,6 +25,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "pruner_dcsbm.f32")
 
+# Threshold on p for the shipped network, chosen on the held-out 4M graph of
+# seed 1001 among 0.02, 0.05, 0.1, 0.2, 0.3, 0.5: the fastest one whose
+# modularity stays within 0.005 of the plain run's (dQ = +0.0015 there; on
+# seed 1000, the measured graph, dQ = +0.0004).  Above 0.2 the gate prunes
+# vertices that still had a move to make and Q drops by up to 0.01.
+DEFAULT_THETA = 0.1
+
 
 def init_params(seed: int) -> np.ndarray:
     """He-uniform weights, zero biases."""

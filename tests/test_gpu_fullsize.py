@@ -7,6 +7,8 @@ Bars:
     see tests/golden/make_dcsbm4m.py) equal to the oracle's stored runs:
     membership digest, iterations and communities per pass, the pruning
     counters, Q within 1e-9; no disconnected community;
+  * 4M graph, the shipped trained network at its threshold: Q within 0.005
+    of the plain run's, no disconnected community;
   * batch: every 16th graph's membership bit-identical to the oracle's run of
     that graph alone, Q within 1e-9, passes equal; no graph with a
     disconnected community; with learned pruning (the trained network), every
@@ -87,6 +89,21 @@ def test_dcsbm4m_learned_equals_oracle(ctx, g4m, gold):
     assert res.stats["communities"] == ref["communities"]
     assert _digest(res.membership) == ref["membership_sha1"]
     assert abs(res.modularity - ref["modularity"]) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
+
+
+def test_dcsbm4m_shipped_network_quality(ctx, g4m, gold):
+    """The shipped trained network at its threshold on the measured 4M graph:
+    modularity within 0.005 of the plain run's (stored oracle Q), no
+    internally-disconnected community, and pruning really happened."""
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, DEFAULT_THETA, load_params
+    ctx.load(g4m.offsets, g4m.cols, g4m.weights, n=g4m.n)
+    ctx.pruner_set(load_params(DEFAULT_OUT))
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=DEFAULT_THETA)
+    print(f"[fullsize] shipped gate theta={DEFAULT_THETA}: Q={res.modularity:.6f} plain {gold['plain']['modularity']:.6f} "
+          f"iterations={res.stats['iterations']} pruned={res.stats['pruned']}", flush=True)
+    assert res.stats["pruned"] > 0
+    assert abs(res.modularity - gold["plain"]["modularity"]) <= 0.005
     assert ctx.count_disconnected(res.membership) == 0
 
 
