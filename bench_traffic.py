@@ -228,6 +228,26 @@ def counter_summary(dbs, cmd: str, title: str, out_md: str, kernels):
             n = max(a[0] for a in vals[k].values())
             row = [f"{vals[k][c][1] / max(vals[k][c][0], 1):.4g}" if c in vals[k] else "" for c in ctrs]
             f.write(f"| `{k}` | {n} | " + " | ".join(row) + " |\n")
+        # ratios of counters of one kernel (means per dispatch)
+        def mean(k, c):
+            return vals[k][c][1] / max(vals[k][c][0], 1) if c in vals[k] else None
+        f.write("\nDerived, per kernel: L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS); L1 hit rate = 1 - "
+                "TCP_TCC_READ_REQ / TCP_TOTAL_CACHE_ACCESSES; issue-wait share = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES "
+                "(wave-cycles waiting for an instruction to issue over wave-cycles resident; waits on memory counters are SQ_WAIT_ANY, not this); waves per CU = 4 SQ_WAVE_CYCLES / "
+                "(GRBM_GUI_ACTIVE / 8 XCDs) / 256 CUs (SQ wave-cycle counters taken in units of 4 cycles, "
+                "GRBM_GUI_ACTIVE summed over the 8 XCDs); VMEM reads per wave = SQ_INSTS_VMEM_RD / SQ_WAVES.\n\n")
+        f.write("| kernel | L2 hit | L1 hit | issue-wait share | waves per CU | VMEM reads per wave |\n|---|---:|---:|---:|---:|---:|\n")
+        for k in sorted(vals):
+            h, m = mean(k, "TCC_HIT_sum"), mean(k, "TCC_MISS_sum")
+            rq, acc = mean(k, "TCP_TCC_READ_REQ_sum"), mean(k, "TCP_TOTAL_CACHE_ACCESSES_sum")
+            wi, wc, ga = mean(k, "SQ_WAIT_INST_ANY"), mean(k, "SQ_WAVE_CYCLES"), mean(k, "GRBM_GUI_ACTIVE")
+            vr, wv = mean(k, "SQ_INSTS_VMEM_RD"), mean(k, "SQ_WAVES")
+            cells = [f"{100 * h / (h + m):.1f}%" if h is not None and m is not None and h + m > 0 else "",
+                     f"{100 * (1 - rq / acc):.1f}%" if rq is not None and acc else "",
+                     f"{100 * wi / wc:.1f}%" if wi is not None and wc else "",
+                     f"{4 * wc / (ga / 8) / 256:.1f}" if wc is not None and ga else "",
+                     f"{vr / wv:.0f}" if vr is not None and wv else ""]
+            f.write(f"| `{k}` | " + " | ".join(cells) + " |\n")
     print(open(out_md).read())
 
 
