@@ -63,6 +63,7 @@ WORKLOADS = {
                     text="degree-corrected SBM, 4M vertices, degrees power law 2.5 on [5, 5000], communities "
                          "power law 1.5 on [20, 50000], mixing 0.3, fp32 weights U[1,4), held-out seed 1000"),
 }
+ORDERS = {"auto": 0, "loaded": 1, "degree": 2}
 GOLDEN_ASYNC = os.path.join(ROOT, "tests", "golden", "async_q.json")
 GOLDEN_KEY = {"rmat26": "rmat26", "rmat20": "rmat20", "dcsbm4m": "dcsbm4m_s1000"}
 
@@ -80,6 +81,8 @@ def parse():
                    help="2: events with a sub-round's scans one after another; 3: events on each kernel's own "
                         "stream, scans side by side")
     p.add_argument("--cpu-sample", type=int, default=4, help="the CPU baseline scans every k-th vertex")
+    p.add_argument("--vertex-order", default="auto", choices=sorted(ORDERS),
+                   help="storage order of the graph inside the runs (auto: degree order from 2^27 entries)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-untimed", action="store_true", help="skip the runs without events")
     p.add_argument("--kernel-class", default="", choices=[""] + sorted(KERNEL_NAMES),
@@ -166,7 +169,7 @@ def timed_runs(ctx, gsp, a, steps, **kw):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.run(a.tolerance, a.max_passes, **kw)
+        ctx.run(a.tolerance, a.max_passes, vertex_order=ORDERS[a.vertex_order], **kw)
         st = ctx.stats()
         for name, v in st["kernels"].items():
             for f in ("launches", "ms", "bytes", "items"):
@@ -260,7 +263,7 @@ def main():
             sys.exit("--only-timed needs --kernel-class")
         ev = dict(timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(a.kernel_class))
         for _ in range(a.warmup):
-            ctx.run(a.tolerance, a.max_passes, **ev, **learned_kw)
+            ctx.run(a.tolerance, a.max_passes, vertex_order=ORDERS[a.vertex_order], **ev, **learned_kw)
         elapsed, kst, _, st_l = timed_runs(ctx, gsp, a, a.steps, **ev, **learned_kw)
         v = kst[a.kernel_class]
         print(json.dumps({"workload": a.workload, "ms_per_step": round(1000.0 * elapsed / a.steps, 4),
@@ -270,8 +273,8 @@ def main():
         ctx.close()
         return
     for _ in range(a.warmup):
-        ctx.run(a.tolerance, a.max_passes)
-        ctx.run(a.tolerance, a.max_passes, **learned_kw)
+        ctx.run(a.tolerance, a.max_passes, vertex_order=ORDERS[a.vertex_order])
+        ctx.run(a.tolerance, a.max_passes, vertex_order=ORDERS[a.vertex_order], **learned_kw)
     log(f"{a.warmup} warm-up run(s) of each method done")
 
     # the dominant single-kernel class of the learned runs: one probe run per
@@ -282,7 +285,7 @@ def main():
     else:
         cand = {}
         for k in KERNEL_NAMES:
-            ctx.run(a.tolerance, a.max_passes, timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(k),
+            ctx.run(a.tolerance, a.max_passes, vertex_order=ORDERS[a.vertex_order], timing=a.timing, timing_mask=1 << gsp.KERNEL_CLASSES.index(k),
                     **learned_kw)
             ms = ctx.stats()["kernels"][k]["ms"]
             if ms > 0:
@@ -364,6 +367,8 @@ def main():
                                f"passes, 8 sub-rounds; value = learned-pruned runs (8-64-64-1 gate, theta "
                                f"{a.theta}, trained on DC-SBM traces), plain runs beside",
                    "n": g.n, "nnz": g.nnz, "weight_grid_exp": grid[0], "weights_moved_to_grid": grid[1],
+                   "vertex_order": a.vertex_order + (" (degree order at this size)" if a.vertex_order == "auto"
+                                                     and g.nnz >= 1 << 27 else ""),
                    "modularity": round(q_l, 6), "disconnected": disc_l, "passes": st_l["passes"],
                    "iterations": st_l["iterations"], "scanned_entries": st_l["scanned_entries"],
                    "pruned": st_l["pruned"], "confirm_sweeps": st_l["confirm_sweeps"],

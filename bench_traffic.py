@@ -271,8 +271,12 @@ def kernel_summary(db: str, cmd: str, title: str, out_md: str, bench_out: str = 
         last = [x for x in open(bench_out).read().splitlines() if x.startswith("{")]
         if last:
             b = json.loads(last[-1])
+            if "value" not in b:   # bench.py --only-timed: the timed runs' line
+                b = {"ms_per_step": b["ms_per_step"], "value": None, "roofline": b,
+                     "config": {"plain": {"ms_per_step": None}}}
             line = (f"Bench line of this command: {b['ms_per_step']} ms per learned-pruned run "
-                    f"({b['value'] / 1e9:.3f} G entries/s), plain {b['config']['plain']['ms_per_step']} ms; roofline "
+                    + (f"({b['value'] / 1e9:.3f} G entries/s), plain {b['config']['plain']['ms_per_step']} ms"
+                       if b["value"] else "(warm-up and timed runs only)") + "; roofline "
                     f"kernel `{b['roofline']['kernel']}` {b['roofline']['avg_launch_us']} us per launch by events, "
                     f"{b['roofline']['bytes_per_launch']:.0f} algorithmic bytes per launch.\n\n")
     with open(out_md, "w") as f:

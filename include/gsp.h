@@ -90,10 +90,22 @@ typedef struct gsp_options {
     int32_t grid_cap;              /* launch schedule: the local-moving scans and apply take at most this many
                                       workgroups each (0, the default: each kernel's own cap, 2048-8192);
                                       results do not depend on it */
+    int32_t vertex_order;          /* storage order of the input graph inside gsp_run: GSP_ORDER_AUTO
+                                      (default: degree order for graphs of at least 2^27 entries),
+                                      GSP_ORDER_LOADED or GSP_ORDER_DEGREE (vertices renumbered by degree,
+                                      largest first, so that the high-degree vertices' words share cache
+                                      lines).  The copy in degree order is built by the first run that asks
+                                      for it and kept until the next load (device memory: about as much
+                                      as the loaded graph).  Results do not depend on it: every rule that
+                                      orders vertex or community ids compares the caller's ids.  Batches
+                                      and the step entry points use the loaded order. */
 } gsp_options;
 
 /* split_algo values. */
 enum { GSP_SPLIT_UF = 0, GSP_SPLIT_LPP = 1 };
+
+/* vertex_order values. */
+enum { GSP_ORDER_AUTO = 0, GSP_ORDER_LOADED = 1, GSP_ORDER_DEGREE = 2 };
 
 /* Vertex pruning of the local-moving phase (prune_mode). */
 enum { GSP_PRUNE_PLAIN = 0, GSP_PRUNE_LEARNED = 1 };

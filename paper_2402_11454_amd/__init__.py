@@ -28,6 +28,7 @@ KERNEL_CLASSES = ("move_small", "move_wave", "move_block", "move_hub", "move_hub
                   "split", "aggregate", "gate", "move_hub_gather")
 PRUNE_PLAIN, PRUNE_LEARNED = 0, 1
 SPLIT_UF, SPLIT_LPP = 0, 1
+ORDER_AUTO, ORDER_LOADED, ORDER_DEGREE = 0, 1, 2
 GATE_PARAMS = 4801  # (8*64 + 64) + (64*64 + 64) + (64 + 1)
 
 _STATUS = {GSP_EINVAL: "GSP_EINVAL", GSP_ENOMEM: "GSP_ENOMEM", GSP_EHIP: "GSP_EHIP",
@@ -48,7 +49,8 @@ class Options(ctypes.Structure):
                 ("prune_threshold", ctypes.c_float), ("use_graphs", ctypes.c_int32),
                 ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32),
                 ("hub_max_parts", ctypes.c_int32), ("return_moves", ctypes.c_int32),
-                ("split_algo", ctypes.c_int32), ("grid_cap", ctypes.c_int32)]
+                ("split_algo", ctypes.c_int32), ("grid_cap", ctypes.c_int32),
+                ("vertex_order", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):

@@ -120,6 +120,10 @@ struct gsp_ctx {
     int32_t grid_S = 0;
     int64_t grid_moved = 0;
     int *lp_counts = nullptr;   // queue sizes of the label-propagation split (4 ints)
+    // the input graph in degree order (built by the first run asking for it)
+    DegreeOrder ord;
+    double *Kord = nullptr;
+    bool ordered = false;
 
     // super-vertex levels (ping-pong) and the gapped aggregation rows
     int64_t *offL[2] = {nullptr, nullptr};
@@ -243,6 +247,9 @@ struct gsp_ctx {
         gap_col = nullptr;
         gap_w = nullptr;
         lp_counts = nullptr;
+        ord = DegreeOrder();
+        Kord = nullptr;
+        ordered = false;
         mhist = iter_dev = nullptr;
         ctr = nullptr;
         hfrac = hgain = nullptr;
@@ -326,6 +333,18 @@ Level level0(const gsp_ctx *ctx) {
     g.w = ctx->w0;
     g.wt = ctx->wt0;
     g.deg = ctx->deg0;
+    return g;
+}
+
+// The input graph in degree order (ensure_order has built it).
+Level level_ordered(const gsp_ctx *ctx) {
+    Level g = level0(ctx);
+    g.off = ctx->ord.off;
+    g.col = ctx->ord.col;
+    g.w = ctx->wt0 == W_UNIT ? nullptr : ctx->ord.w;
+    g.deg = ctx->ord.deg;
+    g.orig = ctx->ord.orig;
+    g.nlong = ctx->ord.nlong;
     return g;
 }
 
@@ -696,7 +715,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         key = {g.n, g.nnz, g.wt, g.graphs, ptr(g.off), ptr(g.col), ptr(g.w), ptr(g.deg), ptr(g.gid), ptr(g.vbase),
                ptr(K), P, (int64_t)cfg.grid_cap, ptr(wl.bl), ptr(wl.ch_vert), ptr(wl.ch_beg), ptr(wl.hub_off), ptr(ctx->sc.hkeys),
                ptr(ctx->sc.hvals), ptr(ctx->sc.part_g), ptr(ctx->sc.hbuck), (int64_t)(batch ? 1 : 0),
-               ptr(ctx->ggated), ptr(ctx->giter)};
+               ptr(ctx->ggated), ptr(ctx->giter), ptr(g.orig), g.nlong};
         for (int k = 0; k <= kNumBins * P; k++) key.push_back(wl.boff[k]);
         for (int p = 0; p <= P; p++) key.push_back(wl.ch_poff[p]);
         int64_t m2bits;
@@ -886,6 +905,45 @@ gsp_status ensure_levels(gsp_ctx *ctx) {
     return GSP_OK;
 }
 
+// Whether gsp_run stores the input graph in degree order (vertex_order;
+// batches never).
+constexpr int64_t kAutoOrderEntries = int64_t(1) << 27;
+bool wants_order(const gsp_ctx *ctx, const gsp_options &opt, bool batch, int32_t max_passes) {
+    if (batch || max_passes == 0 || ctx->n == 0 || ctx->nnz == 0) return false;
+    if (opt.vertex_order == GSP_ORDER_DEGREE) return true;
+    return opt.vertex_order == GSP_ORDER_AUTO && ctx->nnz >= kAutoOrderEntries;
+}
+
+// Builds the input graph's copy in degree order once per load.
+gsp_status ensure_order(gsp_ctx *ctx) {
+    if (ctx->ordered) return GSP_OK;
+    const int64_t n = ctx->n, nnz = ctx->nnz;
+    const int wb = ctx->wt0 == W_UNIT ? 0 : (ctx->wt0 == W_F32 ? 4 : 8);
+    if (ctx->mem_limit) {
+        uint64_t need = (uint64_t)n * 20 + (uint64_t)(n + 1) * 8 + (uint64_t)nnz * (4 + wb) + 64;
+        if (ctx->mem_used + need > ctx->mem_limit)
+            return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached (degree order)");
+    }
+    hipError_t e = hipSuccess;
+    DegreeOrder o;
+    auto fail = [&](const char *what) { return ctx->fail_hip(e, what); };
+    if (!(o.orig = ctx->dalloc<int32_t>(n, &e))) return fail("hipMalloc(order)");
+    if (!(o.rank = ctx->dalloc<int32_t>(n, &e))) return fail("hipMalloc(order rank)");
+    if (!(o.deg = ctx->dalloc<int32_t>(n, &e))) return fail("hipMalloc(order degrees)");
+    if (!(o.off = ctx->dalloc<int64_t>(n + 1, &e))) return fail("hipMalloc(order offsets)");
+    if (!(o.col = ctx->dalloc<int32_t>(nnz, &e))) return fail("hipMalloc(order columns)");
+    if (wb == 4 && !(o.w = ctx->dalloc<float>(nnz, &e))) return fail("hipMalloc(order weights)");
+    if (wb == 8 && !(o.w = ctx->dalloc<double>(nnz, &e))) return fail("hipMalloc(order weights)");
+    double *K = ctx->dalloc<double>(n, &e);
+    if (!K) return fail("hipMalloc(order K)");
+    HIP_TRY(order_by_degree(level0(ctx), ctx->sc, o, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->ord = o;
+    ctx->Kord = K;
+    ctx->ordered = true;
+    return GSP_OK;
+}
+
 int bit_length(uint64_t x) {
     int b = 0;
     while (x) {
@@ -991,7 +1049,7 @@ gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64,
     for (int32_t **p : {&sc.i32a, &sc.i32b, &sc.i32c, &sc.i32d, &sc.i32e, &sc.bl2})
         if ((st = A(*p, n1, "hipMalloc(scratch)")) != GSP_OK) return st;
     if ((st = A(sc.err, 4, "hipMalloc(err)")) != GSP_OK) return st;
-    if ((st = A(sc.u64, 2 * kNumBuckets + 16, "hipMalloc(counters)")) != GSP_OK) return st;
+    if ((st = A(sc.u64, kScratchU64, "hipMalloc(counters)")) != GSP_OK) return st;
     if ((st = A(sc.f64, 16, "hipMalloc(scalars)")) != GSP_OK) return st;
     // chunks: vertex hubs need <= nnz/2048 + #hubs, hub communities <=
     // nnz/1024 + #hubs, with #hubs <= nnz/2049
@@ -1117,6 +1175,8 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
     if (opt.timing < 0 || opt.timing > 3) return ctx->fail(GSP_EINVAL, "timing must lie in [0, 3]");
     if (opt.return_moves != 0 && opt.return_moves != 1) return ctx->fail(GSP_EINVAL, "return_moves must be 0 or 1");
     if (opt.grid_cap < 0) return ctx->fail(GSP_EINVAL, "grid_cap must be >= 0");
+    if (opt.vertex_order < GSP_ORDER_AUTO || opt.vertex_order > GSP_ORDER_DEGREE)
+        return ctx->fail(GSP_EINVAL, "vertex_order must be GSP_ORDER_AUTO, GSP_ORDER_LOADED or GSP_ORDER_DEGREE");
     if (opt.split_algo != GSP_SPLIT_UF && opt.split_algo != GSP_SPLIT_LPP)
         return ctx->fail(GSP_EINVAL, "split_algo must be GSP_SPLIT_UF or GSP_SPLIT_LPP");
     if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
@@ -1155,6 +1215,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->hub_max_parts = 0;
     out->return_moves = 0;
     out->split_algo = GSP_SPLIT_UF;
+    out->vertex_order = GSP_ORDER_AUTO;
     return GSP_OK;
 }
 
@@ -1276,6 +1337,8 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
     gsp_status st = ensure_levels(ctx);
     if (st != GSP_OK) return st;
+    const bool ordered = wants_order(ctx, opt, batch, max_passes);
+    if (ordered && (st = ensure_order(ctx)) != GSP_OK) return st;
     hipStream_t s = ctx->stream;
     ctx->have_result = false;
     ctx->have_batch_result = false;
@@ -1295,8 +1358,9 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     std::vector<int64_t> cfirst_h(G + 1, 0);
     if (batch) ctx->bpasses_h.assign(G, 0);
 
-    launch_iota_i32(ctx->top, ctx->n, s);
-    Level g = level0(ctx);
+    launch_iota_i32(ctx->top, ctx->n, s);   // level-0 ids (in degree order if ordered)
+    Level g = ordered ? level_ordered(ctx) : level0(ctx);
+    double *K0 = ordered ? ctx->Kord : ctx->K0;
     if (batch) {
         g.graphs = G;
         g.gid = ctx->gid0;
@@ -1309,15 +1373,15 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         // aggregation); exact sums, so equal to the load's values
         int t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
         launch_fill_f64(ctx->sc.f64, 0.0, 1, s);
-        launch_vertex_weights(g, ctx->K0, ctx->sc.f64, s);
-        if (batch) launch_batch_m2(ctx->K0, ctx->vbase0, G, ctx->M2g, s);
+        launch_vertex_weights(g, K0, ctx->sc.f64, s);
+        if (batch) launch_batch_m2(K0, ctx->vbase0, G, ctx->M2g, s);
         HIP_TRY(hipMemcpyAsync(ctx->f64_h, ctx->sc.f64, sizeof(double), hipMemcpyDeviceToHost, s));
         if (batch) HIP_TRY(hipMemcpyAsync(ctx->M2g_h.data(), ctx->M2g, G * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         ctx->M2 = ctx->f64_h[0];
         ctx->timer.end(t);
     }
-    const double *K = ctx->K0;
+    const double *K = K0;
     double tau = tolerance;
     int next = 0;
     int passes = 0;
@@ -1373,6 +1437,16 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
             labels = ctx->lab;
         }
         t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
+        if (g.orig) {
+            // level 0 in degree order: number the communities as in the
+            // caller's order, split components by their smallest vertex and
+            // communities by their founding vertex, both as caller's ids
+            if (labels == ctx->lab)
+                launch_labels_min_orig(ctx->lab, g.orig, g.n, ctx->sc.i32c, s);
+            else
+                launch_labels_orig(ctx->cm, g.orig, g.n, ctx->lab, s);
+            labels = ctx->lab;
+        }
         int64_t ncomm = 0;
         st = renumber(ctx, labels, g.n, ctx->cm, &ncomm);
         if (st != GSP_OK) return st;
@@ -1444,6 +1518,11 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         K = out.K;
         next ^= 1;
         tau = tau / opt.tolerance_drop;                                    // threshold scaling
+    }
+    if (ordered) {
+        // the top-level membership back in the caller's vertex order
+        launch_scatter_by_orig(ctx->top, ctx->ord.orig, ctx->n, ctx->lab, s);
+        HIP_TRY(hipMemcpyAsync(ctx->top, ctx->lab, ctx->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     if (opt.split_mode == GSP_SPLIT_LAST && ctx->n > 0) {
         Level g0 = level0(ctx);

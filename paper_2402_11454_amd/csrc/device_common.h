@@ -12,6 +12,7 @@ namespace gsp {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;            // threads per block for every kernel here
 constexpr int kEmpty = -1;             // empty table key (community ids are >= 0)
+constexpr int kIntMax = 0x7fffffff;     // "no community" in an argmax
 
 // Degree bins.  A vertex (or a community, for aggregation) with d entries is
 // processed by:
@@ -174,18 +175,23 @@ __device__ __forceinline__ int last_le(const int *v, int n, int t) {
 }
 
 // (g, c) beats (g2, c2): larger score, ties to the lower community id.
-__device__ __forceinline__ bool better(double g, int c, double g2, int c2) {
-    return g > g2 || (g == g2 && c < c2);
+// Community ids are vertex ids of the level; on a level stored in degree
+// order (orig != nullptr) they are compared as the caller's vertex ids,
+// orig[c], which are read on exact ties only.
+__device__ __forceinline__ bool better(double g, int c, double g2, int c2, const int32_t *orig) {
+    if (g != g2) return g > g2;
+    if (!orig || c == kIntMax || c2 == kIntMax) return c < c2;
+    return orig[c] < orig[c2];
 }
 
 // Argmax over the W lanes of an aligned lane group (W power of two <= 64).
 template <int W>
-__device__ __forceinline__ void group_argmax(double &g, int &c) {
+__device__ __forceinline__ void group_argmax(double &g, int &c, const int32_t *orig) {
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1) {
         double og = __shfl_xor(g, off, W);
         int oc = __shfl_xor(c, off, W);
-        if (better(og, oc, g, c)) {
+        if (better(og, oc, g, c, orig)) {
             g = og;
             c = oc;
         }

@@ -27,6 +27,29 @@ struct Level {
     const int32_t *gid = nullptr;     // graph of each vertex
     const int64_t *vbase = nullptr;   // first vertex of each graph (graphs + 1 entries)
     const double *M2g = nullptr;      // 2m of each graph
+    // a graph stored in degree order: orig[v] = the caller's id of vertex v
+    // (nullptr: stored as loaded).  Wherever the method orders vertex or
+    // community ids (ties, the singleton rule, sub-rounds, traces) it uses
+    // orig, so results do not depend on the storage order.
+    const int32_t *orig = nullptr;
+    // in degree order, rows [0, nlong) are the rows of at least kLongRow
+    // entries (0 otherwise)
+    int64_t nlong = 0;
+};
+
+constexpr int kLongLog = 8;
+constexpr int kLongRow = 1 << kLongLog;   // rows this long are cut into entry chunks
+constexpr int kScratchU64 = 2 * kNumBuckets + 16;   // counters in Scratch::u64
+
+// The input graph stored in degree order (k_order.hip): vertex p is the
+// caller's vertex orig[p], rank is the inverse, and row p is row orig[p]
+// with its columns renumbered by rank.
+struct DegreeOrder {
+    int32_t *orig = nullptr, *rank = nullptr, *deg = nullptr;
+    int64_t *off = nullptr;
+    int32_t *col = nullptr;
+    void *w = nullptr;
+    int64_t nlong = 0;
 };
 
 // Vertex work lists of a level: every vertex with deg > 0 sits in bucket
@@ -192,6 +215,21 @@ void launch_degrees(const int64_t *off, int32_t *deg, int64_t n, hipStream_t s);
 void launch_weights_to_f64(const float *in, double *out, int64_t nnz, hipStream_t s);
 // K_i = row sums (one wavefront per row) and *M2 += sum K_i.
 void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s);
+
+// ---- k_order.hip ----
+struct Scratch;
+// K of the long rows of a level in degree order (rows [0, g.nlong)), and
+// their part of *M2; the rows after them are launch_vertex_weights' part.
+void launch_vertex_weights_long(const Level &g, double *K, double *M2, hipStream_t s);
+// Fills o (arrays allocated by the caller: orig, rank, deg n; off n + 1;
+// col, w nnz) with g in degree order and sets o.nlong.  Synchronizes s.
+hipError_t order_by_degree(const Level &g, Scratch &sc, DegreeOrder &o, hipStream_t s);
+// lab[v] <- the smallest orig[u] over the u with lab[u] = lab[v] (tmp: n ints).
+void launch_labels_min_orig(int32_t *lab, const int32_t *orig, int64_t n, int32_t *tmp, hipStream_t s);
+// out[v] <- orig[lab[v]].
+void launch_labels_orig(const int32_t *lab, const int32_t *orig, int64_t n, int32_t *out, hipStream_t s);
+// out[orig[v]] <- in[v].
+void launch_scatter_by_orig(const int32_t *in, const int32_t *orig, int64_t n, int32_t *out, hipStream_t s);
 // Modularity parts: *sigma_in += sum of entries inside communities,
 // sig[c] += K_i; then q = sigma_in/M2 - sum_c (sig[c]/M2)^2, the second sum
 // in units of 2^-62 (*out of launch_sum_squares), exact in any order.
@@ -225,7 +263,8 @@ hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &
 // Only the buckets (no hub chunks or tables): items with deg[i] > 0 into
 // wl.bl by (bin of deg[i], sub-round of i).
 hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s,
-                        const int32_t *gid = nullptr, const int64_t *vbase = nullptr);
+                        const int32_t *gid = nullptr, const int64_t *vbase = nullptr,
+                        const int32_t *orig = nullptr);
 
 // ---- k_move.hip ----
 void launch_community_totals(const double *K, const int32_t *cm, int64_t n, double *sig, int32_t *csize,

@@ -13,13 +13,16 @@ constexpr int kBinTile = kBlock * 4;
 
 // Sub-round of vertex v: by its id within its graph when the level holds a
 // batch of graphs (gid: graph of each vertex, vbase: first vertex of each
-// graph), so every graph of a batch sees the groups it would see alone.
-__device__ __forceinline__ int vertex_round(int64_t v, int shift, const int32_t *gid, const int64_t *vbase) {
+// graph), so every graph of a batch sees the groups it would see alone; by
+// its caller's id orig[v] when the level is stored in degree order.
+__device__ __forceinline__ int vertex_round(int64_t v, int shift, const int32_t *gid, const int64_t *vbase,
+                                            const int32_t *orig) {
+    if (orig) return sub_round_of(orig[v], shift);
     return sub_round_of(gid ? v - vbase[gid[v]] : v, shift);
 }
 
 __global__ void __launch_bounds__(kBlock) k_bin_count(const int32_t *deg, int64_t n, int rounds, int shift,
-                                                     const int32_t *gid, const int64_t *vbase,
+                                                     const int32_t *gid, const int64_t *vbase, const int32_t *orig,
                                                      unsigned long long *cnt, unsigned long long *ent) {
     __shared__ unsigned int lcnt[kNumBuckets];
     __shared__ unsigned long long lent[kNumBuckets];
@@ -34,7 +37,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const int32_t *deg, int64_
             int d = deg[v];
             int b = bin_of_degree(d);
             if (b < 0) continue;
-            int k = b * rounds + vertex_round(v, shift, gid, vbase);
+            int k = b * rounds + vertex_round(v, shift, gid, vbase, orig);
             atomicAdd(&lcnt[k], 1u);
             atomicAdd(&lent[k], (unsigned long long)d);
         }
@@ -50,7 +53,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_count(const int32_t *deg, int64_
 // Places vertex ids into their buckets.  cursor[k] starts at the bucket's
 // begin; each block reserves its slots with one atomic per bucket.
 __global__ void __launch_bounds__(kBlock) k_bin_fill(const int32_t *deg, int64_t n, int rounds, int shift,
-                                                    const int32_t *gid, const int64_t *vbase,
+                                                    const int32_t *gid, const int64_t *vbase, const int32_t *orig,
                                                     unsigned long long *cursor, int32_t *bl) {
     __shared__ unsigned int lcnt[kNumBuckets];
     __shared__ unsigned long long lbase[kNumBuckets];
@@ -67,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_fill(const int32_t *deg, int64_t
             if (v < n) {
                 int b = bin_of_degree(deg[v]);
                 if (b >= 0) {
-                    bk[r] = b * rounds + vertex_round(v, shift, gid, vbase);
+                    bk[r] = b * rounds + vertex_round(v, shift, gid, vbase, orig);
                     rk[r] = atomicAdd(&lcnt[bk[r]], 1u);
                 }
             }
@@ -116,7 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_fill(const int32_t *bl, int64_t 
 }  // namespace
 
 hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s,
-                        const int32_t *gid, const int64_t *vbase) {
+                        const int32_t *gid, const int64_t *vbase, const int32_t *orig) {
     int shift = 0;
     while ((1 << shift) < rounds) shift++;
     wl.rounds = rounds;
@@ -129,7 +132,7 @@ hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl
     if (n > 0) {
         int64_t gr = (n + kBinTile - 1) / kBinTile;
         if (gr > 4096) gr = 4096;
-        k_bin_count<<<(unsigned)gr, kBlock, 0, s>>>(deg, n, rounds, shift, gid, vbase, cnt, ent);
+        k_bin_count<<<(unsigned)gr, kBlock, 0, s>>>(deg, n, rounds, shift, gid, vbase, orig, cnt, ent);
     }
     unsigned long long hc[2 * kNumBuckets];
     e = hipMemcpyAsync(hc, sc.u64, sizeof(unsigned long long) * 2 * kNumBuckets, hipMemcpyDeviceToHost, s);
@@ -151,13 +154,13 @@ hipError_t bin_vertices(const int32_t *deg, int64_t n, int rounds, WorkLists &wl
     if (n > 0) {
         int64_t gr = (n + kBinTile - 1) / kBinTile;
         if (gr > 4096) gr = 4096;
-        k_bin_fill<<<(unsigned)gr, kBlock, 0, s>>>(deg, n, rounds, shift, gid, vbase, sc.u64, wl.bl);
+        k_bin_fill<<<(unsigned)gr, kBlock, 0, s>>>(deg, n, rounds, shift, gid, vbase, orig, sc.u64, wl.bl);
     }
     return hipGetLastError();
 }
 
 hipError_t build_work_lists(const Level &g, int rounds, WorkLists &wl, Scratch &sc, hipStream_t s) {
-    hipError_t e = bin_vertices(g.deg, g.n, rounds, wl, sc, s, g.gid, g.vbase);
+    hipError_t e = bin_vertices(g.deg, g.n, rounds, wl, sc, s, g.gid, g.vbase, g.orig);
     if (e != hipSuccess) return e;
     // hubs
     int64_t hb = wl.bin_begin(BIN_HUB), H = wl.bin_size(BIN_HUB);

@@ -26,7 +26,6 @@ namespace gsp {
 
 namespace {
 
-constexpr int kIntMax = 0x7fffffff;
 
 struct Acc {          // per-thread counters, reduced per block at the end
     unsigned long long gain = 0;   // units of 2^-61 of delta-modularity (gain_units)
@@ -103,7 +102,7 @@ __device__ __forceinline__ bool decide(double m2, int d, double ki, double kid, 
     if (bc == kIntMax) return false;
     double gstay = m2 * kid - ki * (sig_d - ki);
     if (!(bg > gstay)) return false;
-    if (csz_d == 1 && bc_single && bc > d) return false;
+    if (bc_single) return false;
     *gain = bg - gstay;
     return true;
 }
@@ -111,7 +110,10 @@ __device__ __forceinline__ bool decide(double m2, int d, double ki, double kid, 
 // Whether community bc is a singleton, read only where the singleton rule
 // can reject the move (d a singleton, bc > d).
 __device__ __forceinline__ int best_single(const MoveArgs &a, int d, int csz_d, int bc) {
-    return (csz_d == 1 && bc != kIntMax && bc > d) ? a.csize[bc] == 1 : 0;
+    if (csz_d != 1 || bc == kIntMax) return 0;
+    const int32_t *o = a.g.orig;
+    if (!(o ? o[bc] > o[d] : bc > d)) return 0;
+    return a.csize[bc] == 1;
 }
 
 // History of a scan (for the learned gate's features) and, if sampled, a
@@ -121,7 +123,8 @@ __device__ __forceinline__ void record_scan(const MoveArgs &a, double m2, int i,
                                            double bg, int bc, bool mv) {
     uint8_t hb = a.hbits[i];
     float hf = a.hfrac[i], hg = a.hgain[i];
-    if (a.tr.x && trace_keep(a.tr.seed, a.pass, a.sweep, i, a.tr.thr)) {
+    const int vid = a.g.orig ? a.g.orig[i] : i;   // the caller's id of i
+    if (a.tr.x && trace_keep(a.tr.seed, a.pass, a.sweep, vid, a.tr.thr)) {
         uint16_t x[kGateFeatures];
         gate_features(di, ki, a.sig[d], hf, hg, hb, a.dsnap[i], a.pass, a.iter, x);
         int r = blockIdx.x % kStripes;
@@ -131,7 +134,7 @@ __device__ __forceinline__ void record_scan(const MoveArgs &a, double m2, int i,
 #pragma unroll
             for (int f = 0; f < kGateFeatures; f++) a.tr.x[row * kGateFeatures + f] = bf16_value(x[f]);
             a.tr.y[row] = mv ? 1 : 0;
-            a.tr.v[row] = i;
+            a.tr.v[row] = vid;
             a.tr.meta[row] = a.pass * 256 + a.sweep;
         }
     }
@@ -168,7 +171,7 @@ __device__ __forceinline__ void fold_key(const MoveArgs &a, double m2, int key, 
         kid = v;
     } else {
         double g = m2 * v - ki * a.sig[key];
-        if (better(g, key, bg, bc)) {
+        if (better(g, key, bg, bc, a.g.orig)) {
             bg = g;
             bc = key;
         }
@@ -213,7 +216,7 @@ __device__ __forceinline__ void take_slot(const MoveArgs &a, double m2, int *key
         kid = v;
     } else {
         double g = m2 * v - ki * a.sig[key];
-        if (better(g, key, bg, bc)) {
+        if (better(g, key, bg, bc, a.g.orig)) {
             bg = g;
             bc = key;
         }
@@ -252,7 +255,7 @@ __device__ __forceinline__ void fold_table(const MoveArgs &a, double m2, int *ke
                 kid = v[u];
             } else {
                 double g = m2 * v[u] - ki * sg[u];
-                if (better(g, key[u], bg, bc)) {
+                if (better(g, key[u], bg, bc, a.g.orig)) {
                     bg = g;
                     bc = key[u];
                 }
@@ -329,11 +332,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Argmax / sum over aligned groups of G lanes, G a runtime power of two.
-__device__ __forceinline__ void group_argmax_rt(double &g, int &c, int G) {
+__device__ __forceinline__ void group_argmax_rt(double &g, int &c, int G, const int32_t *orig) {
     for (int off = G >> 1; off > 0; off >>= 1) {
         double og = __shfl_xor(g, off);
         int oc = __shfl_xor(c, off);
-        if (better(og, oc, g, c)) {
+        if (better(og, oc, g, c, orig)) {
             g = og;
             c = oc;
         }
@@ -404,7 +407,7 @@ __device__ void small_unit(const MoveArgs &a, int bin, int G, int64_t unit, int 
         for (int q = 0; q < 2 * kSmallE; q++)
             if (gl + q * L < kSlots) take_slot(a, m2, keys, vals, gl + q * L, d, ki, bg, bc, kid, acc.keys);
     }
-    group_argmax_rt(bg, bc, L);
+    group_argmax_rt(bg, bc, L, a.g.orig);
     kid = group_sum_rt(kid, L);
     double gain = 0.0;
     bool mv = valid && decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
@@ -471,10 +474,10 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 5 : 4) k_move_small(Mov
 // ---------------------------------------------------------------- large
 
 // Block-wide argmax / sum through LDS; every thread gets the result.
-__device__ void block_argmax_sum(double &bg, int &bc, double &x) {
+__device__ void block_argmax_sum(double &bg, int &bc, double &x, const int32_t *orig) {
     __shared__ double sg[kBlock / kWave], sx[kBlock / kWave];
     __shared__ int sc[kBlock / kWave];
-    group_argmax<kWave>(bg, bc);
+    group_argmax<kWave>(bg, bc, orig);
     x = group_sum<kWave>(x);
     int w = threadIdx.x / kWave;
     if (lane_id() == 0) { sg[w] = bg; sc[w] = bc; sx[w] = x; }
@@ -484,7 +487,7 @@ __device__ void block_argmax_sum(double &bg, int &bc, double &x) {
     x = sx[0];
 #pragma unroll
     for (int q = 1; q < kBlock / kWave; q++) {
-        if (better(sg[q], sc[q], bg, bc)) { bg = sg[q]; bc = sc[q]; }
+        if (better(sg[q], sc[q], bg, bc, orig)) { bg = sg[q]; bc = sc[q]; }
         x += sx[q];
     }
     __syncthreads();
@@ -538,7 +541,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
         fold_table<kWave, 4>(a, m2, keys, vals, T, lane, d, ki, bg, bc, kid, acc.keys);
-        group_argmax<kWave>(bg, bc);
+        group_argmax<kWave>(bg, bc, a.g.orig);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
         bool mv = decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
@@ -607,7 +610,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(Mov
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
         fold_table<kBlock, 4>(a, m2, keys, vals, T, tid, d, ki, bg, bc, kid, acc.keys);
-        block_argmax_sum(bg, bc, kid);
+        block_argmax_sum(bg, bc, kid, a.g.orig);
         double gain = 0.0;
         bool mv = decide(m2, d, ki, kid, bg, bc, sgd, csd, best_single(a, d, csd, bc), &gain);
         if (mv)   // the thread's columns are still in registers (weights reloaded)
@@ -848,14 +851,14 @@ __device__ void hub_finish_block(const MoveArgs &a, int i, int P, Acc &acc) {
         for (int q = tid; q < P; q += kBlock) {
             double g = a.part_g[c0 + q];
             int c = a.part_c[c0 + q];
-            if (better(g, c, bg, bc)) {
+            if (better(g, c, bg, bc, a.g.orig)) {
                 bg = g;
                 bc = c;
             }
             kid += a.part_kid[c0 + q];
         }
     }
-    block_argmax_sum(bg, bc, kid);
+    block_argmax_sum(bg, bc, kid, a.g.orig);
     hub_decide(a, i, bg, bc, kid, P, acc);
     __syncthreads();
 }
@@ -960,7 +963,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
             double bg = -INFINITY, kid = 0.0;
             int bc = kIntMax;
             fold_table<kBlock, 8>(a, m2, tkeys, tvals, kBlockTable, tid, d, ki, bg, bc, kid, acc.keys);
-            block_argmax_sum(bg, bc, kid);
+            block_argmax_sum(bg, bc, kid, a.g.orig);
             if (tid == 0) {
                 a.part_g[k] = bg;
                 a.part_c[k] = bc;
@@ -1019,7 +1022,7 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_part(MoveArgs a) {
             for (int u = 0; u < 4; u++)
                 if (key[u] != kEmpty) fold_key(a, m2, key[u], v[u], d, ki, bg, bc, kid);
         }
-        block_argmax_sum(bg, bc, kid);
+        block_argmax_sum(bg, bc, kid, a.g.orig);
         if (threadIdx.x == 0) {
             a.part_g[k] = bg;
             a.part_c[k] = bc;
@@ -1049,10 +1052,10 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_final(MoveArgs a) {
         for (int q = lane; q < nch; q += kWave) {
             double g = a.part_g[c0 + q];
             int c = a.part_c[c0 + q];
-            if (better(g, c, bg, bc)) { bg = g; bc = c; }
+            if (better(g, c, bg, bc, a.g.orig)) { bg = g; bc = c; }
             kid += a.part_kid[c0 + q];
         }
-        group_argmax<kWave>(bg, bc);
+        group_argmax<kWave>(bg, bc, a.g.orig);
         kid = group_sum<kWave>(kid);
         double gain = 0.0;
         const int csd = a.csize[d];

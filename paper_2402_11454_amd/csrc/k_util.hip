@@ -161,7 +161,9 @@ __global__ void __launch_bounds__(kBlock) k_weights_to_f64(const float *in, doub
 // rows: each lane sums its own row if it has at most kShortRow entries (most
 // rows of sparse graphs), then the wavefront sums the longer ones together,
 // one at a time.  Sums of weights are exact (weight grid), so the order of
-// the additions does not matter.
+// the additions does not matter.  On a level in degree order the first
+// g.nlong rows (the long ones, side by side) are left to
+// launch_vertex_weights_long, which cuts them into equal entry chunks.
 constexpr int kShortRow = 32;
 
 template <int WT>
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, d
     const int lane = lane_id(), w = threadIdx.x / kWave;
     double blk = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t r0 = (int64_t)blockIdx.x * kBlock + w * kWave; r0 < g.n; r0 += stride) {
+    for (int64_t r0 = g.nlong + (int64_t)blockIdx.x * kBlock + w * kWave; r0 < g.n; r0 += stride) {
         const int64_t i = r0 + lane;
         int64_t b = 0, d = 0;
         if (i < g.n) {
@@ -178,7 +180,9 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, d
             d = g.deg[i];   // rows may be gapped
         }
         double s = 0.0;
-        const bool shortrow = d <= kShortRow;
+        // in degree order a wavefront's 64 rows have about the same length:
+        // every lane sums its own row up to the long rows' bound
+        const bool shortrow = d <= (g.orig ? (int64_t)kLongRow : (int64_t)kShortRow);
         if (shortrow)
             for (int64_t k = b; k < b + d; k++) s += edge_weight<WT>(g.w, k);
         unsigned long long longs = __ballot(!shortrow);
@@ -368,7 +372,9 @@ void launch_weights_to_f64(const float *in, double *out, int64_t nnz, hipStream_
 
 void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s) {
     if (g.n == 0) return;
-    unsigned gr = grid_for(g.n, kBlock, 8192);
+    launch_vertex_weights_long(g, K, M2, s);
+    if (g.nlong >= g.n) return;
+    unsigned gr = grid_for(g.n - g.nlong, kBlock, 8192);
     if (g.wt == W_UNIT)
         k_vertex_weights<W_UNIT><<<gr, kBlock, 0, s>>>(g, K, M2);
     else if (g.wt == W_F32)
