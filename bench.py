@@ -82,7 +82,7 @@ def parse():
                         "stream, scans side by side")
     p.add_argument("--cpu-sample", type=int, default=4, help="the CPU baseline scans every k-th vertex")
     p.add_argument("--vertex-order", default="auto", choices=sorted(ORDERS),
-                   help="storage order of the graph inside the runs (auto: degree order from 2^27 entries)")
+                   help="storage order of the graph inside the runs (auto: degree order from 2^25 entries)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-untimed", action="store_true", help="skip the runs without events")
     p.add_argument("--kernel-class", default="", choices=[""] + sorted(KERNEL_NAMES),
@@ -368,7 +368,7 @@ def main():
                                f"{a.theta}, trained on DC-SBM traces), plain runs beside",
                    "n": g.n, "nnz": g.nnz, "weight_grid_exp": grid[0], "weights_moved_to_grid": grid[1],
                    "vertex_order": a.vertex_order + (" (degree order at this size)" if a.vertex_order == "auto"
-                                                     and g.nnz >= 1 << 27 else ""),
+                                                     and g.nnz >= 1 << 25 else ""),
                    "modularity": round(q_l, 6), "disconnected": disc_l, "passes": st_l["passes"],
                    "iterations": st_l["iterations"], "scanned_entries": st_l["scanned_entries"],
                    "pruned": st_l["pruned"], "confirm_sweeps": st_l["confirm_sweeps"],

@@ -87,7 +87,7 @@ def short(name: str) -> str:
     return s.replace("void ", "")
 
 
-def summarize(fetch_db, write_db, cmd, workload: str, runs: int = 2):
+def summarize(fetch_db, write_db, cmd, workload: str, runs: int = 2, tag: str = ""):
     sys.path.insert(0, ROOT)
     from bench import kernel_source_hash
     fe = per_kernel(fetch_db, "FETCH_SIZE")
@@ -121,10 +121,11 @@ def summarize(fetch_db, write_db, cmd, workload: str, runs: int = 2):
     out = {"workload": workload, "command": cmd, "runs": runs, "copy_kernel": short(copy),
            "scale_fetch": f_scale, "scale_write": w_scale, "kernels": kernels}
     prof = os.path.join(ROOT, "profiles")
-    with open(os.path.join(prof, f"traffic_{workload}.json"), "w") as f:
+    with open(os.path.join(prof, f"traffic_{workload}{tag}.json"), "w") as f:
         json.dump(out, f, indent=1)
-    with open(os.path.join(prof, f"traffic_{workload}.md"), "w") as f:
-        f.write(f"# Memory traffic per dispatch (FETCH_SIZE / WRITE_SIZE): GSP-Louvain on {workload}\n\n")
+    with open(os.path.join(prof, f"traffic_{workload}{tag}.md"), "w") as f:
+        kind = "plain" if tag == "_plain" else "learned-pruned"
+        f.write(f"# Memory traffic per dispatch (FETCH_SIZE / WRITE_SIZE): {kind} GSP-Louvain on {workload}\n\n")
         f.write(f"Command (two passes, one counter each):\n\n```\n{cmd}\n```\n\n")
         f.write(f"Scale: y = 2x over {COPY_BYTES} bytes (`{short(copy)[:60]}`) reads {fe[copy][1]:.0f} KiB "
                 f"(FETCH_SIZE) -> factor {f_scale:.4f}; write factor {w_scale:.4f}.\n\n")
@@ -135,7 +136,9 @@ def summarize(fetch_db, write_db, cmd, workload: str, runs: int = 2):
 
 
 def phase_times(out_path: str, runs: int, workload: str):
-    """Mean phase wall times (ms) of `runs` runs after two warm-up runs."""
+    """Mean phase wall times (ms) of `runs` plain runs after two warm-up
+    runs, and the algorithmic bytes of each kernel class (the library's
+    counts) from one more run with per-kernel events."""
     sys.path.insert(0, ROOT)
     import paper_2402_11454_amd as gsp
     from bench import make_graph
@@ -151,8 +154,10 @@ def phase_times(out_path: str, runs: int, workload: str):
         for f in acc:
             acc[f] += st[f] / runs
         print(f"[phases] run {k + 1}/{runs}: {st['ms_total']:.3f} ms", flush=True)
+    ctx.run(1e-2, 10, timing=2)
+    alg = {k: v["bytes"] for k, v in ctx.stats()["kernels"].items()}
     ctx.close()
-    out = {"workload": workload, "n": int(g.n), "nnz": int(g.nnz), "runs": runs, **acc}
+    out = {"workload": workload, "n": int(g.n), "nnz": int(g.nnz), "runs": runs, **acc, "algorithmic_bytes": alg}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out), flush=True)
@@ -163,6 +168,10 @@ def phase_times(out_path: str, runs: int, workload: str):
 # phase's bytes are a lower bound while its time includes them
 PHASE_OF = (("move", ("k_move", "k_hub", "k_gate")), ("split", ("k_split",)),
             ("aggregate", ("k_agg", "k_member_degrees")))
+# the library's kernel classes of each phase (algorithmic bytes)
+PHASE_CLASSES = {"move": ("move_small", "move_wave", "move_block", "move_hub", "move_hub_finish", "move_hub_gather",
+                          "move_apply", "frontier", "gate"),
+                 "split": ("split",), "aggregate": ("aggregate",)}
 
 
 def phases(traffic_json: str, times_json: str, cmd: str):
@@ -177,22 +186,32 @@ def phases(traffic_json: str, times_json: str, cmd: str):
         if ph:
             byts[ph] += v["bytes_per_launch"] * v["dispatches"] / runs
     ms = {"move": tm["ms_move"], "split": tm["ms_split"], "aggregate": tm["ms_aggregate"]}
+    alg = {p: sum(tm.get("algorithmic_bytes", {}).get(k, 0.0) for k in cl) for p, cl in PHASE_CLASSES.items()}
     w = tm["workload"]
     path = os.path.join(ROOT, "profiles", f"phases_{w}.md")
     with open(path, "w") as f:
-        f.write(f"# Memory traffic per phase: plain GSP-Louvain on {w} "
-                f"(n={tm['n']}, {tm['nnz']} entries)\n\n")
+        f.write(f"# Bytes per phase: plain GSP-Louvain on {w} (n={tm['n']}, {tm['nnz']} entries)\n\n")
         f.write(f"Commands:\n\n```\n{cmd}\n```\n\n")
-        f.write(f"Bytes: the counters' FETCH + WRITE bytes of one run ({traffic_json}, {runs} run(s) under counters) "
-                f"of the kernels that belong to one phase (fills, scans and renumbering shared by the phases are "
-                f"left out); FETCH_SIZE / WRITE_SIZE count the L2's traffic to memory, i.e. HBM and the Infinity "
-                f"Cache in front of it.  Time: the phases' wall times from HIP events, mean of {tm['runs']} runs "
-                f"with timing = 1 (scans side by side, sweeps replayed from graphs); whole run "
-                f"{tm['ms_total']:.3f} ms (other steps {tm['ms_other']:.3f} ms).  Peak: HBM 8000 GB/s.\n\n")
-        f.write("| phase | GB per run | ms per run | GB/s | of HBM peak |\n|---|---:|---:|---:|---:|\n")
+        f.write(f"Time: the phases' wall times from HIP events, mean of {tm['runs']} runs with timing = 1 (scans "
+                f"side by side, sweeps replayed from graphs); whole run {tm['ms_total']:.3f} ms (other steps "
+                f"{tm['ms_other']:.3f} ms).\n\n"
+                f"Algorithmic bytes: the bytes the method must move by the library's per-class counts (one run "
+                f"with per-kernel events); their rate is the one compared with the HBM peak (8000 GB/s).\n\n"
+                f"Counter bytes: FETCH + WRITE of one run ({traffic_json}, {runs} run(s) under counters) of the "
+                f"kernels that belong to one phase (fills, scans and renumbering shared by the phases left out), "
+                f"scaled by an elementwise kernel of known traffic.  FETCH_SIZE / WRITE_SIZE count the L2's "
+                f"requests to the memory side, Infinity Cache hits included, and every random 4- or 8-byte "
+                f"gather moves a whole line: this rate is memory-side traffic, an upper bound of HBM traffic, "
+                f"not HBM bandwidth.\n\n")
+        f.write("| phase | ms per run | algorithmic GB per run | algorithmic GB/s | of HBM peak | counter GB per run "
+                "| counter GB/s | counter / algorithmic |\n|---|---:|---:|---:|---:|---:|---:|---:|\n")
         for p in ("move", "split", "aggregate"):
-            gbs = byts[p] / 1e9 / (ms[p] * 1e-3) if ms[p] > 0 else 0.0
-            f.write(f"| {p} | {byts[p] / 1e9:.3f} | {ms[p]:.3f} | {gbs:.0f} | {gbs / 8000.0:.1%} |\n")
+            t = ms[p] * 1e-3
+            ga = alg[p] / 1e9 / t if t > 0 else 0.0
+            gc = byts[p] / 1e9 / t if t > 0 else 0.0
+            amp = f"{byts[p] / alg[p]:.1f}x" if alg[p] > 0 else ""
+            f.write(f"| {p} | {ms[p]:.3f} | {alg[p] / 1e9:.3f} | {ga:.0f} | {ga / 8000.0:.1%} | "
+                    f"{byts[p] / 1e9:.3f} | {gc:.0f} | {amp} |\n")
     print(open(path).read())
 
 
@@ -298,6 +317,7 @@ if __name__ == "__main__":
     ap.add_argument("--cmd", default="")
     ap.add_argument("--workload", default="rmat26")
     ap.add_argument("--learned", action="store_true", help="learned-pruned runs (bench.py's timed runs)")
+    ap.add_argument("--tag", default="", help="suffix of the summary's file names (e.g. _plain)")
     ap.add_argument("--phase-times", default="", help="write the phases' mean wall times to this JSON")
     ap.add_argument("--phases", nargs=2, help="TRAFFIC_JSON TIMES_JSON: per-phase summary")
     ap.add_argument("--kernel-summary", nargs=2, metavar=("DB", "OUT_MD"),
@@ -316,7 +336,7 @@ if __name__ == "__main__":
     if a.run:
         run_workload(a.runs, a.workload, a.learned)
     if a.summarize:
-        summarize(a.summarize[0], a.summarize[1], a.cmd, a.workload, a.runs)
+        summarize(a.summarize[0], a.summarize[1], a.cmd, a.workload, a.runs, a.tag)
     if a.phase_times:
         phase_times(a.phase_times, 3, a.workload)
     if a.phases:

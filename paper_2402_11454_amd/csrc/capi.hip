@@ -907,20 +907,28 @@ gsp_status ensure_levels(gsp_ctx *ctx) {
 
 // Whether gsp_run stores the input graph in degree order (vertex_order;
 // batches never).
-constexpr int64_t kAutoOrderEntries = int64_t(1) << 27;
+constexpr int64_t kAutoOrderEntries = int64_t(1) << 25;
 bool wants_order(const gsp_ctx *ctx, const gsp_options &opt, bool batch, int32_t max_passes) {
     if (batch || max_passes == 0 || ctx->n == 0 || ctx->nnz == 0) return false;
     if (opt.vertex_order == GSP_ORDER_DEGREE) return true;
     return opt.vertex_order == GSP_ORDER_AUTO && ctx->nnz >= kAutoOrderEntries;
 }
 
-// Builds the input graph's copy in degree order once per load.
-gsp_status ensure_order(gsp_ctx *ctx) {
-    if (ctx->ordered) return GSP_OK;
+// Builds the input graph's copy in degree order once per load (again when
+// a run asks for another number of sub-rounds: the layout groups the
+// shorter rows by sub-round).
+gsp_status ensure_order(gsp_ctx *ctx, int rounds) {
+    if (ctx->ordered && ctx->ord.rounds == rounds) return GSP_OK;
+    if (ctx->ordered) {
+        ctx->drop_sweep_graphs();   // captured sweeps hold the old layout's work lists
+        HIP_TRY(order_by_degree(level0(ctx), ctx->sc, ctx->ord, rounds, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return GSP_OK;
+    }
     const int64_t n = ctx->n, nnz = ctx->nnz;
     const int wb = ctx->wt0 == W_UNIT ? 0 : (ctx->wt0 == W_F32 ? 4 : 8);
     if (ctx->mem_limit) {
-        uint64_t need = (uint64_t)n * 20 + (uint64_t)(n + 1) * 8 + (uint64_t)nnz * (4 + wb) + 64;
+        uint64_t need = (uint64_t)n * 20 + (uint64_t)(n + 1) * 8 + (uint64_t)nnz * (4 + wb) + 16 * kOrderBucketsMax + 64;
         if (ctx->mem_used + need > ctx->mem_limit)
             return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached (degree order)");
     }
@@ -934,9 +942,10 @@ gsp_status ensure_order(gsp_ctx *ctx) {
     if (!(o.col = ctx->dalloc<int32_t>(nnz, &e))) return fail("hipMalloc(order columns)");
     if (wb == 4 && !(o.w = ctx->dalloc<float>(nnz, &e))) return fail("hipMalloc(order weights)");
     if (wb == 8 && !(o.w = ctx->dalloc<double>(nnz, &e))) return fail("hipMalloc(order weights)");
+    if (!(o.hist = ctx->dalloc<unsigned long long>(2 * kOrderBucketsMax, &e))) return fail("hipMalloc(order counters)");
     double *K = ctx->dalloc<double>(n, &e);
     if (!K) return fail("hipMalloc(order K)");
-    HIP_TRY(order_by_degree(level0(ctx), ctx->sc, o, ctx->stream));
+    HIP_TRY(order_by_degree(level0(ctx), ctx->sc, o, rounds, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->ord = o;
     ctx->Kord = K;
@@ -1338,7 +1347,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     gsp_status st = ensure_levels(ctx);
     if (st != GSP_OK) return st;
     const bool ordered = wants_order(ctx, opt, batch, max_passes);
-    if (ordered && (st = ensure_order(ctx)) != GSP_OK) return st;
+    if (ordered && (st = ensure_order(ctx, opt.sub_rounds)) != GSP_OK) return st;
     hipStream_t s = ctx->stream;
     ctx->have_result = false;
     ctx->have_batch_result = false;

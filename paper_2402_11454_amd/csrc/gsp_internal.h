@@ -50,7 +50,10 @@ struct DegreeOrder {
     int32_t *col = nullptr;
     void *w = nullptr;
     int64_t nlong = 0;
+    unsigned long long *hist = nullptr;   // 2 kOrderBucketsMax counters (bucket sizes, cursors)
+    int rounds = 0;                       // the sub-rounds the short rows are grouped by
 };
+constexpr int kOrderBucketsMax = 128 * (kMaxRounds + 1);
 
 // Vertex work lists of a level: every vertex with deg > 0 sits in bucket
 // (bin of its degree, its sub-round); bl holds the buckets back to back, in
@@ -222,8 +225,10 @@ struct Scratch;
 // their part of *M2; the rows after them are launch_vertex_weights' part.
 void launch_vertex_weights_long(const Level &g, double *K, double *M2, hipStream_t s);
 // Fills o (arrays allocated by the caller: orig, rank, deg n; off n + 1;
-// col, w nnz) with g in degree order and sets o.nlong.  Synchronizes s.
-hipError_t order_by_degree(const Level &g, Scratch &sc, DegreeOrder &o, hipStream_t s);
+// col, w nnz; hist 2 kOrderBucketsMax) with g in degree order, its shorter
+// rows grouped by their sub-round out of `rounds`, and sets o.nlong and
+// o.rounds.  Synchronizes s.
+hipError_t order_by_degree(const Level &g, Scratch &sc, DegreeOrder &o, int rounds, hipStream_t s);
 // lab[v] <- the smallest orig[u] over the u with lab[u] = lab[v] (tmp: n ints).
 void launch_labels_min_orig(int32_t *lab, const int32_t *orig, int64_t n, int32_t *tmp, hipStream_t s);
 // out[v] <- orig[lab[v]].

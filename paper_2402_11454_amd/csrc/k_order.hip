@@ -5,7 +5,9 @@
 // membership and community-total words each sit in a different cache line,
 // and every scan of an entry pulls a whole line for one 4- or 8-byte word.
 // Here the vertices are renumbered by degree class, largest first, so that
-// the words most entries gather share lines and stay in the caches.  The
+// the words most entries gather share lines and stay in the caches; the
+// shorter rows are grouped by sub-round first, so that a sub-round reads
+// its vertices' rows and per-vertex words as contiguous ranges.  The
 // method's results do not change: wherever it orders vertex or community ids
 // (ties, the singleton rule, sub-rounds, traces, the numbering of
 // communities) it compares the caller's ids, orig[v].
@@ -13,8 +15,11 @@
 // Layout of the ordered copy: vertex p is the caller's vertex orig[p];
 // rank[orig[p]] = p; row p holds row orig[p]'s entries, in the same order,
 // with every column v replaced by rank[v] and the same weights.  Rows with
-// at least kLongRow entries come first (p < nlong), so the long rows are
-// one contiguous entry range.
+// at least kLongRow entries come first (p < nlong, by degree class), so the
+// long rows are one contiguous entry range; then, for each sub-round in
+// turn, its other rows by degree class.
+#include <vector>
+
 #include "gsp_internal.h"
 
 namespace gsp {
@@ -30,6 +35,8 @@ constexpr int kShortCopy = 32;     // rows up to this length are copied by one l
 // leading one), largest degrees first, empty rows last.  d >= kLongRow =
 // 2^kLongLog exactly when the class is at most kLongClass.
 constexpr int kLongClass = kOrderClasses - 2 - 4 * kLongLog;
+constexpr int kOrderBuckets = kOrderClasses * (kMaxRounds + 1);   // at most
+static_assert(kOrderBuckets == kOrderBucketsMax, "bucket bound");
 
 __device__ __forceinline__ int degree_class(int d) {
     if (d <= 0) return kOrderClasses - 1;
@@ -38,14 +45,22 @@ __device__ __forceinline__ int degree_class(int d) {
     return kOrderClasses - 2 - (4 * e + q);
 }
 
-__global__ void __launch_bounds__(kBlock) k_order_count(const int32_t *deg, int64_t n, unsigned long long *hist) {
-    __shared__ unsigned int h[kOrderClasses];
-    for (int k = threadIdx.x; k < kOrderClasses; k += kBlock) h[k] = 0;
+// Bucket of vertex v (the caller's id) with d entries: its degree class if
+// the row is long, else kOrderClasses * (1 + its sub-round) + its class.
+__device__ __forceinline__ int order_bucket(int64_t v, int d, int shift) {
+    const int c = degree_class(d);
+    return c <= kLongClass ? c : kOrderClasses * (1 + sub_round_of(v, shift)) + c;
+}
+
+__global__ void __launch_bounds__(kBlock) k_order_count(const int32_t *deg, int64_t n, int shift, int nb,
+                                                       unsigned long long *hist) {
+    __shared__ unsigned int h[kOrderBuckets];
+    for (int k = threadIdx.x; k < nb; k += kBlock) h[k] = 0;
     __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        atomicAdd(&h[degree_class(deg[i])], 1u);
+        atomicAdd(&h[order_bucket(i, deg[i], shift)], 1u);
     __syncthreads();
-    for (int k = threadIdx.x; k < kOrderClasses; k += kBlock)
+    for (int k = threadIdx.x; k < nb; k += kBlock)
         if (h[k]) atomicAdd(&hist[k], (unsigned long long)h[k]);
 }
 
@@ -53,23 +68,23 @@ __global__ void __launch_bounds__(kBlock) k_order_count(const int32_t *deg, int6
 // position; each tile reserves its positions with one atomic per class.
 // (The order inside a class depends on the atomics' order; nothing but
 // cache behaviour depends on it.)
-__global__ void __launch_bounds__(kBlock) k_order_place(const int32_t *deg, int64_t n, unsigned long long *cursor,
-                                                       int32_t *orig, int32_t *rank) {
-    __shared__ unsigned int lcnt[kOrderClasses];
-    __shared__ unsigned long long lbase[kOrderClasses];
+__global__ void __launch_bounds__(kBlock) k_order_place(const int32_t *deg, int64_t n, int shift, int nb,
+                                                       unsigned long long *cursor, int32_t *orig, int32_t *rank) {
+    __shared__ unsigned int lcnt[kOrderBuckets];
+    __shared__ unsigned long long lbase[kOrderBuckets];
     for (int64_t t0 = blockIdx.x * (int64_t)kOrderTile; t0 < n; t0 += (int64_t)gridDim.x * kOrderTile) {
-        for (int k = threadIdx.x; k < kOrderClasses; k += kBlock) lcnt[k] = 0;
+        for (int k = threadIdx.x; k < nb; k += kBlock) lcnt[k] = 0;
         __syncthreads();
         int cls[4];
         unsigned int r[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int64_t v = t0 + u * kBlock + threadIdx.x;
-            cls[u] = v < n ? degree_class(deg[v]) : 0;
+            cls[u] = v < n ? order_bucket(v, deg[v], shift) : 0;
             r[u] = v < n ? atomicAdd(&lcnt[cls[u]], 1u) : 0u;
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < kOrderClasses; k += kBlock)
+        for (int k = threadIdx.x; k < nb; k += kBlock)
             if (lcnt[k]) lbase[k] = atomicAdd(&cursor[k], (unsigned long long)lcnt[k]);
         __syncthreads();
 #pragma unroll
@@ -229,27 +244,33 @@ inline unsigned grid_of(int64_t n, int64_t per_block, unsigned cap) {
 
 }  // namespace
 
-hipError_t order_by_degree(const Level &g, Scratch &sc, DegreeOrder &o, hipStream_t s) {
+hipError_t order_by_degree(const Level &g, Scratch &sc, DegreeOrder &o, int rounds, hipStream_t s) {
     const int64_t n = g.n;
     o.nlong = 0;
+    o.rounds = rounds;
     if (n == 0) return hipSuccess;
-    unsigned long long *hist = sc.u64;   // kOrderClasses counters, then the cursors
-    static_assert(2 * kOrderClasses <= kScratchU64, "order counters exceed the scratch counters");
-    hipError_t e = hipMemsetAsync(hist, 0, sizeof(unsigned long long) * kOrderClasses, s);
+    int shift = 0;
+    while ((1 << shift) < rounds) shift++;
+    const int nb = kOrderClasses * (rounds + 1);
+    unsigned long long *hist = o.hist, *cursor = o.hist + kOrderBuckets;
+    hipError_t e = hipMemsetAsync(hist, 0, sizeof(unsigned long long) * nb, s);
     if (e != hipSuccess) return e;
-    k_order_count<<<grid_of(n, kBlock * 16, 4096), kBlock, 0, s>>>(g.deg, n, hist);
-    unsigned long long h[kOrderClasses];
-    if ((e = hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    k_order_count<<<grid_of(n, kBlock * 16, 4096), kBlock, 0, s>>>(g.deg, n, shift, nb, hist);
+    std::vector<unsigned long long> h(nb), cur(nb);
+    if ((e = hipMemcpyAsync(h.data(), hist, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    unsigned long long cur[kOrderClasses], at = 0;
-    for (int k = 0; k < kOrderClasses; k++) {
+    unsigned long long at = 0;
+    for (int k = 0; k < nb; k++) {
         cur[k] = at;
         at += h[k];
         if (k == kLongClass) o.nlong = (int64_t)at;
     }
-    if ((e = hipMemcpyAsync(hist + kOrderClasses, cur, sizeof(cur), hipMemcpyHostToDevice, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(cursor, cur.data(), sizeof(unsigned long long) * nb, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
         return e;
-    k_order_place<<<grid_of(n, kOrderTile, 4096), kBlock, 0, s>>>(g.deg, n, hist + kOrderClasses, o.orig, o.rank);
+    k_order_place<<<grid_of(n, kOrderTile, 4096), kBlock, 0, s>>>(g.deg, n, shift, nb, cursor, o.orig, o.rank);
     k_order_degrees<<<grid_of(n, kBlock * 4, 8192), kBlock, 0, s>>>(o.orig, g.deg, n, o.deg);
     scan_exclusive_i32_to_i64(o.deg, o.off, n, sc.scan_tmp, s);
     int64_t long_entries = 0;

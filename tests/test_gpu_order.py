@@ -7,8 +7,9 @@ The graphs cover many exact ties (unit weights: the tie-break and the
 singleton rule compare the caller's ids), long rows (at least 256 entries,
 copied and summed in entry chunks), isolated vertices, self-loops and fp32 /
 fp64 weights; the options cover every split mode and split algorithm, the
-return-move option, graph replay on and off, and the learned gate with
-traces.
+return-move option, graph replay on and off, the learned gate with traces,
+and other numbers of sub-rounds (the layout groups the shorter rows by
+sub-round and is rebuilt for another number).
 """
 import math
 
@@ -195,3 +196,17 @@ def test_degree_order_errors_and_defaults(ctx):
     ctx.load_graph(h)
     ref = oracle.louvain(h, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
     np.testing.assert_array_equal(ctx.louvain(1e-2, 10, **DEG).membership, ref.membership)
+
+
+@pytest.mark.parametrize("name", ["rmat15w", "sbm10k"])
+def test_degree_order_other_sub_rounds(ctx, name):
+    """The layout groups the shorter rows by sub-round; a run with another
+    number of sub-rounds rebuilds it, and every run still equals the run in
+    the loaded order."""
+    g = _graph(name)
+    ctx.load_graph(g)
+    for rounds in (8, 4, 1, 8, 16):
+        ref = ctx.louvain(1e-2, 10, sub_rounds=rounds, **LOADED)
+        _same_run(ctx.louvain(1e-2, 10, sub_rounds=rounds, **DEG), ref)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=4)
+    np.testing.assert_array_equal(ctx.louvain(1e-2, 10, sub_rounds=4, **DEG).membership, ref.membership)
