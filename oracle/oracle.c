@@ -684,13 +684,17 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
     if (n < 0 || !opt || opt->max_passes < 0) return -1;
     if (stats) memset(stats, 0, sizeof(*stats));
     int64_t nnz = off[n];
-    /* G' starts as G */
+    /* G' starts as G itself (read only); the super-vertex graphs G'' go to
+     * two buffers of G's size in turn (pages only touched as they fill) */
     int64_t *goff = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
     int32_t *gcol = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
     double *gw = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
     int64_t *noff = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
     int32_t *ncol = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
     double *nw = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    const int64_t *loff = off;
+    const int32_t *lcol = col;
+    const double *lw = w;
     double *K = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double *sigma = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     int32_t *cm = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
@@ -700,9 +704,6 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         free(K); free(sigma); free(cm); free(lab);
         return -1;
     }
-    memcpy(goff, off, ((size_t)n + 1) * sizeof(int64_t));
-    if (nnz) memcpy(gcol, col, (size_t)nnz * sizeof(int32_t));
-    if (nnz) memcpy(gw, w, (size_t)nnz * sizeof(double));
     int64_t gn = n;
     for (int64_t v = 0; v < n; v++) memb_out[v] = (int32_t)v;       /* C <- [0 .. |V|) */
     double M2 = orc_vertex_weights(n, off, col, w, NULL);            /* 2m of G */
@@ -711,23 +712,23 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
     for (int32_t lp = 0; lp < opt->max_passes; lp++) {
         passes = lp + 1;
         /* Sigma' <- K' <- vertexWeights(G'); C' <- [0 .. |V'|); all unprocessed */
-        orc_vertex_weights(gn, goff, gcol, gw, K);
+        orc_vertex_weights(gn, loff, lcol, lw, K);
         for (int64_t i = 0; i < gn; i++) { sigma[i] = K[i]; cm[i] = (int32_t)i; }
         int32_t li;
         if (opt->sync_moves && (opt->prune_params || opt->trace)) {
             int64_t c4[4];
-            li = orc_move_sync_gated(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds,
+            li = orc_move_sync_gated(gn, loff, lcol, lw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds,
                                      opt->prune_params, opt->prune_theta_logit, lp, opt->trace, NULL, NULL, c4,
                                      opt->return_moves, !(opt->prune_params && opt->confirm_final));
             if (stats)
                 for (int q = 0; q < 4; q++) stats->counters[q] += c4[q];
         } else if (opt->sync_moves)
-            li = orc_move_sync(gn, goff, gcol, gw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds, NULL, NULL,
+            li = orc_move_sync(gn, loff, lcol, lw, M2, K, cm, tau, opt->max_iterations, opt->sync_rounds, NULL, NULL,
                                opt->return_moves);
         else
-            li = orc_move_async(gn, goff, gcol, gw, M2, K, cm, sigma, tau, opt->max_iterations, NULL);
+            li = orc_move_async(gn, loff, lcol, lw, M2, K, cm, sigma, tau, opt->max_iterations, NULL);
         if (opt->split_mode == 0) {                                   /* C' <- split(G', C') */
-            orc_split_bfs(gn, goff, gcol, cm, lab);
+            orc_split_bfs(gn, loff, lcol, cm, lab);
             memcpy(cm, lab, (size_t)gn * sizeof(int32_t));
         }
         int64_t ng = orc_renumber(gn, cm, lab);                       /* |Gamma| */
@@ -746,9 +747,10 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         if (li <= 1) break;                                           /* globally converged */
         if ((double)ng / (double)gn > opt->aggregation_tolerance) break; /* low shrink */
         if (lp == opt->max_passes - 1) break;                          /* G'' would be unused */
-        int64_t nn = orc_aggregate(gn, goff, gcol, gw, cm, ng, noff, ncol, nw, nnz);
+        int64_t nn = orc_aggregate(gn, loff, lcol, lw, cm, ng, noff, ncol, nw, nnz);
         if (nn < 0) { passes = -1; break; }
-        int64_t *to = goff; goff = noff; noff = to;
+        loff = noff; lcol = ncol; lw = nw;                              /* G' <- G'' */
+        int64_t *to = goff; goff = noff; noff = to;                    /* the next G'' goes to the other buffer */
         int32_t *tc = gcol; gcol = ncol; ncol = tc;
         double *tw = gw; gw = nw; nw = tw;
         gn = ng;

@@ -6,7 +6,7 @@ without rerunning that loop in every test.
 Only the oracle and the seeded input generators are used.
 
     python tests/golden/make_async_q.py              # R-MAT 20, DC-SBM 4M (seed 1000): a few minutes
-    python tests/golden/make_async_q.py rmat26       # only R-MAT 26 (needs ~80 GB of host memory, ~15 min)
+    python tests/golden/make_async_q.py rmat26       # only R-MAT 26 (about 50 GB of host memory)
 """
 import json
 import os
@@ -43,6 +43,7 @@ def main():
         t = time.time()
         g = make()
         print(f"{name}: n={g.n} nnz={g.nnz} generated in {time.time() - t:.0f}s", flush=True)
+        g = oracle.CSR.of(g)   # the oracle's types (fp64 weights on the grid); the generator's arrays go
         t = time.time()
         oracle.set_verbose(True)
         r = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=False)
