@@ -244,10 +244,10 @@ def main():
     import torch
 
     import paper_2402_11454_amd as gsp
-    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, DEFAULT_THETA, load_params
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, THETA_BY_CLASS, load_params
 
-    if a.theta is None:
-        a.theta = DEFAULT_THETA
+    if a.theta is None:   # the shipped network's threshold for this graph class
+        a.theta = THETA_BY_CLASS[WORKLOADS[a.workload]["kind"]]
     t0 = time.time()
     g = make_graph(a.workload)
     log(f"generated {a.workload}: n={g.n} nnz={g.nnz} in {time.time() - t0:.1f}s")
@@ -364,8 +364,9 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{a.workload}: {w['text']}; GSP-Louvain tol {a.tolerance}, <= {a.max_passes} "
-                               f"passes, 8 sub-rounds; value = learned-pruned runs (8-64-64-1 gate, theta "
-                               f"{a.theta}, trained on DC-SBM traces), plain runs beside",
+                               f"passes, 8 sub-rounds; value = learned-pruned runs (8-64-64-1 gate trained on "
+                               f"DC-SBM traces, theta {a.theta}: this class's threshold, chosen on a held-out "
+                               f"graph), plain runs beside",
                    "n": g.n, "nnz": g.nnz, "weight_grid_exp": grid[0], "weights_moved_to_grid": grid[1],
                    "vertex_order": a.vertex_order + (" (degree order at this size)" if a.vertex_order == "auto"
                                                      and g.nnz >= 1 << 25 else ""),

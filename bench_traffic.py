@@ -37,7 +37,7 @@ def run_workload(runs: int, workload: str, learned: bool):
     import torch
     import paper_2402_11454_amd as gsp
     from bench import make_graph
-    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, DEFAULT_THETA, load_params
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, THETA_BY_CLASS, load_params
     torch.cuda.init()
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
@@ -51,7 +51,8 @@ def run_workload(runs: int, workload: str, learned: bool):
     kw = {}
     if learned:
         ctx.pruner_set(load_params(DEFAULT_OUT))
-        kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=DEFAULT_THETA)
+        from bench import WORKLOADS
+        kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=THETA_BY_CLASS[WORKLOADS[workload]["kind"]])
     for k in range(runs):
         ctx.run(1e-2, 10, **kw)
         print(f"[pmc] run {k + 1}/{runs}", flush=True)

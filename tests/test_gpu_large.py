@@ -17,6 +17,8 @@ pass at this size in a test, so the checks are:
     with numpy on the host; no internally disconnected community; the split
     of the result is the result; and, where the asynchronous oracle's
     modularity is stored (tests/golden/async_q.json), Q >= Q_async - 0.005.
+  * the shipped network at the R-MAT class's threshold: Q within 0.005 of
+    the plain run's, no disconnected community.
 
 Needs about 60 GB of host memory and 150 GB of device memory (a few
 minutes, most of it generating the graph).
@@ -123,3 +125,20 @@ def test_whole_run_properties_and_repeat(big):
     if ref is not None:
         assert ref["nnz"] == g.nnz
         assert res.modularity >= ref["modularity"] - 0.005, (res.modularity, ref["modularity"])
+
+
+def test_shipped_network_quality(big):
+    """The shipped network at the R-MAT class's threshold (chosen on the
+    held-out R-MAT 26 graph of seed 27): modularity within 0.005 of the plain
+    run's, no internally-disconnected community, pruning happened."""
+    from paper_2402_11454_amd.train_pruner import DEFAULT_OUT, THETA_BY_CLASS, load_params
+    g, w, S, moved, ctx = big
+    plain = ctx.louvain(tolerance=1e-2, max_passes=10)
+    ctx.pruner_set(load_params(DEFAULT_OUT))
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED,
+                      prune_threshold=THETA_BY_CLASS["rmat"])
+    print(f"[large] shipped gate: Q={res.modularity:.6f} plain {plain.modularity:.6f} "
+          f"iterations={res.stats['iterations']} pruned={res.stats['pruned']}", flush=True)
+    assert res.stats["pruned"] > 0
+    assert abs(res.modularity - plain.modularity) <= 0.005
+    assert ctx.count_disconnected(res.membership) == 0
