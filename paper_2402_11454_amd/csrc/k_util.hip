@@ -180,9 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, d
             d = g.deg[i];   // rows may be gapped
         }
         double s = 0.0;
-        // in degree order a wavefront's 64 rows have about the same length:
-        // every lane sums its own row up to the long rows' bound
-        const bool shortrow = d <= (g.orig ? (int64_t)kLongRow : (int64_t)kShortRow);
+        const bool shortrow = d <= kShortRow;
         if (shortrow)
             for (int64_t k = b; k < b + d; k++) s += edge_weight<WT>(g.w, k);
         unsigned long long longs = __ballot(!shortrow);
@@ -204,6 +202,51 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights(Level g, double *K, d
         double t = 0.0;
         for (int k = 0; k < kBlock / kWave; k++) t += part[k];
         unsafeAtomicAdd(M2, t);
+    }
+}
+
+// The short rows of a level in degree order (rows [nlong, n), dense CSR):
+// a workgroup takes 256 consecutive rows and reads their entries as one
+// contiguous range, 256 at a time (coalesced), each thread finding its
+// entry's row by a binary search over the rows' offsets in LDS and adding
+// the weight to the row's LDS sum (exact sums, so the order of the atomics
+// does not matter).
+template <int WT>
+__global__ void __launch_bounds__(kBlock) k_vertex_weights_rows(Level g, double *K, double *M2) {
+    __shared__ int64_t so[kBlock + 1];
+    __shared__ double acc[kBlock];
+    __shared__ double part[kBlock / kWave];
+    const int tid = threadIdx.x;
+    double blk = 0.0;
+    for (int64_t r0 = g.nlong + (int64_t)blockIdx.x * kBlock; r0 < g.n; r0 += (int64_t)gridDim.x * kBlock) {
+        const int nr = g.n - r0 < kBlock ? (int)(g.n - r0) : kBlock;
+        so[tid] = g.off[r0 + (tid < nr ? tid : nr)];
+        if (tid == 0) so[kBlock] = g.off[r0 + nr];
+        acc[tid] = 0.0;
+        __syncthreads();
+        const int64_t e0 = so[0], e1 = so[kBlock];
+        for (int64_t e = e0 + tid; e < e1; e += kBlock) {
+            int lo = 0, hi = nr - 1;   // the row r with so[r] <= e < so[r + 1]
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (so[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            atomicAdd(&acc[lo], edge_weight<WT>(g.w, e));
+        }
+        __syncthreads();
+        if (tid < nr) {
+            K[r0 + tid] = acc[tid];
+            blk += acc[tid];
+        }
+        __syncthreads();
+    }
+    blk = group_sum<kWave>(blk);
+    if (lane_id() == 0) part[tid / kWave] = blk;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / kWave; k++) t += part[k];
+        if (t != 0.0) unsafeAtomicAdd(M2, t);
     }
 }
 
@@ -375,6 +418,15 @@ void launch_vertex_weights(const Level &g, double *K, double *M2, hipStream_t s)
     launch_vertex_weights_long(g, K, M2, s);
     if (g.nlong >= g.n) return;
     unsigned gr = grid_for(g.n - g.nlong, kBlock, 8192);
+    if (g.orig) {   // degree order: dense rows of similar length side by side
+        if (g.wt == W_UNIT)
+            k_vertex_weights_rows<W_UNIT><<<gr, kBlock, 0, s>>>(g, K, M2);
+        else if (g.wt == W_F32)
+            k_vertex_weights_rows<W_F32><<<gr, kBlock, 0, s>>>(g, K, M2);
+        else
+            k_vertex_weights_rows<W_F64><<<gr, kBlock, 0, s>>>(g, K, M2);
+        return;
+    }
     if (g.wt == W_UNIT)
         k_vertex_weights<W_UNIT><<<gr, kBlock, 0, s>>>(g, K, M2);
     else if (g.wt == W_F32)
