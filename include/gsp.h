@@ -91,7 +91,8 @@ typedef struct gsp_options {
                                       workgroups each (0, the default: each kernel's own cap, 2048-8192);
                                       results do not depend on it */
     int32_t vertex_order;          /* storage order of the input graph inside gsp_run: GSP_ORDER_AUTO
-                                      (default: degree order for graphs of at least 2^25 entries),
+                                      (default: degree order for graphs of at least 2^25 entries whose
+                                      copy fits mem_limit_bytes),
                                       GSP_ORDER_LOADED or GSP_ORDER_DEGREE (vertices renumbered by degree,
                                       largest first, so that the high-degree vertices' words share cache
                                       lines).  The copy in degree order is built by the first run that asks

@@ -908,10 +908,19 @@ gsp_status ensure_levels(gsp_ctx *ctx) {
 // Whether gsp_run stores the input graph in degree order (vertex_order;
 // batches never).
 constexpr int64_t kAutoOrderEntries = int64_t(1) << 25;
+// Device bytes of the copy in degree order.
+uint64_t order_bytes(const gsp_ctx *ctx) {
+    const int wb = ctx->wt0 == W_UNIT ? 0 : (ctx->wt0 == W_F32 ? 4 : 8);
+    return (uint64_t)ctx->n * 20 + (uint64_t)(ctx->n + 1) * 8 + (uint64_t)ctx->nnz * (4 + wb) +
+           16 * (uint64_t)kOrderBucketsMax + 64;
+}
+
+// AUTO keeps the loaded order where the copy would pass mem_limit_bytes.
 bool wants_order(const gsp_ctx *ctx, const gsp_options &opt, bool batch, int32_t max_passes) {
     if (batch || max_passes == 0 || ctx->n == 0 || ctx->nnz == 0) return false;
     if (opt.vertex_order == GSP_ORDER_DEGREE) return true;
-    return opt.vertex_order == GSP_ORDER_AUTO && ctx->nnz >= kAutoOrderEntries;
+    if (opt.vertex_order != GSP_ORDER_AUTO || ctx->nnz < kAutoOrderEntries) return false;
+    return ctx->ordered || !ctx->mem_limit || ctx->mem_used + order_bytes(ctx) <= ctx->mem_limit;
 }
 
 // Builds the input graph's copy in degree order once per load (again when
@@ -928,8 +937,7 @@ gsp_status ensure_order(gsp_ctx *ctx, int rounds) {
     const int64_t n = ctx->n, nnz = ctx->nnz;
     const int wb = ctx->wt0 == W_UNIT ? 0 : (ctx->wt0 == W_F32 ? 4 : 8);
     if (ctx->mem_limit) {
-        uint64_t need = (uint64_t)n * 20 + (uint64_t)(n + 1) * 8 + (uint64_t)nnz * (4 + wb) + 16 * kOrderBucketsMax + 64;
-        if (ctx->mem_used + need > ctx->mem_limit)
+        if (ctx->mem_used + order_bytes(ctx) > ctx->mem_limit)
             return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached (degree order)");
     }
     hipError_t e = hipSuccess;
