@@ -9,8 +9,11 @@ the 8-64-64-1 network is trained by the library's fp32 training kernels
 positives).  Then, on held-out seeds, the gated method is run beside the
 plain one and the result is reported.  The parameters are written as a raw
 little-endian fp32 file of 4801 values (the layout of gsp_pruner_set).
+The R-MAT class has its own network, trained the same way on R-MAT scale 22
+graphs (seeds 100..115, a/b/c/d .57/.19/.19/.05, weights in [1, 10)).
 
-    python -m paper_2402_11454_amd.train_pruner --out paper_2402_11454_amd/pruner_dcsbm.f32
+    python -m paper_2402_11454_amd.train_pruner                     # -> pruner_dcsbm.f32
+    python -m paper_2402_11454_amd.train_pruner --graph-class rmat  # -> pruner_rmat.f32
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "pruner_dcsbm.f32")
+RMAT_OUT = os.path.join(HERE, "pruner_rmat.f32")
 
 # Threshold on p for the shipped network, chosen on the held-out 4M graph of
 # seed 1001 among 0.02, 0.05, 0.1, 0.2, 0.3, 0.5: the fastest one whose
@@ -79,9 +83,11 @@ def collect(ctx, graphs, rate: float, cap: int, log=print):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=DEFAULT_OUT)
-    ap.add_argument("--n", type=int, default=4_000_000, help="vertices per graph")
-    ap.add_argument("--train-seeds", type=int, default=32)
+    ap.add_argument("--graph-class", default="dcsbm", choices=("dcsbm", "rmat"))
+    ap.add_argument("--out", default=None, help="default: the class's network file")
+    ap.add_argument("--n", type=int, default=4_000_000, help="vertices per graph (DC-SBM)")
+    ap.add_argument("--scale", type=int, default=22, help="R-MAT scale")
+    ap.add_argument("--train-seeds", type=int, default=None, help="default: 32 (DC-SBM), 16 (R-MAT)")
     ap.add_argument("--heldout", default="1000,1001")
     ap.add_argument("--rate", type=float, default=1.0 / 16)
     ap.add_argument("--epochs", type=int, default=4)
@@ -96,10 +102,21 @@ def main(argv=None):
 
     log = lambda s: print(s, flush=True)
     ctx = gsp.Context(0)
-    if a.n == 4_000_000:
-        makes = [lambda s=s: gi.dcsbm_4m(s) for s in range(a.train_seeds)]
-    else:
-        makes = [lambda s=s: gi.dcsbm(a.n, 2.5, 5, 5000, 1.5, 20, 50_000, 0.3, s) for s in range(a.train_seeds)]
+    rmat = a.graph_class == "rmat"
+    if a.out is None:
+        a.out = RMAT_OUT if rmat else DEFAULT_OUT
+    if a.train_seeds is None:
+        a.train_seeds = 16 if rmat else 32
+
+    def graph(s):
+        if rmat:
+            return gi.rmat(a.scale, 16, *gi.RMAT_ABC, s, weights=(1.0, 10.0), name=f"rmat-{a.scale}")
+        if a.n == 4_000_000:
+            return gi.dcsbm_4m(s)
+        return gi.dcsbm(a.n, 2.5, 5, 5000, 1.5, 20, 50_000, 0.3, s)
+
+    first = 100 if rmat else 0
+    makes = [lambda s=s: graph(s) for s in range(first, first + a.train_seeds)]
     x, y = collect(ctx, makes, a.rate, 8_000_000, log)
     order = np.random.default_rng(a.seed).permutation(y.shape[0])
     x, y = np.ascontiguousarray(x[order]), np.ascontiguousarray(y[order])
@@ -112,7 +129,7 @@ def main(argv=None):
     log(f"[train] wrote {a.out}")
     ctx.pruner_set(p)
     for s in [int(v) for v in a.heldout.split(",") if v]:
-        g = gi.dcsbm_4m(s) if a.n == 4_000_000 else gi.dcsbm(a.n, 2.5, 5, 5000, 1.5, 20, 50_000, 0.3, s)
+        g = graph(s)
         ctx.load(g.offsets, g.cols, g.weights, n=g.n)
         out = {}
         for mode in (gsp.PRUNE_PLAIN, gsp.PRUNE_LEARNED):
