@@ -18,11 +18,16 @@ pass at this size in a test, so the checks are:
     of the result is the result; and, where the asynchronous oracle's
     modularity is stored (tests/golden/async_q.json), Q >= Q_async - 0.005.
   * the shipped network at the R-MAT class's threshold: Q within 0.005 of
-    the plain run's, no disconnected community.
+    the plain run's, no disconnected community;
+  * the whole run equal to the oracle's synchronous run (stored by
+    tests/golden/make_rmat26.py): membership digest, iterations and
+    communities per pass, Q within 1e-9, in the degree order the run picks
+    at this size and in the loaded order.
 
 Needs about 60 GB of host memory and 150 GB of device memory (a few
 minutes, most of it generating the graph).
 """
+import hashlib
 import json
 import os
 
@@ -142,3 +147,17 @@ def test_shipped_network_quality(big):
     assert res.stats["pruned"] > 0
     assert abs(res.modularity - plain.modularity) <= 0.005
     assert ctx.count_disconnected(res.membership) == 0
+
+
+@pytest.mark.parametrize("order", [gsp.ORDER_AUTO, gsp.ORDER_LOADED])
+def test_whole_run_equals_oracle(big, order):
+    g, w, S, moved, ctx = big
+    with open(os.path.join(os.path.dirname(GOLDEN), "rmat26_oracle.json")) as f:
+        ref = json.load(f)
+    assert ref["nnz"] == g.nnz and ref["n"] == g.n
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, vertex_order=order)
+    sha = hashlib.sha1(np.ascontiguousarray(res.membership, dtype=np.int32).tobytes()).hexdigest()
+    assert res.stats["iterations"] == ref["iterations"]
+    assert res.stats["communities"] == ref["communities"]
+    assert sha == ref["membership_sha1"]
+    assert abs(res.modularity - ref["modularity"]) <= 1e-9
