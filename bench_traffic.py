@@ -32,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 
 
-def run_workload(runs: int, workload: str, learned: bool):
+def run_workload(runs: int, workload: str, learned: bool, order: str = "auto"):
     sys.path.insert(0, ROOT)
     import torch
     import paper_2402_11454_amd as gsp
@@ -48,11 +48,12 @@ def run_workload(runs: int, workload: str, learned: bool):
     print(f"[pmc] graph ready: n={g.n} nnz={g.nnz}", flush=True)
     ctx = gsp.Context(0, stream=torch.cuda.current_stream())
     ctx.load_graph(g)
-    kw = {}
+    from bench import ORDERS
+    kw = dict(vertex_order=ORDERS[order])
     if learned:
         ctx.pruner_set(load_params(DEFAULT_OUT))
         from bench import WORKLOADS
-        kw = dict(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=THETA_BY_CLASS[WORKLOADS[workload]["kind"]])
+        kw.update(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=THETA_BY_CLASS[WORKLOADS[workload]["kind"]])
     for k in range(runs):
         ctx.run(1e-2, 10, **kw)
         print(f"[pmc] run {k + 1}/{runs}", flush=True)
@@ -319,6 +320,8 @@ if __name__ == "__main__":
     ap.add_argument("--workload", default="rmat26")
     ap.add_argument("--learned", action="store_true", help="learned-pruned runs (bench.py's timed runs)")
     ap.add_argument("--tag", default="", help="suffix of the summary's file names (e.g. _plain)")
+    ap.add_argument("--vertex-order", default="auto", choices=("auto", "loaded", "degree"),
+                    help="storage order of the graph inside the --run runs")
     ap.add_argument("--phase-times", default="", help="write the phases' mean wall times to this JSON")
     ap.add_argument("--phases", nargs=2, help="TRAFFIC_JSON TIMES_JSON: per-phase summary")
     ap.add_argument("--kernel-summary", nargs=2, metavar=("DB", "OUT_MD"),
@@ -335,7 +338,7 @@ if __name__ == "__main__":
     if a.kernel_summary:
         kernel_summary(a.kernel_summary[0], a.cmd, a.title, a.kernel_summary[1], a.bench_out)
     if a.run:
-        run_workload(a.runs, a.workload, a.learned)
+        run_workload(a.runs, a.workload, a.learned, a.vertex_order)
     if a.summarize:
         summarize(a.summarize[0], a.summarize[1], a.cmd, a.workload, a.runs, a.tag)
     if a.phase_times:
