@@ -47,14 +47,15 @@ class _Options(ctypes.Structure):
                 ("sync_rounds", ctypes.c_int32), ("split_mode", ctypes.c_int32),
                 ("prune_params", ctypes.c_void_p), ("prune_theta_logit", ctypes.c_double),
                 ("trace", ctypes.POINTER(_Trace)), ("return_moves", ctypes.c_int32),
-                ("confirm_final", ctypes.c_int32)]
+                ("confirm_final", ctypes.c_int32), ("leiden", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("iterations", ctypes.c_int32 * 64),
                 ("communities", ctypes.c_int64 * 64), ("vertices", ctypes.c_int64 * 64),
                 ("modularity", ctypes.c_double), ("counters", ctypes.c_int64 * 4),
-                ("tau", ctypes.c_double * 64), ("final_iterations", ctypes.c_int32)]
+                ("tau", ctypes.c_double * 64), ("final_iterations", ctypes.c_int32),
+                ("refine_iterations", ctypes.c_int32 * 64), ("refined", ctypes.c_int64 * 64)]
 
 
 def _load():
@@ -72,6 +73,7 @@ def _load():
         "orc_move_async": (i32, [i64, vp, vp, vp, dbl, vp, vp, vp, dbl, i32, vp]),
         "orc_move_sync_step": (i64, [i64, vp, vp, vp, dbl, vp, vp, vp, vp, vp, vp, vp]),
         "orc_move_sync": (i32, [i64, vp, vp, vp, dbl, vp, vp, dbl, i32, i32, vp, vp, i32]),
+        "orc_refine_sync": (i32, [i64, vp, vp, vp, dbl, vp, vp, vp, dbl, i32, i32, vp, vp]),
         "orc_split_bfs": (i32, [i64, vp, vp, vp, vp]),
         "orc_split_lp": (i32, [i64, vp, vp, vp, i32, vp]),
         "orc_renumber": (i64, [i64, vp, vp]),
@@ -225,6 +227,22 @@ def move_sync(g, memb=None, tau: float = 0.0, max_iter: int = 20, rounds: int = 
     li = _load().orc_move_sync(*g.args(), M2, _p(K), _p(m), tau, max_iter, rounds, _p(dq), _p(mv), int(returns))
     if li < 0:
         raise ValueError("orc_move_sync failed")
+    return m, li, dq[:li], mv[:li]
+
+
+def refine_sync(g, bound, memb=None, tau: float = 0.0, max_iter: int = 20, rounds: int = 8):
+    """GSP-Leiden's refinement within the communities `bound`, from memb
+    (default: every vertex alone); returns (sub-communities, iterations,
+    per-iteration dQ, per-iteration movers)."""
+    g = CSR.of(g)
+    K, M2 = vertex_weights(g)
+    b = _memb(bound, g.n)
+    m = np.arange(g.n, dtype=np.int32) if memb is None else _memb(memb, g.n).copy()
+    dq = np.zeros(max(max_iter, 1), dtype=np.float64)
+    mv = np.zeros(max(max_iter, 1), dtype=np.int64)
+    li = _load().orc_refine_sync(*g.args(), M2, _p(K), _p(b), _p(m), tau, max_iter, rounds, _p(dq), _p(mv))
+    if li < 0:
+        raise ValueError("orc_refine_sync failed")
     return m, li, dq[:li], mv[:li]
 
 
@@ -432,15 +450,17 @@ def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: in
             tolerance_drop: float = 10.0, aggregation_tolerance: float = 0.8,
             sync: bool = False, rounds: int = 8, split_mode: int = 0, prune_params=None, theta: float = 0.5,
             trace: Optional[Trace] = None, theta_logit=None, return_moves: bool = False,
-            confirm_final: bool = False) -> Result:
+            confirm_final: bool = False, leiden: bool = False) -> Result:
     """The whole method; split_mode 0 = every pass, 1 = after the last, 2 = none.
-    prune_params / trace / return_moves need sync=True."""
+    prune_params / trace / return_moves need sync=True; leiden=True runs
+    GSP-Leiden (sync=True, no gate or trace)."""
     g = CSR.of(g)
     p = _params(prune_params)
     tl = theta_logit if theta_logit is not None else logit_of(theta)
     opt = _Options(tolerance, max_passes, max_iterations, tolerance_drop, aggregation_tolerance,
                    int(sync), rounds, split_mode, _p(p), tl,
-                   ctypes.pointer(trace.c) if trace is not None else None, int(return_moves), int(confirm_final))
+                   ctypes.pointer(trace.c) if trace is not None else None, int(return_moves), int(confirm_final),
+                   int(leiden))
     st = _Stats()
     memb = np.empty(g.n, dtype=np.int32)
     passes = _load().orc_louvain(*g.args(), ctypes.byref(opt), _p(memb), ctypes.byref(st))
@@ -453,4 +473,6 @@ def louvain(g, tolerance: float = 1e-2, max_passes: int = 10, max_iterations: in
                       pruned=int(st.counters[2]), confirm_sweeps=int(st.counters[3]))
     r.tau = list(st.tau[:k])
     r.final_iterations = int(st.final_iterations)
+    r.refine_iterations = list(st.refine_iterations[:k])
+    r.refined = list(st.refined[:k])
     return r

@@ -489,6 +489,107 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
 }
 
 /* ------------------------------------------------------------------ */
+/* Refinement phase (GSP-Leiden)                                        */
+/* ------------------------------------------------------------------ */
+
+/* The refinement phase of the Leiden algorithm (Section 3.5), in the
+ * reading this oracle takes for GSP-Leiden (the paper gives prose only):
+ * the communities of the local-moving phase are the bounds, and within them
+ * vertices build sub-communities.  A vertex may leave its sub-community only
+ * while it is alone in it, and may join only the sub-community of a
+ * neighbour in its own bound; among those it takes the one of largest
+ * delta-modularity (Eq. 2 with the whole graph's K and 2m), ties to the
+ * lowest id, and only for a positive gain: the greedy limit of the
+ * randomised choice.  The moves run in the ordered synchronous sub-rounds of
+ * orc_move_sync, with its gain total, tolerance test and singleton rule; a
+ * mover marks its neighbours in the same bound unprocessed.  memb holds the
+ * starting sub-communities (normally every vertex alone), each inside one
+ * bound, and is updated in place.  Returns the iterations run. */
+int32_t orc_refine_sync(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
+                        const double *K, const int32_t *bound, int32_t *memb, double tau, int32_t max_iter,
+                        int32_t rounds, double *dq_iter, int64_t *moved_iter) {
+    if (n < 0 || max_iter < 0 || rounds < 1 || rounds > 64 || (rounds & (rounds - 1)) || !valid_memb(n, memb) ||
+        !valid_memb(n, bound))
+        return -1;
+    if (n == 0 || max_iter == 0) return 0;
+    int32_t *home = (int32_t *)malloc((size_t)n * sizeof(int32_t));   /* bound of each sub-community */
+    double *sigma = (double *)malloc((size_t)n * sizeof(double));
+    int32_t *csize = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    uint8_t *unprocessed = (uint8_t *)malloc((size_t)n);
+    int32_t *dec = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    double *gain = (double *)malloc((size_t)n * sizeof(double));
+    table h = {0};
+    int bad = !home || !sigma || !csize || !unprocessed || !dec || !gain || table_init(&h, n);
+    for (int64_t c = 0; !bad && c < n; c++) home[c] = -1;
+    for (int64_t i = 0; !bad && i < n; i++) {
+        int32_t c = memb[i];
+        if (home[c] < 0) home[c] = bound[i];
+        else if (home[c] != bound[i]) bad = 1;   /* a sub-community across two bounds */
+    }
+    if (bad) {
+        free(home); free(sigma); free(csize); free(unprocessed); free(dec); free(gain);
+        if (h.val) table_free(&h);
+        return -1;
+    }
+    memset(unprocessed, 1, (size_t)n);
+    int32_t li = 0;
+    for (int32_t it = 0; it < max_iter; it++) {
+        int64_t gsum = 0, moved = 0;
+        for (int32_t p = 0; p < rounds; p++) {
+            for (int64_t c = 0; c < n; c++) { sigma[c] = 0.0; csize[c] = 0; }
+            for (int64_t i = 0; i < n; i++) { sigma[memb[i]] += K[i]; csize[memb[i]]++; }
+            for (int64_t i = 0; i < n; i++) {
+                int32_t d = memb[i];
+                dec[i] = d;
+                gain[i] = 0.0;
+                if (!unprocessed[i] || sub_round_of(i, rounds) != p) continue;
+                unprocessed[i] = 0;
+                if (csize[d] != 1) continue;   /* merged already: stays */
+                for (int64_t e = off[i]; e < off[i + 1]; e++) {
+                    int32_t j = col[e];
+                    if (j != i && bound[j] == bound[i]) table_add(&h, memb[j], w[e]);
+                }
+                double ki = K[i];
+                double kid = h.used[d] ? h.val[d] : 0.0;
+                double g_stay = M2 * kid - ki * (sigma[d] - ki);
+                int32_t best = -1;
+                double g_best = 0.0;
+                for (int64_t k = 0; k < h.nkeys; k++) {
+                    int32_t c = h.keys[k];
+                    if (c == d) continue;
+                    double g = M2 * h.val[c] - ki * sigma[c];
+                    if (best < 0 || g > g_best || (g == g_best && c < best)) {
+                        best = c;
+                        g_best = g;
+                    }
+                }
+                table_clear(&h);
+                if (best < 0 || !(g_best > g_stay)) continue;
+                if (csize[best] == 1 && best > d) continue;   /* singleton rule */
+                dec[i] = best;
+                gain[i] = g_best - g_stay;
+            }
+            for (int64_t i = 0; i < n; i++) {
+                if (dec[i] == memb[i]) continue;
+                gsum += orc_gain_fixed(gain[i], M2);
+                moved++;
+                for (int64_t e = off[i]; e < off[i + 1]; e++)
+                    if (col[e] != i && bound[col[e]] == bound[i]) unprocessed[col[e]] = 1;
+            }
+            for (int64_t i = 0; i < n; i++) memb[i] = dec[i];
+        }
+        double dq = ldexp((double)gsum, -61);
+        if (dq_iter) dq_iter[it] = dq;
+        if (moved_iter) moved_iter[it] = moved;
+        li = it + 1;
+        if (dq <= tau) break;
+    }
+    free(home); free(sigma); free(csize); free(unprocessed); free(dec); free(gain);
+    table_free(&h);
+    return li;
+}
+
+/* ------------------------------------------------------------------ */
 /* Split phase                                                          */
 /* ------------------------------------------------------------------ */
 
@@ -682,6 +783,7 @@ static void canonical_labels(int64_t n, int32_t *memb) {
 int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const double *w, const orc_options *opt,
                     int32_t *memb_out, orc_stats *stats) {
     if (n < 0 || !opt || opt->max_passes < 0) return -1;
+    if (opt->leiden && (!opt->sync_moves || opt->prune_params || opt->trace)) return -1;
     if (stats) memset(stats, 0, sizeof(*stats));
     int64_t nnz = off[n];
     /* G' starts as G itself (read only); the super-vertex graphs G'' go to
@@ -699,9 +801,13 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
     double *sigma = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     int32_t *cm = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
     int32_t *lab = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-    if (!goff || !gcol || !gw || !noff || !ncol || !nw || !K || !sigma || !cm || !lab) {
+    /* GSP-Leiden: the refined sub-communities, and each super-vertex's
+     * starting community at the next level */
+    int32_t *ref = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *init = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!goff || !gcol || !gw || !noff || !ncol || !nw || !K || !sigma || !cm || !lab || !ref || !init) {
         free(goff); free(gcol); free(gw); free(noff); free(ncol); free(nw);
-        free(K); free(sigma); free(cm); free(lab);
+        free(K); free(sigma); free(cm); free(lab); free(ref); free(init);
         return -1;
     }
     int64_t gn = n;
@@ -714,6 +820,7 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         /* Sigma' <- K' <- vertexWeights(G'); C' <- [0 .. |V'|); all unprocessed */
         orc_vertex_weights(gn, loff, lcol, lw, K);
         for (int64_t i = 0; i < gn; i++) { sigma[i] = K[i]; cm[i] = (int32_t)i; }
+        if (opt->leiden && lp > 0) memcpy(cm, init, (size_t)gn * sizeof(int32_t));   /* C' <- the bounds' communities */
         int32_t li;
         if (opt->sync_moves && (opt->prune_params || opt->trace)) {
             int64_t c4[4];
@@ -738,8 +845,51 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
             stats->communities[lp] = ng;
             stats->vertices[lp] = gn;
         }
-        /* renumber, then dendrogram lookup C <- C'[C] */
         memcpy(cm, lab, (size_t)gn * sizeof(int32_t));
+        if (opt->leiden) {
+            /* GSP-Leiden: the result is the local-moving communities; the
+             * next level's super-vertices are their refined sub-communities,
+             * each starting in the community that holds it */
+            int stop = li <= 1 || (double)ng / (double)gn > opt->aggregation_tolerance || lp == opt->max_passes - 1;
+            int64_t nr = 0;
+            if (!stop) {
+                for (int64_t i = 0; i < gn; i++) ref[i] = (int32_t)i;
+                int32_t ri = orc_refine_sync(gn, loff, lcol, lw, M2, K, cm, ref, tau, opt->max_iterations,
+                                             opt->sync_rounds, NULL, NULL);
+                if (opt->split_mode == 0) {
+                    /* simultaneous moves can leave a sub-community in pieces
+                     * (its founder left as others joined it): split it too,
+                     * so that every super-vertex is connected */
+                    orc_split_bfs(gn, loff, lcol, ref, lab);
+                    memcpy(ref, lab, (size_t)gn * sizeof(int32_t));
+                }
+                nr = orc_renumber(gn, ref, lab);
+                if (stats && lp < 64) {
+                    stats->refine_iterations[lp] = ri;
+                    stats->refined[lp] = nr;
+                }
+                stop = (double)nr / (double)gn > opt->aggregation_tolerance;
+            }
+            if (orc_verbose)
+                fprintf(stderr, "[oracle] pass %d: %lld vertices, %d iterations, %lld communities, %lld refined\n",
+                        (int)lp, (long long)gn, (int)li, (long long)ng, (long long)nr);
+            if (stop) {
+                for (int64_t v = 0; v < n; v++) memb_out[v] = cm[memb_out[v]];
+                break;
+            }
+            for (int64_t v = 0; v < n; v++) memb_out[v] = lab[memb_out[v]];
+            for (int64_t i = 0; i < gn; i++) init[lab[i]] = cm[i];
+            int64_t nn = orc_aggregate(gn, loff, lcol, lw, lab, nr, noff, ncol, nw, nnz);
+            if (nn < 0) { passes = -1; break; }
+            loff = noff; lcol = ncol; lw = nw;
+            int64_t *to = goff; goff = noff; noff = to;
+            int32_t *tc = gcol; gcol = ncol; ncol = tc;
+            double *tw = gw; gw = nw; nw = tw;
+            gn = nr;
+            tau = tau / opt->tolerance_drop;
+            continue;
+        }
+        /* renumber, then dendrogram lookup C <- C'[C] */
         for (int64_t v = 0; v < n; v++) memb_out[v] = cm[memb_out[v]];
         if (orc_verbose)
             fprintf(stderr, "[oracle] pass %d: %lld vertices, %d iterations, %lld communities\n", (int)lp,
@@ -792,6 +942,6 @@ int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const dou
         stats->modularity = orc_modularity(n, off, col, w, memb_out);
     }
     free(goff); free(gcol); free(gw); free(noff); free(ncol); free(nw);
-    free(K); free(sigma); free(cm); free(lab);
+    free(K); free(sigma); free(cm); free(lab); free(ref); free(init);
     return passes;
 }

@@ -82,6 +82,17 @@ int32_t orc_move_sync(int64_t n, const int64_t *off, const int32_t *col, const d
                       double *dq_iter, int64_t *moved_iter,
                       int32_t returns);
 
+/* Refinement phase of GSP-Leiden (Section 3.5, greedy reading): within
+ * each bound community, vertices alone in their sub-community join the
+ * sub-community of a same-bound neighbour of largest delta-modularity, in
+ * the ordered synchronous sub-rounds of orc_move_sync.  bound[n] holds the
+ * local-moving communities; memb (starting sub-communities, each inside one
+ * bound; normally memb[i] = i) is updated in place.  Returns the iterations
+ * run; dq_iter / moved_iter as for orc_move_sync. */
+int32_t orc_refine_sync(int64_t n, const int64_t *off, const int32_t *col, const double *w, double M2,
+                        const double *K, const int32_t *bound, int32_t *memb, double tau, int32_t max_iter,
+                        int32_t rounds, double *dq_iter, int64_t *moved_iter);
+
 /* Split of internally-disconnected communities by BFS (Algorithm
  * "splitDisconnectedBfs", one thread, lowest unvisited source):
  * labels[i] = smallest vertex id of i's component in the same-community
@@ -177,6 +188,10 @@ typedef struct orc_options {
     int32_t return_moves;          /* sync_moves = 1: return moves add nothing to the gain total (option) */
     int32_t confirm_final;         /* with prune_params: no confirming sweep per pass; after the passes one
                                       plain local-moving phase over G from the result, then the split */
+    int32_t leiden;                /* 1: GSP-Leiden (sync_moves = 1, no gate, no trace): each pass refines the
+                                      split communities (orc_refine_sync), splits the refined ones too
+                                      (split_mode 0) and aggregates them; they start the next pass in
+                                      their community */
 } orc_options;
 
 typedef struct orc_stats {
@@ -188,11 +203,13 @@ typedef struct orc_stats {
     int64_t counters[4];           /* gated phase: scanned vertices, scanned entries, pruned, confirming sweeps */
     double tau[64];                /* the iteration tolerance each pass ran with (threshold scaling) */
     int32_t final_iterations;      /* confirm_final: iterations of the final plain phase over G */
+    int32_t refine_iterations[64]; /* leiden: iterations of each pass's refinement (0 if none ran) */
+    int64_t refined[64];           /* leiden: refined sub-communities of each pass (0 if none ran) */
 } orc_stats;
 
-/* The whole method (Algorithm "louvain").  memb_out[n] gets the top-level
- * membership, numbered by ascending smallest vertex id.  Returns the number
- * of passes run. */
+/* The whole method (Algorithm "louvain"; with opt->leiden, GSP-Leiden).
+ * memb_out[n] gets the top-level membership, numbered by ascending smallest
+ * vertex id.  Returns the number of passes run. */
 int32_t orc_louvain(int64_t n, const int64_t *off, const int32_t *col, const double *w, const orc_options *opt,
                     int32_t *memb_out, orc_stats *stats);
 
