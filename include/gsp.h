@@ -100,6 +100,17 @@ typedef struct gsp_options {
                                       as the loaded graph).  Results do not depend on it: every rule that
                                       orders vertex or community ids compares the caller's ids.  Batches
                                       and the step entry points use the loaded order. */
+    int32_t leiden;                /* 1: GSP-Leiden (the Leiden algorithm's refinement, Section 3.5, taken
+                                      greedily, with the split of Section 4.1): after each pass's local
+                                      moving and split, a refinement phase runs inside every community
+                                      (a vertex alone in its sub-community joins the sub-community of a
+                                      same-community neighbour of largest delta-modularity, Eq. 2, in the
+                                      same ordered synchronous sub-rounds and tolerance test); with
+                                      GSP_SPLIT_PASS the refined sub-communities are split too; they become
+                                      the next level's super-vertices, each starting in the community that
+                                      holds it.  The result is the local-moving communities.  Single graphs
+                                      only, plain pruning, no trace capture (else GSP_EINVAL).
+                                      0 (default): GSP-Louvain. */
 } gsp_options;
 
 /* split_algo values. */
@@ -149,6 +160,11 @@ typedef struct gsp_stats {
     int32_t confirm_sweeps;                    /* confirming plain sweeps run after gated convergence */
     int32_t sweeps;                            /* local-moving sweeps run, all passes (counted or not) */
     int32_t split_rounds;                      /* split_algo = GSP_SPLIT_LPP: propagation rounds, all splits */
+    int32_t refine_iterations[GSP_MAX_PASSES_STATS]; /* leiden: iterations of each pass's refinement (0: none) */
+    int64_t refined[GSP_MAX_PASSES_STATS];     /* leiden: sub-communities of each pass's refinement, after
+                                                  their split (0: none ran) */
+    double ms_refine;                          /* leiden, timing >= 1: refinement phases (the same-community
+                                                  subgraph included; their splits count as split time) */
 } gsp_stats;
 
 /* Fills *out with the defaults above. */
@@ -308,6 +324,26 @@ gsp_status gsp_step_aggregate(gsp_ctx *ctx, const int32_t *membership, int where
 gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where, double tolerance, int32_t pass_index,
                              const gsp_options *opt, int32_t *iterations, double *dq_iter, int64_t *moved_iter,
                              int64_t *counters);
+
+/* GSP-Leiden's refinement phase on the loaded graph (the Leiden algorithm's
+ * refinement, Section 3.5, taken greedily; gsp_options.leiden).  bound
+ * (n labels in [0, n)) holds the communities of a local-moving phase;
+ * membership_inout holds the starting sub-communities, each inside one bound
+ * community (normally membership[i] = i), and receives the refined ones as
+ * labels (founding vertex ids, not renumbered).  In every iteration's
+ * ordered sub-rounds a vertex alone in its sub-community takes the
+ * sub-community of a neighbour in its bound community with the largest
+ * delta-modularity (Eq. 2 with the whole graph's K and 2m; ties to the
+ * lowest id; a positive gain; the singleton rule of gsp_move_phase); movers
+ * mark their same-community neighbours; the iterations stop as
+ * gsp_move_phase's do.  Uses opt's max_iterations, sub_rounds, use_graphs,
+ * grid_cap and hub options (opt = NULL: the defaults); prune_mode must be
+ * GSP_PRUNE_PLAIN.  iterations, dq_iter and moved_iter as for
+ * gsp_move_phase.  Both arrays live where `where` says.  GSP_EINVAL for a
+ * label outside [0, n) or a sub-community across two bound communities. */
+gsp_status gsp_refine_phase(gsp_ctx *ctx, const int32_t *bound, int32_t *membership_inout, int where,
+                            double tolerance, const gsp_options *opt, int32_t *iterations, double *dq_iter,
+                            int64_t *moved_iter);
 
 /* ---- batches of independent graphs ----
  *

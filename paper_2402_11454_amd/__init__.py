@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
                 ("timing_mask", ctypes.c_uint32), ("hub_global", ctypes.c_int32),
                 ("hub_max_parts", ctypes.c_int32), ("return_moves", ctypes.c_int32),
                 ("split_algo", ctypes.c_int32), ("grid_cap", ctypes.c_int32),
-                ("vertex_order", ctypes.c_int32)]
+                ("vertex_order", ctypes.c_int32), ("leiden", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -68,7 +68,9 @@ class Stats(ctypes.Structure):
                 ("kernels", KernelStat * len(KERNEL_CLASSES)),
                 ("scanned_vertices", ctypes.c_int64), ("pruned", ctypes.c_int64),
                 ("confirm_sweeps", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("split_rounds", ctypes.c_int32)]
+                ("split_rounds", ctypes.c_int32),
+                ("refine_iterations", ctypes.c_int32 * MAX_PASSES_STATS),
+                ("refined", ctypes.c_int64 * MAX_PASSES_STATS), ("ms_refine", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         k = self.passes
@@ -78,6 +80,8 @@ class Stats(ctypes.Structure):
                     ms_aggregate=self.ms_aggregate, ms_other=self.ms_other, ms_total=self.ms_total,
                     scanned_vertices=self.scanned_vertices, pruned=self.pruned,
                     confirm_sweeps=self.confirm_sweeps, sweeps=self.sweeps, split_rounds=self.split_rounds,
+                    refine_iterations=list(self.refine_iterations[:k]), refined=list(self.refined[:k]),
+                    ms_refine=self.ms_refine,
                     kernels={name: dict(launches=s.launches, ms=s.ms, bytes=s.bytes, items=s.items)
                              for name, s in zip(KERNEL_CLASSES, self.kernels)})
 
@@ -128,6 +132,7 @@ def lib():
         "gsp_get_weight_grid": [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "gsp_count_disconnected_noalloc": [i64, i64, vp, vp, vp, vp, vp],
         "gsp_step_split_lp": [vp, vp, ctypes.c_int, vp, ctypes.POINTER(i32)],
+        "gsp_refine_phase": [vp, vp, vp, ctypes.c_int, dbl, ctypes.POINTER(Options), ctypes.POINTER(i32), vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -365,6 +370,22 @@ class Context:
         cnt = dict(scanned_vertices=int(c4[0]), scanned_entries=int(c4[1]), pruned=int(c4[2]),
                    confirm_sweeps=int(c4[3]))
         return m, li.value, dq[:li.value], mv[:li.value], cnt
+
+    def refine_phase(self, bound, membership=None, tolerance: float = 0.0, options: Optional[Options] = None,
+                     **kw):
+        """GSP-Leiden's refinement within the communities `bound`, from
+        `membership` (default: every vertex alone); returns (sub-community
+        labels, iterations, dq per iteration, movers per iteration)."""
+        opt = options if options is not None else default_options(**kw)
+        b = np.ascontiguousarray(bound, dtype=np.int32)
+        m = np.arange(self.n, dtype=np.int32) if membership is None else np.array(membership, dtype=np.int32)
+        li = ctypes.c_int32()
+        mi = max(opt.max_iterations, 1)
+        dq = np.zeros(mi, dtype=np.float64)
+        mv = np.zeros(mi, dtype=np.int64)
+        self._check(lib().gsp_refine_phase(self._h, b.ctypes.data, m.ctypes.data, HOST, tolerance, ctypes.byref(opt),
+                                           ctypes.byref(li), dq.ctypes.data, mv.ctypes.data), "gsp_refine_phase")
+        return m, li.value, dq[:li.value], mv[:li.value]
 
     # -------------------------------------------------------------- batches
     def load_batch(self, graphs) -> None:

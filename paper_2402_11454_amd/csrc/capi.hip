@@ -73,7 +73,7 @@ struct Timer {
     }
 };
 
-enum { PH_MOVE = 0, PH_SPLIT, PH_AGG, PH_OTHER, PH_COUNT };
+enum { PH_MOVE = 0, PH_SPLIT, PH_AGG, PH_OTHER, PH_REFINE, PH_COUNT };
 
 }  // namespace
 
@@ -122,6 +122,9 @@ struct gsp_ctx {
     int *lp_counts = nullptr;   // queue sizes of the label-propagation split (4 ints)
     // the input graph in degree order (built by the first run asking for it)
     DegreeOrder ord;
+    // GSP-Leiden: the level's bound communities and the next level's
+    // starting communities (graph-sized, allocated on first use)
+    int32_t *bnd = nullptr, *bstart = nullptr;
     double *Kord = nullptr;
     bool ordered = false;
 
@@ -248,6 +251,7 @@ struct gsp_ctx {
         gap_w = nullptr;
         lp_counts = nullptr;
         ord = DegreeOrder();
+        bnd = bstart = nullptr;
         Kord = nullptr;
         ordered = false;
         mhist = iter_dev = nullptr;
@@ -446,6 +450,7 @@ struct PhaseCfg {
     // each graph's counted iterations
     const uint8_t *gdone = nullptr;   // host, per graph
     std::vector<int32_t> li_g;
+    bool single_only = false;         // GSP-Leiden's refinement (MoveArgs::single_only)
     // out
     int32_t li = 0;
     int64_t scanned_vertices = 0, scanned_entries = 0, pruned = 0, confirm_sweeps = 0, sweeps = 0;
@@ -605,6 +610,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
             a.hbuck = ctx->sc.hbuck;
             a.hub_b0 = wl.hub_b0;
             a.grid_cap = cfg.grid_cap;
+            a.single_only = cfg.single_only;
             // the history feeds the gate's features: once a pass has left its
             // gated sweeps it never returns to them, so later sweeps skip it
             // (the history's per-entry adds to D_j cost most of it); trace
@@ -727,6 +733,7 @@ gsp_status move_phase(gsp_ctx *ctx, const Level &g, const double *K, const WorkL
         memcpy(&thbits, &cfg.theta_logit, sizeof(thbits));
         memcpy(&b3bits, &net.b3, sizeof(b3bits));
         key.push_back((int64_t)cfg.return_moves);   // the kernels' move records (or none)
+        key.push_back((int64_t)cfg.single_only);
         key.insert(key.end(), {(int64_t)hist, (int64_t)cfg.pass, (int64_t)thbits, (int64_t)b3bits, ptr(net.w1),
                                ptr(net.w2), ptr(net.b1), ptr(ctx->hbits), (int64_t)ctx->hub_parts,
                                (int64_t)ctx->hub_max_parts});
@@ -903,6 +910,48 @@ gsp_status ensure_levels(gsp_ctx *ctx) {
     ctx->iter_dev = ctx->dalloc<int64_t>(2, &e);
     if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(sweep index)");
     return GSP_OK;
+}
+
+gsp_status ensure_leiden(gsp_ctx *ctx) {
+    if (ctx->bnd) return GSP_OK;
+    if (ctx->mem_limit && ctx->mem_used + 8 * (uint64_t)ctx->n + 16 > ctx->mem_limit)
+        return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached (refinement)");
+    hipError_t e = hipSuccess;
+    ctx->bnd = ctx->dalloc<int32_t>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(bound communities)");
+    ctx->bstart = ctx->dalloc<int32_t>(ctx->n, &e);
+    if (e != hipSuccess) return ctx->fail_hip(e, "hipMalloc(starting communities)");
+    return GSP_OK;
+}
+
+// GSP-Leiden's refinement of level g (Section 3.5, read greedily) within the
+// communities ctx->bnd, from the sub-communities in ctx->cm / sig / csize:
+// the local-moving phase over the same-bound subgraph (built in the level
+// buffers of `slot`, which the caller's next aggregation overwrites) with
+// g's K and 2m, only vertices alone in their sub-community moving.  wl holds
+// g's work lists; its buffers then hold the subgraph's, so the caller builds
+// g's again before it uses them.
+gsp_status refine_level(gsp_ctx *ctx, const Level &g, const double *K, const WorkLists &wl, int slot,
+                        PhaseCfg &pc, int rounds) {
+    hipStream_t s = ctx->stream;
+    Level r = g;
+    r.nlong = 0;
+    r.off = ctx->offL[slot];
+    r.col = ctx->colL[slot];
+    r.deg = ctx->degL[slot];
+    r.wt = g.wt == W_UNIT ? W_UNIT : W_F64;
+    r.w = r.wt == W_UNIT ? nullptr : ctx->wL[slot];
+    HIP_TRY(bound_subgraph(g, wl, ctx->bnd, ctx->degL[slot], ctx->offL[slot], ctx->colL[slot], ctx->wL[slot],
+                           ctx->sc.cch_k0, ctx->sc.scan_tmp, s));
+    HIP_TRY(hipMemcpyAsync(ctx->i64_h, ctx->offL[slot] + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    r.nnz = ctx->i64_h[0];
+    WorkLists wr = make_lists(ctx);
+    HIP_TRY(build_work_lists(r, rounds, wr, ctx->sc, s));
+    pc.single_only = true;
+    pc.return_moves = false;
+    pc.gated = false;
+    return move_phase(ctx, r, K, wr, pc);
 }
 
 // Whether gsp_run stores the input graph in degree order (vertex_order;
@@ -1198,6 +1247,9 @@ gsp_status check_options(gsp_ctx *ctx, const gsp_options &opt) {
         return ctx->fail(GSP_EINVAL, "split_algo must be GSP_SPLIT_UF or GSP_SPLIT_LPP");
     if (opt.hub_max_parts < 0 || opt.hub_max_parts > kMaxParts)
         return ctx->fail(GSP_EINVAL, "hub_max_parts must lie in [0, 4096]");
+    if (opt.leiden != 0 && opt.leiden != 1) return ctx->fail(GSP_EINVAL, "leiden must be 0 or 1");
+    if (opt.leiden && opt.prune_mode != GSP_PRUNE_PLAIN)
+        return ctx->fail(GSP_EINVAL, "GSP-Leiden (leiden = 1) runs with prune_mode GSP_PRUNE_PLAIN");
     if (opt.prune_mode == GSP_PRUNE_LEARNED) {
         if (!(opt.prune_threshold > 0.0f && opt.prune_threshold < 1.0f))
             return ctx->fail(GSP_EINVAL, "prune_threshold must lie in (0, 1)");
@@ -1233,6 +1285,7 @@ gsp_status gsp_default_options(gsp_options *out) {
     out->return_moves = 0;
     out->split_algo = GSP_SPLIT_UF;
     out->vertex_order = GSP_ORDER_AUTO;
+    out->leiden = 0;
     return GSP_OK;
 }
 
@@ -1349,11 +1402,15 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
     if (!(tolerance >= 0.0) || max_passes < 0) return ctx->fail(GSP_EINVAL, "tolerance < 0 or max_passes < 0");
     gsp_status st0 = check_options(ctx, opt);
     if (st0 != GSP_OK) return st0;
+    const bool leiden = opt.leiden != 0;
+    if (leiden && (batch || ctx->tracing))
+        return ctx->fail(GSP_EINVAL, "GSP-Leiden (leiden = 1) runs single graphs without trace capture");
     ctx->mem_limit = opt.mem_limit_bytes;
     if (ctx->mem_limit && ctx->mem_used > ctx->mem_limit)
         return ctx->fail(GSP_ENOMEM, "device memory limit (mem_limit_bytes) reached");
     gsp_status st = ensure_levels(ctx);
     if (st != GSP_OK) return st;
+    if (leiden && (st = ensure_leiden(ctx)) != GSP_OK) return st;
     const bool ordered = wants_order(ctx, opt, batch, max_passes);
     if (ordered && (st = ensure_order(ctx, opt.sub_rounds)) != GSP_OK) return st;
     hipStream_t s = ctx->stream;
@@ -1407,10 +1464,19 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         int t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
         WorkLists wl = make_lists(ctx);
         HIP_TRY(build_work_lists(g, opt.sub_rounds, wl, ctx->sc, s));
-        // Sigma' <- K'; C' <- [0 .. |V'|); sizes 1
-        launch_iota_i32(ctx->cm, g.n, s);
-        HIP_TRY(hipMemcpyAsync(ctx->sig, K, g.n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        launch_fill_i32(ctx->csize, 1, g.n, s);
+        if (leiden && lp > 0) {
+            // GSP-Leiden: each super-vertex starts in the community that
+            // holds its sub-community
+            launch_copy_i32(ctx->cm, ctx->bstart, g.n, s);
+            launch_fill_f64(ctx->sig, 0.0, g.n, s);
+            launch_fill_i32(ctx->csize, 0, g.n, s);
+            launch_community_totals(K, ctx->cm, g.n, ctx->sig, ctx->csize, s);
+        } else {
+            // Sigma' <- K'; C' <- [0 .. |V'|); sizes 1
+            launch_iota_i32(ctx->cm, g.n, s);
+            HIP_TRY(hipMemcpyAsync(ctx->sig, K, g.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            launch_fill_i32(ctx->csize, 1, g.n, s);
+        }
         ctx->timer.end(t);
         t = tphase ? ctx->timer.begin(PH_MOVE) : -1;
         PhaseCfg pc;
@@ -1454,22 +1520,79 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
             labels = ctx->lab;
         }
         t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
-        if (g.orig) {
-            // level 0 in degree order: number the communities as in the
-            // caller's order, split components by their smallest vertex and
-            // communities by their founding vertex, both as caller's ids
-            if (labels == ctx->lab)
+        // level 0 in degree order: number the communities as in the caller's
+        // order, split components by their smallest vertex and communities
+        // by their founding vertex, both as caller's ids
+        auto caller_labels = [&](const int32_t *l) -> const int32_t * {
+            if (!g.orig) return l;
+            if (l == ctx->lab)
                 launch_labels_min_orig(ctx->lab, g.orig, g.n, ctx->sc.i32c, s);
             else
-                launch_labels_orig(ctx->cm, g.orig, g.n, ctx->lab, s);
-            labels = ctx->lab;
-        }
+                launch_labels_orig(l, g.orig, g.n, ctx->lab, s);
+            return ctx->lab;
+        };
+        labels = caller_labels(labels);
         int64_t ncomm = 0;
         st = renumber(ctx, labels, g.n, ctx->cm, &ncomm);
         if (st != GSP_OK) return st;
-        launch_lookup(ctx->top, ctx->n, ctx->cm, s);
         bool stop = false;
-        if (batch) {
+        int64_t nnext = ncomm;   // vertices of the next level
+        if (leiden) {
+            // GSP-Leiden: the result stays the local-moving communities
+            // (ctx->cm, then ctx->bnd); the next level's super-vertices are
+            // their refined sub-communities
+            stop = li <= 1 || (double)ncomm / (double)g.n > opt.aggregation_tolerance || lp == max_passes - 1;
+            const int32_t *result = ctx->cm;
+            if (!stop) {
+                launch_copy_i32(ctx->bnd, ctx->cm, g.n, s);
+                result = ctx->bnd;
+                launch_iota_i32(ctx->cm, g.n, s);
+                HIP_TRY(hipMemcpyAsync(ctx->sig, K, g.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                launch_fill_i32(ctx->csize, 1, g.n, s);
+                ctx->timer.end(t);
+                t = tphase ? ctx->timer.begin(PH_REFINE) : -1;
+                PhaseCfg rc;
+                rc.tau = tau;
+                rc.max_iter = opt.max_iterations;
+                rc.timing_k = tk;
+                rc.timing_side = opt.timing == 3;
+                rc.pass = lp;
+                rc.use_graphs = opt.use_graphs != 0;
+                rc.grid_cap = opt.grid_cap;
+                rc.kernel_bytes = kbytes;
+                st = refine_level(ctx, g, K, wl, next, rc, opt.sub_rounds);
+                if (st != GSP_OK) return st;
+                ctx->stats.scanned_entries += rc.scanned_entries;
+                ctx->stats.scanned_vertices += rc.scanned_vertices;
+                ctx->stats.sweeps += (int32_t)rc.sweeps;
+                ctx->timer.end(t);
+                t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
+                HIP_TRY(build_work_lists(g, opt.sub_rounds, wl, ctx->sc, s));   // g's lists again
+                ctx->timer.end(t);
+                const int32_t *rl = ctx->cm;
+                if (opt.split_mode == GSP_SPLIT_PASS) {
+                    // synchronous moves can leave a sub-community in pieces
+                    // (its founder left as others joined it): split it too
+                    t = tphase ? ctx->timer.begin(PH_SPLIT) : -1;
+                    st = run_split(ctx, g, wl, ctx->cm, ctx->lab, opt.split_algo, &ctx->stats.split_rounds);
+                    if (st != GSP_OK) return st;
+                    kbytes[GSP_K_SPLIT] += 8.0 * (double)g.nnz + 24.0 * (double)g.n;
+                    ctx->timer.end(t);
+                    rl = ctx->lab;
+                }
+                t = tphase ? ctx->timer.begin(PH_OTHER) : -1;
+                rl = caller_labels(rl);
+                st = renumber(ctx, rl, g.n, ctx->cm, &nnext);
+                if (st != GSP_OK) return st;
+                if (lp < GSP_MAX_PASSES_STATS) {
+                    ctx->stats.refine_iterations[lp] = rc.li;
+                    ctx->stats.refined[lp] = nnext;
+                }
+                stop = (double)nnext / (double)g.n > opt.aggregation_tolerance;
+            }
+            launch_lookup(ctx->top, ctx->n, stop ? result : ctx->cm, s);
+        } else if (batch) {
+            launch_lookup(ctx->top, ctx->n, ctx->cm, s);
             // each graph's communities: [cfirst[k], cfirst[k+1])
             launch_batch_cfirst(ctx->sc.i32b, g.vbase, G, ctx->sc.i64e, ctx->cfirst, s);
             HIP_TRY(hipMemcpyAsync(cfirst_h.data(), ctx->cfirst, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1486,6 +1609,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
             }
             stop = all;
         } else {
+            launch_lookup(ctx->top, ctx->n, ctx->cm, s);
             stop = li <= 1 ||                                                // globally converged
                    (double)ncomm / (double)g.n > opt.aggregation_tolerance;    // low shrink
         }
@@ -1501,20 +1625,21 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         int tk2 = tk ? ctx->timer.begin(100 + GSP_K_AGGREGATE) : -1;
         AggOut out{ctx->offL[next], ctx->colL[next], ctx->wL[next], ctx->KL[next], ctx->degL[next]};
         int64_t nnz2 = 0;
-        HIP_TRY(aggregate(g, wl, ctx->cm, ncomm, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s, ctx->hub_parts));
+        HIP_TRY(aggregate(g, wl, ctx->cm, nnext, out, ctx->gap_col, ctx->gap_w, ctx->sc, &nnz2, s, ctx->hub_parts));
         ctx->timer.end(tk2);
+        if (leiden) launch_bound_start(ctx->cm, ctx->bnd, g.n, ctx->bstart, s);
         {
             // read every entry (column, weight, neighbour membership), write
             // the gapped rows of G'' (12 B per entry); per vertex membership,
             // degree, offset and the member list
             int ws = g.wt == W_UNIT ? 0 : (g.wt == W_F32 ? 4 : 8);
             kbytes[GSP_K_AGGREGATE] += (8.0 + ws) * (double)g.nnz + 12.0 * (double)nnz2 + 28.0 * (double)g.n +
-                                       40.0 * (double)ncomm;
+                                       40.0 * (double)nnext;
             if (tk) ctx->kernel_launches[GSP_K_AGGREGATE] += 1;
         }
         ctx->timer.end(t);
         Level g2;
-        g2.n = ncomm;
+        g2.n = nnext;
         g2.nnz = nnz2;
         g2.off = out.off;
         g2.col = out.col;
@@ -1578,6 +1703,7 @@ gsp_status run_passes(gsp_ctx *ctx, double tolerance, int32_t max_passes, const 
         ctx->stats.ms_split = acc[PH_SPLIT];
         ctx->stats.ms_aggregate = acc[PH_AGG];
         ctx->stats.ms_other = acc[PH_OTHER];
+        ctx->stats.ms_refine = acc[PH_REFINE];
         ctx->stats.ms_total = acc[PH_COUNT];
         for (int k = 0; k < GSP_K_COUNT; k++) {
             ctx->stats.kernels[k].ms = acc[100 + k];
@@ -1969,6 +2095,66 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
         counters[1] = pc.scanned_entries;
         counters[2] = pc.pruned;
         counters[3] = pc.confirm_sweeps;
+    }
+    return GSP_OK;
+}
+
+gsp_status gsp_refine_phase(gsp_ctx *ctx, const int32_t *bound, int32_t *membership_inout, int where,
+                            double tolerance, const gsp_options *optp, int32_t *iterations, double *dq_iter,
+                            int64_t *moved_iter) {
+    if (!ctx || !iterations) return GSP_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    gsp_options opt;
+    if (optp)
+        opt = *optp;
+    else
+        gsp_default_options(&opt);
+    opt.leiden = 1;
+    gsp_status st = check_options(ctx, opt);
+    if (st != GSP_OK) return st;
+    if (!(tolerance >= 0.0)) return ctx->fail(GSP_EINVAL, "bad tolerance");
+    if (!ctx->loaded) return ctx->fail(GSP_ESTATE, "no graph loaded");
+    if (!bound && ctx->n > 0) return ctx->fail(GSP_EINVAL, "bound is NULL");
+    if ((st = ensure_levels(ctx)) != GSP_OK) return st;   // the subgraph and the hub staging
+    if ((st = ensure_leiden(ctx)) != GSP_OK) return st;
+    ctx->hub_parts = opt.hub_global == 0;
+    ctx->hub_max_parts = opt.hub_max_parts ? opt.hub_max_parts : kMaxParts;
+    // the bound communities (checked as a membership), then the start
+    if ((st = take_membership(ctx, bound, where)) != GSP_OK) return st;
+    hipStream_t s = ctx->stream;
+    launch_copy_i32(ctx->bnd, ctx->cm, ctx->n, s);
+    if ((st = take_membership(ctx, membership_inout, where)) != GSP_OK) return st;
+    HIP_TRY(hipMemsetAsync(ctx->sc.err, 0, sizeof(int), s));
+    launch_bound_check(ctx->cm, ctx->bnd, ctx->n, ctx->sc.i32c, ctx->sc.err, s);
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, ctx->sc.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return ctx->fail(GSP_EINVAL, "a starting sub-community lies in two bound communities");
+    Level g = level0(ctx);
+    launch_fill_f64(ctx->sig, 0.0, g.n, s);
+    launch_fill_i32(ctx->csize, 0, g.n, s);
+    launch_community_totals(ctx->K0, ctx->cm, g.n, ctx->sig, ctx->csize, s);
+    WorkLists wl = make_lists(ctx);
+    HIP_TRY(build_work_lists(g, opt.sub_rounds, wl, ctx->sc, s));
+    int mi = opt.max_iterations;
+    std::vector<double> dq(mi > 0 ? mi : 1);
+    std::vector<int64_t> mv(mi > 0 ? mi : 1);
+    PhaseCfg pc;
+    pc.tau = tolerance;
+    pc.max_iter = mi;
+    pc.use_graphs = opt.use_graphs != 0;
+    pc.grid_cap = opt.grid_cap;
+    pc.dq_out = dq.data();
+    pc.moved_out = mv.data();
+    st = refine_level(ctx, g, ctx->K0, wl, 0, pc, opt.sub_rounds);
+    if (st != GSP_OK) return st;
+    st = copy_out(ctx, membership_inout, ctx->cm, g.n, where);
+    if (st != GSP_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    *iterations = pc.li;
+    for (int k = 0; k < pc.li; k++) {
+        if (dq_iter) dq_iter[k] = dq[k];
+        if (moved_iter) moved_iter[k] = mv[k];
     }
     return GSP_OK;
 }

@@ -188,6 +188,9 @@ struct MoveArgs {
     // workgroups (0: each kernel's own cap); their loops stride over the
     // grid, so any cap gives the same results
     int grid_cap = 0;
+    // GSP-Leiden's refinement: a vertex is queued only while its community
+    // (sub-community) holds it alone; the others leave the frontier
+    bool single_only = false;
     // batch of graphs (g.gid != nullptr): per-graph totals of the sweep and
     // the graphs still iterating
     unsigned long long *ggain = nullptr;        // per graph, units of gain_units
@@ -291,6 +294,22 @@ void launch_move_hub_parts(const MoveArgs &a, hipStream_t s);    // phase 1: chu
 void launch_move_hub_gather(const MoveArgs &a, hipStream_t s);   // phase 2: partitions merged and scored
 void launch_move_hub_decide(const MoveArgs &a, hipStream_t s);   // phase 3: a workgroup per hub decides
 void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
+
+// ---- k_leiden.hip ----
+// The same-bound subgraph of a level for GSP-Leiden's refinement: row i
+// keeps the entries (i, j) with bound[j] == bound[i], in order.  Writes its
+// degrees (deg, n), offsets (off, n + 1) and entries (col; w as fp64 unless
+// g has unit weights); wl holds g's work lists (their hub chunks split the
+// long rows), ch_cnt one value per hub chunk.
+hipError_t bound_subgraph(const Level &g, const WorkLists &wl, const int32_t *bound, int32_t *deg, int64_t *off,
+                          int32_t *col, double *w, int64_t *ch_cnt, void *scan_tmp, hipStream_t s);
+// *err |= 1 if a sub-community has members in two bound communities (home:
+// n ints of scratch; *err is not cleared here).
+void launch_bound_check(const int32_t *sub, const int32_t *bound, int64_t n, int32_t *home, int *err,
+                        hipStream_t s);
+// start[sub[i]] <- bound[i]: each sub-community (super-vertex of the next
+// level) starts in the community that holds it.
+void launch_bound_start(const int32_t *sub, const int32_t *bound, int64_t n, int32_t *start, hipStream_t s);
 
 // ---- k_gate.hip ----
 // Gated sweep: the candidates of every bin (cand, ctr->ccnt[round]) go

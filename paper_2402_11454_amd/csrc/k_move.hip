@@ -299,7 +299,11 @@ __global__ void __launch_bounds__(kBlock) k_move_compact(MoveArgs a, const int32
         int b = 0;
         while (t >= pre[b + 1]) b++;
         const int i = bl[a.qbase[b] + (t - pre[b])];
-        const bool act = a.flag[i] != 0 && (!a.gactive || a.gactive[a.g.gid[i]]);
+        bool act = a.flag[i] != 0 && (!a.gactive || a.gactive[a.g.gid[i]]);
+        if (act && a.single_only && a.csize[a.cm[i]] != 1) {
+            a.flag[i] = 0;   // merged into a sub-community: stays
+            act = false;
+        }
         if (b == BIN_HUB) a.hub_act[i] = act ? 1 : 0;
         if (act) {
             a.flag[i] = 0;
