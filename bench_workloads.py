@@ -1,10 +1,13 @@
 """Timings of the other workloads (beside bench.py's R-MAT 26): the batch of
 512 planted-partition SBMs and the 4M-vertex degree-corrected SBM, plain
 and learned-pruned, with the return-move option off (the tolerance test as
-written) and on.  Whole runs, graph resident in device memory, best of
-`--reps` runs after one warm-up run; prints one line per case.
+written) and on; the split ablation; GSP-Leiden against GSP-Louvain.  Whole
+runs, graph resident in device memory, best of `--reps` runs after one
+warm-up run; prints one line per case.
 
-    python bench_workloads.py [--batch] [--dcsbm] [--reps 3]
+    python bench_workloads.py [--batch] [--dcsbm] [--road] [--reps 3]
+    python bench_workloads.py --split-ablation rmat20,dcsbm4m,road,rmat26
+    python bench_workloads.py --leiden rmat20,dcsbm4m,road,rmat26
 """
 import argparse
 import os
@@ -45,6 +48,23 @@ def split_ablation(ctx, gsp, name, g, reps):
               f"{disc} of {ncomm} communities disconnected ({disc / ncomm:.2%}), passes {st['passes']}", flush=True)
 
 
+def leiden_vs_louvain(ctx, name, g, reps):
+    """GSP-Leiden (refinement in every pass) beside GSP-Louvain on one graph:
+    time per run, phase times, passes, modularity and disconnected
+    communities."""
+    for label, lei in (("louvain", 0), ("leiden", 1)):
+        dt = _best(lambda: ctx.run(1e-2, 10, leiden=lei), reps)
+        ctx.run(1e-2, 10, leiden=lei, timing=1)
+        st = ctx.stats()
+        m = ctx.membership()
+        print(f"leiden {name} {label}: {dt * 1e3:.2f} ms per run, {g.nnz / dt / 1e9:.3f} G entries/s, "
+              f"passes {st['passes']}, iterations {st['iterations']}, refine iterations {st['refine_iterations']}, "
+              f"communities {st['communities']}, refined {st['refined']}, phases ms move {st['ms_move']:.1f} "
+              f"refine {st['ms_refine']:.1f} split {st['ms_split']:.1f} aggregate {st['ms_aggregate']:.1f} "
+              f"other {st['ms_other']:.1f}, scanned {st['scanned_entries']}, Q {ctx.result_modularity():.6f}, "
+              f"{ctx.count_disconnected(m)} of {int(m.max()) + 1} communities disconnected", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--batch", action="store_true", help="512 SBM graphs, n log-uniform in [1e3, 2e5]")
@@ -52,8 +72,22 @@ def main():
     ap.add_argument("--road", action="store_true", help="road-like graph, 59M vertices, average degree 2.1")
     ap.add_argument("--split-ablation", default="", help="comma list of bench.py workloads (rmat20, dcsbm4m, "
                                                           "rmat26) or road: split modes x algorithms")
+    ap.add_argument("--leiden", default="", help="comma list of bench.py workloads or road: GSP-Leiden beside "
+                                                  "GSP-Louvain")
     ap.add_argument("--reps", type=int, default=3)
     a = ap.parse_args()
+    if a.leiden:
+        import gsp_inputs as gi
+        import paper_2402_11454_amd as gsp
+        from bench import make_graph
+        ctx = gsp.Context(0)
+        for name in a.leiden.split(","):
+            g = gi.road_network() if name == "road" else make_graph(name)
+            ctx.load_graph(g)
+            leiden_vs_louvain(ctx, name, g, a.reps)
+            del g
+        ctx.close()
+        return
     if a.split_ablation:
         import gsp_inputs as gi
         import paper_2402_11454_amd as gsp

@@ -12,7 +12,12 @@ Bars:
   * batch: every 16th graph's membership bit-identical to the oracle's run of
     that graph alone, Q within 1e-9, passes equal; no graph with a
     disconnected community; with learned pruning (the trained network), every
-    32nd graph equal to its single-graph GPU run.
+    32nd graph equal to its single-graph GPU run;
+  * GSP-Leiden, whole runs in the loaded order and in degree order: on the 4M
+    graph equal to the oracle's stored run (tests/golden/make_leiden.py), on
+    R-MAT 20 equal to the oracle's run made here: membership, per-pass
+    local-moving and refinement statistics, Q within 1e-9; no disconnected
+    community.
 """
 import hashlib
 import json
@@ -29,6 +34,7 @@ from golden import make_dcsbm4m as mk
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dcsbm4m_oracle.json")
+LEIDEN = os.path.join(os.path.dirname(GOLDEN), "leiden_oracle.json")
 
 
 def _gpu_count():
@@ -142,3 +148,44 @@ def test_batch512_learned_equals_single_runs(ctx, batch):
         res = ctx.louvain(1e-2, 10, **kw)
         assert np.array_equal(m, res.membership), k
         assert abs(q[k] - res.modularity) <= 1e-12
+
+
+def _leiden_matches(res, ref_stats, sha, q):
+    assert res.stats["iterations"] == ref_stats["iterations"]
+    assert res.stats["communities"] == ref_stats["communities"]
+    assert res.stats["refine_iterations"] == ref_stats["refine_iterations"]
+    assert res.stats["refined"] == ref_stats["refined"]
+    assert hashlib.sha1(np.ascontiguousarray(res.membership, dtype=np.int32).tobytes()).hexdigest() == sha
+    assert abs(res.modularity - q) <= 1e-9
+
+
+@pytest.mark.parametrize("order", [gsp.ORDER_LOADED, gsp.ORDER_DEGREE])
+def test_dcsbm4m_leiden_equals_oracle(ctx, g4m, order):
+    with open(LEIDEN) as f:
+        ref = json.load(f)["dcsbm4m"]
+    assert ref["n"] == g4m.n and ref["nnz"] == g4m.nnz
+    ctx.load_graph(g4m)
+    print(f"[leiden] dcsbm4m order={order}", flush=True)
+    res = ctx.louvain(1e-2, 10, leiden=1, vertex_order=order)
+    _leiden_matches(res, ref, ref["membership_sha1"], ref["modularity"])
+    assert ctx.count_disconnected(res.membership) == 0
+
+
+@pytest.fixture(scope="module")
+def rmat20_leiden():
+    g = gi.rmat20()
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=True)
+    sha = hashlib.sha1(np.ascontiguousarray(ref.membership, dtype=np.int32).tobytes()).hexdigest()
+    stats = dict(iterations=ref.iterations, communities=ref.communities, refine_iterations=ref.refine_iterations,
+                 refined=ref.refined)
+    return g, stats, sha, ref.modularity
+
+
+@pytest.mark.parametrize("order", [gsp.ORDER_LOADED, gsp.ORDER_DEGREE])
+def test_rmat20_leiden_equals_oracle(ctx, rmat20_leiden, order):
+    g, stats, sha, q = rmat20_leiden
+    ctx.load_graph(g)
+    print(f"[leiden] rmat20 order={order}", flush=True)
+    res = ctx.louvain(1e-2, 10, leiden=1, vertex_order=order)
+    _leiden_matches(res, stats, sha, q)
+    assert ctx.count_disconnected(res.membership) == 0
