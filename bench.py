@@ -20,6 +20,8 @@ of gsp_run (tolerance 1e-2, at most 10 passes) follow:
     (config.plain, config.vs_plain) and the local-moving phase's
     algorithmic GB/s (scan bytes over the phase's event time);
   * the same runs without any events (config.untimed);
+  * GSP-Leiden runs (the refinement in every pass) without events, after one
+    warm-up run (config.leiden);
   * a CPU baseline: the sequential oracle on one pinned host core, on a
     bounded sample of the same graph.
 
@@ -85,6 +87,7 @@ def parse():
                    help="storage order of the graph inside the runs (auto: degree order from 2^25 entries)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-untimed", action="store_true", help="skip the runs without events")
+    p.add_argument("--no-leiden", action="store_true", help="skip the GSP-Leiden runs")
     p.add_argument("--kernel-class", default="", choices=[""] + sorted(KERNEL_NAMES),
                    help="time this kernel class (no probe runs)")
     p.add_argument("--only-timed", action="store_true",
@@ -330,6 +333,20 @@ def main():
                    "vs_plain": round(el0 / el1, 4)}
         log(f"no events: plain {untimed['plain_ms_per_step']} ms, learned {untimed['learned_ms_per_step']} ms")
 
+    leiden = None
+    if not a.no_leiden:
+        vo = ORDERS[a.vertex_order]
+        ctx.run(a.tolerance, a.max_passes, vertex_order=vo, leiden=1)
+        el_d, _, _, st_d = timed_runs(ctx, gsp, a, a.steps, leiden=1)
+        memb_d = ctx.membership()
+        q_d = ctx.result_modularity()
+        leiden = {"ms_per_step": round(1000.0 * el_d / a.steps, 3), "value": round(g.nnz / (el_d / a.steps), 1),
+                  "modularity": round(q_d, 6), "disconnected": ctx.count_disconnected(memb_d),
+                  "passes": st_d["passes"], "iterations": st_d["iterations"], "refined": st_d["refined"],
+                  "time_vs_plain_untimed": None if untimed is None else
+                  round(1000.0 * el_d / a.steps / untimed["plain_ms_per_step"], 4)}
+        log(f"GSP-Leiden: {leiden['ms_per_step']} ms/run, Q={q_d:.6f}, passes={st_d['passes']}")
+
     v = kst[dom]
     achieved = v["bytes"] / (v["ms"] * 1e-3) / 1e9
     kern = KERNEL_NAMES[dom]
@@ -381,7 +398,7 @@ def main():
                              "phase_ms_per_run": {k: round(x / a.steps, 3) for k, x in ph_p.items()}},
                    "learned_local_moving": move_phase(kst, ph_l),
                    "modularity_minus_plain": round(q_l - q_p, 6), "quality": quality, "target": target,
-                   "untimed": untimed},
+                   "untimed": untimed, "leiden": leiden},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

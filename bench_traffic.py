@@ -32,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 
 
-def run_workload(runs: int, workload: str, learned: bool, order: str = "auto"):
+def run_workload(runs: int, workload: str, learned: bool, order: str = "auto", leiden: bool = False):
     sys.path.insert(0, ROOT)
     import torch
     import paper_2402_11454_amd as gsp
@@ -54,6 +54,8 @@ def run_workload(runs: int, workload: str, learned: bool, order: str = "auto"):
         ctx.pruner_set(load_params(DEFAULT_OUT))
         from bench import WORKLOADS
         kw.update(prune_mode=gsp.PRUNE_LEARNED, prune_threshold=THETA_BY_CLASS[WORKLOADS[workload]["kind"]])
+    if leiden:
+        kw.update(leiden=1)
     for k in range(runs):
         ctx.run(1e-2, 10, **kw)
         print(f"[pmc] run {k + 1}/{runs}", flush=True)
@@ -319,6 +321,7 @@ if __name__ == "__main__":
     ap.add_argument("--cmd", default="")
     ap.add_argument("--workload", default="rmat26")
     ap.add_argument("--learned", action="store_true", help="learned-pruned runs (bench.py's timed runs)")
+    ap.add_argument("--leiden", action="store_true", help="GSP-Leiden runs")
     ap.add_argument("--tag", default="", help="suffix of the summary's file names (e.g. _plain)")
     ap.add_argument("--vertex-order", default="auto", choices=("auto", "loaded", "degree"),
                     help="storage order of the graph inside the --run runs")
@@ -338,7 +341,7 @@ if __name__ == "__main__":
     if a.kernel_summary:
         kernel_summary(a.kernel_summary[0], a.cmd, a.title, a.kernel_summary[1], a.bench_out)
     if a.run:
-        run_workload(a.runs, a.workload, a.learned, a.vertex_order)
+        run_workload(a.runs, a.workload, a.learned, a.vertex_order, a.leiden)
     if a.summarize:
         summarize(a.summarize[0], a.summarize[1], a.cmd, a.workload, a.runs, a.tag)
     if a.phase_times:

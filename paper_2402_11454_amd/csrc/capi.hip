@@ -941,8 +941,10 @@ gsp_status refine_level(gsp_ctx *ctx, const Level &g, const double *K, const Wor
     r.deg = ctx->degL[slot];
     r.wt = g.wt == W_UNIT ? W_UNIT : W_F64;
     r.w = r.wt == W_UNIT ? nullptr : ctx->wL[slot];
+    // the gap buffer (hub staging of the local-moving phases, the
+    // aggregation's rows) is idle here: a byte per entry of g
     HIP_TRY(bound_subgraph(g, wl, ctx->bnd, ctx->degL[slot], ctx->offL[slot], ctx->colL[slot], ctx->wL[slot],
-                           ctx->sc.cch_k0, ctx->sc.scan_tmp, s));
+                           ctx->sc.cch_k0, reinterpret_cast<uint8_t *>(ctx->gap_col), ctx->sc.scan_tmp, s));
     HIP_TRY(hipMemcpyAsync(ctx->i64_h, ctx->offL[slot] + g.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     r.nnz = ctx->i64_h[0];

@@ -300,9 +300,11 @@ void launch_move_apply(const MoveArgs &a, int64_t cap, hipStream_t s);
 // keeps the entries (i, j) with bound[j] == bound[i], in order.  Writes its
 // degrees (deg, n), offsets (off, n + 1) and entries (col; w as fp64 unless
 // g has unit weights); wl holds g's work lists (their hub chunks split the
-// long rows), ch_cnt one value per hub chunk.
+// long rows), ch_cnt one value per hub chunk, kept one byte per entry of g
+// (scratch, indexed like g's entries).
 hipError_t bound_subgraph(const Level &g, const WorkLists &wl, const int32_t *bound, int32_t *deg, int64_t *off,
-                          int32_t *col, double *w, int64_t *ch_cnt, void *scan_tmp, hipStream_t s);
+                          int32_t *col, double *w, int64_t *ch_cnt, uint8_t *kept, void *scan_tmp,
+                          hipStream_t s);
 // *err |= 1 if a sub-community has members in two bound communities (home:
 // n ints of scratch; *err is not cleared here).
 void launch_bound_check(const int32_t *sub, const int32_t *bound, int64_t n, int32_t *home, int *err,

@@ -14,18 +14,19 @@
 // A level's row i is [off[i], off[i] + deg[i]) (aggregated levels leave a
 // gap after each row, whose stale contents are never read).
 //
-// Rows of at most kBlockMaxDeg entries are counted and copied by the lanes
-// (rows of at most kLaneRow entries, one lane each) or by a wavefront
-// (longer rows, one after another, ballot-ordered); hub rows by their work
-// list chunks of kHubChunk entries, one workgroup each, a chunk's place in
-// its row being the kept entries of the row's earlier chunks.
+// Rows of at most kBlockMaxDeg entries are counted and copied by tiles of
+// rows whose entries stream through a workgroup in order; hub rows by their
+// work list chunks of kHubChunk entries, one workgroup each, a chunk's place
+// in its row being the kept entries of the row's earlier chunks.  The count
+// pass leaves a byte per entry (kept or not) for the copy pass, which so
+// reads bytes in order instead of gathering bound[j] again.
 #include "device_common.h"
 #include "gsp_internal.h"
 
 namespace gsp {
 namespace {
 
-constexpr int kLaneRow = 32;
+constexpr int kTileRows = kBlock;
 
 template <int WT>
 __device__ __forceinline__ void put_entry(const Level &g, int64_t e, int64_t at, int32_t *colR, double *wR) {
@@ -33,53 +34,88 @@ __device__ __forceinline__ void put_entry(const Level &g, int64_t e, int64_t at,
     if constexpr (WT != W_UNIT) wR[at] = edge_weight<WT>(g.w, e);
 }
 
-// Rows that are not hubs: FILL = false writes their kept-entry counts (0 for
-// hubs, whose chunks add theirs after), FILL = true copies their kept
-// entries to offR[i] onwards.  Wavefront k takes rows [64 k, 64 k + 64).
+// Rows that are not hubs, kTileRows per workgroup: the tile's rows' entries
+// are taken as one sequence (row after row, each [off, off + deg); hub rows
+// count as empty), kBlock at a time, each entry's row found by binary
+// search in the tile's prefix of row lengths, so the loads of consecutive
+// threads are consecutive.  FILL = false writes each row's kept-entry count
+// (0 for hubs, whose chunks add theirs after); FILL = true writes the kept
+// entries in order: an entry's place is the number of kept entries of the
+// tile before it, less that number at its row's first entry.
 template <int WT, bool FILL>
-__global__ void __launch_bounds__(kBlock) k_bound_rows(Level g, const int32_t *bound, int32_t *cnt,
+__global__ void __launch_bounds__(kBlock) k_bound_tile(Level g, const int32_t *bound, uint8_t *kept, int32_t *cnt,
                                                       const int64_t *offR, int32_t *colR, double *wR) {
-    const int lane = lane_id();
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t r0 = ((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * kWave; r0 < g.n;
-         r0 += waves * kWave) {
-        const int64_t r = r0 + lane;
-        int64_t d = 0;
-        if (r < g.n) d = g.deg[r];
-        if (r < g.n && d <= kLaneRow) {
-            const int b = bound[r];
-            int64_t k = 0;
-            for (int64_t e = g.off[r]; e < g.off[r] + d; e++) {
-                if (bound[g.col[e]] != b) continue;
-                if constexpr (FILL) put_entry<WT>(g, e, offR[r] + k, colR, wR);
-                k++;
-            }
-            if constexpr (!FILL) cnt[r] = (int32_t)k;
-        } else if (!FILL && r < g.n && d > kBlockMaxDeg) {
-            cnt[r] = 0;
+    __shared__ int32_t pre[kTileRows + 1];   // exclusive prefix of the tile's row lengths
+    __shared__ int32_t acc[kTileRows];       // kept entries per row / kept before the row's first entry
+    __shared__ int32_t wsum[kBlock / kWave];
+    const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+    static_assert(kTileRows == kBlock, "one row length per thread");
+    for (int64_t r0 = (int64_t)blockIdx.x * kTileRows; r0 < g.n; r0 += (int64_t)gridDim.x * kTileRows) {
+        const int nr = g.n - r0 < kTileRows ? (int)(g.n - r0) : kTileRows;
+        int d = 0;
+        if (t < nr) {
+            d = g.deg[r0 + t];
+            if (d > kBlockMaxDeg) d = 0;
         }
-        // the wavefront's rows of kLaneRow < d <= kBlockMaxDeg, one by one
-        unsigned long long longer = __ballot(r < g.n && d > kLaneRow && d <= kBlockMaxDeg);
-        while (longer) {
-            const int l = __builtin_ctzll(longer);
-            longer &= longer - 1;
-            const int64_t i = r0 + l;
-            const int b = bound[i];
-            const int64_t beg = g.off[i], end = beg + g.deg[i];
-            int64_t k = 0;
-            for (int64_t e0 = beg; e0 < end; e0 += kWave) {
-                const int64_t e = e0 + lane;
-                const bool keep = e < end && bound[g.col[e]] == b;
-                const unsigned long long m = __ballot(keep);
-                if constexpr (FILL) {
-                    if (keep) put_entry<WT>(g, e, offR[i] + k + __popcll(m & ((1ull << lane) - 1)), colR, wR);
+        int x = d;   // inclusive prefix within the wavefront
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(x, o, kWave);
+            if (lane >= o) x += y;
+        }
+        if (lane == kWave - 1) wsum[w] = x;
+        __syncthreads();
+        int base = 0, total = 0;
+        for (int q = 0; q < kBlock / kWave; q++) {
+            base += q < w ? wsum[q] : 0;
+            total += wsum[q];
+        }
+        pre[t] = base + x - d;
+        if (t == kBlock - 1) pre[kTileRows] = total;
+        acc[t] = 0;
+        __syncthreads();
+        int carry = 0;   // FILL: kept entries of the tile before this step (the same in every thread)
+        for (int v0 = 0; v0 < total; v0 += kBlock) {
+            const int v = v0 + t;
+            int j = 0;
+            bool keep = false;
+            int64_t e = 0;
+            if (v < total) {
+                int lo = 0, hi = nr - 1;   // the last row j with pre[j] <= v
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= v) lo = mid; else hi = mid - 1;
                 }
-                k += __popcll(m);
+                j = lo;
+                e = g.off[r0 + j] + (v - pre[j]);
+                if constexpr (FILL)
+                    keep = kept[e] != 0;
+                else
+                    keep = bound[g.col[e]] == bound[r0 + j];
             }
             if constexpr (!FILL) {
-                if (lane == 0) cnt[i] = (int32_t)k;
+                if (v < total) kept[e] = keep ? 1 : 0;
+                if (keep) atomicAdd(&acc[j], 1);
+            } else {
+                const unsigned long long m = __ballot(keep);
+                if (lane == 0) wsum[w] = __popcll(m);
+                __syncthreads();
+                int before = carry, step = 0;
+                for (int q = 0; q < kBlock / kWave; q++) {
+                    before += q < w ? wsum[q] : 0;
+                    step += wsum[q];
+                }
+                before += __popcll(m & ((1ull << lane) - 1));
+                if (v < total && v == pre[j]) acc[j] = before;
+                __syncthreads();
+                if (keep) put_entry<WT>(g, e, offR[r0 + j] + (before - acc[j]), colR, wR);
+                carry += step;
             }
         }
+        __syncthreads();
+        if constexpr (!FILL) {
+            if (t < nr) cnt[r0 + t] = acc[t];
+        }
+        __syncthreads();   // pre, acc and wsum are rewritten by the next tile
     }
 }
 
@@ -88,7 +124,8 @@ __global__ void __launch_bounds__(kBlock) k_bound_rows(Level g, const int32_t *b
 // row's count; FILL = true copies the kept entries, in order, after those
 // of the row's earlier chunks (hub_ch0[i] is the row's first chunk).
 template <int WT, bool FILL>
-__global__ void __launch_bounds__(kBlock) k_bound_chunks(Level g, const int32_t *bound, const int32_t *ch_vert,
+__global__ void __launch_bounds__(kBlock) k_bound_chunks(Level g, const int32_t *bound, uint8_t *kept,
+                                                        const int32_t *ch_vert,
                                                         const int64_t *ch_beg, int64_t nch, const int32_t *hub_ch0,
                                                         int64_t *ch_cnt, int32_t *cnt, const int64_t *offR,
                                                         int32_t *colR, double *wR) {
@@ -103,7 +140,11 @@ __global__ void __launch_bounds__(kBlock) k_bound_chunks(Level g, const int32_t 
         const int64_t end = beg + kHubChunk < row_end ? beg + kHubChunk : row_end;
         if constexpr (!FILL) {
             int64_t k = 0;
-            for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) k += bound[g.col[e]] == b;
+            for (int64_t e = beg + threadIdx.x; e < end; e += kBlock) {
+                const bool keep = bound[g.col[e]] == b;
+                kept[e] = keep ? 1 : 0;
+                k += keep;
+            }
             k = group_sum_ll<kWave>(k);
             if (lane == 0) wsum[w] = k;
             __syncthreads();
@@ -130,7 +171,7 @@ __global__ void __launch_bounds__(kBlock) k_bound_chunks(Level g, const int32_t 
             int64_t at = base;
             for (int64_t e0 = beg; e0 < end; e0 += kBlock) {
                 const int64_t e = e0 + threadIdx.x;
-                const bool keep = e < end && bound[g.col[e]] == b;
+                const bool keep = e < end && kept[e] != 0;
                 const unsigned long long m = __ballot(keep);
                 __syncthreads();   // the previous round's wsum reads are done
                 if (lane == 0) wsum[w] = __popcll(m);
@@ -174,32 +215,33 @@ inline unsigned grid_of(int64_t n, int64_t per_block, unsigned cap) {
 
 template <int WT>
 void bound_subgraph_t(const Level &g, const WorkLists &wl, const int32_t *bound, int32_t *deg, int64_t *off,
-                      int32_t *col, double *w, int64_t *ch_cnt, void *scan_tmp, hipStream_t s) {
-    const unsigned gr = grid_of(g.n, kBlock, 16384);
+                      int32_t *col, double *w, int64_t *ch_cnt, uint8_t *kept, void *scan_tmp, hipStream_t s) {
+    const unsigned gr = grid_of(g.n, kTileRows, 16384);
     const int64_t nch = wl.nchunks;
     const unsigned gc = grid_of(nch, 1, 65536);
-    k_bound_rows<WT, false><<<gr, kBlock, 0, s>>>(g, bound, deg, nullptr, nullptr, nullptr);
+    k_bound_tile<WT, false><<<gr, kBlock, 0, s>>>(g, bound, kept, deg, nullptr, nullptr, nullptr);
     if (nch > 0)
-        k_bound_chunks<WT, false><<<gc, kBlock, 0, s>>>(g, bound, wl.ch_vert, wl.ch_beg, nch, wl.hub_ch0, ch_cnt,
-                                                        deg, nullptr, nullptr, nullptr);
+        k_bound_chunks<WT, false><<<gc, kBlock, 0, s>>>(g, bound, kept, wl.ch_vert, wl.ch_beg, nch, wl.hub_ch0,
+                                                        ch_cnt, deg, nullptr, nullptr, nullptr);
     scan_exclusive_i32_to_i64(deg, off, g.n, scan_tmp, s);
-    k_bound_rows<WT, true><<<gr, kBlock, 0, s>>>(g, bound, nullptr, off, col, w);
+    k_bound_tile<WT, true><<<gr, kBlock, 0, s>>>(g, bound, kept, nullptr, off, col, w);
     if (nch > 0)
-        k_bound_chunks<WT, true><<<gc, kBlock, 0, s>>>(g, bound, wl.ch_vert, wl.ch_beg, nch, wl.hub_ch0, ch_cnt,
-                                                       nullptr, off, col, w);
+        k_bound_chunks<WT, true><<<gc, kBlock, 0, s>>>(g, bound, kept, wl.ch_vert, wl.ch_beg, nch, wl.hub_ch0,
+                                                       ch_cnt, nullptr, off, col, w);
 }
 
 }  // namespace
 
 hipError_t bound_subgraph(const Level &g, const WorkLists &wl, const int32_t *bound, int32_t *deg, int64_t *off,
-                          int32_t *col, double *w, int64_t *ch_cnt, void *scan_tmp, hipStream_t s) {
+                          int32_t *col, double *w, int64_t *ch_cnt, uint8_t *kept, void *scan_tmp,
+                          hipStream_t s) {
     if (g.n == 0) return hipSuccess;
     if (g.wt == W_UNIT)
-        bound_subgraph_t<W_UNIT>(g, wl, bound, deg, off, col, w, ch_cnt, scan_tmp, s);
+        bound_subgraph_t<W_UNIT>(g, wl, bound, deg, off, col, w, ch_cnt, kept, scan_tmp, s);
     else if (g.wt == W_F32)
-        bound_subgraph_t<W_F32>(g, wl, bound, deg, off, col, w, ch_cnt, scan_tmp, s);
+        bound_subgraph_t<W_F32>(g, wl, bound, deg, off, col, w, ch_cnt, kept, scan_tmp, s);
     else
-        bound_subgraph_t<W_F64>(g, wl, bound, deg, off, col, w, ch_cnt, scan_tmp, s);
+        bound_subgraph_t<W_F64>(g, wl, bound, deg, off, col, w, ch_cnt, kept, scan_tmp, s);
     return hipGetLastError();
 }
 
