@@ -18,11 +18,15 @@ constexpr int kIntMax = 0x7fffffff;     // "no community" in an argmax
 // processed by:
 //   d <= 4, 8, 16, 32, 64 : a group of 4/8/16/32/64 lanes, one entry per lane,
 //                           table of 2*group slots in LDS;
-//   d <= 512              : one wavefront, table of 1024 slots in LDS;
-//   d <= 2048             : one 256-thread workgroup, table of 4096 slots in LDS;
+//   d <= 512              : one wavefront, table in LDS (1024 slots on unit
+//                           weights, 768 otherwise);
+//   d <= 2048             : one 256-thread workgroup, table in LDS (4096 slots
+//                           on unit weights, 3072 otherwise);
 //   d > 2048              : several workgroups, table of nextpow2(2d) slots in
 //                           global memory ("hub").
-// Every table is at most half full, so linear probing always terminates.
+// Every table is at most half full (the local-moving scan's wave and
+// workgroup tables on weighted graphs two thirds), so linear probing always
+// terminates.
 constexpr int kNumBins = 8;
 enum { BIN_G4 = 0, BIN_G8, BIN_G16, BIN_G32, BIN_G64, BIN_WAVE, BIN_BLOCK, BIN_HUB };
 constexpr int kNumSmallBins = 5;

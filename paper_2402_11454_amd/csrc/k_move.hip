@@ -497,16 +497,68 @@ __device__ void block_argmax_sum(double &bg, int &bc, double &x, const int32_t *
     __syncthreads();
 }
 
-// One wavefront per vertex of 65..512 entries, 1024-slot table in its LDS.
+// The LDS tables of the wave and workgroup bins (and of the hub chunks).
+// With fp64 values they have 768 and 3072 slots, at most two thirds full for
+// 512 and 2048 entries: 36 KB per workgroup of four wave tables or one
+// workgroup table, so four workgroups share a CU's LDS where half-full
+// tables let three (R-MAT 26: 3 % less time per run).  A key's first slot is
+// then the multiply-shift reduction of its hash onto the T slots in use, and
+// probing is linear with wrap-around.  On unit weights (int values) the
+// half-full power-of-two tables already fit four workgroups, and the
+// fuller ones only lengthened the probes (R-MAT 20: 2.6 % more time), so
+// they stay.
+template <int WT> struct ScanSlots {
+    static constexpr int wave = WT == W_UNIT ? kWaveTable : 3 * kWaveMaxDeg / 2;
+    static constexpr int block = WT == W_UNIT ? kBlockTable : 3 * kBlockMaxDeg / 2;
+    // slots a vertex of d entries uses in a table of `cap` slots
+    __device__ static int of(int d, int cap) {
+        return WT == W_UNIT || d <= cap / 3 ? (int)hub_table_size(d) : cap;
+    }
+};
+__device__ __forceinline__ uint32_t block_slot(int key, uint32_t T) {
+    return (uint32_t)(((uint64_t)key_hash(key) * T) >> 32);
+}
+__device__ __forceinline__ void block_put(int *keys, int *vals, uint32_t T, int key, double) {
+    uint32_t s = block_slot(key, T);
+    while (true) {
+        const int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            atomicAdd(&vals[s], 1);
+            return;
+        }
+        s = s + 1 == T ? 0 : s + 1;
+    }
+}
+__device__ __forceinline__ void block_put(int *keys, double *vals, uint32_t T, int key, double w) {
+    uint32_t s = block_slot(key, T);
+    while (true) {
+        const int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            atomicAdd(&vals[s], w);
+            return;
+        }
+        s = s + 1 == T ? 0 : s + 1;
+    }
+}
+template <int WT, typename V>
+__device__ __forceinline__ void scan_put(int *keys, V *vals, int T, int key, double w) {
+    if constexpr (WT == W_UNIT)
+        lds_table_put(keys, vals, (uint32_t)T - 1, key, w);   // T a power of two
+    else
+        block_put(keys, vals, (uint32_t)T, key, w);
+}
+
+// One wavefront per vertex of 65..512 entries, table in its LDS.
 template <int WT>
-__global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, 4) k_move_wave(MoveArgs a) {
     using V = typename TabVal<WT>::T;
-    __shared__ int tkeys[kBlock / kWave * kWaveTable];
-    __shared__ V tvals[kBlock / kWave * kWaveTable];
+    constexpr int S = ScanSlots<WT>::wave;
+    __shared__ int tkeys[kBlock / kWave * S];
+    __shared__ V tvals[kBlock / kWave * S];
     const int w = threadIdx.x / kWave, lane = lane_id();
-    int *keys = tkeys + w * kWaveTable;
-    V *vals = tvals + w * kWaveTable;
-    for (int k = lane; k < kWaveTable; k += kWave) {
+    int *keys = tkeys + w * S;
+    V *vals = tvals + w * S;
+    for (int k = lane; k < S; k += kWave) {
         keys[k] = kEmpty;
         vals[k] = 0;
     }
@@ -523,7 +575,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
         double ki = a.K[i];
         const double sgd = a.sig[d];
         const int csd = a.csize[d];
-        const int T = (int)hub_table_size(di);   // <= kWaveTable: at most half full
+        const int T = ScanSlots<WT>::of(di, S);
         // the lane's entries (at most R) are loaded together, then their
         // memberships: two round trips to memory instead of 2R
         constexpr int R = kWaveMaxDeg / kWave;
@@ -540,7 +592,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
         for (int r = 0; r < R; r++) cj[r] = jj[r] != i ? a.cm[jj[r]] : kEmpty;
 #pragma unroll
         for (int r = 0; r < R; r++)
-            if (cj[r] != kEmpty) lds_table_put(keys, vals, T - 1, cj[r], ww[r]);
+            if (cj[r] != kEmpty) scan_put<WT>(keys, vals, T, cj[r], ww[r]);
         wave_lds_sync();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
@@ -571,14 +623,15 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_wave(Move
     flush_acc(acc, a.ctr, 1);
 }
 
-// One workgroup per vertex of 513..2048 entries, 4096-slot table in LDS.
+// One workgroup per vertex of 513..2048 entries, table in LDS.
 template <int WT>
-__global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(MoveArgs a) {
+__global__ void __launch_bounds__(kBlock, 4) k_move_block(MoveArgs a) {
     using V = typename TabVal<WT>::T;
-    __shared__ int keys[kBlockTable];
-    __shared__ V vals[kBlockTable];
+    constexpr int S = ScanSlots<WT>::block;
+    __shared__ int keys[S];
+    __shared__ V vals[S];
     const int tid = threadIdx.x;
-    for (int k = tid; k < kBlockTable; k += kBlock) {
+    for (int k = tid; k < S; k += kBlock) {
         keys[k] = kEmpty;
         vals[k] = 0;
     }
@@ -594,7 +647,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(Mov
         double ki = a.K[i];
         const double sgd = a.sig[d];
         const int csd = a.csize[d];
-        const int T = (int)hub_table_size(di);   // <= kBlockTable: at most half full
+        const int T = ScanSlots<WT>::of(di, S);
         constexpr int R = kBlockMaxDeg / kBlock;   // entries per thread, loaded together
         int jj[R];
         double ww[R];
@@ -609,7 +662,7 @@ __global__ void __launch_bounds__(kBlock, WT == W_UNIT ? 4 : 3) k_move_block(Mov
         for (int r = 0; r < R; r++) cj[r] = jj[r] != i ? a.cm[jj[r]] : kEmpty;
 #pragma unroll
         for (int r = 0; r < R; r++)
-            if (cj[r] != kEmpty) lds_table_put(keys, vals, T - 1, cj[r], ww[r]);
+            if (cj[r] != kEmpty) scan_put<WT>(keys, vals, T, cj[r], ww[r]);
         __syncthreads();
         double bg = -INFINITY, kid = 0.0;
         int bc = kIntMax;
@@ -722,11 +775,12 @@ __global__ void __launch_bounds__(kBlock) k_move_hub_insert(MoveArgs a) {
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
     using V = typename TabVal<WT>::T;
-    __shared__ int tkeys[kBlockTable];
-    __shared__ V tvals[kBlockTable];
+    constexpr int S = ScanSlots<WT>::block;   // a chunk's <= 2048 communities
+    __shared__ int tkeys[S];
+    __shared__ V tvals[S];
     __shared__ int pcnt[kMaxParts + 1];
     const int tid = threadIdx.x;
-    for (int k = tid; k < kBlockTable; k += kBlock) {
+    for (int k = tid; k < S; k += kBlock) {
         tkeys[k] = kEmpty;
         tvals[k] = 0;
     }
@@ -760,11 +814,11 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
             for (int r = 0; r < R; r++) cj[r] = jj[r] != i ? a.cm[jj[r]] : kEmpty;
 #pragma unroll
             for (int r = 0; r < R; r++)
-                if (cj[r] != kEmpty) lds_table_put(tkeys, tvals, kBlockTable - 1, cj[r], ww[r]);
+                if (cj[r] != kEmpty) scan_put<WT>(tkeys, tvals, S, cj[r], ww[r]);
         }
         for (int b = tid; b <= P; b += kBlock) pcnt[b] = 0;
         __syncthreads();
-        for (int sl = tid; sl < kBlockTable; sl += kBlock) {
+        for (int sl = tid; sl < S; sl += kBlock) {
             int key = tkeys[sl];
             if (key != kEmpty) atomicAdd(&pcnt[part_of(key, P)], 1);
         }
@@ -774,7 +828,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_bucket(MoveArgs a) {
         for (int b = tid; b < P; b += kBlock) words[b] = ((uint32_t)pcnt[b] << 16) | (uint32_t)(pcnt[b + 1] - pcnt[b]);
         if (tid == 0) acc.aux += (unsigned long long)P;
         __syncthreads();
-        for (int sl = tid; sl < kBlockTable; sl += kBlock) {
+        for (int sl = tid; sl < S; sl += kBlock) {
             int key = tkeys[sl];
             if (key == kEmpty) continue;
             double v = (double)tvals[sl];
