@@ -241,7 +241,23 @@ __device__ __forceinline__ int group_search(int incl, int x) {
 
 // Inserts the entries of a chunk of at most W members (positions
 // [m0, m1) of c's member list) into the table; uniform across the group.
-template <int W, int WT, bool GLOBAL>
+// Adds w to `key` in an LDS table of T slots (any T): first slot by the
+// multiply-shift reduction of the hash, linear probing with wrap-around.
+__device__ __forceinline__ void lds_table_add_mod(int *keys, double *vals, uint32_t T, int key, double w) {
+    uint32_t s = (uint32_t)(((uint64_t)key_hash(key) * T) >> 32);
+    while (true) {
+        const int prev = atomicCAS(&keys[s], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+            atomicAdd(&vals[s], w);
+            return;
+        }
+        s = s + 1 == T ? 0 : s + 1;
+    }
+}
+
+// GLOBAL: a global table of mask + 1 slots; else an LDS table of mask + 1
+// slots, or (MOD) of `mask` slots.
+template <int W, int WT, bool GLOBAL, bool MOD = false>
 __device__ void insert_member_chunk(const AggArgs &a, int64_t m0, int64_t m1, int gl, int *keys, double *vals,
                                     uint64_t mask) {
     int dm = 0;
@@ -281,6 +297,8 @@ __device__ void insert_member_chunk(const AggArgs &a, int64_t m0, int64_t m1, in
             if (e[r] < 0) continue;
             if constexpr (GLOBAL)
                 gbl_table_add(keys, vals, mask, c[r], w[r]);
+            else if constexpr (MOD)
+                lds_table_add_mod(keys, vals, (uint32_t)mask, c[r], w[r]);
             else
                 lds_table_add(keys, vals, (uint32_t)mask, c[r], w[r]);
         }
@@ -426,11 +444,24 @@ __device__ void emit_table(const AggArgs &a, int c, int *keys, double *vals, int
     }
 }
 
+// Communities of 65..512 entries (four per workgroup, a wavefront and a
+// table of up to 768 slots each) and of 513..2048 entries (a workgroup and
+// a table of up to 3072 slots): 36 KB, so that four workgroups share a CU's
+// LDS (half-full tables of 48 KB let three).  A community of at most a third
+// of the capacity in entries keeps a half-full power-of-two table (and the
+// emit scans only that); larger ones fill theirs at most two thirds.
+constexpr int kAggWaveSlots = 3 * kWaveMaxDeg / 2;
+constexpr int kAggBlockSlots = 3 * kBlockMaxDeg / 2;
+static_assert(kAggBlockSlots == (kBlock / kWave) * kAggWaveSlots, "the wave tables tile the workgroup table");
+__device__ __forceinline__ int agg_slots(int64_t entries, int cap) {
+    return entries <= cap / 3 ? (int)hub_table_size(entries) : cap;
+}
+
 template <int WT>
-__global__ void __launch_bounds__(kBlock) k_agg_large(AggArgs a) {
-    __shared__ int tkeys[kBlockTable];
-    __shared__ double tvals[kBlockTable];
-    for (int k = threadIdx.x; k < kBlockTable; k += kBlock) { tkeys[k] = kEmpty; tvals[k] = 0.0; }
+__global__ void __launch_bounds__(kBlock, 4) k_agg_large(AggArgs a) {
+    __shared__ int tkeys[kAggBlockSlots];
+    __shared__ double tvals[kAggBlockSlots];
+    for (int k = threadIdx.x; k < kAggBlockSlots; k += kBlock) { tkeys[k] = kEmpty; tvals[k] = 0.0; }
     __syncthreads();
     int64_t uw = (a.cn[BIN_WAVE] + 3) / 4;
     int64_t total = uw + a.cn[BIN_BLOCK];
@@ -439,26 +470,28 @@ __global__ void __launch_bounds__(kBlock) k_agg_large(AggArgs a) {
         if (u < uw) {
             int64_t qi = u * 4 + w;
             bool valid = qi < a.cn[BIN_WAVE];
-            int *keys = tkeys + w * kWaveTable;
-            double *vals = tvals + w * kWaveTable;
+            int *keys = tkeys + w * kAggWaveSlots;
+            double *vals = tvals + w * kAggWaveSlots;
             int c = valid ? a.cbl[a.cbeg[BIN_WAVE] + qi] : 0;
+            const int T = valid ? agg_slots(a.eoff[c + 1] - a.eoff[c], kAggWaveSlots) : 0;
             if (valid)
                 for (int64_t m0 = a.coff[c]; m0 < a.coff[c + 1]; m0 += kWave) {
                     int64_t m1 = m0 + kWave < a.coff[c + 1] ? m0 + kWave : a.coff[c + 1];
-                    insert_member_chunk<kWave, WT, false>(a, m0, m1, lane, keys, vals, kWaveTable - 1);
+                    insert_member_chunk<kWave, WT, false, true>(a, m0, m1, lane, keys, vals, T);
                 }
             __syncthreads();
-            if (valid) emit_table<kWave>(a, c, keys, vals, kWaveTable);
+            if (valid) emit_table<kWave>(a, c, keys, vals, T);
             __syncthreads();
         } else {
             int c = a.cbl[a.cbeg[BIN_BLOCK] + (u - uw)];
+            const int T = agg_slots(a.eoff[c + 1] - a.eoff[c], kAggBlockSlots);
             // the four waves take member chunks in turn
             for (int64_t m0 = a.coff[c] + (int64_t)w * kWave; m0 < a.coff[c + 1]; m0 += kBlock) {
                 int64_t m1 = m0 + kWave < a.coff[c + 1] ? m0 + kWave : a.coff[c + 1];
-                insert_member_chunk<kWave, WT, false>(a, m0, m1, lane, tkeys, tvals, kBlockTable - 1);
+                insert_member_chunk<kWave, WT, false, true>(a, m0, m1, lane, tkeys, tvals, T);
             }
             __syncthreads();
-            emit_table<kBlock>(a, c, tkeys, tvals, kBlockTable);
+            emit_table<kBlock>(a, c, tkeys, tvals, T);
             __syncthreads();
         }
     }
