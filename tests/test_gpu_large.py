@@ -22,7 +22,10 @@ pass at this size in a test, so the checks are:
   * the whole run equal to the oracle's synchronous run (stored by
     tests/golden/make_rmat26.py): membership digest, iterations and
     communities per pass, Q within 1e-9, in the degree order the run picks
-    at this size and in the loaded order.
+    at this size and in the loaded order;
+  * GSP-Leiden's whole run equal to the oracle's (stored by
+    tests/golden/make_leiden.py): the same, plus the refinement's per-pass
+    iterations and sub-community counts; no disconnected community.
 
 Needs about 60 GB of host memory and 150 GB of device memory (a few
 minutes, most of it generating the graph).
@@ -161,3 +164,20 @@ def test_whole_run_equals_oracle(big, order):
     assert res.stats["communities"] == ref["communities"]
     assert sha == ref["membership_sha1"]
     assert abs(res.modularity - ref["modularity"]) <= 1e-9
+
+
+def test_leiden_equals_oracle(big):
+    g, w, S, moved, ctx = big
+    path = os.path.join(os.path.dirname(GOLDEN), "leiden_oracle.json")
+    with open(path) as f:
+        ref = json.load(f)["rmat26"]
+    assert ref["nnz"] == g.nnz and ref["n"] == g.n
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, leiden=1)
+    sha = hashlib.sha1(np.ascontiguousarray(res.membership, dtype=np.int32).tobytes()).hexdigest()
+    assert res.stats["iterations"] == ref["iterations"]
+    assert res.stats["communities"] == ref["communities"]
+    assert res.stats["refine_iterations"] == ref["refine_iterations"]
+    assert res.stats["refined"] == ref["refined"]
+    assert sha == ref["membership_sha1"]
+    assert abs(res.modularity - ref["modularity"]) <= 1e-9
+    assert ctx.count_disconnected(res.membership) == 0
