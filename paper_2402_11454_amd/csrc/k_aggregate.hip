@@ -684,13 +684,21 @@ __global__ void __launch_bounds__(kBlock) k_agg_hub_emit(AggArgs a, const int32_
 // positions of the staging arrays, with one word per partition (start << 16
 // | count).  Phase 2, per partition: merge that partition's pairs from every
 // chunk of c in one LDS table and append the table to row c.  Each pair is
-// written once and read once.  A partition with more than kPartCap distinct
-// communities (its table would not fit) spills its pairs into c's global
-// table instead; the emit kernel appends those.
+// written once and read once.  A partition with more than kAggGatherCap
+// distinct communities (its table would not fit) spills its pairs into c's
+// global table instead; the emit kernel appends those.
 
 constexpr int kAggPartTarget = 1536;   // distinct communities aimed at per partition
 constexpr int kAggMaxParts = 4086;     // partition counts (+1) fit the bucket kernel's 40 KB of LDS
 constexpr int kGatherWin = 2048;       // source chunks per window of the gather
+// The gather's LDS table: 3072 slots, at most kAggGatherCap distinct
+// communities per partition (a third above the target; past it the
+// partition spills) plus fewer than kBlock inserts in flight, so at most
+// three quarters full: 49 KB of LDS with the window, three workgroups per
+// CU where the 4096-slot table allowed two.
+constexpr int kAggGatherSlots = 3072;
+constexpr int kAggGatherCap = 2048;
+static_assert(kAggGatherCap + kBlock < kAggGatherSlots, "the gather's table never fills");
 
 // P_c: one partition per kAggPartTarget possible distinct neighbours (at most
 // min(total degree, n2)); at most kAggMaxParts and at most the chunk count.
@@ -785,15 +793,15 @@ __device__ __forceinline__ int load_window(const uint32_t *wd, int P, int p, int
 // s >= P_c have nothing to do).
 __global__ void __launch_bounds__(kBlock) k_agg_part_gather(AggArgs a, const int32_t *cch_comm,
                                                            const int64_t *cch_beg, int64_t nchunks) {
-    __shared__ int tkeys[kBlockTable];
-    __shared__ double tvals[kBlockTable];
+    __shared__ int tkeys[kAggGatherSlots];
+    __shared__ double tvals[kAggGatherSlots];
     __shared__ int pst[kGatherWin + 1];
     __shared__ short srcst[kGatherWin];
     __shared__ int s_cnt[kBlock / kWave];
     __shared__ double s_sum[kBlock / kWave];
     __shared__ int nkeys, ovf, s_base;
     const int tid = threadIdx.x;
-    for (int k = tid; k < kBlockTable; k += kBlock) {
+    for (int k = tid; k < kAggGatherSlots; k += kBlock) {
         tkeys[k] = kEmpty;
         tvals[k] = 0.0;
     }
@@ -819,13 +827,13 @@ __global__ void __launch_bounds__(kBlock) k_agg_part_gather(AggArgs a, const int
                 int64_t idx = e0 + (w0 + s) * kAggChunk + (int64_t)srcst[s] + (t - pst[s]);
                 int key = a.stage_col[idx];
                 double v = a.stage_w[idx];
-                // at most kPartCap distinct keys (plus fewer than kBlock in
-                // flight): the table never fills
-                uint32_t sl = key_hash(key) & (kBlockTable - 1);
+                // at most kAggGatherCap distinct keys (plus fewer than kBlock
+                // in flight): the table never fills
+                uint32_t sl = (uint32_t)(((uint64_t)key_hash(key) * kAggGatherSlots) >> 32);
                 while (true) {
                     int prev = atomicCAS(&tkeys[sl], kEmpty, key);
                     if (prev == kEmpty) {
-                        if (atomicAdd(&nkeys, 1) >= kPartCap) ovf = 1;
+                        if (atomicAdd(&nkeys, 1) >= kAggGatherCap) ovf = 1;
                         atomicAdd(&tvals[sl], v);
                         break;
                     }
@@ -833,7 +841,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_part_gather(AggArgs a, const int
                         atomicAdd(&tvals[sl], v);
                         break;
                     }
-                    sl = (sl + 1) & (kBlockTable - 1);
+                    sl = sl + 1 == kAggGatherSlots ? 0 : sl + 1;
                 }
             }
             __syncthreads();
@@ -841,7 +849,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_part_gather(AggArgs a, const int
         }
         if (ovf) {
             // spill: the partition's pairs go to c's global table
-            for (int q = tid; q < kBlockTable; q += kBlock) {
+            for (int q = tid; q < kAggGatherSlots; q += kBlock) {
                 tkeys[q] = kEmpty;
                 tvals[q] = 0.0;
             }
@@ -861,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_part_gather(AggArgs a, const int
             continue;
         }
         // append the table to row c: one reservation on deg''[c] per block
-        constexpr int R = kBlockTable / kBlock;
+        constexpr int R = kAggGatherSlots / kBlock;
         int key[R];
         double val[R];
         int cnt = 0;
