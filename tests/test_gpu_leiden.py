@@ -5,10 +5,12 @@ modularity, per-pass local-moving and refinement statistics), in the loaded
 order and in degree order, with every split mode.
 
 The graphs cover hubs of more than 2048 entries (their same-community
-subgraph rows are built chunk by chunk), rows of 33-2048 entries (a
-wavefront each) and short rows, unit and fp32 weights, exact ties and a
-low-degree grid; the bounds cover a local-moving result, one community for
-all, random communities and every vertex alone.
+subgraph rows are built chunk by chunk), rows of up to 2048 entries (in
+256-row tiles) and short rows, unit, fp32 and fp64 weights, self-loops,
+exact ties and a low-degree grid; the bounds cover a local-moving result,
+one community for all, random communities and every vertex alone; the
+options cover the split modes and algorithms, other sub-round counts, the
+hubs' global-table path, per-kernel events and the return-move option.
 """
 import numpy as np
 import pytest
@@ -207,3 +209,66 @@ def test_leiden_louvain_runs_unchanged(ctx):
     res = ctx.louvain(1e-2, 10)
     ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
     np.testing.assert_array_equal(res.membership, ref.membership)
+
+
+def _run_both(ctx, g):
+    res = ctx.louvain(1e-2, 10, leiden=1)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=True)
+    _check_run(res, ref)
+
+
+def test_leiden_self_loops_and_weights(ctx):
+    """Self-loops (skipped by every scan, kept in the same-community
+    subgraph) and fp32 weights."""
+    base = gi.rmat_small(13, 21, weights=(1.0, 4.0))
+    g = gi.with_self_loops(base, {3: 2.0, 77: 0.5, 4000: 3.0})
+    ctx.load_graph(g)
+    _run_both(ctx, g)
+
+
+def test_leiden_fp64_weights(ctx):
+    """fp64 weights through gsp_load_csr_f64 (on the exact-sum grid): the
+    subgraph keeps them in fp64."""
+    g = gi.rmat_small(12, 22, weights=(1.0, 3.0))
+    w = g.weights.astype(np.float64) * 0.75
+    ctx.load(g.offsets, g.cols, w, n=g.n)
+    res = ctx.louvain(1e-2, 10, leiden=1)
+    wg = w.copy()
+    oracle.weight_grid(wg)   # the load's rounding, applied on the host
+    ref = oracle.louvain(oracle.CSR(g.n, g.offsets, g.cols, wg), tolerance=1e-2, max_passes=10, sync=True,
+                         rounds=8, leiden=True)
+    _check_run(res, ref)
+
+
+@pytest.mark.parametrize("rounds", [1, 4, 16])
+def test_leiden_other_sub_rounds(ctx, rounds):
+    g = _graph("rmat15")
+    ctx.load_graph(g)
+    res = ctx.louvain(1e-2, 10, leiden=1, sub_rounds=rounds)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=rounds, leiden=True)
+    _check_run(res, ref)
+
+
+def test_leiden_hub_paths_and_event_timing(ctx):
+    """The hubs' global-table path, a small partition limit and per-kernel
+    events change the launches, not the run."""
+    g = _graph("rmat16w")
+    ctx.load_graph(g)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=True)
+    for kw in (dict(hub_global=1, use_graphs=0), dict(hub_max_parts=2, use_graphs=0), dict(timing=2),
+               dict(timing=3)):
+        res = ctx.louvain(1e-2, 10, leiden=1, **kw)
+        _check_run(res, ref)
+        if kw.get("timing"):
+            assert res.stats["ms_refine"] > 0.0
+
+
+def test_leiden_return_moves_option(ctx):
+    """The return-move option applies to the local-moving phases (the
+    refinement moves only vertices alone in their sub-community, so it has
+    no swap cycles): equal to the oracle's run with the option."""
+    g = _graph("dcsbm50k")
+    ctx.load_graph(g)
+    res = ctx.louvain(1e-2, 10, leiden=1, return_moves=1)
+    ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=True, return_moves=True)
+    _check_run(res, ref)
