@@ -938,16 +938,35 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(MoveArgs a) {
 // and scores it.  On unit weights the values are counts (int slots).
 constexpr int kHubWin = 512;
 
+// A hub partition's merge table: on unit weights (int values, 32 KB) 4096
+// slots and at most kPartCap distinct communities; otherwise 3072 slots and
+// at most 2560 (a partition holds about 2048 on average, as a hub has one
+// partition per chunk of 2048 entries), so that four workgroups share a
+// CU's LDS where the 4096-slot fp64 table let three.  Past the cap the hub
+// takes its global table.  Fewer than kBlock inserts overshoot the cap.
+template <int WT> struct GatherSlots {
+    static constexpr int slots = WT == W_UNIT ? kBlockTable : 3 * kBlockMaxDeg / 2;
+    static constexpr int cap = WT == W_UNIT ? kPartCap : 2560;
+    static_assert(cap + kBlock < slots, "the merge table never fills");
+    __device__ static uint32_t first(int key) {
+        if constexpr (WT == W_UNIT)
+            return key_hash(key) & (uint32_t)(slots - 1);
+        else
+            return (uint32_t)(((uint64_t)key_hash(key) * slots) >> 32);
+    }
+};
+
 template <int WT>
 __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
     using V = typename TabVal<WT>::T;
-    __shared__ int tkeys[kBlockTable];
-    __shared__ V tvals[kBlockTable];
+    constexpr int S = GatherSlots<WT>::slots;
+    __shared__ int tkeys[S];
+    __shared__ V tvals[S];
     __shared__ int pst[kHubWin + 1];
     __shared__ short srcst[kHubWin];   // this partition's start within each source chunk
     __shared__ int nkeys, ovf;
     const int tid = threadIdx.x;
-    for (int k = tid; k < kBlockTable; k += kBlock) {
+    for (int k = tid; k < S; k += kBlock) {
         tkeys[k] = kEmpty;
         tvals[k] = 0;
     }
@@ -990,11 +1009,11 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
                 double v = a.sval[idx];
                 // insert, counting distinct keys; past kPartCap the partition
                 // stops (at most kBlock inserts overshoot: the table never fills)
-                uint32_t sl = key_hash(key) & (kBlockTable - 1);
+                uint32_t sl = GatherSlots<WT>::first(key);
                 while (true) {
                     int prev = atomicCAS(&tkeys[sl], kEmpty, key);
                     if (prev == kEmpty) {
-                        if (atomicAdd(&nkeys, 1) >= kPartCap) ovf = 1;
+                        if (atomicAdd(&nkeys, 1) >= GatherSlots<WT>::cap) ovf = 1;
                         atomicAdd(&tvals[sl], (V)v);
                         break;
                     }
@@ -1002,14 +1021,14 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
                         atomicAdd(&tvals[sl], (V)v);
                         break;
                     }
-                    sl = (sl + 1) & (kBlockTable - 1);
+                    sl = sl + 1 == (uint32_t)S ? 0 : sl + 1;
                 }
             }
             __syncthreads();
             if (ovf) break;
         }
         if (ovf) {   // rare: this hub goes through its global table
-            for (int q = tid; q < kBlockTable; q += kBlock) {
+            for (int q = tid; q < S; q += kBlock) {
                 tkeys[q] = kEmpty;
                 tvals[q] = 0;
             }
@@ -1020,7 +1039,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_gather(MoveArgs a) {
             const double m2 = m2_of(a, i);
             double bg = -INFINITY, kid = 0.0;
             int bc = kIntMax;
-            fold_table<kBlock, 8>(a, m2, tkeys, tvals, kBlockTable, tid, d, ki, bg, bc, kid, acc.keys);
+            fold_table<kBlock, 8>(a, m2, tkeys, tvals, S, tid, d, ki, bg, bc, kid, acc.keys);
             block_argmax_sum(bg, bc, kid, a.g.orig);
             if (tid == 0) {
                 a.part_g[k] = bg;
