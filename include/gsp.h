@@ -340,7 +340,8 @@ gsp_status gsp_move_phase_ex(gsp_ctx *ctx, int32_t *membership_inout, int where,
  * grid_cap and hub options (opt = NULL: the defaults); prune_mode must be
  * GSP_PRUNE_PLAIN.  iterations, dq_iter and moved_iter as for
  * gsp_move_phase.  Both arrays live where `where` says.  GSP_EINVAL for a
- * label outside [0, n) or a sub-community across two bound communities. */
+ * label outside [0, n), a sub-community across two bound communities, or
+ * trace capture on (gsp_capture_traces). */
 gsp_status gsp_refine_phase(gsp_ctx *ctx, const int32_t *bound, int32_t *membership_inout, int where,
                             double tolerance, const gsp_options *opt, int32_t *iterations, double *dq_iter,
                             int64_t *moved_iter);

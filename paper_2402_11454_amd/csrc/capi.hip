@@ -2117,6 +2117,7 @@ gsp_status gsp_refine_phase(gsp_ctx *ctx, const int32_t *bound, int32_t *members
     if (!(tolerance >= 0.0)) return ctx->fail(GSP_EINVAL, "bad tolerance");
     if (!ctx->loaded) return ctx->fail(GSP_ESTATE, "no graph loaded");
     if (!bound && ctx->n > 0) return ctx->fail(GSP_EINVAL, "bound is NULL");
+    if (ctx->tracing) return ctx->fail(GSP_EINVAL, "the refinement runs without trace capture");
     if ((st = ensure_levels(ctx)) != GSP_OK) return st;   // the subgraph and the hub staging
     if ((st = ensure_leiden(ctx)) != GSP_OK) return st;
     ctx->hub_parts = opt.hub_global == 0;

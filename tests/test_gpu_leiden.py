@@ -124,6 +124,15 @@ def test_refinement_rejects_bad_start(ctx):
     bad[3] = g.n
     with pytest.raises(gsp.GspError):
         ctx.refine_phase(bad)
+    # no refinement scans in the gate's training traces
+    ctx.capture_traces(1000, 1.0, 1)
+    try:
+        with pytest.raises(gsp.GspError):
+            ctx.refine_phase(b)
+        with pytest.raises(gsp.GspError):
+            ctx.louvain(1e-2, 10, leiden=1)
+    finally:
+        ctx.capture_traces(0, 1.0, 1)
 
 
 def _check_run(res, ref):
