@@ -225,13 +225,31 @@ __global__ void __launch_bounds__(kBlock) k_vertex_weights_rows(Level g, double 
         acc[tid] = 0.0;
         __syncthreads();
         const int64_t e0 = so[0], e1 = so[kBlock];
-        for (int64_t e = e0 + tid; e < e1; e += kBlock) {
-            int lo = 0, hi = nr - 1;   // the row r with so[r] <= e < so[r + 1]
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (so[mid] <= e) lo = mid; else hi = mid - 1;
+        const int lane = lane_id();
+        for (int64_t eb = e0; eb < e1; eb += kBlock) {   // the same trip count in every lane
+            const int64_t e = eb + tid;
+            int r = -1;   // the row r with so[r] <= e < so[r + 1]
+            double v = 0.0;
+            if (e < e1) {
+                int lo = 0, hi = nr - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (so[mid] <= e) lo = mid; else hi = mid - 1;
+                }
+                r = lo;
+                v = edge_weight<WT>(g.w, e);
             }
-            atomicAdd(&acc[lo], edge_weight<WT>(g.w, e));
+            // consecutive lanes hold consecutive entries, so a row's entries
+            // are a run of lanes: sum each run into its first lane (exact on
+            // the grid's weights), which adds it to the row
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const double y = __shfl_down(v, o, kWave);
+                const int ry = __shfl_down(r, o, kWave);
+                if (lane + o < kWave && ry == r) v += y;
+            }
+            const int rp = __shfl_up(r, 1, kWave);
+            if (r >= 0 && (lane == 0 || rp != r)) atomicAdd(&acc[r], v);
         }
         __syncthreads();
         if (tid < nr) {
