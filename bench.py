@@ -241,8 +241,8 @@ def cpu_baseline(g, every, gpu_scanned, nnz):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {a.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 

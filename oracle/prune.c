@@ -9,7 +9,7 @@
  * pass may end.  The gate is not part of the paper; it prunes the vertices
  * that Algorithm "louvainMove" would scan (the unprocessed vertices of an
  * iteration, Section 4.1's pruning), and the plain sweep keeps the paper's
- * convergence test (per-iteration delta-modularity against tau) as the judge.
+ * convergence test (per-iteration delta-modularity against tau) as the final word.
  *
  * Plain loops, fp64 unless stated.  Only the tests, the smoke check and the
  * bench's CPU leg use it; it shares no code with the GPU library.
