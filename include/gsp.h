@@ -185,7 +185,9 @@ const char *gsp_last_error(const gsp_ctx *ctx);
 /* Loads the graph G (Section 3) and validates it on the device: offsets
  * start at 0, never decrease and end at nnz; columns lie in [0, n); weights
  * are finite and >= 0.  A malformed graph gives GSP_EGRAPH and leaves no
- * graph loaded.  Symmetry is the caller's promise and is not checked.
+ * graph loaded.  n must lie in [1, 2^31 - 2] and nnz be >= 0 (an empty
+ * graph has no community to find): otherwise GSP_EINVAL, and the graph
+ * loaded before, if any, stays.  Symmetry is the caller's promise and is not checked.
  * Replaces any graph loaded before and frees the previous result.
  * weights = NULL means unit weights. */
 gsp_status gsp_load_csr(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,

@@ -1056,7 +1056,7 @@ int32_t host_weight_grid(float *w, int64_t nnz, int64_t *moved) {
 // already (a batch: one grid per graph).
 gsp_status load_impl(gsp_ctx *ctx, int64_t n, int64_t nnz, const int64_t *off64, const int32_t *off32,
                      const int32_t *cols, const void *weights, int wt, int where, bool grid = true) {
-    if (n < 0 || nnz < 0) return ctx->fail(GSP_EINVAL, "negative size");
+    if (n < 1 || nnz < 0) return ctx->fail(GSP_EINVAL, "n must be >= 1 and nnz >= 0");
     if (n > 0x7fffffffLL - 1) return ctx->fail(GSP_EINVAL, "n must be below 2^31 - 1 (int32 vertex ids)");
     if (where != GSP_HOST && where != GSP_DEVICE) return ctx->fail(GSP_EINVAL, "bad `where`");
     if (!off64 && !off32) return ctx->fail(GSP_EINVAL, "offsets is NULL");

@@ -382,6 +382,12 @@ def test_error_paths(ctx):
     with pytest.raises(gsp.GspError) as e:
         ctx.run(sub_rounds=3)
     assert e.value.status == gsp.GSP_EINVAL
+    # an empty graph (no vertex) is refused, and the graph loaded before stays
+    with pytest.raises(gsp.GspError) as e:
+        ctx.load(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert e.value.status == gsp.GSP_EINVAL
+    ctx.run(max_passes=0)
+    assert ctx.membership().tolist() == list(range(g.n))
     with pytest.raises(gsp.GspError) as e:
         ctx.run(mem_limit_bytes=1024)
     assert e.value.status == gsp.GSP_ENOMEM
