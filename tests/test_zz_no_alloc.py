@@ -56,6 +56,14 @@ def test_noalloc_limits_and_bad_labels():
     memb = gi.random_membership(g.n, 50, 3)
     memb[7] = g.n + 5                                  # a label out of range: the count reads -1
     assert _count_noalloc(g, memb) == -1
+    # no vertex: nothing is disconnected
+    dev = torch.device("cuda:0")
+    out = torch.full((1,), -7, dtype=torch.int64, device=dev)
+    gsp.count_disconnected_noalloc(torch.zeros(1, dtype=torch.int64, device=dev),
+                                   torch.zeros(0, dtype=torch.int32, device=dev),
+                                   torch.zeros(0, dtype=torch.int32, device=dev), out)
+    torch.cuda.synchronize()
+    assert int(out.item()) == 0
     # more vertices than the scratch holds: refused before any launch
     st = gsp.lib().gsp_count_disconnected_noalloc(gsp.lib().gsp_noalloc_max_vertices() + 1, 0, 1, None, 1, 1, None)
     assert st == gsp.GSP_EINVAL
