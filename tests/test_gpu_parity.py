@@ -359,6 +359,32 @@ def test_edge_cases(ctx):
     assert ctx.n == g.n and ctx.modularity(np.zeros(g.n, np.int32)) == 0.0
 
 
+@pytest.mark.parametrize("order", [gsp.ORDER_LOADED, gsp.ORDER_DEGREE])
+def test_zero_weight_entries(ctx, order):
+    """Entries of weight 0 (weights need only be finite and >= 0): a fifth
+    of the pairs weigh 0, and vertices whose entries all weigh 0 have
+    K_i = 0; GSP-Louvain and GSP-Leiden equal the oracle.  With every weight
+    0 (2m = 0) no move has a positive gain: singletons, Q = 0."""
+    g = gi.rmat_small(12, 23, weights=(1.0, 4.0))
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    w = g.weights.copy()
+    w[(rows + g.cols.astype(np.int64)) % 5 == 0] = 0.0        # the same for (i, j) and (j, i)
+    z = gi.Graph(n=g.n, offsets=g.offsets, cols=g.cols, weights=w, name="rmat12-zero")
+    K = np.add.reduceat(w.astype(np.float64), g.offsets[:-1])
+    assert ((K == 0.0) & (np.diff(g.offsets) > 0)).sum() > 0
+    ctx.load_graph(z)
+    for leiden in (0, 1):
+        res = ctx.louvain(1e-2, 10, leiden=leiden, vertex_order=order)
+        ref = oracle.louvain(z, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=bool(leiden))
+        np.testing.assert_array_equal(res.membership, ref.membership)
+        assert abs(res.modularity - ref.modularity) <= 1e-9
+        assert res.stats["iterations"] == ref.iterations
+        assert ctx.count_disconnected(res.membership) == 0
+    ctx.load_graph(gi.Graph(n=g.n, offsets=g.offsets, cols=g.cols, weights=np.zeros_like(w), name="zero"))
+    res = ctx.louvain(1e-2, 10, vertex_order=order)
+    assert res.membership.tolist() == list(range(g.n)) and res.modularity == 0.0
+
+
 def test_error_paths(ctx):
     with pytest.raises(gsp.GspError):
         ctx.run(return_moves=2)                         # an option of 0 or 1
