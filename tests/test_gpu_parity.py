@@ -385,6 +385,35 @@ def test_zero_weight_entries(ctx, order):
     assert res.membership.tolist() == list(range(g.n)) and res.modularity == 0.0
 
 
+def _clique(n):
+    iu = np.triu_indices(n, 1)
+    return gi.from_edges(n, list(zip(iu[0].tolist(), iu[1].tolist())), name=f"clique{n}")
+
+
+def _star(leaves):
+    """A hub joined to every leaf, and every 7th leaf to the leaf 7 further."""
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 7) for i in range(1, leaves - 6, 7)]
+    return gi.from_edges(leaves + 1, edges, name=f"star{leaves}")
+
+
+@pytest.mark.parametrize("order", [gsp.ORDER_LOADED, gsp.ORDER_DEGREE])
+@pytest.mark.parametrize("make", [lambda: _clique(2100), lambda: _star(60000)], ids=["clique2100", "star60000"])
+def test_clique_and_star(ctx, make, order):
+    """Degenerate shapes: a clique of 2100 vertices (every vertex a hub of
+    2099 entries, one community at the end) and a star (one hub of 60,000
+    entries among leaves of degree 1-3); GSP-Louvain and GSP-Leiden equal
+    the oracle."""
+    g = make()
+    ctx.load_graph(g)
+    for leiden in (0, 1):
+        res = ctx.louvain(1e-2, 10, leiden=leiden, vertex_order=order)
+        ref = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=bool(leiden))
+        np.testing.assert_array_equal(res.membership, ref.membership)
+        assert abs(res.modularity - ref.modularity) <= 1e-9
+        assert res.stats["iterations"] == ref.iterations
+        assert ctx.count_disconnected(res.membership) == 0
+
+
 def test_error_paths(ctx):
     with pytest.raises(gsp.GspError):
         ctx.run(return_moves=2)                         # an option of 0 or 1
