@@ -259,6 +259,45 @@ def test_gated_run_matches_oracle(ctx, returns):
     assert ctx.count_disconnected(res.membership) == 0
 
 
+def _zero_weight_graph():
+    """R-MAT 12 with a fifth of its pairs at weight 0 (vertices with K_i = 0)."""
+    g = gi.rmat_small(12, 23, weights=(1.0, 4.0))
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    w = g.weights.copy()
+    w[(rows + g.cols.astype(np.int64)) % 5 == 0] = 0.0
+    return gi.Graph(n=g.n, offsets=g.offsets, cols=g.cols, weights=w, name="rmat12-zero")
+
+
+def _star_graph(leaves=60000):
+    edges = [(0, i) for i in range(1, leaves + 1)] + [(i, i + 7) for i in range(1, leaves - 6, 7)]
+    return gi.from_edges(leaves + 1, edges, name=f"star{leaves}")
+
+
+@pytest.mark.parametrize("make", [_zero_weight_graph, _star_graph], ids=["zero_weights", "star"])
+def test_gated_run_degenerate_graphs(ctx, make):
+    """The gate's features divide by K_i and Sigma_d; vertices with K_i = 0
+    and a hub among leaves of degree 1-3 take the guarded branches.  Whole
+    learned runs equal the oracle's."""
+    g = make()
+    p = _params(61, 0.5, sharp=64.0)
+
+    def run(tl):
+        r = oracle.louvain(g, sync=True, prune_params=p, theta_logit=tl)
+        return (r.membership.tobytes(), tuple(r.iterations), tuple(r.counters.values()))
+
+    th = _stable_theta(g, p, [0.5, 0.55, 0.45, 0.6, 0.4], run)
+    ref = oracle.louvain(g, sync=True, prune_params=p, theta=th)
+    assert ref.counters["pruned"] > 0
+    _load(ctx, g)
+    ctx.pruner_set(p)
+    res = ctx.louvain(tolerance=1e-2, max_passes=10, prune_mode=gsp.PRUNE_LEARNED, prune_threshold=th)
+    assert np.array_equal(res.membership, ref.membership)
+    assert res.stats["iterations"] == ref.iterations
+    assert res.stats["pruned"] == ref.counters["pruned"]
+    assert res.stats["scanned_entries"] == ref.counters["scanned_entries"]
+    assert abs(res.modularity - ref.modularity) <= 1e-9
+
+
 def test_second_network_on_a_warm_context(ctx):
     """Two networks in a row on one loaded graph (the first run's gated
     sweeps captured and cached): the second run is the oracle's run with the
