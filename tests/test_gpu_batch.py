@@ -150,6 +150,33 @@ def test_batch_of_shaped_sbms(ctx):
         assert cnt == 0
 
 
+def test_batch_of_degenerate_graphs(ctx):
+    """Degenerate graphs side by side in one batch, each equal to the
+    oracle's run of it alone: zero-weight entries (K_i = 0), every weight 0
+    (2m = 0), no edge, one vertex with a self-loop, a clique whose vertices
+    are all hubs, and a star."""
+    g = gi.rmat_small(12, 23, weights=(1.0, 4.0))
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    w = g.weights.copy()
+    w[(rows + g.cols.astype(np.int64)) % 5 == 0] = 0.0
+    iu = np.triu_indices(2100, 1)
+    leaves = 20000
+    gs = [gi.Graph(n=g.n, offsets=g.offsets, cols=g.cols, weights=w, name="zero-entries"),
+          gi.Graph(n=g.n, offsets=g.offsets, cols=g.cols, weights=np.zeros_like(w), name="zero-all"),
+          gi.Graph(n=5, offsets=np.zeros(6, np.int64), cols=np.zeros(0, np.int32), name="edgeless"),
+          gi.with_self_loops(gi.from_edges(1, []), {0: 2.0}),
+          gi.from_edges(2100, list(zip(iu[0].tolist(), iu[1].tolist())), name="clique"),
+          gi.from_edges(leaves + 1, [(0, i) for i in range(1, leaves + 1)] +
+                        [(i, i + 7) for i in range(1, leaves - 6, 7)], name="star")]
+    ctx.load_batch(gs)
+    ctx.run_batch(1e-2, 10)
+    q = ctx.batch_modularity()
+    for k, gk in enumerate(gs):
+        ref = oracle.louvain(gk, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+        assert np.array_equal(ctx.batch_membership(k), ref.membership), gk.name
+        assert abs(q[k] - ref.modularity) <= 1e-9, gk.name
+
+
 def test_batch_errors(ctx):
     with pytest.raises(gsp.GspError):
         ctx.load_batch([gi.from_edges(3, [(0, 1)]), gi.Graph(n=0, offsets=np.zeros(1, np.int64),
