@@ -6,8 +6,9 @@ partition is that of the graph without those entries.  A vertex whose
 entries all weigh 0 has K_i = 0, so every candidate's gain for it (Eq. 2)
 is 0 and it never moves by its own decision.  With every weight 0 the graph
 has 2m = 0: no move has a positive gain, the run keeps the singletons, and Q
-is 0 by convention.  Decisions and whole phases are replayed by brute force
-on the all-pairs modularity in exact arithmetic.
+is 0 by convention.  Decisions, whole phases and GSP-Leiden's refinement
+are replayed by brute force on the all-pairs modularity in exact
+arithmetic, and both pass loops from their separately pinned steps.
 """
 import numpy as np
 import pytest
@@ -85,3 +86,41 @@ def test_every_weight_zero_keeps_singletons():
     assert r.membership.tolist() == list(range(z.n))
     assert r.modularity == 0.0 and r.passes == 1
     assert oracle.modularity(z, np.zeros(z.n, np.int32)) == 0.0
+
+
+def _zero_rmat12():
+    """R-MAT 12 with a fifth of its pairs at weight 0 (117 vertices with
+    edges but K_i = 0)."""
+    g = gi.rmat_small(12, 23, weights=(1.0, 4.0))
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    w = g.weights.copy()
+    w[(rows + g.cols.astype(np.int64)) % 5 == 0] = 0.0
+    return gi.Graph(n=g.n, offsets=g.offsets, cols=g.cols, weights=w, name="rmat12-zero")
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("kind", ["louvain", "one", "random"])
+def test_refinement_with_zero_entries_matches_replay(seed, kind):
+    from test_oracle_leiden import _bounds, _refine_replay
+    g, _, _ = _zero_small(700 + seed, n=11)
+    bound = _bounds(g, kind, seed)
+    start = np.arange(g.n, dtype=np.int32)
+    want, li, dqs = _refine_replay(g, bound, start, 0.0, 12, 8)
+    got, gli, gdq, _ = oracle.refine_sync(g, bound, tau=0.0, max_iter=12, rounds=8)
+    assert list(got) == want and gli == li
+    np.testing.assert_allclose(gdq, [float(x) for x in dqs], atol=1e-13)
+
+
+def test_pass_loops_with_zero_entries_replay_the_steps():
+    from test_oracle_leiden import _leiden_replay
+    from test_oracle_passloop import _replay
+    g = _zero_rmat12()
+    want, rec = _replay(g, 1e-2, 10, 0)
+    r = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8)
+    assert (r.passes, r.iterations, r.communities, r.tau) == (len(rec), [x[0] for x in rec],
+                                                              [x[1] for x in rec], [x[3] for x in rec])
+    np.testing.assert_array_equal(r.membership, want)
+    want, rec = _leiden_replay(g, 1e-2, 10, 0)
+    r = oracle.louvain(g, tolerance=1e-2, max_passes=10, sync=True, rounds=8, leiden=True)
+    assert (r.passes, r.iterations, r.refined) == (len(rec), [x[0] for x in rec], [x[5] for x in rec])
+    np.testing.assert_array_equal(r.membership, want)
