@@ -150,11 +150,9 @@ def test_batch_of_shaped_sbms(ctx):
         assert cnt == 0
 
 
-def test_batch_of_degenerate_graphs(ctx):
-    """Degenerate graphs side by side in one batch, each equal to the
-    oracle's run of it alone: zero-weight entries (K_i = 0), every weight 0
-    (2m = 0), no edge, one vertex with a self-loop, a clique whose vertices
-    are all hubs, and a star."""
+def _degenerate_batch():
+    """Zero-weight entries (K_i = 0), every weight 0 (2m = 0), no edge, one
+    vertex with a self-loop, a clique whose vertices are all hubs, a star."""
     g = gi.rmat_small(12, 23, weights=(1.0, 4.0))
     rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
     w = g.weights.copy()
@@ -168,6 +166,13 @@ def test_batch_of_degenerate_graphs(ctx):
           gi.from_edges(2100, list(zip(iu[0].tolist(), iu[1].tolist())), name="clique"),
           gi.from_edges(leaves + 1, [(0, i) for i in range(1, leaves + 1)] +
                         [(i, i + 7) for i in range(1, leaves - 6, 7)], name="star")]
+    return gs
+
+
+def test_batch_of_degenerate_graphs(ctx):
+    """Degenerate graphs side by side in one batch, each equal to the
+    oracle's run of it alone."""
+    gs = _degenerate_batch()
     ctx.load_batch(gs)
     ctx.run_batch(1e-2, 10)
     q = ctx.batch_modularity()
@@ -216,7 +221,7 @@ def _gate_params(seed, b3, sharp=1.0):
 
 
 @pytest.mark.parametrize("b3,make", [(0.5, lambda: _mixed_batch()[:14]), (-0.2, lambda: _mixed_batch()[:14]),
-                                     (0.5, _weighted_batch)])
+                                     (0.5, _weighted_batch), (0.5, _degenerate_batch)])
 def test_learned_batch_equals_single_runs(ctx, b3, make):
     gs = make()
     p = _gate_params(61, b3)
